@@ -1,0 +1,167 @@
+"""Pins of the oracle's Remez (Algorithm 3.1) against the paper and the mathematics.
+
+Each pin would fail on a plausible mistake: a wrong sign convention for the
+levelled system, a dropped basis term, a transposed Chebyshev/monomial
+conversion, a wrong residue formula or a wrong pole ordering.
+"""
+
+import json
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+from conftest import golden_path, oracle_bura
+
+
+def _load(name):
+    with open(golden_path(name)) as fh:
+        return json.load(fh)
+
+
+T1 = _load("table1_bura_errors.json")
+T6 = _load("table6_bura_errors_m57.json")
+COEF = _load("tables2to4_8_bura_coefficients.json")
+APP6 = _load("table11_eigvec_errors_k7.json")
+
+
+# --- Table 1: E_alpha(k,k;beta) ------------------------------------------------
+
+@pytest.mark.parametrize("row", T1["rows"], ids=lambda r: f"alpha{r[0]}")
+@pytest.mark.parametrize("col,mkb", [(1, (5, 5, 1)), (2, (6, 6, 1)), (3, (7, 7, 1)), (4, (5, 5, 2)), (5, (5, 5, 3))])
+def test_table1_errors(row, col, mkb):
+    alpha, printed = row[0], row[col]
+    m, k, beta = mkb
+    E = abs(float(oracle_bura(alpha, k, m, beta).E))
+    # printed to 5 significant digits; the alpha = 0.75 column is at the
+    # paper's own precision limit (its tables disagree by ~0.4 %), pinned to 1 %
+    tol = 1e-2 if alpha == 0.75 else 2e-4
+    assert abs(E - printed) <= tol * printed, (alpha, mkb, E, printed)
+
+
+@pytest.mark.parametrize("row", T6["rows"][3:], ids=lambda r: f"alpha{r[0]}")
+@pytest.mark.parametrize("col", [1, 2, 3, 4])
+def test_table6_alpha_0_1(row, col):
+    """Table 6, alpha = 0.1 row: E(5,5;1), E(5,4;2), E(5,3;3), E(7,7;1)."""
+    m, k, beta = T6["mkb"][col - 1]
+    E = abs(float(oracle_bura(row[0], k, m, beta).E))
+    assert abs(E - row[col]) <= 2e-4 * row[col]
+
+
+def test_asymptotic_formula_overestimates_moderately():
+    """eq. (14) vs Table 1: the asymptotic value lies within 1.2x..1.6x of E."""
+    from oracle.remez import stahl_estimate
+    for alpha in (0.25, 0.5, 0.75):
+        for k in (5, 7):
+            ratio = float(stahl_estimate(alpha, k)) / abs(float(oracle_bura(alpha, k).E))
+            assert 1.1 < ratio < 1.7, (alpha, k, ratio)
+
+
+# --- Lemma 2.5: characterisation of the (k,k) 1-BURA --------------------------
+
+@pytest.mark.parametrize("alpha,k", [(0.5, 5), (0.25, 7), (0.75, 5), (0.1, 5)])
+def test_equioscillation(alpha, k):
+    """2k+2 alternation points, t=0 and t=1 among them, t^(1-a) - r = (-1)^j E."""
+    b = oracle_bura(alpha, k)
+    E = b.E
+    assert E > 0
+    assert len(b.eta) == 2 * k + 2
+    assert b.eta[0] == 0 and b.eta[-1] == 1
+    with mp.workdps(b.dps):
+        for j, (t, e) in enumerate(zip(b.eta, b.eta_err), start=1):
+            assert abs(e - (-1) ** j * E) <= mp.mpf(10) ** -18 * E
+        # no point of [0,1] has a larger error (dense log grid + uniform grid)
+        grid = [mp.mpf(10) ** (-x / mp.mpf(20)) for x in range(0, 600)] + [mp.mpf(i) / 200 for i in range(201)]
+        worst = max(abs(b.err(t)) for t in grid)
+    assert worst <= E * (1 + mp.mpf(10) ** -12)
+
+
+@pytest.mark.parametrize("alpha,k", [(0.5, 5), (0.25, 7), (0.75, 7)])
+def test_poles_zeros_interlace_and_weights_positive(alpha, k):
+    b = oracle_bura(alpha, k)
+    with mp.workdps(b.dps):
+        zeros = sorted((mp.re(z) for z in mp.polyroots(list(reversed(b.p)), maxsteps=400, extraprec=4 * b.dps)),
+                       reverse=True)
+    d = b.d[1:]
+    # 0 > z_1 > d_1 > z_2 > d_2 > ... > z_k > d_k
+    seq = []
+    for z, p in zip(zeros, d):
+        seq += [z, p]
+    assert all(x < 0 for x in seq)
+    assert all(seq[i] > seq[i + 1] for i in range(len(seq) - 1))
+    assert all(c > 0 for c in b.c)
+
+
+@pytest.mark.parametrize("alpha,k", [(0.5, 5), (0.25, 7), (0.75, 5)])
+def test_identities(alpha, k):
+    """eq. (23): c_0 = r(0) = E;  eq. (24): sum c_j = p_k/q_k;  r(1) = 1 - E."""
+    b = oracle_bura(alpha, k)
+    with mp.workdps(b.dps):
+        tol = mp.mpf(10) ** -25
+        assert abs(b.c[0] - b.E) <= tol * b.E
+        assert abs(mp.fsum(b.c) - b.p[-1] / b.q[-1]) <= tol
+        assert abs(b.r(1) - (1 - b.E)) <= tol
+
+
+@pytest.mark.parametrize("alpha,k", [(0.5, 5), (0.75, 7)])
+def test_fraction_form_matches_chebyshev_form(alpha, k):
+    """eq. (15) reconstructs eq. (18) on log-spaced t down to 1e-30."""
+    b = oracle_bura(alpha, k)
+    with mp.workdps(b.dps):
+        for x in range(0, 31):
+            t = mp.mpf(10) ** (-x)
+            assert abs(b.r_from_fractions(t) - b.r(t)) <= mp.mpf(10) ** -25 * (b.r(t) + b.E)
+
+
+# --- Tables 2-4, 8 and eq. (17): printed coefficients --------------------------
+
+@pytest.mark.parametrize("alpha", ["0.5", "0.25", "0.75"])
+def test_tables_2_to_4(alpha):
+    ref = COEF["k5"][alpha]
+    b = oracle_bura(float(alpha), 5)
+    tol = 2e-2 if alpha == "0.75" else 1.5e-5      # 6 printed digits; see Table 1 note for 0.75
+    for key in ("c", "p", "q"):
+        got = [float(x) for x in getattr(b, key)]
+        for g, r in zip(got, ref[key]):
+            assert abs(g - r) <= tol * abs(r), (key, g, r)
+    for g, r in zip(b.d_f64[1:], ref["d"][1:]):
+        assert abs(g - r) <= tol * abs(r), ("d", g, r)
+
+
+@pytest.mark.parametrize("alpha", ["0.5", "0.25"])
+def test_table8_k7(alpha):
+    ref = COEF["k7"][alpha]
+    b = oracle_bura(float(alpha), 7)
+    for g, r in zip(b.c_f64, ref["c"]):
+        assert abs(g - r) <= 1.5e-5 * abs(r)
+    for g, r in zip(b.d_f64[1:], ref["d"][1:]):
+        assert abs(g - r) <= 1.5e-5 * abs(r)
+
+
+def test_eq17_fractions():
+    ref = COEF["eq17_alpha0.5_k5"]
+    b = oracle_bura(0.5, 5)
+    for g, r in zip(b.c_f64, ref["c"]):
+        assert abs(g - r) <= 6e-8
+    for g, r in zip(b.d_f64, ref["minus_d"]):
+        assert abs(-g - r) <= 6e-8
+
+
+# --- Table 11: deterministic eigenvector columns of the 1D validation ----------
+
+@pytest.mark.parametrize("alpha", ["0.25", "0.5", "0.75"])
+def test_table11_eigenvector_columns(alpha):
+    """For f = Psi_i, ||u_r - u||_A / ||f||_{A^-1} = |r(Lambda_i) - Lambda_i^(1-alpha)|."""
+    b = oracle_bura(float(alpha), 7)
+    c, d = np.array(b.c_f64), np.array(b.d_f64)
+    a = float(alpha)
+    tol = 1e-2 if alpha == "0.75" else 3e-4
+    for N, cols in APP6["rows"].items():
+        N = int(N)
+        i = np.arange(1, N + 1)
+        lam = np.sin(i * np.pi / (2 * (N + 1))) ** 2
+        r = lam * sum(cj / (lam - dj) for cj, dj in zip(c, d))
+        err = np.abs(r - lam ** (1 - a))
+        mean_ref, max_ref = cols[alpha]
+        assert abs(err.mean() - mean_ref) <= tol * mean_ref, (N, err.mean(), mean_ref)
+        assert abs(err.max() - max_ref) <= tol * max_ref, (N, err.max(), max_ref)
