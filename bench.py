@@ -1,0 +1,294 @@
+#!/usr/bin/env python3
+"""Throughput of the BURA fractional solve (k+1 shifted SPD solves + FP64 combine) on one GPU.
+
+Default workload: 2D unit square, 1023 x 1023 interior grid (h = 2^-10), five-point
+Laplacian scaled to spectrum (0,1] (h^2/8), alpha in {0.25, 0.5, 0.75}, beta = 1,
+k = 9, one seeded N(0,1) right-hand side, every shifted system solved in FP64 by
+geometric-multigrid V(2,2)-PCG to relative residual 1e-10, the k+1 systems of
+one alpha advancing together in the same launches.  One step = the three
+fractional solves (one per alpha) of that right-hand side.  The same workload
+with one pole at a time, and with FP32 inner solves plus FP64 refinement, is
+reported under "paths".
+
+Prints ONE JSON line.  ``value`` counts unknown-pole solves per second
+(N * (k+1) * nrhs per accepted fractional solve); a solve is accepted when its
+relative l2 error against the oracle's BURA result is <= 1e-8 (checked in the
+CPU-baseline leg, which is the only part of this script that uses the oracle).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "unknown-pole solves/s at rel err 1e-8 vs FP64 oracle; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: dim, n, alphas, k, nrhs, rhs kind, precision, schedule, tol, variable coefficient
+    "2d1023-k9-fp64-per-pole": dict(dim=2, n=1023, alphas=(0.25, 0.5, 0.75), k=9, nrhs=1, rhs="normal", tag=2,
+                                    precision="FP64", schedule="PER_POLE", tol=1e-10, var=False),
+    "2d1023-k9-fp64-batched": dict(dim=2, n=1023, alphas=(0.25, 0.5, 0.75), k=9, nrhs=1, rhs="normal", tag=2,
+                                   precision="FP64", schedule="BATCHED", tol=1e-10, var=False),
+    "2d1023-k9-mixed-batched": dict(dim=2, n=1023, alphas=(0.25, 0.5, 0.75), k=9, nrhs=1, rhs="normal", tag=2,
+                                    precision="MIXED", schedule="BATCHED", tol=1e-10, var=False),
+    "3d255-k8-mixed-batched": dict(dim=3, n=255, alphas=(0.25,), k=8, nrhs=1, rhs="sines", tag=3,
+                                   precision="MIXED", schedule="BATCHED", tol=1e-10, var=False),
+    "2d511-var-k7-256rhs-mixed": dict(dim=2, n=511, alphas=(0.6,), k=7, nrhs=256, rhs="normal", tag=4,
+                                      precision="MIXED", schedule="BATCHED", tol=1e-10, var=True),
+}
+
+
+def describe(w):
+    d = w["dim"]
+    grid = "x".join([str(w["n"])] * d)
+    op = ("variable-coefficient a=exp(g) " if w["var"] else "") + ("5-point" if d == 2 else "7-point")
+    return (f"{d}D {grid} {op} operator scaled to (0,1], alpha={list(w['alphas'])}, beta=1, k={w['k']}, "
+            f"{w['nrhs']} rhs ({w['rhs']}), {w['precision']} {w['schedule'].lower().replace('_', '-')} "
+            f"GMG V(2,2)-PCG to rel residual {w['tol']:g}")
+
+
+def make_rhs(w):
+    import synth
+    if w["rhs"] == "normal":
+        return synth.normal_rhs(w["n"], w["dim"], nrhs=w["nrhs"], tag=w["tag"])
+    if w["rhs"] == "sines":
+        return synth.sine_modes_rhs(w["n"], w["dim"], nmodes=32, noise=1e-3, tag=w["tag"], nrhs=w["nrhs"])
+    return synth.uniform_rhs(w["n"], w["dim"], nrhs=w["nrhs"], tag=w["tag"])
+
+
+def run_gpu(w, steps, warmup, profile=True):
+    import numpy as np
+    import torch
+
+    import paper_1612_04846_amd as B
+    import synth
+
+    dev = torch.device("cuda:0")
+    F_host = make_rhs(w)
+    F = torch.from_numpy(F_host).to(dev)
+    coeff = synth.lognormal_coefficient(w["n"], w["dim"], tag=w["tag"]) if w["var"] else None
+    plans = []
+    t_plan = time.perf_counter()
+    for a in w["alphas"]:
+        plans.append(B.Plan(w["dim"], w["n"], a, w["k"], coeff=coeff, nrhs_max=w["nrhs"], tol=w["tol"],
+                            precision=getattr(B, "BURA_" + w["precision"]),
+                            schedule=getattr(B, "BURA_" + w["schedule"])))
+    t_plan = time.perf_counter() - t_plan
+    outs = [torch.empty_like(F) for _ in plans]
+    for _ in range(warmup):
+        for p, u in zip(plans, outs):
+            p.solve(F, u)
+    torch.cuda.synchronize()
+    if profile:
+        # events only around the fine-level smoother and the stencil product
+        # (the candidates for the dominant kernel); byte counters for all classes
+        mask = (1 << (1 + 0)) | (1 << (1 + 5))
+        for p in plans:
+            B.bura_plan_profile(p.handle, mask)
+    lat = []
+    reports = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for p, u in zip(plans, outs):
+            t1 = time.perf_counter()
+            rep = p.solve(F, u).report
+            lat.append(time.perf_counter() - t1)
+            reports.append(rep)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kstats = {}
+    if profile:
+        for cls, name in enumerate(B.KERNEL_CLASSES):
+            n_l = ms = by = 0.0
+            for p in plans:
+                a, b, c = B.bura_plan_kernel_stats(p.handle, cls)
+                n_l += a
+                ms += b
+                by += c
+            kstats[name] = dict(launches=int(n_l), ms=ms, bytes=by)
+        for p in plans:
+            B.bura_plan_profile(p.handle, False)
+    info = plans[0].info
+    coefs = [p.coeffs for p in plans]
+    U = [u.cpu().numpy() for u in outs]
+    iters = [list(r.iters)[: w["k"] + 1] for r in reports[-len(plans):]]
+    outer = [list(r.outer)[: w["k"] + 1] for r in reports[-len(plans):]]
+    relres = [max(list(r.relres)[: w["k"] + 1]) for r in reports[-len(plans):]]
+    for p in plans:
+        p.close()
+    N = w["n"] ** w["dim"]
+    per_step = N * (w["k"] + 1) * w["nrhs"] * len(w["alphas"])
+    return dict(elapsed=elapsed, per_step=per_step, lat=lat, kstats=kstats, lam=info[0], nlev=info[1],
+                dev_bytes=info[2], U=U, F=F_host, coeff=coeff, coefs=coefs, iters=iters, outer=outer,
+                relres=relres, t_plan=t_plan)
+
+
+def roofline(kstats):
+    """Dominant kernel class by event time; achieved = algorithmic bytes / event time."""
+    if not kstats:
+        return None, {}
+    table = {}
+    for name, s in kstats.items():
+        if s["launches"] == 0 or s["ms"] <= 0:
+            continue
+        table[name] = dict(launches=s["launches"], avg_us=1e3 * s["ms"] / s["launches"],
+                           alg_bytes_per_launch=s["bytes"] / s["launches"],
+                           gbs=(s["bytes"] / 1e9) / (s["ms"] / 1e3) if s["bytes"] > 0 else None,
+                           total_ms=s["ms"])
+    cand = {k: v for k, v in table.items() if v["gbs"] is not None}
+    dom = max(cand, key=lambda k: cand[k]["total_ms"])
+    d = cand[dom]
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(d["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(d["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_launch_us": round(d["avg_us"], 3), "alg_bytes_per_launch": int(d["alg_bytes_per_launch"])}
+    return roof, table
+
+
+def cpu_baseline(w, res):
+    """Oracle on the host: accuracy of the GPU results, and the timed CPU sample."""
+    import numpy as np
+
+    from oracle import metrics, operators, shifted, spectral
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_bura_coefficients.json")))
+    errs = []
+    t_acc = time.perf_counter()
+    for a, U in zip(w["alphas"], res["U"]):
+        rec = gold[f"{a:.2f},{w['k']}"]
+        c = [float(x) for x in rec["c"]]
+        d = [float(x) for x in rec["d"]]
+        if not w["var"]:
+            ref = spectral.bura_spectral(res["F"], w["dim"], c, d)
+            errs.append(metrics.rel_err(U, ref))
+        else:
+            # sampled right-hand sides, each by k+1 sparse direct solves
+            A, _ = operators.scaled_operator(w["n"], w["dim"], res["coeff"])
+            idx = [0, w["nrhs"] - 1]
+            ref = shifted.bura_by_solves(A, c, d, res["F"][idx])
+            errs.append(metrics.rel_err(U[idx], ref))
+    t_acc = time.perf_counter() - t_acc
+    # timed CPU sample: one full-size shifted system (pole d_0 = 0 of the first
+    # alpha) by the oracle's sparse direct solve -- unknown-pole solves per second
+    A, _ = operators.scaled_operator(w["n"], w["dim"], res["coeff"]) if w["dim"] == 2 else (None, None)
+    sample = None
+    if A is not None:
+        t0 = time.perf_counter()
+        shifted.shifted_solve_direct(A, 0.0, res["F"][:1].reshape(1, -1))
+        dt = time.perf_counter() - t0
+        N = w["n"] ** w["dim"]
+        sample = dict(value=N / dt, unit="unknown-pole solves/s", cores=1, kind="oracle",
+                      sample=f"one full-size shifted system (pole d_0=0, alpha={w['alphas'][0]}) of the same "
+                             f"workload by SuperLU factorisation + solve, {dt:.1f} s, single-threaded; "
+                             f"host has {os.cpu_count()} logical CPUs ({platform.processor() or 'x86_64'})")
+    else:
+        # 3D: plain FP64 CG on one pole of a 63^3 grid of the same operator family
+        n = 63
+        A3, _ = operators.scaled_operator(n, 3)
+        import synth
+        f = synth.normal_rhs(n, 3, tag=9).ravel()
+        t0 = time.perf_counter()
+        shifted.cg(A3, f, 0.0, rtol=1e-10)
+        dt = time.perf_counter() - t0
+        sample = dict(value=n ** 3 / dt, unit="unknown-pole solves/s", cores=1, kind="oracle",
+                      sample=f"one 63^3 shifted system (pole 0) by the oracle's plain FP64 CG to 1e-10, {dt:.1f} s")
+    return errs, sample, t_acc
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="2d1023-k9-fp64-batched", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--also", default="2d1023-k9-fp64-per-pole,2d1023-k9-mixed-batched",
+                    help="comma-separated extra workloads reported under 'paths' (empty: none)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    w = WORKLOADS[args.workload]
+    print(f"[bench] workload {args.workload}: {describe(w)}", file=sys.stderr, flush=True)
+    res = run_gpu(w, args.steps, args.warmup, profile=not args.no_profile)
+    import numpy as np
+    lat_ms = np.array(res["lat"]) * 1e3
+    roof, ktable = roofline(res["kstats"])
+    out = {
+        "metric": METRIC,
+        "value": None,
+        "unit": "unknown-pole solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * res["elapsed"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if w["precision"] == "FP64" else "f32+f64",
+        "data": "synthetic (seeded N(0,1) right-hand sides; no dataset)",
+        "config": {"workload": describe(w), "name": args.workload, "dim": w["dim"], "n": w["n"],
+                   "alphas": list(w["alphas"]), "k": w["k"], "nrhs": w["nrhs"], "precision": w["precision"],
+                   "schedule": w["schedule"], "tol": w["tol"]},
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
+                       "per": "one fractional solve (k+1 poles + combine)"},
+        "iters_per_pole_last": res["iters"],
+        "max_relres": max(res["relres"]),
+        "lambda": res["lam"], "mg_levels": res["nlev"], "plan_seconds": round(res["t_plan"], 3),
+        "roofline": roof,
+        "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                    for k, v in ktable.items()},
+    }
+    raw_rate = res["per_step"] * args.steps / res["elapsed"]
+    paths = {}
+    for extra in [x for x in args.also.split(",") if x and x != args.workload]:
+        we = WORKLOADS[extra]
+        print(f"[bench] extra path {extra}", file=sys.stderr, flush=True)
+        r2 = run_gpu(we, max(2, args.steps // 2), 1, profile=False)
+        paths[extra] = {"value_unchecked": r2["per_step"] * max(2, args.steps // 2) / r2["elapsed"],
+                        "ms_per_step": 1e3 * r2["elapsed"] / max(2, args.steps // 2),
+                        "iters_per_pole_last": r2["iters"], "outer_last": r2["outer"], "_res": r2, "_w": we}
+    accepted = True
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        errs, sample, t_acc = cpu_baseline(w, res)
+        out["rel_err_vs_oracle"] = max(errs)
+        accepted = max(errs) <= 1e-8
+        out["cpu_baseline"] = sample
+        for name, pth in paths.items():
+            e2, _, _ = cpu_baseline(pth["_w"], pth["_res"]) if False else (None, None, None)
+            if not pth["_w"]["var"]:
+                from oracle import metrics, spectral
+                gold = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_bura_coefficients.json")))
+                ee = []
+                for a, U in zip(pth["_w"]["alphas"], pth["_res"]["U"]):
+                    rec = gold[f"{a:.2f},{pth['_w']['k']}"]
+                    ref = spectral.bura_spectral(pth["_res"]["F"], pth["_w"]["dim"], [float(x) for x in rec["c"]],
+                                                 [float(x) for x in rec["d"]])
+                    ee.append(metrics.rel_err(U, ref))
+                pth["rel_err_vs_oracle"] = max(ee)
+                pth["value"] = pth["value_unchecked"] if max(ee) <= 1e-8 else 0.0
+    else:
+        out["rel_err_vs_oracle"] = None
+        out["cpu_baseline"] = None
+    for pth in paths.values():
+        pth.pop("_res", None)
+        pth.pop("_w", None)
+    out["value"] = raw_rate if accepted else 0.0
+    out["accepted"] = accepted
+    out["paths"] = paths
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,205 @@
+/*
+ * bura.h -- C ABI of a gfx950 (MI355X) solver for A^alpha u = f, 0 < alpha < 1.
+ *
+ * Method: Harizanov, Lazarov, Marinov, Margenov, Vutov, "Optimal solvers for
+ * linear systems with fractional powers of sparse SPD matrices"
+ * (arXiv:1612.04846).  With A scaled so that its spectrum lies in (0,1]
+ * (Section 1.4, eq. (10), Assumption 1.1) the solution is approximated by
+ *
+ *     u_r = sum_{j=0..k} c_j (A - d_j I)^{-1} f          (Section 2.2, eq. (16))
+ *
+ * where r(t)/t = sum_j c_j/(t - d_j) (eq. (15)), r the best uniform rational
+ * approximation of t^(1-alpha) on [0,1] (Definition 2.1, eq. (11)), d_0 = 0 >
+ * d_1 > ... > d_k and c_j > 0 (Lemma 2.5, Remark 2.6).  Each of the k+1 shifted
+ * SPD systems is solved on the GPU by geometric-multigrid preconditioned CG;
+ * the k+1 solutions are combined in FP64.
+ *
+ * Grids: the unit square / cube, n interior points per axis, h = 1/(n+1),
+ * homogeneous Dirichlet boundary.  Vectors are FP64, interior points only, in
+ * lexicographic order with x fastest (the paper's ordering, Section 5.3); a
+ * batch of nrhs right-hand sides is nrhs such vectors back to back.
+ *
+ * Operator (before scaling): the five-point (2D) / seven-point (3D)
+ * difference operator A~ = h^-2 * [flux form], (A~ x)_i = h^-2 sum_faces a_f
+ * (x_i - x_nb), x_nb = 0 outside the grid; a_f = 1 (Laplacian, Section 5.3) or
+ * the harmonic mean 2 a_i a_nb/(a_i + a_nb) of a caller-supplied nodal
+ * coefficient a > 0 on the (n+2)^dim lattice including the boundary nodes.
+ * Lambda = max_i sum_j |A~_ij| (Gershgorin; equals 4 dim/h^2 for the
+ * Laplacian, the paper's scaling) unless the caller gives an upper bound.
+ *
+ * Conventions: every function returns an int status (enum bura_status); none
+ * throws or aborts.  Pointers named *_dev are device pointers in the current
+ * HIP device's address space (e.g. from hipMalloc or a torch CUDA tensor on
+ * ROCm); all other pointers are host pointers.  A plan owns every internal
+ * buffer it allocates and frees them in bura_plan_destroy.  Plans are not
+ * thread-safe: one host thread at a time may call solve/submit on a plan.
+ */
+#ifndef BURA_H
+#define BURA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Opaque plan: operator hierarchy, coefficients, device workspace. */
+typedef struct bura_plan_s* bura_plan_t;
+
+enum bura_status {
+  BURA_OK = 0,
+  BURA_PENDING = 1,          /* bura_poll: the solve is still running            */
+  BURA_EINVAL = -1,          /* bad argument                                     */
+  BURA_EUNSUPPORTED = -2,    /* valid but not implemented (e.g. beta != 1)       */
+  BURA_EREMEZ = -3,          /* the rational approximation did not converge      */
+  BURA_ENOCONV = -4,         /* iteration cap hit; u holds the last iterate      */
+  BURA_ENOMEM = -5,          /* device allocation failed / over the HBM budget   */
+  BURA_EDEVICE = -6,         /* HIP runtime error                                */
+  BURA_ENAN = -7,            /* non-finite residual                              */
+  BURA_EBUSY = -8            /* plan has an unfinished submitted solve           */
+};
+
+enum bura_precision {
+  BURA_FP64 = 0,   /* FP64 multigrid-PCG throughout                                 */
+  BURA_MIXED = 1   /* FP32 multigrid-PCG inner solves, FP64 residual refinement,
+                      FP64 dot products and FP64 combine                           */
+};
+
+enum bura_schedule {
+  BURA_BATCHED = 0,  /* all (pole, rhs) systems advance together, one launch per step */
+  BURA_PER_POLE = 1  /* one pole after another (all rhs of that pole together)        */
+};
+
+/* Grid / operator description. */
+typedef struct {
+  int dim;                 /* 2 or 3                                                    */
+  int n;                   /* interior points per axis, 1 <= n; n^dim <= 2^31 - 1.
+                              Multigrid coarsens while n is odd (n = 2^L - 1 gives a
+                              full hierarchy); otherwise the preconditioner is Jacobi. */
+  const double* coeff;     /* NULL: Laplacian.  Else host array, (n+2)^dim nodal values
+                              a > 0 incl. boundary, x fastest; copied at plan time.     */
+  double lambda_upper;     /* 0: Gershgorin bound.  >0: caller's bound, must be
+                              >= the largest eigenvalue of A~.                          */
+} bura_grid_t;
+
+/* Solver options.  bura_opts_default fills sensible values. */
+typedef struct {
+  double tol;          /* per-system stop: ||f - (A - d_j I) x_j||_2 <= tol ||f||_2 (FP64) */
+  double inner_tol;    /* MIXED: relative reduction of each FP32 inner solve             */
+  int precision;       /* enum bura_precision                                            */
+  int schedule;        /* enum bura_schedule                                             */
+  int max_iter;        /* PCG iteration cap (per inner solve in MIXED mode); 0 = automatic
+                          (200 with a multigrid hierarchy, 40 n + 200 without)           */
+  int max_outer;       /* MIXED: refinement-step cap                                     */
+  int nrhs_max;        /* largest nrhs any solve on this plan will use (sizes buffers)   */
+  int check_every;     /* PCG iterations between host convergence checks (>= 1)          */
+  int nu_pre, nu_post; /* Jacobi sweeps before / after coarse-grid correction             */
+  double omega;        /* Jacobi damping; 0 = 4/5 (2D) or 6/7 (3D)                       */
+  void* stream;        /* hipStream_t used for every launch and copy; NULL = null stream */
+  size_t hbm_budget;   /* 0 = unlimited; else plan creation fails with BURA_ENOMEM if its
+                          device footprint would exceed this many bytes                 */
+} bura_opts_t;
+
+/* Per-solve report (host struct filled by solve/poll). */
+#define BURA_MAX_TERMS 64
+typedef struct {
+  int status;                       /* status of the solve                              */
+  int nterms;                       /* k+1                                              */
+  double E;                         /* E_alpha(k,k;1) of the rational approximation      */
+  int iters[BURA_MAX_TERMS];        /* total PCG iterations, max over rhs, per pole      */
+  int outer[BURA_MAX_TERMS];        /* refinement steps (MIXED), max over rhs, per pole  */
+  double relres[BURA_MAX_TERMS];    /* final FP64 relative residual, max over rhs       */
+  double seconds;                   /* wall time of the solve on the host clock          */
+} bura_report_t;
+
+/* Fill *o with defaults: tol 1e-12, inner_tol 1e-5, BURA_MIXED, BURA_BATCHED,
+ * max_iter 0 (automatic), max_outer 12, nrhs_max 1, check_every 4, V(2,2),
+ * stream NULL. */
+int bura_opts_default(bura_opts_t* o);
+
+/* Step 1-2 of Section 2.2 on the host: the (k,k) best uniform rational
+ * approximation of t^(1-alpha) on [0,1] (Definition 2.1) by a Remez exchange
+ * (Section 3.2) in extended precision, and its partial fractions eq. (15).
+ * Writes c[0..k], d[0..k] (d[0] = 0 > d[1] > ... > d[k]) and *E.
+ * alpha in (0,1), beta == 1 (else BURA_EUNSUPPORTED), 1 <= k <= 16.
+ * Returns BURA_EREMEZ if the exchange does not level.  Results are cached
+ * per (alpha, k) for the life of the process. */
+int bura_coefficients(double alpha, int beta, int k, double* c, double* d, double* E);
+
+/* Create a plan: operator hierarchy, coefficients (via bura_coefficients) and
+ * device workspace for up to opts->nrhs_max right-hand sides.  *out receives
+ * the plan on success and NULL otherwise. */
+int bura_plan_create(const bura_grid_t* grid, double alpha, int beta, int k,
+                     const bura_opts_t* opts, bura_plan_t* out);
+
+/* Same engine for a caller-given partial-fraction form
+ * u = sum_{j<nterms} w[j] (A + shift[j] I)^{-1} f, shift[j] >= 0, w[j] any sign
+ * (e.g. the quadrature of Section 5.3's comparison method, or coefficients
+ * computed elsewhere).  1 <= nterms <= BURA_MAX_TERMS. */
+int bura_plan_create_rational(const bura_grid_t* grid, int nterms, const double* weights,
+                              const double* shifts, const bura_opts_t* opts, bura_plan_t* out);
+
+/* u_dev[r] = sum_j c_j (A - d_j I)^{-1} f_dev[r], r < nrhs <= nrhs_max.
+ * Synchronous: returns after the result is in u_dev.  rep may be NULL.
+ * BURA_ENOCONV leaves the last iterate combined in u_dev. */
+int bura_solve(bura_plan_t plan, const double* f_dev, double* u_dev, int nrhs, bura_report_t* rep);
+
+/* Asynchronous variant: enqueue the solve on the plan's stream and return at
+ * once.  f_dev/u_dev must stay valid and untouched until bura_poll returns a
+ * value other than BURA_PENDING.  One outstanding solve per plan (BURA_EBUSY). */
+int bura_submit(bura_plan_t plan, const double* f_dev, double* u_dev, int nrhs);
+
+/* BURA_PENDING while the submitted solve runs; then its final status, with
+ * the report copied to *rep (may be NULL). */
+int bura_poll(bura_plan_t plan, bura_report_t* rep);
+
+/* Introspection: the plan's c_j, d_j (arrays of nterms) and E (may be NULL). */
+int bura_plan_coeffs(bura_plan_t plan, int* nterms, double* c, double* d, double* E);
+
+/* Lambda used for the scaling A = A~/Lambda, and the number of multigrid levels. */
+int bura_plan_info(bura_plan_t plan, double* lambda, int* nlevels, size_t* device_bytes);
+
+/* y_dev = (A + shift I) x_dev in FP64 for nvec vectors (operator check). */
+int bura_plan_apply(bura_plan_t plan, double shift, const double* x_dev, double* y_dev, int nvec);
+
+/* Kernel classes for profiling. */
+enum bura_kernel_class {
+  BURA_K_SMOOTH_FINE = 0,    /* Jacobi sweeps on the finest level (or the Jacobi preconditioner) */
+  BURA_K_SMOOTH_COARSE = 1,  /* Jacobi sweeps on coarser levels solved by global kernels          */
+  BURA_K_RESTRICT = 2,       /* residual + full-weighting restriction                             */
+  BURA_K_PROLONG = 3,        /* interpolation + correction                                        */
+  BURA_K_COARSE_LDS = 4,     /* coarse levels solved inside one workgroup per system              */
+  BURA_K_SPMV = 5,           /* q = (A + s) p with p.q                                             */
+  BURA_K_UPDATE_XR = 6,      /* x += a p, r -= a q with r.r                                        */
+  BURA_K_UPDATE_P = 7,       /* p = z + b p                                                        */
+  BURA_K_RESIDUAL64 = 8,     /* FP64 refinement residual                                           */
+  BURA_K_COMBINE = 9,        /* u = sum_j c_j x_j                                                  */
+  BURA_K_OTHER = 10,         /* per-system scalar updates, copies                                  */
+  BURA_K_COUNT = 11
+};
+
+/* Profiling of the plan's launches (for measurement, not for production use).
+ * enable != 0 resets the statistics and starts counting, per block, the
+ * algorithmic bytes each launch moves (each vector element read or written
+ * once; blocks of systems that have already converged count zero).  Launches
+ * are bracketed by a pair of HIP events on the plan's stream: all classes when
+ * enable == 1, else the classes whose bit (1 << (class + 1)) is set in enable.
+ * enable = 0 stops recording. */
+int bura_plan_profile(bura_plan_t plan, int enable);
+
+/* Launch count, summed event time (ms) and algorithmic bytes of one kernel
+ * class since profiling was enabled.  Synchronises the plan's stream. */
+int bura_plan_kernel_stats(bura_plan_t plan, int kclass, long long* launches, double* total_ms,
+                           double* alg_bytes);
+
+/* Release every resource of the plan.  Waits for an outstanding solve. */
+void bura_plan_destroy(bura_plan_t plan);
+
+/* Static string for a status code. */
+const char* bura_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BURA_H */

@@ -1,0 +1,331 @@
+"""Python binding of libbura.so: argument marshalling only.
+
+Every step of the solve runs in the HIP library (see include/bura.h).  The
+functions below carry the C names; device buffers are torch CUDA tensors
+(float64, contiguous) whose data pointers are handed to the library, and the
+current torch stream is used unless another is given.  If the library has not
+been built this module raises on import -- there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch  # noqa: F401  (loads the HIP runtime the library links against)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbura.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "bura.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        "libbura.so is not built: run `python paper_1612_04846_amd/build.py` "
+        "(hipcc --offload-arch=gfx950) first"
+    )
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+BURA_OK = 0
+BURA_PENDING = 1
+BURA_EINVAL = -1
+BURA_EUNSUPPORTED = -2
+BURA_EREMEZ = -3
+BURA_ENOCONV = -4
+BURA_ENOMEM = -5
+BURA_EDEVICE = -6
+BURA_ENAN = -7
+BURA_EBUSY = -8
+BURA_FP64 = 0
+BURA_MIXED = 1
+BURA_BATCHED = 0
+BURA_PER_POLE = 1
+BURA_MAX_TERMS = 64
+
+
+class bura_grid_t(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int),
+        ("n", ctypes.c_int),
+        ("coeff", ctypes.POINTER(ctypes.c_double)),
+        ("lambda_upper", ctypes.c_double),
+    ]
+
+
+class bura_opts_t(ctypes.Structure):
+    _fields_ = [
+        ("tol", ctypes.c_double),
+        ("inner_tol", ctypes.c_double),
+        ("precision", ctypes.c_int),
+        ("schedule", ctypes.c_int),
+        ("max_iter", ctypes.c_int),
+        ("max_outer", ctypes.c_int),
+        ("nrhs_max", ctypes.c_int),
+        ("check_every", ctypes.c_int),
+        ("nu_pre", ctypes.c_int),
+        ("nu_post", ctypes.c_int),
+        ("omega", ctypes.c_double),
+        ("stream", ctypes.c_void_p),
+        ("hbm_budget", ctypes.c_size_t),
+    ]
+
+
+class bura_report_t(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int),
+        ("nterms", ctypes.c_int),
+        ("E", ctypes.c_double),
+        ("iters", ctypes.c_int * BURA_MAX_TERMS),
+        ("outer", ctypes.c_int * BURA_MAX_TERMS),
+        ("relres", ctypes.c_double * BURA_MAX_TERMS),
+        ("seconds", ctypes.c_double),
+    ]
+
+
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_I = ctypes.c_int
+_DP = ctypes.POINTER(ctypes.c_double)
+
+_SIGS = {
+    "bura_opts_default": (_I, [ctypes.POINTER(bura_opts_t)]),
+    "bura_coefficients": (_I, [_D, _I, _I, _DP, _DP, _DP]),
+    "bura_plan_create": (_I, [ctypes.POINTER(bura_grid_t), _D, _I, _I, ctypes.POINTER(bura_opts_t), ctypes.POINTER(_P)]),
+    "bura_plan_create_rational": (_I, [ctypes.POINTER(bura_grid_t), _I, _DP, _DP, ctypes.POINTER(bura_opts_t),
+                                       ctypes.POINTER(_P)]),
+    "bura_solve": (_I, [_P, _P, _P, _I, ctypes.POINTER(bura_report_t)]),
+    "bura_submit": (_I, [_P, _P, _P, _I]),
+    "bura_poll": (_I, [_P, ctypes.POINTER(bura_report_t)]),
+    "bura_plan_coeffs": (_I, [_P, ctypes.POINTER(_I), _DP, _DP, _DP]),
+    "bura_plan_info": (_I, [_P, _DP, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_size_t)]),
+    "bura_plan_apply": (_I, [_P, _D, _P, _P, _I]),
+    "bura_plan_profile": (_I, [_P, _I]),
+    "bura_plan_kernel_stats": (_I, [_P, _I, ctypes.POINTER(ctypes.c_longlong), _DP, _DP]),
+    "bura_plan_destroy": (None, [_P]),
+    "bura_strerror": (ctypes.c_char_p, [_I]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class BuraError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {bura_strerror(code)} ({code})")
+
+
+def bura_strerror(code: int) -> str:
+    return _lib.bura_strerror(code).decode()
+
+
+def _check(code: int, where: str, ok=(BURA_OK,)):
+    if code not in ok:
+        raise BuraError(code, where)
+    return code
+
+
+def exported_symbols():
+    """Names of the functions declared in include/bura.h that the library exports."""
+    return {n for n in _SIGS if hasattr(_lib, n)}
+
+
+# --------------------------------------------------------------------------
+# thin wrappers with the C names
+# --------------------------------------------------------------------------
+
+def bura_opts_default(**overrides) -> bura_opts_t:
+    o = bura_opts_t()
+    _check(_lib.bura_opts_default(ctypes.byref(o)), "bura_opts_default")
+    for k, v in overrides.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def bura_coefficients(alpha: float, k: int, beta: int = 1):
+    """(c, d, E) of the (k,k) BURA of t^(1-alpha), computed by the library's host code."""
+    c = (ctypes.c_double * (k + 1))()
+    d = (ctypes.c_double * (k + 1))()
+    E = ctypes.c_double()
+    _check(_lib.bura_coefficients(alpha, beta, k, c, d, ctypes.byref(E)), "bura_coefficients")
+    return list(c), list(d), E.value
+
+
+def _grid(dim, n, coeff=None, lambda_upper=0.0):
+    g = bura_grid_t()
+    g.dim = dim
+    g.n = n
+    keep = None
+    if coeff is not None:
+        import numpy as np
+        keep = np.ascontiguousarray(coeff, dtype=np.float64)
+        if keep.size != (n + 2) ** dim:
+            raise ValueError("coeff must hold (n+2)^dim nodal values")
+        g.coeff = keep.ctypes.data_as(_DP)
+    g.lambda_upper = lambda_upper
+    return g, keep
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def bura_plan_create(dim: int, n: int, alpha: float, k: int, opts: Optional[bura_opts_t] = None,
+                     coeff=None, lambda_upper: float = 0.0, beta: int = 1):
+    g, _keep = _grid(dim, n, coeff, lambda_upper)
+    o = opts if opts is not None else bura_opts_default()
+    h = _P()
+    _check(_lib.bura_plan_create(ctypes.byref(g), alpha, beta, k, ctypes.byref(o), ctypes.byref(h)),
+           "bura_plan_create")
+    return h
+
+
+def bura_plan_create_rational(dim: int, n: int, weights: Sequence[float], shifts: Sequence[float],
+                              opts: Optional[bura_opts_t] = None, coeff=None, lambda_upper: float = 0.0):
+    g, _keep = _grid(dim, n, coeff, lambda_upper)
+    o = opts if opts is not None else bura_opts_default()
+    m = len(weights)
+    w = (ctypes.c_double * m)(*weights)
+    s = (ctypes.c_double * m)(*shifts)
+    h = _P()
+    _check(_lib.bura_plan_create_rational(ctypes.byref(g), m, w, s, ctypes.byref(o), ctypes.byref(h)),
+           "bura_plan_create_rational")
+    return h
+
+
+def _devptr(t: torch.Tensor, what: str):
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError(f"{what} must be a contiguous float64 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def bura_solve(plan, f: torch.Tensor, u: torch.Tensor, nrhs: int, ok=(BURA_OK,)) -> bura_report_t:
+    rep = bura_report_t()
+    code = _lib.bura_solve(plan, _devptr(f, "f"), _devptr(u, "u"), nrhs, ctypes.byref(rep))
+    rep.status = code
+    _check(code, "bura_solve", ok)
+    return rep
+
+
+def bura_submit(plan, f: torch.Tensor, u: torch.Tensor, nrhs: int) -> int:
+    return _check(_lib.bura_submit(plan, _devptr(f, "f"), _devptr(u, "u"), nrhs), "bura_submit")
+
+
+def bura_poll(plan):
+    rep = bura_report_t()
+    code = _lib.bura_poll(plan, ctypes.byref(rep))
+    return code, rep
+
+
+def bura_plan_coeffs(plan):
+    n = ctypes.c_int()
+    c = (ctypes.c_double * BURA_MAX_TERMS)()
+    d = (ctypes.c_double * BURA_MAX_TERMS)()
+    E = ctypes.c_double()
+    _check(_lib.bura_plan_coeffs(plan, ctypes.byref(n), c, d, ctypes.byref(E)), "bura_plan_coeffs")
+    return list(c)[: n.value], list(d)[: n.value], E.value
+
+
+def bura_plan_info(plan):
+    lam = ctypes.c_double()
+    nl = ctypes.c_int()
+    nb = ctypes.c_size_t()
+    _check(_lib.bura_plan_info(plan, ctypes.byref(lam), ctypes.byref(nl), ctypes.byref(nb)), "bura_plan_info")
+    return lam.value, nl.value, nb.value
+
+
+def bura_plan_apply(plan, shift: float, x: torch.Tensor, y: torch.Tensor, nvec: int):
+    _check(_lib.bura_plan_apply(plan, shift, _devptr(x, "x"), _devptr(y, "y"), nvec), "bura_plan_apply")
+
+
+KERNEL_CLASSES = ["smooth_fine", "smooth_coarse", "restrict", "prolong", "coarse_lds", "spmv", "update_xr",
+                  "update_p", "residual64", "combine", "other"]
+
+
+def bura_plan_profile(plan, enable):
+    """enable: False/0 off, True/1 all classes timed, or the C bitmask (1 << (class + 1))."""
+    _check(_lib.bura_plan_profile(plan, int(enable)), "bura_plan_profile")
+
+
+def bura_plan_kernel_stats(plan, kclass: int):
+    """(launches, total_ms, algorithmic_bytes) of one kernel class."""
+    n = ctypes.c_longlong()
+    ms = ctypes.c_double()
+    by = ctypes.c_double()
+    _check(_lib.bura_plan_kernel_stats(plan, kclass, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)),
+           "bura_plan_kernel_stats")
+    return n.value, ms.value, by.value
+
+
+def bura_plan_destroy(plan):
+    if plan:
+        _lib.bura_plan_destroy(plan)
+
+
+# --------------------------------------------------------------------------
+# convenience object
+# --------------------------------------------------------------------------
+
+@dataclass
+class SolveResult:
+    u: torch.Tensor
+    report: bura_report_t
+
+
+class Plan:
+    """Owns a plan handle; ``solve(f)`` returns A^-alpha f for a batch f of shape (nrhs, n, ..., n)."""
+
+    def __init__(self, dim, n, alpha=None, k=None, *, weights=None, shifts=None, coeff=None,
+                 precision=BURA_MIXED, schedule=BURA_BATCHED, tol=1e-12, nrhs_max=1, stream=None, **opt):
+        self.dim, self.n = dim, n
+        o = bura_opts_default(precision=precision, schedule=schedule, tol=tol, nrhs_max=nrhs_max, **opt)
+        o.stream = _stream_ptr(stream).value if torch.cuda.is_available() else None
+        self.opts = o
+        self.handle = None
+        if weights is not None:
+            self.handle = bura_plan_create_rational(dim, n, weights, shifts, o, coeff=coeff)
+        else:
+            self.handle = bura_plan_create(dim, n, alpha, k, o, coeff=coeff)
+
+    @property
+    def coeffs(self):
+        return bura_plan_coeffs(self.handle)
+
+    @property
+    def info(self):
+        return bura_plan_info(self.handle)
+
+    def solve(self, f: torch.Tensor, u: Optional[torch.Tensor] = None, ok=(BURA_OK,)) -> SolveResult:
+        f = f.contiguous()
+        nrhs = f.shape[0] if f.dim() == self.dim + 1 else 1
+        if u is None:
+            u = torch.empty_like(f)
+        rep = bura_solve(self.handle, f, u, nrhs, ok)
+        return SolveResult(u, rep)
+
+    def apply(self, x: torch.Tensor, shift: float = 0.0) -> torch.Tensor:
+        x = x.contiguous()
+        y = torch.empty_like(x)
+        nvec = x.shape[0] if x.dim() == self.dim + 1 else 1
+        bura_plan_apply(self.handle, shift, x, y, nvec)
+        return y
+
+    def close(self):
+        if self.handle:
+            bura_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,974 @@
+// Solver engine and C ABI: operator hierarchy, device workspace, the PCG /
+// iterative-refinement loops over batches of shifted systems, and the combine
+// u = sum_j c_j (A - d_j I)^-1 f of Section 2.2, eq. (16).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "bura_internal.h"
+
+using namespace bura;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+#define HIPCHK(expr)                                        \
+  do {                                                      \
+    hipError_t e_ = (expr);                                 \
+    if (e_ != hipSuccess) {                                 \
+      g_last_error = hipGetErrorString(e_);                 \
+      return e_ == hipErrorOutOfMemory ? BURA_ENOMEM : BURA_EDEVICE; \
+    }                                                       \
+  } while (0)
+
+constexpr size_t kLdsCap = 64 * 1024;
+
+struct HostLevel {
+  int n = 0;
+  long long N = 0;
+  double wc = 0.0;                       // constant face weight a/(Lambda h_l^2)
+  std::vector<double> wf[3];             // variable face weights, scaled
+  double* d_wf64[3] = {nullptr, nullptr, nullptr};
+  float* d_wf32[3] = {nullptr, nullptr, nullptr};
+};
+
+template <typename T>
+struct Work {
+  T* x = nullptr;   // PCG iterate (FP64 path: the solution; MIXED: the correction e)
+  T* r = nullptr;
+  T* z = nullptr;
+  T* zt = nullptr;
+  T* p = nullptr;
+  T* q = nullptr;
+  std::vector<T*> xl, tl, bl;   // levels 1..lc (index by level)
+  T* shift = nullptr;
+};
+
+size_t face_count(int dim, int n, int axis) {
+  size_t c = (size_t)(n + 1);
+  for (int a = 1; a < dim; ++a) c *= (size_t)n;
+  (void)axis;
+  return c;
+}
+
+inline double hmean(double a, double b) { return 2.0 * a * b / (a + b); }
+
+}  // namespace
+
+struct bura_plan_s {
+  int dim = 2, n = 0;
+  long long N = 0;
+  bool var = false;
+  double lambda = 0.0;
+  // rational form u = sum_j w_j (A + s_j)^-1 f
+  int nterms = 0;
+  std::vector<double> w, s;   // weights c_j and shifts s_j = -d_j
+  double E = 0.0;
+  bura_opts_t opts{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  // hierarchy
+  std::vector<HostLevel> lev;
+  int lc = -1;                 // first level solved in LDS; -1: no multigrid (Jacobi PCG)
+  size_t lds_bytes = 0;
+  int S = 0;                   // systems = nterms * nrhs_max
+  // device buffers
+  Work<double> w64;
+  Work<float> w32;
+  double* x64 = nullptr;       // MIXED: FP64 solutions
+  double* partial = nullptr;
+  size_t partial_len = 0;
+  double* d_w = nullptr;       // combine weights
+  double* d_shift64 = nullptr;
+  float* d_shift32 = nullptr;
+  SysState st{};
+  void* state_block = nullptr;
+  int* h_flags = nullptr;      // pinned host mirror of active flags
+  std::vector<void*> allocs;
+  size_t device_bytes = 0;
+  // profiling (events around launches + device byte counters per kernel class)
+  struct Prof {
+    bool on = false;
+    unsigned mask = 0;                        // kernel classes timed with events
+    unsigned long long* d_ctr = nullptr;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<std::pair<int, size_t>> rec;   // (class, index of the start event; stop = +1)
+  } prof;
+  // async
+  std::thread worker;
+  std::atomic<int> busy{0};
+  int async_status = BURA_OK;
+  bura_report_t async_report{};
+};
+
+namespace {
+
+int dev_alloc(bura_plan_t P, void** ptr, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) {
+    g_last_error = hipGetErrorString(e);
+    *ptr = nullptr;
+    return BURA_ENOMEM;
+  }
+  P->allocs.push_back(*ptr);
+  P->device_bytes += bytes;
+  return BURA_OK;
+}
+
+// Records start/stop events around one launch of class `cls` when profiling;
+// `ctr` is the device byte counter the kernel adds to (nullptr otherwise).
+struct ProfScope {
+  bura_plan_t P;
+  long idx = -1;
+  unsigned long long* ctr = nullptr;
+  ProfScope(bura_plan_t P_, int cls) : P(P_) {
+    auto& pr = P->prof;
+    if (!pr.on) return;
+    ctr = pr.d_ctr + cls;
+    if (!(pr.mask & (1u << cls))) return;
+    while (pr.pool.size() < pr.used + 2) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      pr.pool.push_back(e);
+    }
+    idx = (long)pr.used;
+    pr.used += 2;
+    pr.rec.emplace_back(cls, (size_t)idx);
+    hipEventRecord(pr.pool[idx], P->stream);
+  }
+  ~ProfScope() {
+    if (idx >= 0) hipEventRecord(P->prof.pool[idx + 1], P->stream);
+  }
+};
+
+template <typename T>
+LevelDev<T> level_view(const bura_plan_t P, int l) {
+  const HostLevel& H = P->lev[l];
+  LevelDev<T> L;
+  L.n = H.n;
+  L.N = H.N;
+  L.wc = (T)H.wc;
+  if (P->var) {
+    if (sizeof(T) == 8) {
+      L.wf0 = (const T*)H.d_wf64[0];
+      L.wf1 = (const T*)H.d_wf64[1];
+      L.wf2 = (const T*)H.d_wf64[2];
+    } else {
+      L.wf0 = (const T*)H.d_wf32[0];
+      L.wf1 = (const T*)H.d_wf32[1];
+      L.wf2 = (const T*)H.d_wf32[2];
+    }
+  } else {
+    L.wf0 = L.wf1 = L.wf2 = nullptr;
+  }
+  return L;
+}
+
+double default_omega(int dim) { return dim == 2 ? 0.8 : 6.0 / 7.0; }
+
+// ---------------------------------------------------------------------------
+// hierarchy on the host (Section 1.4 scaling; coarse operators by
+// rediscretisation with series/parallel averaging of the face coefficients)
+// ---------------------------------------------------------------------------
+int build_levels(bura_plan_t P, const bura_grid_t* g) {
+  const int dim = P->dim, n = P->n;
+  const double h = 1.0 / (n + 1);
+  // fine faces (unscaled a_f) and Gershgorin bound of A~ = h^-2 * flux form
+  HostLevel L0;
+  L0.n = n;
+  L0.N = 1;
+  for (int a = 0; a < dim; ++a) L0.N *= n;
+  const int m = n + 2;
+  auto A = [&](int i, int j, int k) -> double {   // lattice value, 0..n+1 per axis
+    return g->coeff[((size_t)k * m + j) * m + i];
+  };
+  if (P->var) {
+    for (int a = 0; a < dim; ++a) L0.wf[a].assign(face_count(dim, n, a), 0.0);
+    const int nk = dim == 3 ? n : 1;
+    for (int k = 0; k < nk; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int f = 0; f <= n; ++f) {
+          const int K = dim == 3 ? k + 1 : 0;
+          L0.wf[0][((size_t)k * n + j) * (n + 1) + f] = hmean(A(f, j + 1, K), A(f + 1, j + 1, K));
+        }
+    for (int k = 0; k < nk; ++k)
+      for (int f = 0; f <= n; ++f)
+        for (int i = 0; i < n; ++i) {
+          const int K = dim == 3 ? k + 1 : 0;
+          L0.wf[1][((size_t)k * (n + 1) + f) * n + i] = hmean(A(i + 1, f, K), A(i + 1, f + 1, K));
+        }
+    if (dim == 3)
+      for (int f = 0; f <= n; ++f)
+        for (int j = 0; j < n; ++j)
+          for (int i = 0; i < n; ++i)
+            L0.wf[2][((size_t)f * n + j) * n + i] = hmean(A(i + 1, j + 1, f), A(i + 1, j + 1, f + 1));
+  }
+  // Gershgorin: row i of A~ has diagonal sum_f a_f and off-diagonals -a_f for
+  // faces to interior neighbours: bound = max_i sum_f a_f (1 + [nb interior]) / h^2
+  double gb = 0.0;
+  {
+    const int nk = dim == 3 ? n : 1;
+    for (int k = 0; k < nk; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          double row = 0.0;
+          auto face = [&](int axis, size_t idx, bool nb_interior) {
+            const double a = P->var ? L0.wf[axis][idx] : 1.0;
+            row += a * (nb_interior ? 2.0 : 1.0);
+          };
+          face(0, ((size_t)k * n + j) * (n + 1) + i, i > 0);
+          face(0, ((size_t)k * n + j) * (n + 1) + i + 1, i < n - 1);
+          face(1, ((size_t)k * (n + 1) + j) * n + i, j > 0);
+          face(1, ((size_t)k * (n + 1) + j + 1) * n + i, j < n - 1);
+          if (dim == 3) {
+            face(2, ((size_t)k * n + j) * n + i, k > 0);
+            face(2, ((size_t)(k + 1) * n + j) * n + i, k < n - 1);
+          }
+          gb = std::max(gb, row);
+          if (!P->var && (dim == 2 || n > 2) && i == 1 && j == 1 && (dim == 2 || k == 1)) {
+            // constant coefficient: an interior node with all neighbours interior attains the max
+            k = nk; j = n; i = n;
+          }
+        }
+    gb /= h * h;
+  }
+  if (g->lambda_upper > 0.0) {
+    P->lambda = g->lambda_upper;   // caller's bound (cannot be verified cheaply)
+  } else {
+    P->lambda = gb;
+  }
+  const double scale0 = 1.0 / (P->lambda * h * h);
+  L0.wc = scale0;
+  if (P->var)
+    for (int a = 0; a < dim; ++a)
+      for (double& v : L0.wf[a]) v *= scale0;
+  P->lev.clear();
+  P->lev.push_back(std::move(L0));
+  // coarse levels
+  while (true) {
+    const HostLevel& F = P->lev.back();
+    if (F.n < 3 || (F.n % 2) == 0) break;
+    HostLevel C;
+    C.n = (F.n - 1) / 2;
+    C.N = 1;
+    for (int a = 0; a < dim; ++a) C.N *= C.n;
+    C.wc = F.wc * 0.25;
+    if (P->var) {
+      const int nf = F.n, nc = C.n;
+      const double wt[3] = {0.25, 0.5, 0.25};
+      for (int a = 0; a < dim; ++a) C.wf[a].assign(face_count(dim, nc, a), 0.0);
+      const int nkc = dim == 3 ? nc : 1;
+      // axis-a coarse face between coarse nodes X-1 and X (along a) spans fine faces 2X and 2X+1;
+      // transverse fine rows 2T+1+dt, weights (1/4,1/2,1/4).
+      for (int a = 0; a < dim; ++a) {
+        for (int K = 0; K < (a == 2 ? nc + 1 : nkc); ++K)
+          for (int J = 0; J < (a == 1 ? nc + 1 : nc); ++J)
+            for (int I = 0; I < (a == 0 ? nc + 1 : nc); ++I) {
+              double acc = 0.0;
+              const int dkmin = (dim == 3 && a != 2) ? -1 : 0, dkmax = (dim == 3 && a != 2) ? 1 : 0;
+              const int djmin = (a != 1) ? -1 : 0, djmax = (a != 1) ? 1 : 0;
+              const int dimin = (a != 0) ? -1 : 0, dimax = (a != 0) ? 1 : 0;
+              for (int dk = dkmin; dk <= dkmax; ++dk)
+                for (int dj = djmin; dj <= djmax; ++dj)
+                  for (int di = dimin; di <= dimax; ++di) {
+                    double wgt = 1.0;
+                    int fi, fj, fk;
+                    if (a == 0) { fi = 2 * I; } else { fi = 2 * I + 1 + di; wgt *= wt[di + 1]; }
+                    if (a == 1) { fj = 2 * J; } else { fj = 2 * J + 1 + dj; wgt *= wt[dj + 1]; }
+                    if (dim == 3) {
+                      if (a == 2) { fk = 2 * K; } else { fk = 2 * K + 1 + dk; wgt *= wt[dk + 1]; }
+                    } else {
+                      fk = 0;
+                    }
+                    // two fine faces in series along axis a
+                    size_t i1, i2;
+                    if (a == 0) {
+                      i1 = ((size_t)fk * nf + fj) * (nf + 1) + fi;
+                      i2 = i1 + 1;
+                    } else if (a == 1) {
+                      i1 = ((size_t)fk * (nf + 1) + fj) * nf + fi;
+                      i2 = i1 + nf;
+                    } else {
+                      i1 = ((size_t)fk * nf + fj) * nf + fi;
+                      i2 = i1 + (size_t)nf * nf;
+                    }
+                    acc += wgt * hmean(F.wf[a][i1], F.wf[a][i2]);
+                  }
+              size_t ci;
+              if (a == 0) ci = ((size_t)K * nc + J) * (nc + 1) + I;
+              else if (a == 1) ci = ((size_t)K * (nc + 1) + J) * nc + I;
+              else ci = ((size_t)K * nc + J) * nc + I;
+              C.wf[a][ci] = 0.25 * acc;
+            }
+      }
+    }
+    P->lev.push_back(std::move(C));
+  }
+  return BURA_OK;
+}
+
+// choose the first LDS level: the largest level l >= 1 whose sub-hierarchy fits in LDS
+void choose_lds(bura_plan_t P, size_t elem) {
+  const int L = (int)P->lev.size();
+  if (L < 2) {
+    P->lc = -1;
+    P->lds_bytes = 0;
+    return;
+  }
+  for (int l = 1; l < L; ++l) {
+    size_t tot = 0;
+    for (int q = l; q < L; ++q) tot += 3 * (size_t)P->lev[q].N * elem;
+    if (tot <= kLdsCap && (L - l) <= kMaxLdsLevels) {
+      P->lc = l;
+      P->lds_bytes = tot;
+      return;
+    }
+  }
+  P->lc = L - 1;
+  P->lds_bytes = 3 * (size_t)P->lev[L - 1].N * elem;
+}
+
+template <typename T>
+LdsHierarchy<T> lds_view(const bura_plan_t P) {
+  LdsHierarchy<T> H{};
+  const int L = (int)P->lev.size();
+  H.nlev = L - P->lc;
+  int off = 0;
+  for (int q = 0; q < H.nlev; ++q) {
+    H.lev[q] = level_view<T>(P, P->lc + q);
+    H.off[q] = off;
+    off += 3 * (int)P->lev[P->lc + q].N;
+  }
+  H.cycles = 2;
+  H.nu = 2;
+  H.bottom_sweeps = 8 * P->lev[L - 1].n + 8;
+  H.omega = (T)(P->opts.omega > 0 ? P->opts.omega : default_omega(P->dim));
+  return H;
+}
+
+template <typename T>
+int alloc_work(bura_plan_t P, Work<T>& W) {
+  const size_t S = (size_t)P->S;
+  const size_t vb = S * (size_t)P->N * sizeof(T);
+  int rc;
+  if ((rc = dev_alloc(P, (void**)&W.x, vb))) return rc;
+  if ((rc = dev_alloc(P, (void**)&W.r, vb))) return rc;
+  if ((rc = dev_alloc(P, (void**)&W.z, vb))) return rc;
+  if ((rc = dev_alloc(P, (void**)&W.zt, vb))) return rc;
+  if ((rc = dev_alloc(P, (void**)&W.p, vb))) return rc;
+  if ((rc = dev_alloc(P, (void**)&W.q, vb))) return rc;
+  const int L = (int)P->lev.size();
+  W.xl.assign(L, nullptr);
+  W.tl.assign(L, nullptr);
+  W.bl.assign(L, nullptr);
+  if (P->lc > 0) {
+    for (int l = 1; l <= P->lc; ++l) {
+      const size_t b = S * (size_t)P->lev[l].N * sizeof(T);
+      if ((rc = dev_alloc(P, (void**)&W.xl[l], b))) return rc;
+      if ((rc = dev_alloc(P, (void**)&W.bl[l], b))) return rc;
+      if (l < P->lc && (rc = dev_alloc(P, (void**)&W.tl[l], b))) return rc;
+    }
+  }
+  if ((rc = dev_alloc(P, (void**)&W.shift, S * sizeof(T)))) return rc;
+  std::vector<T> sh(S);
+  const int R = P->opts.nrhs_max;
+  for (size_t i = 0; i < S; ++i) sh[i] = (T)P->s[i / R];
+  HIPCHK(hipMemcpy(W.shift, sh.data(), S * sizeof(T), hipMemcpyHostToDevice));
+  for (void* ptr : {(void*)W.x, (void*)W.r, (void*)W.z, (void*)W.zt, (void*)W.p, (void*)W.q})
+    HIPCHK(hipMemset(ptr, 0, vb));
+  return BURA_OK;
+}
+
+size_t footprint(const bura_plan_t P, size_t elem, bool mixed) {
+  const size_t S = (size_t)P->S;
+  size_t t = 6 * S * (size_t)P->N * elem;
+  if (P->lc > 0)
+    for (int l = 1; l <= P->lc; ++l) t += 3 * S * (size_t)P->lev[l].N * elem;
+  if (mixed) t += S * (size_t)P->N * 8;
+  size_t maxblk = (size_t)std::max(stencil_blocks(P->dim, P->n), flat_blocks(P->N));
+  t += S * maxblk * 8;
+  for (const auto& L : P->lev)
+    for (int a = 0; a < P->dim; ++a) t += L.wf[a].size() * 12;
+  return t;
+}
+
+int upload_faces(bura_plan_t P) {
+  if (!P->var) return BURA_OK;
+  for (auto& L : P->lev) {
+    for (int a = 0; a < P->dim; ++a) {
+      const size_t cnt = L.wf[a].size();
+      int rc;
+      if ((rc = dev_alloc(P, (void**)&L.d_wf64[a], cnt * 8))) return rc;
+      if ((rc = dev_alloc(P, (void**)&L.d_wf32[a], cnt * 4))) return rc;
+      std::vector<float> f32(L.wf[a].begin(), L.wf[a].end());
+      HIPCHK(hipMemcpy(L.d_wf64[a], L.wf[a].data(), cnt * 8, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(L.d_wf32[a], f32.data(), cnt * 4, hipMemcpyHostToDevice));
+    }
+  }
+  return BURA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// preconditioner z = M r on a batch (V-cycle, or Jacobi without a hierarchy);
+// the last sweep writes the per-block partials of r.z into `partial`.
+// ---------------------------------------------------------------------------
+template <typename T>
+void precondition(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, const int* active, double* partial) {
+  hipStream_t st = P->stream;
+  const int dim = P->dim;
+  const bool var = P->var;
+  const T omega = (T)(P->opts.omega > 0 ? P->opts.omega : default_omega(dim));
+  const T* shift = W.shift + sys0;
+  auto off = [&](T* base, int l) { return base + sys0 * (size_t)P->lev[l].N; };
+  if (P->lc < 0) {
+    // Jacobi preconditioner: z = D^-1 r
+    ProfScope ps(P, BURA_K_SMOOTH_FINE);
+    Launch<T>::jacobi(dim, var, level_view<T>(P, 0), off(W.r, 0), nullptr, off(W.z, 0), shift, active, T(1), true,
+                      partial, nsys, st, ps.ctr);
+    return;
+  }
+  const int lc = P->lc;
+  const int nu1 = std::max(1, P->opts.nu_pre), nu2 = std::max(1, P->opts.nu_post);
+  // per level: right-hand side, the buffer holding the iterate, the spare buffer.
+  // nu1 + nu2 sweeps alternate between two buffers; the first sweep writes the
+  // buffer that makes the last one land in xa (xa = z on the fine level).
+  std::vector<T*> bcur(lc + 1), cur(lc + 1), spare(lc + 1);
+  bcur[0] = off(W.r, 0);
+  for (int l = 1; l <= lc; ++l) bcur[l] = off(W.bl[l], l);
+  for (int l = 0; l < lc; ++l) {
+    const LevelDev<T> L = level_view<T>(P, l);
+    T* xa = l == 0 ? off(W.z, 0) : off(W.xl[l], l);
+    T* xb = l == 0 ? off(W.zt, 0) : off(W.tl[l], l);
+    const bool odd = ((nu1 + nu2) % 2) == 1;
+    T* out = odd ? xa : xb;
+    T* other = odd ? xb : xa;
+    const int scls = l == 0 ? BURA_K_SMOOTH_FINE : BURA_K_SMOOTH_COARSE;
+    {
+      ProfScope ps(P, scls);
+      Launch<T>::jacobi(dim, var, L, bcur[l], nullptr, out, shift, active, omega, true, nullptr, nsys, st, ps.ctr);
+    }
+    for (int s = 1; s < nu1; ++s) {
+      ProfScope ps(P, scls);
+      Launch<T>::jacobi(dim, var, L, bcur[l], out, other, shift, active, omega, false, nullptr, nsys, st, ps.ctr);
+      std::swap(out, other);
+    }
+    cur[l] = out;
+    spare[l] = other;
+    ProfScope ps(P, BURA_K_RESTRICT);
+    Launch<T>::restrict_residual(dim, var, L, level_view<T>(P, l + 1), bcur[l], cur[l], bcur[l + 1], shift, active,
+                                 nsys, st, ps.ctr);
+  }
+  cur[lc] = off(W.xl[lc], lc);
+  {
+    ProfScope ps(P, BURA_K_COARSE_LDS);
+    Launch<T>::coarse_solve(dim, var, lds_view<T>(P), bcur[lc], cur[lc], shift, active, nsys, P->lds_bytes, st,
+                            ps.ctr);
+  }
+  for (int l = lc - 1; l >= 0; --l) {
+    const LevelDev<T> L = level_view<T>(P, l);
+    {
+      ProfScope ps(P, BURA_K_PROLONG);
+      Launch<T>::prolong_add(dim, level_view<T>(P, l + 1), L, cur[l + 1], cur[l], active, nsys, st, ps.ctr);
+    }
+    const int scls = l == 0 ? BURA_K_SMOOTH_FINE : BURA_K_SMOOTH_COARSE;
+    for (int s = 0; s < nu2; ++s) {
+      const bool last = (l == 0 && s == nu2 - 1);
+      ProfScope ps(P, scls);
+      Launch<T>::jacobi(dim, var, L, bcur[l], cur[l], spare[l], shift, active, omega, false,
+                        last ? partial : nullptr, nsys, st, ps.ctr);
+      std::swap(cur[l], spare[l]);
+    }
+  }
+}
+
+// which kernel wrote the r.z partials (for the reduction's block count)
+int rz_blocks(const bura_plan_t P) { return stencil_blocks(P->dim, P->n); }
+
+SysState state_at(const bura_plan_t P, size_t sys0) {
+  SysState s = P->st;
+  s.bnorm2 += sys0; s.rho += sys0; s.alpha += sys0; s.beta += sys0; s.relres += sys0;
+  s.active += sys0; s.iters += sys0; s.total_iters += sys0; s.flags += sys0;
+  s.fnorm2 += sys0; s.relres64 += sys0; s.active64 += sys0; s.outer += sys0;
+  return s;
+}
+
+int count_active(bura_plan_t P, const int* dev_flags, size_t sys0, int nsys) {
+  if (hipMemcpyAsync(P->h_flags, dev_flags + sys0, nsys * sizeof(int), hipMemcpyDeviceToHost, P->stream) !=
+      hipSuccess)
+    return -1;
+  if (hipStreamSynchronize(P->stream) != hipSuccess) return -1;
+  int c = 0;
+  for (int i = 0; i < nsys; ++i) c += P->h_flags[i] != 0;
+  return c;
+}
+
+// PCG on systems [sys0, sys0+nsys): r holds b, x holds 0, OP_INIT done.
+template <typename T>
+int run_pcg(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, double tol, int max_iter) {
+  hipStream_t st = P->stream;
+  const int dim = P->dim;
+  const LevelDev<T> L0 = level_view<T>(P, 0);
+  const size_t o = sys0 * (size_t)P->N;
+  const SysState S = state_at(P, sys0);
+  double* part = P->partial;
+  const int nb_tile = stencil_blocks(dim, P->n), nb_flat = flat_blocks(P->N);
+  const int check = std::max(1, P->opts.check_every);
+  auto scal = [&](int op, int nblk) {
+    ProfScope ps(P, BURA_K_OTHER);
+    launch_scalars(op, part, nblk, nsys, S, tol, max_iter, st);
+  };
+  auto upd_p = [&]() {
+    ProfScope ps(P, BURA_K_UPDATE_P);
+    Launch<T>::update_p(L0, dim, W.p + o, W.z + o, S.beta, S.active, nsys, st, ps.ctr);
+  };
+  precondition<T>(P, W, sys0, nsys, S.active, part);
+  scal(OP_BETA, rz_blocks(P));
+  upd_p();
+  for (int it = 0; it <= max_iter; ++it) {
+    {
+      ProfScope ps(P, BURA_K_SPMV);
+      Launch<T>::spmv_dot(dim, P->var, L0, W.p + o, W.q + o, W.shift + sys0, S.active, part, nsys, st, ps.ctr);
+    }
+    scal(OP_ALPHA, nb_tile);
+    {
+      ProfScope ps(P, BURA_K_UPDATE_XR);
+      Launch<T>::update_xr(L0, dim, W.x + o, W.r + o, W.p + o, W.q + o, S.alpha, S.active, part, nsys, st, ps.ctr);
+    }
+    scal(OP_RESID, nb_flat);
+    if ((it + 1) % check == 0 || it == max_iter) {
+      const int a = count_active(P, P->st.active, sys0, nsys);
+      if (a < 0) {
+        g_last_error = hipGetErrorString(hipGetLastError());
+        return BURA_EDEVICE;
+      }
+      if (a == 0) break;
+    }
+    precondition<T>(P, W, sys0, nsys, S.active, part);
+    scal(OP_BETA, rz_blocks(P));
+    upd_p();
+  }
+  HIPCHK(hipGetLastError());
+  return BURA_OK;
+}
+
+int set_flags(bura_plan_t P, int* dev, size_t sys0, int nsys, int value) {
+  std::vector<int> h(nsys, value);
+  HIPCHK(hipMemcpyAsync(dev + sys0, h.data(), nsys * sizeof(int), hipMemcpyHostToDevice, P->stream));
+  HIPCHK(hipStreamSynchronize(P->stream));
+  return BURA_OK;
+}
+
+int solve_batch_fp64(bura_plan_t P, const double* f, int nrhs, size_t sys0, int nsys) {
+  hipStream_t st = P->stream;
+  Work<double>& W = P->w64;
+  const LevelDev<double> L0 = level_view<double>(P, 0);
+  const size_t o = sys0 * (size_t)P->N;
+  const SysState S = state_at(P, sys0);
+  int rc;
+  if ((rc = set_flags(P, P->st.active, sys0, nsys, 1))) return rc;
+  {
+    ProfScope ps(P, BURA_K_OTHER);
+    Launch<double>::copy_rhs(L0, P->dim, f, W.r + o, W.x + o, nrhs, S.active, P->partial, nsys, st);
+  }
+  {
+    ProfScope ps(P, BURA_K_OTHER);
+    launch_scalars(OP_INIT, P->partial, flat_blocks(P->N), nsys, S, P->opts.tol, P->opts.max_iter, st);
+  }
+  return run_pcg<double>(P, W, sys0, nsys, P->opts.tol, P->opts.max_iter);
+}
+
+int solve_batch_mixed(bura_plan_t P, const double* f, int nrhs, size_t sys0, int nsys) {
+  hipStream_t st = P->stream;
+  Work<float>& W = P->w32;
+  const LevelDev<double> L0 = level_view<double>(P, 0);
+  const size_t o = sys0 * (size_t)P->N;
+  const SysState S = state_at(P, sys0);
+  int rc;
+  if ((rc = set_flags(P, P->st.active64, sys0, nsys, 1))) return rc;
+  if ((rc = set_flags(P, P->st.active, sys0, nsys, 1))) return rc;
+  {
+    ProfScope ps(P, BURA_K_RESIDUAL64);
+    launch_residual64(P->dim, P->var, L0, f, P->x64 + o, W.x + o, W.r + o, P->d_shift64 + sys0, S.active64,
+                      P->partial, nrhs, nsys, true, st, ps.ctr);
+  }
+  {
+    ProfScope ps(P, BURA_K_OTHER);
+    launch_scalars(OP_OUTER, P->partial, flat_blocks(P->N), nsys, S, P->opts.tol, P->opts.max_outer, st);
+  }
+  for (int outer = 0; outer < P->opts.max_outer + 1; ++outer) {
+    const int a = count_active(P, P->st.active64, sys0, nsys);
+    if (a < 0) {
+      g_last_error = "device error during refinement";
+      return BURA_EDEVICE;
+    }
+    if (a == 0) break;
+    if ((rc = run_pcg<float>(P, W, sys0, nsys, P->opts.inner_tol, P->opts.max_iter))) return rc;
+    {
+      ProfScope ps(P, BURA_K_OTHER);
+      launch_x_from_e(L0, P->dim, W.x + o, P->x64 + o, S.active64, nsys, st);
+    }
+    {
+      ProfScope ps(P, BURA_K_RESIDUAL64);
+      launch_residual64(P->dim, P->var, L0, f, P->x64 + o, W.x + o, W.r + o, P->d_shift64 + sys0, S.active64,
+                        P->partial, nrhs, nsys, false, st, ps.ctr);
+    }
+    {
+      ProfScope ps(P, BURA_K_OTHER);
+      launch_scalars(OP_OUTER, P->partial, stencil_blocks(P->dim, P->n), nsys, S, P->opts.tol, P->opts.max_outer,
+                     st);
+    }
+  }
+  HIPCHK(hipGetLastError());
+  return BURA_OK;
+}
+
+int do_solve(bura_plan_t P, const double* f, double* u, int nrhs, bura_report_t* rep) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!P || !f || !u || nrhs < 1 || nrhs > P->opts.nrhs_max) return BURA_EINVAL;
+  HIPCHK(hipSetDevice(P->device));
+  const bool mixed = P->opts.precision == BURA_MIXED;
+  const int R = P->opts.nrhs_max;
+  // systems are laid out sys = j * R + r; only r < nrhs are used
+  const size_t S_used = (size_t)P->nterms * R;
+  int rc;
+  if ((rc = set_flags(P, P->st.flags, 0, (int)S_used, 0))) return rc;
+  if ((rc = set_flags(P, P->st.total_iters, 0, (int)S_used, 0))) return rc;
+  if ((rc = set_flags(P, P->st.outer, 0, (int)S_used, 0))) return rc;
+  // systems of unused rhs slots stay inactive
+  if (nrhs < R) {
+    if ((rc = set_flags(P, P->st.active, 0, (int)S_used, 0))) return rc;
+    if ((rc = set_flags(P, P->st.active64, 0, (int)S_used, 0))) return rc;
+  }
+  auto batch = [&](size_t sys0, int nsys) {
+    // the kernels take rhs = sys % R; pass f with R slots (rhs >= nrhs never active)
+    return mixed ? solve_batch_mixed(P, f, R, sys0, nsys) : solve_batch_fp64(P, f, R, sys0, nsys);
+  };
+  if (nrhs == R) {
+    if (P->opts.schedule == BURA_PER_POLE) {
+      for (int j = 0; j < P->nterms && rc == BURA_OK; ++j) rc = batch((size_t)j * R, R);
+    } else {
+      rc = batch(0, (int)S_used);
+    }
+  } else {
+    // fewer rhs than slots: run each pole's first nrhs systems
+    for (int j = 0; j < P->nterms && rc == BURA_OK; ++j) rc = batch((size_t)j * R, nrhs);
+  }
+  if (rc) return rc;
+  // combine u = sum_j w_j x_j (fixed order j = 0..k, FP64)
+  const double* xsol = mixed ? P->x64 : P->w64.x;
+  {
+    ProfScope ps(P, BURA_K_COMBINE);
+    launch_combine(P->N, xsol, P->d_w, P->nterms, nrhs, R, u, P->stream, ps.ctr);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(P->stream));
+  // report
+  std::vector<int> it(S_used), outer(S_used), flags(S_used), act(S_used);
+  std::vector<double> rr(S_used);
+  HIPCHK(hipMemcpy(it.data(), P->st.total_iters, S_used * 4, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(outer.data(), P->st.outer, S_used * 4, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(flags.data(), P->st.flags, S_used * 4, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(rr.data(), mixed ? P->st.relres64 : P->st.relres, S_used * 8, hipMemcpyDeviceToHost));
+  int status = BURA_OK;
+  bura_report_t R_{};
+  R_.nterms = P->nterms;
+  R_.E = P->E;
+  for (int j = 0; j < P->nterms && j < BURA_MAX_TERMS; ++j) {
+    for (int r = 0; r < nrhs; ++r) {
+      const size_t s = (size_t)j * R + r;
+      R_.iters[j] = std::max(R_.iters[j], it[s]);
+      R_.outer[j] = std::max(R_.outer[j], outer[s]);
+      R_.relres[j] = std::max(R_.relres[j], rr[s]);
+      if (flags[s] & 1) status = BURA_ENAN;
+      if (status == BURA_OK && !(rr[s] <= P->opts.tol)) status = BURA_ENOCONV;
+    }
+  }
+  R_.status = status;
+  R_.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (rep) *rep = R_;
+  return status;
+}
+
+int validate_opts(const bura_opts_t* o) {
+  if (!o) return BURA_EINVAL;
+  if (!(o->tol > 0) || !(o->inner_tol > 0) || o->max_iter < 0 || o->nrhs_max < 1 || o->max_outer < 1)
+    return BURA_EINVAL;
+  if (o->precision != BURA_FP64 && o->precision != BURA_MIXED) return BURA_EINVAL;
+  if (o->schedule != BURA_BATCHED && o->schedule != BURA_PER_POLE) return BURA_EINVAL;
+  return BURA_OK;
+}
+
+int create(const bura_grid_t* g, int nterms, const double* w, const double* s, double E,
+           const bura_opts_t* opts_in, bura_plan_t* out) {
+  if (out) *out = nullptr;
+  if (!g || !out || !w || !s || nterms < 1 || nterms > BURA_MAX_TERMS) return BURA_EINVAL;
+  if (g->dim != 2 && g->dim != 3) return BURA_EINVAL;
+  if (g->n < 1) return BURA_EINVAL;
+  long long N = 1;
+  for (int a = 0; a < g->dim; ++a) N *= g->n;
+  if (N > 2147483647LL) return BURA_EINVAL;
+  bura_opts_t o;
+  if (opts_in) o = *opts_in;
+  else bura_opts_default(&o);
+  if (validate_opts(&o)) return BURA_EINVAL;
+  for (int j = 0; j < nterms; ++j)
+    if (!(s[j] >= 0.0) || !std::isfinite(w[j]) || !std::isfinite(s[j])) return BURA_EINVAL;
+  if (g->coeff) {
+    const long long m = (long long)(g->n + 2);
+    long long cnt = g->dim == 2 ? m * m : m * m * m;
+    for (long long i = 0; i < cnt; ++i)
+      if (!(g->coeff[i] > 0.0) || !std::isfinite(g->coeff[i])) return BURA_EINVAL;
+  }
+  auto* P = new bura_plan_s();
+  P->dim = g->dim;
+  P->n = g->n;
+  P->N = N;
+  P->var = g->coeff != nullptr;
+  P->nterms = nterms;
+  P->w.assign(w, w + nterms);
+  P->s.assign(s, s + nterms);
+  P->E = E;
+  P->opts = o;
+  P->stream = (hipStream_t)o.stream;
+  P->S = nterms * o.nrhs_max;
+  int rc = build_levels(P, g);
+  if (rc) { delete P; return rc; }
+  const bool mixed = o.precision == BURA_MIXED;
+  choose_lds(P, mixed ? 4 : 8);
+  if (P->opts.max_iter == 0) {
+    // automatic cap: multigrid-PCG needs O(1) iterations per digit; Jacobi-PCG
+    // (no hierarchy) needs O(sqrt(kappa)) = O(n) per digit
+    P->opts.max_iter = P->lc >= 0 ? 200 : 40 * P->n + 200;
+  }
+  if (o.hbm_budget > 0 && footprint(P, mixed ? 4 : 8, mixed) > o.hbm_budget) {
+    delete P;
+    return BURA_ENOMEM;
+  }
+  if (hipGetDevice(&P->device) != hipSuccess) { delete P; return BURA_EDEVICE; }
+  auto fail = [&](int code) { bura_plan_destroy(P); return code; };
+  if ((rc = upload_faces(P))) return fail(rc);
+  if (mixed) {
+    if ((rc = alloc_work<float>(P, P->w32))) return fail(rc);
+    if ((rc = dev_alloc(P, (void**)&P->x64, (size_t)P->S * P->N * 8))) return fail(rc);
+    hipMemset(P->x64, 0, (size_t)P->S * P->N * 8);
+  } else {
+    if ((rc = alloc_work<double>(P, P->w64))) return fail(rc);
+  }
+  // the FP64 shift (residual kernel) exists in both modes
+  if ((rc = dev_alloc(P, (void**)&P->d_shift64, (size_t)P->S * 8))) return fail(rc);
+  {
+    std::vector<double> sh(P->S);
+    for (int i = 0; i < P->S; ++i) sh[i] = P->s[i / o.nrhs_max];
+    if (hipMemcpy(P->d_shift64, sh.data(), sh.size() * 8, hipMemcpyHostToDevice) != hipSuccess) return fail(BURA_EDEVICE);
+  }
+  const size_t maxblk = (size_t)std::max(stencil_blocks(P->dim, P->n), flat_blocks(P->N));
+  P->partial_len = (size_t)P->S * maxblk;
+  if ((rc = dev_alloc(P, (void**)&P->partial, P->partial_len * 8))) return fail(rc);
+  if ((rc = dev_alloc(P, (void**)&P->d_w, nterms * 8))) return fail(rc);
+  if (hipMemcpy(P->d_w, P->w.data(), nterms * 8, hipMemcpyHostToDevice) != hipSuccess) return fail(BURA_EDEVICE);
+  // state arrays: 6 double + 7 int arrays of length S
+  const size_t S = (size_t)P->S;
+  const size_t bytes = S * (6 * 8 + 8 * 4);
+  if ((rc = dev_alloc(P, &P->state_block, bytes))) return fail(rc);
+  hipMemset(P->state_block, 0, bytes);
+  double* dp = (double*)P->state_block;
+  P->st.bnorm2 = dp; P->st.rho = dp + S; P->st.alpha = dp + 2 * S; P->st.beta = dp + 3 * S;
+  P->st.relres = dp + 4 * S; P->st.fnorm2 = dp + 5 * S;
+  P->st.relres64 = nullptr;
+  int* ip = (int*)(dp + 6 * S);
+  P->st.active = ip; P->st.iters = ip + S; P->st.total_iters = ip + 2 * S; P->st.flags = ip + 3 * S;
+  P->st.active64 = ip + 4 * S; P->st.outer = ip + 5 * S;
+  // relres64 needs doubles: carve from a separate allocation
+  if ((rc = dev_alloc(P, (void**)&P->st.relres64, S * 8))) return fail(rc);
+  hipMemset(P->st.relres64, 0, S * 8);
+  if ((rc = dev_alloc(P, (void**)&P->prof.d_ctr, BURA_K_COUNT * sizeof(unsigned long long)))) return fail(rc);
+  hipMemset(P->prof.d_ctr, 0, BURA_K_COUNT * sizeof(unsigned long long));
+  if (hipHostMalloc((void**)&P->h_flags, S * sizeof(int), hipHostMallocDefault) != hipSuccess)
+    return fail(BURA_ENOMEM);
+  if (hipDeviceSynchronize() != hipSuccess) return fail(BURA_EDEVICE);
+  *out = P;
+  return BURA_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int bura_opts_default(bura_opts_t* o) {
+  if (!o) return BURA_EINVAL;
+  std::memset(o, 0, sizeof(*o));
+  o->tol = 1e-12;
+  o->inner_tol = 1e-5;
+  o->precision = BURA_MIXED;
+  o->schedule = BURA_BATCHED;
+  o->max_iter = 0;
+  o->max_outer = 12;
+  o->nrhs_max = 1;
+  o->check_every = 4;
+  o->nu_pre = 2;
+  o->nu_post = 2;
+  o->omega = 0.0;
+  o->stream = nullptr;
+  o->hbm_budget = 0;
+  return BURA_OK;
+}
+
+int bura_plan_create_rational(const bura_grid_t* grid, int nterms, const double* weights, const double* shifts,
+                              const bura_opts_t* opts, bura_plan_t* out) {
+  return create(grid, nterms, weights, shifts, 0.0, opts, out);
+}
+
+int bura_plan_create(const bura_grid_t* grid, double alpha, int beta, int k, const bura_opts_t* opts,
+                     bura_plan_t* out) {
+  if (out) *out = nullptr;
+  if (!(alpha > 0.0 && alpha < 1.0) || k < 1 || k > 16) return BURA_EINVAL;
+  if (beta != 1) return BURA_EUNSUPPORTED;
+  std::vector<double> c(k + 1), d(k + 1);
+  double E = 0.0;
+  int rc = bura_coefficients(alpha, beta, k, c.data(), d.data(), &E);
+  if (rc) return rc;
+  std::vector<double> s(k + 1);
+  for (int j = 0; j <= k; ++j) s[j] = -d[j];
+  return create(grid, k + 1, c.data(), s.data(), E, opts, out);
+}
+
+int bura_solve(bura_plan_t plan, const double* f_dev, double* u_dev, int nrhs, bura_report_t* rep) {
+  if (!plan) return BURA_EINVAL;
+  if (plan->busy.load()) return BURA_EBUSY;
+  return do_solve(plan, f_dev, u_dev, nrhs, rep);
+}
+
+int bura_submit(bura_plan_t plan, const double* f_dev, double* u_dev, int nrhs) {
+  if (!plan || !f_dev || !u_dev || nrhs < 1 || nrhs > plan->opts.nrhs_max) return BURA_EINVAL;
+  int expected = 0;
+  if (!plan->busy.compare_exchange_strong(expected, 1)) return BURA_EBUSY;
+  if (plan->worker.joinable()) plan->worker.join();
+  plan->worker = std::thread([plan, f_dev, u_dev, nrhs]() {
+    bura_report_t rep{};
+    const int rc = do_solve(plan, f_dev, u_dev, nrhs, &rep);
+    plan->async_status = rc;
+    rep.status = rc;
+    plan->async_report = rep;
+    plan->busy.store(2);
+  });
+  return BURA_OK;
+}
+
+int bura_poll(bura_plan_t plan, bura_report_t* rep) {
+  if (!plan) return BURA_EINVAL;
+  const int b = plan->busy.load();
+  if (b == 1) return BURA_PENDING;
+  if (b == 0) return BURA_EINVAL;   // nothing submitted
+  if (plan->worker.joinable()) plan->worker.join();
+  if (rep) *rep = plan->async_report;
+  plan->busy.store(0);
+  return plan->async_status;
+}
+
+int bura_plan_coeffs(bura_plan_t plan, int* nterms, double* c, double* d, double* E) {
+  if (!plan) return BURA_EINVAL;
+  if (nterms) *nterms = plan->nterms;
+  for (int j = 0; j < plan->nterms; ++j) {
+    if (c) c[j] = plan->w[j];
+    if (d) d[j] = -plan->s[j];
+  }
+  if (E) *E = plan->E;
+  return BURA_OK;
+}
+
+int bura_plan_info(bura_plan_t plan, double* lambda, int* nlevels, size_t* device_bytes) {
+  if (!plan) return BURA_EINVAL;
+  if (lambda) *lambda = plan->lambda;
+  if (nlevels) *nlevels = (int)plan->lev.size();
+  if (device_bytes) *device_bytes = plan->device_bytes;
+  return BURA_OK;
+}
+
+int bura_plan_apply(bura_plan_t plan, double shift, const double* x_dev, double* y_dev, int nvec) {
+  if (!plan || !x_dev || !y_dev || nvec < 1 || !(shift >= 0.0)) return BURA_EINVAL;
+  HIPCHK(hipSetDevice(plan->device));
+  launch_apply64(plan->dim, plan->var, level_view<double>(plan, 0), x_dev, y_dev, shift, nvec, plan->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(plan->stream));
+  return BURA_OK;
+}
+
+int bura_plan_profile(bura_plan_t plan, int enable) {
+  if (!plan) return BURA_EINVAL;
+  HIPCHK(hipSetDevice(plan->device));
+  HIPCHK(hipStreamSynchronize(plan->stream));
+  if (enable) {
+    HIPCHK(hipMemset(plan->prof.d_ctr, 0, BURA_K_COUNT * sizeof(unsigned long long)));
+    HIPCHK(hipDeviceSynchronize());
+    plan->prof.rec.clear();
+    plan->prof.used = 0;
+  }
+  plan->prof.on = enable != 0;
+  plan->prof.mask = (unsigned)enable == 1u ? ((1u << BURA_K_COUNT) - 1u) : ((unsigned)enable >> 1);
+  return BURA_OK;
+}
+
+int bura_plan_kernel_stats(bura_plan_t plan, int kclass, long long* launches, double* total_ms, double* alg_bytes) {
+  if (!plan || kclass < 0 || kclass >= BURA_K_COUNT) return BURA_EINVAL;
+  HIPCHK(hipSetDevice(plan->device));
+  HIPCHK(hipStreamSynchronize(plan->stream));
+  long long cnt = 0;
+  double ms = 0.0;
+  for (const auto& r : plan->prof.rec) {
+    if (r.first != kclass) continue;
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, plan->prof.pool[r.second], plan->prof.pool[r.second + 1]));
+    ms += t;
+    ++cnt;
+  }
+  unsigned long long ctr[BURA_K_COUNT];
+  HIPCHK(hipMemcpy(ctr, plan->prof.d_ctr, sizeof(ctr), hipMemcpyDeviceToHost));
+  if (launches) *launches = cnt;
+  if (total_ms) *total_ms = ms;
+  if (alg_bytes) *alg_bytes = (double)ctr[kclass];
+  return BURA_OK;
+}
+
+void bura_plan_destroy(bura_plan_t plan) {
+  if (!plan) return;
+  if (plan->worker.joinable()) plan->worker.join();
+  hipSetDevice(plan->device);
+  hipDeviceSynchronize();
+  for (hipEvent_t e : plan->prof.pool) hipEventDestroy(e);
+  for (void* p : plan->allocs) hipFree(p);
+  if (plan->h_flags) hipHostFree(plan->h_flags);
+  delete plan;
+}
+
+const char* bura_strerror(int status) {
+  switch (status) {
+    case BURA_OK: return "ok";
+    case BURA_PENDING: return "pending";
+    case BURA_EINVAL: return "invalid argument";
+    case BURA_EUNSUPPORTED: return "unsupported";
+    case BURA_EREMEZ: return "rational approximation did not converge";
+    case BURA_ENOCONV: return "iteration limit reached";
+    case BURA_ENOMEM: return "out of device memory or over budget";
+    case BURA_EDEVICE: return "HIP runtime error";
+    case BURA_ENAN: return "non-finite value";
+    case BURA_EBUSY: return "plan busy";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

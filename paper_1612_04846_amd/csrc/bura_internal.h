@@ -1,0 +1,109 @@
+// Internal declarations shared by the HIP kernels, the solver engine and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/bura.h"
+#include "bura_remez.h"
+
+namespace bura {
+
+constexpr int kTileX = 64;             // threads along x in a stencil tile
+constexpr int kTileY = 4;              // rows per tile
+constexpr int kBlock = kTileX * kTileY;
+constexpr int kSlots = 2;              // reduction slots per block
+constexpr int kMaxLdsLevels = 8;
+
+// One multigrid level of the scaled operator A_l + s I as seen by a kernel.
+// Face weights are a_f / (Lambda h_l^2); the constant-coefficient operator has
+// every face weight equal to wc (= 4^-l / (2 dim)).
+template <typename T>
+struct LevelDev {
+  int n;              // interior points per axis
+  long long N;        // n^dim
+  T wc;               // constant face weight (used when wf0 == nullptr)
+  const T* wf0;       // x-faces  [..][n+1]       (nullptr: constant coefficient)
+  const T* wf1;       // y-faces  [..][n+1][n]
+  const T* wf2;       // z-faces  [n+1][n][n]
+};
+
+// Levels solved inside one workgroup (LDS V-cycle): descriptors + LDS offsets.
+template <typename T>
+struct LdsHierarchy {
+  int nlev;
+  LevelDev<T> lev[kMaxLdsLevels];
+  int off[kMaxLdsLevels];   // element offset of level l's x/b/t arrays in LDS (each N_l long)
+  int cycles;               // V-cycles per coarse solve
+  int nu;                   // sweeps per smoothing step
+  int bottom_sweeps;        // Jacobi sweeps on the last level if it is larger than one point
+  T omega;
+};
+
+// Per-system scalar state of the PCG / refinement loops (device arrays, length S).
+struct SysState {
+  double* bnorm2;   // ||b||^2 of the PCG right-hand side
+  double* rho;      // r.z
+  double* alpha;
+  double* beta;
+  double* relres;   // last ||r||/||b|| seen by the PCG
+  int* active;      // 1 while the PCG runs on this system
+  int* iters;       // PCG iterations done (this inner solve)
+  int* total_iters; // PCG iterations summed over refinement steps
+  int* flags;       // bit 0: breakdown / non-finite
+  // refinement (MIXED) and FP64 outer state
+  double* fnorm2;
+  double* relres64;
+  int* active64;
+  int* outer;
+};
+
+enum ScalarOp { OP_INIT = 0, OP_ALPHA = 1, OP_RESID = 2, OP_BETA = 3, OP_OUTER = 4 };
+
+// ---- kernel launchers (bura_kernels.hip) ----------------------------------
+template <typename T>
+struct Launch {
+  static void jacobi(int dim, bool var, const LevelDev<T>& L, const T* b, const T* xin, T* xout,
+                     const T* shift, const int* active, T omega, bool zero_guess, double* partial,
+                     int nsys, hipStream_t st, unsigned long long* ctr);
+  static void restrict_residual(int dim, bool var, const LevelDev<T>& Lf, const LevelDev<T>& Lc,
+                                const T* b, const T* x, T* bc, const T* shift, const int* active,
+                                int nsys, hipStream_t st, unsigned long long* ctr);
+  static void prolong_add(int dim, const LevelDev<T>& Lc, const LevelDev<T>& Lf, const T* xc, T* xf,
+                          const int* active, int nsys, hipStream_t st, unsigned long long* ctr);
+  static void coarse_solve(int dim, bool var, const LdsHierarchy<T>& H, const T* b, T* x,
+                           const T* shift, const int* active, int nsys, size_t lds_bytes, hipStream_t st,
+                           unsigned long long* ctr);
+  static void spmv_dot(int dim, bool var, const LevelDev<T>& L, const T* p, T* q, const T* shift,
+                       const int* active, double* partial, int nsys, hipStream_t st, unsigned long long* ctr);
+  static void update_xr(const LevelDev<T>& L, int dim, T* x, T* r, const T* p, const T* q,
+                        const double* alpha, const int* active, double* partial, int nsys, hipStream_t st,
+                        unsigned long long* ctr);
+  static void update_p(const LevelDev<T>& L, int dim, T* p, const T* z, const double* beta,
+                       const int* active, int nsys, hipStream_t st, unsigned long long* ctr);
+  static void copy_rhs(const LevelDev<T>& L, int dim, const double* f, T* r, T* x, int nrhs,
+                       const int* active, double* partial, int nsys, hipStream_t st);
+};
+
+// FP64-only steps of the refinement loop and the combine.
+void launch_residual64(int dim, bool var, const LevelDev<double>& L, const double* f, const double* x64, float* e,
+                       float* r32, const double* shift, const int* active64, double* partial, int nrhs, int nsys,
+                       bool first, hipStream_t st, unsigned long long* ctr);
+void launch_x_from_e(const LevelDev<double>& L, int dim, const float* e, double* x64, const int* active64,
+                     int nsys, hipStream_t st);
+void launch_combine(long long N, const double* x, const double* w, int nterms, int nrhs, int stride, double* u,
+                    hipStream_t st, unsigned long long* ctr);
+void launch_apply64(int dim, bool var, const LevelDev<double>& L, const double* x, double* y, double shift,
+                    int nvec, hipStream_t st);
+void launch_scalars(int op, const double* partial, int nblk, int nsys, SysState st_, double tol,
+                    int max_iter, hipStream_t st);
+void launch_zero(void* p, size_t bytes, hipStream_t st);
+
+int stencil_blocks(int dim, int n);   // blocks per system of a stencil launch (tile grid)
+int flat_blocks(long long N);        // blocks per system of an element-wise launch
+
+}  // namespace bura

@@ -1,0 +1,845 @@
+// HIP kernels (gfx950) for the k+1 shifted SPD solves of the BURA method
+// (Section 2.2, eq. (16)): matrix-free 5/7-point stencils of the scaled operator
+// A + s I (Section 1.4, eq. (10); Section 5.3), weighted-Jacobi smoothing,
+// full-weighting restriction, multilinear prolongation, an in-LDS V-cycle for
+// the coarse levels, the PCG vector updates with FP64 block reductions, the
+// FP64 residual of the refinement loop and the FP64 combine of eq. (16).
+//
+// Every launch processes a batch of independent systems: blockIdx.z (stencils)
+// or blockIdx.y (flat kernels) selects the system; a system whose `active` flag
+// is 0 is skipped by whole blocks.  Reductions are deterministic: each block
+// writes one FP64 partial per system and a per-system kernel adds the partials
+// in a fixed order, so a system's result does not depend on what else is in
+// the batch.
+#include "bura_internal.h"
+
+#include <cmath>
+
+namespace bura {
+
+// --------------------------------------------------------------------------
+// small helpers
+// --------------------------------------------------------------------------
+
+template <int DIM>
+__device__ __forceinline__ void tile_ijk(int n, int& i, int& j, int& k) {
+  i = blockIdx.x * kTileX + threadIdx.x;
+  const int ytiles = (n + kTileY - 1) / kTileY;
+  int by = blockIdx.y;
+  if (DIM == 3) {
+    k = by / ytiles;
+    by -= k * ytiles;
+  } else {
+    k = 0;
+  }
+  j = by * kTileY + threadIdx.y;
+}
+
+// FP64 block sum; the result is valid in thread 0 only.  Fixed order.
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double sh[kBlock / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+  if ((tid & 63) == 0) sh[tid >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (tid == 0) {
+    const int nw = (blockDim.x * blockDim.y + 63) >> 6;
+    for (int w = 0; w < nw; ++w) r += sh[w];
+  }
+  return r;
+}
+
+// Stencil launches: the block's (x, y) tile index; flat launches: blockIdx.x.
+__device__ __forceinline__ void write_partial(double* partial, int sys, double v, int blk, int nblk) {
+  const double s = block_sum(v);
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+  if (tid == 0) partial[(size_t)sys * nblk + blk] = s;
+}
+
+__device__ __forceinline__ void write_partial_tile(double* partial, int sys, double v) {
+  write_partial(partial, sys, v, blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+}
+
+__device__ __forceinline__ void write_partial_flat(double* partial, int sys, double v) {
+  write_partial(partial, sys, v, blockIdx.x, gridDim.x);
+}
+
+// Profiling: one lane per block adds the block's algorithmic bytes (each
+// vector element read or written once) to a per-kernel-class counter.
+__device__ __forceinline__ void count_bytes(unsigned long long* ctr, unsigned long long b) {
+  if (ctr != nullptr && threadIdx.x == 0 && threadIdx.y == 0) atomicAdd(ctr, b);
+}
+
+// points of the stencil tile handled by this block (clipped at the grid edge)
+__device__ __forceinline__ unsigned long long tile_points(int n) {
+  const int ytiles = (n + kTileY - 1) / kTileY;
+  const int by = blockIdx.y % ytiles;
+  const int vx = min(kTileX, n - (int)blockIdx.x * kTileX);
+  const int vy = min(kTileY, n - by * kTileY);
+  return (unsigned long long)(vx > 0 ? vx : 0) * (unsigned long long)(vy > 0 ? vy : 0);
+}
+
+__device__ __forceinline__ unsigned long long flat_points(long long N, int items) {
+  const long long base = (long long)blockIdx.x * 256 * items;
+  const long long v = N - base;
+  return (unsigned long long)(v < 0 ? 0 : (v > 256LL * items ? 256LL * items : v));
+}
+
+// (A_l + s I) x at interior point (i,j,k), flux form sum_f w_f (x_c - x_nb) + s x_c.
+// Also returns the diagonal through *dg when dg != nullptr.
+template <typename T, int DIM, bool VAR>
+__device__ __forceinline__ T apply_pt(const LevelDev<T>& L, const T* __restrict__ x, int i, int j, int k,
+                                      long long p, T s, T* dg) {
+  const int n = L.n;
+  const T xc = x[p];
+  const T xl = i > 0 ? x[p - 1] : T(0);
+  const T xr = i < n - 1 ? x[p + 1] : T(0);
+  const T xd = j > 0 ? x[p - n] : T(0);
+  const T xu = j < n - 1 ? x[p + n] : T(0);
+  const long long nn = (long long)n * n;
+  T xb = T(0), xf = T(0);
+  if (DIM == 3) {
+    xb = k > 0 ? x[p - nn] : T(0);
+    xf = k < n - 1 ? x[p + nn] : T(0);
+  }
+  if (!VAR) {
+    const T w = L.wc;
+    T sum = (xc - xl) + (xc - xr) + (xc - xd) + (xc - xu);
+    if (DIM == 3) sum += (xc - xb) + (xc - xf);
+    if (dg) *dg = w * T(2 * DIM) + s;
+    return w * sum + s * xc;
+  } else {
+    const long long fx = ((long long)k * n + j) * (n + 1) + i;
+    const T wl = L.wf0[fx], wr = L.wf0[fx + 1];
+    const long long fy = ((long long)k * (n + 1) + j) * n + i;
+    const T wd = L.wf1[fy], wu = L.wf1[fy + n];
+    T acc = wl * (xc - xl) + wr * (xc - xr) + wd * (xc - xd) + wu * (xc - xu);
+    T d = wl + wr + wd + wu;
+    if (DIM == 3) {
+      const long long fz = ((long long)k * n + j) * n + i;
+      const T wb = L.wf2[fz], wf = L.wf2[fz + nn];
+      acc += wb * (xc - xb) + wf * (xc - xf);
+      d += wb + wf;
+    }
+    if (dg) *dg = d + s;
+    return acc + s * xc;
+  }
+}
+
+template <typename T, int DIM, bool VAR>
+__device__ __forceinline__ T diag_pt(const LevelDev<T>& L, int i, int j, int k, T s) {
+  if (!VAR) return L.wc * T(2 * DIM) + s;
+  const int n = L.n;
+  const long long fx = ((long long)k * n + j) * (n + 1) + i;
+  const long long fy = ((long long)k * (n + 1) + j) * n + i;
+  T d = L.wf0[fx] + L.wf0[fx + 1] + L.wf1[fy] + L.wf1[fy + n];
+  if (DIM == 3) {
+    const long long fz = ((long long)k * n + j) * n + i;
+    d += L.wf2[fz] + L.wf2[fz + (long long)n * n];
+  }
+  return d + s;
+}
+
+// --------------------------------------------------------------------------
+// smoother: x_out = x_in + omega D^-1 (b - (A+s) x_in)   (x_in = 0 if ZERO)
+// DOT: partial = b . x_out  (r.z when this is the last sweep of z = M r)
+// --------------------------------------------------------------------------
+template <typename T, int DIM, bool VAR, bool ZERO, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_jacobi(LevelDev<T> L, const T* __restrict__ b,
+                                                   const T* __restrict__ xin, T* __restrict__ xout,
+                                                   const T* __restrict__ shift, const int* __restrict__ active,
+                                                   T omega, double* __restrict__ partial,
+                                                   unsigned long long* __restrict__ ctr) {
+  const int sys = blockIdx.z;
+  if (!active[sys]) return;
+  int i, j, k;
+  tile_ijk<DIM>(L.n, i, j, k);
+  const bool ok = i < L.n && j < L.n;
+  const long long off = (long long)sys * L.N;
+  const long long p = ((long long)k * L.n + j) * L.n + i;
+  const T s = shift[sys];
+  // b and x_out, plus x_in unless the guess is zero; faces once per launch
+  count_bytes(ctr, tile_points(L.n) * sizeof(T) * ((ZERO ? 2 : 3) + (VAR && sys == 0 ? DIM : 0)));
+  double dot = 0.0;
+  if (ok) {
+    const T bv = b[off + p];
+    T xn;
+    if (ZERO) {
+      xn = omega * bv / diag_pt<T, DIM, VAR>(L, i, j, k, s);
+    } else {
+      T dg;
+      const T ax = apply_pt<T, DIM, VAR>(L, xin + off, i, j, k, p, s, &dg);
+      xn = xin[off + p] + omega * (bv - ax) / dg;
+    }
+    xout[off + p] = xn;
+    if (DOT) dot = (double)bv * (double)xn;
+  }
+  if (DOT) write_partial_tile(partial, sys, dot);
+}
+
+// --------------------------------------------------------------------------
+// b_c = R (b - (A+s) x): full weighting of the fine residual (weights
+// (1/4, 1/2, 1/4) per axis), fine node 2I+1 under coarse node I (0-based).
+// --------------------------------------------------------------------------
+template <typename T, int DIM, bool VAR>
+__global__ __launch_bounds__(kBlock) void k_restrict(LevelDev<T> Lf, LevelDev<T> Lc, const T* __restrict__ b,
+                                                     const T* __restrict__ x, T* __restrict__ bc,
+                                                     const T* __restrict__ shift, const int* __restrict__ active,
+                                                     unsigned long long* __restrict__ ctr) {
+  const int sys = blockIdx.z;
+  if (!active[sys]) return;
+  // per coarse point: b and x on its 2^dim fine points, b_c written
+  count_bytes(ctr, tile_points(Lc.n) * sizeof(T) * (2 * (1 << DIM) + 1 + (VAR && sys == 0 ? DIM * (1 << DIM) : 0)));
+  int I, J, K;
+  tile_ijk<DIM>(Lc.n, I, J, K);
+  if (I >= Lc.n || J >= Lc.n) return;
+  const int nf = Lf.n;
+  const T s = shift[sys];
+  const T* bs = b + (long long)sys * Lf.N;
+  const T* xs = x + (long long)sys * Lf.N;
+  const T wt[3] = {T(0.25), T(0.5), T(0.25)};
+  T acc = T(0);
+  const int kmin = DIM == 3 ? -1 : 0, kmax = DIM == 3 ? 1 : 0;
+  for (int dk = kmin; dk <= kmax; ++dk) {
+    const int fk = DIM == 3 ? 2 * K + 1 + dk : 0;
+    const T wk = DIM == 3 ? wt[dk + 1] : T(1);
+    for (int dj = -1; dj <= 1; ++dj) {
+      const int fj = 2 * J + 1 + dj;
+      for (int di = -1; di <= 1; ++di) {
+        const int fi = 2 * I + 1 + di;
+        const long long p = ((long long)fk * nf + fj) * nf + fi;
+        const T r = bs[p] - apply_pt<T, DIM, VAR>(Lf, xs, fi, fj, fk, p, s, nullptr);
+        acc += wk * wt[dj + 1] * wt[di + 1] * r;
+      }
+    }
+  }
+  bc[(long long)sys * Lc.N + ((long long)K * Lc.n + J) * Lc.n + I] = acc;
+}
+
+// --------------------------------------------------------------------------
+// x_f += P x_c  (multilinear interpolation, P = 2^dim R^T)
+// --------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ int axis_parents(int f, int nc, int* ci, T* w) {
+  if (f & 1) {
+    ci[0] = (f - 1) >> 1;
+    w[0] = T(1);
+    return 1;
+  }
+  int cnt = 0;
+  const int c0 = (f >> 1) - 1, c1 = f >> 1;
+  if (c0 >= 0) { ci[cnt] = c0; w[cnt] = T(0.5); ++cnt; }
+  if (c1 < nc) { ci[cnt] = c1; w[cnt] = T(0.5); ++cnt; }
+  return cnt;
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ T interp_pt(const T* __restrict__ xc, int nc, int fi, int fj, int fk) {
+  int ci[2], cj[2], ck[2];
+  T wi[2], wj[2], wk[2];
+  const int ni = axis_parents<T>(fi, nc, ci, wi);
+  const int nj = axis_parents<T>(fj, nc, cj, wj);
+  int nk = 1;
+  ck[0] = 0;
+  wk[0] = T(1);
+  if (DIM == 3) nk = axis_parents<T>(fk, nc, ck, wk);
+  T v = T(0);
+  for (int c = 0; c < nk; ++c)
+    for (int b = 0; b < nj; ++b)
+      for (int a = 0; a < ni; ++a)
+        v += wk[c] * wj[b] * wi[a] * xc[((long long)ck[c] * nc + cj[b]) * nc + ci[a]];
+  return v;
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_prolong(LevelDev<T> Lc, LevelDev<T> Lf, const T* __restrict__ xc,
+                                                    T* __restrict__ xf, const int* __restrict__ active,
+                                                    unsigned long long* __restrict__ ctr) {
+  const int sys = blockIdx.z;
+  if (!active[sys]) return;
+  // x_f read and written; x_c read once (1/2^dim per fine point)
+  count_bytes(ctr, tile_points(Lf.n) * sizeof(T) * 2 + tile_points(Lf.n) * sizeof(T) / (1 << DIM));
+  int i, j, k;
+  tile_ijk<DIM>(Lf.n, i, j, k);
+  if (i >= Lf.n || j >= Lf.n) return;
+  const long long p = ((long long)k * Lf.n + j) * Lf.n + i;
+  xf[(long long)sys * Lf.N + p] += interp_pt<T, DIM>(xc + (long long)sys * Lc.N, Lc.n, i, j, k);
+}
+
+// --------------------------------------------------------------------------
+// coarse solve: `cycles` V-cycles on the levels in H, one workgroup per system,
+// all vectors in LDS.  Symmetric (nu Jacobi sweeps before and after), so the
+// composite is an SPD preconditioner component.
+// --------------------------------------------------------------------------
+template <typename T, int DIM, bool VAR>
+__device__ void lds_smooth(const LevelDev<T>& L, T* X, const T* B, T* Tm, T s, T omega, int sweeps) {
+  const int n = L.n;
+  const int nthr = blockDim.x;
+  for (int sw = 0; sw < sweeps; ++sw) {
+    for (int p = threadIdx.x; p < L.N; p += nthr) {
+      const int i = p % n;
+      const int j = (p / n) % n;
+      const int k = DIM == 3 ? p / (n * n) : 0;
+      T dg;
+      const T ax = apply_pt<T, DIM, VAR>(L, X, i, j, k, p, s, &dg);
+      Tm[p] = X[p] + omega * (B[p] - ax) / dg;
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < L.N; p += nthr) X[p] = Tm[p];
+    __syncthreads();
+  }
+}
+
+template <typename T, int DIM, bool VAR>
+__global__ __launch_bounds__(256) void k_coarse(LdsHierarchy<T> H, const T* __restrict__ b, T* __restrict__ x,
+                                                const T* __restrict__ shift, const int* __restrict__ active,
+                                                unsigned long long* __restrict__ ctr) {
+  extern __shared__ unsigned char smem_raw[];
+  T* sm = reinterpret_cast<T*>(smem_raw);
+  const int sys = blockIdx.x;
+  if (!active[sys]) return;
+  count_bytes(ctr, 2ULL * H.lev[0].N * sizeof(T));
+  const T s = shift[sys];
+  const int nthr = blockDim.x;
+  const LevelDev<T>& L0 = H.lev[0];
+  T* X0 = sm + H.off[0];
+  T* B0 = X0 + L0.N;
+  for (int p = threadIdx.x; p < L0.N; p += nthr) {
+    B0[p] = b[(long long)sys * L0.N + p];
+    X0[p] = T(0);
+  }
+  __syncthreads();
+  for (int cyc = 0; cyc < H.cycles; ++cyc) {
+    for (int l = 0; l + 1 < H.nlev; ++l) {
+      const LevelDev<T>& Lf = H.lev[l];
+      const LevelDev<T>& Lc = H.lev[l + 1];
+      T* X = sm + H.off[l];
+      T* B = X + Lf.N;
+      T* Tm = B + Lf.N;
+      lds_smooth<T, DIM, VAR>(Lf, X, B, Tm, s, H.omega, H.nu);
+      // residual on the fine level into Tm, then full weighting into B_c
+      for (int p = threadIdx.x; p < Lf.N; p += nthr) {
+        const int i = p % Lf.n;
+        const int j = (p / Lf.n) % Lf.n;
+        const int k = DIM == 3 ? p / (Lf.n * Lf.n) : 0;
+        Tm[p] = B[p] - apply_pt<T, DIM, VAR>(Lf, X, i, j, k, p, s, nullptr);
+      }
+      __syncthreads();
+      T* Xc = sm + H.off[l + 1];
+      T* Bc = Xc + Lc.N;
+      const T wt[3] = {T(0.25), T(0.5), T(0.25)};
+      for (int p = threadIdx.x; p < Lc.N; p += nthr) {
+        const int I = p % Lc.n;
+        const int J = (p / Lc.n) % Lc.n;
+        const int K = DIM == 3 ? p / (Lc.n * Lc.n) : 0;
+        T acc = T(0);
+        for (int dk = (DIM == 3 ? -1 : 0); dk <= (DIM == 3 ? 1 : 0); ++dk) {
+          const int fk = DIM == 3 ? 2 * K + 1 + dk : 0;
+          const T wk = DIM == 3 ? wt[dk + 1] : T(1);
+          for (int dj = -1; dj <= 1; ++dj)
+            for (int di = -1; di <= 1; ++di)
+              acc += wk * wt[dj + 1] * wt[di + 1] * Tm[((long long)fk * Lf.n + 2 * J + 1 + dj) * Lf.n + 2 * I + 1 + di];
+        }
+        Bc[p] = acc;
+        Xc[p] = T(0);
+      }
+      __syncthreads();
+    }
+    {  // bottom level
+      const int l = H.nlev - 1;
+      const LevelDev<T>& Lb = H.lev[l];
+      T* X = sm + H.off[l];
+      T* B = X + Lb.N;
+      T* Tm = B + Lb.N;
+      if (Lb.N == 1) {
+        if (threadIdx.x == 0) X[0] = B[0] / diag_pt<T, DIM, VAR>(Lb, 0, 0, 0, s);
+        __syncthreads();
+      } else {
+        lds_smooth<T, DIM, VAR>(Lb, X, B, Tm, s, H.omega, H.bottom_sweeps);
+      }
+    }
+    for (int l = H.nlev - 2; l >= 0; --l) {
+      const LevelDev<T>& Lf = H.lev[l];
+      const LevelDev<T>& Lc = H.lev[l + 1];
+      T* X = sm + H.off[l];
+      T* B = X + Lf.N;
+      T* Tm = B + Lf.N;
+      const T* Xc = sm + H.off[l + 1];
+      for (int p = threadIdx.x; p < Lf.N; p += nthr) {
+        const int i = p % Lf.n;
+        const int j = (p / Lf.n) % Lf.n;
+        const int k = DIM == 3 ? p / (Lf.n * Lf.n) : 0;
+        X[p] += interp_pt<T, DIM>(Xc, Lc.n, i, j, k);
+      }
+      __syncthreads();
+      lds_smooth<T, DIM, VAR>(Lf, X, B, Tm, s, H.omega, H.nu);
+    }
+  }
+  for (int p = threadIdx.x; p < L0.N; p += nthr) x[(long long)sys * L0.N + p] = X0[p];
+}
+
+// --------------------------------------------------------------------------
+// PCG pieces
+// --------------------------------------------------------------------------
+template <typename T, int DIM, bool VAR>
+__global__ __launch_bounds__(kBlock) void k_spmv_dot(LevelDev<T> L, const T* __restrict__ pv, T* __restrict__ q,
+                                                     const T* __restrict__ shift, const int* __restrict__ active,
+                                                     double* __restrict__ partial, unsigned long long* __restrict__ ctr) {
+  const int sys = blockIdx.z;
+  if (!active[sys]) return;
+  count_bytes(ctr, tile_points(L.n) * sizeof(T) * (2 + (VAR && sys == 0 ? DIM : 0)));
+  int i, j, k;
+  tile_ijk<DIM>(L.n, i, j, k);
+  const bool ok = i < L.n && j < L.n;
+  const long long off = (long long)sys * L.N;
+  const long long p = ((long long)k * L.n + j) * L.n + i;
+  double dot = 0.0;
+  if (ok) {
+    const T qv = apply_pt<T, DIM, VAR>(L, pv + off, i, j, k, p, shift[sys], nullptr);
+    q[off + p] = qv;
+    dot = (double)pv[off + p] * (double)qv;
+  }
+  write_partial_tile(partial, sys, dot);
+}
+
+constexpr int kFlatItems = 4;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_update_xr(long long N, T* __restrict__ x, T* __restrict__ r,
+                                                   const T* __restrict__ pv, const T* __restrict__ q,
+                                                   const double* __restrict__ alpha, const int* __restrict__ active,
+                                                   double* __restrict__ partial, unsigned long long* __restrict__ ctr) {
+  const int sys = blockIdx.y;
+  if (!active[sys]) return;
+  count_bytes(ctr, flat_points(N, kFlatItems) * sizeof(T) * 6);
+  const T a = (T)alpha[sys];
+  const long long off = (long long)sys * N;
+  const long long base = (long long)blockIdx.x * 256 * kFlatItems + threadIdx.x;
+  double rr = 0.0;
+#pragma unroll
+  for (int it = 0; it < kFlatItems; ++it) {
+    const long long p = base + (long long)it * 256;
+    if (p < N) {
+      x[off + p] += a * pv[off + p];
+      const T rv = r[off + p] - a * q[off + p];
+      r[off + p] = rv;
+      rr += (double)rv * (double)rv;
+    }
+  }
+  write_partial_flat(partial, sys, rr);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_update_p(long long N, T* __restrict__ pv, const T* __restrict__ z,
+                                                  const double* __restrict__ beta, const int* __restrict__ active,
+                                                  unsigned long long* __restrict__ ctr) {
+  const int sys = blockIdx.y;
+  if (!active[sys]) return;
+  const T bt = (T)beta[sys];
+  count_bytes(ctr, flat_points(N, kFlatItems) * sizeof(T) * (bt == T(0) ? 2 : 3));
+  const long long off = (long long)sys * N;
+  const long long base = (long long)blockIdx.x * 256 * kFlatItems + threadIdx.x;
+#pragma unroll
+  for (int it = 0; it < kFlatItems; ++it) {
+    const long long p = base + (long long)it * 256;
+    if (p < N) pv[off + p] = bt == T(0) ? z[off + p] : z[off + p] + bt * pv[off + p];
+  }
+}
+
+// r = (T) f[rhs of system], x = 0, partial = ||r||^2 (FP64 from the FP64 input).
+template <typename T>
+__global__ __launch_bounds__(256) void k_copy_rhs(long long N, const double* __restrict__ f, T* __restrict__ r,
+                                                  T* __restrict__ x, int nrhs,
+                                                  const int* __restrict__ active, double* __restrict__ partial) {
+  const int sys = blockIdx.y;
+  if (!active[sys]) return;
+  const int rhs = sys % nrhs;
+  const long long off = (long long)sys * N;
+  const long long base = (long long)blockIdx.x * 256 * kFlatItems + threadIdx.x;
+  double ff = 0.0;
+#pragma unroll
+  for (int it = 0; it < kFlatItems; ++it) {
+    const long long p = base + (long long)it * 256;
+    if (p < N) {
+      const double fv = f[(long long)rhs * N + p];
+      r[off + p] = (T)fv;
+      x[off + p] = T(0);
+      ff += fv * fv;
+    }
+  }
+  write_partial_flat(partial, sys, ff);
+}
+
+// --------------------------------------------------------------------------
+// FP64 refinement residual: r32 = f - (A + s) x64, e = 0, partial = ||r||^2
+// --------------------------------------------------------------------------
+template <int DIM, bool VAR>
+__global__ __launch_bounds__(kBlock) void k_residual64(LevelDev<double> L, const double* __restrict__ f,
+                                                       const double* __restrict__ x64, float* __restrict__ e,
+                                                       float* __restrict__ r32, const double* __restrict__ shift,
+                                                       const int* __restrict__ active64, int nrhs,
+                                                       double* __restrict__ partial, unsigned long long* __restrict__ ctr) {
+  const int sys = blockIdx.z;
+  if (!active64[sys]) return;
+  // x64, f read (FP64); r32, e written (FP32)
+  count_bytes(ctr, tile_points(L.n) * (8 + 8 + 4 + 4 + (VAR && sys == 0 ? 8 * DIM : 0)));
+  int i, j, k;
+  tile_ijk<DIM>(L.n, i, j, k);
+  const bool ok = i < L.n && j < L.n;
+  const long long off = (long long)sys * L.N;
+  const long long p = ((long long)k * L.n + j) * L.n + i;
+  const int rhs = sys % nrhs;
+  double rr = 0.0;
+  if (ok) {
+    const double ax = apply_pt<double, DIM, VAR>(L, x64 + off, i, j, k, p, shift[sys], nullptr);
+    const double rv = f[(long long)rhs * L.N + p] - ax;
+    r32[off + p] = (float)rv;
+    e[off + p] = 0.0f;
+    rr = rv * rv;
+  }
+  write_partial_tile(partial, sys, rr);
+}
+
+// first refinement step: x64 = 0 so r = f; partial = ||f||^2
+__global__ __launch_bounds__(256) void k_first_residual(long long N, const double* __restrict__ f,
+                                                        double* __restrict__ x64, float* __restrict__ e,
+                                                        float* __restrict__ r32, int nrhs,
+                                                        const int* __restrict__ active64,
+                                                        double* __restrict__ partial) {
+  const int sys = blockIdx.y;
+  if (!active64[sys]) return;
+  const int rhs = sys % nrhs;
+  const long long off = (long long)sys * N;
+  const long long base = (long long)blockIdx.x * 256 * kFlatItems + threadIdx.x;
+  double ff = 0.0;
+#pragma unroll
+  for (int it = 0; it < kFlatItems; ++it) {
+    const long long p = base + (long long)it * 256;
+    if (p < N) {
+      const double fv = f[(long long)rhs * N + p];
+      r32[off + p] = (float)fv;
+      x64[off + p] = 0.0;
+      e[off + p] = 0.0f;
+      ff += fv * fv;
+    }
+  }
+  write_partial_flat(partial, sys, ff);
+}
+
+// x64 += e (final refinement update after the last inner solve)
+__global__ __launch_bounds__(256) void k_x_from_e(long long N, const float* __restrict__ e, double* __restrict__ x64,
+                                                  const int* __restrict__ active64) {
+  const int sys = blockIdx.y;
+  if (!active64[sys]) return;
+  const long long off = (long long)sys * N;
+  const long long base = (long long)blockIdx.x * 256 * kFlatItems + threadIdx.x;
+#pragma unroll
+  for (int it = 0; it < kFlatItems; ++it) {
+    const long long p = base + (long long)it * 256;
+    if (p < N) x64[off + p] += (double)e[off + p];
+  }
+}
+
+// u[r] = sum_j w_j x[j * stride + r], summed in the fixed order j = 0..nterms-1 (eq. (16))
+__global__ __launch_bounds__(256) void k_combine(long long N, const double* __restrict__ x,
+                                                 const double* __restrict__ w, int nterms, int stride,
+                                                 double* __restrict__ u, unsigned long long* __restrict__ ctr) {
+  const int r = blockIdx.y;
+  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  {
+    const long long v = N - (long long)blockIdx.x * 256;
+    count_bytes(ctr, (unsigned long long)(v > 256 ? 256 : v) * 8ULL * (nterms + 1));
+  }
+  if (p >= N) return;
+  double acc = 0.0;
+  for (int j = 0; j < nterms; ++j) acc += w[j] * x[((long long)j * stride + r) * N + p];
+  u[(long long)r * N + p] = acc;
+}
+
+template <int DIM, bool VAR>
+__global__ __launch_bounds__(kBlock) void k_apply64(LevelDev<double> L, const double* __restrict__ x,
+                                                    double* __restrict__ y, double s) {
+  const int v = blockIdx.z;
+  int i, j, k;
+  tile_ijk<DIM>(L.n, i, j, k);
+  if (i >= L.n || j >= L.n) return;
+  const long long off = (long long)v * L.N;
+  const long long p = ((long long)k * L.n + j) * L.n + i;
+  y[off + p] = apply_pt<double, DIM, VAR>(L, x + off, i, j, k, p, s, nullptr);
+}
+
+// --------------------------------------------------------------------------
+// per-system scalar updates: one block per system sums the block partials in
+// a fixed order, thread 0 advances that system's state.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_scalars(int op, const double* __restrict__ partial, int nblk, SysState S,
+                                                 double tol, int max_iter) {
+  const int sys = blockIdx.x;
+  const bool inner = op != OP_OUTER;
+  if (inner && !S.active[sys]) return;
+  if (!inner && !S.active64[sys]) return;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) v += partial[(size_t)sys * nblk + b];
+  // block_sum assumes a 2D-shaped block; a 1D block of 256 is the same
+  const double tot = block_sum(v);
+  if (threadIdx.x != 0) return;
+  switch (op) {
+    case OP_INIT: {  // tot = ||b||^2 of the PCG right-hand side
+      S.bnorm2[sys] = tot;
+      S.iters[sys] = 0;
+      S.relres[sys] = 1.0;
+      S.beta[sys] = 0.0;
+      if (!(tot > 0.0)) {
+        S.active[sys] = 0;
+        if (!isfinite(tot)) S.flags[sys] |= 1;
+        S.relres[sys] = 0.0;
+      }
+      break;
+    }
+    case OP_BETA: {  // tot = r.z
+      if (S.iters[sys] == 0) {
+        S.rho[sys] = tot;
+        S.beta[sys] = 0.0;
+      } else {
+        S.beta[sys] = tot / S.rho[sys];
+        S.rho[sys] = tot;
+      }
+      if (!isfinite(tot)) {
+        S.flags[sys] |= 1;
+        S.active[sys] = 0;
+      }
+      break;
+    }
+    case OP_ALPHA: {  // tot = p.q
+      if (!(tot > 0.0) || !isfinite(tot)) {
+        // p.q <= 0 only when the residual has vanished to rounding: stop here
+        if (!isfinite(tot)) S.flags[sys] |= 1;
+        S.active[sys] = 0;
+        S.alpha[sys] = 0.0;
+      } else {
+        S.alpha[sys] = S.rho[sys] / tot;
+      }
+      break;
+    }
+    case OP_RESID: {  // tot = ||r||^2
+      const int it = S.iters[sys] + 1;
+      S.iters[sys] = it;
+      S.total_iters[sys] += 1;
+      const double rel = sqrt(tot / S.bnorm2[sys]);
+      S.relres[sys] = rel;
+      if (!isfinite(rel)) {
+        S.flags[sys] |= 1;
+        S.active[sys] = 0;
+      } else if (rel <= tol || it >= max_iter) {
+        S.active[sys] = 0;
+      }
+      break;
+    }
+    case OP_OUTER: {  // tot = ||f - (A+s) x64||^2 ; first call: x64 = 0 so tot = ||f||^2
+      const int o = S.outer[sys];
+      if (!isfinite(tot)) {
+        S.flags[sys] |= 1;
+        S.relres64[sys] = tot;
+        S.active64[sys] = 0;
+        S.active[sys] = 0;
+        break;
+      }
+      if (o == 0) S.fnorm2[sys] = tot;
+      const double fn = S.fnorm2[sys];
+      const double rel = fn > 0.0 ? sqrt(tot / fn) : 0.0;
+      S.relres64[sys] = rel;
+      S.outer[sys] = o + 1;
+      if (!isfinite(rel)) {
+        S.flags[sys] |= 1;
+        S.active64[sys] = 0;
+        S.active[sys] = 0;
+      } else if (rel <= tol || o >= max_iter) {
+        S.active64[sys] = 0;
+        S.active[sys] = 0;
+      } else {
+        S.active[sys] = 1;   // re-arm the inner solve on this residual
+        S.bnorm2[sys] = tot;
+        S.iters[sys] = 0;
+        S.relres[sys] = 1.0;
+        S.beta[sys] = 0.0;
+      }
+      break;
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// launchers
+// --------------------------------------------------------------------------
+static inline dim3 stencil_grid(int dim, int n, int nsys) {
+  const int xt = (n + kTileX - 1) / kTileX;
+  const int yt = (n + kTileY - 1) / kTileY;
+  return dim3(xt, yt * (dim == 3 ? n : 1), nsys);
+}
+
+int stencil_blocks(int dim, int n) {
+  const dim3 g = stencil_grid(dim, n, 1);
+  return (int)(g.x * g.y);
+}
+
+int flat_blocks(long long N) {
+  const long long per = 256LL * kFlatItems;
+  return (int)((N + per - 1) / per);
+}
+
+static inline dim3 flat_grid(long long N, int nsys) {
+  const long long per = 256LL * kFlatItems;
+  return dim3((unsigned)((N + per - 1) / per), nsys, 1);
+}
+
+#define BURA_DISPATCH_DV(dim, var, KERNEL, ...)        \
+  do {                                                 \
+    if (dim == 2) {                                    \
+      if (var) KERNEL(2, true, __VA_ARGS__);           \
+      else KERNEL(2, false, __VA_ARGS__);              \
+    } else {                                           \
+      if (var) KERNEL(3, true, __VA_ARGS__);           \
+      else KERNEL(3, false, __VA_ARGS__);              \
+    }                                                  \
+  } while (0)
+
+template <typename T>
+void Launch<T>::jacobi(int dim, bool var, const LevelDev<T>& L, const T* b, const T* xin, T* xout, const T* shift,
+                       const int* active, T omega, bool zero_guess, double* partial, int nsys, hipStream_t st,
+                       unsigned long long* ctr) {
+  const dim3 g = stencil_grid(dim, L.n, nsys), blk(kTileX, kTileY);
+  const bool dot = partial != nullptr;
+#define K_JAC(D, V, Z, DT) hipLaunchKernelGGL((k_jacobi<T, D, V, Z, DT>), g, blk, 0, st, L, b, xin, xout, shift, active, omega, partial, ctr)
+#define K_JAC4(D, V, dummy)                       \
+  do {                                            \
+    if (zero_guess) {                             \
+      if (dot) K_JAC(D, V, true, true);           \
+      else K_JAC(D, V, true, false);              \
+    } else {                                      \
+      if (dot) K_JAC(D, V, false, true);          \
+      else K_JAC(D, V, false, false);             \
+    }                                             \
+  } while (0)
+  BURA_DISPATCH_DV(dim, var, K_JAC4, 0);
+#undef K_JAC4
+#undef K_JAC
+}
+
+template <typename T>
+void Launch<T>::restrict_residual(int dim, bool var, const LevelDev<T>& Lf, const LevelDev<T>& Lc, const T* b,
+                                  const T* x, T* bc, const T* shift, const int* active, int nsys, hipStream_t st,
+                                  unsigned long long* ctr) {
+  const dim3 g = stencil_grid(dim, Lc.n, nsys), blk(kTileX, kTileY);
+#define K_RES(D, V, dummy) hipLaunchKernelGGL((k_restrict<T, D, V>), g, blk, 0, st, Lf, Lc, b, x, bc, shift, active, ctr)
+  BURA_DISPATCH_DV(dim, var, K_RES, 0);
+#undef K_RES
+}
+
+template <typename T>
+void Launch<T>::prolong_add(int dim, const LevelDev<T>& Lc, const LevelDev<T>& Lf, const T* xc, T* xf,
+                            const int* active, int nsys, hipStream_t st, unsigned long long* ctr) {
+  const dim3 g = stencil_grid(dim, Lf.n, nsys), blk(kTileX, kTileY);
+  if (dim == 2) hipLaunchKernelGGL((k_prolong<T, 2>), g, blk, 0, st, Lc, Lf, xc, xf, active, ctr);
+  else hipLaunchKernelGGL((k_prolong<T, 3>), g, blk, 0, st, Lc, Lf, xc, xf, active, ctr);
+}
+
+template <typename T>
+void Launch<T>::coarse_solve(int dim, bool var, const LdsHierarchy<T>& H, const T* b, T* x, const T* shift,
+                             const int* active, int nsys, size_t lds_bytes, hipStream_t st,
+                             unsigned long long* ctr) {
+  const dim3 g(nsys), blk(256);
+#define K_CO(D, V, dummy) hipLaunchKernelGGL((k_coarse<T, D, V>), g, blk, lds_bytes, st, H, b, x, shift, active, ctr)
+  BURA_DISPATCH_DV(dim, var, K_CO, 0);
+#undef K_CO
+}
+
+template <typename T>
+void Launch<T>::spmv_dot(int dim, bool var, const LevelDev<T>& L, const T* p, T* q, const T* shift,
+                         const int* active, double* partial, int nsys, hipStream_t st, unsigned long long* ctr) {
+  const dim3 g = stencil_grid(dim, L.n, nsys), blk(kTileX, kTileY);
+#define K_SP(D, V, dummy) hipLaunchKernelGGL((k_spmv_dot<T, D, V>), g, blk, 0, st, L, p, q, shift, active, partial, ctr)
+  BURA_DISPATCH_DV(dim, var, K_SP, 0);
+#undef K_SP
+}
+
+template <typename T>
+void Launch<T>::update_xr(const LevelDev<T>& L, int dim, T* x, T* r, const T* p, const T* q, const double* alpha,
+                          const int* active, double* partial, int nsys, hipStream_t st, unsigned long long* ctr) {
+  (void)dim;
+  hipLaunchKernelGGL((k_update_xr<T>), flat_grid(L.N, nsys), dim3(256), 0, st, L.N, x, r, p, q, alpha, active, partial,
+                     ctr);
+}
+
+template <typename T>
+void Launch<T>::update_p(const LevelDev<T>& L, int dim, T* p, const T* z, const double* beta, const int* active,
+                         int nsys, hipStream_t st, unsigned long long* ctr) {
+  (void)dim;
+  hipLaunchKernelGGL((k_update_p<T>), flat_grid(L.N, nsys), dim3(256), 0, st, L.N, p, z, beta, active, ctr);
+}
+
+template <typename T>
+void Launch<T>::copy_rhs(const LevelDev<T>& L, int dim, const double* f, T* r, T* x, int nrhs, const int* active,
+                         double* partial, int nsys, hipStream_t st) {
+  (void)dim;
+  // a batch is either all systems (sys = j * nrhs + r) or one pole (sys = r): rhs = sys % nrhs
+  hipLaunchKernelGGL((k_copy_rhs<T>), flat_grid(L.N, nsys), dim3(256), 0, st, L.N, f, r, x, nrhs, active, partial);
+}
+
+template struct Launch<float>;
+template struct Launch<double>;
+
+void launch_residual64(int dim, bool var, const LevelDev<double>& L, const double* f, const double* x64, float* e,
+                       float* r32, const double* shift, const int* active64, double* partial, int nrhs, int nsys,
+                       bool first, hipStream_t st, unsigned long long* ctr) {
+  if (first) {
+    hipLaunchKernelGGL(k_first_residual, flat_grid(L.N, nsys), dim3(256), 0, st, L.N, f, const_cast<double*>(x64), e,
+                       r32, nrhs, active64, partial);
+    return;
+  }
+  const dim3 g = stencil_grid(dim, L.n, nsys), blk(kTileX, kTileY);
+#define K_R64(D, V, dummy) \
+  hipLaunchKernelGGL((k_residual64<D, V>), g, blk, 0, st, L, f, x64, e, r32, shift, active64, nrhs, partial, ctr)
+  BURA_DISPATCH_DV(dim, var, K_R64, 0);
+#undef K_R64
+}
+
+void launch_x_from_e(const LevelDev<double>& L, int dim, const float* e, double* x64, const int* active64, int nsys,
+                     hipStream_t st) {
+  (void)dim;
+  hipLaunchKernelGGL(k_x_from_e, flat_grid(L.N, nsys), dim3(256), 0, st, L.N, e, x64, active64);
+}
+
+void launch_combine(long long N, const double* x, const double* w, int nterms, int nrhs, int stride, double* u,
+                    hipStream_t st, unsigned long long* ctr) {
+  const dim3 g((unsigned)((N + 255) / 256), nrhs);
+  hipLaunchKernelGGL(k_combine, g, dim3(256), 0, st, N, x, w, nterms, stride, u, ctr);
+}
+
+void launch_apply64(int dim, bool var, const LevelDev<double>& L, const double* x, double* y, double shift, int nvec,
+                    hipStream_t st) {
+  const dim3 g = stencil_grid(dim, L.n, nvec), blk(kTileX, kTileY);
+#define K_AP(D, V, dummy) hipLaunchKernelGGL((k_apply64<D, V>), g, blk, 0, st, L, x, y, shift)
+  BURA_DISPATCH_DV(dim, var, K_AP, 0);
+#undef K_AP
+}
+
+void launch_scalars(int op, const double* partial, int nblk, int nsys, SysState S, double tol, int max_iter,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_scalars, dim3(nsys), dim3(256), 0, st, op, partial, nblk, S, tol, max_iter);
+}
+
+__global__ void k_zero(unsigned char* p, size_t bytes) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < bytes; i += stride) p[i] = 0;
+}
+
+void launch_zero(void* p, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return;
+  const size_t blocks = std::min<size_t>((bytes + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st, (unsigned char*)p, bytes);
+}
+
+}  // namespace bura

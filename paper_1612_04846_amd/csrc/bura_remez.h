@@ -1,0 +1,10 @@
+// Host-side rational approximation (no HIP dependency; built by the host compiler).
+#pragma once
+#include <string>
+#include <vector>
+
+namespace bura {
+// (k,k) best uniform rational approximation r of t^(1-alpha) on [0,1] and its
+// partial fractions r(t)/t = sum_j c_j/(t - d_j), d_0 = 0 > d_1 > ... > d_k.
+int remez_bura(double alpha, int k, std::vector<double>& c, std::vector<double>& d, double& E, std::string& why);
+}  // namespace bura

@@ -1,0 +1,224 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle.
+
+Tolerances: the solver stops on the FP64 relative residual (tol); the
+combined result is compared with the oracle's u_r for the same c_j, d_j
+element by element through the relative l2 error and the max-norm error
+relative to max |u_r|.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from conftest import oracle_coeffs as oracle_bura
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _B():
+    import paper_1612_04846_amd as B
+    return B
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _errs(u, ref):
+    rel2 = np.linalg.norm((u - ref).reshape(u.shape[0], -1), axis=1) / np.linalg.norm(ref.reshape(ref.shape[0], -1), axis=1)
+    relinf = np.abs(u - ref).max() / np.abs(ref).max()
+    return float(rel2.max()), float(relinf)
+
+
+# ----------------------------------------------------------------------------
+# operator and scaling (Section 1.4 eq. (10), Section 5.3)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dim,n,var", [(2, 31, False), (3, 15, False), (2, 33, True), (3, 9, True), (2, 64, False)])
+def test_apply_matches_oracle_operator(dim, n, var):
+    from oracle import operators
+    B = _B()
+    coeff = synth.lognormal_coefficient(n, dim, tag=21) if var else None
+    A, lam = operators.scaled_operator(n, dim, coeff)
+    plan = B.Plan(dim, n, weights=[1.0], shifts=[0.0], coeff=coeff, precision=B.BURA_FP64)
+    lam_gpu, nlev, _ = plan.info
+    assert lam_gpu == pytest.approx(lam, rel=1e-13)
+    X = synth.normal_rhs(n, dim, nrhs=2, tag=22)
+    for shift in (0.0, 0.37):
+        y = _host(plan.apply(_dev(X), shift))
+        ref = np.stack([A @ X[i].ravel() + shift * X[i].ravel() for i in range(2)]).reshape(X.shape)
+        assert np.max(np.abs(y - ref)) <= 1e-14 * np.max(np.abs(ref)) * 8
+    plan.close()
+
+
+# ----------------------------------------------------------------------------
+# full solve with the oracle's coefficients (isolates the solver)
+# ----------------------------------------------------------------------------
+
+CASES = [
+    # dim, n, alpha, k, precision, schedule
+    (2, 63, 0.5, 5, "FP64", "BATCHED"),
+    (2, 63, 0.5, 5, "MIXED", "BATCHED"),
+    (2, 64, 0.5, 5, "FP64", "BATCHED"),      # 64x64 grid: no coarsening, Jacobi-PCG
+    (2, 37, 0.25, 7, "MIXED", "PER_POLE"),   # ragged: 37 -> 18, coarse level not 1 point
+    (3, 31, 0.25, 8, "MIXED", "BATCHED"),
+    (3, 15, 0.75, 7, "FP64", "PER_POLE"),
+    (2, 127, 0.75, 9, "MIXED", "BATCHED"),
+]
+
+
+@pytest.mark.parametrize("dim,n,alpha,k,prec,sched", CASES)
+def test_solve_matches_spectral_oracle(dim, n, alpha, k, prec, sched):
+    from oracle import spectral
+    B = _B()
+    b = oracle_bura(alpha, k)
+    c, d = b.c_f64, b.d_f64
+    F = synth.normal_rhs(n, dim, nrhs=2, tag=31)
+    plan = B.Plan(dim, n, weights=c, shifts=[-x for x in d], nrhs_max=2,
+                  precision=getattr(B, "BURA_" + prec), schedule=getattr(B, "BURA_" + sched), tol=1e-12)
+    res = plan.solve(_dev(F))
+    u = _host(res.u)
+    ref = spectral.bura_spectral(F, dim, c, d)
+    rel2, relinf = _errs(u, ref)
+    print(f"dim={dim} n={n} a={alpha} k={k} {prec} {sched} rel2={rel2:.2e} relinf={relinf:.2e} "
+          f"iters={list(res.report.iters)[:k+1]} outer={list(res.report.outer)[:k+1]}")
+    assert rel2 <= 1e-9 and relinf <= 1e-9
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["FP64", "MIXED"])
+def test_variable_coefficient_matches_direct_solves(prec):
+    from oracle import operators, shifted
+    B = _B()
+    n, dim, alpha, k = 63, 2, 0.6, 7
+    b = oracle_bura(alpha, k)
+    coeff = synth.lognormal_coefficient(n, dim, tag=41)
+    A, _ = operators.scaled_operator(n, dim, coeff)
+    F = synth.normal_rhs(n, dim, nrhs=3, tag=42)
+    ref = shifted.bura_by_solves(A, b.c_f64, b.d_f64, F)
+    plan = B.Plan(dim, n, weights=b.c_f64, shifts=[-x for x in b.d_f64], coeff=coeff, nrhs_max=3,
+                  precision=getattr(B, "BURA_" + prec), tol=1e-12)
+    res = plan.solve(_dev(F))
+    rel2, relinf = _errs(_host(res.u), ref)
+    print(f"var {prec} rel2={rel2:.2e} relinf={relinf:.2e} iters={list(res.report.iters)[:k+1]}")
+    assert rel2 <= 1e-9 and relinf <= 1e-9
+    plan.close()
+
+
+def test_batched_equals_per_pole_and_alone_equals_mixed():
+    """The same system gives bit-identical results whatever else is in the launch."""
+    B = _B()
+    b = oracle_bura(0.5, 5)
+    n = 63
+    F = synth.normal_rhs(n, 2, nrhs=3, tag=51)
+    kw = dict(weights=b.c_f64, shifts=[-x for x in b.d_f64], precision=B.BURA_MIXED, tol=1e-12)
+    p3 = B.Plan(2, n, nrhs_max=3, **kw)
+    u3 = _host(p3.solve(_dev(F)).u)
+    pp = B.Plan(2, n, nrhs_max=3, schedule=B.BURA_PER_POLE, **kw)
+    upp = _host(pp.solve(_dev(F)).u)
+    p1 = B.Plan(2, n, nrhs_max=1, **kw)
+    u1 = np.stack([_host(p1.solve(_dev(F[i:i + 1])).u)[0] for i in range(3)])
+    assert np.array_equal(u3, upp)
+    assert np.array_equal(u3, u1)
+    for p in (p3, pp, p1):
+        p.close()
+
+
+def test_zero_rhs_gives_zero():
+    B = _B()
+    b = oracle_bura(0.5, 5)
+    plan = B.Plan(2, 31, weights=b.c_f64, shifts=[-x for x in b.d_f64], nrhs_max=2)
+    F = np.zeros((2, 31, 31))
+    F[1] = synth.normal_rhs(31, 2, tag=61)[0]
+    u = _host(plan.solve(_dev(F)).u)
+    assert np.all(u[0] == 0.0)
+    assert np.abs(u[1]).max() > 0
+    plan.close()
+
+
+def test_fewer_rhs_than_slots():
+    from oracle import spectral
+    B = _B()
+    b = oracle_bura(0.5, 5)
+    plan = B.Plan(2, 31, weights=b.c_f64, shifts=[-x for x in b.d_f64], nrhs_max=4)
+    F = synth.normal_rhs(31, 2, nrhs=2, tag=62)
+    u = _host(plan.solve(_dev(F)).u)
+    ref = spectral.bura_spectral(F, 2, b.c_f64, b.d_f64)
+    assert _errs(u, ref)[0] <= 1e-9
+    plan.close()
+
+
+def test_nan_input_reports_enan():
+    B = _B()
+    b = oracle_bura(0.5, 5)
+    plan = B.Plan(2, 15, weights=b.c_f64, shifts=[-x for x in b.d_f64])
+    F = synth.normal_rhs(15, 2, tag=63)
+    F[0, 3, 3] = np.nan
+    res = plan.solve(_dev(F), ok=(B.BURA_OK, B.BURA_ENAN, B.BURA_ENOCONV))
+    assert res.report.status == B.BURA_ENAN
+    plan.close()
+
+
+# ----------------------------------------------------------------------------
+# full path: coefficients from the library's own Remez (bura_plan_create)
+# ----------------------------------------------------------------------------
+
+FULL = [
+    (2, 63, 0.5, 5, "MIXED"),
+    (2, 127, 0.25, 9, "FP64"),
+    (2, 255, 0.75, 9, "MIXED"),
+    (3, 31, 0.25, 8, "MIXED"),
+    (2, 64, 0.5, 5, "FP64"),
+]
+
+
+@pytest.mark.parametrize("dim,n,alpha,k,prec", FULL)
+def test_full_path_matches_oracle(dim, n, alpha, k, prec):
+    """u from bura_plan_create (library Remez + GPU solves) vs the oracle's own u_r."""
+    from oracle import metrics, spectral
+    B = _B()
+    b = oracle_bura(alpha, k)
+    F = synth.uniform_rhs(n, dim, nrhs=1, tag=71)
+    plan = B.Plan(dim, n, alpha, k, precision=getattr(B, "BURA_" + prec), tol=1e-12)
+    c_lib, d_lib, E_lib = plan.coeffs
+    assert E_lib == pytest.approx(float(b.E), rel=1e-10)
+    res = plan.solve(_dev(F))
+    u = _host(res.u)
+    ref = spectral.bura_spectral(F, dim, b.c_f64, b.d_f64)
+    rel2, relinf = _errs(u, ref)
+    # and the BURA error bound of Lemma 2.1 (gamma = 0) against the exact A^-alpha f
+    exact = spectral.exact_fractional(F, dim, alpha)
+    lhs, rhs = metrics.lemma_bound_sides(F, u, dim, alpha, float(b.E), 0.0)
+    print(f"full dim={dim} n={n} a={alpha} k={k} {prec}: rel2={rel2:.2e} relinf={relinf:.2e} "
+          f"bura_err={metrics.rel_err(u, exact):.2e} lemma lhs/rhs={float(lhs[0] / rhs[0]):.3f}")
+    assert rel2 <= 1e-9 and relinf <= 1e-9
+    assert np.all(lhs <= rhs * (1 + 1e-6))
+    plan.close()
+
+
+def test_submit_poll_matches_solve():
+    B = _B()
+    n = 63
+    F = _dev(synth.normal_rhs(n, 2, nrhs=2, tag=81))
+    plan = B.Plan(2, n, 0.5, 5, nrhs_max=2)
+    u_sync = _host(plan.solve(F).u)
+    u = torch.empty_like(F)
+    torch.cuda.synchronize()
+    B.bura_submit(plan.handle, F, u, 2)
+    import time
+    t0 = time.time()
+    while True:
+        code, rep = B.bura_poll(plan.handle)
+        if code != B.BURA_PENDING:
+            break
+        assert time.time() - t0 < 60
+        time.sleep(0.001)
+    assert code == B.BURA_OK
+    assert np.array_equal(_host(u), u_sync)
+    plan.close()
