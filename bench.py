@@ -153,6 +153,25 @@ def roofline(kstats):
     return roof, table
 
 
+def counter_traffic(workload, kclass):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it was
+    taken on the current kernel source (else None)."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_1612_04846_amd", "csrc", "bura_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*_hbm_counters.md")):
+        kv = {}
+        for line in open(path):
+            if ":" in line and not line.startswith(("#", "-", "`", " ")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        if kv.get("workload") == workload and kv.get("kernel_class") == kclass and \
+                kv.get("kernel_source_sha256_prefix") == sha:
+            return int(kv["traffic_bytes_per_launch"])
+    return None
+
+
 def cpu_baseline(w, res):
     """Oracle on the host: accuracy of the GPU results, and the timed CPU sample."""
     import numpy as np
@@ -211,9 +230,22 @@ def main():
     ap.add_argument("--workload", default="2d1023-k9-fp64-batched", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
+                    help="only run a plain device-to-device copy of this many GiB (counter calibration)")
     ap.add_argument("--also", default="2d1023-k9-fp64-per-pole,2d1023-k9-mixed-batched",
                     help="comma-separated extra workloads reported under 'paths' (empty: none)")
     args = ap.parse_args()
+    if args.copy_probe > 0:
+        import torch
+        nbytes = int(args.copy_probe * (1 << 30))
+        x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes, "launches": 3}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))
@@ -224,6 +256,8 @@ def main():
     import numpy as np
     lat_ms = np.array(res["lat"]) * 1e3
     roof, ktable = roofline(res["kstats"])
+    if roof is not None:
+        roof["traffic"] = counter_traffic(args.workload, roof["kernel"])
     out = {
         "metric": METRIC,
         "value": None,

@@ -66,25 +66,18 @@ __device__ __forceinline__ void write_partial_flat(double* partial, int sys, dou
   write_partial(partial, sys, v, blockIdx.x, gridDim.x);
 }
 
-// Profiling: one lane per block adds the block's algorithmic bytes (each
-// vector element read or written once) to a per-kernel-class counter.
+// Profiling: the first block of each system adds that system's algorithmic
+// bytes for the whole launch (each vector element read or written once) to a
+// per-kernel-class counter -- one atomic per system per launch.
+// Stencil launches: grid (x tiles, y tiles, system); element-wise launches:
+// grid (chunks, system); the coarse solve: one block per system.
+enum CountKind { COUNT_TILE, COUNT_FLAT, COUNT_ONE };
+
+template <CountKind K>
 __device__ __forceinline__ void count_bytes(unsigned long long* ctr, unsigned long long b) {
-  if (ctr != nullptr && threadIdx.x == 0 && threadIdx.y == 0) atomicAdd(ctr, b);
-}
-
-// points of the stencil tile handled by this block (clipped at the grid edge)
-__device__ __forceinline__ unsigned long long tile_points(int n) {
-  const int ytiles = (n + kTileY - 1) / kTileY;
-  const int by = blockIdx.y % ytiles;
-  const int vx = min(kTileX, n - (int)blockIdx.x * kTileX);
-  const int vy = min(kTileY, n - by * kTileY);
-  return (unsigned long long)(vx > 0 ? vx : 0) * (unsigned long long)(vy > 0 ? vy : 0);
-}
-
-__device__ __forceinline__ unsigned long long flat_points(long long N, int items) {
-  const long long base = (long long)blockIdx.x * 256 * items;
-  const long long v = N - base;
-  return (unsigned long long)(v < 0 ? 0 : (v > 256LL * items ? 256LL * items : v));
+  if (ctr == nullptr || threadIdx.x != 0 || threadIdx.y != 0) return;
+  const bool first = K == COUNT_ONE ? true : (K == COUNT_FLAT ? blockIdx.x == 0 : (blockIdx.x == 0 && blockIdx.y == 0));
+  if (first) atomicAdd(ctr, b);
 }
 
 // (A_l + s I) x at interior point (i,j,k), flux form sum_f w_f (x_c - x_nb) + s x_c.
@@ -161,7 +154,7 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(LevelDev<T> L, const T* __res
   const long long p = ((long long)k * L.n + j) * L.n + i;
   const T s = shift[sys];
   // b and x_out, plus x_in unless the guess is zero; faces once per launch
-  count_bytes(ctr, tile_points(L.n) * sizeof(T) * ((ZERO ? 2 : 3) + (VAR && sys == 0 ? DIM : 0)));
+  count_bytes<COUNT_TILE>(ctr, (unsigned long long)L.N * sizeof(T) * ((ZERO ? 2 : 3) + (VAR && sys == 0 ? DIM : 0)));
   double dot = 0.0;
   if (ok) {
     const T bv = b[off + p];
@@ -191,7 +184,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelDev<T> Lf, LevelDev<T>
   const int sys = blockIdx.z;
   if (!active[sys]) return;
   // per coarse point: b and x on its 2^dim fine points, b_c written
-  count_bytes(ctr, tile_points(Lc.n) * sizeof(T) * (2 * (1 << DIM) + 1 + (VAR && sys == 0 ? DIM * (1 << DIM) : 0)));
+  count_bytes<COUNT_TILE>(ctr, (unsigned long long)Lc.N * sizeof(T) * (2 * (1 << DIM) + 1 + (VAR && sys == 0 ? DIM * (1 << DIM) : 0)));
   int I, J, K;
   tile_ijk<DIM>(Lc.n, I, J, K);
   if (I >= Lc.n || J >= Lc.n) return;
@@ -260,7 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong(LevelDev<T> Lc, LevelDev<T> 
   const int sys = blockIdx.z;
   if (!active[sys]) return;
   // x_f read and written; x_c read once (1/2^dim per fine point)
-  count_bytes(ctr, tile_points(Lf.n) * sizeof(T) * 2 + tile_points(Lf.n) * sizeof(T) / (1 << DIM));
+  count_bytes<COUNT_TILE>(ctr, (unsigned long long)Lf.N * sizeof(T) * 2 + (unsigned long long)Lc.N * sizeof(T));
   int i, j, k;
   tile_ijk<DIM>(Lf.n, i, j, k);
   if (i >= Lf.n || j >= Lf.n) return;
@@ -300,7 +293,7 @@ __global__ __launch_bounds__(256) void k_coarse(LdsHierarchy<T> H, const T* __re
   T* sm = reinterpret_cast<T*>(smem_raw);
   const int sys = blockIdx.x;
   if (!active[sys]) return;
-  count_bytes(ctr, 2ULL * H.lev[0].N * sizeof(T));
+  count_bytes<COUNT_ONE>(ctr, 2ULL * H.lev[0].N * sizeof(T));
   const T s = shift[sys];
   const int nthr = blockDim.x;
   const LevelDev<T>& L0 = H.lev[0];
@@ -389,7 +382,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(LevelDev<T> L, const T* __r
                                                      double* __restrict__ partial, unsigned long long* __restrict__ ctr) {
   const int sys = blockIdx.z;
   if (!active[sys]) return;
-  count_bytes(ctr, tile_points(L.n) * sizeof(T) * (2 + (VAR && sys == 0 ? DIM : 0)));
+  count_bytes<COUNT_TILE>(ctr, (unsigned long long)L.N * sizeof(T) * (2 + (VAR && sys == 0 ? DIM : 0)));
   int i, j, k;
   tile_ijk<DIM>(L.n, i, j, k);
   const bool ok = i < L.n && j < L.n;
@@ -413,7 +406,7 @@ __global__ __launch_bounds__(256) void k_update_xr(long long N, T* __restrict__ 
                                                    double* __restrict__ partial, unsigned long long* __restrict__ ctr) {
   const int sys = blockIdx.y;
   if (!active[sys]) return;
-  count_bytes(ctr, flat_points(N, kFlatItems) * sizeof(T) * 6);
+  count_bytes<COUNT_FLAT>(ctr, (unsigned long long)N * sizeof(T) * 6);
   const T a = (T)alpha[sys];
   const long long off = (long long)sys * N;
   const long long base = (long long)blockIdx.x * 256 * kFlatItems + threadIdx.x;
@@ -438,7 +431,7 @@ __global__ __launch_bounds__(256) void k_update_p(long long N, T* __restrict__ p
   const int sys = blockIdx.y;
   if (!active[sys]) return;
   const T bt = (T)beta[sys];
-  count_bytes(ctr, flat_points(N, kFlatItems) * sizeof(T) * (bt == T(0) ? 2 : 3));
+  count_bytes<COUNT_FLAT>(ctr, (unsigned long long)N * sizeof(T) * (bt == T(0) ? 2 : 3));
   const long long off = (long long)sys * N;
   const long long base = (long long)blockIdx.x * 256 * kFlatItems + threadIdx.x;
 #pragma unroll
@@ -484,7 +477,7 @@ __global__ __launch_bounds__(kBlock) void k_residual64(LevelDev<double> L, const
   const int sys = blockIdx.z;
   if (!active64[sys]) return;
   // x64, f read (FP64); r32, e written (FP32)
-  count_bytes(ctr, tile_points(L.n) * (8 + 8 + 4 + 4 + (VAR && sys == 0 ? 8 * DIM : 0)));
+  count_bytes<COUNT_TILE>(ctr, (unsigned long long)L.N * (8 + 8 + 4 + 4 + (VAR && sys == 0 ? 8 * DIM : 0)));
   int i, j, k;
   tile_ijk<DIM>(L.n, i, j, k);
   const bool ok = i < L.n && j < L.n;
@@ -548,10 +541,7 @@ __global__ __launch_bounds__(256) void k_combine(long long N, const double* __re
                                                  double* __restrict__ u, unsigned long long* __restrict__ ctr) {
   const int r = blockIdx.y;
   const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
-  {
-    const long long v = N - (long long)blockIdx.x * 256;
-    count_bytes(ctr, (unsigned long long)(v > 256 ? 256 : v) * 8ULL * (nterms + 1));
-  }
+  count_bytes<COUNT_FLAT>(ctr, (unsigned long long)N * 8ULL * (nterms + 1));
   if (p >= N) return;
   double acc = 0.0;
   for (int j = 0; j < nterms; ++j) acc += w[j] * x[((long long)j * stride + r) * N + p];
