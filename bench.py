@@ -39,6 +39,10 @@ WORKLOADS = {
                                    precision="FP64", schedule="BATCHED", tol=1e-10, var=False),
     "2d1023-k9-mixed-batched": dict(dim=2, n=1023, alphas=(0.25, 0.5, 0.75), k=9, nrhs=1, rhs="normal", tag=2,
                                     precision="MIXED", schedule="BATCHED", tol=1e-10, var=False),
+    "2d1023-k9-fp64-multi": dict(dim=2, n=1023, alphas=(0.25, 0.5, 0.75), k=9, nrhs=1, rhs="normal", tag=2,
+                                 precision="FP64", schedule="BATCHED", tol=1e-10, var=False, multi=True),
+    "2d1023-k9-mixed-multi": dict(dim=2, n=1023, alphas=(0.25, 0.5, 0.75), k=9, nrhs=1, rhs="normal", tag=2,
+                                  precision="MIXED", schedule="BATCHED", tol=1e-10, var=False, multi=True),
     "3d255-k8-mixed-batched": dict(dim=3, n=255, alphas=(0.25,), k=8, nrhs=1, rhs="sines", tag=3,
                                    precision="MIXED", schedule="BATCHED", tol=1e-10, var=False),
     "2d511-var-k7-256rhs-mixed": dict(dim=2, n=511, alphas=(0.6,), k=7, nrhs=256, rhs="normal", tag=4,
@@ -50,8 +54,11 @@ def describe(w):
     d = w["dim"]
     grid = "x".join([str(w["n"])] * d)
     op = ("variable-coefficient a=exp(g) " if w["var"] else "") + ("5-point" if d == 2 else "7-point")
+    sched = w['schedule'].lower().replace('_', '-')
+    if w.get("multi"):
+        sched = "batched over all poles of all alphas"
     return (f"{d}D {grid} {op} operator scaled to (0,1], alpha={list(w['alphas'])}, beta=1, k={w['k']}, "
-            f"{w['nrhs']} rhs ({w['rhs']}), {w['precision']} {w['schedule'].lower().replace('_', '-')} "
+            f"{w['nrhs']} rhs ({w['rhs']}), {w['precision']} {sched} "
             f"GMG V(2,2)-PCG to rel residual {w['tol']:g}")
 
 
@@ -77,20 +84,23 @@ def run_gpu(w, steps, warmup, profile=True):
     coeff = synth.lognormal_coefficient(w["n"], w["dim"], tag=w["tag"]) if w["var"] else None
     plans = []
     t_plan = time.perf_counter()
-    for a in w["alphas"]:
+    groups = [list(w["alphas"])] if w.get("multi") else [a for a in w["alphas"]]
+    for a in groups:
         plans.append(B.Plan(w["dim"], w["n"], a, w["k"], coeff=coeff, nrhs_max=w["nrhs"], tol=w["tol"],
                             precision=getattr(B, "BURA_" + w["precision"]),
                             schedule=getattr(B, "BURA_" + w["schedule"])))
     t_plan = time.perf_counter() - t_plan
-    outs = [torch.empty_like(F) for _ in plans]
+    outs = [torch.empty((p.nout,) + tuple(F.shape), dtype=F.dtype, device=dev) if p.nout > 1 else torch.empty_like(F)
+            for p in plans]
     for _ in range(warmup):
         for p, u in zip(plans, outs):
             p.solve(F, u)
     torch.cuda.synchronize()
     if profile:
-        # events only around the fine-level smoother and the stencil product
-        # (the candidates for the dominant kernel); byte counters for all classes
-        mask = (1 << (1 + 0)) | (1 << (1 + 5))
+        # events only around the fine-level kernels that can dominate (smoother or
+        # fused down/up, stencil product, vector update); byte counters for all classes
+        mask = sum(1 << (1 + B.KERNEL_CLASSES.index(c))
+                   for c in ("smooth_fine", "down_fine", "up_fine", "spmv", "update_xr"))
         for p in plans:
             B.bura_plan_profile(p.handle, mask)
     lat = []
@@ -119,10 +129,16 @@ def run_gpu(w, steps, warmup, profile=True):
             B.bura_plan_profile(p.handle, False)
     info = plans[0].info
     coefs = [p.coeffs for p in plans]
-    U = [u.cpu().numpy() for u in outs]
-    iters = [list(r.iters)[: w["k"] + 1] for r in reports[-len(plans):]]
-    outer = [list(r.outer)[: w["k"] + 1] for r in reports[-len(plans):]]
-    relres = [max(list(r.relres)[: w["k"] + 1]) for r in reports[-len(plans):]]
+    U = []
+    for p, u in zip(plans, outs):
+        if p.nout > 1:
+            U += [u[i].cpu().numpy() for i in range(p.nout)]
+        else:
+            U.append(u.cpu().numpy())
+    nt = (w["k"] + 1) * (len(w["alphas"]) if w.get("multi") else 1)
+    iters = [list(r.iters)[:nt] for r in reports[-len(plans):]]
+    outer = [list(r.outer)[:nt] for r in reports[-len(plans):]]
+    relres = [max(list(r.relres)[:nt]) for r in reports[-len(plans):]]
     for p in plans:
         p.close()
     N = w["n"] ** w["dim"]
@@ -145,6 +161,8 @@ def roofline(kstats):
                            gbs=(s["bytes"] / 1e9) / (s["ms"] / 1e3) if s["bytes"] > 0 else None,
                            total_ms=s["ms"])
     cand = {k: v for k, v in table.items() if v["gbs"] is not None}
+    if not cand:
+        return None, table
     dom = max(cand, key=lambda k: cand[k]["total_ms"])
     d = cand[dom]
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(d["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -227,12 +245,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="2d1023-k9-fp64-batched", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="2d1023-k9-fp64-multi", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of this many GiB (counter calibration)")
-    ap.add_argument("--also", default="2d1023-k9-fp64-per-pole,2d1023-k9-mixed-batched",
+    ap.add_argument("--also", default="2d1023-k9-fp64-per-pole,2d1023-k9-fp64-batched,2d1023-k9-mixed-multi",
                     help="comma-separated extra workloads reported under 'paths' (empty: none)")
     args = ap.parse_args()
     if args.copy_probe > 0:
@@ -275,7 +293,8 @@ def main():
                    "alphas": list(w["alphas"]), "k": w["k"], "nrhs": w["nrhs"], "precision": w["precision"],
                    "schedule": w["schedule"], "tol": w["tol"]},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
-                       "per": "one fractional solve (k+1 poles + combine)"},
+                       "per": ("one solve of all alphas together" if w.get("multi") else
+                               "one fractional solve (k+1 poles + combine)")},
         "iters_per_pole_last": res["iters"],
         "max_relres": max(res["relres"]),
         "lambda": res["lam"], "mg_levels": res["nlev"], "plan_seconds": round(res["t_plan"], 3),

@@ -140,6 +140,19 @@ int bura_plan_create(const bura_grid_t* grid, double alpha, int beta, int k,
 int bura_plan_create_rational(const bura_grid_t* grid, int nterms, const double* weights,
                               const double* shifts, const bura_opts_t* opts, bura_plan_t* out);
 
+/* Several fractional powers of the same operator in one plan: alpha[a] with
+ * ks[a] poles each (a < nalpha, sum_a (ks[a]+1) <= BURA_MAX_TERMS).  All
+ * shifted systems of all outputs advance together; bura_solve then writes
+ * nalpha * nrhs vectors, output a of right-hand side r at u_dev[a * nrhs + r].
+ * bura_plan_coeffs returns the terms of all outputs back to back and the
+ * largest E. */
+int bura_plan_create_multi(const bura_grid_t* grid, int nalpha, const double* alphas, int beta, const int* ks,
+                           const bura_opts_t* opts, bura_plan_t* out);
+
+/* Number of outputs and their term ranges: output i uses terms
+ * [term_begin[i], term_begin[i+1]); term_begin has nout + 1 entries. */
+int bura_plan_outputs(bura_plan_t plan, int* nout, int* term_begin);
+
 /* u_dev[r] = sum_j c_j (A - d_j I)^{-1} f_dev[r], r < nrhs <= nrhs_max.
  * Synchronous: returns after the result is in u_dev.  rep may be NULL.
  * BURA_ENOCONV leaves the last iterate combined in u_dev. */
@@ -166,7 +179,7 @@ int bura_plan_apply(bura_plan_t plan, double shift, const double* x_dev, double*
 /* Kernel classes for profiling. */
 enum bura_kernel_class {
   BURA_K_SMOOTH_FINE = 0,    /* Jacobi sweeps on the finest level (or the Jacobi preconditioner) */
-  BURA_K_SMOOTH_COARSE = 1,  /* Jacobi sweeps on coarser levels solved by global kernels          */
+  BURA_K_SMOOTH_COARSE = 1,  /* Jacobi sweeps (or fused level kernels) on coarser global levels   */
   BURA_K_RESTRICT = 2,       /* residual + full-weighting restriction                             */
   BURA_K_PROLONG = 3,        /* interpolation + correction                                        */
   BURA_K_COARSE_LDS = 4,     /* coarse levels solved inside one workgroup per system              */
@@ -176,7 +189,9 @@ enum bura_kernel_class {
   BURA_K_RESIDUAL64 = 8,     /* FP64 refinement residual                                           */
   BURA_K_COMBINE = 9,        /* u = sum_j c_j x_j                                                  */
   BURA_K_OTHER = 10,         /* per-system scalar updates, copies                                  */
-  BURA_K_COUNT = 11
+  BURA_K_DOWN_FINE = 11,     /* finest level, fused: sweeps from zero + residual + restriction    */
+  BURA_K_UP_FINE = 12,       /* finest level, fused: prolongation + sweeps + r.z                  */
+  BURA_K_COUNT = 13
 };
 
 /* Profiling of the plan's launches (for measurement, not for production use).

@@ -95,6 +95,9 @@ _SIGS = {
     "bura_plan_create": (_I, [ctypes.POINTER(bura_grid_t), _D, _I, _I, ctypes.POINTER(bura_opts_t), ctypes.POINTER(_P)]),
     "bura_plan_create_rational": (_I, [ctypes.POINTER(bura_grid_t), _I, _DP, _DP, ctypes.POINTER(bura_opts_t),
                                        ctypes.POINTER(_P)]),
+    "bura_plan_create_multi": (_I, [ctypes.POINTER(bura_grid_t), _I, _DP, _I, ctypes.POINTER(_I),
+                                    ctypes.POINTER(bura_opts_t), ctypes.POINTER(_P)]),
+    "bura_plan_outputs": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "bura_solve": (_I, [_P, _P, _P, _I, ctypes.POINTER(bura_report_t)]),
     "bura_submit": (_I, [_P, _P, _P, _I]),
     "bura_poll": (_I, [_P, ctypes.POINTER(bura_report_t)]),
@@ -189,6 +192,26 @@ def bura_plan_create(dim: int, n: int, alpha: float, k: int, opts: Optional[bura
     return h
 
 
+def bura_plan_create_multi(dim: int, n: int, alphas: Sequence[float], ks: Sequence[int],
+                           opts: Optional[bura_opts_t] = None, coeff=None, lambda_upper: float = 0.0, beta: int = 1):
+    g, _keep = _grid(dim, n, coeff, lambda_upper)
+    o = opts if opts is not None else bura_opts_default()
+    m = len(alphas)
+    a = (ctypes.c_double * m)(*alphas)
+    k = (ctypes.c_int * m)(*ks)
+    h = _P()
+    _check(_lib.bura_plan_create_multi(ctypes.byref(g), m, a, beta, k, ctypes.byref(o), ctypes.byref(h)),
+           "bura_plan_create_multi")
+    return h
+
+
+def bura_plan_outputs(plan):
+    n = ctypes.c_int()
+    tb = (ctypes.c_int * (BURA_MAX_TERMS + 1))()
+    _check(_lib.bura_plan_outputs(plan, ctypes.byref(n), tb), "bura_plan_outputs")
+    return n.value, list(tb)[: n.value + 1]
+
+
 def bura_plan_create_rational(dim: int, n: int, weights: Sequence[float], shifts: Sequence[float],
                               opts: Optional[bura_opts_t] = None, coeff=None, lambda_upper: float = 0.0):
     g, _keep = _grid(dim, n, coeff, lambda_upper)
@@ -248,7 +271,7 @@ def bura_plan_apply(plan, shift: float, x: torch.Tensor, y: torch.Tensor, nvec: 
 
 
 KERNEL_CLASSES = ["smooth_fine", "smooth_coarse", "restrict", "prolong", "coarse_lds", "spmv", "update_xr",
-                  "update_p", "residual64", "combine", "other"]
+                  "update_p", "residual64", "combine", "other", "down_fine", "up_fine"]
 
 
 def bura_plan_profile(plan, enable):
@@ -291,8 +314,13 @@ class Plan:
         o.stream = _stream_ptr(stream).value if torch.cuda.is_available() else None
         self.opts = o
         self.handle = None
+        self.nout = 1
         if weights is not None:
             self.handle = bura_plan_create_rational(dim, n, weights, shifts, o, coeff=coeff)
+        elif isinstance(alpha, (list, tuple)):
+            ks = list(k) if isinstance(k, (list, tuple)) else [k] * len(alpha)
+            self.handle = bura_plan_create_multi(dim, n, list(alpha), ks, o, coeff=coeff)
+            self.nout = len(alpha)
         else:
             self.handle = bura_plan_create(dim, n, alpha, k, o, coeff=coeff)
 
@@ -308,7 +336,8 @@ class Plan:
         f = f.contiguous()
         nrhs = f.shape[0] if f.dim() == self.dim + 1 else 1
         if u is None:
-            u = torch.empty_like(f)
+            u = torch.empty_like(f) if self.nout == 1 else torch.empty((self.nout,) + tuple(f.shape),
+                                                                         dtype=f.dtype, device=f.device)
         rep = bura_solve(self.handle, f, u, nrhs, ok)
         return SolveResult(u, rep)
 

@@ -10,7 +10,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <string>
+#include <tuple>
 #include <thread>
 #include <vector>
 
@@ -49,6 +52,7 @@ struct Work {
   T* z = nullptr;
   T* zt = nullptr;
   T* p = nullptr;
+  T* p2 = nullptr;  // p ping-pong partner (p_new = z + beta p_old is written to the other buffer)
   T* q = nullptr;
   std::vector<T*> xl, tl, bl;   // levels 1..lc (index by level)
   T* shift = nullptr;
@@ -73,6 +77,10 @@ struct bura_plan_s {
   // rational form u = sum_j w_j (A + s_j)^-1 f
   int nterms = 0;
   std::vector<double> w, s;   // weights c_j and shifts s_j = -d_j
+  // outputs: output i combines the terms [out_begin[i], out_end[i]) (several
+  // fractional powers of the same operator solved in one batch)
+  int nout = 1;
+  std::vector<int> out_begin, out_end;
   double E = 0.0;
   bura_opts_t opts{};
   hipStream_t stream = nullptr;
@@ -80,6 +88,7 @@ struct bura_plan_s {
   // hierarchy
   std::vector<HostLevel> lev;
   int lc = -1;                 // first level solved in LDS; -1: no multigrid (Jacobi PCG)
+  bool unfused = false;        // force the one-kernel-per-step V-cycle (BURA_UNFUSED=1)
   size_t lds_bytes = 0;
   int S = 0;                   // systems = nterms * nrhs_max
   // device buffers
@@ -101,10 +110,27 @@ struct bura_plan_s {
     bool on = false;
     unsigned mask = 0;                        // kernel classes timed with events
     unsigned long long* d_ctr = nullptr;
-    std::vector<hipEvent_t> pool;
+    std::vector<hipEvent_t> pool;             // eager-mode events, reused after each flush
     size_t used = 0;
-    std::vector<std::pair<int, size_t>> rec;   // (class, index of the start event; stop = +1)
+    std::vector<std::pair<int, size_t>> rec;   // pending (class, index of the start event; stop = +1)
+    double ms[BURA_K_COUNT] = {};
+    long long launches[BURA_K_COUNT] = {};
   } prof;
+  // graphs: one captured chunk of PCG iterations per (precision, batch, tolerance)
+  struct Graph {
+    hipGraphExec_t exec = nullptr;
+    std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> ev;   // events recorded inside the graph
+  };
+  std::map<std::string, Graph> graphs;
+  bool capturing = false;
+  bool capture_failed = false;
+  std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> cap_ev;
+  bool use_graphs = true;
+  bool fold = false;                   // scalar updates folded into the producing kernels
+  unsigned int* d_cnt = nullptr;       // per-system block counters for the folded updates
+  hipStream_t user_stream = nullptr;   // caller's stream (opts.stream)
+  hipEvent_t join_ev = nullptr;
+  void* h_state = nullptr;             // pinned mirror of the scalar state for reports
   // async
   std::thread worker;
   std::atomic<int> busy{0};
@@ -132,12 +158,24 @@ int dev_alloc(bura_plan_t P, void** ptr, size_t bytes) {
 struct ProfScope {
   bura_plan_t P;
   long idx = -1;
+  hipEvent_t e1 = nullptr;
   unsigned long long* ctr = nullptr;
   ProfScope(bura_plan_t P_, int cls) : P(P_) {
     auto& pr = P->prof;
     if (!pr.on) return;
     ctr = pr.d_ctr + cls;
     if (!(pr.mask & (1u << cls))) return;
+    if (P->capturing) {
+      // events recorded inside the graph being captured (owned by that graph)
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess) { P->capture_failed = true; return; }
+      if (hipEventCreate(&b) != hipSuccess) { hipEventDestroy(a); P->capture_failed = true; return; }
+      // external record nodes: the replayed graph writes real timestamps
+      if (hipEventRecordWithFlags(a, P->stream, hipEventRecordExternal) != hipSuccess) P->capture_failed = true;
+      P->cap_ev.emplace_back(cls, a, b);
+      e1 = b;
+      return;
+    }
     while (pr.pool.size() < pr.used + 2) {
       hipEvent_t e;
       if (hipEventCreate(&e) != hipSuccess) return;
@@ -149,9 +187,51 @@ struct ProfScope {
     hipEventRecord(pr.pool[idx], P->stream);
   }
   ~ProfScope() {
-    if (idx >= 0) hipEventRecord(P->prof.pool[idx + 1], P->stream);
+    if (e1) {
+      if (hipEventRecordWithFlags(e1, P->stream, hipEventRecordExternal) != hipSuccess) P->capture_failed = true;
+    } else if (idx >= 0) {
+      hipEventRecord(P->prof.pool[idx + 1], P->stream);
+    }
   }
 };
+
+// after a stream synchronisation: fold the pending eager events into the totals
+void prof_flush(bura_plan_t P) {
+  auto& pr = P->prof;
+  for (const auto& r : pr.rec) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, pr.pool[r.second], pr.pool[r.second + 1]) == hipSuccess) {
+      pr.ms[r.first] += t;
+      pr.launches[r.first] += 1;
+    }
+  }
+  pr.rec.clear();
+  pr.used = 0;
+  (void)hipGetLastError();   // an unreadable event must not surface as a later launch error
+}
+
+void prof_graph(bura_plan_t P, const bura_plan_s::Graph& g) {
+  if (!P->prof.on) return;
+  for (const auto& e : g.ev) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, std::get<1>(e), std::get<2>(e)) == hipSuccess) {
+      P->prof.ms[std::get<0>(e)] += t;
+      P->prof.launches[std::get<0>(e)] += 1;
+    }
+  }
+  (void)hipGetLastError();
+}
+
+void destroy_graphs(bura_plan_t P) {
+  for (auto& kv : P->graphs) {
+    if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+    for (auto& e : kv.second.ev) {
+      hipEventDestroy(std::get<1>(e));
+      hipEventDestroy(std::get<2>(e));
+    }
+  }
+  P->graphs.clear();
+}
 
 template <typename T>
 LevelDev<T> level_view(const bura_plan_t P, int l) {
@@ -368,6 +448,7 @@ int alloc_work(bura_plan_t P, Work<T>& W) {
   if ((rc = dev_alloc(P, (void**)&W.z, vb))) return rc;
   if ((rc = dev_alloc(P, (void**)&W.zt, vb))) return rc;
   if ((rc = dev_alloc(P, (void**)&W.p, vb))) return rc;
+  if ((rc = dev_alloc(P, (void**)&W.p2, vb))) return rc;
   if ((rc = dev_alloc(P, (void**)&W.q, vb))) return rc;
   const int L = (int)P->lev.size();
   W.xl.assign(L, nullptr);
@@ -386,14 +467,14 @@ int alloc_work(bura_plan_t P, Work<T>& W) {
   const int R = P->opts.nrhs_max;
   for (size_t i = 0; i < S; ++i) sh[i] = (T)P->s[i / R];
   HIPCHK(hipMemcpy(W.shift, sh.data(), S * sizeof(T), hipMemcpyHostToDevice));
-  for (void* ptr : {(void*)W.x, (void*)W.r, (void*)W.z, (void*)W.zt, (void*)W.p, (void*)W.q})
+  for (void* ptr : {(void*)W.x, (void*)W.r, (void*)W.z, (void*)W.zt, (void*)W.p, (void*)W.p2, (void*)W.q})
     HIPCHK(hipMemset(ptr, 0, vb));
   return BURA_OK;
 }
 
 size_t footprint(const bura_plan_t P, size_t elem, bool mixed) {
   const size_t S = (size_t)P->S;
-  size_t t = 6 * S * (size_t)P->N * elem;
+  size_t t = 7 * S * (size_t)P->N * elem;
   if (P->lc > 0)
     for (int l = 1; l <= P->lc; ++l) t += 3 * S * (size_t)P->lev[l].N * elem;
   if (mixed) t += S * (size_t)P->N * 8;
@@ -424,8 +505,15 @@ int upload_faces(bura_plan_t P) {
 // preconditioner z = M r on a batch (V-cycle, or Jacobi without a hierarchy);
 // the last sweep writes the per-block partials of r.z into `partial`.
 // ---------------------------------------------------------------------------
+// the fused level kernels exist for 2D hierarchies with 1..3 sweeps
+bool fused_ok(const bura_plan_t P) {
+  return P->dim == 2 && P->lc > 0 && P->opts.nu_pre >= 1 && P->opts.nu_pre <= 3 && P->opts.nu_post >= 1 &&
+         P->opts.nu_post <= 3 && !P->unfused;
+}
+
 template <typename T>
-void precondition(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, const int* active, double* partial) {
+void precondition(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, const int* active, double* partial,
+                  Fin fin = Fin()) {
   hipStream_t st = P->stream;
   const int dim = P->dim;
   const bool var = P->var;
@@ -436,11 +524,37 @@ void precondition(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, const int* a
     // Jacobi preconditioner: z = D^-1 r
     ProfScope ps(P, BURA_K_SMOOTH_FINE);
     Launch<T>::jacobi(dim, var, level_view<T>(P, 0), off(W.r, 0), nullptr, off(W.z, 0), shift, active, T(1), true,
-                      partial, nsys, st, ps.ctr);
+                      partial, nsys, st, ps.ctr, fin);
     return;
   }
   const int lc = P->lc;
   const int nu1 = std::max(1, P->opts.nu_pre), nu2 = std::max(1, P->opts.nu_post);
+  if (fused_ok(P)) {
+    // two LDS-tiled kernels per level: down (nu1 sweeps + residual + restriction)
+    // writes the pre-smoothed iterate into A_l; up (prolongation + nu2 sweeps)
+    // writes the final iterate into B_l (B_0 = z).
+    auto A = [&](int l) { return l == 0 ? off(W.zt, 0) : off(W.tl[l], l); };
+    auto Bv = [&](int l) { return l == 0 ? off(W.z, 0) : off(W.xl[l], l); };
+    auto bl = [&](int l) { return l == 0 ? off(W.r, 0) : off(W.bl[l], l); };
+    for (int l = 0; l < lc; ++l) {
+      ProfScope ps(P, l == 0 ? BURA_K_DOWN_FINE : BURA_K_SMOOTH_COARSE);
+      Launch<T>::fused_down(dim, var, nu1, level_view<T>(P, l), level_view<T>(P, l + 1), bl(l), A(l), bl(l + 1),
+                            shift, active, omega, nsys, st, ps.ctr);
+    }
+    {
+      ProfScope ps(P, BURA_K_COARSE_LDS);
+      Launch<T>::coarse_solve(dim, var, lds_view<T>(P), bl(lc), off(W.xl[lc], lc), shift, active, nsys,
+                              P->lds_bytes, st, ps.ctr);
+    }
+    for (int l = lc - 1; l >= 0; --l) {
+      ProfScope ps(P, l == 0 ? BURA_K_UP_FINE : BURA_K_SMOOTH_COARSE);
+      const T* xc = l + 1 == lc ? off(W.xl[lc], lc) : Bv(l + 1);
+      Launch<T>::fused_up(dim, var, nu2, level_view<T>(P, l + 1), level_view<T>(P, l), xc, A(l), bl(l), Bv(l),
+                          shift, active, omega, l == 0 ? partial : nullptr, nsys, st, ps.ctr,
+                          l == 0 ? fin : Fin());
+    }
+    return;
+  }
   // per level: right-hand side, the buffer holding the iterate, the spare buffer.
   // nu1 + nu2 sweeps alternate between two buffers; the first sweep writes the
   // buffer that makes the last one land in xa (xa = z on the fine level).
@@ -487,14 +601,14 @@ void precondition(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, const int* a
       const bool last = (l == 0 && s == nu2 - 1);
       ProfScope ps(P, scls);
       Launch<T>::jacobi(dim, var, L, bcur[l], cur[l], spare[l], shift, active, omega, false,
-                        last ? partial : nullptr, nsys, st, ps.ctr);
+                        last ? partial : nullptr, nsys, st, ps.ctr, last ? fin : Fin());
       std::swap(cur[l], spare[l]);
     }
   }
 }
 
 // which kernel wrote the r.z partials (for the reduction's block count)
-int rz_blocks(const bura_plan_t P) { return stencil_blocks(P->dim, P->n); }
+int rz_blocks(const bura_plan_t P) { return fused_ok(P) ? up_blocks(P->dim, P->n) : stencil_blocks(P->dim, P->n); }
 
 SysState state_at(const bura_plan_t P, size_t sys0) {
   SysState s = P->st;
@@ -509,6 +623,7 @@ int count_active(bura_plan_t P, const int* dev_flags, size_t sys0, int nsys) {
       hipSuccess)
     return -1;
   if (hipStreamSynchronize(P->stream) != hipSuccess) return -1;
+  prof_flush(P);
   int c = 0;
   for (int i = 0; i < nsys; ++i) c += P->h_flags[i] != 0;
   return c;
@@ -529,44 +644,107 @@ int run_pcg(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, double tol, int ma
     ProfScope ps(P, BURA_K_OTHER);
     launch_scalars(op, part, nblk, nsys, S, tol, max_iter, st);
   };
-  auto upd_p = [&]() {
-    ProfScope ps(P, BURA_K_UPDATE_P);
-    Launch<T>::update_p(L0, dim, W.p + o, W.z + o, S.beta, S.active, nsys, st, ps.ctr);
+  T* pold = W.p + o;
+  T* pnew = W.p2 + o;
+  // one PCG iteration for the systems of this batch (converged systems are
+  // skipped by their blocks); p_new = z + beta p_old goes to the other buffer
+  auto fin = [&](int op) {
+    Fin f;
+    if (!P->fold) return f;
+    f.op = op;
+    f.cnt = P->d_cnt + sys0;
+    f.st = S;
+    f.tol = tol;
+    f.max_iter = max_iter;
+    return f;
   };
-  precondition<T>(P, W, sys0, nsys, S.active, part);
-  scal(OP_BETA, rz_blocks(P));
-  upd_p();
-  for (int it = 0; it <= max_iter; ++it) {
+  auto body = [&](T* po, T* pn) {
     {
       ProfScope ps(P, BURA_K_SPMV);
-      Launch<T>::spmv_dot(dim, P->var, L0, W.p + o, W.q + o, W.shift + sys0, S.active, part, nsys, st, ps.ctr);
+      Launch<T>::spmv_p(dim, P->var, L0, W.z + o, po, pn, W.q + o, S.beta, W.shift + sys0, S.active, part, nsys, st,
+                        ps.ctr, fin(OP_ALPHA));
     }
-    scal(OP_ALPHA, nb_tile);
+    if (!P->fold) scal(OP_ALPHA, nb_tile);
     {
       ProfScope ps(P, BURA_K_UPDATE_XR);
-      Launch<T>::update_xr(L0, dim, W.x + o, W.r + o, W.p + o, W.q + o, S.alpha, S.active, part, nsys, st, ps.ctr);
+      Launch<T>::update_xr(L0, dim, W.x + o, W.r + o, pn, W.q + o, S.alpha, S.active, part, nsys, st, ps.ctr,
+                           fin(OP_RESID));
     }
-    scal(OP_RESID, nb_flat);
-    if ((it + 1) % check == 0 || it == max_iter) {
-      const int a = count_active(P, P->st.active, sys0, nsys);
-      if (a < 0) {
-        g_last_error = hipGetErrorString(hipGetLastError());
-        return BURA_EDEVICE;
+    if (!P->fold) scal(OP_RESID, nb_flat);
+    precondition<T>(P, W, sys0, nsys, S.active, part, fin(OP_BETA));
+    if (!P->fold) scal(OP_BETA, rz_blocks(P));
+  };
+  precondition<T>(P, W, sys0, nsys, S.active, part, fin(OP_BETA));
+  if (!P->fold) scal(OP_BETA, rz_blocks(P));
+  // chunks of an even number of iterations, so p_old is W.p at every chunk start
+  const int chunk = std::max(2, check + (check & 1));
+  const int nchunks = max_iter / chunk + 1;
+  bura_plan_s::Graph* g = nullptr;
+  if (P->use_graphs) {
+    char key[160];
+    std::snprintf(key, sizeof(key), "%zu/%zu/%d/%.17g/%d/%d", sizeof(T), sys0, nsys, tol, max_iter, chunk);
+    auto it = P->graphs.find(key);
+    if (it != P->graphs.end()) {
+      g = &it->second;
+    } else {
+      // capture the chunk once; replays cost one launch
+      HIPCHK(hipStreamSynchronize(st));
+      prof_flush(P);
+      P->capturing = true;
+      P->capture_failed = false;
+      P->cap_ev.clear();
+      hipGraph_t graph = nullptr;
+      bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        T* a = pold;
+        T* b = pnew;
+        for (int c = 0; c < chunk; ++c) {
+          body(a, b);
+          std::swap(a, b);
+        }
+        ok = hipStreamEndCapture(st, &graph) == hipSuccess && graph != nullptr && !P->capture_failed;
       }
-      if (a == 0) break;
+      P->capturing = false;
+      bura_plan_s::Graph G;
+      G.ev = P->cap_ev;
+      P->cap_ev.clear();
+      if (ok && hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0) != hipSuccess) ok = false;
+      if (graph) hipGraphDestroy(graph);
+      (void)hipGetLastError();
+      if (!ok) {
+        for (auto& e : G.ev) { hipEventDestroy(std::get<1>(e)); hipEventDestroy(std::get<2>(e)); }
+        if (G.exec) hipGraphExecDestroy(G.exec);
+        P->use_graphs = false;   // fall back to direct launches for this plan
+      } else {
+        g = &(P->graphs[key] = std::move(G));
+      }
     }
-    precondition<T>(P, W, sys0, nsys, S.active, part);
-    scal(OP_BETA, rz_blocks(P));
-    upd_p();
+  }
+  for (int ch = 0; ch < nchunks; ++ch) {
+    if (g) {
+      HIPCHK(hipGraphLaunch(g->exec, st));
+    } else {
+      T* a = pold;
+      T* b = pnew;
+      for (int c = 0; c < chunk; ++c) {
+        body(a, b);
+        std::swap(a, b);
+      }
+    }
+    const int a = count_active(P, P->st.active, sys0, nsys);
+    if (a < 0) {
+      g_last_error = hipGetErrorString(hipGetLastError());
+      return BURA_EDEVICE;
+    }
+    if (g) prof_graph(P, *g);
+    if (a == 0) break;
   }
   HIPCHK(hipGetLastError());
   return BURA_OK;
 }
 
 int set_flags(bura_plan_t P, int* dev, size_t sys0, int nsys, int value) {
-  std::vector<int> h(nsys, value);
-  HIPCHK(hipMemcpyAsync(dev + sys0, h.data(), nsys * sizeof(int), hipMemcpyHostToDevice, P->stream));
-  HIPCHK(hipStreamSynchronize(P->stream));
+  launch_fill_int(dev + sys0, nsys, value, P->stream);
   return BURA_OK;
 }
 
@@ -643,6 +821,9 @@ int do_solve(bura_plan_t P, const double* f, double* u, int nrhs, bura_report_t*
   // systems are laid out sys = j * R + r; only r < nrhs are used
   const size_t S_used = (size_t)P->nterms * R;
   int rc;
+  // the plan works on its own stream, ordered after the caller's pending work
+  HIPCHK(hipEventRecord(P->join_ev, P->user_stream));
+  HIPCHK(hipStreamWaitEvent(P->stream, P->join_ev, 0));
   if ((rc = set_flags(P, P->st.flags, 0, (int)S_used, 0))) return rc;
   if ((rc = set_flags(P, P->st.total_iters, 0, (int)S_used, 0))) return rc;
   if ((rc = set_flags(P, P->st.outer, 0, (int)S_used, 0))) return rc;
@@ -666,21 +847,28 @@ int do_solve(bura_plan_t P, const double* f, double* u, int nrhs, bura_report_t*
     for (int j = 0; j < P->nterms && rc == BURA_OK; ++j) rc = batch((size_t)j * R, nrhs);
   }
   if (rc) return rc;
-  // combine u = sum_j w_j x_j (fixed order j = 0..k, FP64)
+  // combine u_i = sum_{j in output i} w_j x_j (fixed order, FP64)
   const double* xsol = mixed ? P->x64 : P->w64.x;
-  {
+  for (int i = 0; i < P->nout; ++i) {
     ProfScope ps(P, BURA_K_COMBINE);
-    launch_combine(P->N, xsol, P->d_w, P->nterms, nrhs, R, u, P->stream, ps.ctr);
+    const int b = P->out_begin[i], e = P->out_end[i];
+    launch_combine(P->N, xsol + (size_t)b * R * P->N, P->d_w + b, e - b, nrhs, R, u + (size_t)i * nrhs * P->N,
+                   P->stream, ps.ctr);
   }
   HIPCHK(hipGetLastError());
+  // report: one copy of the per-system scalar state into pinned memory
+  const size_t S = (size_t)P->S;
+  const size_t sb = S * (6 * 8 + 8 * 4);
+  HIPCHK(hipMemcpyAsync(P->h_state, P->state_block, sb, hipMemcpyDeviceToHost, P->stream));
+  HIPCHK(hipMemcpyAsync((char*)P->h_state + sb, P->st.relres64, S * 8, hipMemcpyDeviceToHost, P->stream));
   HIPCHK(hipStreamSynchronize(P->stream));
-  // report
-  std::vector<int> it(S_used), outer(S_used), flags(S_used), act(S_used);
-  std::vector<double> rr(S_used);
-  HIPCHK(hipMemcpy(it.data(), P->st.total_iters, S_used * 4, hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(outer.data(), P->st.outer, S_used * 4, hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(flags.data(), P->st.flags, S_used * 4, hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(rr.data(), mixed ? P->st.relres64 : P->st.relres, S_used * 8, hipMemcpyDeviceToHost));
+  prof_flush(P);
+  const double* hd = (const double*)P->h_state;
+  const int* hi = (const int*)(hd + 6 * S);
+  const int* it = hi + 2 * S;
+  const int* flags = hi + 3 * S;
+  const int* outer = hi + 5 * S;
+  const double* rr = mixed ? (const double*)((const char*)P->h_state + sb) : hd + 4 * S;
   int status = BURA_OK;
   bura_report_t R_{};
   R_.nterms = P->nterms;
@@ -711,7 +899,7 @@ int validate_opts(const bura_opts_t* o) {
 }
 
 int create(const bura_grid_t* g, int nterms, const double* w, const double* s, double E,
-           const bura_opts_t* opts_in, bura_plan_t* out) {
+           const bura_opts_t* opts_in, bura_plan_t* out, int nout = 1, const int* out_begin = nullptr) {
   if (out) *out = nullptr;
   if (!g || !out || !w || !s || nterms < 1 || nterms > BURA_MAX_TERMS) return BURA_EINVAL;
   if (g->dim != 2 && g->dim != 3) return BURA_EINVAL;
@@ -739,10 +927,28 @@ int create(const bura_grid_t* g, int nterms, const double* w, const double* s, d
   P->nterms = nterms;
   P->w.assign(w, w + nterms);
   P->s.assign(s, s + nterms);
+  P->nout = nout;
+  for (int i = 0; i < nout; ++i) {
+    P->out_begin.push_back(out_begin ? out_begin[i] : 0);
+    P->out_end.push_back(out_begin && i + 1 < nout ? out_begin[i + 1] : nterms);
+  }
   P->E = E;
   P->opts = o;
-  P->stream = (hipStream_t)o.stream;
+  P->user_stream = (hipStream_t)o.stream;
+  {
+    const char* ev = std::getenv("BURA_NO_GRAPH");
+    P->use_graphs = !(ev && ev[0] == '1');
+    // folding the scalar updates into the producing kernels needs a
+    // device-scope fence per block, which on a multi-XCD part writes back L2;
+    // it is slower than a separate launch, so it is opt-in (BURA_FOLD=1)
+    const char* ef = std::getenv("BURA_FOLD");
+    P->fold = ef && ef[0] == '1';
+  }
   P->S = nterms * o.nrhs_max;
+  {
+    const char* ev = std::getenv("BURA_UNFUSED");
+    P->unfused = ev && ev[0] == '1';
+  }
   int rc = build_levels(P, g);
   if (rc) { delete P; return rc; }
   const bool mixed = o.precision == BURA_MIXED;
@@ -758,6 +964,8 @@ int create(const bura_grid_t* g, int nterms, const double* w, const double* s, d
   }
   if (hipGetDevice(&P->device) != hipSuccess) { delete P; return BURA_EDEVICE; }
   auto fail = [&](int code) { bura_plan_destroy(P); return code; };
+  if (hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking) != hipSuccess) return fail(BURA_EDEVICE);
+  if (hipEventCreateWithFlags(&P->join_ev, hipEventDisableTiming) != hipSuccess) return fail(BURA_EDEVICE);
   if ((rc = upload_faces(P))) return fail(rc);
   if (mixed) {
     if ((rc = alloc_work<float>(P, P->w32))) return fail(rc);
@@ -773,7 +981,7 @@ int create(const bura_grid_t* g, int nterms, const double* w, const double* s, d
     for (int i = 0; i < P->S; ++i) sh[i] = P->s[i / o.nrhs_max];
     if (hipMemcpy(P->d_shift64, sh.data(), sh.size() * 8, hipMemcpyHostToDevice) != hipSuccess) return fail(BURA_EDEVICE);
   }
-  const size_t maxblk = (size_t)std::max(stencil_blocks(P->dim, P->n), flat_blocks(P->N));
+  const size_t maxblk = (size_t)std::max({stencil_blocks(P->dim, P->n), flat_blocks(P->N), up_blocks(P->dim, P->n)});
   P->partial_len = (size_t)P->S * maxblk;
   if ((rc = dev_alloc(P, (void**)&P->partial, P->partial_len * 8))) return fail(rc);
   if ((rc = dev_alloc(P, (void**)&P->d_w, nterms * 8))) return fail(rc);
@@ -793,9 +1001,13 @@ int create(const bura_grid_t* g, int nterms, const double* w, const double* s, d
   // relres64 needs doubles: carve from a separate allocation
   if ((rc = dev_alloc(P, (void**)&P->st.relres64, S * 8))) return fail(rc);
   hipMemset(P->st.relres64, 0, S * 8);
+  if ((rc = dev_alloc(P, (void**)&P->d_cnt, S * sizeof(unsigned int)))) return fail(rc);
+  hipMemset(P->d_cnt, 0, S * sizeof(unsigned int));
   if ((rc = dev_alloc(P, (void**)&P->prof.d_ctr, BURA_K_COUNT * sizeof(unsigned long long)))) return fail(rc);
   hipMemset(P->prof.d_ctr, 0, BURA_K_COUNT * sizeof(unsigned long long));
   if (hipHostMalloc((void**)&P->h_flags, S * sizeof(int), hipHostMallocDefault) != hipSuccess)
+    return fail(BURA_ENOMEM);
+  if (hipHostMalloc(&P->h_state, S * (6 * 8 + 8 * 4) + S * 8, hipHostMallocDefault) != hipSuccess)
     return fail(BURA_ENOMEM);
   if (hipDeviceSynchronize() != hipSuccess) return fail(BURA_EDEVICE);
   *out = P;
@@ -831,6 +1043,32 @@ int bura_opts_default(bura_opts_t* o) {
 int bura_plan_create_rational(const bura_grid_t* grid, int nterms, const double* weights, const double* shifts,
                               const bura_opts_t* opts, bura_plan_t* out) {
   return create(grid, nterms, weights, shifts, 0.0, opts, out);
+}
+
+int bura_plan_create_multi(const bura_grid_t* grid, int nalpha, const double* alphas, int beta, const int* ks,
+                           const bura_opts_t* opts, bura_plan_t* out) {
+  if (out) *out = nullptr;
+  if (!alphas || !ks || nalpha < 1) return BURA_EINVAL;
+  if (beta != 1) return BURA_EUNSUPPORTED;
+  std::vector<double> c, s;
+  std::vector<int> begin;
+  double E = 0.0;
+  for (int a = 0; a < nalpha; ++a) {
+    const int k = ks[a];
+    if (!(alphas[a] > 0.0 && alphas[a] < 1.0) || k < 1 || k > 16) return BURA_EINVAL;
+    std::vector<double> cc(k + 1), dd(k + 1);
+    double Ea = 0.0;
+    const int rc = bura_coefficients(alphas[a], beta, k, cc.data(), dd.data(), &Ea);
+    if (rc) return rc;
+    begin.push_back((int)c.size());
+    for (int j = 0; j <= k; ++j) {
+      c.push_back(cc[j]);
+      s.push_back(-dd[j]);
+    }
+    E = std::max(E, Ea);
+  }
+  if ((int)c.size() > BURA_MAX_TERMS) return BURA_EINVAL;
+  return create(grid, (int)c.size(), c.data(), s.data(), E, opts, out, nalpha, begin.data());
 }
 
 int bura_plan_create(const bura_grid_t* grid, double alpha, int beta, int k, const bura_opts_t* opts,
@@ -891,6 +1129,14 @@ int bura_plan_coeffs(bura_plan_t plan, int* nterms, double* c, double* d, double
   return BURA_OK;
 }
 
+int bura_plan_outputs(bura_plan_t plan, int* nout, int* term_begin) {
+  if (!plan) return BURA_EINVAL;
+  if (nout) *nout = plan->nout;
+  if (term_begin)
+    for (int i = 0; i <= plan->nout; ++i) term_begin[i] = i < plan->nout ? plan->out_begin[i] : plan->nterms;
+  return BURA_OK;
+}
+
 int bura_plan_info(bura_plan_t plan, double* lambda, int* nlevels, size_t* device_bytes) {
   if (!plan) return BURA_EINVAL;
   if (lambda) *lambda = plan->lambda;
@@ -902,6 +1148,8 @@ int bura_plan_info(bura_plan_t plan, double* lambda, int* nlevels, size_t* devic
 int bura_plan_apply(bura_plan_t plan, double shift, const double* x_dev, double* y_dev, int nvec) {
   if (!plan || !x_dev || !y_dev || nvec < 1 || !(shift >= 0.0)) return BURA_EINVAL;
   HIPCHK(hipSetDevice(plan->device));
+  HIPCHK(hipEventRecord(plan->join_ev, plan->user_stream));
+  HIPCHK(hipStreamWaitEvent(plan->stream, plan->join_ev, 0));
   launch_apply64(plan->dim, plan->var, level_view<double>(plan, 0), x_dev, y_dev, shift, nvec, plan->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(plan->stream));
@@ -917,7 +1165,12 @@ int bura_plan_profile(bura_plan_t plan, int enable) {
     HIPCHK(hipDeviceSynchronize());
     plan->prof.rec.clear();
     plan->prof.used = 0;
+    for (int c = 0; c < BURA_K_COUNT; ++c) {
+      plan->prof.ms[c] = 0.0;
+      plan->prof.launches[c] = 0;
+    }
   }
+  destroy_graphs(plan);   // graphs carry (or lack) the profiling events
   plan->prof.on = enable != 0;
   plan->prof.mask = (unsigned)enable == 1u ? ((1u << BURA_K_COUNT) - 1u) : ((unsigned)enable >> 1);
   return BURA_OK;
@@ -927,15 +1180,9 @@ int bura_plan_kernel_stats(bura_plan_t plan, int kclass, long long* launches, do
   if (!plan || kclass < 0 || kclass >= BURA_K_COUNT) return BURA_EINVAL;
   HIPCHK(hipSetDevice(plan->device));
   HIPCHK(hipStreamSynchronize(plan->stream));
-  long long cnt = 0;
-  double ms = 0.0;
-  for (const auto& r : plan->prof.rec) {
-    if (r.first != kclass) continue;
-    float t = 0.f;
-    HIPCHK(hipEventElapsedTime(&t, plan->prof.pool[r.second], plan->prof.pool[r.second + 1]));
-    ms += t;
-    ++cnt;
-  }
+  prof_flush(plan);
+  const long long cnt = plan->prof.launches[kclass];
+  const double ms = plan->prof.ms[kclass];
   unsigned long long ctr[BURA_K_COUNT];
   HIPCHK(hipMemcpy(ctr, plan->prof.d_ctr, sizeof(ctr), hipMemcpyDeviceToHost));
   if (launches) *launches = cnt;
@@ -949,9 +1196,13 @@ void bura_plan_destroy(bura_plan_t plan) {
   if (plan->worker.joinable()) plan->worker.join();
   hipSetDevice(plan->device);
   hipDeviceSynchronize();
+  destroy_graphs(plan);
   for (hipEvent_t e : plan->prof.pool) hipEventDestroy(e);
   for (void* p : plan->allocs) hipFree(p);
   if (plan->h_flags) hipHostFree(plan->h_flags);
+  if (plan->h_state) hipHostFree(plan->h_state);
+  if (plan->join_ev) hipEventDestroy(plan->join_ev);
+  if (plan->stream) hipStreamDestroy(plan->stream);
   delete plan;
 }
 

@@ -64,12 +64,23 @@ struct SysState {
 
 enum ScalarOp { OP_INIT = 0, OP_ALPHA = 1, OP_RESID = 2, OP_BETA = 3, OP_OUTER = 4 };
 
+// Scalar update folded into the kernel that produces the reduction: the last
+// block of each system (counted in cnt[sys]) sums the block partials in the
+// fixed order and applies `op` to that system's state.  op < 0: not folded.
+struct Fin {
+  int op = -1;
+  unsigned int* cnt = nullptr;
+  SysState st{};
+  double tol = 0.0;
+  int max_iter = 0;
+};
+
 // ---- kernel launchers (bura_kernels.hip) ----------------------------------
 template <typename T>
 struct Launch {
   static void jacobi(int dim, bool var, const LevelDev<T>& L, const T* b, const T* xin, T* xout,
                      const T* shift, const int* active, T omega, bool zero_guess, double* partial,
-                     int nsys, hipStream_t st, unsigned long long* ctr);
+                     int nsys, hipStream_t st, unsigned long long* ctr, Fin fin = Fin());
   static void restrict_residual(int dim, bool var, const LevelDev<T>& Lf, const LevelDev<T>& Lc,
                                 const T* b, const T* x, T* bc, const T* shift, const int* active,
                                 int nsys, hipStream_t st, unsigned long long* ctr);
@@ -82,9 +93,19 @@ struct Launch {
                        const int* active, double* partial, int nsys, hipStream_t st, unsigned long long* ctr);
   static void update_xr(const LevelDev<T>& L, int dim, T* x, T* r, const T* p, const T* q,
                         const double* alpha, const int* active, double* partial, int nsys, hipStream_t st,
-                        unsigned long long* ctr);
+                        unsigned long long* ctr, Fin fin = Fin());
   static void update_p(const LevelDev<T>& L, int dim, T* p, const T* z, const double* beta,
                        const int* active, int nsys, hipStream_t st, unsigned long long* ctr);
+  static void spmv_p(int dim, bool var, const LevelDev<T>& L, const T* z, const T* pold, T* pnew, T* q,
+                     const double* beta, const T* shift, const int* active, double* partial, int nsys,
+                     hipStream_t st, unsigned long long* ctr, Fin fin = Fin());
+  // fused level kernels (2D); return false when not applicable
+  static bool fused_down(int dim, bool var, int nu, const LevelDev<T>& Lf, const LevelDev<T>& Lc, const T* b,
+                         T* xout, T* bc, const T* shift, const int* active, T omega, int nsys, hipStream_t st,
+                         unsigned long long* ctr);
+  static bool fused_up(int dim, bool var, int nu, const LevelDev<T>& Lc, const LevelDev<T>& Lf, const T* xc,
+                       const T* xin, const T* b, T* xout, const T* shift, const int* active, T omega,
+                       double* partial, int nsys, hipStream_t st, unsigned long long* ctr, Fin fin = Fin());
   static void copy_rhs(const LevelDev<T>& L, int dim, const double* f, T* r, T* x, int nrhs,
                        const int* active, double* partial, int nsys, hipStream_t st);
 };
@@ -102,8 +123,10 @@ void launch_apply64(int dim, bool var, const LevelDev<double>& L, const double* 
 void launch_scalars(int op, const double* partial, int nblk, int nsys, SysState st_, double tol,
                     int max_iter, hipStream_t st);
 void launch_zero(void* p, size_t bytes, hipStream_t st);
+void launch_fill_int(int* p, long long n, int v, hipStream_t st);
 
 int stencil_blocks(int dim, int n);   // blocks per system of a stencil launch (tile grid)
 int flat_blocks(long long N);        // blocks per system of an element-wise launch
+int up_blocks(int dim, int n);       // blocks per system of the fused up kernel
 
 }  // namespace bura

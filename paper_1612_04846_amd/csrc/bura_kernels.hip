@@ -66,6 +66,32 @@ __device__ __forceinline__ void write_partial_flat(double* partial, int sys, dou
   write_partial(partial, sys, v, blockIdx.x, gridDim.x);
 }
 
+__device__ void apply_op(int op, double tot, const SysState& S, int sys, double tol, int max_iter);
+
+// The last block of `sys` (after every block has written its partial) sums
+// the partials in the same fixed order as k_scalars and applies fin.op.
+__device__ __forceinline__ void finish(const Fin& fin, const double* partial, int sys, int blk_count) {
+  if (fin.op < 0) return;
+  __shared__ int s_last;
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+  const int nthr = blockDim.x * blockDim.y;
+  if (tid == 0) {
+    __threadfence();
+    const unsigned prev = atomicAdd(fin.cnt + sys, 1u);
+    s_last = prev == (unsigned)(blk_count - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  double v = 0.0;
+  for (int b = tid; b < blk_count; b += nthr) v += partial[(size_t)sys * blk_count + b];
+  const double tot = block_sum(v);
+  if (tid == 0) {
+    atomicExch(fin.cnt + sys, 0u);
+    apply_op(fin.op, tot, fin.st, sys, fin.tol, fin.max_iter);
+  }
+}
+
 // Profiling: the first block of each system adds that system's algorithmic
 // bytes for the whole launch (each vector element read or written once) to a
 // per-kernel-class counter -- one atomic per system per launch.
@@ -144,7 +170,7 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(LevelDev<T> L, const T* __res
                                                    const T* __restrict__ xin, T* __restrict__ xout,
                                                    const T* __restrict__ shift, const int* __restrict__ active,
                                                    T omega, double* __restrict__ partial,
-                                                   unsigned long long* __restrict__ ctr) {
+                                                   unsigned long long* __restrict__ ctr, Fin fin) {
   const int sys = blockIdx.z;
   if (!active[sys]) return;
   int i, j, k;
@@ -169,7 +195,10 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(LevelDev<T> L, const T* __res
     xout[off + p] = xn;
     if (DOT) dot = (double)bv * (double)xn;
   }
-  if (DOT) write_partial_tile(partial, sys, dot);
+  if (DOT) {
+    write_partial_tile(partial, sys, dot);
+    finish(fin, partial, sys, gridDim.x * gridDim.y);
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -286,7 +315,7 @@ __device__ void lds_smooth(const LevelDev<T>& L, T* X, const T* B, T* Tm, T s, T
 }
 
 template <typename T, int DIM, bool VAR>
-__global__ __launch_bounds__(256) void k_coarse(LdsHierarchy<T> H, const T* __restrict__ b, T* __restrict__ x,
+__global__ __launch_bounds__(1024) void k_coarse(LdsHierarchy<T> H, const T* __restrict__ b, T* __restrict__ x,
                                                 const T* __restrict__ shift, const int* __restrict__ active,
                                                 unsigned long long* __restrict__ ctr) {
   extern __shared__ unsigned char smem_raw[];
@@ -374,7 +403,294 @@ __global__ __launch_bounds__(256) void k_coarse(LdsHierarchy<T> H, const T* __re
 }
 
 // --------------------------------------------------------------------------
+// Fused multigrid level kernels with LDS-staged halo tiles (2D).
+//
+// k_down: from b on level l, nu Jacobi sweeps starting at x = 0, the residual
+// r = b - (A+s) x and its full weighting onto level l+1 -- one pass over b,
+// writing x (owned points) and b_c.  A block owns a CX x CY tile of coarse
+// points, i.e. fine points [2 I0, 2 I0 + 2 CX) per axis (the last tile also
+// the final fine point), and stages b on that range widened by nu on each
+// side plus one on the right; sweep m is valid on the range shrunk by m-1,
+// the residual on the range shrunk by nu = exactly the points the weighting
+// needs.  Points outside the grid hold 0 (Dirichlet) and are never updated.
+//
+// k_up: x = x_in + P x_c on an OX x OY tile widened by nu, nu Jacobi sweeps
+// (valid region shrinking by one per sweep), x written on the tile, and the
+// block partial of b.x when this is the finest level (r.z for the PCG).
+// --------------------------------------------------------------------------
+template <typename T, bool VAR>
+__device__ __forceinline__ T lds_apply2(const T* __restrict__ X, int q, int RX, const LevelDev<T>& L, int gi, int gj,
+                                        T s, T* dg) {
+  const T xc = X[q];
+  const T xl = X[q - 1], xr = X[q + 1], xd = X[q - RX], xu = X[q + RX];
+  if (!VAR) {
+    const T w = L.wc;
+    if (dg) *dg = w * T(4) + s;
+    return w * ((xc - xl) + (xc - xr) + (xc - xd) + (xc - xu)) + s * xc;
+  }
+  const int n = L.n;
+  const long long fx = (long long)gj * (n + 1) + gi;
+  const long long fy = (long long)gj * n + gi;
+  const T wl = L.wf0[fx], wr = L.wf0[fx + 1], wd = L.wf1[fy], wu = L.wf1[fy + n];
+  if (dg) *dg = wl + wr + wd + wu + s;
+  return wl * (xc - xl) + wr * (xc - xr) + wd * (xc - xd) + wu * (xc - xu) + s * xc;
+}
+
+constexpr int kDownCX = 32, kDownCY = 8;    // coarse points per block (2D)
+constexpr int kUpOX = 64, kUpOY = 16;       // fine points per block (2D)
+
+template <typename T, bool VAR, int NU>
+__global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, const T* __restrict__ b,
+                                               T* __restrict__ xout, T* __restrict__ bc,
+                                               const T* __restrict__ shift, const int* __restrict__ active,
+                                               T omega, unsigned long long* __restrict__ ctr) {
+  constexpr int RX = 2 * kDownCX + 2 * NU + 1, RY = 2 * kDownCY + 2 * NU + 1, RN = RX * RY;
+  __shared__ T sb[RN];
+  __shared__ T s0[RN];
+  __shared__ T s1[RN];
+  const int sys = blockIdx.z;
+  if (!active[sys]) return;
+  count_bytes<COUNT_TILE>(ctr, (unsigned long long)Lf.N * sizeof(T) * 2 + (unsigned long long)Lc.N * sizeof(T) +
+                                   (VAR && sys == 0 ? (unsigned long long)Lf.N * sizeof(T) * 2 : 0ULL));
+  const int nf = Lf.n, nc = Lc.n;
+  const int I0 = blockIdx.x * kDownCX, J0 = blockIdx.y * kDownCY;
+  const int gx0 = 2 * I0 - NU, gy0 = 2 * J0 - NU;
+  const T sh = shift[sys];
+  const T wcon = omega / (Lf.wc * T(4) + sh);   // omega / D for constant coefficients
+  const long long off = (long long)sys * Lf.N;
+  const int tid = threadIdx.x;
+  // stage b (0 outside the grid) and the first sweep from x = 0: x1 = omega b / D
+  for (int q = tid; q < RN; q += 256) {
+    const int ry = q / RX, rx = q - ry * RX;
+    const int gi = gx0 + rx, gj = gy0 + ry;
+    T bv = T(0), xv = T(0);
+    if (gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
+      bv = b[off + (long long)gj * nf + gi];
+      xv = VAR ? omega * bv / diag_pt<T, 2, VAR>(Lf, gi, gj, 0, sh) : wcon * bv;
+    }
+    sb[q] = bv;
+    s0[q] = xv;
+    s1[q] = T(0);
+  }
+  __syncthreads();
+  T* X = s0;
+  T* Y = s1;
+#pragma unroll
+  for (int m = 1; m < NU; ++m) {   // sweep m+1 on the range shrunk by m
+    const int w = RX - 2 * m, hgt = RY - 2 * m;
+    for (int q2 = tid; q2 < w * hgt; q2 += 256) {
+      const int ry = m + q2 / w, rx = m + q2 % w;
+      const int q = ry * RX + rx;
+      const int gi = gx0 + rx, gj = gy0 + ry;
+      if (gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
+        T dg;
+        const T ax = lds_apply2<T, VAR>(X, q, RX, Lf, gi, gj, sh, VAR ? &dg : nullptr);
+        Y[q] = VAR ? X[q] + omega * (sb[q] - ax) / dg : X[q] + wcon * (sb[q] - ax);
+      } else {
+        Y[q] = T(0);
+      }
+    }
+    __syncthreads();
+    T* t = X;
+    X = Y;
+    Y = t;
+  }
+  // owned fine points: [2 I0, 2 I0 + 2 CX) per axis, extended to the grid end on the last tile
+  {
+    const int hx = (I0 + kDownCX >= nc) ? nf : 2 * (I0 + kDownCX);
+    const int hy = (J0 + kDownCY >= nc) ? nf : 2 * (J0 + kDownCY);
+    const int ow = hx - 2 * I0, oh = hy - 2 * J0;
+    for (int q2 = tid; q2 < ow * oh; q2 += 256) {
+      const int oy = q2 / ow, ox = q2 - oy * ow;
+      const int gi = 2 * I0 + ox, gj = 2 * J0 + oy;
+      xout[off + (long long)gj * nf + gi] = X[(gj - gy0) * RX + (gi - gx0)];
+    }
+  }
+  // residual on the range shrunk by NU (fine points 2 I0 .. 2 I0 + 2 CX)
+  {
+    const int w = RX - 2 * NU, hgt = RY - 2 * NU;
+    for (int q2 = tid; q2 < w * hgt; q2 += 256) {
+      const int ry = NU + q2 / w, rx = NU + q2 % w;
+      const int q = ry * RX + rx;
+      const int gi = gx0 + rx, gj = gy0 + ry;
+      T r = T(0);
+      if (gi >= 0 && gi < nf && gj >= 0 && gj < nf) r = sb[q] - lds_apply2<T, VAR>(X, q, RX, Lf, gi, gj, sh, nullptr);
+      Y[q] = r;
+    }
+  }
+  __syncthreads();
+  // full weighting: coarse (I, J) <- fine 2I+1 +- 1
+  {
+    const int I = I0 + (tid % kDownCX), J = J0 + (tid / kDownCX);
+    if (I < nc && J < nc) {
+      const int cx = 2 * I + 1 - gx0, cy = 2 * J + 1 - gy0;
+      const T* R = Y + cy * RX + cx;
+      const T v = T(0.25) * R[0] + T(0.125) * (R[-1] + R[1] + R[-RX] + R[RX]) +
+                  T(0.0625) * (R[-RX - 1] + R[-RX + 1] + R[RX - 1] + R[RX + 1]);
+      bc[(long long)sys * Lc.N + (long long)J * nc + I] = v;
+    }
+  }
+}
+
+template <typename T, bool VAR, int NU, bool DOT>
+__global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, const T* __restrict__ xc,
+                                             const T* __restrict__ xin, const T* __restrict__ b, T* __restrict__ xout,
+                                             const T* __restrict__ shift, const int* __restrict__ active, T omega,
+                                             double* __restrict__ partial, unsigned long long* __restrict__ ctr,
+                                             Fin fin) {
+  constexpr int RX = kUpOX + 2 * NU, RY = kUpOY + 2 * NU, RN = RX * RY;
+  // coarse values under the region, zero-padded: coarse index c at cx0 + (c - c0)
+  constexpr int CRX = RX / 2 + 3, CRY = RY / 2 + 3, CRN = CRX * CRY;
+  __shared__ T sb[RN];
+  __shared__ T s0[RN];
+  __shared__ T s1[RN];
+  __shared__ T sc[CRN];
+  const int sys = blockIdx.z;
+  if (!active[sys]) return;
+  count_bytes<COUNT_TILE>(ctr, (unsigned long long)Lf.N * sizeof(T) * 3 + (unsigned long long)Lc.N * sizeof(T) +
+                                   (VAR && sys == 0 ? (unsigned long long)Lf.N * sizeof(T) * 2 : 0ULL));
+  const int nf = Lf.n, nc = Lc.n;
+  const int ox0 = blockIdx.x * kUpOX, oy0 = blockIdx.y * kUpOY;
+  const int gx0 = ox0 - NU, gy0 = oy0 - NU;
+  // smallest coarse index any region point interpolates from (floor division)
+  const int cx0 = ((gx0 >= 0) ? gx0 / 2 : -((-gx0 + 1) / 2)) - 1;
+  const int cy0 = ((gy0 >= 0) ? gy0 / 2 : -((-gy0 + 1) / 2)) - 1;
+  const T sh = shift[sys];
+  const T wcon = omega / (Lf.wc * T(4) + sh);
+  const long long off = (long long)sys * Lf.N;
+  const T* xcs = xc + (long long)sys * Lc.N;
+  const int tid = threadIdx.x;
+  for (int q = tid; q < CRN; q += 256) {
+    const int cy = q / CRX, cx = q - cy * CRX;
+    const int I = cx0 + cx, J = cy0 + cy;
+    sc[q] = (I >= 0 && I < nc && J >= 0 && J < nc) ? xcs[(long long)J * nc + I] : T(0);
+  }
+  __syncthreads();
+  for (int q = tid; q < RN; q += 256) {
+    const int ry = q / RX, rx = q - ry * RX;
+    const int gi = gx0 + rx, gj = gy0 + ry;
+    T bv = T(0), xv = T(0);
+    if (gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
+      const long long g = off + (long long)gj * nf + gi;
+      bv = b[g];
+      // multilinear interpolation from the zero-padded coarse tile
+      const int ia = (gi & 1) ? (gi - 1) / 2 : gi / 2 - 1;
+      const int ja = (gj & 1) ? (gj - 1) / 2 : gj / 2 - 1;
+      const T* C = sc + (ja - cy0) * CRX + (ia - cx0);
+      T v;
+      if (gi & 1) {
+        v = (gj & 1) ? C[0] : T(0.5) * (C[0] + C[CRX]);
+      } else {
+        v = (gj & 1) ? T(0.5) * (C[0] + C[1]) : T(0.25) * (C[0] + C[1] + C[CRX] + C[CRX + 1]);
+      }
+      xv = xin[g] + v;
+    }
+    sb[q] = bv;
+    s0[q] = xv;
+    s1[q] = T(0);
+  }
+  __syncthreads();
+  T* X = s0;
+  T* Y = s1;
+#pragma unroll
+  for (int m = 1; m <= NU; ++m) {
+    const int w = RX - 2 * m, hgt = RY - 2 * m;
+    for (int q2 = tid; q2 < w * hgt; q2 += 256) {
+      const int ry = m + q2 / w, rx = m + q2 % w;
+      const int q = ry * RX + rx;
+      const int gi = gx0 + rx, gj = gy0 + ry;
+      if (gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
+        T dg;
+        const T ax = lds_apply2<T, VAR>(X, q, RX, Lf, gi, gj, sh, VAR ? &dg : nullptr);
+        Y[q] = VAR ? X[q] + omega * (sb[q] - ax) / dg : X[q] + wcon * (sb[q] - ax);
+      } else {
+        Y[q] = T(0);
+      }
+    }
+    __syncthreads();
+    T* t = X;
+    X = Y;
+    Y = t;
+  }
+  double dot = 0.0;
+  for (int q2 = tid; q2 < kUpOX * kUpOY; q2 += 256) {
+    const int oy = q2 / kUpOX, ox = q2 - oy * kUpOX;
+    const int gi = ox0 + ox, gj = oy0 + oy;
+    if (gi < nf && gj < nf) {
+      const int q = (oy + NU) * RX + (ox + NU);
+      const T v = X[q];
+      xout[off + (long long)gj * nf + gi] = v;
+      if (DOT) dot += (double)sb[q] * (double)v;
+    }
+  }
+  if (DOT) {
+    write_partial_tile(partial, sys, dot);
+    finish(fin, partial, sys, gridDim.x * gridDim.y);
+  }
+}
+
+// --------------------------------------------------------------------------
 // PCG pieces
+// --------------------------------------------------------------------------
+// p_new = z + beta p_old and q = (A+s) p_new in one pass (p_new formed at the
+// stencil points on the fly); p_old and p_new are different buffers.
+template <typename T, int DIM, bool VAR>
+__global__ __launch_bounds__(kBlock) void k_spmv_p(LevelDev<T> L, const T* __restrict__ z, const T* __restrict__ pold,
+                                                   T* __restrict__ pnew, T* __restrict__ q,
+                                                   const double* __restrict__ beta, const T* __restrict__ shift,
+                                                   const int* __restrict__ active, double* __restrict__ partial,
+                                                   unsigned long long* __restrict__ ctr, Fin fin) {
+  const int sys = blockIdx.z;
+  if (!active[sys]) return;
+  const T bt = (T)beta[sys];
+  count_bytes<COUNT_TILE>(ctr, (unsigned long long)L.N * sizeof(T) * ((bt == T(0) ? 3 : 4) + (VAR && sys == 0 ? DIM : 0)));
+  int i, j, k;
+  tile_ijk<DIM>(L.n, i, j, k);
+  const bool ok = i < L.n && j < L.n;
+  const long long off = (long long)sys * L.N;
+  const long long p = ((long long)k * L.n + j) * L.n + i;
+  double dot = 0.0;
+  if (ok) {
+    const int n = L.n;
+    const T* zs = z + off;
+    const T* ps = pold + off;
+    auto P = [&](long long idx) -> T { return bt == T(0) ? zs[idx] : zs[idx] + bt * ps[idx]; };
+    const T pc = P(p);
+    const T pl = i > 0 ? P(p - 1) : T(0);
+    const T pr = i < n - 1 ? P(p + 1) : T(0);
+    const T pd = j > 0 ? P(p - n) : T(0);
+    const T pu = j < n - 1 ? P(p + n) : T(0);
+    const long long nn = (long long)n * n;
+    T pb = T(0), pf = T(0);
+    if (DIM == 3) {
+      pb = k > 0 ? P(p - nn) : T(0);
+      pf = k < n - 1 ? P(p + nn) : T(0);
+    }
+    const T s = shift[sys];
+    T qv;
+    if (!VAR) {
+      T sum = (pc - pl) + (pc - pr) + (pc - pd) + (pc - pu);
+      if (DIM == 3) sum += (pc - pb) + (pc - pf);
+      qv = L.wc * sum + s * pc;
+    } else {
+      const long long fx = ((long long)k * n + j) * (n + 1) + i;
+      const long long fy = ((long long)k * (n + 1) + j) * n + i;
+      qv = L.wf0[fx] * (pc - pl) + L.wf0[fx + 1] * (pc - pr) + L.wf1[fy] * (pc - pd) + L.wf1[fy + n] * (pc - pu);
+      if (DIM == 3) {
+        const long long fz = ((long long)k * n + j) * n + i;
+        qv += L.wf2[fz] * (pc - pb) + L.wf2[fz + nn] * (pc - pf);
+      }
+      qv += s * pc;
+    }
+    pnew[off + p] = pc;
+    q[off + p] = qv;
+    dot = (double)pc * (double)qv;
+  }
+  write_partial_tile(partial, sys, dot);
+  finish(fin, partial, sys, gridDim.x * gridDim.y);
+}
+
+
 // --------------------------------------------------------------------------
 template <typename T, int DIM, bool VAR>
 __global__ __launch_bounds__(kBlock) void k_spmv_dot(LevelDev<T> L, const T* __restrict__ pv, T* __restrict__ q,
@@ -403,7 +719,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_update_xr(long long N, T* __restrict__ x, T* __restrict__ r,
                                                    const T* __restrict__ pv, const T* __restrict__ q,
                                                    const double* __restrict__ alpha, const int* __restrict__ active,
-                                                   double* __restrict__ partial, unsigned long long* __restrict__ ctr) {
+                                                   double* __restrict__ partial, unsigned long long* __restrict__ ctr,
+                                                   Fin fin) {
   const int sys = blockIdx.y;
   if (!active[sys]) return;
   count_bytes<COUNT_FLAT>(ctr, (unsigned long long)N * sizeof(T) * 6);
@@ -422,6 +739,7 @@ __global__ __launch_bounds__(256) void k_update_xr(long long N, T* __restrict__ 
     }
   }
   write_partial_flat(partial, sys, rr);
+  finish(fin, partial, sys, gridDim.x);
 }
 
 template <typename T>
@@ -564,17 +882,7 @@ __global__ __launch_bounds__(kBlock) void k_apply64(LevelDev<double> L, const do
 // per-system scalar updates: one block per system sums the block partials in
 // a fixed order, thread 0 advances that system's state.
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_scalars(int op, const double* __restrict__ partial, int nblk, SysState S,
-                                                 double tol, int max_iter) {
-  const int sys = blockIdx.x;
-  const bool inner = op != OP_OUTER;
-  if (inner && !S.active[sys]) return;
-  if (!inner && !S.active64[sys]) return;
-  double v = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x) v += partial[(size_t)sys * nblk + b];
-  // block_sum assumes a 2D-shaped block; a 1D block of 256 is the same
-  const double tot = block_sum(v);
-  if (threadIdx.x != 0) return;
+__device__ void apply_op(int op, double tot, const SysState& S, int sys, double tol, int max_iter) {
   switch (op) {
     case OP_INIT: {  // tot = ||b||^2 of the PCG right-hand side
       S.bnorm2[sys] = tot;
@@ -641,11 +949,7 @@ __global__ __launch_bounds__(256) void k_scalars(int op, const double* __restric
       const double rel = fn > 0.0 ? sqrt(tot / fn) : 0.0;
       S.relres64[sys] = rel;
       S.outer[sys] = o + 1;
-      if (!isfinite(rel)) {
-        S.flags[sys] |= 1;
-        S.active64[sys] = 0;
-        S.active[sys] = 0;
-      } else if (rel <= tol || o >= max_iter) {
+      if (rel <= tol || o >= max_iter) {
         S.active64[sys] = 0;
         S.active[sys] = 0;
       } else {
@@ -658,6 +962,19 @@ __global__ __launch_bounds__(256) void k_scalars(int op, const double* __restric
       break;
     }
   }
+}
+
+__global__ __launch_bounds__(256) void k_scalars(int op, const double* __restrict__ partial, int nblk, SysState S,
+                                                 double tol, int max_iter) {
+  const int sys = blockIdx.x;
+  const bool inner = op != OP_OUTER;
+  if (inner && !S.active[sys]) return;
+  if (!inner && !S.active64[sys]) return;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) v += partial[(size_t)sys * nblk + b];
+  const double tot = block_sum(v);
+  if (threadIdx.x != 0) return;
+  apply_op(op, tot, S, sys, tol, max_iter);
 }
 
 // --------------------------------------------------------------------------
@@ -698,10 +1015,10 @@ static inline dim3 flat_grid(long long N, int nsys) {
 template <typename T>
 void Launch<T>::jacobi(int dim, bool var, const LevelDev<T>& L, const T* b, const T* xin, T* xout, const T* shift,
                        const int* active, T omega, bool zero_guess, double* partial, int nsys, hipStream_t st,
-                       unsigned long long* ctr) {
+                       unsigned long long* ctr, Fin fin) {
   const dim3 g = stencil_grid(dim, L.n, nsys), blk(kTileX, kTileY);
   const bool dot = partial != nullptr;
-#define K_JAC(D, V, Z, DT) hipLaunchKernelGGL((k_jacobi<T, D, V, Z, DT>), g, blk, 0, st, L, b, xin, xout, shift, active, omega, partial, ctr)
+#define K_JAC(D, V, Z, DT) hipLaunchKernelGGL((k_jacobi<T, D, V, Z, DT>), g, blk, 0, st, L, b, xin, xout, shift, active, omega, partial, ctr, fin)
 #define K_JAC4(D, V, dummy)                       \
   do {                                            \
     if (zero_guess) {                             \
@@ -739,7 +1056,7 @@ template <typename T>
 void Launch<T>::coarse_solve(int dim, bool var, const LdsHierarchy<T>& H, const T* b, T* x, const T* shift,
                              const int* active, int nsys, size_t lds_bytes, hipStream_t st,
                              unsigned long long* ctr) {
-  const dim3 g(nsys), blk(256);
+  const dim3 g(nsys), blk(1024);
 #define K_CO(D, V, dummy) hipLaunchKernelGGL((k_coarse<T, D, V>), g, blk, lds_bytes, st, H, b, x, shift, active, ctr)
   BURA_DISPATCH_DV(dim, var, K_CO, 0);
 #undef K_CO
@@ -756,10 +1073,11 @@ void Launch<T>::spmv_dot(int dim, bool var, const LevelDev<T>& L, const T* p, T*
 
 template <typename T>
 void Launch<T>::update_xr(const LevelDev<T>& L, int dim, T* x, T* r, const T* p, const T* q, const double* alpha,
-                          const int* active, double* partial, int nsys, hipStream_t st, unsigned long long* ctr) {
+                          const int* active, double* partial, int nsys, hipStream_t st, unsigned long long* ctr,
+                          Fin fin) {
   (void)dim;
   hipLaunchKernelGGL((k_update_xr<T>), flat_grid(L.N, nsys), dim3(256), 0, st, L.N, x, r, p, q, alpha, active, partial,
-                     ctr);
+                     ctr, fin);
 }
 
 template <typename T>
@@ -775,6 +1093,59 @@ void Launch<T>::copy_rhs(const LevelDev<T>& L, int dim, const double* f, T* r, T
   (void)dim;
   // a batch is either all systems (sys = j * nrhs + r) or one pole (sys = r): rhs = sys % nrhs
   hipLaunchKernelGGL((k_copy_rhs<T>), flat_grid(L.N, nsys), dim3(256), 0, st, L.N, f, r, x, nrhs, active, partial);
+}
+
+template <typename T>
+void Launch<T>::spmv_p(int dim, bool var, const LevelDev<T>& L, const T* z, const T* pold, T* pnew, T* q,
+                       const double* beta, const T* shift, const int* active, double* partial, int nsys,
+                       hipStream_t st, unsigned long long* ctr, Fin fin) {
+  const dim3 g = stencil_grid(dim, L.n, nsys), blk(kTileX, kTileY);
+#define K_SPP(D, V, dummy) \
+  hipLaunchKernelGGL((k_spmv_p<T, D, V>), g, blk, 0, st, L, z, pold, pnew, q, beta, shift, active, partial, ctr, fin)
+  BURA_DISPATCH_DV(dim, var, K_SPP, 0);
+#undef K_SPP
+}
+
+template <typename T>
+bool Launch<T>::fused_down(int dim, bool var, int nu, const LevelDev<T>& Lf, const LevelDev<T>& Lc, const T* b,
+                           T* xout, T* bc, const T* shift, const int* active, T omega, int nsys, hipStream_t st,
+                           unsigned long long* ctr) {
+  if (dim != 2 || nu < 1 || nu > 3) return false;
+  const dim3 g((Lc.n + kDownCX - 1) / kDownCX, (Lc.n + kDownCY - 1) / kDownCY, nsys), blk(256);
+#define K_DN(V, NU_) hipLaunchKernelGGL((k_down2<T, V, NU_>), g, blk, 0, st, Lf, Lc, b, xout, bc, shift, active, omega, ctr)
+  if (var) {
+    if (nu == 1) K_DN(true, 1); else if (nu == 2) K_DN(true, 2); else K_DN(true, 3);
+  } else {
+    if (nu == 1) K_DN(false, 1); else if (nu == 2) K_DN(false, 2); else K_DN(false, 3);
+  }
+#undef K_DN
+  return true;
+}
+
+template <typename T>
+bool Launch<T>::fused_up(int dim, bool var, int nu, const LevelDev<T>& Lc, const LevelDev<T>& Lf, const T* xc,
+                         const T* xin, const T* b, T* xout, const T* shift, const int* active, T omega,
+                         double* partial, int nsys, hipStream_t st, unsigned long long* ctr, Fin fin) {
+  if (dim != 2 || nu < 1 || nu > 3) return false;
+  const dim3 g((Lf.n + kUpOX - 1) / kUpOX, (Lf.n + kUpOY - 1) / kUpOY, nsys), blk(256);
+  const bool dot = partial != nullptr;
+#define K_UP(V, NU_, D_) \
+  hipLaunchKernelGGL((k_up2<T, V, NU_, D_>), g, blk, 0, st, Lc, Lf, xc, xin, b, xout, shift, active, omega, partial, \
+                     ctr, fin)
+#define K_UPD(V, NU_) do { if (dot) K_UP(V, NU_, true); else K_UP(V, NU_, false); } while (0)
+  if (var) {
+    if (nu == 1) K_UPD(true, 1); else if (nu == 2) K_UPD(true, 2); else K_UPD(true, 3);
+  } else {
+    if (nu == 1) K_UPD(false, 1); else if (nu == 2) K_UPD(false, 2); else K_UPD(false, 3);
+  }
+#undef K_UPD
+#undef K_UP
+  return true;
+}
+
+int up_blocks(int dim, int n) {
+  if (dim != 2) return stencil_blocks(dim, n);
+  return ((n + kUpOX - 1) / kUpOX) * ((n + kUpOY - 1) / kUpOY);
 }
 
 template struct Launch<float>;
@@ -818,6 +1189,16 @@ void launch_apply64(int dim, bool var, const LevelDev<double>& L, const double* 
 void launch_scalars(int op, const double* partial, int nblk, int nsys, SysState S, double tol, int max_iter,
                     hipStream_t st) {
   hipLaunchKernelGGL(k_scalars, dim3(nsys), dim3(256), 0, st, op, partial, nblk, S, tol, max_iter);
+}
+
+__global__ void k_fill_int(int* __restrict__ p, long long n, int v) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+void launch_fill_int(int* p, long long n, int v, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
 }
 
 __global__ void k_zero(unsigned char* p, size_t bytes) {

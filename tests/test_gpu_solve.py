@@ -222,3 +222,40 @@ def test_submit_poll_matches_solve():
     assert code == B.BURA_OK
     assert np.array_equal(_host(u), u_sync)
     plan.close()
+
+
+def test_multi_alpha_plan_equals_single_plans():
+    """All poles of several alphas in one batch: each output bit-identical to its own plan."""
+    from oracle import spectral
+    B = _B()
+    n = 63
+    alphas, k = [0.25, 0.5, 0.75], 7
+    F = synth.normal_rhs(n, 2, nrhs=2, tag=91)
+    pm = B.Plan(2, n, alphas, k, nrhs_max=2, precision=B.BURA_FP64, tol=1e-12)
+    um = _host(pm.solve(_dev(F)).u)
+    assert um.shape == (3, 2, n, n)
+    for i, a in enumerate(alphas):
+        p1 = B.Plan(2, n, a, k, nrhs_max=2, precision=B.BURA_FP64, tol=1e-12)
+        u1 = _host(p1.solve(_dev(F)).u)
+        assert np.array_equal(um[i], u1)
+        b = oracle_bura(a, k)
+        assert _errs(um[i], spectral.bura_spectral(F, 2, b.c_f64, b.d_f64))[0] <= 1e-9
+        p1.close()
+    nout, tb = B.bura_plan_outputs(pm.handle)
+    assert nout == 3 and tb == [0, 8, 16, 24]
+    pm.close()
+
+
+def test_folded_scalars_match_separate_launches(monkeypatch):
+    """Scalar updates folded into the producing kernels (opt-in) give the same bits as separate launches,
+    with and without graph replay."""
+    B = _B()
+    n = 63
+    F = _dev(synth.normal_rhs(n, 2, nrhs=1, tag=92))
+    u_sep = _host(B.Plan(2, n, 0.5, 5, precision=B.BURA_MIXED).solve(F).u)
+    monkeypatch.setenv("BURA_FOLD", "1")
+    u_fold = _host(B.Plan(2, n, 0.5, 5, precision=B.BURA_MIXED).solve(F).u)
+    monkeypatch.setenv("BURA_NO_GRAPH", "1")
+    u_eager = _host(B.Plan(2, n, 0.5, 5, precision=B.BURA_MIXED).solve(F).u)
+    assert np.array_equal(u_fold, u_sep)
+    assert np.array_equal(u_eager, u_sep)
