@@ -240,6 +240,59 @@ def cpu_baseline(w, res):
     return errs, sample, t_acc
 
 
+def run_serving(args):
+    """Seeded Poisson stream of requests through the continuous-batching server."""
+    import numpy as np
+    import torch
+
+    import paper_1612_04846_amd as B
+    import synth
+    reqs = synth.request_stream(args.serve_requests, args.serve_rate, tag=5)
+    dev = torch.device("cuda:0")
+    F = [torch.from_numpy(synth.normal_rhs(r.n, r.dim, nrhs=1, tag=r.rhs_tag)[0]).to(dev) for r in reqs]
+    U = [torch.empty_like(f) for f in F]
+    torch.cuda.synchronize()
+    budget = int(args.serve_budget_gb * (1 << 30))
+    server = B.bura_server_create(budget, args.serve_concurrency, args.serve_group)
+
+    failures = []
+
+    def stream(timed):
+        t0 = time.perf_counter()
+        tickets = []
+        for r, f, u in zip(reqs, F, U):
+            if timed:
+                delay = t0 + r.arrival - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+            tickets.append(B.bura_server_submit(server, r.dim, r.n, r.alpha, r.k, f, u,
+                                                tol=min(r.target, 1e-8), precision=B.BURA_MIXED))
+        codes = []
+        for i, t in enumerate(tickets):
+            code, rep = B.bura_server_wait(server, t)
+            codes.append(code)
+            if code != B.BURA_OK:
+                r = reqs[i]
+                failures.append(dict(dim=r.dim, n=r.n, alpha=r.alpha, k=r.k, target=r.target, code=code,
+                                     iters=list(rep.iters)[: r.k + 1], outer=list(rep.outer)[: r.k + 1],
+                                     relres=[float(x) for x in list(rep.relres)[: r.k + 1]]))
+            if (i + 1) % 8 == 0:
+                print(f"[bench]   {i + 1}/{len(tickets)} requests done", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, codes
+
+    print("[bench] serving warm-up (plans and coefficients)", file=sys.stderr, flush=True)
+    stream(False)
+    base = B.bura_server_stats(server)
+    print("[bench] serving timed stream", file=sys.stderr, flush=True)
+    wall, codes = stream(True)
+    st = B.bura_server_stats(server)
+    B.bura_server_destroy(server)
+    ok = [c == B.BURA_OK for c in codes]
+    upole = st["unknown_pole_solves"] - base["unknown_pole_solves"]
+    return dict(wall=wall, ok=ok, stats=st, base=base, upole=upole, reqs=reqs, F=F, U=U, failures=failures)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -248,6 +301,13 @@ def main():
     ap.add_argument("--workload", default="2d1023-k9-fp64-multi", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--serving", action="store_true",
+                    help="run the request-server workload (seeded Poisson stream) instead")
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-rate", type=float, default=16.0, help="mean arrivals per second")
+    ap.add_argument("--serve-concurrency", type=int, default=4)
+    ap.add_argument("--serve-group", type=int, default=2)
+    ap.add_argument("--serve-budget-gb", type=float, default=160.0)
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of this many GiB (counter calibration)")
     ap.add_argument("--also", default="2d1023-k9-fp64-per-pole,2d1023-k9-fp64-batched,2d1023-k9-mixed-multi",
@@ -263,6 +323,41 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes, "launches": 3}))
+        return
+    if args.serving:
+        res = run_serving(args)
+        st = res["stats"]
+        out = {"metric": METRIC, "value": None, "unit": "unknown-pole solves/s", "n_gpus": 1,
+               "steps": 1, "warmup": 1, "ms_per_step": 1e3 * res["wall"], "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+               "data": "synthetic (seeded Poisson request stream, N(0,1) right-hand sides)",
+               "config": {"workload": f"serving: {args.serve_requests} requests, Poisson rate {args.serve_rate}/s, "
+                                      "grids 127^2-1023^2 and 63^3-255^3, alpha in 0.1..0.9, target 1e-6..1e-9 "
+                                      "-> k 5..12, mixed precision", "max_group": args.serve_group,
+                          "max_concurrent": args.serve_concurrency, "hbm_budget_gb": args.serve_budget_gb},
+               "latency_ms": {"p50": 1e3 * st["p50_latency_s"], "p99": 1e3 * st["p99_latency_s"],
+                              "per": "one request (submit to result), both passes"},
+               "server": {k: v for k, v in st.items()}}
+        accepted = all(res["ok"])
+        out["failures"] = res["failures"][:12]
+        if not args.no_cpu_baseline:
+            from oracle import metrics, spectral
+            gold = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_bura_coefficients.json")))
+            errs = []
+            for r, f, u in list(zip(res["reqs"], res["F"], res["U"]))[:8]:
+                rec = gold.get(f"{r.alpha:.2f},{r.k}")
+                if not rec or "error" in rec:
+                    continue
+                ref = spectral.bura_spectral(f.cpu().numpy()[None], r.dim, [float(x) for x in rec["c"]],
+                                             [float(x) for x in rec["d"]])
+                e = metrics.rel_err(u.cpu().numpy()[None], ref)
+                errs.append((e, r.target))
+                accepted &= e <= max(r.target, 1e-8)
+            out["rel_err_vs_oracle"] = max(e for e, _ in errs) if errs else None
+            out["checked_requests"] = len(errs)
+        out["accepted"] = accepted
+        out["value"] = res["upole"] / res["wall"] if accepted else 0.0
+        print(json.dumps(out))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of it",

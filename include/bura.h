@@ -208,6 +208,54 @@ int bura_plan_profile(bura_plan_t plan, int enable);
 int bura_plan_kernel_stats(bura_plan_t plan, int kclass, long long* launches, double* total_ms,
                            double* alg_bytes);
 
+/* ---------------------------------------------------------------------------
+ * Request server (continuous batching on one GPU).
+ *
+ * Requests for the constant-coefficient grids are queued by bura_server_submit
+ * and served by a dispatcher thread: plans are kept resident per
+ * (dim, n, alpha, k, precision, tol); an idle plan takes the queued requests
+ * with its key (up to max_group of them, batched as right-hand sides of one
+ * solve); up to max_concurrent plans solve at once on their own streams, so
+ * requests that arrive while others run are admitted as soon as a plan and
+ * memory are free.  New plans are admitted against hbm_budget bytes (0 =
+ * unlimited), evicting idle plans least recently used first; a request whose
+ * plan can never fit fails with BURA_ENOMEM.  A request's result does not
+ * depend on which other requests share its batch.  f_dev / u_dev are FP64
+ * device vectors of n^dim values; f_dev must be fully written (its stream
+ * synchronised) before submit, and both must stay valid until the ticket
+ * completes.  All server functions are thread-safe.
+ * ------------------------------------------------------------------------- */
+typedef struct bura_server_s* bura_server_t;
+
+typedef struct {
+  int dim, n;        /* grid (Laplacian, scaled as above)                    */
+  double alpha;      /* 0 < alpha < 1                                        */
+  int k;             /* poles: k+1 shifted systems, 1 <= k <= 16             */
+  double tol;        /* FP64 relative residual per shifted system            */
+  int precision;     /* enum bura_precision                                  */
+} bura_request_t;
+
+typedef struct {
+  long long submitted, completed, failed, batches, plans_created, plans_evicted;
+  double unknown_pole_solves;   /* sum over successful requests of n^dim (k+1)   */
+  double p50_latency_s, p99_latency_s;   /* submit -> result, completed requests */
+  double mean_batch;            /* requests per solve                            */
+  size_t resident_bytes;        /* device bytes of resident plans                */
+} bura_server_stats_t;
+
+int bura_server_create(size_t hbm_budget, int max_concurrent, int max_group, bura_server_t* out);
+/* Queue a request; *ticket identifies it.  Returns at once. */
+int bura_server_submit(bura_server_t s, const bura_request_t* req, const double* f_dev, double* u_dev,
+                       uint64_t* ticket);
+/* BURA_PENDING while queued or running; then the request's status (the ticket
+ * is released) with its report in *rep (may be NULL). */
+int bura_server_poll(bura_server_t s, uint64_t ticket, bura_report_t* rep);
+/* Blocking variant of bura_server_poll. */
+int bura_server_wait(bura_server_t s, uint64_t ticket, bura_report_t* rep);
+int bura_server_stats(bura_server_t s, bura_server_stats_t* st);
+/* Waits for queued and running requests, then frees every plan. */
+void bura_server_destroy(bura_server_t s);
+
 /* Release every resource of the plan.  Waits for an outstanding solve. */
 void bura_plan_destroy(bura_plan_t plan);
 

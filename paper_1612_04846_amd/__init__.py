@@ -84,6 +84,33 @@ class bura_report_t(ctypes.Structure):
     ]
 
 
+class bura_request_t(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int),
+        ("n", ctypes.c_int),
+        ("alpha", ctypes.c_double),
+        ("k", ctypes.c_int),
+        ("tol", ctypes.c_double),
+        ("precision", ctypes.c_int),
+    ]
+
+
+class bura_server_stats_t(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_longlong),
+        ("completed", ctypes.c_longlong),
+        ("failed", ctypes.c_longlong),
+        ("batches", ctypes.c_longlong),
+        ("plans_created", ctypes.c_longlong),
+        ("plans_evicted", ctypes.c_longlong),
+        ("unknown_pole_solves", ctypes.c_double),
+        ("p50_latency_s", ctypes.c_double),
+        ("p99_latency_s", ctypes.c_double),
+        ("mean_batch", ctypes.c_double),
+        ("resident_bytes", ctypes.c_size_t),
+    ]
+
+
 _P = ctypes.c_void_p
 _D = ctypes.c_double
 _I = ctypes.c_int
@@ -108,6 +135,12 @@ _SIGS = {
     "bura_plan_kernel_stats": (_I, [_P, _I, ctypes.POINTER(ctypes.c_longlong), _DP, _DP]),
     "bura_plan_destroy": (None, [_P]),
     "bura_strerror": (ctypes.c_char_p, [_I]),
+    "bura_server_create": (_I, [ctypes.c_size_t, _I, _I, ctypes.POINTER(_P)]),
+    "bura_server_submit": (_I, [_P, ctypes.POINTER(bura_request_t), _P, _P, ctypes.POINTER(ctypes.c_uint64)]),
+    "bura_server_poll": (_I, [_P, ctypes.c_uint64, ctypes.POINTER(bura_report_t)]),
+    "bura_server_wait": (_I, [_P, ctypes.c_uint64, ctypes.POINTER(bura_report_t)]),
+    "bura_server_stats": (_I, [_P, ctypes.POINTER(bura_server_stats_t)]),
+    "bura_server_destroy": (None, [_P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -358,3 +391,45 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+# --------------------------------------------------------------------------
+# request server
+# --------------------------------------------------------------------------
+
+def bura_server_create(hbm_budget: int = 0, max_concurrent: int = 4, max_group: int = 4):
+    h = _P()
+    _check(_lib.bura_server_create(hbm_budget, max_concurrent, max_group, ctypes.byref(h)), "bura_server_create")
+    return h
+
+
+def bura_server_submit(server, dim, n, alpha, k, f: torch.Tensor, u: torch.Tensor, tol=1e-10,
+                       precision=BURA_MIXED) -> int:
+    q = bura_request_t(dim, n, alpha, k, tol, precision)
+    t = ctypes.c_uint64()
+    _check(_lib.bura_server_submit(server, ctypes.byref(q), _devptr(f, "f"), _devptr(u, "u"), ctypes.byref(t)),
+           "bura_server_submit")
+    return t.value
+
+
+def bura_server_poll(server, ticket: int):
+    rep = bura_report_t()
+    code = _lib.bura_server_poll(server, ticket, ctypes.byref(rep))
+    return code, rep
+
+
+def bura_server_wait(server, ticket: int):
+    rep = bura_report_t()
+    code = _lib.bura_server_wait(server, ticket, ctypes.byref(rep))
+    return code, rep
+
+
+def bura_server_stats(server) -> dict:
+    st = bura_server_stats_t()
+    _check(_lib.bura_server_stats(server, ctypes.byref(st)), "bura_server_stats")
+    return {name: getattr(st, name) for name, _ in bura_server_stats_t._fields_}
+
+
+def bura_server_destroy(server):
+    if server:
+        _lib.bura_server_destroy(server)

@@ -466,9 +466,10 @@ int alloc_work(bura_plan_t P, Work<T>& W) {
   std::vector<T> sh(S);
   const int R = P->opts.nrhs_max;
   for (size_t i = 0; i < S; ++i) sh[i] = (T)P->s[i / R];
-  HIPCHK(hipMemcpy(W.shift, sh.data(), S * sizeof(T), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpyAsync(W.shift, sh.data(), S * sizeof(T), hipMemcpyHostToDevice, P->stream));
+  HIPCHK(hipStreamSynchronize(P->stream));
   for (void* ptr : {(void*)W.x, (void*)W.r, (void*)W.z, (void*)W.zt, (void*)W.p, (void*)W.p2, (void*)W.q})
-    HIPCHK(hipMemset(ptr, 0, vb));
+    HIPCHK(hipMemsetAsync(ptr, 0, vb, P->stream));
   return BURA_OK;
 }
 
@@ -494,8 +495,9 @@ int upload_faces(bura_plan_t P) {
       if ((rc = dev_alloc(P, (void**)&L.d_wf64[a], cnt * 8))) return rc;
       if ((rc = dev_alloc(P, (void**)&L.d_wf32[a], cnt * 4))) return rc;
       std::vector<float> f32(L.wf[a].begin(), L.wf[a].end());
-      HIPCHK(hipMemcpy(L.d_wf64[a], L.wf[a].data(), cnt * 8, hipMemcpyHostToDevice));
-      HIPCHK(hipMemcpy(L.d_wf32[a], f32.data(), cnt * 4, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpyAsync(L.d_wf64[a], L.wf[a].data(), cnt * 8, hipMemcpyHostToDevice, P->stream));
+      HIPCHK(hipMemcpyAsync(L.d_wf32[a], f32.data(), cnt * 4, hipMemcpyHostToDevice, P->stream));
+      HIPCHK(hipStreamSynchronize(P->stream));
     }
   }
   return BURA_OK;
@@ -748,14 +750,14 @@ int set_flags(bura_plan_t P, int* dev, size_t sys0, int nsys, int value) {
   return BURA_OK;
 }
 
-int solve_batch_fp64(bura_plan_t P, const double* f, int nrhs, size_t sys0, int nsys) {
+int solve_batch_fp64(bura_plan_t P, const double* f, int nrhs, size_t sys0, int nsys, bool preset) {
   hipStream_t st = P->stream;
   Work<double>& W = P->w64;
   const LevelDev<double> L0 = level_view<double>(P, 0);
   const size_t o = sys0 * (size_t)P->N;
   const SysState S = state_at(P, sys0);
   int rc;
-  if ((rc = set_flags(P, P->st.active, sys0, nsys, 1))) return rc;
+  if (!preset && (rc = set_flags(P, P->st.active, sys0, nsys, 1))) return rc;
   {
     ProfScope ps(P, BURA_K_OTHER);
     Launch<double>::copy_rhs(L0, P->dim, f, W.r + o, W.x + o, nrhs, S.active, P->partial, nsys, st);
@@ -767,15 +769,21 @@ int solve_batch_fp64(bura_plan_t P, const double* f, int nrhs, size_t sys0, int 
   return run_pcg<double>(P, W, sys0, nsys, P->opts.tol, P->opts.max_iter);
 }
 
-int solve_batch_mixed(bura_plan_t P, const double* f, int nrhs, size_t sys0, int nsys) {
+int solve_batch_mixed(bura_plan_t P, const double* f, int nrhs, size_t sys0, int nsys, bool preset) {
   hipStream_t st = P->stream;
   Work<float>& W = P->w32;
   const LevelDev<double> L0 = level_view<double>(P, 0);
   const size_t o = sys0 * (size_t)P->N;
   const SysState S = state_at(P, sys0);
   int rc;
-  if ((rc = set_flags(P, P->st.active64, sys0, nsys, 1))) return rc;
-  if ((rc = set_flags(P, P->st.active, sys0, nsys, 1))) return rc;
+  if (!preset) {
+    if ((rc = set_flags(P, P->st.active64, sys0, nsys, 1))) return rc;
+    if ((rc = set_flags(P, P->st.active, sys0, nsys, 1))) return rc;
+  } else {
+    // inner flags follow the outer ones (OP_OUTER re-arms them per system)
+    HIPCHK(hipMemcpyAsync(P->st.active + sys0, P->st.active64 + sys0, nsys * sizeof(int), hipMemcpyDeviceToDevice,
+                          P->stream));
+  }
   {
     ProfScope ps(P, BURA_K_RESIDUAL64);
     launch_residual64(P->dim, P->var, L0, f, P->x64 + o, W.x + o, W.r + o, P->d_shift64 + sys0, S.active64,
@@ -827,24 +835,23 @@ int do_solve(bura_plan_t P, const double* f, double* u, int nrhs, bura_report_t*
   if ((rc = set_flags(P, P->st.flags, 0, (int)S_used, 0))) return rc;
   if ((rc = set_flags(P, P->st.total_iters, 0, (int)S_used, 0))) return rc;
   if ((rc = set_flags(P, P->st.outer, 0, (int)S_used, 0))) return rc;
-  // systems of unused rhs slots stay inactive
-  if (nrhs < R) {
-    if ((rc = set_flags(P, P->st.active, 0, (int)S_used, 0))) return rc;
-    if ((rc = set_flags(P, P->st.active64, 0, (int)S_used, 0))) return rc;
-  }
-  auto batch = [&](size_t sys0, int nsys) {
+  auto batch = [&](size_t sys0, int nsys, bool preset) {
     // the kernels take rhs = sys % R; pass f with R slots (rhs >= nrhs never active)
-    return mixed ? solve_batch_mixed(P, f, R, sys0, nsys) : solve_batch_fp64(P, f, R, sys0, nsys);
+    return mixed ? solve_batch_mixed(P, f, R, sys0, nsys, preset) : solve_batch_fp64(P, f, R, sys0, nsys, preset);
   };
-  if (nrhs == R) {
-    if (P->opts.schedule == BURA_PER_POLE) {
-      for (int j = 0; j < P->nterms && rc == BURA_OK; ++j) rc = batch((size_t)j * R, R);
-    } else {
-      rc = batch(0, (int)S_used);
+  if (P->opts.schedule == BURA_PER_POLE) {
+    if (nrhs < R) {
+      if ((rc = set_flags(P, P->st.active, 0, (int)S_used, 0))) return rc;
+      if ((rc = set_flags(P, P->st.active64, 0, (int)S_used, 0))) return rc;
     }
+    for (int j = 0; j < P->nterms && rc == BURA_OK; ++j) rc = batch((size_t)j * R, nrhs, false);
+  } else if (nrhs == R) {
+    rc = batch(0, (int)S_used, false);
   } else {
-    // fewer rhs than slots: run each pole's first nrhs systems
-    for (int j = 0; j < P->nterms && rc == BURA_OK; ++j) rc = batch((size_t)j * R, nrhs);
+    // fewer rhs than slots: one batch over all systems, unused slots inactive
+    launch_slot_flags(P->st.active, P->nterms, R, nrhs, P->stream);
+    if (mixed) launch_slot_flags(P->st.active64, P->nterms, R, nrhs, P->stream);
+    rc = batch(0, (int)S_used, true);
   }
   if (rc) return rc;
   // combine u_i = sum_{j in output i} w_j x_j (fixed order, FP64)
@@ -970,7 +977,7 @@ int create(const bura_grid_t* g, int nterms, const double* w, const double* s, d
   if (mixed) {
     if ((rc = alloc_work<float>(P, P->w32))) return fail(rc);
     if ((rc = dev_alloc(P, (void**)&P->x64, (size_t)P->S * P->N * 8))) return fail(rc);
-    hipMemset(P->x64, 0, (size_t)P->S * P->N * 8);
+    hipMemsetAsync(P->x64, 0, (size_t)P->S * P->N * 8, P->stream);
   } else {
     if ((rc = alloc_work<double>(P, P->w64))) return fail(rc);
   }
@@ -979,18 +986,22 @@ int create(const bura_grid_t* g, int nterms, const double* w, const double* s, d
   {
     std::vector<double> sh(P->S);
     for (int i = 0; i < P->S; ++i) sh[i] = P->s[i / o.nrhs_max];
-    if (hipMemcpy(P->d_shift64, sh.data(), sh.size() * 8, hipMemcpyHostToDevice) != hipSuccess) return fail(BURA_EDEVICE);
+    if (hipMemcpyAsync(P->d_shift64, sh.data(), sh.size() * 8, hipMemcpyHostToDevice, P->stream) != hipSuccess ||
+        hipStreamSynchronize(P->stream) != hipSuccess)
+      return fail(BURA_EDEVICE);
   }
   const size_t maxblk = (size_t)std::max({stencil_blocks(P->dim, P->n), flat_blocks(P->N), up_blocks(P->dim, P->n)});
   P->partial_len = (size_t)P->S * maxblk;
   if ((rc = dev_alloc(P, (void**)&P->partial, P->partial_len * 8))) return fail(rc);
   if ((rc = dev_alloc(P, (void**)&P->d_w, nterms * 8))) return fail(rc);
-  if (hipMemcpy(P->d_w, P->w.data(), nterms * 8, hipMemcpyHostToDevice) != hipSuccess) return fail(BURA_EDEVICE);
+  if (hipMemcpyAsync(P->d_w, P->w.data(), nterms * 8, hipMemcpyHostToDevice, P->stream) != hipSuccess ||
+      hipStreamSynchronize(P->stream) != hipSuccess)
+    return fail(BURA_EDEVICE);
   // state arrays: 6 double + 7 int arrays of length S
   const size_t S = (size_t)P->S;
   const size_t bytes = S * (6 * 8 + 8 * 4);
   if ((rc = dev_alloc(P, &P->state_block, bytes))) return fail(rc);
-  hipMemset(P->state_block, 0, bytes);
+  hipMemsetAsync(P->state_block, 0, bytes, P->stream);
   double* dp = (double*)P->state_block;
   P->st.bnorm2 = dp; P->st.rho = dp + S; P->st.alpha = dp + 2 * S; P->st.beta = dp + 3 * S;
   P->st.relres = dp + 4 * S; P->st.fnorm2 = dp + 5 * S;
@@ -1000,16 +1011,18 @@ int create(const bura_grid_t* g, int nterms, const double* w, const double* s, d
   P->st.active64 = ip + 4 * S; P->st.outer = ip + 5 * S;
   // relres64 needs doubles: carve from a separate allocation
   if ((rc = dev_alloc(P, (void**)&P->st.relres64, S * 8))) return fail(rc);
-  hipMemset(P->st.relres64, 0, S * 8);
+  hipMemsetAsync(P->st.relres64, 0, S * 8, P->stream);
   if ((rc = dev_alloc(P, (void**)&P->d_cnt, S * sizeof(unsigned int)))) return fail(rc);
-  hipMemset(P->d_cnt, 0, S * sizeof(unsigned int));
+  hipMemsetAsync(P->d_cnt, 0, S * sizeof(unsigned int), P->stream);
   if ((rc = dev_alloc(P, (void**)&P->prof.d_ctr, BURA_K_COUNT * sizeof(unsigned long long)))) return fail(rc);
-  hipMemset(P->prof.d_ctr, 0, BURA_K_COUNT * sizeof(unsigned long long));
+  hipMemsetAsync(P->prof.d_ctr, 0, BURA_K_COUNT * sizeof(unsigned long long), P->stream);
   if (hipHostMalloc((void**)&P->h_flags, S * sizeof(int), hipHostMallocDefault) != hipSuccess)
     return fail(BURA_ENOMEM);
   if (hipHostMalloc(&P->h_state, S * (6 * 8 + 8 * 4) + S * 8, hipHostMallocDefault) != hipSuccess)
     return fail(BURA_ENOMEM);
-  if (hipDeviceSynchronize() != hipSuccess) return fail(BURA_EDEVICE);
+  // only this plan's stream: a device-wide synchronisation would break graph
+  // capture running on other plans' streams in other threads
+  if (hipStreamSynchronize(P->stream) != hipSuccess) return fail(BURA_EDEVICE);
   *out = P;
   return BURA_OK;
 }
@@ -1161,8 +1174,8 @@ int bura_plan_profile(bura_plan_t plan, int enable) {
   HIPCHK(hipSetDevice(plan->device));
   HIPCHK(hipStreamSynchronize(plan->stream));
   if (enable) {
-    HIPCHK(hipMemset(plan->prof.d_ctr, 0, BURA_K_COUNT * sizeof(unsigned long long)));
-    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemsetAsync(plan->prof.d_ctr, 0, BURA_K_COUNT * sizeof(unsigned long long), plan->stream));
+    HIPCHK(hipStreamSynchronize(plan->stream));
     plan->prof.rec.clear();
     plan->prof.used = 0;
     for (int c = 0; c < BURA_K_COUNT; ++c) {
@@ -1184,7 +1197,8 @@ int bura_plan_kernel_stats(bura_plan_t plan, int kclass, long long* launches, do
   const long long cnt = plan->prof.launches[kclass];
   const double ms = plan->prof.ms[kclass];
   unsigned long long ctr[BURA_K_COUNT];
-  HIPCHK(hipMemcpy(ctr, plan->prof.d_ctr, sizeof(ctr), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpyAsync(ctr, plan->prof.d_ctr, sizeof(ctr), hipMemcpyDeviceToHost, plan->stream));
+  HIPCHK(hipStreamSynchronize(plan->stream));
   if (launches) *launches = cnt;
   if (total_ms) *total_ms = ms;
   if (alg_bytes) *alg_bytes = (double)ctr[kclass];
@@ -1195,7 +1209,7 @@ void bura_plan_destroy(bura_plan_t plan) {
   if (!plan) return;
   if (plan->worker.joinable()) plan->worker.join();
   hipSetDevice(plan->device);
-  hipDeviceSynchronize();
+  if (plan->stream) hipStreamSynchronize(plan->stream);
   destroy_graphs(plan);
   for (hipEvent_t e : plan->prof.pool) hipEventDestroy(e);
   for (void* p : plan->allocs) hipFree(p);

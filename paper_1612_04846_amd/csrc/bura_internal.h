@@ -124,6 +124,7 @@ void launch_scalars(int op, const double* partial, int nblk, int nsys, SysState 
                     int max_iter, hipStream_t st);
 void launch_zero(void* p, size_t bytes, hipStream_t st);
 void launch_fill_int(int* p, long long n, int v, hipStream_t st);
+void launch_slot_flags(int* p, int nterms, int R, int nrhs, hipStream_t st);
 
 int stencil_blocks(int dim, int n);   // blocks per system of a stencil launch (tile grid)
 int flat_blocks(long long N);        // blocks per system of an element-wise launch

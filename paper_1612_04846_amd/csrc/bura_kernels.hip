@@ -1196,6 +1196,17 @@ __global__ void k_fill_int(int* __restrict__ p, long long n, int v) {
   if (i < n) p[i] = v;
 }
 
+// flags of system j * R + r: 1 for r < nrhs, 0 otherwise
+__global__ void k_slot_flags(int* __restrict__ p, int nterms, int R, int nrhs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nterms * R) p[i] = (i % R) < nrhs ? 1 : 0;
+}
+
+void launch_slot_flags(int* p, int nterms, int R, int nrhs, hipStream_t st) {
+  const int n = nterms * R;
+  hipLaunchKernelGGL(k_slot_flags, dim3((n + 255) / 256), dim3(256), 0, st, p, nterms, R, nrhs);
+}
+
 void launch_fill_int(int* p, long long n, int v, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
