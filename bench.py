@@ -47,6 +47,11 @@ WORKLOADS = {
                                    precision="MIXED", schedule="BATCHED", tol=1e-10, var=False),
     "2d511-var-k7-256rhs-mixed": dict(dim=2, n=511, alphas=(0.6,), k=7, nrhs=256, rhs="normal", tag=4,
                                       precision="MIXED", schedule="BATCHED", tol=1e-10, var=True),
+    # the sinc quadrature Section 5.3 compares against, with k_Q = 9, 7, 6 (11 + 9 + 8
+    # shifted systems), on the paper's checkerboard right-hand side
+    "2d1023-sinc-fp64-multi": dict(dim=2, n=1023, alphas=(0.25, 0.5, 0.75), k=None, kq=(9, 7, 6), nrhs=1,
+                                   rhs="checkerboard", tag=0, precision="FP64", schedule="BATCHED", tol=1e-10,
+                                   var=False, multi=True, method="sinc"),
 }
 
 
@@ -57,7 +62,12 @@ def describe(w):
     sched = w['schedule'].lower().replace('_', '-')
     if w.get("multi"):
         sched = "batched over all poles of all alphas"
-    return (f"{d}D {grid} {op} operator scaled to (0,1], alpha={list(w['alphas'])}, beta=1, k={w['k']}, "
+    if w.get("method") == "sinc":
+        what = (f"alpha={list(w['alphas'])}, sinc quadrature (Bonito-Pasciak) with k_Q={list(w['kq'])} "
+                f"applied to the unscaled operator")
+    else:
+        what = f"alpha={list(w['alphas'])}, beta=1, k={w['k']}"
+    return (f"{d}D {grid} {op} operator scaled to (0,1], {what}, "
             f"{w['nrhs']} rhs ({w['rhs']}), {w['precision']} {sched} "
             f"GMG V(2,2)-PCG to rel residual {w['tol']:g}")
 
@@ -68,6 +78,9 @@ def make_rhs(w):
         return synth.normal_rhs(w["n"], w["dim"], nrhs=w["nrhs"], tag=w["tag"])
     if w["rhs"] == "sines":
         return synth.sine_modes_rhs(w["n"], w["dim"], nmodes=32, noise=1e-3, tag=w["tag"], nrhs=w["nrhs"])
+    if w["rhs"] == "checkerboard":
+        import numpy as np
+        return np.repeat(synth.checkerboard_rhs(w["n"])[None], w["nrhs"], axis=0)
     return synth.uniform_rhs(w["n"], w["dim"], nrhs=w["nrhs"], tag=w["tag"])
 
 
@@ -85,10 +98,14 @@ def run_gpu(w, steps, warmup, profile=True):
     plans = []
     t_plan = time.perf_counter()
     groups = [list(w["alphas"])] if w.get("multi") else [a for a in w["alphas"]]
+    kq = {a: q for a, q in zip(w["alphas"], w.get("kq") or [None] * len(w["alphas"]))}
     for a in groups:
-        plans.append(B.Plan(w["dim"], w["n"], a, w["k"], coeff=coeff, nrhs_max=w["nrhs"], tol=w["tol"],
-                            precision=getattr(B, "BURA_" + w["precision"]),
-                            schedule=getattr(B, "BURA_" + w["schedule"])))
+        kw = dict(coeff=coeff, nrhs_max=w["nrhs"], tol=w["tol"], precision=getattr(B, "BURA_" + w["precision"]),
+                  schedule=getattr(B, "BURA_" + w["schedule"]))
+        if w.get("method") == "sinc":
+            al = a if isinstance(a, list) else [a]
+            kw["kprime"] = [B.sinc_kprime(x, kq[x]) for x in al]
+        plans.append(B.Plan(w["dim"], w["n"], a, w["k"], **kw))
     t_plan = time.perf_counter() - t_plan
     outs = [torch.empty((p.nout,) + tuple(F.shape), dtype=F.dtype, device=dev) if p.nout > 1 else torch.empty_like(F)
             for p in plans]
@@ -135,14 +152,14 @@ def run_gpu(w, steps, warmup, profile=True):
             U += [u[i].cpu().numpy() for i in range(p.nout)]
         else:
             U.append(u.cpu().numpy())
-    nt = (w["k"] + 1) * (len(w["alphas"]) if w.get("multi") else 1)
-    iters = [list(r.iters)[:nt] for r in reports[-len(plans):]]
-    outer = [list(r.outer)[:nt] for r in reports[-len(plans):]]
-    relres = [max(list(r.relres)[:nt]) for r in reports[-len(plans):]]
+    terms = [B.bura_plan_outputs(p.handle)[1][-1] for p in plans]   # shifted systems per plan and rhs
+    iters = [list(r.iters)[:nt] for r, nt in zip(reports[-len(plans):], terms)]
+    outer = [list(r.outer)[:nt] for r, nt in zip(reports[-len(plans):], terms)]
+    relres = [max(list(r.relres)[:nt]) for r, nt in zip(reports[-len(plans):], terms)]
     for p in plans:
         p.close()
     N = w["n"] ** w["dim"]
-    per_step = N * (w["k"] + 1) * w["nrhs"] * len(w["alphas"])
+    per_step = N * sum(terms) * w["nrhs"]
     return dict(elapsed=elapsed, per_step=per_step, lat=lat, kstats=kstats, lam=info[0], nlev=info[1],
                 dev_bytes=info[2], U=U, F=F_host, coeff=coeff, coefs=coefs, iters=iters, outer=outer,
                 relres=relres, t_plan=t_plan)
@@ -190,16 +207,19 @@ def counter_traffic(workload, kclass):
     return None
 
 
-def cpu_baseline(w, res):
-    """Oracle on the host: accuracy of the GPU results, and the timed CPU sample."""
-    import numpy as np
-
-    from oracle import metrics, operators, shifted, spectral
-    sys.path.insert(0, os.path.join(ROOT, "tests"))
+def oracle_errors(w, res):
+    """Relative l2 error of each GPU output against the oracle's result for the same terms."""
+    from oracle import metrics, operators, quadrature, shifted, spectral
     gold = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_bura_coefficients.json")))
     errs = []
-    t_acc = time.perf_counter()
-    for a, U in zip(w["alphas"], res["U"]):
+    for i, (a, U) in enumerate(zip(w["alphas"], res["U"])):
+        if w.get("method") == "sinc":
+            kp = quadrature.sinc_kprime(a, w["kq"][i])
+            if w["var"]:
+                raise ValueError("sinc workloads are constant-coefficient")
+            ref = quadrature.sinc_spectral(res["F"], w["dim"], a, kp, res["lam"])
+            errs.append(metrics.rel_err(U, ref))
+            continue
         rec = gold[f"{a:.2f},{w['k']}"]
         c = [float(x) for x in rec["c"]]
         d = [float(x) for x in rec["d"]]
@@ -212,6 +232,14 @@ def cpu_baseline(w, res):
             idx = [0, w["nrhs"] - 1]
             ref = shifted.bura_by_solves(A, c, d, res["F"][idx])
             errs.append(metrics.rel_err(U[idx], ref))
+    return errs
+
+
+def cpu_baseline(w, res):
+    """Oracle on the host: accuracy of the GPU results, and the timed CPU sample."""
+    from oracle import operators, shifted
+    t_acc = time.perf_counter()
+    errs = oracle_errors(w, res)
     t_acc = time.perf_counter() - t_acc
     # timed CPU sample: one full-size shifted system (pole d_0 = 0 of the first
     # alpha) by the oracle's sparse direct solve -- unknown-pole solves per second
@@ -223,7 +251,7 @@ def cpu_baseline(w, res):
         dt = time.perf_counter() - t0
         N = w["n"] ** w["dim"]
         sample = dict(value=N / dt, unit="unknown-pole solves/s", cores=1, kind="oracle",
-                      sample=f"one full-size shifted system (pole d_0=0, alpha={w['alphas'][0]}) of the same "
+                      sample=f"one full-size shifted system (shift 0, the pole d_0 = 0 of a BURA) of the same "
                              f"workload by SuperLU factorisation + solve, {dt:.1f} s, single-threaded; "
                              f"host has {os.cpu_count()} logical CPUs ({platform.processor() or 'x86_64'})")
     else:
@@ -310,7 +338,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=160.0)
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of this many GiB (counter calibration)")
-    ap.add_argument("--also", default="2d1023-k9-fp64-per-pole,2d1023-k9-fp64-batched,2d1023-k9-mixed-multi",
+    ap.add_argument("--also", default="2d1023-k9-fp64-per-pole,2d1023-k9-fp64-batched,2d1023-k9-mixed-multi,"
+                                      "2d1023-sinc-fp64-multi",
                     help="comma-separated extra workloads reported under 'paths' (empty: none)")
     args = ap.parse_args()
     if args.copy_probe > 0:
@@ -414,18 +443,9 @@ def main():
         accepted = max(errs) <= 1e-8
         out["cpu_baseline"] = sample
         for name, pth in paths.items():
-            e2, _, _ = cpu_baseline(pth["_w"], pth["_res"]) if False else (None, None, None)
-            if not pth["_w"]["var"]:
-                from oracle import metrics, spectral
-                gold = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_bura_coefficients.json")))
-                ee = []
-                for a, U in zip(pth["_w"]["alphas"], pth["_res"]["U"]):
-                    rec = gold[f"{a:.2f},{pth['_w']['k']}"]
-                    ref = spectral.bura_spectral(pth["_res"]["F"], pth["_w"]["dim"], [float(x) for x in rec["c"]],
-                                                 [float(x) for x in rec["d"]])
-                    ee.append(metrics.rel_err(U, ref))
-                pth["rel_err_vs_oracle"] = max(ee)
-                pth["value"] = pth["value_unchecked"] if max(ee) <= 1e-8 else 0.0
+            ee = oracle_errors(pth["_w"], pth["_res"])
+            pth["rel_err_vs_oracle"] = max(ee)
+            pth["value"] = pth["value_unchecked"] if max(ee) <= 1e-8 else 0.0
     else:
         out["rel_err_vs_oracle"] = None
         out["cpu_baseline"] = None

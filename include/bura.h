@@ -140,6 +140,37 @@ int bura_plan_create(const bura_grid_t* grid, double alpha, int beta, int k,
 int bura_plan_create_rational(const bura_grid_t* grid, int nterms, const double* weights,
                               const double* shifts, const bura_opts_t* opts, bura_plan_t* out);
 
+/* Several caller-given partial-fraction forms in one plan: output a uses the
+ * nterms[a] consecutive terms that follow those of outputs 0..a-1 in
+ * weights/shifts (sum_a nterms[a] <= BURA_MAX_TERMS).  All systems advance
+ * together; bura_solve writes nout * nrhs vectors, output a of right-hand side
+ * r at u_dev[a * nrhs + r]. */
+int bura_plan_create_rational_multi(const bura_grid_t* grid, int nout, const int* nterms, const double* weights,
+                                    const double* shifts, const bura_opts_t* opts, bura_plan_t* out);
+
+/* The sinc quadrature of Bonito and Pasciak that Section 5.3 compares against:
+ * for an SPD B,
+ *   B^-alpha ~= (2 k' sin(pi alpha)/pi) sum_{l=-m}^{M} e^{2(alpha-1) l k'} (e^{-2 l k'} I + B)^-1,
+ *   m = ceil(pi^2/(4 alpha k'^2)), M = ceil(pi^2/(4 (1-alpha) k'^2)),
+ * with step k' > 0 (Section 5.3 parametrises it by k_Q = pi^2/(4 alpha (1-alpha) k'^2)).
+ * Values of the two ceiling arguments within 1e-9 (relative) of an integer are
+ * taken as that integer.  The rule is applied to B = scale * A and returned as
+ * weights/shifts for A that approximate A^-alpha itself:
+ *   weights[l+m] = scale^(alpha-1) (2k' sin(pi alpha)/pi) e^{2(alpha-1) l k'},
+ *   shifts[l+m]  = e^{-2 l k'} / scale,   l = -m..M (shifts decreasing).
+ * *nterms receives m+M+1 even when it exceeds max_terms (then BURA_EINVAL and
+ * nothing is written).  Host-only; alpha in (0,1), k' > 0, scale > 0. */
+int bura_sinc_coefficients(double alpha, double kprime, double scale, int max_terms, double* weights,
+                           double* shifts, int* nterms);
+
+/* A plan for the sinc quadrature, one output per (alphas[a], kprimes[a]).
+ * As in Section 5.3's comparison the rule is applied to the unscaled operator
+ * Lambda * A (scale = the plan's spectral bound Lambda, see bura_plan_info), and
+ * the result is multiplied by Lambda^alpha, so that output a approximates the
+ * same A^-alpha f as a BURA plan.  Total terms <= BURA_MAX_TERMS; E is 0. */
+int bura_plan_create_sinc(const bura_grid_t* grid, int nalpha, const double* alphas, const double* kprimes,
+                          const bura_opts_t* opts, bura_plan_t* out);
+
 /* Several fractional powers of the same operator in one plan: alpha[a] with
  * ks[a] poles each (a < nalpha, sum_a (ks[a]+1) <= BURA_MAX_TERMS).  All
  * shifted systems of all outputs advance together; bura_solve then writes

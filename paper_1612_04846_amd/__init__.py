@@ -10,6 +10,7 @@ been built this module raises on import -- there is no fallback path.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from dataclasses import dataclass
 from typing import Optional, Sequence
@@ -124,6 +125,11 @@ _SIGS = {
                                        ctypes.POINTER(_P)]),
     "bura_plan_create_multi": (_I, [ctypes.POINTER(bura_grid_t), _I, _DP, _I, ctypes.POINTER(_I),
                                     ctypes.POINTER(bura_opts_t), ctypes.POINTER(_P)]),
+    "bura_plan_create_rational_multi": (_I, [ctypes.POINTER(bura_grid_t), _I, ctypes.POINTER(_I), _DP, _DP,
+                                             ctypes.POINTER(bura_opts_t), ctypes.POINTER(_P)]),
+    "bura_sinc_coefficients": (_I, [_D, _D, _D, _I, _DP, _DP, ctypes.POINTER(_I)]),
+    "bura_plan_create_sinc": (_I, [ctypes.POINTER(bura_grid_t), _I, _DP, _DP, ctypes.POINTER(bura_opts_t),
+                                   ctypes.POINTER(_P)]),
     "bura_plan_outputs": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "bura_solve": (_I, [_P, _P, _P, _I, ctypes.POINTER(bura_report_t)]),
     "bura_submit": (_I, [_P, _P, _P, _I]),
@@ -258,6 +264,53 @@ def bura_plan_create_rational(dim: int, n: int, weights: Sequence[float], shifts
     return h
 
 
+def bura_plan_create_rational_multi(dim: int, n: int, nterms: Sequence[int], weights: Sequence[float],
+                                    shifts: Sequence[float], opts: Optional[bura_opts_t] = None, coeff=None,
+                                    lambda_upper: float = 0.0):
+    g, _keep = _grid(dim, n, coeff, lambda_upper)
+    o = opts if opts is not None else bura_opts_default()
+    m = len(weights)
+    nt = (ctypes.c_int * len(nterms))(*nterms)
+    w = (ctypes.c_double * m)(*weights)
+    s = (ctypes.c_double * m)(*shifts)
+    h = _P()
+    _check(_lib.bura_plan_create_rational_multi(ctypes.byref(g), len(nterms), nt, w, s, ctypes.byref(o),
+                                                ctypes.byref(h)), "bura_plan_create_rational_multi")
+    return h
+
+
+def sinc_kprime(alpha: float, kq: float) -> float:
+    """The quadrature step k' for a nominal number of systems k_Q = pi^2/(4 alpha (1-alpha) k'^2)."""
+    return math.pi / (2.0 * math.sqrt(alpha * (1.0 - alpha) * kq))
+
+
+def bura_sinc_coefficients(alpha: float, kprime: float, scale: float = 1.0):
+    """(weights, shifts) of the sinc quadrature applied to scale * A, for A (host only)."""
+    cnt = ctypes.c_int()
+    w = (ctypes.c_double * BURA_MAX_TERMS)()
+    s = (ctypes.c_double * BURA_MAX_TERMS)()
+    code = _lib.bura_sinc_coefficients(alpha, kprime, scale, BURA_MAX_TERMS, w, s, ctypes.byref(cnt))
+    if code == BURA_EINVAL and cnt.value > BURA_MAX_TERMS:
+        w = (ctypes.c_double * cnt.value)()
+        s = (ctypes.c_double * cnt.value)()
+        code = _lib.bura_sinc_coefficients(alpha, kprime, scale, cnt.value, w, s, ctypes.byref(cnt))
+    _check(code, "bura_sinc_coefficients")
+    return list(w)[: cnt.value], list(s)[: cnt.value]
+
+
+def bura_plan_create_sinc(dim: int, n: int, alphas: Sequence[float], kprimes: Sequence[float],
+                          opts: Optional[bura_opts_t] = None, coeff=None, lambda_upper: float = 0.0):
+    g, _keep = _grid(dim, n, coeff, lambda_upper)
+    o = opts if opts is not None else bura_opts_default()
+    m = len(alphas)
+    a = (ctypes.c_double * m)(*alphas)
+    kp = (ctypes.c_double * m)(*kprimes)
+    h = _P()
+    _check(_lib.bura_plan_create_sinc(ctypes.byref(g), m, a, kp, ctypes.byref(o), ctypes.byref(h)),
+           "bura_plan_create_sinc")
+    return h
+
+
 def _devptr(t: torch.Tensor, what: str):
     if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
         raise ValueError(f"{what} must be a contiguous float64 CUDA tensor")
@@ -340,16 +393,28 @@ class SolveResult:
 class Plan:
     """Owns a plan handle; ``solve(f)`` returns A^-alpha f for a batch f of shape (nrhs, n, ..., n)."""
 
-    def __init__(self, dim, n, alpha=None, k=None, *, weights=None, shifts=None, coeff=None,
-                 precision=BURA_MIXED, schedule=BURA_BATCHED, tol=1e-12, nrhs_max=1, stream=None, **opt):
+    def __init__(self, dim, n, alpha=None, k=None, *, weights=None, shifts=None, nterms=None, kprime=None,
+                 coeff=None, precision=BURA_MIXED, schedule=BURA_BATCHED, tol=1e-12, nrhs_max=1, stream=None,
+                 **opt):
+        """alpha (one value or a list) with k poles: the BURA; alpha with kprime
+        (one value or lists): the sinc quadrature of step k'; weights/shifts
+        (with nterms per output for several outputs): a caller-given form."""
         self.dim, self.n = dim, n
         o = bura_opts_default(precision=precision, schedule=schedule, tol=tol, nrhs_max=nrhs_max, **opt)
         o.stream = _stream_ptr(stream).value if torch.cuda.is_available() else None
         self.opts = o
         self.handle = None
         self.nout = 1
-        if weights is not None:
+        if weights is not None and nterms is not None:
+            self.handle = bura_plan_create_rational_multi(dim, n, nterms, weights, shifts, o, coeff=coeff)
+            self.nout = len(nterms)
+        elif weights is not None:
             self.handle = bura_plan_create_rational(dim, n, weights, shifts, o, coeff=coeff)
+        elif kprime is not None:
+            al = list(alpha) if isinstance(alpha, (list, tuple)) else [alpha]
+            kp = list(kprime) if isinstance(kprime, (list, tuple)) else [kprime] * len(al)
+            self.handle = bura_plan_create_sinc(dim, n, al, kp, o, coeff=coeff)
+            self.nout = len(al) if isinstance(alpha, (list, tuple)) else 1
         elif isinstance(alpha, (list, tuple)):
             ks = list(k) if isinstance(k, (list, tuple)) else [k] * len(alpha)
             self.handle = bura_plan_create_multi(dim, n, list(alpha), ks, o, coeff=coeff)

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbura.so")
 HIP_SOURCES = ["bura_kernels.hip", "bura_engine.cpp", "bura_server.cpp"]
-HOST_SOURCES = ["bura_remez.cpp"]   # plain C++ (uses __float128), built by g++
+HOST_SOURCES = ["bura_remez.cpp", "bura_sinc.cpp"]   # plain C++ (Remez in __float128; quadrature), built by g++
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -905,10 +906,34 @@ int validate_opts(const bura_opts_t* o) {
   return BURA_OK;
 }
 
-int create(const bura_grid_t* g, int nterms, const double* w, const double* s, double E,
-           const bura_opts_t* opts_in, bura_plan_t* out, int nout = 1, const int* out_begin = nullptr) {
+// The partial-fraction terms of a plan, u_a = sum_{j in output a} w_j (A + s_j I)^-1 f.
+struct Terms {
+  std::vector<double> w, s;
+  std::vector<int> begin{0};   // first term of each output
+  double E = 0.0;
+};
+
+int check_terms(const Terms& t) {
+  const int nterms = (int)t.w.size();
+  if (nterms < 1 || nterms > BURA_MAX_TERMS || t.s.size() != t.w.size() || t.begin.empty()) return BURA_EINVAL;
+  for (size_t a = 0; a < t.begin.size(); ++a) {
+    const int e = a + 1 < t.begin.size() ? t.begin[a + 1] : nterms;
+    if (t.begin[a] < 0 || t.begin[a] >= e || (a == 0 && t.begin[0] != 0)) return BURA_EINVAL;
+  }
+  for (int j = 0; j < nterms; ++j)
+    if (!(t.s[j] >= 0.0) || !std::isfinite(t.w[j]) || !std::isfinite(t.s[j])) return BURA_EINVAL;
+  return BURA_OK;
+}
+
+// Terms that depend on the plan's spectral bound Lambda (known after the
+// operator is built) are produced by `late`.
+using LateTerms = std::function<int(double lambda, Terms& t)>;
+
+int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_plan_t* out,
+           const LateTerms& late = LateTerms()) {
   if (out) *out = nullptr;
-  if (!g || !out || !w || !s || nterms < 1 || nterms > BURA_MAX_TERMS) return BURA_EINVAL;
+  if (!g || !out) return BURA_EINVAL;
+  if (!late && check_terms(terms)) return BURA_EINVAL;
   if (g->dim != 2 && g->dim != 3) return BURA_EINVAL;
   if (g->n < 1) return BURA_EINVAL;
   long long N = 1;
@@ -918,8 +943,6 @@ int create(const bura_grid_t* g, int nterms, const double* w, const double* s, d
   if (opts_in) o = *opts_in;
   else bura_opts_default(&o);
   if (validate_opts(&o)) return BURA_EINVAL;
-  for (int j = 0; j < nterms; ++j)
-    if (!(s[j] >= 0.0) || !std::isfinite(w[j]) || !std::isfinite(s[j])) return BURA_EINVAL;
   if (g->coeff) {
     const long long m = (long long)(g->n + 2);
     long long cnt = g->dim == 2 ? m * m : m * m * m;
@@ -931,15 +954,6 @@ int create(const bura_grid_t* g, int nterms, const double* w, const double* s, d
   P->n = g->n;
   P->N = N;
   P->var = g->coeff != nullptr;
-  P->nterms = nterms;
-  P->w.assign(w, w + nterms);
-  P->s.assign(s, s + nterms);
-  P->nout = nout;
-  for (int i = 0; i < nout; ++i) {
-    P->out_begin.push_back(out_begin ? out_begin[i] : 0);
-    P->out_end.push_back(out_begin && i + 1 < nout ? out_begin[i + 1] : nterms);
-  }
-  P->E = E;
   P->opts = o;
   P->user_stream = (hipStream_t)o.stream;
   {
@@ -951,13 +965,26 @@ int create(const bura_grid_t* g, int nterms, const double* w, const double* s, d
     const char* ef = std::getenv("BURA_FOLD");
     P->fold = ef && ef[0] == '1';
   }
-  P->S = nterms * o.nrhs_max;
   {
     const char* ev = std::getenv("BURA_UNFUSED");
     P->unfused = ev && ev[0] == '1';
   }
   int rc = build_levels(P, g);
   if (rc) { delete P; return rc; }
+  if (late) {
+    if ((rc = late(P->lambda, terms)) || (rc = check_terms(terms))) { delete P; return rc ? rc : BURA_EINVAL; }
+  }
+  const int nterms = (int)terms.w.size();
+  P->nterms = nterms;
+  P->w = terms.w;
+  P->s = terms.s;
+  P->nout = (int)terms.begin.size();
+  for (int i = 0; i < P->nout; ++i) {
+    P->out_begin.push_back(terms.begin[i]);
+    P->out_end.push_back(i + 1 < P->nout ? terms.begin[i + 1] : nterms);
+  }
+  P->E = terms.E;
+  P->S = nterms * o.nrhs_max;
   const bool mixed = o.precision == BURA_MIXED;
   choose_lds(P, mixed ? 4 : 8);
   if (P->opts.max_iter == 0) {
@@ -1055,7 +1082,58 @@ int bura_opts_default(bura_opts_t* o) {
 
 int bura_plan_create_rational(const bura_grid_t* grid, int nterms, const double* weights, const double* shifts,
                               const bura_opts_t* opts, bura_plan_t* out) {
-  return create(grid, nterms, weights, shifts, 0.0, opts, out);
+  if (out) *out = nullptr;
+  if (!weights || !shifts || nterms < 1 || nterms > BURA_MAX_TERMS) return BURA_EINVAL;
+  Terms t;
+  t.w.assign(weights, weights + nterms);
+  t.s.assign(shifts, shifts + nterms);
+  return create(grid, t, opts, out);
+}
+
+int bura_plan_create_rational_multi(const bura_grid_t* grid, int nout, const int* nterms, const double* weights,
+                                    const double* shifts, const bura_opts_t* opts, bura_plan_t* out) {
+  if (out) *out = nullptr;
+  if (!nterms || !weights || !shifts || nout < 1 || nout > BURA_MAX_TERMS) return BURA_EINVAL;
+  Terms t;
+  t.begin.clear();
+  int total = 0;
+  for (int a = 0; a < nout; ++a) {
+    if (nterms[a] < 1 || total + nterms[a] > BURA_MAX_TERMS) return BURA_EINVAL;
+    t.begin.push_back(total);
+    total += nterms[a];
+  }
+  t.w.assign(weights, weights + total);
+  t.s.assign(shifts, shifts + total);
+  return create(grid, t, opts, out);
+}
+
+int bura_plan_create_sinc(const bura_grid_t* grid, int nalpha, const double* alphas, const double* kprimes,
+                          const bura_opts_t* opts, bura_plan_t* out) {
+  if (out) *out = nullptr;
+  if (!alphas || !kprimes || nalpha < 1 || nalpha > BURA_MAX_TERMS) return BURA_EINVAL;
+  for (int a = 0; a < nalpha; ++a) {
+    int cnt = 0;
+    // validate and count before the operator is built
+    const int rc = bura_sinc_coefficients(alphas[a], kprimes[a], 1.0, 0, nullptr, nullptr, &cnt);
+    if (rc != BURA_OK && cnt == 0) return rc;
+  }
+  std::vector<double> al(alphas, alphas + nalpha), kp(kprimes, kprimes + nalpha);
+  LateTerms late = [al, kp](double lambda, Terms& t) -> int {
+    t.w.clear();
+    t.s.clear();
+    t.begin.clear();
+    for (size_t a = 0; a < al.size(); ++a) {
+      double w[BURA_MAX_TERMS], s[BURA_MAX_TERMS];
+      int cnt = 0;
+      const int rc = bura_sinc_coefficients(al[a], kp[a], lambda, BURA_MAX_TERMS - (int)t.w.size(), w, s, &cnt);
+      if (rc) return rc;
+      t.begin.push_back((int)t.w.size());
+      t.w.insert(t.w.end(), w, w + cnt);
+      t.s.insert(t.s.end(), s, s + cnt);
+    }
+    return BURA_OK;
+  };
+  return create(grid, Terms(), opts, out, late);
 }
 
 int bura_plan_create_multi(const bura_grid_t* grid, int nalpha, const double* alphas, int beta, const int* ks,
@@ -1081,7 +1159,12 @@ int bura_plan_create_multi(const bura_grid_t* grid, int nalpha, const double* al
     E = std::max(E, Ea);
   }
   if ((int)c.size() > BURA_MAX_TERMS) return BURA_EINVAL;
-  return create(grid, (int)c.size(), c.data(), s.data(), E, opts, out, nalpha, begin.data());
+  Terms t;
+  t.w = c;
+  t.s = s;
+  t.begin = begin;
+  t.E = E;
+  return create(grid, t, opts, out);
 }
 
 int bura_plan_create(const bura_grid_t* grid, double alpha, int beta, int k, const bura_opts_t* opts,
@@ -1095,7 +1178,11 @@ int bura_plan_create(const bura_grid_t* grid, double alpha, int beta, int k, con
   if (rc) return rc;
   std::vector<double> s(k + 1);
   for (int j = 0; j <= k; ++j) s[j] = -d[j];
-  return create(grid, k + 1, c.data(), s.data(), E, opts, out);
+  Terms t;
+  t.w = c;
+  t.s = s;
+  t.E = E;
+  return create(grid, t, opts, out);
 }
 
 int bura_solve(bura_plan_t plan, const double* f_dev, double* u_dev, int nrhs, bura_report_t* rep) {
