@@ -55,6 +55,7 @@ struct Work {
   T* p = nullptr;
   T* p2 = nullptr;  // p ping-pong partner (p_new = z + beta p_old is written to the other buffer)
   T* q = nullptr;
+  T* r2 = nullptr;  // r ping-pong partner when the residual update is folded into the down kernel
   std::vector<T*> xl, tl, bl;   // levels 1..lc (index by level)
   T* shift = nullptr;
 };
@@ -90,6 +91,10 @@ struct bura_plan_s {
   std::vector<HostLevel> lev;
   int lc = -1;                 // first level solved in LDS; -1: no multigrid (Jacobi PCG)
   bool unfused = false;        // force the one-kernel-per-step V-cycle (BURA_UNFUSED=1)
+  // PCG vector updates folded into the fused kernels: x += alpha p deferred to the
+  // next stencil-product pass, r -= alpha q done by the fine down kernel into a
+  // second residual buffer (off with BURA_NO_FOLDXR=1)
+  bool foldxr = false;
   size_t lds_bytes = 0;
   int S = 0;                   // systems = nterms * nrhs_max
   // device buffers
@@ -451,6 +456,10 @@ int alloc_work(bura_plan_t P, Work<T>& W) {
   if ((rc = dev_alloc(P, (void**)&W.p, vb))) return rc;
   if ((rc = dev_alloc(P, (void**)&W.p2, vb))) return rc;
   if ((rc = dev_alloc(P, (void**)&W.q, vb))) return rc;
+  if (P->foldxr) {
+    if ((rc = dev_alloc(P, (void**)&W.r2, vb))) return rc;
+    HIPCHK(hipMemsetAsync(W.r2, 0, vb, P->stream));
+  }
   const int L = (int)P->lev.size();
   W.xl.assign(L, nullptr);
   W.tl.assign(L, nullptr);
@@ -476,11 +485,12 @@ int alloc_work(bura_plan_t P, Work<T>& W) {
 
 size_t footprint(const bura_plan_t P, size_t elem, bool mixed) {
   const size_t S = (size_t)P->S;
-  size_t t = 7 * S * (size_t)P->N * elem;
+  size_t t = (P->foldxr ? 8 : 7) * S * (size_t)P->N * elem;
   if (P->lc > 0)
     for (int l = 1; l <= P->lc; ++l) t += 3 * S * (size_t)P->lev[l].N * elem;
   if (mixed) t += S * (size_t)P->N * 8;
-  size_t maxblk = (size_t)std::max(stencil_blocks(P->dim, P->n), flat_blocks(P->N));
+  size_t maxblk = (size_t)std::max({stencil_blocks(P->dim, P->n), flat_blocks(P->N), up_blocks(P->dim, P->n),
+                                    down_blocks(P->dim, P->n)});
   t += S * maxblk * 8;
   for (const auto& L : P->lev)
     for (int a = 0; a < P->dim; ++a) t += L.wf[a].size() * 12;
@@ -514,9 +524,23 @@ bool fused_ok(const bura_plan_t P) {
          P->opts.nu_post <= 3 && !P->unfused;
 }
 
+// The PCG residual update folded into the fine down kernel: r_new = r_old -
+// alpha q is formed while staging, written to rnew (a different buffer) with
+// its squared norm; `after` runs once that kernel is queued (the convergence
+// test on |r_new|).
+template <typename T>
+struct ResidUpdate {
+  const T* rold;
+  T* rnew;
+  const T* q;
+  const double* alpha;
+  Fin fin;
+  std::function<void()> after;
+};
+
 template <typename T>
 void precondition(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, const int* active, double* partial,
-                  Fin fin = Fin()) {
+                  Fin fin = Fin(), const ResidUpdate<T>* ru = nullptr) {
   hipStream_t st = P->stream;
   const int dim = P->dim;
   const bool var = P->var;
@@ -538,11 +562,19 @@ void precondition(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, const int* a
     // writes the final iterate into B_l (B_0 = z).
     auto A = [&](int l) { return l == 0 ? off(W.zt, 0) : off(W.tl[l], l); };
     auto Bv = [&](int l) { return l == 0 ? off(W.z, 0) : off(W.xl[l], l); };
-    auto bl = [&](int l) { return l == 0 ? off(W.r, 0) : off(W.bl[l], l); };
+    auto bl = [&](int l) { return l == 0 ? (ru ? ru->rnew : off(W.r, 0)) : off(W.bl[l], l); };
     for (int l = 0; l < lc; ++l) {
-      ProfScope ps(P, l == 0 ? BURA_K_DOWN_FINE : BURA_K_SMOOTH_COARSE);
-      Launch<T>::fused_down(dim, var, nu1, level_view<T>(P, l), level_view<T>(P, l + 1), bl(l), A(l), bl(l + 1),
-                            shift, active, omega, nsys, st, ps.ctr);
+      {
+        ProfScope ps(P, l == 0 ? BURA_K_DOWN_FINE : BURA_K_SMOOTH_COARSE);
+        if (l == 0 && ru)
+          Launch<T>::fused_down(dim, var, nu1, level_view<T>(P, 0), level_view<T>(P, 1), ru->rold, A(0), bl(1),
+                                shift, active, omega, nsys, st, ps.ctr, ru->q, ru->alpha, ru->rnew, partial,
+                                ru->fin);
+        else
+          Launch<T>::fused_down(dim, var, nu1, level_view<T>(P, l), level_view<T>(P, l + 1), bl(l), A(l),
+                                bl(l + 1), shift, active, omega, nsys, st, ps.ctr);
+      }
+      if (l == 0 && ru && ru->after) ru->after();
     }
     {
       ProfScope ps(P, BURA_K_COARSE_LDS);
@@ -661,22 +693,33 @@ int run_pcg(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, double tol, int ma
     f.max_iter = max_iter;
     return f;
   };
-  auto body = [&](T* po, T* pn) {
+  const bool fx = P->foldxr;
+  const int nb_down = down_blocks(dim, P->n);
+  auto body = [&](T* po, T* pn, T* ro, T* rn) {
     {
       ProfScope ps(P, BURA_K_SPMV);
       Launch<T>::spmv_p(dim, P->var, L0, W.z + o, po, pn, W.q + o, S.beta, W.shift + sys0, S.active, part, nsys, st,
-                        ps.ctr, fin(OP_ALPHA));
+                        ps.ctr, fin(OP_ALPHA), fx ? W.x + o : nullptr, S.alpha);
     }
     if (!P->fold) scal(OP_ALPHA, nb_tile);
-    {
-      ProfScope ps(P, BURA_K_UPDATE_XR);
-      Launch<T>::update_xr(L0, dim, W.x + o, W.r + o, pn, W.q + o, S.alpha, S.active, part, nsys, st, ps.ctr,
-                           fin(OP_RESID));
+    if (fx) {
+      ResidUpdate<T> ru{ro, rn, W.q + o, S.alpha, fin(OP_RESID), [&]() {
+                          if (!P->fold) scal(OP_RESID, nb_down);
+                        }};
+      precondition<T>(P, W, sys0, nsys, S.active, part, fin(OP_BETA), &ru);
+    } else {
+      {
+        ProfScope ps(P, BURA_K_UPDATE_XR);
+        Launch<T>::update_xr(L0, dim, W.x + o, W.r + o, pn, W.q + o, S.alpha, S.active, part, nsys, st, ps.ctr,
+                             fin(OP_RESID));
+      }
+      if (!P->fold) scal(OP_RESID, nb_flat);
+      precondition<T>(P, W, sys0, nsys, S.active, part, fin(OP_BETA));
     }
-    if (!P->fold) scal(OP_RESID, nb_flat);
-    precondition<T>(P, W, sys0, nsys, S.active, part, fin(OP_BETA));
     if (!P->fold) scal(OP_BETA, rz_blocks(P));
   };
+  T* rold = W.r + o;
+  T* rnew = fx ? W.r2 + o : W.r + o;
   precondition<T>(P, W, sys0, nsys, S.active, part, fin(OP_BETA));
   if (!P->fold) scal(OP_BETA, rz_blocks(P));
   // chunks of an even number of iterations, so p_old is W.p at every chunk start
@@ -701,9 +744,12 @@ int run_pcg(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, double tol, int ma
       if (ok) {
         T* a = pold;
         T* b = pnew;
+        T* ra = rold;
+        T* rb = rnew;
         for (int c = 0; c < chunk; ++c) {
-          body(a, b);
+          body(a, b, ra, rb);
           std::swap(a, b);
+          std::swap(ra, rb);
         }
         ok = hipStreamEndCapture(st, &graph) == hipSuccess && graph != nullptr && !P->capture_failed;
       }
@@ -729,9 +775,12 @@ int run_pcg(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, double tol, int ma
     } else {
       T* a = pold;
       T* b = pnew;
+      T* ra = rold;
+      T* rb = rnew;
       for (int c = 0; c < chunk; ++c) {
-        body(a, b);
+        body(a, b, ra, rb);
         std::swap(a, b);
+        std::swap(ra, rb);
       }
     }
     const int a = count_active(P, P->st.active, sys0, nsys);
@@ -741,6 +790,11 @@ int run_pcg(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, double tol, int ma
     }
     if (g) prof_graph(P, *g);
     if (a == 0) break;
+  }
+  if (fx) {
+    // the iterate update of each system's last iteration is still pending
+    ProfScope ps(P, BURA_K_UPDATE_XR);
+    Launch<T>::finish_x(P->N, W.x + o, W.p + o, W.p2 + o, S.alpha, S.iters, nsys, st, ps.ctr);
   }
   HIPCHK(hipGetLastError());
   return BURA_OK;
@@ -759,6 +813,9 @@ int solve_batch_fp64(bura_plan_t P, const double* f, int nrhs, size_t sys0, int 
   const SysState S = state_at(P, sys0);
   int rc;
   if (!preset && (rc = set_flags(P, P->st.active, sys0, nsys, 1))) return rc;
+  // no deferred iterate update pending on any system of the batch (slots that
+  // stay inactive keep alpha = 0, so the final update skips them)
+  launch_zero(S.alpha, (size_t)nsys * sizeof(double), st);
   {
     ProfScope ps(P, BURA_K_OTHER);
     Launch<double>::copy_rhs(L0, P->dim, f, W.r + o, W.x + o, nrhs, S.active, P->partial, nsys, st);
@@ -785,6 +842,7 @@ int solve_batch_mixed(bura_plan_t P, const double* f, int nrhs, size_t sys0, int
     HIPCHK(hipMemcpyAsync(P->st.active + sys0, P->st.active64 + sys0, nsys * sizeof(int), hipMemcpyDeviceToDevice,
                           P->stream));
   }
+  launch_zero(S.alpha, (size_t)nsys * sizeof(double), st);   // see solve_batch_fp64
   {
     ProfScope ps(P, BURA_K_RESIDUAL64);
     launch_residual64(P->dim, P->var, L0, f, P->x64 + o, W.x + o, W.r + o, P->d_shift64 + sys0, S.active64,
@@ -987,6 +1045,10 @@ int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_p
   P->S = nterms * o.nrhs_max;
   const bool mixed = o.precision == BURA_MIXED;
   choose_lds(P, mixed ? 4 : 8);
+  {
+    const char* ev = std::getenv("BURA_NO_FOLDXR");
+    P->foldxr = fused_ok(P) && !(ev && ev[0] == '1');
+  }
   if (P->opts.max_iter == 0) {
     // automatic cap: multigrid-PCG needs O(1) iterations per digit; Jacobi-PCG
     // (no hierarchy) needs O(sqrt(kappa)) = O(n) per digit
@@ -1017,7 +1079,8 @@ int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_p
         hipStreamSynchronize(P->stream) != hipSuccess)
       return fail(BURA_EDEVICE);
   }
-  const size_t maxblk = (size_t)std::max({stencil_blocks(P->dim, P->n), flat_blocks(P->N), up_blocks(P->dim, P->n)});
+  const size_t maxblk = (size_t)std::max({stencil_blocks(P->dim, P->n), flat_blocks(P->N), up_blocks(P->dim, P->n),
+                                          down_blocks(P->dim, P->n)});
   P->partial_len = (size_t)P->S * maxblk;
   if ((rc = dev_alloc(P, (void**)&P->partial, P->partial_len * 8))) return fail(rc);
   if ((rc = dev_alloc(P, (void**)&P->d_w, nterms * 8))) return fail(rc);

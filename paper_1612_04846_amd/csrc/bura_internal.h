@@ -96,13 +96,22 @@ struct Launch {
                         unsigned long long* ctr, Fin fin = Fin());
   static void update_p(const LevelDev<T>& L, int dim, T* p, const T* z, const double* beta,
                        const int* active, int nsys, hipStream_t st, unsigned long long* ctr);
+  // p_new = z + beta p_old, q = (A+s) p_new, p_new.q; with x != nullptr also the
+  // deferred x += alpha p_old of the previous iteration
   static void spmv_p(int dim, bool var, const LevelDev<T>& L, const T* z, const T* pold, T* pnew, T* q,
                      const double* beta, const T* shift, const int* active, double* partial, int nsys,
-                     hipStream_t st, unsigned long long* ctr, Fin fin = Fin());
-  // fused level kernels (2D); return false when not applicable
+                     hipStream_t st, unsigned long long* ctr, Fin fin = Fin(), T* x = nullptr,
+                     const double* alpha = nullptr);
+  // the last deferred x += alpha p of each system (see k_finish_x)
+  static void finish_x(long long N, T* x, const T* pa, const T* pb, const double* alpha, const int* iters,
+                       int nsys, hipStream_t st, unsigned long long* ctr);
+  // fused level kernels (2D); return false when not applicable.  With bout !=
+  // nullptr the down kernel first forms b - alpha q, writes it to bout and its
+  // squared norm to partial.
   static bool fused_down(int dim, bool var, int nu, const LevelDev<T>& Lf, const LevelDev<T>& Lc, const T* b,
                          T* xout, T* bc, const T* shift, const int* active, T omega, int nsys, hipStream_t st,
-                         unsigned long long* ctr);
+                         unsigned long long* ctr, const T* q = nullptr, const double* alpha = nullptr,
+                         T* bout = nullptr, double* partial = nullptr, Fin fin = Fin());
   static bool fused_up(int dim, bool var, int nu, const LevelDev<T>& Lc, const LevelDev<T>& Lf, const T* xc,
                        const T* xin, const T* b, T* xout, const T* shift, const int* active, T omega,
                        double* partial, int nsys, hipStream_t st, unsigned long long* ctr, Fin fin = Fin());
@@ -129,5 +138,6 @@ void launch_slot_flags(int* p, int nterms, int R, int nrhs, hipStream_t st);
 int stencil_blocks(int dim, int n);   // blocks per system of a stencil launch (tile grid)
 int flat_blocks(long long N);        // blocks per system of an element-wise launch
 int up_blocks(int dim, int n);       // blocks per system of the fused up kernel
+int down_blocks(int dim, int n);     // blocks per system of the fused down kernel (fine level n)
 
 }  // namespace bura

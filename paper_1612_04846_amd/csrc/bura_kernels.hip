@@ -5,8 +5,8 @@
 // the coarse levels, the PCG vector updates with FP64 block reductions, the
 // FP64 residual of the refinement loop and the FP64 combine of eq. (16).
 //
-// Every launch processes a batch of independent systems: blockIdx.z (stencils)
-// or blockIdx.y (flat kernels) selects the system; a system whose `active` flag
+// Every launch processes a batch of independent systems: blockIdx.z (stencil
+// launches) or blockIdx.y (flat kernels) selects the system; a system whose `active` flag
 // is 0 is skipped by whole blocks.  Reductions are deterministic: each block
 // writes one FP64 partial per system and a per-system kernel adds the partials
 // in a fixed order, so a system's result does not depend on what else is in
@@ -21,11 +21,30 @@ namespace bura {
 // small helpers
 // --------------------------------------------------------------------------
 
+// Tile coordinates of a stencil workgroup: (x tile, y tile, system), in launch
+// order.  Workgroups are dealt to the 8 XCDs round-robin, so vertically
+// adjacent tiles sit on different L2s and their common halo rows are fetched
+// twice; those second fetches hit the on-package last-level cache.  Renumbering
+// the workgroups so that an XCD takes contiguous tiles removed them but made
+// every stencil kernel slower (it concentrates each XCD on one address range),
+// so launch order is kept.
+struct Tile {
+  int x, y, z;
+};
+
+__device__ __forceinline__ Tile block_tile() {
+  Tile r;
+  r.x = blockIdx.x;
+  r.y = blockIdx.y;
+  r.z = blockIdx.z;
+  return r;
+}
+
 template <int DIM>
-__device__ __forceinline__ void tile_ijk(int n, int& i, int& j, int& k) {
-  i = blockIdx.x * kTileX + threadIdx.x;
+__device__ __forceinline__ void tile_ijk(const Tile& tl, int n, int& i, int& j, int& k) {
+  i = tl.x * kTileX + threadIdx.x;
   const int ytiles = (n + kTileY - 1) / kTileY;
-  int by = blockIdx.y;
+  int by = tl.y;
   if (DIM == 3) {
     k = by / ytiles;
     by -= k * ytiles;
@@ -58,8 +77,8 @@ __device__ __forceinline__ void write_partial(double* partial, int sys, double v
   if (tid == 0) partial[(size_t)sys * nblk + blk] = s;
 }
 
-__device__ __forceinline__ void write_partial_tile(double* partial, int sys, double v) {
-  write_partial(partial, sys, v, blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+__device__ __forceinline__ void write_partial_tile(const Tile& tl, double* partial, int sys, double v) {
+  write_partial(partial, sys, v, tl.y * gridDim.x + tl.x, gridDim.x * gridDim.y);
 }
 
 __device__ __forceinline__ void write_partial_flat(double* partial, int sys, double v) {
@@ -106,23 +125,32 @@ __device__ __forceinline__ void count_bytes(unsigned long long* ctr, unsigned lo
   if (first) atomicAdd(ctr, b);
 }
 
+// stencil launches: the workgroup holding tile (0, 0) of the system counts
+__device__ __forceinline__ void count_bytes_tile(const Tile& tl, unsigned long long* ctr, unsigned long long b) {
+  if (ctr == nullptr || threadIdx.x != 0 || threadIdx.y != 0) return;
+  if (tl.x == 0 && tl.y == 0) atomicAdd(ctr, b);
+}
+
 // (A_l + s I) x at interior point (i,j,k), flux form sum_f w_f (x_c - x_nb) + s x_c.
 // Also returns the diagonal through *dg when dg != nullptr.
 template <typename T, int DIM, bool VAR>
 __device__ __forceinline__ T apply_pt(const LevelDev<T>& L, const T* __restrict__ x, int i, int j, int k,
                                       long long p, T s, T* dg) {
   const int n = L.n;
-  const T xc = x[p];
-  const T xl = i > 0 ? x[p - 1] : T(0);
-  const T xr = i < n - 1 ? x[p + 1] : T(0);
-  const T xd = j > 0 ? x[p - n] : T(0);
-  const T xu = j < n - 1 ? x[p + n] : T(0);
   const long long nn = (long long)n * n;
-  T xb = T(0), xf = T(0);
+  // neighbour loads are unconditional (a boundary neighbour reads the centre
+  // instead) so that they are all in flight together; the value is selected after
+  const T xc = x[p];
+  const T xl0 = x[i > 0 ? p - 1 : p], xr0 = x[i < n - 1 ? p + 1 : p];
+  const T xd0 = x[j > 0 ? p - n : p], xu0 = x[j < n - 1 ? p + n : p];
+  T xb0 = T(0), xf0 = T(0);
   if (DIM == 3) {
-    xb = k > 0 ? x[p - nn] : T(0);
-    xf = k < n - 1 ? x[p + nn] : T(0);
+    xb0 = x[k > 0 ? p - nn : p];
+    xf0 = x[k < n - 1 ? p + nn : p];
   }
+  const T xl = i > 0 ? xl0 : T(0), xr = i < n - 1 ? xr0 : T(0);
+  const T xd = j > 0 ? xd0 : T(0), xu = j < n - 1 ? xu0 : T(0);
+  const T xb = DIM == 3 && k > 0 ? xb0 : T(0), xf = DIM == 3 && k < n - 1 ? xf0 : T(0);
   if (!VAR) {
     const T w = L.wc;
     T sum = (xc - xl) + (xc - xr) + (xc - xd) + (xc - xu);
@@ -171,16 +199,17 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(LevelDev<T> L, const T* __res
                                                    const T* __restrict__ shift, const int* __restrict__ active,
                                                    T omega, double* __restrict__ partial,
                                                    unsigned long long* __restrict__ ctr, Fin fin) {
-  const int sys = blockIdx.z;
+  const Tile tl = block_tile();
+  const int sys = tl.z;
   if (!active[sys]) return;
   int i, j, k;
-  tile_ijk<DIM>(L.n, i, j, k);
+  tile_ijk<DIM>(tl, L.n, i, j, k);
   const bool ok = i < L.n && j < L.n;
   const long long off = (long long)sys * L.N;
   const long long p = ((long long)k * L.n + j) * L.n + i;
   const T s = shift[sys];
   // b and x_out, plus x_in unless the guess is zero; faces once per launch
-  count_bytes<COUNT_TILE>(ctr, (unsigned long long)L.N * sizeof(T) * ((ZERO ? 2 : 3) + (VAR && sys == 0 ? DIM : 0)));
+  count_bytes_tile(tl, ctr, (unsigned long long)L.N * sizeof(T) * ((ZERO ? 2 : 3) + (VAR && sys == 0 ? DIM : 0)));
   double dot = 0.0;
   if (ok) {
     const T bv = b[off + p];
@@ -196,7 +225,7 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(LevelDev<T> L, const T* __res
     if (DOT) dot = (double)bv * (double)xn;
   }
   if (DOT) {
-    write_partial_tile(partial, sys, dot);
+    write_partial_tile(tl, partial, sys, dot);
     finish(fin, partial, sys, gridDim.x * gridDim.y);
   }
 }
@@ -210,12 +239,13 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelDev<T> Lf, LevelDev<T>
                                                      const T* __restrict__ x, T* __restrict__ bc,
                                                      const T* __restrict__ shift, const int* __restrict__ active,
                                                      unsigned long long* __restrict__ ctr) {
-  const int sys = blockIdx.z;
+  const Tile tl = block_tile();
+  const int sys = tl.z;
   if (!active[sys]) return;
   // per coarse point: b and x on its 2^dim fine points, b_c written
-  count_bytes<COUNT_TILE>(ctr, (unsigned long long)Lc.N * sizeof(T) * (2 * (1 << DIM) + 1 + (VAR && sys == 0 ? DIM * (1 << DIM) : 0)));
+  count_bytes_tile(tl, ctr, (unsigned long long)Lc.N * sizeof(T) * (2 * (1 << DIM) + 1 + (VAR && sys == 0 ? DIM * (1 << DIM) : 0)));
   int I, J, K;
-  tile_ijk<DIM>(Lc.n, I, J, K);
+  tile_ijk<DIM>(tl, Lc.n, I, J, K);
   if (I >= Lc.n || J >= Lc.n) return;
   const int nf = Lf.n;
   const T s = shift[sys];
@@ -279,12 +309,13 @@ template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_prolong(LevelDev<T> Lc, LevelDev<T> Lf, const T* __restrict__ xc,
                                                     T* __restrict__ xf, const int* __restrict__ active,
                                                     unsigned long long* __restrict__ ctr) {
-  const int sys = blockIdx.z;
+  const Tile tl = block_tile();
+  const int sys = tl.z;
   if (!active[sys]) return;
   // x_f read and written; x_c read once (1/2^dim per fine point)
-  count_bytes<COUNT_TILE>(ctr, (unsigned long long)Lf.N * sizeof(T) * 2 + (unsigned long long)Lc.N * sizeof(T));
+  count_bytes_tile(tl, ctr, (unsigned long long)Lf.N * sizeof(T) * 2 + (unsigned long long)Lc.N * sizeof(T));
   int i, j, k;
-  tile_ijk<DIM>(Lf.n, i, j, k);
+  tile_ijk<DIM>(tl, Lf.n, i, j, k);
   if (i >= Lf.n || j >= Lf.n) return;
   const long long p = ((long long)k * Lf.n + j) * Lf.n + i;
   xf[(long long)sys * Lf.N + p] += interp_pt<T, DIM>(xc + (long long)sys * Lc.N, Lc.n, i, j, k);
@@ -439,38 +470,67 @@ __device__ __forceinline__ T lds_apply2(const T* __restrict__ X, int q, int RX, 
 constexpr int kDownCX = 32, kDownCY = 8;    // coarse points per block (2D)
 constexpr int kUpOX = 64, kUpOY = 16;       // fine points per block (2D)
 
-template <typename T, bool VAR, int NU>
+// RUP: the right-hand side is first advanced by the PCG step, b = b_old - alpha q
+// (read from b, written to bout on the owned points, |b|^2 into partial), so the
+// vector update of the PCG iteration costs no pass of its own.  bout must not
+// be b: neighbouring blocks still read b_old in their halos.
+template <typename T, bool VAR, int NU, bool RUP>
 __global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, const T* __restrict__ b,
                                                T* __restrict__ xout, T* __restrict__ bc,
                                                const T* __restrict__ shift, const int* __restrict__ active,
-                                               T omega, unsigned long long* __restrict__ ctr) {
+                                               T omega, unsigned long long* __restrict__ ctr,
+                                               const T* __restrict__ qv, const double* __restrict__ alpha,
+                                               T* __restrict__ bout, double* __restrict__ partial, Fin fin) {
   constexpr int RX = 2 * kDownCX + 2 * NU + 1, RY = 2 * kDownCY + 2 * NU + 1, RN = RX * RY;
   __shared__ T sb[RN];
   __shared__ T s0[RN];
   __shared__ T s1[RN];
-  const int sys = blockIdx.z;
+  const Tile tl = block_tile();
+  const int sys = tl.z;
   if (!active[sys]) return;
-  count_bytes<COUNT_TILE>(ctr, (unsigned long long)Lf.N * sizeof(T) * 2 + (unsigned long long)Lc.N * sizeof(T) +
+  count_bytes_tile(tl, ctr, (unsigned long long)Lf.N * sizeof(T) * (RUP ? 4 : 2) +
+                                   (unsigned long long)Lc.N * sizeof(T) +
                                    (VAR && sys == 0 ? (unsigned long long)Lf.N * sizeof(T) * 2 : 0ULL));
+  const T am = RUP ? (T)alpha[sys] : T(0);
   const int nf = Lf.n, nc = Lc.n;
-  const int I0 = blockIdx.x * kDownCX, J0 = blockIdx.y * kDownCY;
+  const int I0 = tl.x * kDownCX, J0 = tl.y * kDownCY;
   const int gx0 = 2 * I0 - NU, gy0 = 2 * J0 - NU;
   const T sh = shift[sys];
   const T wcon = omega / (Lf.wc * T(4) + sh);   // omega / D for constant coefficients
   const long long off = (long long)sys * Lf.N;
   const int tid = threadIdx.x;
-  // stage b (0 outside the grid) and the first sweep from x = 0: x1 = omega b / D
-  for (int q = tid; q < RN; q += 256) {
+  // stage b (0 outside the grid) and the first sweep from x = 0: x1 = omega b / D.
+  // All loads of a thread are issued before any is used (clamped addresses,
+  // results selected afterwards), so a wave keeps PER loads in flight.
+  constexpr int PER = (RN + 255) / 256;
+  T bl[PER], ql[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int q = tid + 256 * u;
     const int ry = q / RX, rx = q - ry * RX;
     const int gi = gx0 + rx, gj = gy0 + ry;
-    T bv = T(0), xv = T(0);
-    if (gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
-      bv = b[off + (long long)gj * nf + gi];
-      xv = VAR ? omega * bv / diag_pt<T, 2, VAR>(Lf, gi, gj, 0, sh) : wcon * bv;
+    const bool in = q < RN && gi >= 0 && gi < nf && gj >= 0 && gj < nf;
+    const long long g = off + (in ? (long long)gj * nf + gi : 0LL);
+    bl[u] = b[g];
+    if (RUP) ql[u] = qv[g];
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int q = tid + 256 * u;
+    if (q < RN) {
+      const int ry = q / RX, rx = q - ry * RX;
+      const int gi = gx0 + rx, gj = gy0 + ry;
+      const bool in = gi >= 0 && gi < nf && gj >= 0 && gj < nf;
+      const T bv = in ? (RUP ? bl[u] - am * ql[u] : bl[u]) : T(0);
+      T xv = wcon * bv;
+      if (VAR) {
+        const int ci = min(max(gi, 0), nf - 1), cj = min(max(gj, 0), nf - 1);
+        xv = omega * bv / diag_pt<T, 2, VAR>(Lf, ci, cj, 0, sh);
+      }
+      sb[q] = bv;
+      s0[q] = in ? xv : T(0);
+      s1[q] = T(0);
     }
-    sb[q] = bv;
-    s0[q] = xv;
-    s1[q] = T(0);
   }
   __syncthreads();
   T* X = s0;
@@ -500,10 +560,21 @@ __global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, c
     const int hx = (I0 + kDownCX >= nc) ? nf : 2 * (I0 + kDownCX);
     const int hy = (J0 + kDownCY >= nc) ? nf : 2 * (J0 + kDownCY);
     const int ow = hx - 2 * I0, oh = hy - 2 * J0;
+    double rr = 0.0;
     for (int q2 = tid; q2 < ow * oh; q2 += 256) {
       const int oy = q2 / ow, ox = q2 - oy * ow;
       const int gi = 2 * I0 + ox, gj = 2 * J0 + oy;
-      xout[off + (long long)gj * nf + gi] = X[(gj - gy0) * RX + (gi - gx0)];
+      const int q = (gj - gy0) * RX + (gi - gx0);
+      xout[off + (long long)gj * nf + gi] = X[q];
+      if (RUP) {
+        const T bv = sb[q];
+        bout[off + (long long)gj * nf + gi] = bv;
+        rr += (double)bv * (double)bv;
+      }
+    }
+    if (RUP) {
+      write_partial_tile(tl, partial, sys, rr);
+      finish(fin, partial, sys, gridDim.x * gridDim.y);
     }
   }
   // residual on the range shrunk by NU (fine points 2 I0 .. 2 I0 + 2 CX)
@@ -545,12 +616,13 @@ __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, con
   __shared__ T s0[RN];
   __shared__ T s1[RN];
   __shared__ T sc[CRN];
-  const int sys = blockIdx.z;
+  const Tile tl = block_tile();
+  const int sys = tl.z;
   if (!active[sys]) return;
-  count_bytes<COUNT_TILE>(ctr, (unsigned long long)Lf.N * sizeof(T) * 3 + (unsigned long long)Lc.N * sizeof(T) +
+  count_bytes_tile(tl, ctr, (unsigned long long)Lf.N * sizeof(T) * 3 + (unsigned long long)Lc.N * sizeof(T) +
                                    (VAR && sys == 0 ? (unsigned long long)Lf.N * sizeof(T) * 2 : 0ULL));
   const int nf = Lf.n, nc = Lc.n;
-  const int ox0 = blockIdx.x * kUpOX, oy0 = blockIdx.y * kUpOY;
+  const int ox0 = tl.x * kUpOX, oy0 = tl.y * kUpOY;
   const int gx0 = ox0 - NU, gy0 = oy0 - NU;
   // smallest coarse index any region point interpolates from (floor division)
   const int cx0 = ((gx0 >= 0) ? gx0 / 2 : -((-gx0 + 1) / 2)) - 1;
@@ -560,19 +632,45 @@ __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, con
   const long long off = (long long)sys * Lf.N;
   const T* xcs = xc + (long long)sys * Lc.N;
   const int tid = threadIdx.x;
-  for (int q = tid; q < CRN; q += 256) {
+  // every global load of the staging phase is issued up front (clamped
+  // addresses, selected afterwards): the coarse tile, then b and x_in
+  constexpr int CPER = (CRN + 255) / 256, PER = (RN + 255) / 256;
+  T cl[CPER], bl[PER], xl[PER];
+#pragma unroll
+  for (int u = 0; u < CPER; ++u) {
+    const int q = tid + 256 * u;
     const int cy = q / CRX, cx = q - cy * CRX;
     const int I = cx0 + cx, J = cy0 + cy;
-    sc[q] = (I >= 0 && I < nc && J >= 0 && J < nc) ? xcs[(long long)J * nc + I] : T(0);
+    const bool in = q < CRN && I >= 0 && I < nc && J >= 0 && J < nc;
+    cl[u] = xcs[in ? (long long)J * nc + I : 0LL];
   }
-  __syncthreads();
-  for (int q = tid; q < RN; q += 256) {
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int q = tid + 256 * u;
     const int ry = q / RX, rx = q - ry * RX;
     const int gi = gx0 + rx, gj = gy0 + ry;
-    T bv = T(0), xv = T(0);
-    if (gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
-      const long long g = off + (long long)gj * nf + gi;
-      bv = b[g];
+    const bool in = q < RN && gi >= 0 && gi < nf && gj >= 0 && gj < nf;
+    const long long g = off + (in ? (long long)gj * nf + gi : 0LL);
+    bl[u] = b[g];
+    xl[u] = xin[g];
+  }
+#pragma unroll
+  for (int u = 0; u < CPER; ++u) {
+    const int q = tid + 256 * u;
+    if (q < CRN) {
+      const int cy = q / CRX, cx = q - cy * CRX;
+      const int I = cx0 + cx, J = cy0 + cy;
+      sc[q] = (I >= 0 && I < nc && J >= 0 && J < nc) ? cl[u] : T(0);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int q = tid + 256 * u;
+    if (q < RN) {
+      const int ry = q / RX, rx = q - ry * RX;
+      const int gi = gx0 + rx, gj = gy0 + ry;
+      const bool in = gi >= 0 && gi < nf && gj >= 0 && gj < nf;
       // multilinear interpolation from the zero-padded coarse tile
       const int ia = (gi & 1) ? (gi - 1) / 2 : gi / 2 - 1;
       const int ja = (gj & 1) ? (gj - 1) / 2 : gj / 2 - 1;
@@ -583,11 +681,10 @@ __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, con
       } else {
         v = (gj & 1) ? T(0.5) * (C[0] + C[1]) : T(0.25) * (C[0] + C[1] + C[CRX] + C[CRX + 1]);
       }
-      xv = xin[g] + v;
+      sb[q] = in ? bl[u] : T(0);
+      s0[q] = in ? xl[u] + v : T(0);
+      s1[q] = T(0);
     }
-    sb[q] = bv;
-    s0[q] = xv;
-    s1[q] = T(0);
   }
   __syncthreads();
   T* X = s0;
@@ -624,7 +721,7 @@ __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, con
     }
   }
   if (DOT) {
-    write_partial_tile(partial, sys, dot);
+    write_partial_tile(tl, partial, sys, dot);
     finish(fin, partial, sys, gridDim.x * gridDim.y);
   }
 }
@@ -634,18 +731,25 @@ __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, con
 // --------------------------------------------------------------------------
 // p_new = z + beta p_old and q = (A+s) p_new in one pass (p_new formed at the
 // stencil points on the fly); p_old and p_new are different buffers.
-template <typename T, int DIM, bool VAR>
+// XUP: also x += alpha_prev p_old, the iterate update of the previous PCG
+// iteration, deferred to this pass which reads p_old anyway.  alpha == 0 marks
+// "nothing pending" (first iteration); p_old is then not used.
+template <typename T, int DIM, bool VAR, bool XUP>
 __global__ __launch_bounds__(kBlock) void k_spmv_p(LevelDev<T> L, const T* __restrict__ z, const T* __restrict__ pold,
                                                    T* __restrict__ pnew, T* __restrict__ q,
                                                    const double* __restrict__ beta, const T* __restrict__ shift,
                                                    const int* __restrict__ active, double* __restrict__ partial,
-                                                   unsigned long long* __restrict__ ctr, Fin fin) {
-  const int sys = blockIdx.z;
+                                                   unsigned long long* __restrict__ ctr, Fin fin,
+                                                   T* __restrict__ x, const double* __restrict__ alpha) {
+  const Tile tl = block_tile();
+  const int sys = tl.z;
   if (!active[sys]) return;
   const T bt = (T)beta[sys];
-  count_bytes<COUNT_TILE>(ctr, (unsigned long long)L.N * sizeof(T) * ((bt == T(0) ? 3 : 4) + (VAR && sys == 0 ? DIM : 0)));
+  const T ap = XUP ? (T)alpha[sys] : T(0);
+  count_bytes_tile(tl, ctr, (unsigned long long)L.N * sizeof(T) *
+                                   ((bt == T(0) ? 3 : 4) + (XUP && ap != T(0) ? 2 : 0) + (VAR && sys == 0 ? DIM : 0)));
   int i, j, k;
-  tile_ijk<DIM>(L.n, i, j, k);
+  tile_ijk<DIM>(tl, L.n, i, j, k);
   const bool ok = i < L.n && j < L.n;
   const long long off = (long long)sys * L.N;
   const long long p = ((long long)k * L.n + j) * L.n + i;
@@ -654,18 +758,27 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p(LevelDev<T> L, const T* __res
     const int n = L.n;
     const T* zs = z + off;
     const T* ps = pold + off;
-    auto P = [&](long long idx) -> T { return bt == T(0) ? zs[idx] : zs[idx] + bt * ps[idx]; };
-    const T pc = P(p);
-    const T pl = i > 0 ? P(p - 1) : T(0);
-    const T pr = i < n - 1 ? P(p + 1) : T(0);
-    const T pd = j > 0 ? P(p - n) : T(0);
-    const T pu = j < n - 1 ? P(p + n) : T(0);
+    // unconditional loads (a boundary neighbour reads the centre), selected after
+    // beta = 0 (first iteration): p_old may hold anything, so read z in its place
+    const T* pe = bt == T(0) ? zs : ps;
+    auto P = [&](long long idx) -> T { return zs[idx] + bt * pe[idx]; };
     const long long nn = (long long)n * n;
-    T pb = T(0), pf = T(0);
-    if (DIM == 3) {
-      pb = k > 0 ? P(p - nn) : T(0);
-      pf = k < n - 1 ? P(p + nn) : T(0);
+    T xv = T(0), pov = T(0);
+    if (XUP) {
+      xv = x[off + p];
+      pov = ps[p];
     }
+    const T pc = P(p);
+    const T pl0 = P(i > 0 ? p - 1 : p), pr0 = P(i < n - 1 ? p + 1 : p);
+    const T pd0 = P(j > 0 ? p - n : p), pu0 = P(j < n - 1 ? p + n : p);
+    T pb0 = T(0), pf0 = T(0);
+    if (DIM == 3) {
+      pb0 = P(k > 0 ? p - nn : p);
+      pf0 = P(k < n - 1 ? p + nn : p);
+    }
+    const T pl = i > 0 ? pl0 : T(0), pr = i < n - 1 ? pr0 : T(0);
+    const T pd = j > 0 ? pd0 : T(0), pu = j < n - 1 ? pu0 : T(0);
+    const T pb = DIM == 3 && k > 0 ? pb0 : T(0), pf = DIM == 3 && k < n - 1 ? pf0 : T(0);
     const T s = shift[sys];
     T qv;
     if (!VAR) {
@@ -684,9 +797,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p(LevelDev<T> L, const T* __res
     }
     pnew[off + p] = pc;
     q[off + p] = qv;
+    if (XUP && ap != T(0)) x[off + p] = xv + ap * pov;
     dot = (double)pc * (double)qv;
   }
-  write_partial_tile(partial, sys, dot);
+  write_partial_tile(tl, partial, sys, dot);
   finish(fin, partial, sys, gridDim.x * gridDim.y);
 }
 
@@ -696,11 +810,12 @@ template <typename T, int DIM, bool VAR>
 __global__ __launch_bounds__(kBlock) void k_spmv_dot(LevelDev<T> L, const T* __restrict__ pv, T* __restrict__ q,
                                                      const T* __restrict__ shift, const int* __restrict__ active,
                                                      double* __restrict__ partial, unsigned long long* __restrict__ ctr) {
-  const int sys = blockIdx.z;
+  const Tile tl = block_tile();
+  const int sys = tl.z;
   if (!active[sys]) return;
-  count_bytes<COUNT_TILE>(ctr, (unsigned long long)L.N * sizeof(T) * (2 + (VAR && sys == 0 ? DIM : 0)));
+  count_bytes_tile(tl, ctr, (unsigned long long)L.N * sizeof(T) * (2 + (VAR && sys == 0 ? DIM : 0)));
   int i, j, k;
-  tile_ijk<DIM>(L.n, i, j, k);
+  tile_ijk<DIM>(tl, L.n, i, j, k);
   const bool ok = i < L.n && j < L.n;
   const long long off = (long long)sys * L.N;
   const long long p = ((long long)k * L.n + j) * L.n + i;
@@ -710,7 +825,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(LevelDev<T> L, const T* __r
     q[off + p] = qv;
     dot = (double)pv[off + p] * (double)qv;
   }
-  write_partial_tile(partial, sys, dot);
+  write_partial_tile(tl, partial, sys, dot);
 }
 
 constexpr int kFlatItems = 4;
@@ -728,18 +843,57 @@ __global__ __launch_bounds__(256) void k_update_xr(long long N, T* __restrict__ 
   const long long off = (long long)sys * N;
   const long long base = (long long)blockIdx.x * 256 * kFlatItems + threadIdx.x;
   double rr = 0.0;
+  // all loads first (clamped index), then the updates and stores
+  T xv[kFlatItems], pl[kFlatItems], rl[kFlatItems], ql[kFlatItems];
+#pragma unroll
+  for (int it = 0; it < kFlatItems; ++it) {
+    const long long p = min(base + (long long)it * 256, N - 1);
+    xv[it] = x[off + p];
+    pl[it] = pv[off + p];
+    rl[it] = r[off + p];
+    ql[it] = q[off + p];
+  }
 #pragma unroll
   for (int it = 0; it < kFlatItems; ++it) {
     const long long p = base + (long long)it * 256;
     if (p < N) {
-      x[off + p] += a * pv[off + p];
-      const T rv = r[off + p] - a * q[off + p];
+      x[off + p] = xv[it] + a * pl[it];
+      const T rv = rl[it] - a * ql[it];
       r[off + p] = rv;
       rr += (double)rv * (double)rv;
     }
   }
   write_partial_flat(partial, sys, rr);
   finish(fin, partial, sys, gridDim.x);
+}
+
+// The deferred update of the last PCG iteration: x += alpha p_last, with
+// p_last in pa when the system's iteration count is even and in pb otherwise
+// (iteration c reads p_old from pa for even c and writes p_new to the other).
+template <typename T>
+__global__ __launch_bounds__(256) void k_finish_x(long long N, T* __restrict__ x, const T* __restrict__ pa,
+                                                  const T* __restrict__ pb, const double* __restrict__ alpha,
+                                                  const int* __restrict__ iters, unsigned long long* __restrict__ ctr) {
+  const int sys = blockIdx.y;
+  const int it = iters[sys];
+  const T a = (T)alpha[sys];
+  if (it <= 0 || a == T(0)) return;
+  count_bytes<COUNT_FLAT>(ctr, (unsigned long long)N * sizeof(T) * 3);
+  const T* pl = ((it - 1) & 1) ? pa : pb;
+  const long long off = (long long)sys * N;
+  const long long base = (long long)blockIdx.x * 256 * kFlatItems + threadIdx.x;
+  T xv[kFlatItems], pv[kFlatItems];
+#pragma unroll
+  for (int k = 0; k < kFlatItems; ++k) {
+    const long long p = min(base + (long long)k * 256, N - 1);
+    xv[k] = x[off + p];
+    pv[k] = pl[off + p];
+  }
+#pragma unroll
+  for (int k = 0; k < kFlatItems; ++k) {
+    const long long p = base + (long long)k * 256;
+    if (p < N) x[off + p] = xv[k] + a * pv[k];
+  }
 }
 
 template <typename T>
@@ -770,11 +924,14 @@ __global__ __launch_bounds__(256) void k_copy_rhs(long long N, const double* __r
   const long long off = (long long)sys * N;
   const long long base = (long long)blockIdx.x * 256 * kFlatItems + threadIdx.x;
   double ff = 0.0;
+  double fl[kFlatItems];
+#pragma unroll
+  for (int it = 0; it < kFlatItems; ++it) fl[it] = f[(long long)rhs * N + min(base + (long long)it * 256, N - 1)];
 #pragma unroll
   for (int it = 0; it < kFlatItems; ++it) {
     const long long p = base + (long long)it * 256;
     if (p < N) {
-      const double fv = f[(long long)rhs * N + p];
+      const double fv = fl[it];
       r[off + p] = (T)fv;
       x[off + p] = T(0);
       ff += fv * fv;
@@ -792,12 +949,13 @@ __global__ __launch_bounds__(kBlock) void k_residual64(LevelDev<double> L, const
                                                        float* __restrict__ r32, const double* __restrict__ shift,
                                                        const int* __restrict__ active64, int nrhs,
                                                        double* __restrict__ partial, unsigned long long* __restrict__ ctr) {
-  const int sys = blockIdx.z;
+  const Tile tl = block_tile();
+  const int sys = tl.z;
   if (!active64[sys]) return;
   // x64, f read (FP64); r32, e written (FP32)
-  count_bytes<COUNT_TILE>(ctr, (unsigned long long)L.N * (8 + 8 + 4 + 4 + (VAR && sys == 0 ? 8 * DIM : 0)));
+  count_bytes_tile(tl, ctr, (unsigned long long)L.N * (8 + 8 + 4 + 4 + (VAR && sys == 0 ? 8 * DIM : 0)));
   int i, j, k;
-  tile_ijk<DIM>(L.n, i, j, k);
+  tile_ijk<DIM>(tl, L.n, i, j, k);
   const bool ok = i < L.n && j < L.n;
   const long long off = (long long)sys * L.N;
   const long long p = ((long long)k * L.n + j) * L.n + i;
@@ -810,7 +968,7 @@ __global__ __launch_bounds__(kBlock) void k_residual64(LevelDev<double> L, const
     e[off + p] = 0.0f;
     rr = rv * rv;
   }
-  write_partial_tile(partial, sys, rr);
+  write_partial_tile(tl, partial, sys, rr);
 }
 
 // first refinement step: x64 = 0 so r = f; partial = ||f||^2
@@ -825,11 +983,14 @@ __global__ __launch_bounds__(256) void k_first_residual(long long N, const doubl
   const long long off = (long long)sys * N;
   const long long base = (long long)blockIdx.x * 256 * kFlatItems + threadIdx.x;
   double ff = 0.0;
+  double fl[kFlatItems];
+#pragma unroll
+  for (int it = 0; it < kFlatItems; ++it) fl[it] = f[(long long)rhs * N + min(base + (long long)it * 256, N - 1)];
 #pragma unroll
   for (int it = 0; it < kFlatItems; ++it) {
     const long long p = base + (long long)it * 256;
     if (p < N) {
-      const double fv = f[(long long)rhs * N + p];
+      const double fv = fl[it];
       r32[off + p] = (float)fv;
       x64[off + p] = 0.0;
       e[off + p] = 0.0f;
@@ -846,10 +1007,18 @@ __global__ __launch_bounds__(256) void k_x_from_e(long long N, const float* __re
   if (!active64[sys]) return;
   const long long off = (long long)sys * N;
   const long long base = (long long)blockIdx.x * 256 * kFlatItems + threadIdx.x;
+  double xl[kFlatItems];
+  float el[kFlatItems];
+#pragma unroll
+  for (int it = 0; it < kFlatItems; ++it) {
+    const long long p = min(base + (long long)it * 256, N - 1);
+    xl[it] = x64[off + p];
+    el[it] = e[off + p];
+  }
 #pragma unroll
   for (int it = 0; it < kFlatItems; ++it) {
     const long long p = base + (long long)it * 256;
-    if (p < N) x64[off + p] += (double)e[off + p];
+    if (p < N) x64[off + p] = xl[it] + (double)el[it];
   }
 }
 
@@ -869,9 +1038,10 @@ __global__ __launch_bounds__(256) void k_combine(long long N, const double* __re
 template <int DIM, bool VAR>
 __global__ __launch_bounds__(kBlock) void k_apply64(LevelDev<double> L, const double* __restrict__ x,
                                                     double* __restrict__ y, double s) {
-  const int v = blockIdx.z;
+  const Tile tl = block_tile();
+  const int v = tl.z;
   int i, j, k;
-  tile_ijk<DIM>(L.n, i, j, k);
+  tile_ijk<DIM>(tl, L.n, i, j, k);
   if (i >= L.n || j >= L.n) return;
   const long long off = (long long)v * L.N;
   const long long p = ((long long)k * L.n + j) * L.n + i;
@@ -889,6 +1059,7 @@ __device__ void apply_op(int op, double tot, const SysState& S, int sys, double 
       S.iters[sys] = 0;
       S.relres[sys] = 1.0;
       S.beta[sys] = 0.0;
+      S.alpha[sys] = 0.0;   // no deferred iterate update pending
       if (!(tot > 0.0)) {
         S.active[sys] = 0;
         if (!isfinite(tot)) S.flags[sys] |= 1;
@@ -937,6 +1108,7 @@ __device__ void apply_op(int op, double tot, const SysState& S, int sys, double 
     }
     case OP_OUTER: {  // tot = ||f - (A+s) x64||^2 ; first call: x64 = 0 so tot = ||f||^2
       const int o = S.outer[sys];
+      S.alpha[sys] = 0.0;   // the inner solve's deferred update has been applied (or is void)
       if (!isfinite(tot)) {
         S.flags[sys] |= 1;
         S.relres64[sys] = tot;
@@ -1098,28 +1270,54 @@ void Launch<T>::copy_rhs(const LevelDev<T>& L, int dim, const double* f, T* r, T
 template <typename T>
 void Launch<T>::spmv_p(int dim, bool var, const LevelDev<T>& L, const T* z, const T* pold, T* pnew, T* q,
                        const double* beta, const T* shift, const int* active, double* partial, int nsys,
-                       hipStream_t st, unsigned long long* ctr, Fin fin) {
+                       hipStream_t st, unsigned long long* ctr, Fin fin, T* x, const double* alpha) {
   const dim3 g = stencil_grid(dim, L.n, nsys), blk(kTileX, kTileY);
-#define K_SPP(D, V, dummy) \
-  hipLaunchKernelGGL((k_spmv_p<T, D, V>), g, blk, 0, st, L, z, pold, pnew, q, beta, shift, active, partial, ctr, fin)
+  const bool xup = x != nullptr;
+#define K_SPP(D, V, dummy)                                                                                          \
+  do {                                                                                                              \
+    if (xup)                                                                                                        \
+      hipLaunchKernelGGL((k_spmv_p<T, D, V, true>), g, blk, 0, st, L, z, pold, pnew, q, beta, shift, active,      \
+                         partial, ctr, fin, x, alpha);                                                              \
+    else                                                                                                            \
+      hipLaunchKernelGGL((k_spmv_p<T, D, V, false>), g, blk, 0, st, L, z, pold, pnew, q, beta, shift, active,     \
+                         partial, ctr, fin, x, alpha);                                                              \
+  } while (0)
   BURA_DISPATCH_DV(dim, var, K_SPP, 0);
 #undef K_SPP
 }
 
 template <typename T>
+void Launch<T>::finish_x(long long N, T* x, const T* pa, const T* pb, const double* alpha, const int* iters,
+                         int nsys, hipStream_t st, unsigned long long* ctr) {
+  hipLaunchKernelGGL((k_finish_x<T>), flat_grid(N, nsys), dim3(256), 0, st, N, x, pa, pb, alpha, iters, ctr);
+}
+
+template <typename T>
 bool Launch<T>::fused_down(int dim, bool var, int nu, const LevelDev<T>& Lf, const LevelDev<T>& Lc, const T* b,
                            T* xout, T* bc, const T* shift, const int* active, T omega, int nsys, hipStream_t st,
-                           unsigned long long* ctr) {
+                           unsigned long long* ctr, const T* q, const double* alpha, T* bout, double* partial,
+                           Fin fin) {
   if (dim != 2 || nu < 1 || nu > 3) return false;
   const dim3 g((Lc.n + kDownCX - 1) / kDownCX, (Lc.n + kDownCY - 1) / kDownCY, nsys), blk(256);
-#define K_DN(V, NU_) hipLaunchKernelGGL((k_down2<T, V, NU_>), g, blk, 0, st, Lf, Lc, b, xout, bc, shift, active, omega, ctr)
+  const bool rup = bout != nullptr;
+#define K_DN0(V, NU_, R_)                                                                                          \
+  hipLaunchKernelGGL((k_down2<T, V, NU_, R_>), g, blk, 0, st, Lf, Lc, b, xout, bc, shift, active, omega, ctr, q,  \
+                     alpha, bout, partial, fin)
+#define K_DN(V, NU_) do { if (rup) K_DN0(V, NU_, true); else K_DN0(V, NU_, false); } while (0)
   if (var) {
     if (nu == 1) K_DN(true, 1); else if (nu == 2) K_DN(true, 2); else K_DN(true, 3);
   } else {
     if (nu == 1) K_DN(false, 1); else if (nu == 2) K_DN(false, 2); else K_DN(false, 3);
   }
 #undef K_DN
+#undef K_DN0
   return true;
+}
+
+int down_blocks(int dim, int n) {
+  if (dim != 2) return stencil_blocks(dim, n);
+  const int nc = (n - 1) / 2;
+  return ((nc + kDownCX - 1) / kDownCX) * ((nc + kDownCY - 1) / kDownCY);
 }
 
 template <typename T>
