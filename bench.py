@@ -351,7 +351,17 @@ def main():
         for _ in range(3):
             y.copy_(x)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes, "launches": 3}))
+        # achievable rate of a plain device copy (1 read + 1 write per byte), by
+        # events around 10 launches
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(10):
+            y.copy_(x)
+        ev[1].record()
+        torch.cuda.synchronize()
+        t_copy = ev[0].elapsed_time(ev[1]) / 10 / 1e3
+        print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes, "launches": 13,
+                          "copy_GBs": 2 * nbytes / t_copy / 1e9}))
         return
     if args.serving:
         res = run_serving(args)

@@ -437,7 +437,7 @@ LdsHierarchy<T> lds_view(const bura_plan_t P) {
     H.off[q] = off;
     off += 3 * (int)P->lev[P->lc + q].N;
   }
-  H.cycles = 2;
+  H.cycles = 1;   // one V-cycle through the in-LDS levels: the hierarchy is then a plain V-cycle
   H.nu = 2;
   H.bottom_sweeps = 8 * P->lev[L - 1].n + 8;
   H.omega = (T)(P->opts.omega > 0 ? P->opts.omega : default_omega(P->dim));
@@ -673,7 +673,7 @@ int run_pcg(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, double tol, int ma
   const size_t o = sys0 * (size_t)P->N;
   const SysState S = state_at(P, sys0);
   double* part = P->partial;
-  const int nb_tile = stencil_blocks(dim, P->n), nb_flat = flat_blocks(P->N);
+  const int nb_flat = flat_blocks(P->N);
   const int check = std::max(1, P->opts.check_every);
   auto scal = [&](int op, int nblk) {
     ProfScope ps(P, BURA_K_OTHER);
@@ -701,7 +701,7 @@ int run_pcg(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, double tol, int ma
       Launch<T>::spmv_p(dim, P->var, L0, W.z + o, po, pn, W.q + o, S.beta, W.shift + sys0, S.active, part, nsys, st,
                         ps.ctr, fin(OP_ALPHA), fx ? W.x + o : nullptr, S.alpha);
     }
-    if (!P->fold) scal(OP_ALPHA, nb_tile);
+    if (!P->fold) scal(OP_ALPHA, spmv_blocks(dim, P->n));
     if (fx) {
       ResidUpdate<T> ru{ro, rn, W.q + o, S.alpha, fin(OP_RESID), [&]() {
                           if (!P->fold) scal(OP_RESID, nb_down);

@@ -139,5 +139,6 @@ int stencil_blocks(int dim, int n);   // blocks per system of a stencil launch (
 int flat_blocks(long long N);        // blocks per system of an element-wise launch
 int up_blocks(int dim, int n);       // blocks per system of the fused up kernel
 int down_blocks(int dim, int n);     // blocks per system of the fused down kernel (fine level n)
+int spmv_blocks(int dim, int n);     // blocks per system of the stencil product with the p update
 
 }  // namespace bura

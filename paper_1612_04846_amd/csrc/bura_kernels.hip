@@ -805,6 +805,91 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p(LevelDev<T> L, const T* __res
 }
 
 
+// 2D version: each thread owns kSpRows consecutive rows of one column (a
+// workgroup covers kTileX x kTileY*kSpRows points), so the column's p_new
+// values are formed once and reused by the rows above and below; only the
+// left/right neighbours are extra loads.
+constexpr int kSpRows = 4;
+
+template <typename T, bool VAR, bool XUP>
+__global__ __launch_bounds__(kBlock) void k_spmv_p2(LevelDev<T> L, const T* __restrict__ z, const T* __restrict__ pold,
+                                                    T* __restrict__ pnew, T* __restrict__ q,
+                                                    const double* __restrict__ beta, const T* __restrict__ shift,
+                                                    const int* __restrict__ active, double* __restrict__ partial,
+                                                    unsigned long long* __restrict__ ctr, Fin fin,
+                                                    T* __restrict__ x, const double* __restrict__ alpha) {
+  constexpr int R = kSpRows;
+  const Tile tl = block_tile();
+  const int sys = tl.z;
+  if (!active[sys]) return;
+  const T bt = (T)beta[sys];
+  const T ap = XUP ? (T)alpha[sys] : T(0);
+  count_bytes_tile(tl, ctr, (unsigned long long)L.N * sizeof(T) *
+                                ((bt == T(0) ? 3 : 4) + (XUP && ap != T(0) ? 2 : 0) + (VAR && sys == 0 ? 2 : 0)));
+  const int n = L.n;
+  const int i = tl.x * kTileX + threadIdx.x;
+  const int j0 = (tl.y * kTileY + threadIdx.y) * R;
+  const long long off = (long long)sys * L.N;
+  double dot = 0.0;
+  if (i < n && j0 < n) {
+    const T* zs = z + off;
+    // beta = 0 (first iteration): p_old may hold anything, so read z in its place
+    const T* pe = bt == T(0) ? zs : pold + off;
+    const T s = shift[sys];
+    const int il = i > 0 ? i - 1 : i, ir = i < n - 1 ? i + 1 : i;
+    // every load first (clamped rows/columns), then the arithmetic
+    T zc[R + 2], pc[R + 2], zl[R], pl[R], zr[R], pr[R], xv[R];
+#pragma unroll
+    for (int r = 0; r < R + 2; ++r) {
+      const int jj = min(max(j0 - 1 + r, 0), n - 1);
+      const long long g = (long long)jj * n + i;
+      zc[r] = zs[g];
+      pc[r] = pe[g];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const long long row = (long long)min(j0 + r, n - 1) * n;
+      zl[r] = zs[row + il];
+      pl[r] = pe[row + il];
+      zr[r] = zs[row + ir];
+      pr[r] = pe[row + ir];
+      if (XUP) xv[r] = x[off + row + i];
+    }
+    T v[R + 2];
+#pragma unroll
+    for (int r = 0; r < R + 2; ++r) {
+      const int jj = j0 - 1 + r;
+      v[r] = (jj >= 0 && jj < n) ? zc[r] + bt * pc[r] : T(0);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int j = j0 + r;
+      if (j < n) {
+        const T c = v[r + 1], dn = v[r], up = v[r + 2];
+        const T lv = i > 0 ? zl[r] + bt * pl[r] : T(0);
+        const T rv = i < n - 1 ? zr[r] + bt * pr[r] : T(0);
+        T qv;
+        if (!VAR) {
+          qv = L.wc * ((c - lv) + (c - rv) + (c - dn) + (c - up)) + s * c;
+        } else {
+          const long long fx = (long long)j * (n + 1) + i;
+          const long long fy = (long long)j * n + i;
+          qv = L.wf0[fx] * (c - lv) + L.wf0[fx + 1] * (c - rv) + L.wf1[fy] * (c - dn) + L.wf1[fy + n] * (c - up) +
+               s * c;
+        }
+        const long long g = off + (long long)j * n + i;
+        pnew[g] = c;
+        q[g] = qv;
+        // the deferred update uses p_old = pc (pe is p_old whenever alpha != 0)
+        if (XUP && ap != T(0)) x[g] = xv[r] + ap * pc[r + 1];
+        dot += (double)c * (double)qv;
+      }
+    }
+  }
+  write_partial_tile(tl, partial, sys, dot);
+  finish(fin, partial, sys, gridDim.x * gridDim.y);
+}
+
 // --------------------------------------------------------------------------
 template <typename T, int DIM, bool VAR>
 __global__ __launch_bounds__(kBlock) void k_spmv_dot(LevelDev<T> L, const T* __restrict__ pv, T* __restrict__ q,
@@ -1163,6 +1248,18 @@ int stencil_blocks(int dim, int n) {
   return (int)(g.x * g.y);
 }
 
+// the 2D stencil product: kTileX x (kTileY * kSpRows) points per workgroup
+static inline dim3 spmv2_grid(int n, int nsys) {
+  const int rows = kTileY * kSpRows;
+  return dim3((n + kTileX - 1) / kTileX, (n + rows - 1) / rows, nsys);
+}
+
+int spmv_blocks(int dim, int n) {
+  if (dim != 2) return stencil_blocks(dim, n);
+  const dim3 g = spmv2_grid(n, 1);
+  return (int)(g.x * g.y);
+}
+
 int flat_blocks(long long N) {
   const long long per = 256LL * kFlatItems;
   return (int)((N + per - 1) / per);
@@ -1271,8 +1368,21 @@ template <typename T>
 void Launch<T>::spmv_p(int dim, bool var, const LevelDev<T>& L, const T* z, const T* pold, T* pnew, T* q,
                        const double* beta, const T* shift, const int* active, double* partial, int nsys,
                        hipStream_t st, unsigned long long* ctr, Fin fin, T* x, const double* alpha) {
-  const dim3 g = stencil_grid(dim, L.n, nsys), blk(kTileX, kTileY);
   const bool xup = x != nullptr;
+  if (dim == 2) {
+    const dim3 g2 = spmv2_grid(L.n, nsys), blk2(kTileX, kTileY);
+#define K_SP2(V, X_) \
+  hipLaunchKernelGGL((k_spmv_p2<T, V, X_>), g2, blk2, 0, st, L, z, pold, pnew, q, beta, shift, active, partial, ctr, \
+                     fin, x, alpha)
+    if (var) {
+      if (xup) K_SP2(true, true); else K_SP2(true, false);
+    } else {
+      if (xup) K_SP2(false, true); else K_SP2(false, false);
+    }
+#undef K_SP2
+    return;
+  }
+  const dim3 g = stencil_grid(dim, L.n, nsys), blk(kTileX, kTileY);
 #define K_SPP(D, V, dummy)                                                                                          \
   do {                                                                                                              \
     if (xup)                                                                                                        \
