@@ -25,6 +25,8 @@ of sparse SPD matrices" (arXiv:1612.04846) that it follows):
 * ``metrics``  -- relative errors and the error-lemma norms of eq. (bound).
 * ``multistep`` -- the multi-step BURA of Section 4.4 (sequential 1-BURA
                   steps) and its eigenvector errors.
+* ``product``  -- the zero-pole product form of the remark in Section 2.2
+                  (zeros, leading constant, factor-by-factor evaluation).
 * ``quadrature`` -- the sinc quadrature u_Q of Bonito and Pasciak that
                   Section 5.3 compares the BURA against (its weights, shifts and
                   term counts), and its closed-form eigenbasis evaluation.
