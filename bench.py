@@ -49,6 +49,14 @@ WORKLOADS = {
                                       precision="MIXED", schedule="BATCHED", tol=1e-10, var=True),
     # the sinc quadrature Section 5.3 compares against, with k_Q = 9, 7, 6 (11 + 9 + 8
     # shifted systems), on the paper's checkerboard right-hand side
+    # multi-step BURA (Section 4.4): alpha = 0.75 as 0.5 then 0.25, k = 9 each (two
+    # sequential stages of 10 systems); the zero-pole product form (alpha 0.5,
+    # k = 9: ten sequential single-system stages)
+    "2d1023-multistep-k9-fp64": dict(dim=2, n=1023, alphas=(0.5, 0.25), k=9, nrhs=1, rhs="normal", tag=2,
+                                     precision="FP64", schedule="BATCHED", tol=1e-10, var=False, multi=True,
+                                     method="multistep"),
+    "2d1023-product-k9-fp64": dict(dim=2, n=1023, alphas=(0.5,), k=9, nrhs=1, rhs="normal", tag=2,
+                                   precision="FP64", schedule="BATCHED", tol=1e-10, var=False, method="product"),
     "2d1023-sinc-fp64-multi": dict(dim=2, n=1023, alphas=(0.25, 0.5, 0.75), k=None, kq=(9, 7, 6), nrhs=1,
                                    rhs="checkerboard", tag=0, precision="FP64", schedule="BATCHED", tol=1e-10,
                                    var=False, multi=True, method="sinc"),
@@ -65,6 +73,12 @@ def describe(w):
     if w.get("method") == "sinc":
         what = (f"alpha={list(w['alphas'])}, sinc quadrature (Bonito-Pasciak) with k_Q={list(w['kq'])} "
                 f"applied to the unscaled operator")
+    elif w.get("method") == "multistep":
+        what = f"alpha={sum(w['alphas'])} as multi-step BURA steps {list(w['alphas'])}, k={w['k']} each"
+        sched = "sequential steps, each step's poles batched"
+    elif w.get("method") == "product":
+        what = f"alpha={w['alphas'][0]}, beta=1, k={w['k']}, zero-pole product form"
+        sched = "sequential factors"
     else:
         what = f"alpha={list(w['alphas'])}, beta=1, k={w['k']}"
     return (f"{d}D {grid} {op} operator scaled to (0,1], {what}, "
@@ -105,6 +119,8 @@ def run_gpu(w, steps, warmup, profile=True):
         if w.get("method") == "sinc":
             al = a if isinstance(a, list) else [a]
             kw["kprime"] = [B.sinc_kprime(x, kq[x]) for x in al]
+        if w.get("method") in ("multistep", "product"):
+            kw["form"] = w["method"]
         plans.append(B.Plan(w["dim"], w["n"], a, w["k"], **kw))
     t_plan = time.perf_counter() - t_plan
     outs = [torch.empty((p.nout,) + tuple(F.shape), dtype=F.dtype, device=dev) if p.nout > 1 else torch.empty_like(F)
@@ -212,6 +228,13 @@ def oracle_errors(w, res):
     from oracle import metrics, operators, quadrature, shifted, spectral
     gold = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_bura_coefficients.json")))
     errs = []
+    if w.get("method") == "multistep":
+        from oracle import multistep
+        steps = []
+        for a in w["alphas"]:
+            rec = gold[f"{a:.2f},{w['k']}"]
+            steps.append(([float(x) for x in rec["c"]], [float(x) for x in rec["d"]]))
+        return [metrics.rel_err(res["U"][0], multistep.multistep_spectral(res["F"], w["dim"], steps))]
     for i, (a, U) in enumerate(zip(w["alphas"], res["U"])):
         if w.get("method") == "sinc":
             kp = quadrature.sinc_kprime(a, w["kq"][i])
@@ -339,7 +362,7 @@ def main():
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of this many GiB (counter calibration)")
     ap.add_argument("--also", default="2d1023-k9-fp64-per-pole,2d1023-k9-fp64-batched,2d1023-k9-mixed-multi,"
-                                      "2d1023-sinc-fp64-multi",
+                                      "2d1023-sinc-fp64-multi,2d1023-multistep-k9-fp64,2d1023-product-k9-fp64",
                     help="comma-separated extra workloads reported under 'paths' (empty: none)")
     args = ap.parse_args()
     if args.copy_probe > 0:

@@ -127,6 +127,13 @@ int bura_opts_default(bura_opts_t* o);
  * per (alpha, k) for the life of the process. */
 int bura_coefficients(double alpha, int beta, int k, double* c, double* d, double* E);
 
+/* The zeros of the same (k,k) BURA r (Lemma 2.5: real, negative, interlacing
+ * with the poles, 0 > zeta[0] > d_1 > zeta[1] > ... > zeta[k-1] > d_k) and the
+ * leading constant *C with r(t) = C prod_j (t - zeta_j)/(t - d_j), for the
+ * zero-pole product form of the remark in Section 2.2.  zeta has room for k
+ * doubles.  Same arguments, errors and caching as bura_coefficients. */
+int bura_zeros(double alpha, int beta, int k, double* zeta, double* C);
+
 /* Create a plan: operator hierarchy, coefficients (via bura_coefficients) and
  * device workspace for up to opts->nrhs_max right-hand sides.  *out receives
  * the plan on success and NULL otherwise. */
@@ -170,6 +177,26 @@ int bura_sinc_coefficients(double alpha, double kprime, double scale, int max_te
  * same A^-alpha f as a BURA plan.  Total terms <= BURA_MAX_TERMS; E is 0. */
 int bura_plan_create_sinc(const bura_grid_t* grid, int nalpha, const double* alphas, const double* kprimes,
                           const bura_opts_t* opts, bura_plan_t* out);
+
+/* Multi-step BURA (Section 4.4): A^-alpha f for alpha = sum_i alphas[i] as
+ * nsteps 1-BURA steps applied in order, u_i = r_{alphas[i]}(A) A^-1 u_{i-1},
+ * u_0 = f, each with ks[i] + 1 shifted systems (sum <= BURA_MAX_TERMS).  The
+ * steps run one after the other (each step's systems in one batch); the plan
+ * holds one extra nrhs_max x N FP64 buffer between steps.  bura_solve writes
+ * u_n; the report's E is the largest E_{alphas[i]}(ks[i],ks[i];1) (the error
+ * of the composition depends on the condition number, eq. (general 2-step
+ * error)). */
+int bura_plan_create_multistep(const bura_grid_t* grid, int nsteps, const double* alphas, const int* ks,
+                               const bura_opts_t* opts, bura_plan_t* out);
+
+/* The zero-pole product form of the remark in Section 2.2:
+ * u = C prod_{j=1..k} (A - zeta_j I)(A - d_j I)^-1 A^-1 f, evaluated as k+1
+ * sequential solves, v_0 = A^-1 f, v_j = v_{j-1} + (d_j - zeta_j)(A - d_j I)^-1 v_{j-1},
+ * u = C v_k (zeros and C from bura_zeros).  Same result as bura_plan_create
+ * up to rounding; the systems cannot run concurrently (only the right-hand
+ * sides of a batch do).  Extra nrhs_max x N FP64 buffer as for multistep. */
+int bura_plan_create_product(const bura_grid_t* grid, double alpha, int beta, int k, const bura_opts_t* opts,
+                             bura_plan_t* out);
 
 /* Several fractional powers of the same operator in one plan: alpha[a] with
  * ks[a] poles each (a < nalpha, sum_a (ks[a]+1) <= BURA_MAX_TERMS).  All

@@ -128,6 +128,11 @@ _SIGS = {
     "bura_plan_create_rational_multi": (_I, [ctypes.POINTER(bura_grid_t), _I, ctypes.POINTER(_I), _DP, _DP,
                                              ctypes.POINTER(bura_opts_t), ctypes.POINTER(_P)]),
     "bura_sinc_coefficients": (_I, [_D, _D, _D, _I, _DP, _DP, ctypes.POINTER(_I)]),
+    "bura_zeros": (_I, [_D, _I, _I, _DP, _DP]),
+    "bura_plan_create_multistep": (_I, [ctypes.POINTER(bura_grid_t), _I, _DP, ctypes.POINTER(_I),
+                                        ctypes.POINTER(bura_opts_t), ctypes.POINTER(_P)]),
+    "bura_plan_create_product": (_I, [ctypes.POINTER(bura_grid_t), _D, _I, _I, ctypes.POINTER(bura_opts_t),
+                                      ctypes.POINTER(_P)]),
     "bura_plan_create_sinc": (_I, [ctypes.POINTER(bura_grid_t), _I, _DP, _DP, ctypes.POINTER(bura_opts_t),
                                    ctypes.POINTER(_P)]),
     "bura_plan_outputs": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
@@ -298,6 +303,37 @@ def bura_sinc_coefficients(alpha: float, kprime: float, scale: float = 1.0):
     return list(w)[: cnt.value], list(s)[: cnt.value]
 
 
+def bura_zeros(alpha: float, k: int, beta: int = 1):
+    """(zeta_1 > ... > zeta_k, C) of the (k,k) BURA: r(t) = C prod (t - zeta_j)/(t - d_j) (host only)."""
+    z = (ctypes.c_double * k)()
+    C = ctypes.c_double()
+    _check(_lib.bura_zeros(alpha, beta, k, z, ctypes.byref(C)), "bura_zeros")
+    return list(z), C.value
+
+
+def bura_plan_create_multistep(dim: int, n: int, alphas: Sequence[float], ks: Sequence[int],
+                               opts: Optional[bura_opts_t] = None, coeff=None, lambda_upper: float = 0.0):
+    g, _keep = _grid(dim, n, coeff, lambda_upper)
+    o = opts if opts is not None else bura_opts_default()
+    m = len(alphas)
+    a = (ctypes.c_double * m)(*alphas)
+    k = (ctypes.c_int * m)(*ks)
+    h = _P()
+    _check(_lib.bura_plan_create_multistep(ctypes.byref(g), m, a, k, ctypes.byref(o), ctypes.byref(h)),
+           "bura_plan_create_multistep")
+    return h
+
+
+def bura_plan_create_product(dim: int, n: int, alpha: float, k: int, opts: Optional[bura_opts_t] = None,
+                             coeff=None, lambda_upper: float = 0.0, beta: int = 1):
+    g, _keep = _grid(dim, n, coeff, lambda_upper)
+    o = opts if opts is not None else bura_opts_default()
+    h = _P()
+    _check(_lib.bura_plan_create_product(ctypes.byref(g), alpha, beta, k, ctypes.byref(o), ctypes.byref(h)),
+           "bura_plan_create_product")
+    return h
+
+
 def bura_plan_create_sinc(dim: int, n: int, alphas: Sequence[float], kprimes: Sequence[float],
                           opts: Optional[bura_opts_t] = None, coeff=None, lambda_upper: float = 0.0):
     g, _keep = _grid(dim, n, coeff, lambda_upper)
@@ -394,18 +430,28 @@ class Plan:
     """Owns a plan handle; ``solve(f)`` returns A^-alpha f for a batch f of shape (nrhs, n, ..., n)."""
 
     def __init__(self, dim, n, alpha=None, k=None, *, weights=None, shifts=None, nterms=None, kprime=None,
-                 coeff=None, precision=BURA_MIXED, schedule=BURA_BATCHED, tol=1e-12, nrhs_max=1, stream=None,
-                 **opt):
+                 form="fractions", coeff=None, precision=BURA_MIXED, schedule=BURA_BATCHED, tol=1e-12, nrhs_max=1,
+                 stream=None, **opt):
         """alpha (one value or a list) with k poles: the BURA; alpha with kprime
         (one value or lists): the sinc quadrature of step k'; weights/shifts
-        (with nterms per output for several outputs): a caller-given form."""
+        (with nterms per output for several outputs): a caller-given form.
+        form="multistep" (alpha and k lists: the steps, in order) or
+        form="product" (one alpha): the sequential forms."""
         self.dim, self.n = dim, n
         o = bura_opts_default(precision=precision, schedule=schedule, tol=tol, nrhs_max=nrhs_max, **opt)
         o.stream = _stream_ptr(stream).value if torch.cuda.is_available() else None
         self.opts = o
         self.handle = None
         self.nout = 1
-        if weights is not None and nterms is not None:
+        if form == "multistep":
+            al = list(alpha)
+            ks = list(k) if isinstance(k, (list, tuple)) else [k] * len(al)
+            self.handle = bura_plan_create_multistep(dim, n, al, ks, o, coeff=coeff)
+        elif form == "product":
+            self.handle = bura_plan_create_product(dim, n, alpha, k, o, coeff=coeff)
+        elif form != "fractions":
+            raise ValueError("form must be 'fractions', 'multistep' or 'product'")
+        elif weights is not None and nterms is not None:
             self.handle = bura_plan_create_rational_multi(dim, n, nterms, weights, shifts, o, coeff=coeff)
             self.nout = len(nterms)
         elif weights is not None:

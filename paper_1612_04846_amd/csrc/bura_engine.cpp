@@ -69,6 +69,22 @@ size_t face_count(int dim, int n, int axis) {
 
 inline double hmean(double a, double b) { return 2.0 * a * b / (a + b); }
 
+// One stage of a sequential form: solve the terms [tb, te) against an input
+// vector (the caller's f, an earlier stage's output, or the solution of one
+// term) and write out = base_w * base + sum_j w_j x_j, where base is the
+// stage buffer (the previous stage's output) or nothing.  Stages run in order;
+// the last one writes the caller's u.  Used for the multi-step BURA
+// (Section 4.4) and the zero-pole product form (remark on the product form in
+// Section 2.2).
+struct Stage {
+  enum Input { F = 0, PREV = 1, SOL = 2 };
+  int tb = 0, te = 0;
+  int input = F;
+  int sol_term = 0;      // input == SOL: the term whose solution is the right-hand side
+  bool base = false;     // add base_w * (previous stage output)
+  double base_w = 0.0;
+};
+
 }  // namespace
 
 struct bura_plan_s {
@@ -83,6 +99,8 @@ struct bura_plan_s {
   // fractional powers of the same operator solved in one batch)
   int nout = 1;
   std::vector<int> out_begin, out_end;
+  std::vector<Stage> stages;   // empty: all terms at once against f
+  double* d_buf = nullptr;     // stage output between stages, nrhs_max x N FP64
   double E = 0.0;
   bura_opts_t opts{};
   hipStream_t stream = nullptr;
@@ -489,6 +507,7 @@ size_t footprint(const bura_plan_t P, size_t elem, bool mixed) {
   if (P->lc > 0)
     for (int l = 1; l <= P->lc; ++l) t += 3 * S * (size_t)P->lev[l].N * elem;
   if (mixed) t += S * (size_t)P->N * 8;
+  if (!P->stages.empty()) t += (size_t)P->opts.nrhs_max * P->N * 8;
   size_t maxblk = (size_t)std::max({stencil_blocks(P->dim, P->n), flat_blocks(P->N), up_blocks(P->dim, P->n),
                                     down_blocks(P->dim, P->n)});
   t += S * maxblk * 8;
@@ -894,11 +913,38 @@ int do_solve(bura_plan_t P, const double* f, double* u, int nrhs, bura_report_t*
   if ((rc = set_flags(P, P->st.flags, 0, (int)S_used, 0))) return rc;
   if ((rc = set_flags(P, P->st.total_iters, 0, (int)S_used, 0))) return rc;
   if ((rc = set_flags(P, P->st.outer, 0, (int)S_used, 0))) return rc;
-  auto batch = [&](size_t sys0, int nsys, bool preset) {
-    // the kernels take rhs = sys % R; pass f with R slots (rhs >= nrhs never active)
-    return mixed ? solve_batch_mixed(P, f, R, sys0, nsys, preset) : solve_batch_fp64(P, f, R, sys0, nsys, preset);
+  auto batch_rhs = [&](const double* rhs, size_t sys0, int nsys, bool preset) {
+    // the kernels take rhs = sys % R; pass rhs with R slots (rhs >= nrhs never active)
+    return mixed ? solve_batch_mixed(P, rhs, R, sys0, nsys, preset)
+                 : solve_batch_fp64(P, rhs, R, sys0, nsys, preset);
   };
-  if (P->opts.schedule == BURA_PER_POLE) {
+  auto batch = [&](size_t sys0, int nsys, bool preset) { return batch_rhs(f, sys0, nsys, preset); };
+  const double* xsol = mixed ? P->x64 : P->w64.x;
+  if (!P->stages.empty()) {
+    // sequential form: each stage solves its terms against its input, then
+    // combines into the stage buffer (or u for the last stage)
+    rc = BURA_OK;
+    for (size_t si = 0; si < P->stages.size() && rc == BURA_OK; ++si) {
+      const Stage& g = P->stages[si];
+      const bool last = si + 1 == P->stages.size();
+      const double* in = g.input == Stage::F ? f
+                         : g.input == Stage::PREV ? P->d_buf
+                                                  : xsol + (size_t)g.sol_term * R * P->N;
+      const size_t sys0 = (size_t)g.tb * R;
+      const int nt = g.te - g.tb;
+      if (nrhs == R) {
+        rc = batch_rhs(in, sys0, nt * R, false);
+      } else {
+        launch_slot_flags(P->st.active + sys0, nt, R, nrhs, P->stream);
+        if (mixed) launch_slot_flags(P->st.active64 + sys0, nt, R, nrhs, P->stream);
+        rc = batch_rhs(in, sys0, nt * R, true);
+      }
+      if (rc) break;
+      ProfScope ps(P, BURA_K_COMBINE);
+      launch_combine(P->N, xsol + sys0 * P->N, P->d_w + g.tb, nt, nrhs, R, last ? u : P->d_buf, P->stream, ps.ctr,
+                     g.base ? P->d_buf : nullptr, g.base_w);
+    }
+  } else if (P->opts.schedule == BURA_PER_POLE) {
     if (nrhs < R) {
       if ((rc = set_flags(P, P->st.active, 0, (int)S_used, 0))) return rc;
       if ((rc = set_flags(P, P->st.active64, 0, (int)S_used, 0))) return rc;
@@ -914,8 +960,7 @@ int do_solve(bura_plan_t P, const double* f, double* u, int nrhs, bura_report_t*
   }
   if (rc) return rc;
   // combine u_i = sum_{j in output i} w_j x_j (fixed order, FP64)
-  const double* xsol = mixed ? P->x64 : P->w64.x;
-  for (int i = 0; i < P->nout; ++i) {
+  for (int i = 0; i < P->nout && P->stages.empty(); ++i) {
     ProfScope ps(P, BURA_K_COMBINE);
     const int b = P->out_begin[i], e = P->out_end[i];
     launch_combine(P->N, xsol + (size_t)b * R * P->N, P->d_w + b, e - b, nrhs, R, u + (size_t)i * nrhs * P->N,
@@ -969,6 +1014,7 @@ struct Terms {
   std::vector<double> w, s;
   std::vector<int> begin{0};   // first term of each output
   double E = 0.0;
+  std::vector<Stage> stages;   // sequential form (one output), see Stage
 };
 
 int check_terms(const Terms& t) {
@@ -980,6 +1026,19 @@ int check_terms(const Terms& t) {
   }
   for (int j = 0; j < nterms; ++j)
     if (!(t.s[j] >= 0.0) || !std::isfinite(t.w[j]) || !std::isfinite(t.s[j])) return BURA_EINVAL;
+  if (!t.stages.empty()) {
+    if (t.begin.size() != 1) return BURA_EINVAL;
+    int next = 0;
+    for (size_t i = 0; i < t.stages.size(); ++i) {
+      const Stage& g = t.stages[i];
+      if (g.tb != next || g.te <= g.tb || g.te > nterms) return BURA_EINVAL;
+      if (i == 0 && (g.input != Stage::F || g.base)) return BURA_EINVAL;
+      if (g.input == Stage::SOL && (g.sol_term < 0 || g.sol_term >= g.tb)) return BURA_EINVAL;
+      if (!std::isfinite(g.base_w)) return BURA_EINVAL;
+      next = g.te;
+    }
+    if (next != nterms) return BURA_EINVAL;
+  }
   return BURA_OK;
 }
 
@@ -1042,6 +1101,7 @@ int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_p
     P->out_end.push_back(i + 1 < P->nout ? terms.begin[i + 1] : nterms);
   }
   P->E = terms.E;
+  P->stages = terms.stages;
   P->S = nterms * o.nrhs_max;
   const bool mixed = o.precision == BURA_MIXED;
   choose_lds(P, mixed ? 4 : 8);
@@ -1084,6 +1144,7 @@ int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_p
   P->partial_len = (size_t)P->S * maxblk;
   if ((rc = dev_alloc(P, (void**)&P->partial, P->partial_len * 8))) return fail(rc);
   if ((rc = dev_alloc(P, (void**)&P->d_w, nterms * 8))) return fail(rc);
+  if (!P->stages.empty() && (rc = dev_alloc(P, (void**)&P->d_buf, (size_t)o.nrhs_max * P->N * 8))) return fail(rc);
   if (hipMemcpyAsync(P->d_w, P->w.data(), nterms * 8, hipMemcpyHostToDevice, P->stream) != hipSuccess ||
       hipStreamSynchronize(P->stream) != hipSuccess)
     return fail(BURA_EDEVICE);
@@ -1197,6 +1258,70 @@ int bura_plan_create_sinc(const bura_grid_t* grid, int nalpha, const double* alp
     return BURA_OK;
   };
   return create(grid, Terms(), opts, out, late);
+}
+
+int bura_plan_create_multistep(const bura_grid_t* grid, int nsteps, const double* alphas, const int* ks,
+                               const bura_opts_t* opts, bura_plan_t* out) {
+  if (out) *out = nullptr;
+  if (!alphas || !ks || nsteps < 1 || nsteps > BURA_MAX_TERMS) return BURA_EINVAL;
+  Terms t;
+  double asum = 0.0;
+  for (int i = 0; i < nsteps; ++i) {
+    const int k = ks[i];
+    if (!(alphas[i] > 0.0 && alphas[i] < 1.0) || k < 1 || k > 16) return BURA_EINVAL;
+    asum += alphas[i];
+    std::vector<double> c(k + 1), d(k + 1);
+    double E = 0.0;
+    const int rc = bura_coefficients(alphas[i], 1, k, c.data(), d.data(), &E);
+    if (rc) return rc;
+    Stage g;
+    g.tb = (int)t.w.size();
+    for (int j = 0; j <= k; ++j) {
+      t.w.push_back(c[j]);
+      t.s.push_back(-d[j]);
+    }
+    g.te = (int)t.w.size();
+    g.input = i == 0 ? Stage::F : Stage::PREV;
+    t.stages.push_back(g);
+    t.E = std::max(t.E, E);
+  }
+  if (!(asum > 0.0) || (int)t.w.size() > BURA_MAX_TERMS) return BURA_EINVAL;
+  return create(grid, t, opts, out);
+}
+
+int bura_plan_create_product(const bura_grid_t* grid, double alpha, int beta, int k, const bura_opts_t* opts,
+                             bura_plan_t* out) {
+  if (out) *out = nullptr;
+  if (!(alpha > 0.0 && alpha < 1.0) || k < 1 || k > 16) return BURA_EINVAL;
+  if (beta != 1) return BURA_EUNSUPPORTED;
+  std::vector<double> c(k + 1), d(k + 1), zeta(k);
+  double E = 0.0, C = 0.0;
+  int rc = bura_coefficients(alpha, beta, k, c.data(), d.data(), &E);
+  if (rc) return rc;
+  if ((rc = bura_zeros(alpha, beta, k, zeta.data(), &C))) return rc;
+  // v_0 = A^-1 f; v_j = (A - zeta_j)(A - d_j)^-1 v_{j-1} = v_{j-1} + (d_j - zeta_j)(A - d_j)^-1 v_{j-1};
+  // u = C v_k, the constant folded into the last stage
+  Terms t;
+  t.w.push_back(1.0);
+  t.s.push_back(0.0);
+  Stage g0;
+  g0.tb = 0;
+  g0.te = 1;
+  t.stages.push_back(g0);
+  for (int j = 1; j <= k; ++j) {
+    const double scale = j == k ? C : 1.0;
+    t.w.push_back(scale * (d[j] - zeta[j - 1]));
+    t.s.push_back(-d[j]);
+    Stage g;
+    g.tb = j;
+    g.te = j + 1;
+    g.input = Stage::PREV;
+    g.base = true;
+    g.base_w = scale;
+    t.stages.push_back(g);
+  }
+  t.E = E;
+  return create(grid, t, opts, out);
 }
 
 int bura_plan_create_multi(const bura_grid_t* grid, int nalpha, const double* alphas, int beta, const int* ks,

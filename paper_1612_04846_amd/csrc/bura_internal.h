@@ -126,7 +126,7 @@ void launch_residual64(int dim, bool var, const LevelDev<double>& L, const doubl
 void launch_x_from_e(const LevelDev<double>& L, int dim, const float* e, double* x64, const int* active64,
                      int nsys, hipStream_t st);
 void launch_combine(long long N, const double* x, const double* w, int nterms, int nrhs, int stride, double* u,
-                    hipStream_t st, unsigned long long* ctr);
+                    hipStream_t st, unsigned long long* ctr, const double* base = nullptr, double base_w = 0.0);
 void launch_apply64(int dim, bool var, const LevelDev<double>& L, const double* x, double* y, double shift,
                     int nvec, hipStream_t st);
 void launch_scalars(int op, const double* partial, int nblk, int nsys, SysState st_, double tol,

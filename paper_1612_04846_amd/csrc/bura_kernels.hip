@@ -1107,15 +1107,17 @@ __global__ __launch_bounds__(256) void k_x_from_e(long long N, const float* __re
   }
 }
 
-// u[r] = sum_j w_j x[j * stride + r], summed in the fixed order j = 0..nterms-1 (eq. (16))
-__global__ __launch_bounds__(256) void k_combine(long long N, const double* __restrict__ x,
-                                                 const double* __restrict__ w, int nterms, int stride,
-                                                 double* __restrict__ u, unsigned long long* __restrict__ ctr) {
+// u[r] = base_w base[r] + sum_j w_j x[j * stride + r], summed in the fixed order
+// base, j = 0..nterms-1 (eq. (16); the base term serves the sequential forms).
+// base may be u itself (each element is read before it is written).
+__global__ __launch_bounds__(256) void k_combine(long long N, const double* x, const double* __restrict__ w,
+                                                 int nterms, int stride, double* u, const double* base,
+                                                 double base_w, unsigned long long* __restrict__ ctr) {
   const int r = blockIdx.y;
   const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
-  count_bytes<COUNT_FLAT>(ctr, (unsigned long long)N * 8ULL * (nterms + 1));
+  count_bytes<COUNT_FLAT>(ctr, (unsigned long long)N * 8ULL * (nterms + 1 + (base ? 1 : 0)));
   if (p >= N) return;
-  double acc = 0.0;
+  double acc = base ? base_w * base[(long long)r * N + p] : 0.0;
   for (int j = 0; j < nterms; ++j) acc += w[j] * x[((long long)j * stride + r) * N + p];
   u[(long long)r * N + p] = acc;
 }
@@ -1481,9 +1483,9 @@ void launch_x_from_e(const LevelDev<double>& L, int dim, const float* e, double*
 }
 
 void launch_combine(long long N, const double* x, const double* w, int nterms, int nrhs, int stride, double* u,
-                    hipStream_t st, unsigned long long* ctr) {
+                    hipStream_t st, unsigned long long* ctr, const double* base, double base_w) {
   const dim3 g((unsigned)((N + 255) / 256), nrhs);
-  hipLaunchKernelGGL(k_combine, g, dim3(256), 0, st, N, x, w, nterms, stride, u, ctr);
+  hipLaunchKernelGGL(k_combine, g, dim3(256), 0, st, N, x, w, nterms, stride, u, base, base_w, ctr);
 }
 
 void launch_apply64(int dim, bool var, const LevelDev<double>& L, const double* x, double* y, double shift, int nvec,

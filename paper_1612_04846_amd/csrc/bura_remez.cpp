@@ -17,7 +17,10 @@
 //     inverse iteration with Rayleigh-quotient updates;
 //   * a pole-free solution has weights b_j alternating in sign;
 //   * the poles are the zeros of D on t < 0 (bracketed on a log grid, then
-//     bisected), and c_j = N(d_j) / (d_j D'(d_j)), c_0 = r(0) = E (eq. (23)).
+//     bisected), and c_j = N(d_j) / (d_j D'(d_j)), c_0 = r(0) = E (eq. (23));
+//   * the zeros of r (for the product form of Section 2.2's remark) are the
+//     zeros of N on t < 0, found the same way, and the leading constant is
+//     lim r(t) = sum a_j / sum b_j as t -> infinity.
 // Initial reference set: interpolation at 2k+1 nodes placed by a model of
 // the extremal-point distribution (sqrt(-log t) about equispaced, smallest
 // ~30 E^(1/(1-alpha)) with E from the asymptotic formula eq. (14)), moved by
@@ -324,7 +327,7 @@ bool levelled(const Problem& P, const std::vector<Q>& x, int k, Q& E, Bary& r) {
 }
 
 int remez_q(double alpha, int k, std::vector<double>& c_out, std::vector<double>& d_out, double& E_out,
-            std::string& why) {
+            std::vector<double>& zeta_out, double& C_out, std::string& why) {
   Problem P;
   P.g = 1 - Q(alpha);
   std::vector<Q> ref;
@@ -360,30 +363,50 @@ int remez_q(double alpha, int k, std::vector<double>& c_out, std::vector<double>
   }
   if (!ok) { why = "exchange did not level"; return BURA_EREMEZ; }
   if (!levelled(P, ref, k, E, r)) { why = "final levelled solve failed"; return BURA_EREMEZ; }
-  // poles: zeros of D(t) on t < 0
+  // poles: zeros of D(t) on t < 0; zeros of r: zeros of N(t) on t < 0 (no
+  // support point lies there, so N and D have no common singularity)
   auto D = [&](Q t) { Q s = 0; for (size_t j = 0; j < r.z.size(); ++j) s += r.b[j] / (t - r.z[j]); return s; };
   auto Dp = [&](Q t) { Q s = 0; for (size_t j = 0; j < r.z.size(); ++j) { Q dt = t - r.z[j]; s -= r.b[j] / (dt * dt); } return s; };
   auto N = [&](Q t) { Q s = 0; for (size_t j = 0; j < r.z.size(); ++j) s += r.a[j] / (t - r.z[j]); return s; };
-  std::vector<Q> poles;
-  const Q u0 = -200, u1 = 30, du = Q(0.01);   // t = -exp(u)
-  Q uprev = u0, dprev = D(-expq(u0));
-  for (Q u = u0 + du; u <= u1; u += du) {
-    const Q dv = D(-expq(u));
-    if ((dv > 0) != (dprev > 0)) {
-      Q lo = uprev, hi = u, flo = dprev;
-      for (int i = 0; i < 200; ++i) {
-        const Q mid = (lo + hi) / 2;
-        const Q fm = D(-expq(mid));
-        if ((fm > 0) == (flo > 0)) { lo = mid; flo = fm; } else hi = mid;
-        if (hi - lo < Q(1e-33)) break;
+  auto negative_roots = [](auto&& fn) {
+    std::vector<Q> roots;
+    const Q u0 = -200, u1 = 30, du = Q(0.01);   // t = -exp(u)
+    Q uprev = u0, fprev = fn(-expq(u0));
+    for (Q u = u0 + du; u <= u1; u += du) {
+      const Q fv = fn(-expq(u));
+      if ((fv > 0) != (fprev > 0)) {
+        Q lo = uprev, hi = u, flo = fprev;
+        for (int i = 0; i < 200; ++i) {
+          const Q mid = (lo + hi) / 2;
+          const Q fm = fn(-expq(mid));
+          if ((fm > 0) == (flo > 0)) { lo = mid; flo = fm; } else hi = mid;
+          if (hi - lo < Q(1e-33)) break;
+        }
+        roots.push_back(-expq((lo + hi) / 2));
       }
-      poles.push_back(-expq((lo + hi) / 2));
+      uprev = u;
+      fprev = fv;
     }
-    uprev = u;
-    dprev = dv;
-  }
+    std::sort(roots.begin(), roots.end(), [](Q a, Q b) { return a > b; });   // descending
+    return roots;
+  };
+  std::vector<Q> poles = negative_roots(D);
   if ((int)poles.size() != k) { why = "pole count differs from k"; return BURA_EREMEZ; }
-  std::sort(poles.begin(), poles.end(), [](Q a, Q b) { return a > b; });   // 0 > d_1 > ... > d_k
+  std::vector<Q> zeros = negative_roots(N);
+  if ((int)zeros.size() != k) { why = "zero count differs from k"; return BURA_EREMEZ; }
+  // Lemma 2.5: 0 > zeta_1 > d_1 > zeta_2 > ... > zeta_k > d_k
+  for (int j = 0; j < k; ++j)
+    if (!(zeros[j] > poles[j]) || (j > 0 && !(zeros[j] < poles[j - 1]))) {
+      why = "zeros and poles do not interlace";
+      return BURA_EREMEZ;
+    }
+  {
+    Q sa = 0, sb = 0;   // r(t) -> sum a / sum b as t -> infinity: the leading constant
+    for (size_t j = 0; j < r.z.size(); ++j) { sa += r.a[j]; sb += r.b[j]; }
+    C_out = (double)(sa / sb);
+  }
+  zeta_out.assign(k, 0.0);
+  for (int j = 0; j < k; ++j) zeta_out[j] = (double)zeros[j];
   c_out.assign(k + 1, 0.0);
   d_out.assign(k + 1, 0.0);
   c_out[0] = (double)r.eval(0);   // = E, eq. (23)
@@ -398,13 +421,17 @@ int remez_q(double alpha, int k, std::vector<double>& c_out, std::vector<double>
   return BURA_OK;
 }
 
+struct Cached {
+  std::vector<double> c, d, zeta;
+  double E = 0.0, C = 0.0;
+};
 std::mutex g_mu;
-std::map<std::pair<uint64_t, int>, std::pair<std::vector<double>, std::vector<double>>> g_cache;
-std::map<std::pair<uint64_t, int>, double> g_cacheE;
+std::map<std::pair<uint64_t, int>, Cached> g_cache;
 
 }  // namespace
 
-int remez_bura(double alpha, int k, std::vector<double>& c, std::vector<double>& d, double& E, std::string& why) {
+int remez_bura_full(double alpha, int k, std::vector<double>& c, std::vector<double>& d, double& E,
+                    std::vector<double>& zeta, double& C, std::string& why) {
   uint64_t bits;
   std::memcpy(&bits, &alpha, 8);
   const auto key = std::make_pair(bits, k);
@@ -412,19 +439,31 @@ int remez_bura(double alpha, int k, std::vector<double>& c, std::vector<double>&
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_cache.find(key);
     if (it != g_cache.end()) {
-      c = it->second.first;
-      d = it->second.second;
-      E = g_cacheE[key];
+      c = it->second.c;
+      d = it->second.d;
+      E = it->second.E;
+      zeta = it->second.zeta;
+      C = it->second.C;
       return BURA_OK;
     }
   }
-  const int rc = remez_q(alpha, k, c, d, E, why);
+  const int rc = remez_q(alpha, k, c, d, E, zeta, C, why);
   if (rc == BURA_OK) {
     std::lock_guard<std::mutex> lk(g_mu);
-    g_cache[key] = std::make_pair(c, d);
-    g_cacheE[key] = E;
+    Cached& e = g_cache[key];
+    e.c = c;
+    e.d = d;
+    e.E = E;
+    e.zeta = zeta;
+    e.C = C;
   }
   return rc;
+}
+
+int remez_bura(double alpha, int k, std::vector<double>& c, std::vector<double>& d, double& E, std::string& why) {
+  std::vector<double> zeta;
+  double C = 0.0;
+  return remez_bura_full(alpha, k, c, d, E, zeta, C, why);
 }
 
 }  // namespace bura
@@ -440,5 +479,17 @@ extern "C" int bura_coefficients(double alpha, int beta, int k, double* c, doubl
     c[j] = cc[j];
     d[j] = dd[j];
   }
+  return BURA_OK;
+}
+
+extern "C" int bura_zeros(double alpha, int beta, int k, double* zeta, double* C) {
+  if (!(alpha > 0 && alpha < 1) || k < 1 || k > 16 || !zeta || !C) return BURA_EINVAL;
+  if (beta != 1) return BURA_EUNSUPPORTED;
+  std::vector<double> cc, dd, zz;
+  double E = 0.0;
+  std::string why;
+  const int rc = bura::remez_bura_full(alpha, k, cc, dd, E, zz, *C, why);
+  if (rc) return rc;
+  for (int j = 0; j < k; ++j) zeta[j] = zz[j];
   return BURA_OK;
 }
