@@ -184,8 +184,7 @@ int bura_plan_create_sinc(const bura_grid_t* grid, int nalpha, const double* alp
  * steps run one after the other (each step's systems in one batch); the plan
  * holds one extra nrhs_max x N FP64 buffer between steps.  bura_solve writes
  * u_n; the report's E is the largest E_{alphas[i]}(ks[i],ks[i];1) (the error
- * of the composition depends on the condition number, eq. (general 2-step
- * error)). */
+ * of the composition depends on the condition number, eq. (29)). */
 int bura_plan_create_multistep(const bura_grid_t* grid, int nsteps, const double* alphas, const int* ks,
                                const bura_opts_t* opts, bura_plan_t* out);
 

@@ -22,7 +22,7 @@ of sparse SPD matrices" (arXiv:1612.04846) that it follows):
                   u_r = sum_j c_j (A - d_j I)^-1 f evaluated in the closed-form
                   sine eigenbasis of the constant-coefficient Laplacian.
 * ``shifted``  -- u_r by k+1 shifted sparse solves, eq. (eq:Rgeneral).
-* ``metrics``  -- relative errors and the error-lemma norms of eq. (bound).
+* ``metrics``  -- relative errors and the error-lemma norms of eq. (12) (Lemma 2.1).
 * ``multistep`` -- the multi-step BURA of Section 4.4 (sequential 1-BURA
                   steps) and its eigenvector errors.
 * ``product``  -- the zero-pole product form of the remark in Section 2.2

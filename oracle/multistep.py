@@ -5,8 +5,8 @@ each factor is replaced by its 1-BURA, u_i = r_{alpha_i}(A) A^-1 u_{i-1}
 (eq. (16) with u_0 = f), applied in the order the steps are given.  The
 error of the composition over an eigenvector Psi with eigenvalue lambda is
 |lambda prod_i (r_i(lambda)/lambda) - lambda^(1-alpha)| in the ratio
-||u_n - u||_A / ||f||_A^-1 of eq. (bound) with gamma = 1 (the quantity of
-eq. (multi-step error)).
+||u_n - u||_A / ||f||_A^-1 of eq. (12) (Lemma 2.1) with gamma = 1 (the quantity of
+eq. (28)).
 """
 
 from __future__ import annotations
@@ -45,5 +45,5 @@ def eigvec_errors_1d(N: int, steps, alpha: float) -> tuple[float, float]:
 
 
 def two_step_bound(E1: float, E2: float, alpha1: float, alpha2: float, kappa: float) -> float:
-    """Right-hand side of eq. (general 2-step error)."""
+    """Right-hand side of eq. (29)."""
     return E2 * kappa ** alpha1 + E1 * kappa ** alpha2 + E1 * E2 * kappa

@@ -20,6 +20,9 @@ Follows the paper (arXiv:1612.04846):
 * Lemma 2.5 and eq. (15): for m = k, beta = 1 the poles are real, negative and
   simple; r(t)/t = sum_{j=0..k} c_j/(t - d_j) with d_0 = 0.  The weights are the
   residues of P/(t Q): c_0 = P(0)/Q(0) = r(0) and c_j = P(d_j)/(d_j Q'(d_j)).
+* Section 4.1 for beta > 1 (m - k < beta): polynomial part and simple
+  fractions of P/Q, then the relations of eq. (22) give the weights of
+  eq. (25), c_{0,i} for A^-i f (i = 1..beta) and c_j for (A - d_j)^-1 f.
 
 Readings where the paper is silent (also listed in the design notes):
 
@@ -97,6 +100,9 @@ class Bura:
     q: List[mp.mpf] = field(default_factory=list)
     d: List[mp.mpf] = field(default_factory=list)   # poles, d_0 = 0 > d_1 > ... (beta=1, m=k)
     c: List[mp.mpf] = field(default_factory=list)   # residues of r(t)/t
+    # beta > 1 (eq. (25)): c0[i-1] = c_{0,i} multiplies A^-i f, i = 1..beta; then
+    # c = [c_{0,1}, c_1, ..., c_k] and d = [0, d_1, ..., d_k] as for beta = 1
+    c0: List[mp.mpf] = field(default_factory=list)
 
     # -- evaluation helpers (multiprecision) -------------------------------
     def r(self, t):
@@ -381,6 +387,8 @@ def remez(alpha, k, m=None, beta=1, dps=None, delta_rel=1e-20, max_iter=60,
         _monomial(res)
         if beta == 1 and m == k:
             _partial_fractions(res)
+        elif beta > 1 and 0 <= m - k < beta:
+            _partial_fractions_beta(res)
         return res
 
 
@@ -421,6 +429,43 @@ def _monomial(res: Bura):
 
 def _poly(coefs, t):
     return mp.fsum(cf * t ** i for i, cf in enumerate(coefs))
+
+
+def _polydiv(num, den):
+    """Quotient and remainder of num/den (ascending monomial coefficients)."""
+    num = list(num)
+    dq = len(den) - 1
+    quo = [mp.mpf(0)] * max(1, len(num) - dq)
+    for i in range(len(num) - 1, dq - 1, -1):
+        f = num[i] / den[dq]
+        quo[i - dq] = f
+        for j in range(dq + 1):
+            num[i - dq + j] -= f * den[j]
+    return quo, num[:dq]
+
+
+def _partial_fractions_beta(res: Bura):
+    """Section 4.1 for beta > 1 with m - k < beta: P/Q = sum_{j<beta} b_j t^j +
+    sum_j c*_j/(t - d_j) (polynomial division, simple real poles), then eq. (22):
+    c_{0,i} = b_{beta-i} - sum_j c*_j / d_j^(beta-i+1) and c_j = c*_j / d_j^beta."""
+    beta = res.beta
+    roots = mp.polyroots(list(reversed(res.q)), maxsteps=400, extraprec=4 * res.dps)
+    d = []
+    for z in roots:
+        if abs(mp.im(z)) > mp.mpf(10) ** (-(res.dps // 3)) * (1 + abs(z)):
+            raise RemezError("complex pole: partial fractions with p_2 > 0 are not covered")
+        d.append(mp.re(z))
+    if any(x >= 0 for x in d):
+        raise RemezError("non-negative pole")
+    d = sorted(d, reverse=True)
+    quo, _ = _polydiv(res.p, res.q)
+    b = [quo[j] if j < len(quo) else mp.mpf(0) for j in range(beta)]
+    dq = [i * res.q[i] for i in range(1, len(res.q))]
+    cstar = [_poly(res.p, dj) / _poly(dq, dj) for dj in d]
+    c0 = [b[beta - i] - mp.fsum(cs / dj ** (beta - i + 1) for cs, dj in zip(cstar, d)) for i in range(1, beta + 1)]
+    res.c0 = c0
+    res.d = [mp.mpf(0)] + d
+    res.c = [c0[0]] + [cs / dj ** beta for cs, dj in zip(cstar, d)]
 
 
 def _partial_fractions(res: Bura):

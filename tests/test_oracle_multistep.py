@@ -32,7 +32,7 @@ def test_tables13_14_eigenvector_columns(k):
 
 
 def test_two_step_error_within_bound_and_order_free():
-    """eq. (general 2-step error) bounds the A-norm error over every eigenvector, and
+    """eq. (29) bounds the A-norm error over every eigenvector, and
     the product form makes the order of the steps irrelevant (up to rounding)."""
     n = 31
     F = synth.normal_rhs(n, 2, nrhs=2, tag=31)
