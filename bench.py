@@ -57,6 +57,10 @@ WORKLOADS = {
                                      method="multistep"),
     "2d1023-product-k9-fp64": dict(dim=2, n=1023, alphas=(0.5,), k=9, nrhs=1, rhs="normal", tag=2,
                                    precision="FP64", schedule="BATCHED", tol=1e-10, var=False, method="product"),
+    # the 2-BURA of t^(2 - alpha) (Section 4.1), alpha 0.5, (m,k) = (7,6): 7 systems
+    # together, then the chained A^-1 of the pole-0 solution
+    "2d1023-beta2-k6-fp64": dict(dim=2, n=1023, alphas=(0.5,), k=6, nrhs=1, rhs="normal", tag=2,
+                                 precision="FP64", schedule="BATCHED", tol=1e-12, var=False, method="beta2"),
     "2d1023-sinc-fp64-multi": dict(dim=2, n=1023, alphas=(0.25, 0.5, 0.75), k=None, kq=(9, 7, 6), nrhs=1,
                                    rhs="checkerboard", tag=0, precision="FP64", schedule="BATCHED", tol=1e-10,
                                    var=False, multi=True, method="sinc"),
@@ -76,6 +80,9 @@ def describe(w):
     elif w.get("method") == "multistep":
         what = f"alpha={sum(w['alphas'])} as multi-step BURA steps {list(w['alphas'])}, k={w['k']} each"
         sched = "sequential steps, each step's poles batched"
+    elif w.get("method") == "beta2":
+        what = f"alpha={w['alphas'][0]}, beta=2, (m,k)=({w['k'] + 1},{w['k']}) 2-BURA"
+        sched = "k+1 systems batched, then the chained solve"
     elif w.get("method") == "product":
         what = f"alpha={w['alphas'][0]}, beta=1, k={w['k']}, zero-pole product form"
         sched = "sequential factors"
@@ -121,6 +128,8 @@ def run_gpu(w, steps, warmup, profile=True):
             kw["kprime"] = [B.sinc_kprime(x, kq[x]) for x in al]
         if w.get("method") in ("multistep", "product"):
             kw["form"] = w["method"]
+        if w.get("method") == "beta2":
+            kw["beta"] = 2
         plans.append(B.Plan(w["dim"], w["n"], a, w["k"], **kw))
     t_plan = time.perf_counter() - t_plan
     outs = [torch.empty((p.nout,) + tuple(F.shape), dtype=F.dtype, device=dev) if p.nout > 1 else torch.empty_like(F)
@@ -235,6 +244,11 @@ def oracle_errors(w, res):
             rec = gold[f"{a:.2f},{w['k']}"]
             steps.append(([float(x) for x in rec["c"]], [float(x) for x in rec["d"]]))
         return [metrics.rel_err(res["U"][0], multistep.multistep_spectral(res["F"], w["dim"], steps))]
+    if w.get("method") == "beta2":
+        # 2-BURA coefficients of the oracle (multiprecision Remez, a few seconds)
+        from oracle import remez as oremez
+        o = oremez.remez(w["alphas"][0], w["k"], m=w["k"] + 1, beta=2)
+        return [metrics.rel_err(res["U"][0], spectral.bura_beta_spectral(res["F"], w["dim"], o.c0, o.c, o.d))]
     for i, (a, U) in enumerate(zip(w["alphas"], res["U"])):
         if w.get("method") == "sinc":
             kp = quadrature.sinc_kprime(a, w["kq"][i])
@@ -362,7 +376,8 @@ def main():
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of this many GiB (counter calibration)")
     ap.add_argument("--also", default="2d1023-k9-fp64-per-pole,2d1023-k9-fp64-batched,2d1023-k9-mixed-multi,"
-                                      "2d1023-sinc-fp64-multi,2d1023-multistep-k9-fp64,2d1023-product-k9-fp64",
+                                      "2d1023-sinc-fp64-multi,2d1023-multistep-k9-fp64,2d1023-product-k9-fp64,"
+                                      "2d1023-beta2-k6-fp64",
                     help="comma-separated extra workloads reported under 'paths' (empty: none)")
     args = ap.parse_args()
     if args.copy_probe > 0:

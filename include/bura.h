@@ -122,9 +122,12 @@ int bura_opts_default(bura_opts_t* o);
  * approximation of t^(1-alpha) on [0,1] (Definition 2.1) by a Remez exchange
  * (Section 3.2) in extended precision, and its partial fractions eq. (15).
  * Writes c[0..k], d[0..k] (d[0] = 0 > d[1] > ... > d[k]) and *E.
- * alpha in (0,1), beta == 1 (else BURA_EUNSUPPORTED), 1 <= k <= 16.
- * Returns BURA_EREMEZ if the exchange does not level.  Results are cached
- * per (alpha, k) for the life of the process. */
+ * beta == 2: the (k+1,k) 2-BURA of t^(2-alpha) (Section 4.1) with
+ * r(t)/t^2 = c_{0,2}/t^2 + c_{0,1}/t + sum_j c_j/(t - d_j) (eq. (22), (25)):
+ * c[0] = c_{0,1}, c[1..k], and c[k+1] = c_{0,2} (= -E, eq. (23)), so c needs
+ * k+2 doubles.  alpha in (0,1), beta 1 or 2 (else BURA_EUNSUPPORTED),
+ * 1 <= k <= 16.  Returns BURA_EREMEZ if the exchange does not level.
+ * Results are cached per (alpha, beta, k) for the life of the process. */
 int bura_coefficients(double alpha, int beta, int k, double* c, double* d, double* E);
 
 /* The zeros of the same (k,k) BURA r (Lemma 2.5: real, negative, interlacing
@@ -139,6 +142,11 @@ int bura_zeros(double alpha, int beta, int k, double* zeta, double* C);
  * the plan on success and NULL otherwise. */
 int bura_plan_create(const bura_grid_t* grid, double alpha, int beta, int k,
                      const bura_opts_t* opts, bura_plan_t* out);
+/* (beta == 2 runs k+2 systems: the k+1 of c_{0,1} A^-1 f + sum_j c_j (A - d_j)^-1 f
+ * together, then A^-1 applied to the pole-0 solution for the c_{0,2} A^-2 f
+ * term (eq. (25); Section 4.3's chained solve).  The negative c_{0,2} makes
+ * the FP64 combine subtract large terms; errors grow like E kappa(A)^(beta-1)
+ * (the corollary in Section 4.3).) */
 
 /* Same engine for a caller-given partial-fraction form
  * u = sum_{j<nterms} w[j] (A + shift[j] I)^{-1} f, shift[j] >= 0, w[j] any sign

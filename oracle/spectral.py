@@ -78,3 +78,16 @@ def energy_norm(X: np.ndarray, dim: int, gamma: float) -> np.ndarray:
     G = to_eigenbasis(X, dim)
     axes = tuple(range(X.ndim - dim, X.ndim))
     return np.sqrt(np.sum(lam ** gamma * G ** 2, axis=axes))
+
+
+def bura_beta_spectral(F: np.ndarray, dim: int, c0, c, d) -> np.ndarray:
+    """eq. (25) in the eigenbasis: u_r = sum_i c0[i-1] A^-i f + sum_{j>=1} c_j (A - d_j I)^-1 f,
+    i = 1..beta (c[0], d[0] belong to the pole at 0 and are carried by c0)."""
+    def phi(lam):
+        out = np.zeros_like(lam)
+        for i, ci in enumerate(c0, start=1):
+            out = out + float(ci) / lam ** i
+        for cj, dj in zip(c[1:], d[1:]):
+            out = out + float(cj) / (lam - float(dj))
+        return out
+    return apply_function(F, dim, phi)

@@ -195,12 +195,13 @@ def bura_opts_default(**overrides) -> bura_opts_t:
 
 
 def bura_coefficients(alpha: float, k: int, beta: int = 1):
-    """(c, d, E) of the (k,k) BURA of t^(1-alpha), computed by the library's host code."""
-    c = (ctypes.c_double * (k + 1))()
+    """(c, d, E) of the (k,k) BURA of t^(1-alpha), computed by the library's host code.
+    beta = 2: the (k+1,k) 2-BURA; c then has k+2 entries, c[k+1] = c_{0,2}."""
+    c = (ctypes.c_double * (k + 2))()
     d = (ctypes.c_double * (k + 1))()
     E = ctypes.c_double()
     _check(_lib.bura_coefficients(alpha, beta, k, c, d, ctypes.byref(E)), "bura_coefficients")
-    return list(c), list(d), E.value
+    return list(c)[: k + 1 + (beta == 2)], list(d), E.value
 
 
 def _grid(dim, n, coeff=None, lambda_upper=0.0):
@@ -430,13 +431,14 @@ class Plan:
     """Owns a plan handle; ``solve(f)`` returns A^-alpha f for a batch f of shape (nrhs, n, ..., n)."""
 
     def __init__(self, dim, n, alpha=None, k=None, *, weights=None, shifts=None, nterms=None, kprime=None,
-                 form="fractions", coeff=None, precision=BURA_MIXED, schedule=BURA_BATCHED, tol=1e-12, nrhs_max=1,
-                 stream=None, **opt):
+                 form="fractions", beta=1, coeff=None, precision=BURA_MIXED, schedule=BURA_BATCHED, tol=1e-12,
+                 nrhs_max=1, stream=None, **opt):
         """alpha (one value or a list) with k poles: the BURA; alpha with kprime
         (one value or lists): the sinc quadrature of step k'; weights/shifts
         (with nterms per output for several outputs): a caller-given form.
         form="multistep" (alpha and k lists: the steps, in order) or
-        form="product" (one alpha): the sequential forms."""
+        form="product" (one alpha): the sequential forms.  beta=2: the (k+1,k)
+        2-BURA of t^(2-alpha)."""
         self.dim, self.n = dim, n
         o = bura_opts_default(precision=precision, schedule=schedule, tol=tol, nrhs_max=nrhs_max, **opt)
         o.stream = _stream_ptr(stream).value if torch.cuda.is_available() else None
@@ -466,7 +468,7 @@ class Plan:
             self.handle = bura_plan_create_multi(dim, n, list(alpha), ks, o, coeff=coeff)
             self.nout = len(alpha)
         else:
-            self.handle = bura_plan_create(dim, n, alpha, k, o, coeff=coeff)
+            self.handle = bura_plan_create(dim, n, alpha, k, o, coeff=coeff, beta=beta)
 
     @property
     def coeffs(self):

@@ -1359,17 +1359,35 @@ int bura_plan_create(const bura_grid_t* grid, double alpha, int beta, int k, con
                      bura_plan_t* out) {
   if (out) *out = nullptr;
   if (!(alpha > 0.0 && alpha < 1.0) || k < 1 || k > 16) return BURA_EINVAL;
-  if (beta != 1) return BURA_EUNSUPPORTED;
-  std::vector<double> c(k + 1), d(k + 1);
+  if (beta != 1 && beta != 2) return BURA_EUNSUPPORTED;
+  std::vector<double> c(k + 2), d(k + 1);
   double E = 0.0;
   int rc = bura_coefficients(alpha, beta, k, c.data(), d.data(), &E);
   if (rc) return rc;
-  std::vector<double> s(k + 1);
-  for (int j = 0; j <= k; ++j) s[j] = -d[j];
   Terms t;
-  t.w = c;
-  t.s = s;
+  for (int j = 0; j <= k; ++j) {
+    t.w.push_back(c[j]);
+    t.s.push_back(-d[j]);
+  }
   t.E = E;
+  if (beta == 2) {
+    // eq. (25) with beta = 2: the k+1 systems of c_{0,1} A^-1 f + sum_j c_j (A - d_j)^-1 f
+    // in one stage, then A^-2 f = A^-1 (A^-1 f) from the first stage's pole-0
+    // solution, added with c_{0,2} (Section 4.3's chained solve)
+    t.w.push_back(c[k + 1]);
+    t.s.push_back(0.0);
+    Stage g0;
+    g0.tb = 0;
+    g0.te = k + 1;
+    Stage g1;
+    g1.tb = k + 1;
+    g1.te = k + 2;
+    g1.input = Stage::SOL;
+    g1.sol_term = 0;
+    g1.base = true;
+    g1.base_w = 1.0;
+    t.stages = {g0, g1};
+  }
   return create(grid, t, opts, out);
 }
 

@@ -1,7 +1,9 @@
 // Host computation of the (k,k) best uniform rational approximation r of
 // t^(1-alpha) on [0,1] (Definition 2.1) and of its partial fractions
 // r(t)/t = sum_{j=0..k} c_j/(t - d_j), d_0 = 0 > d_1 > ... > d_k (eq. (15),
-// Lemma 2.5), in __float128 arithmetic.
+// Lemma 2.5), in __float128 arithmetic; and of the (k+1,k) 2-BURA of
+// t^(2-alpha) with r(t)/t^2 = c_{0,2}/t^2 + c_{0,1}/t + sum_j c_j/(t - d_j)
+// (Section 4.1, eq. (22)-(25)).
 //
 // Same mathematics as the modified Remez algorithm of Section 3.2 (levelled
 // equations f(x_i) - r(x_i) = (-1)^i E on 2k+2 reference points, Step 3;
@@ -11,7 +13,8 @@
 // because the alternation points cluster geometrically at t = 0 (Table 5), so
 // here r = N/D is kept in barycentric form
 //     N(t) = sum_j a_j/(t - z_j),  D(t) = sum_j b_j/(t - z_j)
-// with the support points z_j at every other reference point.  Then
+// with the support points z_j at every other reference point (for type
+// (k+1,k) N has one more term, a constant).  Then
 //   * the levelled system is a (k+1)x(k+1) pencil (L + 2E C) b = 0 (L a Loewner,
 //     C a Cauchy matrix), solved for the E nearest the current estimate by
 //     inverse iteration with Rayleigh-quotient updates;
@@ -47,8 +50,9 @@ inline Q qabs(Q x) { return x < 0 ? -x : x; }
 
 struct Bary {
   std::vector<Q> z, a, b;   // support points, numerator and denominator weights
+  Q ainf = 0;               // constant numerator term: type (k+1, k) instead of (k, k)
   Q eval(Q t) const {
-    Q n = 0, d = 0;
+    Q n = ainf, d = 0;
     for (size_t j = 0; j < z.size(); ++j) {
       const Q dt = t - z[j];
       if (dt == 0) return a[j] / b[j];
@@ -60,7 +64,8 @@ struct Bary {
 };
 
 struct Problem {
-  Q g;   // exponent 1 - alpha
+  Q g;        // exponent beta - alpha
+  int ex = 0;  // numerator degree minus denominator degree: 0 (beta = 1) or 1 (beta = 2)
   Q f(Q t) const { return t <= 0 ? Q(0) : powq(t, g); }
 };
 
@@ -180,19 +185,25 @@ Q zero_between(const F& e, Q lo, Q hi) {
 // ---- stage 1: interpolation and node equalisation ---------------------------
 
 bool interpolant(const Problem& P, const std::vector<Q>& X, int k, Bary& r) {
-  // support: X[0], X[2], ..., X[2k]; test nodes X[1], X[3], ..., X[2k-1]
+  // support: X[0], X[2], ..., X[2k]; test nodes X[1], X[3], ..., X[2k-1] and,
+  // for type (k+1, k), X[2k+1].  At a test node y: ainf + sum_j (f(z_j) - f(y)) b_j/(y - z_j) = 0.
   r.z.clear(); r.a.clear(); r.b.clear();
+  r.ainf = 0;
   std::vector<Q> y, fy, fz;
-  for (int i = 0; i < 2 * k + 1; ++i) {
-    if (i % 2 == 0) { r.z.push_back(X[i]); fz.push_back(P.f(X[i])); }
+  for (int i = 0; i < 2 * k + 1 + P.ex; ++i) {
+    if (i % 2 == 0 && i <= 2 * k) { r.z.push_back(X[i]); fz.push_back(P.f(X[i])); }
     else { y.push_back(X[i]); fy.push_back(P.f(X[i])); }
   }
-  std::vector<Q> L(k * (k + 1));
-  for (int i = 0; i < k; ++i)
-    for (int j = 0; j <= k; ++j) L[i * (k + 1) + j] = (fy[i] - fz[j]) / (y[i] - r.z[j]);
-  std::vector<Q> bvec;
-  if (!null_vector(L, k, bvec)) return false;
-  r.b = bvec;
+  const int rows = k + P.ex, cols = k + 1 + P.ex;
+  std::vector<Q> L(rows * cols);
+  for (int i = 0; i < rows; ++i) {
+    for (int j = 0; j <= k; ++j) L[i * cols + j] = (fy[i] - fz[j]) / (y[i] - r.z[j]);
+    if (P.ex) L[i * cols + k + 1] = -1;
+  }
+  std::vector<Q> v;
+  if (!null_vector(L, rows, v)) return false;
+  r.b.assign(v.begin(), v.begin() + k + 1);
+  if (P.ex) r.ainf = v[k + 1];
   r.a.resize(k + 1);
   for (int j = 0; j <= k; ++j) r.a[j] = fz[j] * r.b[j];
   return true;
@@ -203,7 +214,7 @@ Q stahl(Q g, int k) {   // eq. (14) with beta = 1
 }
 
 bool initial_reference(const Problem& P, int k, std::vector<Q>& ref, Q& E0, std::string& why) {
-  const int n = 2 * k + 1;
+  const int n = 2 * k + 1 + P.ex;   // interpolation nodes = degrees of freedom
   const Q tmin = 30 * powq(stahl(P.g, k), 1 / P.g);
   const Q a_ = sqrtq(-logq(tmin)) / n;
   std::vector<Q> eta(n + 1);
@@ -268,26 +279,30 @@ bool initial_reference(const Problem& P, int k, std::vector<Q>& ref, Q& E0, std:
 
 // ---- stage 2: levelled barycentric solve + exchange ---------------------------
 
-// reference x[0..2k+1] (x[0] = 0, x[2k+1] = 1); support = even positions.
-// Solve (L + 2E C) b = 0 for the E nearest Eguess.
+// reference x[0..2k+1+ex] (x[0] = 0, last = 1); support = even positions
+// 0..2k.  Solve (L + 2E C) v = 0 for the E nearest Eguess, v = (b, ainf).
 bool levelled(const Problem& P, const std::vector<Q>& x, int k, Q& E, Bary& r) {
-  const int m = k + 1;
+  const int nb = k + 1, m = k + 1 + P.ex;   // weights b; unknowns (and rows) incl. ainf
   std::vector<Q> z, y, fz, fy;
-  for (int i = 0; i < 2 * k + 2; ++i) {
-    if (i % 2 == 0) { z.push_back(x[i]); fz.push_back(P.f(x[i])); }
-    else { y.push_back(x[i]); fy.push_back(P.f(x[i])); }
+  std::vector<int> ty;   // 1: test point of opposite sign to the supports; 0: same sign
+  for (int i = 0; i < 2 * k + 2 + P.ex; ++i) {
+    if (i % 2 == 0 && i <= 2 * k) { z.push_back(x[i]); fz.push_back(P.f(x[i])); }
+    else { y.push_back(x[i]); fy.push_back(P.f(x[i])); ty.push_back(i % 2); }
   }
-  // sigma(support) = -1 (odd 1-based index), sigma(test) = +1:
-  // sum_j b_j [(f(z_j) - f(y_i)) + 2E] / (y_i - z_j) = 0
-  std::vector<Q> L(m * m), C(m * m);
-  for (int i = 0; i < m; ++i)
-    for (int j = 0; j < m; ++j) {
+  // sigma(support) = -1 (odd 1-based index), sigma(odd-position test) = +1, the
+  // extra last point of type (k+1, k) has the supports' sign:
+  // ainf + sum_j b_j [(f(z_j) - f(y_i)) + (sigma_i + 1) E] / (y_i - z_j) = 0
+  std::vector<Q> L(m * m, 0), C(m * m, 0);
+  for (int i = 0; i < m; ++i) {
+    for (int j = 0; j < nb; ++j) {
       const Q dd = y[i] - z[j];
       L[i * m + j] = (fz[j] - fy[i]) / dd;
-      C[i * m + j] = 1 / dd;
+      C[i * m + j] = ty[i] ? 1 / dd : Q(0);
     }
-  std::vector<Q> b(m, 1), w;
-  for (int j = 0; j < m; ++j) b[j] = (j % 2 == 0) ? 1 : -1;
+    if (P.ex) L[i * m + nb] = 1;
+  }
+  std::vector<Q> b(m, 0), w;
+  for (int j = 0; j < nb; ++j) b[j] = (j % 2 == 0) ? 1 : -1;
   Q Ec = E;
   for (int it = 0; it < 60; ++it) {
     std::vector<Q> M(m * (m + 1));
@@ -316,25 +331,29 @@ bool levelled(const Problem& P, const std::vector<Q>& x, int k, Q& E, Bary& r) {
     if (done) break;
   }
   // pole-free on [0,1] needs alternating weights
-  for (int j = 0; j + 1 < m; ++j)
+  for (int j = 0; j + 1 < nb; ++j)
     if ((b[j] > 0) == (b[j + 1] > 0)) return false;
   E = Ec;
   r.z = z;
-  r.b = b;
-  r.a.resize(m);
-  for (int j = 0; j < m; ++j) r.a[j] = (fz[j] + E) * b[j];   // r(z_j) = f(z_j) - sigma E = f + E
+  r.b.assign(b.begin(), b.begin() + nb);
+  r.ainf = P.ex ? b[nb] : Q(0);
+  r.a.resize(nb);
+  for (int j = 0; j < nb; ++j) r.a[j] = (fz[j] + E) * b[j];   // r(z_j) = f(z_j) - sigma E = f + E
   return true;
 }
 
-int remez_q(double alpha, int k, std::vector<double>& c_out, std::vector<double>& d_out, double& E_out,
-            std::vector<double>& zeta_out, double& C_out, std::string& why) {
+// The beta-BURA of t^(beta - alpha), beta = 1 (type (k,k)) or 2 (type (k+1,k)).
+int remez_q(double alpha, int beta, int k, std::vector<double>& c_out, std::vector<double>& d_out,
+            double& E_out, std::vector<double>& zeta_out, double& C_out, std::string& why) {
   Problem P;
-  P.g = 1 - Q(alpha);
+  P.g = Q(beta) - Q(alpha);
+  P.ex = beta - 1;
+  const int nref = 2 * k + 2 + P.ex;   // m + k + 2 reference points
   std::vector<Q> ref;
   Q E0;
   if (!initial_reference(P, k, ref, E0, why)) return BURA_EREMEZ;
   ref[0] = 0;
-  ref[2 * k + 1] = 1;
+  ref[nref - 1] = 1;
   Q E = E0;
   Bary r;
   bool ok = false;
@@ -344,21 +363,21 @@ int remez_q(double alpha, int k, std::vector<double>& c_out, std::vector<double>
     // zeros of the error between consecutive reference points
     std::vector<Q> Z;
     Z.push_back(0);
-    for (int i = 0; i + 1 < 2 * k + 2; ++i) {
+    for (int i = 0; i + 1 < nref; ++i) {
       const Q e0 = e(ref[i]), e1 = e(ref[i + 1]);
       if ((e0 > 0) == (e1 > 0)) { why = "alternation lost"; return BURA_EREMEZ; }
       Z.push_back(zero_between(e, ref[i], ref[i + 1]));
     }
     Z.push_back(1);
-    std::vector<Q> nref(2 * k + 2);
+    std::vector<Q> next(nref);
     Q mx = 0, mn = -1;
-    for (int i = 0; i < 2 * k + 2; ++i) {
-      nref[i] = local_max(e, Z[i], Z[i + 1], i == 0, i == 2 * k + 1, 110);
-      const Q v = qabs(e(nref[i]));
+    for (int i = 0; i < nref; ++i) {
+      next[i] = local_max(e, Z[i], Z[i + 1], i == 0, i == nref - 1, 110);
+      const Q v = qabs(e(next[i]));
       mx = std::max(mx, v);
       mn = (mn < 0) ? v : std::min(mn, v);
     }
-    ref = nref;
+    ref = next;
     if (mx - mn <= Q(1e-16) * mx) { ok = true; break; }
   }
   if (!ok) { why = "exchange did not level"; return BURA_EREMEZ; }
@@ -367,7 +386,7 @@ int remez_q(double alpha, int k, std::vector<double>& c_out, std::vector<double>
   // support point lies there, so N and D have no common singularity)
   auto D = [&](Q t) { Q s = 0; for (size_t j = 0; j < r.z.size(); ++j) s += r.b[j] / (t - r.z[j]); return s; };
   auto Dp = [&](Q t) { Q s = 0; for (size_t j = 0; j < r.z.size(); ++j) { Q dt = t - r.z[j]; s -= r.b[j] / (dt * dt); } return s; };
-  auto N = [&](Q t) { Q s = 0; for (size_t j = 0; j < r.z.size(); ++j) s += r.a[j] / (t - r.z[j]); return s; };
+  auto N = [&](Q t) { Q s = r.ainf; for (size_t j = 0; j < r.z.size(); ++j) s += r.a[j] / (t - r.z[j]); return s; };
   auto negative_roots = [](auto&& fn) {
     std::vector<Q> roots;
     const Q u0 = -200, u1 = 30, du = Q(0.01);   // t = -exp(u)
@@ -392,6 +411,31 @@ int remez_q(double alpha, int k, std::vector<double>& c_out, std::vector<double>
   };
   std::vector<Q> poles = negative_roots(D);
   if ((int)poles.size() != k) { why = "pole count differs from k"; return BURA_EREMEZ; }
+  if (beta == 2) {
+    // Section 4.1 / eq. (22): residues c*_j = N(d_j)/D'(d_j) of r, c_j = c*_j / d_j^2,
+    // c_{0,2} = r(0) (eq. (23)); c_{0,1} from the identity
+    // r(t)/t^2 = c_{0,2}/t^2 + c_{0,1}/t + sum_j c_j/(t - d_j) at t = 1
+    c_out.assign(k + 2, 0.0);
+    d_out.assign(k + 1, 0.0);
+    const Q c02 = r.eval(0);
+    Q sum = 0;
+    std::vector<Q> cj(k);
+    for (int j = 0; j < k; ++j) {
+      const Q dj = poles[j];
+      cj[j] = N(dj) / Dp(dj) / (dj * dj);
+      if (!(cj[j] > 0)) { why = "non-positive weight"; return BURA_EREMEZ; }
+      sum += cj[j] / (1 - dj);
+      c_out[j + 1] = (double)cj[j];
+      d_out[j + 1] = (double)dj;
+    }
+    const Q c01 = r.eval(1) - c02 - sum;
+    c_out[0] = (double)c01;
+    c_out[k + 1] = (double)c02;
+    zeta_out.clear();
+    C_out = 0.0;
+    E_out = (double)qabs(E);
+    return BURA_OK;
+  }
   std::vector<Q> zeros = negative_roots(N);
   if ((int)zeros.size() != k) { why = "zero count differs from k"; return BURA_EREMEZ; }
   // Lemma 2.5: 0 > zeta_1 > d_1 > zeta_2 > ... > zeta_k > d_k
@@ -430,11 +474,11 @@ std::map<std::pair<uint64_t, int>, Cached> g_cache;
 
 }  // namespace
 
-int remez_bura_full(double alpha, int k, std::vector<double>& c, std::vector<double>& d, double& E,
+int remez_bura_full(double alpha, int beta, int k, std::vector<double>& c, std::vector<double>& d, double& E,
                     std::vector<double>& zeta, double& C, std::string& why) {
   uint64_t bits;
   std::memcpy(&bits, &alpha, 8);
-  const auto key = std::make_pair(bits, k);
+  const auto key = std::make_pair(bits, k * 4 + beta);
   {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_cache.find(key);
@@ -447,7 +491,7 @@ int remez_bura_full(double alpha, int k, std::vector<double>& c, std::vector<dou
       return BURA_OK;
     }
   }
-  const int rc = remez_q(alpha, k, c, d, E, zeta, C, why);
+  const int rc = remez_q(alpha, beta, k, c, d, E, zeta, C, why);
   if (rc == BURA_OK) {
     std::lock_guard<std::mutex> lk(g_mu);
     Cached& e = g_cache[key];
@@ -463,18 +507,20 @@ int remez_bura_full(double alpha, int k, std::vector<double>& c, std::vector<dou
 int remez_bura(double alpha, int k, std::vector<double>& c, std::vector<double>& d, double& E, std::string& why) {
   std::vector<double> zeta;
   double C = 0.0;
-  return remez_bura_full(alpha, k, c, d, E, zeta, C, why);
+  return remez_bura_full(alpha, 1, k, c, d, E, zeta, C, why);
 }
 
 }  // namespace bura
 
 extern "C" int bura_coefficients(double alpha, int beta, int k, double* c, double* d, double* E) {
   if (!(alpha > 0 && alpha < 1) || k < 1 || k > 16 || !c || !d || !E) return BURA_EINVAL;
-  if (beta != 1) return BURA_EUNSUPPORTED;
-  std::vector<double> cc, dd;
+  if (beta != 1 && beta != 2) return BURA_EUNSUPPORTED;
+  std::vector<double> cc, dd, zz;
+  double C = 0.0;
   std::string why;
-  const int rc = bura::remez_bura(alpha, k, cc, dd, *E, why);
+  const int rc = bura::remez_bura_full(alpha, beta, k, cc, dd, *E, zz, C, why);
   if (rc) return rc;
+  if (beta == 2) c[k + 1] = cc[k + 1];   // c_{0,2}, the weight of A^-2 f
   for (int j = 0; j <= k; ++j) {
     c[j] = cc[j];
     d[j] = dd[j];
@@ -488,7 +534,7 @@ extern "C" int bura_zeros(double alpha, int beta, int k, double* zeta, double* C
   std::vector<double> cc, dd, zz;
   double E = 0.0;
   std::string why;
-  const int rc = bura::remez_bura_full(alpha, k, cc, dd, E, zz, *C, why);
+  const int rc = bura::remez_bura_full(alpha, 1, k, cc, dd, E, zz, *C, why);
   if (rc) return rc;
   for (int j = 0; j < k; ++j) zeta[j] = zz[j];
   return BURA_OK;

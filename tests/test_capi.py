@@ -42,7 +42,7 @@ def test_strerror_and_defaults():
 
 
 @pytest.mark.parametrize("alpha,k,beta,code", [(0.0, 5, 1, -1), (1.0, 5, 1, -1), (0.5, 0, 1, -1),
-                                               (0.5, 17, 1, -1), (0.5, 5, 2, -2)])
+                                               (0.5, 17, 1, -1), (0.5, 5, 3, -2)])
 def test_coefficients_argument_errors(alpha, k, beta, code):
     import paper_1612_04846_amd as B
     with pytest.raises(B.BuraError) as ei:

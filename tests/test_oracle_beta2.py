@@ -53,10 +53,7 @@ def test_beta2_spectral_within_lemma_bound():
     b = _b2(alpha, 5, 4)
     F = synth.normal_rhs(n, 2, nrhs=2, tag=61)
     lam = spectral.eigenvalues(n, 2)
-    c01, c02 = float(b.c0[0]), float(b.c0[1])
-    cj, dj = [float(x) for x in b.c[1:]], [float(x) for x in b.d[1:]]
-    phi = lambda l: c02 / l ** 2 + c01 / l + sum(c / (l - d) for c, d in zip(cj, dj))
-    Ur = spectral.apply_function(F, 2, phi)
+    Ur = spectral.bura_beta_spectral(F, 2, b.c0, b.c, b.d)
     Ue = spectral.exact_fractional(F, 2, alpha)
     A2f = spectral.apply_function(F, 2, lambda l: l ** -2.0)
     for r in range(2):
