@@ -388,7 +388,12 @@ def remez(alpha, k, m=None, beta=1, dps=None, delta_rel=1e-20, max_iter=60,
         if beta == 1 and m == k:
             _partial_fractions(res)
         elif beta > 1 and 0 <= m - k < beta:
-            _partial_fractions_beta(res)
+            # eq. (25) needs simple real negative poles; some (m, k, beta) of
+            # Table 1 do not have them, and only E is used there
+            try:
+                _partial_fractions_beta(res)
+            except RemezError:
+                res.c0, res.c, res.d = [], [], []
         return res
 
 
