@@ -467,6 +467,8 @@ __device__ __forceinline__ T lds_apply2(const T* __restrict__ X, int q, int RX, 
   return wl * (xc - xl) + wr * (xc - xr) + wd * (xc - xd) + wu * (xc - xu) + s * xc;
 }
 
+// tile shapes (taller tiles, 8 rows per thread in the stencil product and
+// 12x / 24-row down/up tiles, measured no faster)
 constexpr int kDownCX = 32, kDownCY = 8;    // coarse points per block (2D)
 constexpr int kUpOX = 64, kUpOY = 16;       // fine points per block (2D)
 
@@ -591,8 +593,8 @@ __global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, c
   }
   __syncthreads();
   // full weighting: coarse (I, J) <- fine 2I+1 +- 1
-  {
-    const int I = I0 + (tid % kDownCX), J = J0 + (tid / kDownCX);
+  for (int q2 = tid; q2 < kDownCX * kDownCY; q2 += 256) {
+    const int I = I0 + (q2 % kDownCX), J = J0 + (q2 / kDownCX);
     if (I < nc && J < nc) {
       const int cx = 2 * I + 1 - gx0, cy = 2 * J + 1 - gy0;
       const T* R = Y + cy * RX + cx;
