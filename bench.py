@@ -105,6 +105,9 @@ def make_rhs(w):
     return synth.uniform_rhs(w["n"], w["dim"], nrhs=w["nrhs"], tag=w["tag"])
 
 
+SMOOTHER = {}   # plan options from --omega / --nu (empty: the library defaults)
+
+
 def run_gpu(w, steps, warmup, profile=True):
     import numpy as np
     import torch
@@ -122,7 +125,7 @@ def run_gpu(w, steps, warmup, profile=True):
     kq = {a: q for a, q in zip(w["alphas"], w.get("kq") or [None] * len(w["alphas"]))}
     for a in groups:
         kw = dict(coeff=coeff, nrhs_max=w["nrhs"], tol=w["tol"], precision=getattr(B, "BURA_" + w["precision"]),
-                  schedule=getattr(B, "BURA_" + w["schedule"]))
+                  schedule=getattr(B, "BURA_" + w["schedule"]), **SMOOTHER)
         if w.get("method") == "sinc":
             al = a if isinstance(a, list) else [a]
             kw["kprime"] = [B.sinc_kprime(x, kq[x]) for x in al]
@@ -347,15 +350,26 @@ def run_serving(args):
         return time.perf_counter() - t0, codes
 
     print("[bench] serving warm-up (plans and coefficients)", file=sys.stderr, flush=True)
-    stream(False)
+    cold, _ = stream(False)
+    cold_st = B.bura_server_stats(server)
+    # latency under the Poisson arrivals, plans resident
+    B.bura_server_reset_latency(server)
+    print("[bench] serving timed stream (Poisson arrivals)", file=sys.stderr, flush=True)
     base = B.bura_server_stats(server)
-    print("[bench] serving timed stream", file=sys.stderr, flush=True)
     wall, codes = stream(True)
     st = B.bura_server_stats(server)
+    # capacity: the same requests all queued at once
+    print("[bench] serving capacity pass (all requests queued)", file=sys.stderr, flush=True)
+    base_cap = B.bura_server_stats(server)
+    wall_cap, codes_cap = stream(False)
+    st_cap = B.bura_server_stats(server)
     B.bura_server_destroy(server)
-    ok = [c == B.BURA_OK for c in codes]
+    ok = [c == B.BURA_OK for c in codes + codes_cap]
     upole = st["unknown_pole_solves"] - base["unknown_pole_solves"]
-    return dict(wall=wall, ok=ok, stats=st, base=base, upole=upole, reqs=reqs, F=F, U=U, failures=failures)
+    upole_cap = st_cap["unknown_pole_solves"] - base_cap["unknown_pole_solves"]
+    return dict(wall=wall, ok=ok, stats=st, base=base, upole=upole, reqs=reqs, F=F, U=U, failures=failures,
+                wall_cap=wall_cap, upole_cap=upole_cap, cold=cold, cold_p50=cold_st["p50_latency_s"],
+                cold_p99=cold_st["p99_latency_s"])
 
 
 def main():
@@ -373,6 +387,9 @@ def main():
     ap.add_argument("--serve-concurrency", type=int, default=4)
     ap.add_argument("--serve-group", type=int, default=2)
     ap.add_argument("--serve-budget-gb", type=float, default=160.0)
+    ap.add_argument("--omega", type=float, default=0.0,
+                    help="uniform damping of every smoothing sweep (0: the library's default weights)")
+    ap.add_argument("--nu", type=int, default=0, help="smoothing sweeps before and after (0: default 2)")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of this many GiB (counter calibration)")
     ap.add_argument("--also", default="2d1023-k9-fp64-per-pole,2d1023-k9-fp64-batched,2d1023-k9-mixed-multi,"
@@ -380,6 +397,10 @@ def main():
                                       "2d1023-beta2-k6-fp64",
                     help="comma-separated extra workloads reported under 'paths' (empty: none)")
     args = ap.parse_args()
+    if args.omega > 0:
+        SMOOTHER["omega"] = args.omega
+    if args.nu > 0:
+        SMOOTHER["nu_pre"] = SMOOTHER["nu_post"] = args.nu
     if args.copy_probe > 0:
         import torch
         nbytes = int(args.copy_probe * (1 << 30))
@@ -413,7 +434,12 @@ def main():
                                       "-> k 5..12, mixed precision", "max_group": args.serve_group,
                           "max_concurrent": args.serve_concurrency, "hbm_budget_gb": args.serve_budget_gb},
                "latency_ms": {"p50": 1e3 * st["p50_latency_s"], "p99": 1e3 * st["p99_latency_s"],
-                              "per": "one request (submit to result), both passes"},
+                              "per": "one request, submit to result, Poisson arrivals, plans resident"},
+               "cold_latency_ms": {"p50": 1e3 * res["cold_p50"], "p99": 1e3 * res["cold_p99"],
+                                   "per": "first pass, including plan creation (Remez, hierarchy, graphs)"},
+               "offered_load_solves_per_s": res["upole"] / res["wall"],
+               "capacity": {"seconds": res["wall_cap"], "unknown_pole_solves_per_s": res["upole_cap"] / res["wall_cap"],
+                            "per": "all requests queued at once"},
                "server": {k: v for k, v in st.items()}}
         accepted = all(res["ok"])
         out["failures"] = res["failures"][:12]
@@ -433,7 +459,7 @@ def main():
             out["rel_err_vs_oracle"] = max(e for e, _ in errs) if errs else None
             out["checked_requests"] = len(errs)
         out["accepted"] = accepted
-        out["value"] = res["upole"] / res["wall"] if accepted else 0.0
+        out["value"] = res["upole_cap"] / res["wall_cap"] if accepted else 0.0
         print(json.dumps(out))
         return
     if args.gpus != 1:

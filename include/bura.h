@@ -95,7 +95,9 @@ typedef struct {
   int nrhs_max;        /* largest nrhs any solve on this plan will use (sizes buffers)   */
   int check_every;     /* PCG iterations between host convergence checks (>= 1)          */
   int nu_pre, nu_post; /* Jacobi sweeps before / after coarse-grid correction             */
-  double omega;        /* Jacobi damping; 0 = 4/5 (2D) or 6/7 (3D)                       */
+  double omega;        /* Jacobi damping of every sweep; 0 = library default: 4/5 (2D)
+                          or 6/7 (3D), and for the FP32 inner solves of BURA_MIXED in
+                          2D per-sweep Chebyshev weights on [0.4, 2] (nu = 2)         */
   void* stream;        /* hipStream_t used for every launch and copy; NULL = null stream */
   size_t hbm_budget;   /* 0 = unlimited; else plan creation fails with BURA_ENOMEM if its
                           device footprint would exceed this many bytes                 */
@@ -318,6 +320,10 @@ int bura_server_poll(bura_server_t s, uint64_t ticket, bura_report_t* rep);
 /* Blocking variant of bura_server_poll. */
 int bura_server_wait(bura_server_t s, uint64_t ticket, bura_report_t* rep);
 int bura_server_stats(bura_server_t s, bura_server_stats_t* st);
+
+/* Forget the latency samples collected so far (the counters stay cumulative),
+ * e.g. after a warm-up pass that created the plans. */
+int bura_server_reset_latency(bura_server_t s);
 /* Waits for queued and running requests, then frees every plan. */
 void bura_server_destroy(bura_server_t s);
 

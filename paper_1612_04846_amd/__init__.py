@@ -151,6 +151,7 @@ _SIGS = {
     "bura_server_poll": (_I, [_P, ctypes.c_uint64, ctypes.POINTER(bura_report_t)]),
     "bura_server_wait": (_I, [_P, ctypes.c_uint64, ctypes.POINTER(bura_report_t)]),
     "bura_server_stats": (_I, [_P, ctypes.POINTER(bura_server_stats_t)]),
+    "bura_server_reset_latency": (_I, [_P]),
     "bura_server_destroy": (None, [_P]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -535,6 +536,10 @@ def bura_server_wait(server, ticket: int):
     rep = bura_report_t()
     code = _lib.bura_server_wait(server, ticket, ctypes.byref(rep))
     return code, rep
+
+
+def bura_server_reset_latency(server):
+    _check(_lib.bura_server_reset_latency(server), "bura_server_reset_latency")
 
 
 def bura_server_stats(server) -> dict:

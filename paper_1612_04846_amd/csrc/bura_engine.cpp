@@ -282,6 +282,36 @@ LevelDev<T> level_view(const bura_plan_t P, int l) {
 
 double default_omega(int dim) { return dim == 2 ? 0.8 : 6.0 / 7.0; }
 
+// Damping of the nu sweeps of a half-cycle.  opts.omega > 0: that weight for
+// every sweep.  Otherwise FP64 solves use the uniform default_omega, and the
+// FP32 inner solves of BURA_MIXED in 2D use the reciprocals of the roots of the
+// degree-nu Chebyshev polynomial on [lo, 2] (D^-1 A has its spectrum in
+// (0, 2], its high-frequency part above ~0.5 for full coarsening), which damp
+// that range by 1/T_nu((2 + lo)/(2 - lo)) instead of max|1 - omega t|^nu (for
+// nu = 2, 0.21 against 0.36).  The Chebyshev weights shorten the 1e-5 inner
+// solves (7 % less time on the 1023^2 three-alpha workload) but lengthen the
+// 1e-10 FP64 solves (+5 % iterations: they damp the poles with large shifts,
+// whose spectrum sits near 1, less than omega = 0.8 does), hence the split.
+// The weights are polynomials in the same operator, so the smoother stays
+// symmetric in any order.  3D keeps the uniform 6/7.
+template <typename T>
+Sweeps<T> sweep_weights(const bura_plan_t P, int nu) {
+  Sweeps<T> s{};
+  const double om = P->opts.omega;
+  const double lo = nu >= 3 ? 0.3 : 0.4;
+  const bool cheb = !(om > 0) && P->dim == 2 && sizeof(T) == 4;
+  for (int i = 0; i < 3; ++i) {
+    double w = om > 0 ? om : default_omega(P->dim);
+    if (cheb && i < nu) {
+      const double pi = 3.141592653589793;
+      const double th = (lo + 2.0) / 2 + (2.0 - lo) / 2 * std::cos((2 * i + 1) * pi / (2 * nu));
+      w = 1.0 / th;
+    }
+    s.w[i] = (T)w;
+  }
+  return s;
+}
+
 // ---------------------------------------------------------------------------
 // hierarchy on the host (Section 1.4 scaling; coarse operators by
 // rediscretisation with series/parallel averaging of the face coefficients)
@@ -459,6 +489,7 @@ LdsHierarchy<T> lds_view(const bura_plan_t P) {
   H.nu = 2;
   H.bottom_sweeps = 8 * P->lev[L - 1].n + 8;
   H.omega = (T)(P->opts.omega > 0 ? P->opts.omega : default_omega(P->dim));
+  H.pre = sweep_weights<T>(P, H.nu);
   return H;
 }
 
@@ -563,7 +594,6 @@ void precondition(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, const int* a
   hipStream_t st = P->stream;
   const int dim = P->dim;
   const bool var = P->var;
-  const T omega = (T)(P->opts.omega > 0 ? P->opts.omega : default_omega(dim));
   const T* shift = W.shift + sys0;
   auto off = [&](T* base, int l) { return base + sys0 * (size_t)P->lev[l].N; };
   if (P->lc < 0) {
@@ -575,6 +605,8 @@ void precondition(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, const int* a
   }
   const int lc = P->lc;
   const int nu1 = std::max(1, P->opts.nu_pre), nu2 = std::max(1, P->opts.nu_post);
+  const Sweeps<T> wpre = sweep_weights<T>(P, nu1), wpost = sweep_weights<T>(P, nu2);
+  auto w_at = [](const Sweeps<T>& sw, int i) { return sw.w[std::min(i, 2)]; };
   if (fused_ok(P)) {
     // two LDS-tiled kernels per level: down (nu1 sweeps + residual + restriction)
     // writes the pre-smoothed iterate into A_l; up (prolongation + nu2 sweeps)
@@ -587,11 +619,11 @@ void precondition(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, const int* a
         ProfScope ps(P, l == 0 ? BURA_K_DOWN_FINE : BURA_K_SMOOTH_COARSE);
         if (l == 0 && ru)
           Launch<T>::fused_down(dim, var, nu1, level_view<T>(P, 0), level_view<T>(P, 1), ru->rold, A(0), bl(1),
-                                shift, active, omega, nsys, st, ps.ctr, ru->q, ru->alpha, ru->rnew, partial,
+                                shift, active, wpre, nsys, st, ps.ctr, ru->q, ru->alpha, ru->rnew, partial,
                                 ru->fin);
         else
           Launch<T>::fused_down(dim, var, nu1, level_view<T>(P, l), level_view<T>(P, l + 1), bl(l), A(l),
-                                bl(l + 1), shift, active, omega, nsys, st, ps.ctr);
+                                bl(l + 1), shift, active, wpre, nsys, st, ps.ctr);
       }
       if (l == 0 && ru && ru->after) ru->after();
     }
@@ -604,7 +636,7 @@ void precondition(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, const int* a
       ProfScope ps(P, l == 0 ? BURA_K_UP_FINE : BURA_K_SMOOTH_COARSE);
       const T* xc = l + 1 == lc ? off(W.xl[lc], lc) : Bv(l + 1);
       Launch<T>::fused_up(dim, var, nu2, level_view<T>(P, l + 1), level_view<T>(P, l), xc, A(l), bl(l), Bv(l),
-                          shift, active, omega, l == 0 ? partial : nullptr, nsys, st, ps.ctr,
+                          shift, active, wpost, l == 0 ? partial : nullptr, nsys, st, ps.ctr,
                           l == 0 ? fin : Fin());
     }
     return;
@@ -625,11 +657,13 @@ void precondition(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, const int* a
     const int scls = l == 0 ? BURA_K_SMOOTH_FINE : BURA_K_SMOOTH_COARSE;
     {
       ProfScope ps(P, scls);
-      Launch<T>::jacobi(dim, var, L, bcur[l], nullptr, out, shift, active, omega, true, nullptr, nsys, st, ps.ctr);
+      Launch<T>::jacobi(dim, var, L, bcur[l], nullptr, out, shift, active, w_at(wpre, 0), true, nullptr, nsys, st,
+                        ps.ctr);
     }
     for (int s = 1; s < nu1; ++s) {
       ProfScope ps(P, scls);
-      Launch<T>::jacobi(dim, var, L, bcur[l], out, other, shift, active, omega, false, nullptr, nsys, st, ps.ctr);
+      Launch<T>::jacobi(dim, var, L, bcur[l], out, other, shift, active, w_at(wpre, s), false, nullptr, nsys, st,
+                        ps.ctr);
       std::swap(out, other);
     }
     cur[l] = out;
@@ -654,7 +688,7 @@ void precondition(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, const int* a
     for (int s = 0; s < nu2; ++s) {
       const bool last = (l == 0 && s == nu2 - 1);
       ProfScope ps(P, scls);
-      Launch<T>::jacobi(dim, var, L, bcur[l], cur[l], spare[l], shift, active, omega, false,
+      Launch<T>::jacobi(dim, var, L, bcur[l], cur[l], spare[l], shift, active, w_at(wpost, nu2 - 1 - s), false,
                         last ? partial : nullptr, nsys, st, ps.ctr, last ? fin : Fin());
       std::swap(cur[l], spare[l]);
     }

@@ -32,6 +32,13 @@ struct LevelDev {
   const T* wf2;       // z-faces  [n+1][n][n]
 };
 
+// Damping weights of the smoothing sweeps of one half-cycle, in the order of
+// the pre-smoothing sweeps (the post-smoothing uses them in reverse).
+template <typename T>
+struct Sweeps {
+  T w[3];
+};
+
 // Levels solved inside one workgroup (LDS V-cycle): descriptors + LDS offsets.
 template <typename T>
 struct LdsHierarchy {
@@ -41,7 +48,8 @@ struct LdsHierarchy {
   int cycles;               // V-cycles per coarse solve
   int nu;                   // sweeps per smoothing step
   int bottom_sweeps;        // Jacobi sweeps on the last level if it is larger than one point
-  T omega;
+  T omega;                  // bottom-level damping
+  Sweeps<T> pre;            // weights of the nu pre-smoothing sweeps (post: reversed)
 };
 
 // Per-system scalar state of the PCG / refinement loops (device arrays, length S).
@@ -109,11 +117,11 @@ struct Launch {
   // nullptr the down kernel first forms b - alpha q, writes it to bout and its
   // squared norm to partial.
   static bool fused_down(int dim, bool var, int nu, const LevelDev<T>& Lf, const LevelDev<T>& Lc, const T* b,
-                         T* xout, T* bc, const T* shift, const int* active, T omega, int nsys, hipStream_t st,
+                         T* xout, T* bc, const T* shift, const int* active, Sweeps<T> om, int nsys, hipStream_t st,
                          unsigned long long* ctr, const T* q = nullptr, const double* alpha = nullptr,
                          T* bout = nullptr, double* partial = nullptr, Fin fin = Fin());
   static bool fused_up(int dim, bool var, int nu, const LevelDev<T>& Lc, const LevelDev<T>& Lf, const T* xc,
-                       const T* xin, const T* b, T* xout, const T* shift, const int* active, T omega,
+                       const T* xin, const T* b, T* xout, const T* shift, const int* active, Sweeps<T> om,
                        double* partial, int nsys, hipStream_t st, unsigned long long* ctr, Fin fin = Fin());
   static void copy_rhs(const LevelDev<T>& L, int dim, const double* f, T* r, T* x, int nrhs,
                        const int* active, double* partial, int nsys, hipStream_t st);

@@ -326,18 +326,29 @@ __global__ __launch_bounds__(kBlock) void k_prolong(LevelDev<T> Lc, LevelDev<T> 
 // all vectors in LDS.  Symmetric (nu Jacobi sweeps before and after), so the
 // composite is an SPD preconditioner component.
 // --------------------------------------------------------------------------
+// weight i of a half-cycle (selected without indexing the array, which would
+// put the by-value argument in scratch memory)
+template <typename T>
+__device__ __forceinline__ T sweep_w(const Sweeps<T>& sw, int i) {
+  return i == 0 ? sw.w[0] : (i == 1 ? sw.w[1] : sw.w[2]);
+}
+
+// omega for every sweep, or (per != nullptr) the half-cycle weights, reversed
+// for post-smoothing
 template <typename T, int DIM, bool VAR>
-__device__ void lds_smooth(const LevelDev<T>& L, T* X, const T* B, T* Tm, T s, T omega, int sweeps) {
+__device__ void lds_smooth(const LevelDev<T>& L, T* X, const T* B, T* Tm, T s, T omega, int sweeps,
+                           const Sweeps<T>* per = nullptr, bool reverse = false) {
   const int n = L.n;
   const int nthr = blockDim.x;
   for (int sw = 0; sw < sweeps; ++sw) {
+    const T om = per ? sweep_w(*per, reverse ? sweeps - 1 - sw : sw) : omega;
     for (int p = threadIdx.x; p < L.N; p += nthr) {
       const int i = p % n;
       const int j = (p / n) % n;
       const int k = DIM == 3 ? p / (n * n) : 0;
       T dg;
       const T ax = apply_pt<T, DIM, VAR>(L, X, i, j, k, p, s, &dg);
-      Tm[p] = X[p] + omega * (B[p] - ax) / dg;
+      Tm[p] = X[p] + om * (B[p] - ax) / dg;
     }
     __syncthreads();
     for (int p = threadIdx.x; p < L.N; p += nthr) X[p] = Tm[p];
@@ -371,7 +382,7 @@ __global__ __launch_bounds__(1024) void k_coarse(LdsHierarchy<T> H, const T* __r
       T* X = sm + H.off[l];
       T* B = X + Lf.N;
       T* Tm = B + Lf.N;
-      lds_smooth<T, DIM, VAR>(Lf, X, B, Tm, s, H.omega, H.nu);
+      lds_smooth<T, DIM, VAR>(Lf, X, B, Tm, s, H.omega, H.nu, &H.pre, false);
       // residual on the fine level into Tm, then full weighting into B_c
       for (int p = threadIdx.x; p < Lf.N; p += nthr) {
         const int i = p % Lf.n;
@@ -427,7 +438,7 @@ __global__ __launch_bounds__(1024) void k_coarse(LdsHierarchy<T> H, const T* __r
         X[p] += interp_pt<T, DIM>(Xc, Lc.n, i, j, k);
       }
       __syncthreads();
-      lds_smooth<T, DIM, VAR>(Lf, X, B, Tm, s, H.omega, H.nu);
+      lds_smooth<T, DIM, VAR>(Lf, X, B, Tm, s, H.omega, H.nu, &H.pre, true);
     }
   }
   for (int p = threadIdx.x; p < L0.N; p += nthr) x[(long long)sys * L0.N + p] = X0[p];
@@ -480,7 +491,7 @@ template <typename T, bool VAR, int NU, bool RUP>
 __global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, const T* __restrict__ b,
                                                T* __restrict__ xout, T* __restrict__ bc,
                                                const T* __restrict__ shift, const int* __restrict__ active,
-                                               T omega, unsigned long long* __restrict__ ctr,
+                                               Sweeps<T> om, unsigned long long* __restrict__ ctr,
                                                const T* __restrict__ qv, const double* __restrict__ alpha,
                                                T* __restrict__ bout, double* __restrict__ partial, Fin fin) {
   constexpr int RX = 2 * kDownCX + 2 * NU + 1, RY = 2 * kDownCY + 2 * NU + 1, RN = RX * RY;
@@ -498,7 +509,7 @@ __global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, c
   const int I0 = tl.x * kDownCX, J0 = tl.y * kDownCY;
   const int gx0 = 2 * I0 - NU, gy0 = 2 * J0 - NU;
   const T sh = shift[sys];
-  const T wcon = omega / (Lf.wc * T(4) + sh);   // omega / D for constant coefficients
+  const T dcon = Lf.wc * T(4) + sh;   // the diagonal for constant coefficients
   const long long off = (long long)sys * Lf.N;
   const int tid = threadIdx.x;
   // stage b (0 outside the grid) and the first sweep from x = 0: x1 = omega b / D.
@@ -524,10 +535,10 @@ __global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, c
       const int gi = gx0 + rx, gj = gy0 + ry;
       const bool in = gi >= 0 && gi < nf && gj >= 0 && gj < nf;
       const T bv = in ? (RUP ? bl[u] - am * ql[u] : bl[u]) : T(0);
-      T xv = wcon * bv;
+      T xv = sweep_w(om, 0) * bv / dcon;
       if (VAR) {
         const int ci = min(max(gi, 0), nf - 1), cj = min(max(gj, 0), nf - 1);
-        xv = omega * bv / diag_pt<T, 2, VAR>(Lf, ci, cj, 0, sh);
+        xv = sweep_w(om, 0) * bv / diag_pt<T, 2, VAR>(Lf, ci, cj, 0, sh);
       }
       sb[q] = bv;
       s0[q] = in ? xv : T(0);
@@ -540,6 +551,7 @@ __global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, c
 #pragma unroll
   for (int m = 1; m < NU; ++m) {   // sweep m+1 on the range shrunk by m
     const int w = RX - 2 * m, hgt = RY - 2 * m;
+    const T wm = sweep_w(om, m), wcon = wm / dcon;
     for (int q2 = tid; q2 < w * hgt; q2 += 256) {
       const int ry = m + q2 / w, rx = m + q2 % w;
       const int q = ry * RX + rx;
@@ -547,7 +559,7 @@ __global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, c
       if (gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
         T dg;
         const T ax = lds_apply2<T, VAR>(X, q, RX, Lf, gi, gj, sh, VAR ? &dg : nullptr);
-        Y[q] = VAR ? X[q] + omega * (sb[q] - ax) / dg : X[q] + wcon * (sb[q] - ax);
+        Y[q] = VAR ? X[q] + wm * (sb[q] - ax) / dg : X[q] + wcon * (sb[q] - ax);
       } else {
         Y[q] = T(0);
       }
@@ -608,7 +620,7 @@ __global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, c
 template <typename T, bool VAR, int NU, bool DOT>
 __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, const T* __restrict__ xc,
                                              const T* __restrict__ xin, const T* __restrict__ b, T* __restrict__ xout,
-                                             const T* __restrict__ shift, const int* __restrict__ active, T omega,
+                                             const T* __restrict__ shift, const int* __restrict__ active, Sweeps<T> om,
                                              double* __restrict__ partial, unsigned long long* __restrict__ ctr,
                                              Fin fin) {
   constexpr int RX = kUpOX + 2 * NU, RY = kUpOY + 2 * NU, RN = RX * RY;
@@ -630,7 +642,7 @@ __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, con
   const int cx0 = ((gx0 >= 0) ? gx0 / 2 : -((-gx0 + 1) / 2)) - 1;
   const int cy0 = ((gy0 >= 0) ? gy0 / 2 : -((-gy0 + 1) / 2)) - 1;
   const T sh = shift[sys];
-  const T wcon = omega / (Lf.wc * T(4) + sh);
+  const T dcon = Lf.wc * T(4) + sh;
   const long long off = (long long)sys * Lf.N;
   const T* xcs = xc + (long long)sys * Lc.N;
   const int tid = threadIdx.x;
@@ -692,8 +704,9 @@ __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, con
   T* X = s0;
   T* Y = s1;
 #pragma unroll
-  for (int m = 1; m <= NU; ++m) {
+  for (int m = 1; m <= NU; ++m) {   // post-smoothing: the pre-smoothing weights reversed
     const int w = RX - 2 * m, hgt = RY - 2 * m;
+    const T wm = sweep_w(om, NU - m), wcon = wm / dcon;
     for (int q2 = tid; q2 < w * hgt; q2 += 256) {
       const int ry = m + q2 / w, rx = m + q2 % w;
       const int q = ry * RX + rx;
@@ -701,7 +714,7 @@ __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, con
       if (gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
         T dg;
         const T ax = lds_apply2<T, VAR>(X, q, RX, Lf, gi, gj, sh, VAR ? &dg : nullptr);
-        Y[q] = VAR ? X[q] + omega * (sb[q] - ax) / dg : X[q] + wcon * (sb[q] - ax);
+        Y[q] = VAR ? X[q] + wm * (sb[q] - ax) / dg : X[q] + wcon * (sb[q] - ax);
       } else {
         Y[q] = T(0);
       }
@@ -1408,14 +1421,14 @@ void Launch<T>::finish_x(long long N, T* x, const T* pa, const T* pb, const doub
 
 template <typename T>
 bool Launch<T>::fused_down(int dim, bool var, int nu, const LevelDev<T>& Lf, const LevelDev<T>& Lc, const T* b,
-                           T* xout, T* bc, const T* shift, const int* active, T omega, int nsys, hipStream_t st,
+                           T* xout, T* bc, const T* shift, const int* active, Sweeps<T> om, int nsys, hipStream_t st,
                            unsigned long long* ctr, const T* q, const double* alpha, T* bout, double* partial,
                            Fin fin) {
   if (dim != 2 || nu < 1 || nu > 3) return false;
   const dim3 g((Lc.n + kDownCX - 1) / kDownCX, (Lc.n + kDownCY - 1) / kDownCY, nsys), blk(256);
   const bool rup = bout != nullptr;
 #define K_DN0(V, NU_, R_)                                                                                          \
-  hipLaunchKernelGGL((k_down2<T, V, NU_, R_>), g, blk, 0, st, Lf, Lc, b, xout, bc, shift, active, omega, ctr, q,  \
+  hipLaunchKernelGGL((k_down2<T, V, NU_, R_>), g, blk, 0, st, Lf, Lc, b, xout, bc, shift, active, om, ctr, q,     \
                      alpha, bout, partial, fin)
 #define K_DN(V, NU_) do { if (rup) K_DN0(V, NU_, true); else K_DN0(V, NU_, false); } while (0)
   if (var) {
@@ -1436,13 +1449,13 @@ int down_blocks(int dim, int n) {
 
 template <typename T>
 bool Launch<T>::fused_up(int dim, bool var, int nu, const LevelDev<T>& Lc, const LevelDev<T>& Lf, const T* xc,
-                         const T* xin, const T* b, T* xout, const T* shift, const int* active, T omega,
+                         const T* xin, const T* b, T* xout, const T* shift, const int* active, Sweeps<T> om,
                          double* partial, int nsys, hipStream_t st, unsigned long long* ctr, Fin fin) {
   if (dim != 2 || nu < 1 || nu > 3) return false;
   const dim3 g((Lf.n + kUpOX - 1) / kUpOX, (Lf.n + kUpOY - 1) / kUpOY, nsys), blk(256);
   const bool dot = partial != nullptr;
 #define K_UP(V, NU_, D_) \
-  hipLaunchKernelGGL((k_up2<T, V, NU_, D_>), g, blk, 0, st, Lc, Lf, xc, xin, b, xout, shift, active, omega, partial, \
+  hipLaunchKernelGGL((k_up2<T, V, NU_, D_>), g, blk, 0, st, Lc, Lf, xc, xin, b, xout, shift, active, om, partial,    \
                      ctr, fin)
 #define K_UPD(V, NU_) do { if (dot) K_UP(V, NU_, true); else K_UP(V, NU_, false); } while (0)
   if (var) {

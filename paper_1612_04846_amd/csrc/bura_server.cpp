@@ -385,6 +385,13 @@ int bura_server_stats(bura_server_t s, bura_server_stats_t* st) {
   return BURA_OK;
 }
 
+int bura_server_reset_latency(bura_server_t s) {
+  if (!s) return BURA_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->latencies.clear();
+  return BURA_OK;
+}
+
 void bura_server_destroy(bura_server_t s) {
   if (!s) return;
   {

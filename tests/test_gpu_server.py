@@ -71,9 +71,13 @@ def test_server_budget_evicts_idle_plans():
     reqs = [(2, 127, 0.5, 5, 111), (2, 127, 0.25, 5, 112), (2, 127, 0.5, 5, 113)]
     _solve_all(B, server, reqs, sequential=True)
     st = B.bura_server_stats(server)
+    assert st["p50_latency_s"] > 0
+    B.bura_server_reset_latency(server)
+    st2 = B.bura_server_stats(server)
     B.bura_server_destroy(server)
     assert st["failed"] == 0 and st["plans_evicted"] >= 1
     assert st["resident_bytes"] <= 12 << 20
+    assert st2["p50_latency_s"] == 0 and st2["completed"] == st["completed"]
 
 
 def test_server_rejects_request_that_cannot_fit():
