@@ -105,7 +105,7 @@ def make_rhs(w):
     return synth.uniform_rhs(w["n"], w["dim"], nrhs=w["nrhs"], tag=w["tag"])
 
 
-SMOOTHER = {}   # plan options from --omega / --nu (empty: the library defaults)
+SMOOTHER = {}   # plan options from --omega / --nu / --inner-tol (empty: the library defaults)
 
 
 def run_gpu(w, steps, warmup, profile=True):
@@ -390,6 +390,8 @@ def main():
     ap.add_argument("--omega", type=float, default=0.0,
                     help="uniform damping of every smoothing sweep (0: the library's default weights)")
     ap.add_argument("--nu", type=int, default=0, help="smoothing sweeps before and after (0: default 2)")
+    ap.add_argument("--inner-tol", type=float, default=0.0,
+                    help="relative residual of the FP32 inner solves in mixed mode (0: library default)")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of this many GiB (counter calibration)")
     ap.add_argument("--also", default="2d1023-k9-fp64-per-pole,2d1023-k9-fp64-batched,2d1023-k9-mixed-multi,"
@@ -401,6 +403,8 @@ def main():
         SMOOTHER["omega"] = args.omega
     if args.nu > 0:
         SMOOTHER["nu_pre"] = SMOOTHER["nu_post"] = args.nu
+    if args.inner_tol > 0:
+        SMOOTHER["inner_tol"] = args.inner_tol
     if args.copy_probe > 0:
         import torch
         nbytes = int(args.copy_probe * (1 << 30))
