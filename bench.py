@@ -105,7 +105,7 @@ def make_rhs(w):
     return synth.uniform_rhs(w["n"], w["dim"], nrhs=w["nrhs"], tag=w["tag"])
 
 
-SMOOTHER = {}   # plan options from --omega / --nu / --inner-tol (empty: the library defaults)
+PLAN_OPTS = {}   # plan options from --omega / --nu / --inner-tol / --autotune (empty: the library defaults)
 
 
 def run_gpu(w, steps, warmup, profile=True):
@@ -125,7 +125,7 @@ def run_gpu(w, steps, warmup, profile=True):
     kq = {a: q for a, q in zip(w["alphas"], w.get("kq") or [None] * len(w["alphas"]))}
     for a in groups:
         kw = dict(coeff=coeff, nrhs_max=w["nrhs"], tol=w["tol"], precision=getattr(B, "BURA_" + w["precision"]),
-                  schedule=getattr(B, "BURA_" + w["schedule"]), **SMOOTHER)
+                  schedule=getattr(B, "BURA_" + w["schedule"]), **PLAN_OPTS)
         if w.get("method") == "sinc":
             al = a if isinstance(a, list) else [a]
             kw["kprime"] = [B.sinc_kprime(x, kq[x]) for x in al]
@@ -135,6 +135,7 @@ def run_gpu(w, steps, warmup, profile=True):
             kw["beta"] = 2
         plans.append(B.Plan(w["dim"], w["n"], a, w["k"], **kw))
     t_plan = time.perf_counter() - t_plan
+    tiles = [p.tiles for p in plans]
     outs = [torch.empty((p.nout,) + tuple(F.shape), dtype=F.dtype, device=dev) if p.nout > 1 else torch.empty_like(F)
             for p in plans]
     for _ in range(warmup):
@@ -190,7 +191,7 @@ def run_gpu(w, steps, warmup, profile=True):
     per_step = N * sum(terms) * w["nrhs"]
     return dict(elapsed=elapsed, per_step=per_step, lat=lat, kstats=kstats, lam=info[0], nlev=info[1],
                 dev_bytes=info[2], U=U, F=F_host, coeff=coeff, coefs=coefs, iters=iters, outer=outer,
-                relres=relres, t_plan=t_plan)
+                relres=relres, t_plan=t_plan, tiles=tiles)
 
 
 def roofline(kstats):
@@ -392,6 +393,9 @@ def main():
     ap.add_argument("--nu", type=int, default=0, help="smoothing sweeps before and after (0: default 2)")
     ap.add_argument("--inner-tol", type=float, default=0.0,
                     help="relative residual of the FP32 inner solves in mixed mode (0: library default)")
+    ap.add_argument("--autotune", type=int, default=1, choices=(0, 1),
+                    help="1: plans time the tile-shape variants at creation and keep the fastest; "
+                         "0: default shapes")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of this many GiB (counter calibration)")
     ap.add_argument("--also", default="2d1023-k9-fp64-per-pole,2d1023-k9-fp64-batched,2d1023-k9-mixed-multi,"
@@ -400,11 +404,12 @@ def main():
                     help="comma-separated extra workloads reported under 'paths' (empty: none)")
     args = ap.parse_args()
     if args.omega > 0:
-        SMOOTHER["omega"] = args.omega
+        PLAN_OPTS["omega"] = args.omega
     if args.nu > 0:
-        SMOOTHER["nu_pre"] = SMOOTHER["nu_post"] = args.nu
+        PLAN_OPTS["nu_pre"] = PLAN_OPTS["nu_post"] = args.nu
     if args.inner_tol > 0:
-        SMOOTHER["inner_tol"] = args.inner_tol
+        PLAN_OPTS["inner_tol"] = args.inner_tol
+    PLAN_OPTS["autotune"] = args.autotune
     if args.copy_probe > 0:
         import torch
         nbytes = int(args.copy_probe * (1 << 30))
@@ -500,6 +505,7 @@ def main():
         "iters_per_pole_last": res["iters"],
         "max_relres": max(res["relres"]),
         "lambda": res["lam"], "mg_levels": res["nlev"], "plan_seconds": round(res["t_plan"], 3),
+        "tiles": res["tiles"],
         "roofline": roof,
         "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in ktable.items()},
@@ -512,7 +518,8 @@ def main():
         r2 = run_gpu(we, max(2, args.steps // 2), 1, profile=False)
         paths[extra] = {"value_unchecked": r2["per_step"] * max(2, args.steps // 2) / r2["elapsed"],
                         "ms_per_step": 1e3 * r2["elapsed"] / max(2, args.steps // 2),
-                        "iters_per_pole_last": r2["iters"], "outer_last": r2["outer"], "_res": r2, "_w": we}
+                        "iters_per_pole_last": r2["iters"], "outer_last": r2["outer"], "tiles": r2["tiles"],
+                        "_res": r2, "_w": we}
     accepted = True
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)

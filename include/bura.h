@@ -101,6 +101,10 @@ typedef struct {
   void* stream;        /* hipStream_t used for every launch and copy; NULL = null stream */
   size_t hbm_budget;   /* 0 = unlimited; else plan creation fails with BURA_ENOMEM if its
                           device footprint would exceed this many bytes                 */
+  int autotune;        /* 2D multigrid plans: 0 = default tile shapes; 1 = plan creation
+                          times every tile-shape variant of the stencil product and of
+                          each level's fused kernels on the plan's buffers and keeps the
+                          fastest (cached per shape in the process; see bura_plan_tiles) */
 } bura_opts_t;
 
 /* Per-solve report (host struct filled by solve/poll). */
@@ -242,6 +246,25 @@ int bura_plan_info(bura_plan_t plan, double* lambda, int* nlevels, size_t* devic
 
 /* y_dev = (A + shift I) x_dev in FP64 for nvec vectors (operator check). */
 int bura_plan_apply(bura_plan_t plan, double shift, const double* x_dev, double* y_dev, int nvec);
+
+/* Tile-shape variants of the 2D stencil product and fused multigrid level
+ * kernels (an implementation choice, not part of the method).  Every variant
+ * computes the same value at every grid point; only the grouping of the
+ * per-block partial sums of the PCG dot products differs, so results of two
+ * variants agree to rounding, not bit for bit. */
+#define BURA_TILE_VARIANTS 3
+
+/* The variants a 2D plan launches: out[0] for the stencil product, out[1 + 2l]
+ * and out[2 + 2l] for the fused down and up kernels of level l, for each of
+ * the plan's levels with fused kernels; *len = 1 + 2 * (those levels) (0 for
+ * a 3D plan, whose kernels have one shape).  With out == NULL only *len is
+ * written.  BURA_EINVAL if max_len < *len. */
+int bura_plan_tiles(bura_plan_t plan, int* out, int max_len, int* len);
+
+/* Set the variants (layout as bura_plan_tiles, len must equal its *len, each
+ * value in [0, BURA_TILE_VARIANTS)).  Synchronises the plan's stream and
+ * drops its captured graphs; BURA_EBUSY while an asynchronous solve runs. */
+int bura_plan_set_tiles(bura_plan_t plan, const int* v, int len);
 
 /* Kernel classes for profiling. */
 enum bura_kernel_class {

@@ -44,6 +44,7 @@ BURA_MIXED = 1
 BURA_BATCHED = 0
 BURA_PER_POLE = 1
 BURA_MAX_TERMS = 64
+BURA_TILE_VARIANTS = 3
 
 
 class bura_grid_t(ctypes.Structure):
@@ -70,6 +71,7 @@ class bura_opts_t(ctypes.Structure):
         ("omega", ctypes.c_double),
         ("stream", ctypes.c_void_p),
         ("hbm_budget", ctypes.c_size_t),
+        ("autotune", ctypes.c_int),
     ]
 
 
@@ -144,6 +146,8 @@ _SIGS = {
     "bura_plan_apply": (_I, [_P, _D, _P, _P, _I]),
     "bura_plan_profile": (_I, [_P, _I]),
     "bura_plan_kernel_stats": (_I, [_P, _I, ctypes.POINTER(ctypes.c_longlong), _DP, _DP]),
+    "bura_plan_tiles": (_I, [_P, ctypes.POINTER(_I), _I, ctypes.POINTER(_I)]),
+    "bura_plan_set_tiles": (_I, [_P, ctypes.POINTER(_I), _I]),
     "bura_plan_destroy": (None, [_P]),
     "bura_strerror": (ctypes.c_char_p, [_I]),
     "bura_server_create": (_I, [ctypes.c_size_t, _I, _I, ctypes.POINTER(_P)]),
@@ -413,6 +417,23 @@ def bura_plan_kernel_stats(plan, kclass: int):
     return n.value, ms.value, by.value
 
 
+def bura_plan_tiles(plan):
+    """Tile-shape variants in use: [stencil product, down_0, up_0, down_1, up_1, ...]."""
+    n = ctypes.c_int()
+    _check(_lib.bura_plan_tiles(plan, None, 0, ctypes.byref(n)), "bura_plan_tiles")
+    if n.value == 0:
+        return []
+    buf = (ctypes.c_int * n.value)()
+    _check(_lib.bura_plan_tiles(plan, buf, n.value, ctypes.byref(n)), "bura_plan_tiles")
+    return list(buf)
+
+
+def bura_plan_set_tiles(plan, variants):
+    v = list(variants)
+    buf = (ctypes.c_int * len(v))(*v)
+    _check(_lib.bura_plan_set_tiles(plan, buf, len(v)), "bura_plan_set_tiles")
+
+
 def bura_plan_destroy(plan):
     if plan:
         _lib.bura_plan_destroy(plan)
@@ -478,6 +499,14 @@ class Plan:
     @property
     def info(self):
         return bura_plan_info(self.handle)
+
+    @property
+    def tiles(self):
+        return bura_plan_tiles(self.handle)
+
+    @tiles.setter
+    def tiles(self, variants):
+        bura_plan_set_tiles(self.handle, variants)
 
     def solve(self, f: torch.Tensor, u: Optional[torch.Tensor] = None, ok=(BURA_OK,)) -> SolveResult:
         f = f.contiguous()

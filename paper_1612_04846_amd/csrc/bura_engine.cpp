@@ -114,6 +114,10 @@ struct bura_plan_s {
   // second residual buffer (off with BURA_NO_FOLDXR=1)
   bool foldxr = false;
   size_t lds_bytes = 0;
+  // launch-shape variant of the 2D stencil product and, per global level, of
+  // the fused down and up kernels (0 = default; chosen by tune_tiles)
+  int tile_spmv = 0;
+  std::vector<int> tile_down, tile_up;
   int S = 0;                   // systems = nterms * nrhs_max
   // device buffers
   Work<double> w64;
@@ -539,9 +543,7 @@ size_t footprint(const bura_plan_t P, size_t elem, bool mixed) {
     for (int l = 1; l <= P->lc; ++l) t += 3 * S * (size_t)P->lev[l].N * elem;
   if (mixed) t += S * (size_t)P->N * 8;
   if (!P->stages.empty()) t += (size_t)P->opts.nrhs_max * P->N * 8;
-  size_t maxblk = (size_t)std::max({stencil_blocks(P->dim, P->n), flat_blocks(P->N), up_blocks(P->dim, P->n),
-                                    down_blocks(P->dim, P->n)});
-  t += S * maxblk * 8;
+  t += S * (size_t)max_partial_blocks(P->dim, P->n, P->N) * 8;
   for (const auto& L : P->lev)
     for (int a = 0; a < P->dim; ++a) t += L.wf[a].size() * 12;
   return t;
@@ -620,10 +622,11 @@ void precondition(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, const int* a
         if (l == 0 && ru)
           Launch<T>::fused_down(dim, var, nu1, level_view<T>(P, 0), level_view<T>(P, 1), ru->rold, A(0), bl(1),
                                 shift, active, wpre, nsys, st, ps.ctr, ru->q, ru->alpha, ru->rnew, partial,
-                                ru->fin);
+                                ru->fin, P->tile_down[0]);
         else
           Launch<T>::fused_down(dim, var, nu1, level_view<T>(P, l), level_view<T>(P, l + 1), bl(l), A(l),
-                                bl(l + 1), shift, active, wpre, nsys, st, ps.ctr);
+                                bl(l + 1), shift, active, wpre, nsys, st, ps.ctr, nullptr, nullptr, nullptr,
+                                nullptr, Fin(), P->tile_down[l]);
       }
       if (l == 0 && ru && ru->after) ru->after();
     }
@@ -637,7 +640,7 @@ void precondition(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, const int* a
       const T* xc = l + 1 == lc ? off(W.xl[lc], lc) : Bv(l + 1);
       Launch<T>::fused_up(dim, var, nu2, level_view<T>(P, l + 1), level_view<T>(P, l), xc, A(l), bl(l), Bv(l),
                           shift, active, wpost, l == 0 ? partial : nullptr, nsys, st, ps.ctr,
-                          l == 0 ? fin : Fin());
+                          l == 0 ? fin : Fin(), P->tile_up[l]);
     }
     return;
   }
@@ -696,7 +699,9 @@ void precondition(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, const int* a
 }
 
 // which kernel wrote the r.z partials (for the reduction's block count)
-int rz_blocks(const bura_plan_t P) { return fused_ok(P) ? up_blocks(P->dim, P->n) : stencil_blocks(P->dim, P->n); }
+int rz_blocks(const bura_plan_t P) {
+  return fused_ok(P) ? up_blocks(P->dim, P->n, P->tile_up[0]) : stencil_blocks(P->dim, P->n);
+}
 
 SysState state_at(const bura_plan_t P, size_t sys0) {
   SysState s = P->st;
@@ -747,14 +752,14 @@ int run_pcg(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, double tol, int ma
     return f;
   };
   const bool fx = P->foldxr;
-  const int nb_down = down_blocks(dim, P->n);
+  const int nb_down = fx ? down_blocks(dim, P->n, P->tile_down[0]) : 0;
   auto body = [&](T* po, T* pn, T* ro, T* rn) {
     {
       ProfScope ps(P, BURA_K_SPMV);
       Launch<T>::spmv_p(dim, P->var, L0, W.z + o, po, pn, W.q + o, S.beta, W.shift + sys0, S.active, part, nsys, st,
-                        ps.ctr, fin(OP_ALPHA), fx ? W.x + o : nullptr, S.alpha);
+                        ps.ctr, fin(OP_ALPHA), fx ? W.x + o : nullptr, S.alpha, P->tile_spmv);
     }
-    if (!P->fold) scal(OP_ALPHA, spmv_blocks(dim, P->n));
+    if (!P->fold) scal(OP_ALPHA, spmv_blocks(dim, P->n, P->tile_spmv));
     if (fx) {
       ResidUpdate<T> ru{ro, rn, W.q + o, S.alpha, fin(OP_RESID), [&]() {
                           if (!P->fold) scal(OP_RESID, nb_down);
@@ -1080,6 +1085,132 @@ int check_terms(const Terms& t) {
 // operator is built) are produced by `late`.
 using LateTerms = std::function<int(double lambda, Terms& t)>;
 
+// ---------------------------------------------------------------------------
+// Launch-shape tuning (opts.autotune).  The knobs are the tile variant of the
+// 2D stencil product and of each level's fused down and up kernels (levels
+// with n >= kTuneMinN; smaller ones are launch-bound and keep the default).
+// Each knob in turn (coordinate descent from the defaults, fine level first)
+// takes the variant for which kTuneReps whole PCG iterations -- stencil
+// product and V-cycle as a solve launches them, on the plan's own buffers,
+// every system active -- run fastest.  Timing whole iterations keeps the cache
+// state of the real sequence (one kernel timed alone on its own output would
+// see warmer caches).  The choice is cached per (precision, grid, coefficients
+// or not, sweeps, systems) for the life of the process.  The variants compute
+// the same value at every point; only the grouping of the per-block partial
+// sums of the dot products differs.
+// ---------------------------------------------------------------------------
+struct TileChoice {
+  int spmv = 0;
+  std::vector<int> down, up;
+};
+
+std::mutex g_tile_mu;
+std::map<std::string, TileChoice> g_tile_cache;
+
+constexpr int kTuneMinN = 127;
+constexpr int kTuneReps = 3;
+
+template <typename T>
+int tune_tiles(bura_plan_t P, Work<T>& W) {
+  if (P->dim != 2) return BURA_OK;   // the 3D kernels have one shape
+  char key[160];
+  std::snprintf(key, sizeof(key), "%zu/%d/%d/%d/%d/%d/%d/%d", sizeof(T), P->dim, P->n, (int)P->var,
+                P->opts.nu_pre, P->opts.nu_post, P->S, (int)P->foldxr);
+  {
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    auto it = g_tile_cache.find(key);
+    if (it != g_tile_cache.end()) {
+      P->tile_spmv = it->second.spmv;
+      P->tile_down = it->second.down;
+      P->tile_up = it->second.up;
+      return BURA_OK;
+    }
+  }
+  hipStream_t st = P->stream;
+  const int nsys = P->S;
+  const int lc = P->lc;
+  const SysState S = P->st;
+  // defined contents (zeros) everywhere the kernels read; every system
+  // active; alpha and beta nonzero so that the kernels move the bytes of a
+  // mid-solve iteration (p_old read, x and r updated)
+  for (int l = 1; l <= lc; ++l) {
+    const size_t b = (size_t)nsys * (size_t)P->lev[l].N * sizeof(T);
+    launch_zero(W.xl[l], b, st);
+    launch_zero(W.bl[l], b, st);
+    if (l < lc) launch_zero(W.tl[l], b, st);
+  }
+  if (W.r2) launch_zero(W.r2, (size_t)nsys * (size_t)P->N * sizeof(T), st);
+  launch_fill_int(S.active, nsys, 1, st);
+  std::vector<double> half((size_t)nsys, 0.5);
+  HIPCHK(hipMemcpyAsync(S.alpha, half.data(), half.size() * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(S.beta, half.data(), half.size() * 8, hipMemcpyHostToDevice, st));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) hipEventDestroy(e0);
+    return BURA_EDEVICE;
+  }
+  const bool fx = P->foldxr;
+  const LevelDev<T> L0 = level_view<T>(P, 0);
+  // one PCG iteration's stencil product and preconditioner, as run_pcg issues them
+  auto iteration = [&]() {
+    Launch<T>::spmv_p(2, P->var, L0, W.z, W.p, W.p2, W.q, S.beta, W.shift, S.active, P->partial, nsys, st, nullptr,
+                      Fin(), fx ? W.x : nullptr, S.alpha, P->tile_spmv);
+    if (fx) {
+      ResidUpdate<T> ru{W.r, W.r2, W.q, S.alpha, Fin(), nullptr};
+      precondition<T>(P, W, 0, nsys, S.active, P->partial, Fin(), &ru);
+    } else {
+      precondition<T>(P, W, 0, nsys, S.active, P->partial, Fin());
+    }
+  };
+  bool ok = true;
+  auto timed = [&]() {
+    iteration();   // warm-up
+    float ms = 0.0f;
+    ok = ok && hipEventRecord(e0, st) == hipSuccess;
+    for (int r = 0; r < kTuneReps && ok; ++r) iteration();
+    ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+         hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    return ms;
+  };
+  // coordinate descent: each knob takes its fastest variant with the others fixed
+  auto tune = [&](int* knob) {
+    int best = *knob;
+    float best_ms = 0.0f;
+    for (int v = 0; v < kTileVariants && ok; ++v) {
+      *knob = v;
+      const float ms = timed();
+      if (ok && (v == 0 || ms < best_ms)) {
+        best = v;
+        best_ms = ms;
+      }
+    }
+    *knob = best;
+  };
+  P->tile_spmv = 0;
+  std::fill(P->tile_down.begin(), P->tile_down.end(), 0);
+  std::fill(P->tile_up.begin(), P->tile_up.end(), 0);
+  tune(&P->tile_spmv);
+  for (int l = 0; l < lc && fused_ok(P) && ok; ++l) {
+    if (P->lev[l].n < kTuneMinN) continue;
+    tune(&P->tile_down[l]);
+    tune(&P->tile_up[l]);
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  // the solves set flags and scalars themselves; leave no pending update behind
+  launch_zero(S.alpha, (size_t)nsys * 8, st);
+  launch_zero(S.beta, (size_t)nsys * 8, st);
+  launch_fill_int(S.active, nsys, 0, st);
+  if (!ok || hipStreamSynchronize(st) != hipSuccess) return BURA_EDEVICE;
+  TileChoice c;
+  c.spmv = P->tile_spmv;
+  c.down = P->tile_down;
+  c.up = P->tile_up;
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  g_tile_cache[key] = c;
+  return BURA_OK;
+}
+
 int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_plan_t* out,
            const LateTerms& late = LateTerms()) {
   if (out) *out = nullptr;
@@ -1122,6 +1253,8 @@ int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_p
   }
   int rc = build_levels(P, g);
   if (rc) { delete P; return rc; }
+  P->tile_down.assign(P->lev.size(), 0);
+  P->tile_up.assign(P->lev.size(), 0);
   if (late) {
     if ((rc = late(P->lambda, terms)) || (rc = check_terms(terms))) { delete P; return rc ? rc : BURA_EINVAL; }
   }
@@ -1173,9 +1306,7 @@ int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_p
         hipStreamSynchronize(P->stream) != hipSuccess)
       return fail(BURA_EDEVICE);
   }
-  const size_t maxblk = (size_t)std::max({stencil_blocks(P->dim, P->n), flat_blocks(P->N), up_blocks(P->dim, P->n),
-                                          down_blocks(P->dim, P->n)});
-  P->partial_len = (size_t)P->S * maxblk;
+  P->partial_len = (size_t)P->S * (size_t)max_partial_blocks(P->dim, P->n, P->N);
   if ((rc = dev_alloc(P, (void**)&P->partial, P->partial_len * 8))) return fail(rc);
   if ((rc = dev_alloc(P, (void**)&P->d_w, nterms * 8))) return fail(rc);
   if (!P->stages.empty() && (rc = dev_alloc(P, (void**)&P->d_buf, (size_t)o.nrhs_max * P->N * 8))) return fail(rc);
@@ -1205,6 +1336,10 @@ int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_p
     return fail(BURA_ENOMEM);
   if (hipHostMalloc(&P->h_state, S * (6 * 8 + 8 * 4) + S * 8, hipHostMallocDefault) != hipSuccess)
     return fail(BURA_ENOMEM);
+  if (o.autotune) {
+    if (hipStreamSynchronize(P->stream) != hipSuccess) return fail(BURA_EDEVICE);
+    if ((rc = mixed ? tune_tiles<float>(P, P->w32) : tune_tiles<double>(P, P->w64))) return fail(rc);
+  }
   // only this plan's stream: a device-wide synchronisation would break graph
   // capture running on other plans' streams in other threads
   if (hipStreamSynchronize(P->stream) != hipSuccess) return fail(BURA_EDEVICE);
@@ -1235,6 +1370,7 @@ int bura_opts_default(bura_opts_t* o) {
   o->omega = 0.0;
   o->stream = nullptr;
   o->hbm_budget = 0;
+  o->autotune = 0;
   return BURA_OK;
 }
 
@@ -1529,6 +1665,39 @@ int bura_plan_kernel_stats(bura_plan_t plan, int kclass, long long* launches, do
   if (launches) *launches = cnt;
   if (total_ms) *total_ms = ms;
   if (alg_bytes) *alg_bytes = (double)ctr[kclass];
+  return BURA_OK;
+}
+
+int bura_plan_tiles(bura_plan_t plan, int* out, int max_len, int* len) {
+  if (!plan || !len) return BURA_EINVAL;
+  const int nf = fused_ok(plan) ? plan->lc : 0;
+  *len = plan->dim == 2 ? 1 + 2 * nf : 0;
+  if (!out || *len == 0) return BURA_OK;
+  if (max_len < *len) return BURA_EINVAL;
+  out[0] = plan->tile_spmv;
+  for (int l = 0; l < nf; ++l) {
+    out[1 + 2 * l] = plan->tile_down[l];
+    out[2 + 2 * l] = plan->tile_up[l];
+  }
+  return BURA_OK;
+}
+
+int bura_plan_set_tiles(bura_plan_t plan, const int* v, int len) {
+  if (!plan || (!v && len > 0)) return BURA_EINVAL;
+  const int nf = fused_ok(plan) ? plan->lc : 0;
+  if (len != (plan->dim == 2 ? 1 + 2 * nf : 0)) return BURA_EINVAL;
+  if (len == 0) return BURA_OK;
+  for (int i = 0; i < len; ++i)
+    if (v[i] < 0 || v[i] >= BURA_TILE_VARIANTS) return BURA_EINVAL;
+  if (plan->busy.load()) return BURA_EBUSY;
+  HIPCHK(hipSetDevice(plan->device));
+  HIPCHK(hipStreamSynchronize(plan->stream));
+  destroy_graphs(plan);   // captured launches carry their grid shapes
+  plan->tile_spmv = v[0];
+  for (int l = 0; l < nf; ++l) {
+    plan->tile_down[l] = v[1 + 2 * l];
+    plan->tile_up[l] = v[2 + 2 * l];
+  }
   return BURA_OK;
 }
 

@@ -18,6 +18,10 @@ constexpr int kTileY = 4;              // rows per tile
 constexpr int kBlock = kTileX * kTileY;
 constexpr int kSlots = 2;              // reduction slots per block
 constexpr int kMaxLdsLevels = 8;
+// Launch-shape variants of the 2D stencil-product and fused level kernels
+// (tile sizes in bura_kernels.hip); 0 is the default shape.
+constexpr int kTileVariants = BURA_TILE_VARIANTS;
+constexpr int tile_variant(int tv) { return tv >= 0 && tv < kTileVariants ? tv : 0; }
 
 // One multigrid level of the scaled operator A_l + s I as seen by a kernel.
 // Face weights are a_f / (Lambda h_l^2); the constant-coefficient operator has
@@ -109,7 +113,7 @@ struct Launch {
   static void spmv_p(int dim, bool var, const LevelDev<T>& L, const T* z, const T* pold, T* pnew, T* q,
                      const double* beta, const T* shift, const int* active, double* partial, int nsys,
                      hipStream_t st, unsigned long long* ctr, Fin fin = Fin(), T* x = nullptr,
-                     const double* alpha = nullptr);
+                     const double* alpha = nullptr, int tv = 0);
   // the last deferred x += alpha p of each system (see k_finish_x)
   static void finish_x(long long N, T* x, const T* pa, const T* pb, const double* alpha, const int* iters,
                        int nsys, hipStream_t st, unsigned long long* ctr);
@@ -119,10 +123,11 @@ struct Launch {
   static bool fused_down(int dim, bool var, int nu, const LevelDev<T>& Lf, const LevelDev<T>& Lc, const T* b,
                          T* xout, T* bc, const T* shift, const int* active, Sweeps<T> om, int nsys, hipStream_t st,
                          unsigned long long* ctr, const T* q = nullptr, const double* alpha = nullptr,
-                         T* bout = nullptr, double* partial = nullptr, Fin fin = Fin());
+                         T* bout = nullptr, double* partial = nullptr, Fin fin = Fin(), int tv = 0);
   static bool fused_up(int dim, bool var, int nu, const LevelDev<T>& Lc, const LevelDev<T>& Lf, const T* xc,
                        const T* xin, const T* b, T* xout, const T* shift, const int* active, Sweeps<T> om,
-                       double* partial, int nsys, hipStream_t st, unsigned long long* ctr, Fin fin = Fin());
+                       double* partial, int nsys, hipStream_t st, unsigned long long* ctr, Fin fin = Fin(),
+                       int tv = 0);
   static void copy_rhs(const LevelDev<T>& L, int dim, const double* f, T* r, T* x, int nrhs,
                        const int* active, double* partial, int nsys, hipStream_t st);
 };
@@ -145,8 +150,11 @@ void launch_slot_flags(int* p, int nterms, int R, int nrhs, hipStream_t st);
 
 int stencil_blocks(int dim, int n);   // blocks per system of a stencil launch (tile grid)
 int flat_blocks(long long N);        // blocks per system of an element-wise launch
-int up_blocks(int dim, int n);       // blocks per system of the fused up kernel
-int down_blocks(int dim, int n);     // blocks per system of the fused down kernel (fine level n)
-int spmv_blocks(int dim, int n);     // blocks per system of the stencil product with the p update
+// blocks per system of the fused up kernel, of the fused down kernel (fine
+// level n) and of the stencil product with the p update, in shape variant tv
+int up_blocks(int dim, int n, int tv);
+int down_blocks(int dim, int n, int tv);
+int spmv_blocks(int dim, int n, int tv);
+int max_partial_blocks(int dim, int n, long long N);   // over every launch shape
 
 }  // namespace bura

@@ -13,7 +13,9 @@
 // the batch.
 #include "bura_internal.h"
 
+#include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 namespace bura {
 
@@ -478,23 +480,26 @@ __device__ __forceinline__ T lds_apply2(const T* __restrict__ X, int q, int RX, 
   return wl * (xc - xl) + wr * (xc - xr) + wd * (xc - xd) + wu * (xc - xu) + s * xc;
 }
 
-// tile shapes (taller tiles, 8 rows per thread in the stencil product and
-// 12x / 24-row down/up tiles, measured no faster)
-constexpr int kDownCX = 32, kDownCY = 8;    // coarse points per block (2D)
-constexpr int kUpOX = 64, kUpOY = 16;       // fine points per block (2D)
+// Tile shapes of the 2D kernels, one row per launch-shape variant (variant 0
+// is the default; a plan may time the others at creation and keep the
+// fastest): coarse points per block of the down kernel, fine points per block
+// of the up kernel, rows per thread of the stencil product.
+constexpr int kDownTile[kTileVariants][2] = {{32, 8}, {32, 4}, {32, 12}};
+constexpr int kUpTile[kTileVariants][2] = {{64, 16}, {64, 8}, {64, 24}};
+constexpr int kSpmvRows[kTileVariants] = {4, 2, 8};
 
 // RUP: the right-hand side is first advanced by the PCG step, b = b_old - alpha q
 // (read from b, written to bout on the owned points, |b|^2 into partial), so the
 // vector update of the PCG iteration costs no pass of its own.  bout must not
 // be b: neighbouring blocks still read b_old in their halos.
-template <typename T, bool VAR, int NU, bool RUP>
+template <typename T, bool VAR, int NU, bool RUP, int CX, int CY>
 __global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, const T* __restrict__ b,
                                                T* __restrict__ xout, T* __restrict__ bc,
                                                const T* __restrict__ shift, const int* __restrict__ active,
                                                Sweeps<T> om, unsigned long long* __restrict__ ctr,
                                                const T* __restrict__ qv, const double* __restrict__ alpha,
                                                T* __restrict__ bout, double* __restrict__ partial, Fin fin) {
-  constexpr int RX = 2 * kDownCX + 2 * NU + 1, RY = 2 * kDownCY + 2 * NU + 1, RN = RX * RY;
+  constexpr int RX = 2 * CX + 2 * NU + 1, RY = 2 * CY + 2 * NU + 1, RN = RX * RY;
   __shared__ T sb[RN];
   __shared__ T s0[RN];
   __shared__ T s1[RN];
@@ -506,7 +511,7 @@ __global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, c
                                    (VAR && sys == 0 ? (unsigned long long)Lf.N * sizeof(T) * 2 : 0ULL));
   const T am = RUP ? (T)alpha[sys] : T(0);
   const int nf = Lf.n, nc = Lc.n;
-  const int I0 = tl.x * kDownCX, J0 = tl.y * kDownCY;
+  const int I0 = tl.x * CX, J0 = tl.y * CY;
   const int gx0 = 2 * I0 - NU, gy0 = 2 * J0 - NU;
   const T sh = shift[sys];
   const T dcon = Lf.wc * T(4) + sh;   // the diagonal for constant coefficients
@@ -571,8 +576,8 @@ __global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, c
   }
   // owned fine points: [2 I0, 2 I0 + 2 CX) per axis, extended to the grid end on the last tile
   {
-    const int hx = (I0 + kDownCX >= nc) ? nf : 2 * (I0 + kDownCX);
-    const int hy = (J0 + kDownCY >= nc) ? nf : 2 * (J0 + kDownCY);
+    const int hx = (I0 + CX >= nc) ? nf : 2 * (I0 + CX);
+    const int hy = (J0 + CY >= nc) ? nf : 2 * (J0 + CY);
     const int ow = hx - 2 * I0, oh = hy - 2 * J0;
     double rr = 0.0;
     for (int q2 = tid; q2 < ow * oh; q2 += 256) {
@@ -605,8 +610,8 @@ __global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, c
   }
   __syncthreads();
   // full weighting: coarse (I, J) <- fine 2I+1 +- 1
-  for (int q2 = tid; q2 < kDownCX * kDownCY; q2 += 256) {
-    const int I = I0 + (q2 % kDownCX), J = J0 + (q2 / kDownCX);
+  for (int q2 = tid; q2 < CX * CY; q2 += 256) {
+    const int I = I0 + (q2 % CX), J = J0 + (q2 / CX);
     if (I < nc && J < nc) {
       const int cx = 2 * I + 1 - gx0, cy = 2 * J + 1 - gy0;
       const T* R = Y + cy * RX + cx;
@@ -617,13 +622,13 @@ __global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, c
   }
 }
 
-template <typename T, bool VAR, int NU, bool DOT>
+template <typename T, bool VAR, int NU, bool DOT, int OX, int OY>
 __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, const T* __restrict__ xc,
                                              const T* __restrict__ xin, const T* __restrict__ b, T* __restrict__ xout,
                                              const T* __restrict__ shift, const int* __restrict__ active, Sweeps<T> om,
                                              double* __restrict__ partial, unsigned long long* __restrict__ ctr,
                                              Fin fin) {
-  constexpr int RX = kUpOX + 2 * NU, RY = kUpOY + 2 * NU, RN = RX * RY;
+  constexpr int RX = OX + 2 * NU, RY = OY + 2 * NU, RN = RX * RY;
   // coarse values under the region, zero-padded: coarse index c at cx0 + (c - c0)
   constexpr int CRX = RX / 2 + 3, CRY = RY / 2 + 3, CRN = CRX * CRY;
   __shared__ T sb[RN];
@@ -636,7 +641,7 @@ __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, con
   count_bytes_tile(tl, ctr, (unsigned long long)Lf.N * sizeof(T) * 3 + (unsigned long long)Lc.N * sizeof(T) +
                                    (VAR && sys == 0 ? (unsigned long long)Lf.N * sizeof(T) * 2 : 0ULL));
   const int nf = Lf.n, nc = Lc.n;
-  const int ox0 = tl.x * kUpOX, oy0 = tl.y * kUpOY;
+  const int ox0 = tl.x * OX, oy0 = tl.y * OY;
   const int gx0 = ox0 - NU, gy0 = oy0 - NU;
   // smallest coarse index any region point interpolates from (floor division)
   const int cx0 = ((gx0 >= 0) ? gx0 / 2 : -((-gx0 + 1) / 2)) - 1;
@@ -725,8 +730,8 @@ __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, con
     Y = t;
   }
   double dot = 0.0;
-  for (int q2 = tid; q2 < kUpOX * kUpOY; q2 += 256) {
-    const int oy = q2 / kUpOX, ox = q2 - oy * kUpOX;
+  for (int q2 = tid; q2 < OX * OY; q2 += 256) {
+    const int oy = q2 / OX, ox = q2 - oy * OX;
     const int gi = ox0 + ox, gj = oy0 + oy;
     if (gi < nf && gj < nf) {
       const int q = (oy + NU) * RX + (ox + NU);
@@ -820,20 +825,17 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p(LevelDev<T> L, const T* __res
 }
 
 
-// 2D version: each thread owns kSpRows consecutive rows of one column (a
-// workgroup covers kTileX x kTileY*kSpRows points), so the column's p_new
-// values are formed once and reused by the rows above and below; only the
-// left/right neighbours are extra loads.
-constexpr int kSpRows = 4;
-
-template <typename T, bool VAR, bool XUP>
+// 2D version: each thread owns R consecutive rows of one column (a workgroup
+// covers kTileX x kTileY*R points), so the column's p_new values are formed
+// once and reused by the rows above and below; only the left/right neighbours
+// are extra loads.
+template <typename T, bool VAR, bool XUP, int R>
 __global__ __launch_bounds__(kBlock) void k_spmv_p2(LevelDev<T> L, const T* __restrict__ z, const T* __restrict__ pold,
                                                     T* __restrict__ pnew, T* __restrict__ q,
                                                     const double* __restrict__ beta, const T* __restrict__ shift,
                                                     const int* __restrict__ active, double* __restrict__ partial,
                                                     unsigned long long* __restrict__ ctr, Fin fin,
                                                     T* __restrict__ x, const double* __restrict__ alpha) {
-  constexpr int R = kSpRows;
   const Tile tl = block_tile();
   const int sys = tl.z;
   if (!active[sys]) return;
@@ -1265,15 +1267,15 @@ int stencil_blocks(int dim, int n) {
   return (int)(g.x * g.y);
 }
 
-// the 2D stencil product: kTileX x (kTileY * kSpRows) points per workgroup
-static inline dim3 spmv2_grid(int n, int nsys) {
-  const int rows = kTileY * kSpRows;
+// the 2D stencil product: kTileX x (kTileY * R) points per workgroup
+static inline dim3 spmv2_grid(int n, int nsys, int tv) {
+  const int rows = kTileY * kSpmvRows[tile_variant(tv)];
   return dim3((n + kTileX - 1) / kTileX, (n + rows - 1) / rows, nsys);
 }
 
-int spmv_blocks(int dim, int n) {
+int spmv_blocks(int dim, int n, int tv) {
   if (dim != 2) return stencil_blocks(dim, n);
-  const dim3 g = spmv2_grid(n, 1);
+  const dim3 g = spmv2_grid(n, 1, tv);
   return (int)(g.x * g.y);
 }
 
@@ -1285,6 +1287,17 @@ int flat_blocks(long long N) {
 static inline dim3 flat_grid(long long N, int nsys) {
   const long long per = 256LL * kFlatItems;
   return dim3((unsigned)((N + per - 1) / per), nsys, 1);
+}
+
+// Calls f(std::integral_constant<int, v>) for the runtime variant tv.
+template <typename F>
+static inline void with_tile(int tv, F&& f) {
+  static_assert(kTileVariants == 3, "one case per variant");
+  switch (tile_variant(tv)) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    default: f(std::integral_constant<int, 0>{}); break;
+  }
 }
 
 #define BURA_DISPATCH_DV(dim, var, KERNEL, ...)        \
@@ -1384,19 +1397,22 @@ void Launch<T>::copy_rhs(const LevelDev<T>& L, int dim, const double* f, T* r, T
 template <typename T>
 void Launch<T>::spmv_p(int dim, bool var, const LevelDev<T>& L, const T* z, const T* pold, T* pnew, T* q,
                        const double* beta, const T* shift, const int* active, double* partial, int nsys,
-                       hipStream_t st, unsigned long long* ctr, Fin fin, T* x, const double* alpha) {
+                       hipStream_t st, unsigned long long* ctr, Fin fin, T* x, const double* alpha, int tv) {
   const bool xup = x != nullptr;
   if (dim == 2) {
-    const dim3 g2 = spmv2_grid(L.n, nsys), blk2(kTileX, kTileY);
+    const dim3 g2 = spmv2_grid(L.n, nsys, tv), blk2(kTileX, kTileY);
+    with_tile(tv, [&](auto v) {
+      constexpr int R = kSpmvRows[decltype(v)::value];
 #define K_SP2(V, X_) \
-  hipLaunchKernelGGL((k_spmv_p2<T, V, X_>), g2, blk2, 0, st, L, z, pold, pnew, q, beta, shift, active, partial, ctr, \
-                     fin, x, alpha)
-    if (var) {
-      if (xup) K_SP2(true, true); else K_SP2(true, false);
-    } else {
-      if (xup) K_SP2(false, true); else K_SP2(false, false);
-    }
+  hipLaunchKernelGGL((k_spmv_p2<T, V, X_, R>), g2, blk2, 0, st, L, z, pold, pnew, q, beta, shift, active, partial, \
+                     ctr, fin, x, alpha)
+      if (var) {
+        if (xup) K_SP2(true, true); else K_SP2(true, false);
+      } else {
+        if (xup) K_SP2(false, true); else K_SP2(false, false);
+      }
 #undef K_SP2
+    });
     return;
   }
   const dim3 g = stencil_grid(dim, L.n, nsys), blk(kTileX, kTileY);
@@ -1423,54 +1439,70 @@ template <typename T>
 bool Launch<T>::fused_down(int dim, bool var, int nu, const LevelDev<T>& Lf, const LevelDev<T>& Lc, const T* b,
                            T* xout, T* bc, const T* shift, const int* active, Sweeps<T> om, int nsys, hipStream_t st,
                            unsigned long long* ctr, const T* q, const double* alpha, T* bout, double* partial,
-                           Fin fin) {
+                           Fin fin, int tv) {
   if (dim != 2 || nu < 1 || nu > 3) return false;
-  const dim3 g((Lc.n + kDownCX - 1) / kDownCX, (Lc.n + kDownCY - 1) / kDownCY, nsys), blk(256);
   const bool rup = bout != nullptr;
+  with_tile(tv, [&](auto v) {
+    constexpr int CX = kDownTile[decltype(v)::value][0], CY = kDownTile[decltype(v)::value][1];
+    const dim3 g((Lc.n + CX - 1) / CX, (Lc.n + CY - 1) / CY, nsys), blk(256);
 #define K_DN0(V, NU_, R_)                                                                                          \
-  hipLaunchKernelGGL((k_down2<T, V, NU_, R_>), g, blk, 0, st, Lf, Lc, b, xout, bc, shift, active, om, ctr, q,     \
-                     alpha, bout, partial, fin)
+  hipLaunchKernelGGL((k_down2<T, V, NU_, R_, CX, CY>), g, blk, 0, st, Lf, Lc, b, xout, bc, shift, active, om, ctr, \
+                     q, alpha, bout, partial, fin)
 #define K_DN(V, NU_) do { if (rup) K_DN0(V, NU_, true); else K_DN0(V, NU_, false); } while (0)
-  if (var) {
-    if (nu == 1) K_DN(true, 1); else if (nu == 2) K_DN(true, 2); else K_DN(true, 3);
-  } else {
-    if (nu == 1) K_DN(false, 1); else if (nu == 2) K_DN(false, 2); else K_DN(false, 3);
-  }
+    if (var) {
+      if (nu == 1) K_DN(true, 1); else if (nu == 2) K_DN(true, 2); else K_DN(true, 3);
+    } else {
+      if (nu == 1) K_DN(false, 1); else if (nu == 2) K_DN(false, 2); else K_DN(false, 3);
+    }
 #undef K_DN
 #undef K_DN0
+  });
   return true;
 }
 
-int down_blocks(int dim, int n) {
+int down_blocks(int dim, int n, int tv) {
   if (dim != 2) return stencil_blocks(dim, n);
   const int nc = (n - 1) / 2;
-  return ((nc + kDownCX - 1) / kDownCX) * ((nc + kDownCY - 1) / kDownCY);
+  const int cx = kDownTile[tile_variant(tv)][0], cy = kDownTile[tile_variant(tv)][1];
+  return ((nc + cx - 1) / cx) * ((nc + cy - 1) / cy);
 }
 
 template <typename T>
 bool Launch<T>::fused_up(int dim, bool var, int nu, const LevelDev<T>& Lc, const LevelDev<T>& Lf, const T* xc,
                          const T* xin, const T* b, T* xout, const T* shift, const int* active, Sweeps<T> om,
-                         double* partial, int nsys, hipStream_t st, unsigned long long* ctr, Fin fin) {
+                         double* partial, int nsys, hipStream_t st, unsigned long long* ctr, Fin fin, int tv) {
   if (dim != 2 || nu < 1 || nu > 3) return false;
-  const dim3 g((Lf.n + kUpOX - 1) / kUpOX, (Lf.n + kUpOY - 1) / kUpOY, nsys), blk(256);
   const bool dot = partial != nullptr;
+  with_tile(tv, [&](auto v) {
+    constexpr int OX = kUpTile[decltype(v)::value][0], OY = kUpTile[decltype(v)::value][1];
+    const dim3 g((Lf.n + OX - 1) / OX, (Lf.n + OY - 1) / OY, nsys), blk(256);
 #define K_UP(V, NU_, D_) \
-  hipLaunchKernelGGL((k_up2<T, V, NU_, D_>), g, blk, 0, st, Lc, Lf, xc, xin, b, xout, shift, active, om, partial,    \
-                     ctr, fin)
+  hipLaunchKernelGGL((k_up2<T, V, NU_, D_, OX, OY>), g, blk, 0, st, Lc, Lf, xc, xin, b, xout, shift, active, om,   \
+                     partial, ctr, fin)
 #define K_UPD(V, NU_) do { if (dot) K_UP(V, NU_, true); else K_UP(V, NU_, false); } while (0)
-  if (var) {
-    if (nu == 1) K_UPD(true, 1); else if (nu == 2) K_UPD(true, 2); else K_UPD(true, 3);
-  } else {
-    if (nu == 1) K_UPD(false, 1); else if (nu == 2) K_UPD(false, 2); else K_UPD(false, 3);
-  }
+    if (var) {
+      if (nu == 1) K_UPD(true, 1); else if (nu == 2) K_UPD(true, 2); else K_UPD(true, 3);
+    } else {
+      if (nu == 1) K_UPD(false, 1); else if (nu == 2) K_UPD(false, 2); else K_UPD(false, 3);
+    }
 #undef K_UPD
 #undef K_UP
+  });
   return true;
 }
 
-int up_blocks(int dim, int n) {
+int up_blocks(int dim, int n, int tv) {
   if (dim != 2) return stencil_blocks(dim, n);
-  return ((n + kUpOX - 1) / kUpOX) * ((n + kUpOY - 1) / kUpOY);
+  const int ox = kUpTile[tile_variant(tv)][0], oy = kUpTile[tile_variant(tv)][1];
+  return ((n + ox - 1) / ox) * ((n + oy - 1) / oy);
+}
+
+// the most blocks per system any reduction-writing launch shape can have
+int max_partial_blocks(int dim, int n, long long N) {
+  int m = std::max(stencil_blocks(dim, n), flat_blocks(N));
+  for (int v = 0; v < kTileVariants; ++v)
+    m = std::max({m, up_blocks(dim, n, v), down_blocks(dim, n, v), spmv_blocks(dim, n, v)});
+  return m;
 }
 
 template struct Launch<float>;

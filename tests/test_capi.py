@@ -48,3 +48,36 @@ def test_coefficients_argument_errors(alpha, k, beta, code):
     with pytest.raises(B.BuraError) as ei:
         B.bura_coefficients(alpha, k, beta)
     assert ei.value.code == code
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The binding's ctypes structures have the C header's sizes and field offsets
+    (a C program built here with gcc prints them)."""
+    import ctypes
+    import subprocess
+    import paper_1612_04846_amd as B
+    structs = {"bura_grid_t": B.bura_grid_t, "bura_opts_t": B.bura_opts_t, "bura_report_t": B.bura_report_t,
+               "bura_request_t": B.bura_request_t, "bura_server_stats_t": B.bura_server_stats_t}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bura.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_tile_variant_count_matches_header():
+    import paper_1612_04846_amd as B
+    src = open(os.path.join(ROOT, "include", "bura.h")).read()
+    m = re.search(r"#define BURA_TILE_VARIANTS (\d+)", src)
+    assert m and int(m.group(1)) == B.BURA_TILE_VARIANTS

@@ -1,0 +1,142 @@
+"""GPU parity of every tile-shape variant of the 2D kernels, and the plan-time tuner.
+
+The variants (bura_plan_set_tiles) change only the launch shape of the
+stencil product and of the fused down/up level kernels: each computes the
+same value at every grid point, and only the grouping of the per-block
+partial sums of the PCG dot products differs.  So every variant, and the
+tuner's choice, must match the oracle at the same tolerance as the default
+shape.  The grids are chosen so that every variant has ragged edge tiles
+(255 -> 127 -> 63 ...: 127 is not a multiple of 4, 8 or 12 coarse rows, 255
+not a multiple of 8, 16 or 24 fine rows; 191 -> 95 -> 47 ... stops at an even
+level).
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from conftest import oracle_coeffs as oracle_bura
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _B():
+    import paper_1612_04846_amd as B
+    return B
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel2(u, ref):
+    return float((np.linalg.norm((u - ref).reshape(u.shape[0], -1), axis=1) /
+                  np.linalg.norm(ref.reshape(ref.shape[0], -1), axis=1)).max())
+
+
+def _reference(n, var, alpha, k, F, tag):
+    from oracle import operators, shifted, spectral
+    b = oracle_bura(alpha, k)
+    if not var:
+        return None, spectral.bura_spectral(F, 2, b.c_f64, b.d_f64)
+    coeff = synth.lognormal_coefficient(n, 2, tag=tag)
+    A, _ = operators.scaled_operator(n, 2, coeff)
+    return coeff, shifted.bura_by_solves(A, b.c_f64, b.d_f64, F)
+
+
+CASES = [
+    # n, variable coefficients, precision, alpha, k
+    (255, False, "FP64", 0.5, 5),
+    (255, True, "MIXED", 0.6, 7),
+    (191, False, "MIXED", 0.25, 6),
+]
+
+
+@pytest.mark.parametrize("n,var,prec,alpha,k", CASES)
+def test_every_tile_variant_matches_oracle(n, var, prec, alpha, k):
+    B = _B()
+    b = oracle_bura(alpha, k)
+    F = synth.normal_rhs(n, 2, nrhs=2, tag=401)
+    coeff, ref = _reference(n, var, alpha, k, F, tag=402)
+    plan = B.Plan(2, n, weights=b.c_f64, shifts=[-x for x in b.d_f64], coeff=coeff, nrhs_max=2,
+                  precision=getattr(B, "BURA_" + prec), tol=1e-12)
+    default = plan.tiles
+    assert default == [0] * len(default) and len(default) % 2 == 1 and len(default) >= 3
+    settings = [[v] * len(default) for v in range(B.BURA_TILE_VARIANTS)]
+    settings.append([(i % B.BURA_TILE_VARIANTS) for i in range(len(default))])   # mixed per level
+    u0 = None
+    for tv in settings:
+        plan.tiles = tv
+        assert plan.tiles == tv
+        res = plan.solve(_dev(F))
+        u = _host(res.u)
+        err = _rel2(u, ref)
+        print(f"n={n} var={var} {prec} tiles={tv}: rel2 vs oracle {err:.2e}, iters {list(res.report.iters)[:k + 1]}")
+        assert err <= 1e-9
+        if u0 is None:
+            u0 = u
+        else:
+            assert _rel2(u, u0) <= 1e-9
+    plan.close()
+
+
+def test_tuner_choice_is_valid_cached_and_correct():
+    B = _B()
+    n, alpha, k = 255, 0.6, 7
+    b = oracle_bura(alpha, k)
+    F = synth.normal_rhs(n, 2, nrhs=4, tag=411)
+    coeff, ref = _reference(n, True, alpha, k, F, tag=412)
+    kw = dict(weights=b.c_f64, shifts=[-x for x in b.d_f64], coeff=coeff, nrhs_max=4, precision=B.BURA_MIXED,
+              tol=1e-12, autotune=1)
+    p1 = B.Plan(2, n, **kw)
+    t1 = p1.tiles
+    assert len(t1) >= 3 and all(0 <= v < B.BURA_TILE_VARIANTS for v in t1)
+    u = _host(p1.solve(_dev(F)).u)
+    err = _rel2(u, ref)
+    print(f"tuned tiles {t1}: rel2 vs oracle {err:.2e}")
+    assert err <= 1e-9
+    p2 = B.Plan(2, n, **kw)   # same shape: the cached choice
+    assert p2.tiles == t1
+    p1.close()
+    p2.close()
+
+
+def test_set_tiles_rejects_bad_input():
+    B = _B()
+    b = oracle_bura(0.5, 5)
+    plan = B.Plan(2, 63, weights=b.c_f64, shifts=[-x for x in b.d_f64])
+    t = plan.tiles
+    with pytest.raises(B.BuraError) as ei:
+        plan.tiles = t + [0]
+    assert ei.value.code == B.BURA_EINVAL
+    with pytest.raises(B.BuraError) as ei:
+        plan.tiles = [B.BURA_TILE_VARIANTS] + t[1:]
+    assert ei.value.code == B.BURA_EINVAL
+    with pytest.raises(B.BuraError):
+        plan.tiles = [-1] + t[1:]
+    assert plan.tiles == t
+    plan.close()
+    p3 = B.Plan(3, 15, weights=b.c_f64, shifts=[-x for x in b.d_f64])
+    assert p3.tiles == []   # one launch shape in 3D
+    p3.close()
+
+
+def test_tiles_of_jacobi_pcg_grid():
+    """A 64 x 64 grid has no hierarchy: only the stencil product has variants."""
+    from oracle import spectral
+    B = _B()
+    b = oracle_bura(0.5, 5)
+    F = synth.normal_rhs(64, 2, nrhs=1, tag=421)
+    ref = spectral.bura_spectral(F, 2, b.c_f64, b.d_f64)
+    plan = B.Plan(2, 64, weights=b.c_f64, shifts=[-x for x in b.d_f64], precision=B.BURA_FP64, autotune=1)
+    assert len(plan.tiles) == 1
+    for v in range(B.BURA_TILE_VARIANTS):
+        plan.tiles = [v]
+        assert _rel2(_host(plan.solve(_dev(F)).u), ref) <= 1e-9
+    plan.close()
