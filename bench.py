@@ -326,12 +326,13 @@ def run_serving(args):
 
     failures = []
 
-    def stream(timed):
+    def stream(timed, scale=1.0):
+        """Submit every request (at its arrival time times scale when timed), wait for all."""
         t0 = time.perf_counter()
         tickets = []
         for r, f, u in zip(reqs, F, U):
             if timed:
-                delay = t0 + r.arrival - time.perf_counter()
+                delay = t0 + scale * r.arrival - time.perf_counter()
                 if delay > 0:
                     time.sleep(delay)
             tickets.append(B.bura_server_submit(server, r.dim, r.n, r.alpha, r.k, f, u,
@@ -364,13 +365,31 @@ def run_serving(args):
     base_cap = B.bura_server_stats(server)
     wall_cap, codes_cap = stream(False)
     st_cap = B.bura_server_stats(server)
+    # offered load swept around the measured capacity (arrival times rescaled)
+    upole_cap = st_cap["unknown_pole_solves"] - base_cap["unknown_pole_solves"]
+    cap_rate = upole_cap / wall_cap
+    span = max(r.arrival for r in reqs)
+    sweep = []
+    for factor in args.serve_load_sweep:
+        scale = upole_cap / (factor * cap_rate) / span if span > 0 else 0.0
+        print(f"[bench] serving load {factor:g} x capacity", file=sys.stderr, flush=True)
+        B.bura_server_reset_latency(server)
+        b0 = B.bura_server_stats(server)
+        w_s, codes_s = stream(True, scale)
+        b1 = B.bura_server_stats(server)
+        codes_cap += codes_s
+        nb = b1["batches"] - b0["batches"]
+        sweep.append({"load_factor": factor, "offered_solves_per_s": upole_cap / (span * scale) if scale else None,
+                      "achieved_solves_per_s": (b1["unknown_pole_solves"] - b0["unknown_pole_solves"]) / w_s,
+                      "p50_ms": 1e3 * b1["p50_latency_s"], "p99_ms": 1e3 * b1["p99_latency_s"],
+                      "requests_per_batch": (b1["completed"] - b0["completed"]) / nb if nb else None})
     B.bura_server_destroy(server)
     ok = [c == B.BURA_OK for c in codes + codes_cap]
     upole = st["unknown_pole_solves"] - base["unknown_pole_solves"]
-    upole_cap = st_cap["unknown_pole_solves"] - base_cap["unknown_pole_solves"]
     return dict(wall=wall, ok=ok, stats=st, base=base, upole=upole, reqs=reqs, F=F, U=U, failures=failures,
                 wall_cap=wall_cap, upole_cap=upole_cap, cold=cold, cold_p50=cold_st["p50_latency_s"],
-                cold_p99=cold_st["p99_latency_s"])
+                cold_p99=cold_st["p99_latency_s"], sweep=sweep,
+                cap_batch=(st_cap["completed"] - base_cap["completed"]) / max(1, st_cap["batches"] - base_cap["batches"]))
 
 
 def main():
@@ -388,6 +407,9 @@ def main():
     ap.add_argument("--serve-concurrency", type=int, default=4)
     ap.add_argument("--serve-group", type=int, default=2)
     ap.add_argument("--serve-budget-gb", type=float, default=160.0)
+    ap.add_argument("--serve-load-sweep", type=lambda x: [float(v) for v in x.split(",") if v],
+                    default=[0.5, 0.8, 1.0, 1.2],
+                    help="offered loads (multiples of the measured capacity) for the latency sweep")
     ap.add_argument("--omega", type=float, default=0.0,
                     help="uniform damping of every smoothing sweep (0: the library's default weights)")
     ap.add_argument("--nu", type=int, default=0, help="smoothing sweeps before and after (0: default 2)")
@@ -448,7 +470,8 @@ def main():
                                    "per": "first pass, including plan creation (Remez, hierarchy, graphs)"},
                "offered_load_solves_per_s": res["upole"] / res["wall"],
                "capacity": {"seconds": res["wall_cap"], "unknown_pole_solves_per_s": res["upole_cap"] / res["wall_cap"],
-                            "per": "all requests queued at once"},
+                            "requests_per_batch": res["cap_batch"], "per": "all requests queued at once"},
+               "load_sweep": res["sweep"],
                "server": {k: v for k, v in st.items()}}
         accepted = all(res["ok"])
         out["failures"] = res["failures"][:12]

@@ -220,6 +220,33 @@ int bura_plan_create_product(const bura_grid_t* grid, double alpha, int beta, in
 int bura_plan_create_multi(const bura_grid_t* grid, int nalpha, const double* alphas, int beta, const int* ks,
                            const bura_opts_t* opts, bura_plan_t* out);
 
+/* A plan whose partial-fraction terms come with each solve (eq. (16) with
+ * per-right-hand-side weights and shifts): right-hand side r of a solve is
+ * mapped to u_r = sum_{j < nterms[r]} w_rj (A + s_rj I)^{-1} f_r, so requests
+ * for different fractional powers, numbers of poles or tolerances on one grid
+ * share one batched solve.  The plan holds max_terms * nrhs_max systems
+ * (max_terms <= BURA_MAX_TERMS); a system slot that a solve leaves unused
+ * costs one early exit per launch.  Only BURA_BATCHED (else
+ * BURA_EUNSUPPORTED).  bura_solve / bura_submit on such a plan return
+ * BURA_EINVAL; bura_plan_coeffs returns max_terms zero placeholders. */
+int bura_plan_create_slots(const bura_grid_t* grid, int max_terms, const bura_opts_t* opts, bura_plan_t* out);
+
+/* Solve on a slot plan.  f_dev, u_dev: [nrhs][N] FP64 device buffers (caller
+ * owned), nrhs <= nrhs_max.  Host arrays: nterms[nrhs] (1..max_terms),
+ * weights and shifts [nrhs][max_terms] (row r, entries j < nterms[r] used;
+ * weights finite, shifts >= 0 and finite), tol[nrhs] the FP64 relative
+ * residual tolerance of each rhs (NULL: opts.tol for all).  The report's
+ * per-term entries are maxima over the rhs that use the term; its E is 0.
+ * Synchronous like bura_solve; BURA_EINVAL on a plan not made by
+ * bura_plan_create_slots or on invalid terms. */
+int bura_solve_slots(bura_plan_t plan, const double* f_dev, double* u_dev, int nrhs, const int* nterms,
+                     const double* weights, const double* shifts, const double* tol, bura_report_t* rep);
+
+/* Asynchronous bura_solve_slots (the host arrays are copied before it
+ * returns); completion and report through bura_poll. */
+int bura_submit_slots(bura_plan_t plan, const double* f_dev, double* u_dev, int nrhs, const int* nterms,
+                      const double* weights, const double* shifts, const double* tol);
+
 /* Number of outputs and their term ranges: output i uses terms
  * [term_begin[i], term_begin[i+1]); term_begin has nout + 1 entries. */
 int bura_plan_outputs(bura_plan_t plan, int* nout, int* term_begin);
@@ -302,10 +329,14 @@ int bura_plan_kernel_stats(bura_plan_t plan, int kclass, long long* launches, do
  * Request server (continuous batching on one GPU).
  *
  * Requests for the constant-coefficient grids are queued by bura_server_submit
- * and served by a dispatcher thread: plans are kept resident per
- * (dim, n, alpha, k, precision, tol); an idle plan takes the queued requests
- * with its key (up to max_group of them, batched as right-hand sides of one
- * solve); up to max_concurrent plans solve at once on their own streams, so
+ * (which computes the request's BURA terms, cached per (alpha, k), and fails
+ * with that status if they cannot be computed) and served by a dispatcher
+ * thread: one slot plan (bura_plan_create_slots, 17 terms per right-hand side)
+ * is kept resident per (dim, n, precision); an idle plan takes the queued
+ * requests for its grid, whatever their alpha, k and tol (up to max_group of
+ * them, first come first served, batched as right-hand sides of one solve,
+ * each with its own terms and tolerance); up to max_concurrent plans solve at
+ * once on their own streams, so
  * requests that arrive while others run are admitted as soon as a plan and
  * memory are free.  New plans are admitted against hbm_budget bytes (0 =
  * unlimited), evicting idle plans least recently used first; a request whose

@@ -137,6 +137,9 @@ _SIGS = {
                                       ctypes.POINTER(_P)]),
     "bura_plan_create_sinc": (_I, [ctypes.POINTER(bura_grid_t), _I, _DP, _DP, ctypes.POINTER(bura_opts_t),
                                    ctypes.POINTER(_P)]),
+    "bura_plan_create_slots": (_I, [ctypes.POINTER(bura_grid_t), _I, ctypes.POINTER(bura_opts_t), ctypes.POINTER(_P)]),
+    "bura_solve_slots": (_I, [_P, _P, _P, _I, ctypes.POINTER(_I), _DP, _DP, _DP, ctypes.POINTER(bura_report_t)]),
+    "bura_submit_slots": (_I, [_P, _P, _P, _I, ctypes.POINTER(_I), _DP, _DP, _DP]),
     "bura_plan_outputs": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "bura_solve": (_I, [_P, _P, _P, _I, ctypes.POINTER(bura_report_t)]),
     "bura_submit": (_I, [_P, _P, _P, _I]),
@@ -273,6 +276,49 @@ def bura_plan_create_rational(dim: int, n: int, weights: Sequence[float], shifts
     _check(_lib.bura_plan_create_rational(ctypes.byref(g), m, w, s, ctypes.byref(o), ctypes.byref(h)),
            "bura_plan_create_rational")
     return h
+
+
+def bura_plan_create_slots(dim: int, n: int, max_terms: int, opts: Optional[bura_opts_t] = None, coeff=None,
+                           lambda_upper: float = 0.0):
+    g, _keep = _grid(dim, n, coeff, lambda_upper)
+    o = opts if opts is not None else bura_opts_default()
+    h = _P()
+    _check(_lib.bura_plan_create_slots(ctypes.byref(g), max_terms, ctypes.byref(o), ctypes.byref(h)),
+           "bura_plan_create_slots")
+    return h
+
+
+def _slot_arrays(max_terms, terms, tols):
+    """terms: per rhs a (weights, shifts) pair -> the C arrays of bura_solve_slots."""
+    nr = len(terms)
+    nt = (ctypes.c_int * nr)(*[len(w) for w, _ in terms])
+    w = (ctypes.c_double * (nr * max_terms))()
+    s = (ctypes.c_double * (nr * max_terms))()
+    for r, (wr, sr) in enumerate(terms):
+        if len(wr) != len(sr) or len(wr) > max_terms:
+            raise ValueError("each rhs needs equally many weights and shifts, at most max_terms")
+        for j, (a, b) in enumerate(zip(wr, sr)):
+            w[r * max_terms + j] = a
+            s[r * max_terms + j] = b
+    t = (ctypes.c_double * nr)(*tols) if tols is not None else None
+    return nt, w, s, t
+
+
+def bura_solve_slots(plan, max_terms: int, f: torch.Tensor, u: torch.Tensor, terms, tols=None,
+                     ok=(BURA_OK,)) -> bura_report_t:
+    """terms[r] = (weights, shifts) of right-hand side r; tols[r] its tolerance (None: the plan's)."""
+    nt, w, s, t = _slot_arrays(max_terms, terms, tols)
+    rep = bura_report_t()
+    code = _lib.bura_solve_slots(plan, _devptr(f, "f"), _devptr(u, "u"), len(terms), nt, w, s, t, ctypes.byref(rep))
+    rep.status = code
+    _check(code, "bura_solve_slots", ok)
+    return rep
+
+
+def bura_submit_slots(plan, max_terms: int, f: torch.Tensor, u: torch.Tensor, terms, tols=None) -> int:
+    nt, w, s, t = _slot_arrays(max_terms, terms, tols)
+    return _check(_lib.bura_submit_slots(plan, _devptr(f, "f"), _devptr(u, "u"), len(terms), nt, w, s, t),
+                  "bura_submit_slots")
 
 
 def bura_plan_create_rational_multi(dim: int, n: int, nterms: Sequence[int], weights: Sequence[float],

@@ -119,6 +119,15 @@ struct bura_plan_s {
   int tile_spmv = 0;
   std::vector<int> tile_down, tile_up;
   int S = 0;                   // systems = nterms * nrhs_max
+  // slot plan (bura_plan_create_slots): weights, shifts and tolerances are set
+  // per solve and per rhs; d_wsys / d_tol hold them per system, h_slot is the
+  // pinned staging area of one solve's per-system values
+  bool slots = false;
+  double* d_wsys = nullptr;
+  double* d_tol = nullptr;
+  void* h_slot = nullptr;
+  std::vector<int> slot_nterms;            // terms per rhs of the pending asynchronous solve
+  std::vector<double> slot_w, slot_s, slot_tol;
   // device buffers
   Work<double> w64;
   Work<float> w32;
@@ -708,6 +717,8 @@ SysState state_at(const bura_plan_t P, size_t sys0) {
   s.bnorm2 += sys0; s.rho += sys0; s.alpha += sys0; s.beta += sys0; s.relres += sys0;
   s.active += sys0; s.iters += sys0; s.total_iters += sys0; s.flags += sys0;
   s.fnorm2 += sys0; s.relres64 += sys0; s.active64 += sys0; s.outer += sys0;
+  if (s.tol_pcg) s.tol_pcg += sys0;
+  if (s.tol_outer) s.tol_outer += sys0;
   return s;
 }
 
@@ -937,9 +948,71 @@ int solve_batch_mixed(bura_plan_t P, const double* f, int nrhs, size_t sys0, int
   return BURA_OK;
 }
 
-int do_solve(bura_plan_t P, const double* f, double* u, int nrhs, bura_report_t* rep) {
+// Per-solve terms of a slot plan: rhs r has nterms[r] terms with weights
+// w[r * max_terms + j], shifts s[r * max_terms + j] and tolerance tol[r].
+struct SlotTerms {
+  const int* nterms;
+  const double* w;
+  const double* s;
+  const double* tol;   // nullptr: opts.tol for every rhs
+};
+
+int check_slot_terms(const bura_plan_t P, int nrhs, const SlotTerms& t) {
+  if (!t.nterms || !t.w || !t.s) return BURA_EINVAL;
+  const int K = P->nterms;
+  for (int r = 0; r < nrhs; ++r) {
+    if (t.nterms[r] < 1 || t.nterms[r] > K) return BURA_EINVAL;
+    if (t.tol && !(t.tol[r] > 0.0)) return BURA_EINVAL;
+    for (int j = 0; j < t.nterms[r]; ++j) {
+      const double w = t.w[(size_t)r * K + j], sh = t.s[(size_t)r * K + j];
+      if (!std::isfinite(w) || !(sh >= 0.0) || !std::isfinite(sh)) return BURA_EINVAL;
+    }
+  }
+  return BURA_OK;
+}
+
+// Upload one solve's per-system weights, shifts, tolerances and active flags
+// (system j * R + r is used iff r < nrhs and j < nterms[r]).
+int upload_slots(bura_plan_t P, int nrhs, const SlotTerms& t) {
+  const int K = P->nterms, R = P->opts.nrhs_max;
+  const size_t S = (size_t)P->S;
+  const bool mixed = P->opts.precision == BURA_MIXED;
+  double* hw = (double*)P->h_slot;
+  double* hs = hw + S;
+  double* ht = hs + S;
+  float* hs32 = (float*)(ht + S);
+  int* hf = (int*)(hs32 + S);
+  for (int j = 0; j < K; ++j) {
+    for (int r = 0; r < R; ++r) {
+      const size_t i = (size_t)j * R + r;
+      const bool used = r < nrhs && j < t.nterms[r];
+      hw[i] = used ? t.w[(size_t)r * K + j] : 0.0;
+      hs[i] = used ? t.s[(size_t)r * K + j] : 0.0;
+      ht[i] = used && t.tol ? t.tol[r] : P->opts.tol;
+      hs32[i] = (float)hs[i];
+      hf[i] = used ? 1 : 0;
+    }
+  }
+  hipStream_t st = P->stream;
+  HIPCHK(hipMemcpyAsync(P->d_wsys, hw, S * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(P->d_shift64, hs, S * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(P->d_tol, ht, S * 8, hipMemcpyHostToDevice, st));
+  if (mixed) {
+    HIPCHK(hipMemcpyAsync(P->w32.shift, hs32, S * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(P->st.active64, hf, S * 4, hipMemcpyHostToDevice, st));
+  } else {
+    HIPCHK(hipMemcpyAsync(P->w64.shift, hs, S * 8, hipMemcpyHostToDevice, st));
+  }
+  HIPCHK(hipMemcpyAsync(P->st.active, hf, S * 4, hipMemcpyHostToDevice, st));
+  return BURA_OK;
+}
+
+int do_solve(bura_plan_t P, const double* f, double* u, int nrhs, bura_report_t* rep,
+             const SlotTerms* slot = nullptr) {
   const auto t0 = std::chrono::steady_clock::now();
   if (!P || !f || !u || nrhs < 1 || nrhs > P->opts.nrhs_max) return BURA_EINVAL;
+  if (P->slots != (slot != nullptr)) return BURA_EINVAL;
+  if (slot && check_slot_terms(P, nrhs, *slot)) return BURA_EINVAL;
   HIPCHK(hipSetDevice(P->device));
   const bool mixed = P->opts.precision == BURA_MIXED;
   const int R = P->opts.nrhs_max;
@@ -959,7 +1032,14 @@ int do_solve(bura_plan_t P, const double* f, double* u, int nrhs, bura_report_t*
   };
   auto batch = [&](size_t sys0, int nsys, bool preset) { return batch_rhs(f, sys0, nsys, preset); };
   const double* xsol = mixed ? P->x64 : P->w64.x;
-  if (!P->stages.empty()) {
+  if (slot) {
+    // every rhs with its own terms, all in one batch; unused slots inactive
+    if ((rc = upload_slots(P, nrhs, *slot))) return rc;
+    rc = batch(0, (int)S_used, true);
+    if (rc) return rc;
+    ProfScope ps(P, BURA_K_COMBINE);
+    launch_combine(P->N, xsol, P->d_wsys, P->nterms, nrhs, R, u, P->stream, ps.ctr, nullptr, 0.0, true);
+  } else if (!P->stages.empty()) {
     // sequential form: each stage solves its terms against its input, then
     // combines into the stage buffer (or u for the last stage)
     rc = BURA_OK;
@@ -999,7 +1079,7 @@ int do_solve(bura_plan_t P, const double* f, double* u, int nrhs, bura_report_t*
   }
   if (rc) return rc;
   // combine u_i = sum_{j in output i} w_j x_j (fixed order, FP64)
-  for (int i = 0; i < P->nout && P->stages.empty(); ++i) {
+  for (int i = 0; i < P->nout && P->stages.empty() && !slot; ++i) {
     ProfScope ps(P, BURA_K_COMBINE);
     const int b = P->out_begin[i], e = P->out_end[i];
     launch_combine(P->N, xsol + (size_t)b * R * P->N, P->d_w + b, e - b, nrhs, R, u + (size_t)i * nrhs * P->N,
@@ -1022,15 +1102,18 @@ int do_solve(bura_plan_t P, const double* f, double* u, int nrhs, bura_report_t*
   int status = BURA_OK;
   bura_report_t R_{};
   R_.nterms = P->nterms;
+  if (slot) R_.nterms = *std::max_element(slot->nterms, slot->nterms + nrhs);
   R_.E = P->E;
   for (int j = 0; j < P->nterms && j < BURA_MAX_TERMS; ++j) {
     for (int r = 0; r < nrhs; ++r) {
+      if (slot && j >= slot->nterms[r]) continue;
+      const double tol = slot && slot->tol ? slot->tol[r] : P->opts.tol;
       const size_t s = (size_t)j * R + r;
       R_.iters[j] = std::max(R_.iters[j], it[s]);
       R_.outer[j] = std::max(R_.outer[j], outer[s]);
       R_.relres[j] = std::max(R_.relres[j], rr[s]);
       if (flags[s] & 1) status = BURA_ENAN;
-      if (status == BURA_OK && !(rr[s] <= P->opts.tol)) status = BURA_ENOCONV;
+      if (status == BURA_OK && !(rr[s] <= tol)) status = BURA_ENOCONV;
     }
   }
   R_.status = status;
@@ -1384,6 +1467,32 @@ int bura_plan_create_rational(const bura_grid_t* grid, int nterms, const double*
   return create(grid, t, opts, out);
 }
 
+int bura_plan_create_slots(const bura_grid_t* grid, int max_terms, const bura_opts_t* opts, bura_plan_t* out) {
+  if (out) *out = nullptr;
+  if (!out || max_terms < 1 || max_terms > BURA_MAX_TERMS) return BURA_EINVAL;
+  if (opts && opts->schedule != BURA_BATCHED) return BURA_EUNSUPPORTED;
+  Terms t;   // placeholders: every solve brings its own weights and shifts
+  t.w.assign(max_terms, 0.0);
+  t.s.assign(max_terms, 0.0);
+  bura_plan_t P = nullptr;
+  int rc = create(grid, t, opts, &P);
+  if (rc) return rc;
+  const size_t S = (size_t)P->S;
+  if ((rc = dev_alloc(P, (void**)&P->d_wsys, S * 8)) || (rc = dev_alloc(P, (void**)&P->d_tol, S * 8))) {
+    bura_plan_destroy(P);
+    return rc;
+  }
+  if (hipHostMalloc(&P->h_slot, S * (3 * 8 + 4 + 4), hipHostMallocDefault) != hipSuccess) {
+    bura_plan_destroy(P);
+    return BURA_ENOMEM;
+  }
+  P->slots = true;
+  if (P->opts.precision == BURA_MIXED) P->st.tol_outer = P->d_tol;
+  else P->st.tol_pcg = P->d_tol;
+  *out = P;
+  return BURA_OK;
+}
+
 int bura_plan_create_rational_multi(const bura_grid_t* grid, int nout, const int* nterms, const double* weights,
                                     const double* shifts, const bura_opts_t* opts, bura_plan_t* out) {
   if (out) *out = nullptr;
@@ -1567,8 +1676,44 @@ int bura_solve(bura_plan_t plan, const double* f_dev, double* u_dev, int nrhs, b
   return do_solve(plan, f_dev, u_dev, nrhs, rep);
 }
 
+int bura_solve_slots(bura_plan_t plan, const double* f_dev, double* u_dev, int nrhs, const int* nterms,
+                     const double* weights, const double* shifts, const double* tol, bura_report_t* rep) {
+  if (!plan) return BURA_EINVAL;
+  if (plan->busy.load()) return BURA_EBUSY;
+  const SlotTerms t{nterms, weights, shifts, tol};
+  return do_solve(plan, f_dev, u_dev, nrhs, rep, &t);
+}
+
+int bura_submit_slots(bura_plan_t plan, const double* f_dev, double* u_dev, int nrhs, const int* nterms,
+                      const double* weights, const double* shifts, const double* tol) {
+  if (!plan || !plan->slots || !f_dev || !u_dev || nrhs < 1 || nrhs > plan->opts.nrhs_max) return BURA_EINVAL;
+  const SlotTerms t{nterms, weights, shifts, tol};
+  if (check_slot_terms(plan, nrhs, t)) return BURA_EINVAL;
+  int expected = 0;
+  if (!plan->busy.compare_exchange_strong(expected, 1)) return BURA_EBUSY;
+  if (plan->worker.joinable()) plan->worker.join();
+  // the worker reads the plan's own copies (the caller's arrays may go away)
+  const size_t K = (size_t)plan->nterms;
+  plan->slot_nterms.assign(nterms, nterms + nrhs);
+  plan->slot_w.assign(weights, weights + nrhs * K);
+  plan->slot_s.assign(shifts, shifts + nrhs * K);
+  if (tol) plan->slot_tol.assign(tol, tol + nrhs);
+  else plan->slot_tol.clear();
+  plan->worker = std::thread([plan, f_dev, u_dev, nrhs]() {
+    bura_report_t rep{};
+    const SlotTerms st{plan->slot_nterms.data(), plan->slot_w.data(), plan->slot_s.data(),
+                       plan->slot_tol.empty() ? nullptr : plan->slot_tol.data()};
+    const int rc = do_solve(plan, f_dev, u_dev, nrhs, &rep, &st);
+    plan->async_status = rc;
+    rep.status = rc;
+    plan->async_report = rep;
+    plan->busy.store(2);
+  });
+  return BURA_OK;
+}
+
 int bura_submit(bura_plan_t plan, const double* f_dev, double* u_dev, int nrhs) {
-  if (!plan || !f_dev || !u_dev || nrhs < 1 || nrhs > plan->opts.nrhs_max) return BURA_EINVAL;
+  if (!plan || plan->slots || !f_dev || !u_dev || nrhs < 1 || nrhs > plan->opts.nrhs_max) return BURA_EINVAL;
   int expected = 0;
   if (!plan->busy.compare_exchange_strong(expected, 1)) return BURA_EBUSY;
   if (plan->worker.joinable()) plan->worker.join();
@@ -1711,6 +1856,7 @@ void bura_plan_destroy(bura_plan_t plan) {
   for (void* p : plan->allocs) hipFree(p);
   if (plan->h_flags) hipHostFree(plan->h_flags);
   if (plan->h_state) hipHostFree(plan->h_state);
+  if (plan->h_slot) hipHostFree(plan->h_slot);
   if (plan->join_ev) hipEventDestroy(plan->join_ev);
   if (plan->stream) hipStreamDestroy(plan->stream);
   delete plan;

@@ -72,6 +72,10 @@ struct SysState {
   double* relres64;
   int* active64;
   int* outer;
+  // per-system stopping tolerances (nullptr: the scalar passed with the
+  // operation): of the PCG (FP64 mode) and of the refinement (MIXED mode)
+  const double* tol_pcg = nullptr;
+  const double* tol_outer = nullptr;
 };
 
 enum ScalarOp { OP_INIT = 0, OP_ALPHA = 1, OP_RESID = 2, OP_BETA = 3, OP_OUTER = 4 };
@@ -138,8 +142,11 @@ void launch_residual64(int dim, bool var, const LevelDev<double>& L, const doubl
                        bool first, hipStream_t st, unsigned long long* ctr);
 void launch_x_from_e(const LevelDev<double>& L, int dim, const float* e, double* x64, const int* active64,
                      int nsys, hipStream_t st);
+// u_r = base_w base_r + sum_j w_j x_{j stride + r}; with w_per_system the weight
+// of term j of rhs r is w[j stride + r] and zero weights skip their term
 void launch_combine(long long N, const double* x, const double* w, int nterms, int nrhs, int stride, double* u,
-                    hipStream_t st, unsigned long long* ctr, const double* base = nullptr, double base_w = 0.0);
+                    hipStream_t st, unsigned long long* ctr, const double* base = nullptr, double base_w = 0.0,
+                    bool w_per_system = false);
 void launch_apply64(int dim, bool var, const LevelDev<double>& L, const double* x, double* y, double shift,
                     int nvec, hipStream_t st);
 void launch_scalars(int op, const double* partial, int nblk, int nsys, SysState st_, double tol,

@@ -1129,13 +1129,21 @@ __global__ __launch_bounds__(256) void k_x_from_e(long long N, const float* __re
 // base may be u itself (each element is read before it is written).
 __global__ __launch_bounds__(256) void k_combine(long long N, const double* x, const double* __restrict__ w,
                                                  int nterms, int stride, double* u, const double* base,
-                                                 double base_w, unsigned long long* __restrict__ ctr) {
+                                                 double base_w, unsigned long long* __restrict__ ctr, int wsys) {
   const int r = blockIdx.y;
   const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
   count_bytes<COUNT_FLAT>(ctr, (unsigned long long)N * 8ULL * (nterms + 1 + (base ? 1 : 0)));
   if (p >= N) return;
   double acc = base ? base_w * base[(long long)r * N + p] : 0.0;
-  for (int j = 0; j < nterms; ++j) acc += w[j] * x[((long long)j * stride + r) * N + p];
+  for (int j = 0; j < nterms; ++j) {
+    if (wsys) {
+      // per-system weights: a zero weight marks an unused slot, whose x is not read
+      const double wv = w[(long long)j * stride + r];
+      if (wv != 0.0) acc += wv * x[((long long)j * stride + r) * N + p];
+    } else {
+      acc += w[j] * x[((long long)j * stride + r) * N + p];
+    }
+  }
   u[(long long)r * N + p] = acc;
 }
 
@@ -1205,7 +1213,7 @@ __device__ void apply_op(int op, double tot, const SysState& S, int sys, double 
       if (!isfinite(rel)) {
         S.flags[sys] |= 1;
         S.active[sys] = 0;
-      } else if (rel <= tol || it >= max_iter) {
+      } else if (rel <= (S.tol_pcg ? S.tol_pcg[sys] : tol) || it >= max_iter) {
         S.active[sys] = 0;
       }
       break;
@@ -1225,7 +1233,7 @@ __device__ void apply_op(int op, double tot, const SysState& S, int sys, double 
       const double rel = fn > 0.0 ? sqrt(tot / fn) : 0.0;
       S.relres64[sys] = rel;
       S.outer[sys] = o + 1;
-      if (rel <= tol || o >= max_iter) {
+      if (rel <= (S.tol_outer ? S.tol_outer[sys] : tol) || o >= max_iter) {
         S.active64[sys] = 0;
         S.active[sys] = 0;
       } else {
@@ -1530,9 +1538,10 @@ void launch_x_from_e(const LevelDev<double>& L, int dim, const float* e, double*
 }
 
 void launch_combine(long long N, const double* x, const double* w, int nterms, int nrhs, int stride, double* u,
-                    hipStream_t st, unsigned long long* ctr, const double* base, double base_w) {
+                    hipStream_t st, unsigned long long* ctr, const double* base, double base_w, bool w_per_system) {
   const dim3 g((unsigned)((N + 255) / 256), nrhs);
-  hipLaunchKernelGGL(k_combine, g, dim3(256), 0, st, N, x, w, nterms, stride, u, base, base_w, ctr);
+  hipLaunchKernelGGL(k_combine, g, dim3(256), 0, st, N, x, w, nterms, stride, u, base, base_w, ctr,
+                     w_per_system ? 1 : 0);
 }
 
 void launch_apply64(int dim, bool var, const LevelDev<double>& L, const double* x, double* y, double shift, int nvec,

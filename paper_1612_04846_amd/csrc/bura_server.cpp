@@ -1,16 +1,17 @@
 // Request server with continuous batching for fractional solves on one GPU.
 //
 // Requests (grid, alpha, k, tolerance, precision, f, u) are queued on submit.
-// A dispatcher thread keeps plans resident in a cache keyed by
-// (dim, n, alpha, k, precision, tol); each plan runs one solve at a time on its
-// own stream, and several plans run concurrently, so work of different
-// requests overlaps on the device.  Whenever a plan is idle, the queued
-// requests with its key (up to the plan's right-hand-side slots) are batched
-// into one solve; a request never waits for unrelated requests.  New plans are
-// admitted against an HBM budget; idle plans are evicted least recently used
-// first when the budget would be exceeded.  Each request's result depends only
-// on its own right-hand side (the solver's per-system arithmetic and fixed-order
-// reductions do not depend on the other systems of a batch).
+// A dispatcher thread keeps one slot plan (bura_plan_create_slots) resident per
+// (dim, n, precision): every right-hand side of a slot plan's solve carries its
+// own partial-fraction terms and tolerance, so queued requests for the same
+// grid are batched into one solve whatever their alpha, k and tolerance.  Each
+// plan runs one solve at a time on its own stream, and several plans run
+// concurrently, so work of different grids overlaps on the device; a request
+// never waits for requests of other grids.  New plans are admitted against an
+// HBM budget; idle plans are evicted least recently used first when the budget
+// would be exceeded.  Each request's result depends only on its own
+// right-hand side and terms (the solver's per-system arithmetic and
+// fixed-order reductions do not depend on the other systems of a batch).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,9 +33,13 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+constexpr int kSlotTerms = 17;   // k <= 16 poles: up to 17 terms per request
+
 struct Req {
   uint64_t id = 0;
   bura_request_t q{};
+  double w[kSlotTerms] = {}, s[kSlotTerms] = {};   // the request's terms (weights, shifts)
+  double E = 0.0;
   const double* f = nullptr;
   double* u = nullptr;
   Clock::time_point t_submit, t_done;
@@ -58,8 +63,8 @@ struct Entry {
 };
 
 std::string key_of(const bura_request_t& q) {
-  char b[200];
-  std::snprintf(b, sizeof(b), "%d/%d/%.17g/%d/%d/%.17g", q.dim, q.n, q.alpha, q.k, q.precision, q.tol);
+  char b[64];
+  std::snprintf(b, sizeof(b), "%d/%d/%d", q.dim, q.n, q.precision);
   return b;
 }
 
@@ -105,7 +110,6 @@ struct bura_server_s {
       bura_opts_t o;
       bura_opts_default(&o);
       o.precision = r->q.precision;
-      o.tol = r->q.tol;
       o.nrhs_max = max_group;
       long long N = 1;
       for (int a = 0; a < g.dim; ++a) N *= g.n;
@@ -126,7 +130,7 @@ struct bura_server_s {
       }
       o.stream = es;
       bura_plan_t p = nullptr;
-      int rc = (*err == BURA_ENOMEM) ? BURA_ENOMEM : bura_plan_create(&g, r->q.alpha, 1, r->q.k, &o, &p);
+      int rc = (*err == BURA_ENOMEM) ? BURA_ENOMEM : bura_plan_create_slots(&g, kSlotTerms, &o, &p);
       if (rc != BURA_OK) hipStreamDestroy(es);
       if (rc == BURA_OK) {
         auto e = std::make_unique<Entry>();
@@ -188,6 +192,8 @@ struct bura_server_s {
       r->status = rc;
       r->rep = rep;
       r->rep.status = rc;
+      r->rep.nterms = r->q.k + 1;
+      r->rep.E = r->E;
       r->t_done = now;
       r->done = true;
       ++completed;
@@ -275,6 +281,17 @@ struct bura_server_s {
         const int g = (int)e->group.size();
         const double* f = r->f;
         double* u = r->u;
+        int nterms[64];
+        double w[64 * kSlotTerms] = {}, sh[64 * kSlotTerms] = {}, tol[64];
+        for (int i = 0; i < g; ++i) {
+          const Req& q = *e->group[i];
+          nterms[i] = q.q.k + 1;
+          tol[i] = q.q.tol;
+          for (int j = 0; j <= q.q.k; ++j) {
+            w[i * kSlotTerms + j] = q.w[j];
+            sh[i * kSlotTerms + j] = q.s[j];
+          }
+        }
         if (g > 1) {
           for (int i = 0; i < g; ++i)
             hipMemcpyAsync(e->f_stage + (size_t)i * e->N, e->group[i]->f, e->N * 8, hipMemcpyDeviceToDevice,
@@ -283,7 +300,7 @@ struct bura_server_s {
           f = e->f_stage;
           u = e->u_stage;
         }
-        const int rc = bura_submit(e->plan, f, u, g);
+        const int rc = bura_submit_slots(e->plan, f, u, g, nterms, w, sh, tol);
         if (rc != BURA_OK) {
           for (auto& q : e->group) fail(q, rc);
           e->group.clear();
@@ -328,6 +345,14 @@ int bura_server_submit(bura_server_t s, const bura_request_t* req, const double*
   r->q = *req;
   r->f = f_dev;
   r->u = u_dev;
+  // the request's terms, eq. (16): weights c_j and shifts -d_j (cached per (alpha, k))
+  double c[kSlotTerms], d[kSlotTerms];
+  const int rc = bura_coefficients(req->alpha, 1, req->k, c, d, &r->E);
+  if (rc != BURA_OK) return rc;
+  for (int j = 0; j <= req->k; ++j) {
+    r->w[j] = c[j];
+    r->s[j] = -d[j];
+  }
   r->t_submit = Clock::now();
   std::lock_guard<std::mutex> lk(s->mu);
   r->id = s->next_id++;

@@ -15,21 +15,21 @@ def _B():
     return B
 
 
-REQS = [  # dim, n, alpha, k, tag
-    (2, 127, 0.5, 5, 101), (2, 127, 0.5, 5, 102), (2, 127, 0.5, 5, 103),
-    (2, 63, 0.25, 7, 104), (3, 31, 0.75, 6, 105), (2, 255, 0.9, 12, 106), (2, 127, 0.5, 5, 107),
-    (3, 31, 0.75, 6, 108),
+REQS = [  # dim, n, alpha, k, tag, tol: requests on one grid batch together whatever alpha, k, tol
+    (2, 127, 0.5, 5, 101, 1e-11), (2, 127, 0.25, 9, 102, 1e-10), (2, 127, 0.5, 5, 103, 1e-11),
+    (2, 63, 0.25, 7, 104, 1e-11), (3, 31, 0.75, 6, 105, 1e-11), (2, 255, 0.9, 12, 106, 1e-11),
+    (2, 127, 0.7, 12, 107, 1e-12), (3, 31, 0.75, 6, 108, 1e-11),
 ]
 
 
 def _solve_all(B, server, reqs, sequential):
     outs, tickets = [], []
-    fs = [torch.from_numpy(synth.normal_rhs(n, d, nrhs=1, tag=t)[0]).cuda() for d, n, a, k, t in reqs]
+    fs = [torch.from_numpy(synth.normal_rhs(n, d, nrhs=1, tag=t)[0]).cuda() for d, n, a, k, t, _ in reqs]
     torch.cuda.synchronize()
-    for (d, n, a, k, t), f in zip(reqs, fs):
+    for (d, n, a, k, t, tol), f in zip(reqs, fs):
         u = torch.empty_like(f)
         outs.append(u)
-        tk = B.bura_server_submit(server, d, n, a, k, f, u, tol=1e-11, precision=B.BURA_MIXED)
+        tk = B.bura_server_submit(server, d, n, a, k, f, u, tol=tol, precision=B.BURA_MIXED)
         if sequential:
             code, _ = B.bura_server_wait(server, tk)
             assert code == B.BURA_OK
@@ -53,10 +53,11 @@ def test_server_alone_equals_mix_and_matches_oracle():
     st = B.bura_server_stats(s_mix)
     B.bura_server_destroy(s_mix)
     assert st["completed"] == len(REQS) and st["failed"] == 0
-    assert st["batches"] < len(REQS)          # same-key requests were batched
+    assert st["batches"] < len(REQS)          # same-grid requests were batched
+    assert st["plans_created"] == 4           # one plan per (dim, n, precision)
     for a, m in zip(alone, mix):
         assert np.array_equal(a, m)
-    for (d, n, al, k, t), f, u in zip(REQS, fs, mix):
+    for (d, n, al, k, t, tol), f, u in zip(REQS, fs, mix):
         if al == 0.9:
             continue   # no oracle coefficients at alpha = 0.9, k = 12 (Chebyshev-basis Remez fails there)
         b = oracle_coeffs(al, k)
@@ -66,9 +67,14 @@ def test_server_alone_equals_mix_and_matches_oracle():
 
 def test_server_budget_evicts_idle_plans():
     B = _B()
-    # room for one 127^2 plan (two rhs slots, about 8 MB) at a time
-    server = B.bura_server_create(12 << 20, 2, 2)
-    reqs = [(2, 127, 0.5, 5, 111), (2, 127, 0.25, 5, 112), (2, 127, 0.5, 5, 113)]
+    # room for the 127^2 plan (17 term slots x 2 rhs, plus 2 x 2 staging vectors)
+    # and 1 MiB more: the 63^2 plan (several MiB) cannot be resident beside it
+    h = B.bura_plan_create_slots(2, 127, 17, B.bura_opts_default(precision=B.BURA_MIXED, nrhs_max=2))
+    plan_bytes = B.bura_plan_info(h)[2]
+    B.bura_plan_destroy(h)
+    budget = plan_bytes + 2 * 2 * 127 * 127 * 8 + (1 << 20)
+    server = B.bura_server_create(budget, 2, 2)
+    reqs = [(2, 127, 0.5, 5, 111, 1e-10), (2, 63, 0.25, 5, 112, 1e-10), (2, 127, 0.5, 5, 113, 1e-10)]
     _solve_all(B, server, reqs, sequential=True)
     st = B.bura_server_stats(server)
     assert st["p50_latency_s"] > 0
@@ -76,7 +82,7 @@ def test_server_budget_evicts_idle_plans():
     st2 = B.bura_server_stats(server)
     B.bura_server_destroy(server)
     assert st["failed"] == 0 and st["plans_evicted"] >= 1
-    assert st["resident_bytes"] <= 12 << 20
+    assert st["resident_bytes"] <= budget
     assert st2["p50_latency_s"] == 0 and st2["completed"] == st["completed"]
 
 
