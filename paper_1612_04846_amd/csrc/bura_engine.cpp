@@ -109,9 +109,10 @@ struct bura_plan_s {
   std::vector<HostLevel> lev;
   int lc = -1;                 // first level solved in LDS; -1: no multigrid (Jacobi PCG)
   bool unfused = false;        // force the one-kernel-per-step V-cycle (BURA_UNFUSED=1)
-  // PCG vector updates folded into the fused kernels: x += alpha p deferred to the
-  // next stencil-product pass, r -= alpha q done by the fine down kernel into a
-  // second residual buffer (off with BURA_NO_FOLDXR=1)
+  // PCG vector updates folded into other passes: x += alpha p deferred to the
+  // next stencil-product pass, r -= alpha q done by the first fine-level
+  // pre-smoothing kernel (the fused down kernel in 2D, k_jacobi0_rup
+  // otherwise) into a second residual buffer (off with BURA_NO_FOLDXR=1)
   bool foldxr = false;
   size_t lds_bytes = 0;
   // launch-shape variant of the 2D stencil product and, per global level, of
@@ -657,7 +658,7 @@ void precondition(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, const int* a
   // nu1 + nu2 sweeps alternate between two buffers; the first sweep writes the
   // buffer that makes the last one land in xa (xa = z on the fine level).
   std::vector<T*> bcur(lc + 1), cur(lc + 1), spare(lc + 1);
-  bcur[0] = off(W.r, 0);
+  bcur[0] = ru ? ru->rnew : off(W.r, 0);
   for (int l = 1; l <= lc; ++l) bcur[l] = off(W.bl[l], l);
   for (int l = 0; l < lc; ++l) {
     const LevelDev<T> L = level_view<T>(P, l);
@@ -667,7 +668,14 @@ void precondition(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, const int* a
     T* out = odd ? xa : xb;
     T* other = odd ? xb : xa;
     const int scls = l == 0 ? BURA_K_SMOOTH_FINE : BURA_K_SMOOTH_COARSE;
-    {
+    if (l == 0 && ru) {
+      {
+        ProfScope ps(P, scls);
+        Launch<T>::jacobi_rup(dim, var, L, ru->rold, ru->q, ru->alpha, ru->rnew, out, shift, active, w_at(wpre, 0),
+                              partial, nsys, st, ps.ctr, ru->fin);
+      }
+      if (ru->after) ru->after();
+    } else {
       ProfScope ps(P, scls);
       Launch<T>::jacobi(dim, var, L, bcur[l], nullptr, out, shift, active, w_at(wpre, 0), true, nullptr, nsys, st,
                         ps.ctr);
@@ -763,7 +771,8 @@ int run_pcg(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, double tol, int ma
     return f;
   };
   const bool fx = P->foldxr;
-  const int nb_down = fx ? down_blocks(dim, P->n, P->tile_down[0]) : 0;
+  // blocks of the kernel that writes the |r_new|^2 partials
+  const int nb_down = !fx ? 0 : fused_ok(P) ? down_blocks(dim, P->n, P->tile_down[0]) : stencil_blocks(dim, P->n);
   auto body = [&](T* po, T* pn, T* ro, T* rn) {
     {
       ProfScope ps(P, BURA_K_SPMV);
@@ -1357,7 +1366,9 @@ int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_p
   choose_lds(P, mixed ? 4 : 8);
   {
     const char* ev = std::getenv("BURA_NO_FOLDXR");
-    P->foldxr = fused_ok(P) && !(ev && ev[0] == '1');
+    // needs a multigrid level with a pre-smoothing sweep (the fused down
+    // kernel in 2D, the first Jacobi sweep otherwise)
+    P->foldxr = P->lc > 0 && !(ev && ev[0] == '1');
   }
   if (P->opts.max_iter == 0) {
     // automatic cap: multigrid-PCG needs O(1) iterations per digit; Jacobi-PCG

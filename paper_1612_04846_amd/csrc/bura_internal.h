@@ -97,6 +97,11 @@ struct Launch {
   static void jacobi(int dim, bool var, const LevelDev<T>& L, const T* b, const T* xin, T* xout,
                      const T* shift, const int* active, T omega, bool zero_guess, double* partial,
                      int nsys, hipStream_t st, unsigned long long* ctr, Fin fin = Fin());
+  // zero-guess sweep with the PCG residual update: bout = bold - alpha q,
+  // xout = omega D^-1 bout, partial = |bout|^2 (see k_jacobi0_rup)
+  static void jacobi_rup(int dim, bool var, const LevelDev<T>& L, const T* bold, const T* q, const double* alpha,
+                         T* bout, T* xout, const T* shift, const int* active, T omega, double* partial, int nsys,
+                         hipStream_t st, unsigned long long* ctr, Fin fin = Fin());
   static void restrict_residual(int dim, bool var, const LevelDev<T>& Lf, const LevelDev<T>& Lc,
                                 const T* b, const T* x, T* bc, const T* shift, const int* active,
                                 int nsys, hipStream_t st, unsigned long long* ctr);

@@ -232,6 +232,40 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(LevelDev<T> L, const T* __res
   }
 }
 
+// The first pre-smoothing sweep of the fine level (from x = 0) with the PCG
+// residual update folded in: b = b_old - alpha q is written to bout with its
+// squared norm into partial, and x_out = omega D^-1 b.  The sweep reads no
+// neighbour of b, so the update needs no second pass.
+template <typename T, int DIM, bool VAR>
+__global__ __launch_bounds__(kBlock) void k_jacobi0_rup(LevelDev<T> L, const T* __restrict__ bold,
+                                                        const T* __restrict__ q, const double* __restrict__ alpha,
+                                                        T* __restrict__ bout, T* __restrict__ xout,
+                                                        const T* __restrict__ shift, const int* __restrict__ active,
+                                                        T omega, double* __restrict__ partial,
+                                                        unsigned long long* __restrict__ ctr, Fin fin) {
+  const Tile tl = block_tile();
+  const int sys = tl.z;
+  if (!active[sys]) return;
+  int i, j, k;
+  tile_ijk<DIM>(tl, L.n, i, j, k);
+  const bool ok = i < L.n && j < L.n;
+  const long long off = (long long)sys * L.N;
+  const long long p = ((long long)k * L.n + j) * L.n + i;
+  const T s = shift[sys];
+  const T a = (T)alpha[sys];
+  // b_old and q read, b and x_out written; faces once per launch
+  count_bytes_tile(tl, ctr, (unsigned long long)L.N * sizeof(T) * (4 + (VAR && sys == 0 ? DIM : 0)));
+  double rr = 0.0;
+  if (ok) {
+    const T bv = bold[off + p] - a * q[off + p];
+    bout[off + p] = bv;
+    xout[off + p] = omega * bv / diag_pt<T, DIM, VAR>(L, i, j, k, s);
+    rr = (double)bv * (double)bv;
+  }
+  write_partial_tile(tl, partial, sys, rr);
+  finish(fin, partial, sys, gridDim.x * gridDim.y);
+}
+
 // --------------------------------------------------------------------------
 // b_c = R (b - (A+s) x): full weighting of the fine residual (weights
 // (1/4, 1/2, 1/4) per axis), fine node 2I+1 under coarse node I (0-based).
@@ -1339,6 +1373,18 @@ void Launch<T>::jacobi(int dim, bool var, const LevelDev<T>& L, const T* b, cons
   BURA_DISPATCH_DV(dim, var, K_JAC4, 0);
 #undef K_JAC4
 #undef K_JAC
+}
+
+template <typename T>
+void Launch<T>::jacobi_rup(int dim, bool var, const LevelDev<T>& L, const T* bold, const T* q, const double* alpha,
+                           T* bout, T* xout, const T* shift, const int* active, T omega, double* partial, int nsys,
+                           hipStream_t st, unsigned long long* ctr, Fin fin) {
+  const dim3 g = stencil_grid(dim, L.n, nsys), blk(kTileX, kTileY);
+#define K_JR(D, V, dummy)                                                                                         \
+  hipLaunchKernelGGL((k_jacobi0_rup<T, D, V>), g, blk, 0, st, L, bold, q, alpha, bout, xout, shift, active, omega, \
+                     partial, ctr, fin)
+  BURA_DISPATCH_DV(dim, var, K_JR, 0);
+#undef K_JR
 }
 
 template <typename T>

@@ -261,22 +261,31 @@ def test_folded_scalars_match_separate_launches(monkeypatch):
     assert np.array_equal(u_eager, u_sep)
 
 
-@pytest.mark.parametrize("prec", ["FP64", "MIXED"])
-def test_folded_vector_updates_match_separate_pass(monkeypatch, prec):
+FOLD_CASES = [  # dim, n, precision, one kernel per V-cycle step (BURA_UNFUSED=1)
+    (2, 255, "FP64", False), (2, 255, "MIXED", False),
+    (3, 63, "FP64", False), (3, 63, "MIXED", False), (2, 127, "MIXED", True),
+]
+
+
+@pytest.mark.parametrize("dim,n,prec,unfused", FOLD_CASES)
+def test_folded_vector_updates_match_separate_pass(monkeypatch, dim, n, prec, unfused):
     """x += alpha p deferred into the stencil-product pass and r -= alpha q done by the
-    fine down kernel give the same result as the separate update pass; both match
-    the oracle.  Ragged 255^2 tiles, several systems converging at different
+    first fine pre-smoothing kernel (fused down kernel in 2D, the zero-guess Jacobi
+    sweep in 3D or unfused) give the same result as the separate update pass; both
+    match the oracle.  Ragged tiles, several systems converging at different
     iterations (so the last deferred update lands in both p buffers)."""
     from oracle import spectral
     B = _B()
-    n, alpha, k = 255, 0.75, 9
-    F = synth.normal_rhs(n, 2, nrhs=2, tag=93)
+    alpha, k = 0.75, 9
+    if unfused:
+        monkeypatch.setenv("BURA_UNFUSED", "1")
+    F = synth.normal_rhs(n, dim, nrhs=2, tag=93)
     pr = getattr(B, "BURA_" + prec)
-    u_fold = _host(B.Plan(2, n, alpha, k, precision=pr, nrhs_max=2, tol=1e-11).solve(_dev(F)).u)
+    u_fold = _host(B.Plan(dim, n, alpha, k, precision=pr, nrhs_max=2, tol=1e-11).solve(_dev(F)).u)
     monkeypatch.setenv("BURA_NO_FOLDXR", "1")
-    u_sep = _host(B.Plan(2, n, alpha, k, precision=pr, nrhs_max=2, tol=1e-11).solve(_dev(F)).u)
+    u_sep = _host(B.Plan(dim, n, alpha, k, precision=pr, nrhs_max=2, tol=1e-11).solve(_dev(F)).u)
     b = oracle_bura(alpha, k)
-    ref = spectral.bura_spectral(F, 2, b.c_f64, b.d_f64)
+    ref = spectral.bura_spectral(F, dim, b.c_f64, b.d_f64)
     d = np.linalg.norm((u_fold - u_sep).reshape(2, -1), axis=1) / np.linalg.norm(ref.reshape(2, -1), axis=1)
     assert np.max(d) <= 1e-12
     for u in (u_fold, u_sep):
