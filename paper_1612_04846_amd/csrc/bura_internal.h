@@ -110,8 +110,6 @@ struct Launch {
   static void coarse_solve(int dim, bool var, const LdsHierarchy<T>& H, const T* b, T* x,
                            const T* shift, const int* active, int nsys, size_t lds_bytes, hipStream_t st,
                            unsigned long long* ctr);
-  static void spmv_dot(int dim, bool var, const LevelDev<T>& L, const T* p, T* q, const T* shift,
-                       const int* active, double* partial, int nsys, hipStream_t st, unsigned long long* ctr);
   static void update_xr(const LevelDev<T>& L, int dim, T* x, T* r, const T* p, const T* q,
                         const double* alpha, const int* active, double* partial, int nsys, hipStream_t st,
                         unsigned long long* ctr, Fin fin = Fin());

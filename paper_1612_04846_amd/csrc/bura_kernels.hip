@@ -56,6 +56,29 @@ __device__ __forceinline__ void tile_ijk(const Tile& tl, int n, int& i, int& j, 
   j = by * kTileY + threadIdx.y;
 }
 
+// 3D launches that march along z (the stencil product, the smoothing sweeps
+// and the FP64 residual): a workgroup of kTileX x kTileY threads owns that
+// block of columns over kMarchZ consecutive planes, and each thread carries
+// its column's values at planes k-1, k, k+1 in registers from one plane to the
+// next, so the points above and below are not loaded again (a
+// one-point-per-thread launch reads them from the last-level caches).
+constexpr int kMarchZ = 16;
+
+struct Column {
+  int i, j, k0, k1;   // the thread's column and its planes [k0, k1)
+};
+
+__device__ __forceinline__ Column march_column(const Tile& tl, int n) {
+  Column c;
+  const int yt = (n + kTileY - 1) / kTileY;
+  const int kc = tl.y / yt;
+  c.i = tl.x * kTileX + threadIdx.x;
+  c.j = (tl.y - kc * yt) * kTileY + threadIdx.y;
+  c.k0 = kc * kMarchZ;
+  c.k1 = min(c.k0 + kMarchZ, n);
+  return c;
+}
+
 // FP64 block sum; the result is valid in thread 0 only.  Fixed order.
 __device__ __forceinline__ double block_sum(double v) {
   __shared__ double sh[kBlock / 64];
@@ -191,6 +214,46 @@ __device__ __forceinline__ T diag_pt(const LevelDev<T>& L, int i, int j, int k, 
   return d + s;
 }
 
+// apply_pt for DIM = 3 from values already loaded: the centre, its in-plane
+// neighbours l, r, d, u and the points below (b) and above (f), each 0 outside
+// the grid.  Same arithmetic and order as apply_pt.
+template <typename T, bool VAR>
+__device__ __forceinline__ T apply_col3(const LevelDev<T>& L, int i, int j, int k, long long p, T xc, T xl, T xr,
+                                        T xd, T xu, T xb, T xf, T s, T* dg) {
+  if (!VAR) {
+    T sum = (xc - xl) + (xc - xr) + (xc - xd) + (xc - xu);
+    sum += (xc - xb) + (xc - xf);
+    if (dg) *dg = L.wc * T(6) + s;
+    return L.wc * sum + s * xc;
+  }
+  const int n = L.n;
+  const long long fx = ((long long)k * n + j) * (n + 1) + i;
+  const long long fy = ((long long)k * (n + 1) + j) * n + i;
+  const T wl = L.wf0[fx], wr = L.wf0[fx + 1], wd = L.wf1[fy], wu = L.wf1[fy + n];
+  const T wb = L.wf2[p], wf = L.wf2[p + (long long)n * n];
+  T acc = wl * (xc - xl) + wr * (xc - xr) + wd * (xc - xd) + wu * (xc - xu);
+  T d = wl + wr + wd + wu;
+  acc += wb * (xc - xb) + wf * (xc - xf);
+  d += wb + wf;
+  if (dg) *dg = d + s;
+  return acc + s * xc;
+}
+
+// In-plane neighbour offsets of a column (0 where the neighbour is outside the
+// grid: the load then reads the centre and the value is replaced by 0).
+struct PlaneNb {
+  int l, r, d, u;
+};
+
+__device__ __forceinline__ PlaneNb plane_nb(int i, int j, int n) {
+  PlaneNb o;
+  o.l = i > 0 ? -1 : 0;
+  o.r = i < n - 1 ? 1 : 0;
+  o.d = j > 0 ? -n : 0;
+  o.u = j < n - 1 ? n : 0;
+  return o;
+}
+
 // --------------------------------------------------------------------------
 // smoother: x_out = x_in + omega D^-1 (b - (A+s) x_in)   (x_in = 0 if ZERO)
 // DOT: partial = b . x_out  (r.z when this is the last sweep of z = M r)
@@ -232,6 +295,64 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(LevelDev<T> L, const T* __res
   }
 }
 
+// k_jacobi in 3D, marching along z (one workgroup per kMarchZ planes).
+template <typename T, bool VAR, bool ZERO, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_jacobi3(LevelDev<T> L, const T* __restrict__ b,
+                                                    const T* __restrict__ xin, T* __restrict__ xout,
+                                                    const T* __restrict__ shift, const int* __restrict__ active,
+                                                    T omega, double* __restrict__ partial,
+                                                    unsigned long long* __restrict__ ctr, Fin fin) {
+  const Tile tl = block_tile();
+  const int sys = tl.z;
+  if (!active[sys]) return;
+  count_bytes_tile(tl, ctr, (unsigned long long)L.N * sizeof(T) * ((ZERO ? 2 : 3) + (VAR && sys == 0 ? 3 : 0)));
+  const int n = L.n;
+  const Column c = march_column(tl, n);
+  double dot = 0.0;
+  if (c.i < n && c.j < n) {
+    const long long off = (long long)sys * L.N, nn = (long long)n * n;
+    const long long col = (long long)c.j * n + c.i;
+    const T s = shift[sys];
+    const T* bs = b + off;
+    T* xo = xout + off;
+    if (ZERO) {
+      for (int k = c.k0; k < c.k1; ++k) {
+        const long long p = k * nn + col;
+        const T bv = bs[p];
+        const T xn = omega * bv / diag_pt<T, 3, VAR>(L, c.i, c.j, k, s);
+        xo[p] = xn;
+        if (DOT) dot += (double)bv * (double)xn;
+      }
+    } else {
+      const T* xs = xin + off;
+      const PlaneNb o = plane_nb(c.i, c.j, n);
+      const long long p0 = c.k0 * nn + col;
+      const T xb0 = xs[c.k0 > 0 ? p0 - nn : p0];
+      T below = c.k0 > 0 ? xb0 : T(0);
+      T centre = xs[p0];
+      for (int k = c.k0; k < c.k1; ++k) {
+        const long long p = k * nn + col;
+        const T xa = xs[k + 1 < n ? p + nn : p];
+        const T xl = xs[p + o.l], xr = xs[p + o.r], xd = xs[p + o.d], xu = xs[p + o.u];
+        const T bv = bs[p];
+        const T above = k + 1 < n ? xa : T(0);
+        T dg;
+        const T ax = apply_col3<T, VAR>(L, c.i, c.j, k, p, centre, o.l ? xl : T(0), o.r ? xr : T(0),
+                                        o.d ? xd : T(0), o.u ? xu : T(0), below, above, s, &dg);
+        const T xn = centre + omega * (bv - ax) / dg;
+        xo[p] = xn;
+        if (DOT) dot += (double)bv * (double)xn;
+        below = centre;
+        centre = above;
+      }
+    }
+  }
+  if (DOT) {
+    write_partial_tile(tl, partial, sys, dot);
+    finish(fin, partial, sys, gridDim.x * gridDim.y);
+  }
+}
+
 // The first pre-smoothing sweep of the fine level (from x = 0) with the PCG
 // residual update folded in: b = b_old - alpha q is written to bout with its
 // squared norm into partial, and x_out = omega D^-1 b.  The sweep reads no
@@ -246,21 +367,32 @@ __global__ __launch_bounds__(kBlock) void k_jacobi0_rup(LevelDev<T> L, const T* 
   const Tile tl = block_tile();
   const int sys = tl.z;
   if (!active[sys]) return;
-  int i, j, k;
-  tile_ijk<DIM>(tl, L.n, i, j, k);
-  const bool ok = i < L.n && j < L.n;
+  const int n = L.n;
+  int i, j, k0, k1;   // 2D: one point; 3D: a column over kMarchZ planes
+  if (DIM == 3) {
+    const Column c = march_column(tl, n);
+    i = c.i;
+    j = c.j;
+    k0 = c.k0;
+    k1 = c.k1;
+  } else {
+    tile_ijk<DIM>(tl, n, i, j, k0);
+    k1 = k0 + 1;
+  }
   const long long off = (long long)sys * L.N;
-  const long long p = ((long long)k * L.n + j) * L.n + i;
   const T s = shift[sys];
   const T a = (T)alpha[sys];
   // b_old and q read, b and x_out written; faces once per launch
   count_bytes_tile(tl, ctr, (unsigned long long)L.N * sizeof(T) * (4 + (VAR && sys == 0 ? DIM : 0)));
   double rr = 0.0;
-  if (ok) {
-    const T bv = bold[off + p] - a * q[off + p];
-    bout[off + p] = bv;
-    xout[off + p] = omega * bv / diag_pt<T, DIM, VAR>(L, i, j, k, s);
-    rr = (double)bv * (double)bv;
+  if (i < n && j < n) {
+    for (int k = k0; k < k1; ++k) {
+      const long long p = ((long long)k * n + j) * n + i;
+      const T bv = bold[off + p] - a * q[off + p];
+      bout[off + p] = bv;
+      xout[off + p] = omega * bv / diag_pt<T, DIM, VAR>(L, i, j, k, s);
+      rr += (double)bv * (double)bv;
+    }
   }
   write_partial_tile(tl, partial, sys, rr);
   finish(fin, partial, sys, gridDim.x * gridDim.y);
@@ -788,76 +920,65 @@ __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, con
 // XUP: also x += alpha_prev p_old, the iterate update of the previous PCG
 // iteration, deferred to this pass which reads p_old anyway.  alpha == 0 marks
 // "nothing pending" (first iteration); p_old is then not used.
-template <typename T, int DIM, bool VAR, bool XUP>
-__global__ __launch_bounds__(kBlock) void k_spmv_p(LevelDev<T> L, const T* __restrict__ z, const T* __restrict__ pold,
-                                                   T* __restrict__ pnew, T* __restrict__ q,
-                                                   const double* __restrict__ beta, const T* __restrict__ shift,
-                                                   const int* __restrict__ active, double* __restrict__ partial,
-                                                   unsigned long long* __restrict__ ctr, Fin fin,
-                                                   T* __restrict__ x, const double* __restrict__ alpha) {
+//
+// 3D version, marching along z: p_new = z + beta p_old is formed once per
+// point; the column's values below and at the point stay in registers.
+template <typename T, bool VAR, bool XUP>
+__global__ __launch_bounds__(kBlock) void k_spmv_p3(LevelDev<T> L, const T* __restrict__ z, const T* __restrict__ pold,
+                                                    T* __restrict__ pnew, T* __restrict__ q,
+                                                    const double* __restrict__ beta, const T* __restrict__ shift,
+                                                    const int* __restrict__ active, double* __restrict__ partial,
+                                                    unsigned long long* __restrict__ ctr, Fin fin,
+                                                    T* __restrict__ x, const double* __restrict__ alpha) {
   const Tile tl = block_tile();
   const int sys = tl.z;
   if (!active[sys]) return;
   const T bt = (T)beta[sys];
   const T ap = XUP ? (T)alpha[sys] : T(0);
   count_bytes_tile(tl, ctr, (unsigned long long)L.N * sizeof(T) *
-                                   ((bt == T(0) ? 3 : 4) + (XUP && ap != T(0) ? 2 : 0) + (VAR && sys == 0 ? DIM : 0)));
-  int i, j, k;
-  tile_ijk<DIM>(tl, L.n, i, j, k);
-  const bool ok = i < L.n && j < L.n;
-  const long long off = (long long)sys * L.N;
-  const long long p = ((long long)k * L.n + j) * L.n + i;
+                                ((bt == T(0) ? 3 : 4) + (XUP && ap != T(0) ? 2 : 0) + (VAR && sys == 0 ? 3 : 0)));
+  const int n = L.n;
+  const Column c = march_column(tl, n);
   double dot = 0.0;
-  if (ok) {
-    const int n = L.n;
+  if (c.i < n && c.j < n) {
+    const long long off = (long long)sys * L.N, nn = (long long)n * n;
+    const long long col = (long long)c.j * n + c.i;
     const T* zs = z + off;
-    const T* ps = pold + off;
-    // unconditional loads (a boundary neighbour reads the centre), selected after
     // beta = 0 (first iteration): p_old may hold anything, so read z in its place
-    const T* pe = bt == T(0) ? zs : ps;
-    auto P = [&](long long idx) -> T { return zs[idx] + bt * pe[idx]; };
-    const long long nn = (long long)n * n;
-    T xv = T(0), pov = T(0);
-    if (XUP) {
-      xv = x[off + p];
-      pov = ps[p];
-    }
-    const T pc = P(p);
-    const T pl0 = P(i > 0 ? p - 1 : p), pr0 = P(i < n - 1 ? p + 1 : p);
-    const T pd0 = P(j > 0 ? p - n : p), pu0 = P(j < n - 1 ? p + n : p);
-    T pb0 = T(0), pf0 = T(0);
-    if (DIM == 3) {
-      pb0 = P(k > 0 ? p - nn : p);
-      pf0 = P(k < n - 1 ? p + nn : p);
-    }
-    const T pl = i > 0 ? pl0 : T(0), pr = i < n - 1 ? pr0 : T(0);
-    const T pd = j > 0 ? pd0 : T(0), pu = j < n - 1 ? pu0 : T(0);
-    const T pb = DIM == 3 && k > 0 ? pb0 : T(0), pf = DIM == 3 && k < n - 1 ? pf0 : T(0);
+    const T* pe = bt == T(0) ? zs : pold + off;
     const T s = shift[sys];
-    T qv;
-    if (!VAR) {
-      T sum = (pc - pl) + (pc - pr) + (pc - pd) + (pc - pu);
-      if (DIM == 3) sum += (pc - pb) + (pc - pf);
-      qv = L.wc * sum + s * pc;
-    } else {
-      const long long fx = ((long long)k * n + j) * (n + 1) + i;
-      const long long fy = ((long long)k * (n + 1) + j) * n + i;
-      qv = L.wf0[fx] * (pc - pl) + L.wf0[fx + 1] * (pc - pr) + L.wf1[fy] * (pc - pd) + L.wf1[fy + n] * (pc - pu);
-      if (DIM == 3) {
-        const long long fz = ((long long)k * n + j) * n + i;
-        qv += L.wf2[fz] * (pc - pb) + L.wf2[fz + nn] * (pc - pf);
-      }
-      qv += s * pc;
+    const PlaneNb o = plane_nb(c.i, c.j, n);
+    const long long p0 = c.k0 * nn + col;
+    const long long pb = c.k0 > 0 ? p0 - nn : p0;
+    const T zb = zs[pb], eb = pe[pb], zc = zs[p0], ec = pe[p0];
+    T below = c.k0 > 0 ? zb + bt * eb : T(0);
+    T centre = zc + bt * ec;
+    T pold_c = ec;   // p_old at the point (used by the deferred update, alpha != 0 => beta != 0)
+    for (int k = c.k0; k < c.k1; ++k) {
+      const long long p = k * nn + col;
+      const long long pa = k + 1 < n ? p + nn : p;
+      // every load of the plane first, then the arithmetic
+      const T za = zs[pa], ea = pe[pa];
+      const T zl = zs[p + o.l], el = pe[p + o.l], zr = zs[p + o.r], er = pe[p + o.r];
+      const T zd = zs[p + o.d], ed = pe[p + o.d], zu = zs[p + o.u], eu = pe[p + o.u];
+      T xv = T(0);
+      if (XUP) xv = x[off + p];
+      const T above = k + 1 < n ? za + bt * ea : T(0);
+      const T lv = o.l ? zl + bt * el : T(0), rv = o.r ? zr + bt * er : T(0);
+      const T dv = o.d ? zd + bt * ed : T(0), uv = o.u ? zu + bt * eu : T(0);
+      const T qv = apply_col3<T, VAR>(L, c.i, c.j, k, p, centre, lv, rv, dv, uv, below, above, s, nullptr);
+      pnew[off + p] = centre;
+      q[off + p] = qv;
+      if (XUP && ap != T(0)) x[off + p] = xv + ap * pold_c;
+      dot += (double)centre * (double)qv;
+      below = centre;
+      centre = above;
+      pold_c = ea;
     }
-    pnew[off + p] = pc;
-    q[off + p] = qv;
-    if (XUP && ap != T(0)) x[off + p] = xv + ap * pov;
-    dot = (double)pc * (double)qv;
   }
   write_partial_tile(tl, partial, sys, dot);
   finish(fin, partial, sys, gridDim.x * gridDim.y);
 }
-
 
 // 2D version: each thread owns R consecutive rows of one column (a workgroup
 // covers kTileX x kTileY*R points), so the column's p_new values are formed
@@ -942,28 +1063,6 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p2(LevelDev<T> L, const T* __re
 }
 
 // --------------------------------------------------------------------------
-template <typename T, int DIM, bool VAR>
-__global__ __launch_bounds__(kBlock) void k_spmv_dot(LevelDev<T> L, const T* __restrict__ pv, T* __restrict__ q,
-                                                     const T* __restrict__ shift, const int* __restrict__ active,
-                                                     double* __restrict__ partial, unsigned long long* __restrict__ ctr) {
-  const Tile tl = block_tile();
-  const int sys = tl.z;
-  if (!active[sys]) return;
-  count_bytes_tile(tl, ctr, (unsigned long long)L.N * sizeof(T) * (2 + (VAR && sys == 0 ? DIM : 0)));
-  int i, j, k;
-  tile_ijk<DIM>(tl, L.n, i, j, k);
-  const bool ok = i < L.n && j < L.n;
-  const long long off = (long long)sys * L.N;
-  const long long p = ((long long)k * L.n + j) * L.n + i;
-  double dot = 0.0;
-  if (ok) {
-    const T qv = apply_pt<T, DIM, VAR>(L, pv + off, i, j, k, p, shift[sys], nullptr);
-    q[off + p] = qv;
-    dot = (double)pv[off + p] * (double)qv;
-  }
-  write_partial_tile(tl, partial, sys, dot);
-}
-
 constexpr int kFlatItems = 4;
 
 template <typename T>
@@ -1103,6 +1202,51 @@ __global__ __launch_bounds__(kBlock) void k_residual64(LevelDev<double> L, const
     r32[off + p] = (float)rv;
     e[off + p] = 0.0f;
     rr = rv * rv;
+  }
+  write_partial_tile(tl, partial, sys, rr);
+}
+
+// k_residual64 in 3D, marching along z
+template <bool VAR>
+__global__ __launch_bounds__(kBlock) void k_residual64_3(LevelDev<double> L, const double* __restrict__ f,
+                                                         const double* __restrict__ x64, float* __restrict__ e,
+                                                         float* __restrict__ r32, const double* __restrict__ shift,
+                                                         const int* __restrict__ active64, int nrhs,
+                                                         double* __restrict__ partial,
+                                                         unsigned long long* __restrict__ ctr) {
+  const Tile tl = block_tile();
+  const int sys = tl.z;
+  if (!active64[sys]) return;
+  count_bytes_tile(tl, ctr, (unsigned long long)L.N * (8 + 8 + 4 + 4 + (VAR && sys == 0 ? 8 * 3 : 0)));
+  const int n = L.n;
+  const Column c = march_column(tl, n);
+  double rr = 0.0;
+  if (c.i < n && c.j < n) {
+    const long long off = (long long)sys * L.N, nn = (long long)n * n;
+    const long long col = (long long)c.j * n + c.i;
+    const double* xs = x64 + off;
+    const double* fs = f + (long long)(sys % nrhs) * L.N;
+    const double s = shift[sys];
+    const PlaneNb o = plane_nb(c.i, c.j, n);
+    const long long p0 = c.k0 * nn + col;
+    const double xb0 = xs[c.k0 > 0 ? p0 - nn : p0];
+    double below = c.k0 > 0 ? xb0 : 0.0;
+    double centre = xs[p0];
+    for (int k = c.k0; k < c.k1; ++k) {
+      const long long p = k * nn + col;
+      const double xa = xs[k + 1 < n ? p + nn : p];
+      const double xl = xs[p + o.l], xr = xs[p + o.r], xd = xs[p + o.d], xu = xs[p + o.u];
+      const double fv = fs[p];
+      const double above = k + 1 < n ? xa : 0.0;
+      const double ax = apply_col3<double, VAR>(L, c.i, c.j, k, p, centre, o.l ? xl : 0.0, o.r ? xr : 0.0,
+                                                o.d ? xd : 0.0, o.u ? xu : 0.0, below, above, s, nullptr);
+      const double rv = fv - ax;
+      r32[off + p] = (float)rv;
+      e[off + p] = 0.0f;
+      rr += rv * rv;
+      below = centre;
+      centre = above;
+    }
   }
   write_partial_tile(tl, partial, sys, rr);
 }
@@ -1298,10 +1442,25 @@ __global__ __launch_bounds__(256) void k_scalars(int op, const double* __restric
 // --------------------------------------------------------------------------
 // launchers
 // --------------------------------------------------------------------------
-static inline dim3 stencil_grid(int dim, int n, int nsys) {
+// one point per thread (2D stencil kernels; 3D transfer operators)
+static inline dim3 point_grid(int dim, int n, int nsys) {
   const int xt = (n + kTileX - 1) / kTileX;
   const int yt = (n + kTileY - 1) / kTileY;
   return dim3(xt, yt * (dim == 3 ? n : 1), nsys);
+}
+
+// 3D kernels marching along z: kMarchZ planes per workgroup
+static inline dim3 march_grid(int n, int nsys) {
+  const int xt = (n + kTileX - 1) / kTileX;
+  const int yt = (n + kTileY - 1) / kTileY;
+  const int zt = (n + kMarchZ - 1) / kMarchZ;
+  return dim3(xt, yt * zt, nsys);
+}
+
+// the smoothing sweeps, the stencil product and the FP64 residual (the kernels
+// that write per-block partials outside the fused 2D path)
+static inline dim3 stencil_grid(int dim, int n, int nsys) {
+  return dim == 3 ? march_grid(n, nsys) : point_grid(dim, n, nsys);
 }
 
 int stencil_blocks(int dim, int n) {
@@ -1359,7 +1518,15 @@ void Launch<T>::jacobi(int dim, bool var, const LevelDev<T>& L, const T* b, cons
                        unsigned long long* ctr, Fin fin) {
   const dim3 g = stencil_grid(dim, L.n, nsys), blk(kTileX, kTileY);
   const bool dot = partial != nullptr;
-#define K_JAC(D, V, Z, DT) hipLaunchKernelGGL((k_jacobi<T, D, V, Z, DT>), g, blk, 0, st, L, b, xin, xout, shift, active, omega, partial, ctr, fin)
+#define K_JAC(D, V, Z, DT)                                                                                      \
+  do {                                                                                                          \
+    if (D == 3)                                                                                                 \
+      hipLaunchKernelGGL((k_jacobi3<T, V, Z, DT>), g, blk, 0, st, L, b, xin, xout, shift, active, omega, partial, \
+                         ctr, fin);                                                                             \
+    else                                                                                                        \
+      hipLaunchKernelGGL((k_jacobi<T, 2, V, Z, DT>), g, blk, 0, st, L, b, xin, xout, shift, active, omega,       \
+                         partial, ctr, fin);                                                                    \
+  } while (0)
 #define K_JAC4(D, V, dummy)                       \
   do {                                            \
     if (zero_guess) {                             \
@@ -1391,7 +1558,7 @@ template <typename T>
 void Launch<T>::restrict_residual(int dim, bool var, const LevelDev<T>& Lf, const LevelDev<T>& Lc, const T* b,
                                   const T* x, T* bc, const T* shift, const int* active, int nsys, hipStream_t st,
                                   unsigned long long* ctr) {
-  const dim3 g = stencil_grid(dim, Lc.n, nsys), blk(kTileX, kTileY);
+  const dim3 g = point_grid(dim, Lc.n, nsys), blk(kTileX, kTileY);
 #define K_RES(D, V, dummy) hipLaunchKernelGGL((k_restrict<T, D, V>), g, blk, 0, st, Lf, Lc, b, x, bc, shift, active, ctr)
   BURA_DISPATCH_DV(dim, var, K_RES, 0);
 #undef K_RES
@@ -1400,7 +1567,7 @@ void Launch<T>::restrict_residual(int dim, bool var, const LevelDev<T>& Lf, cons
 template <typename T>
 void Launch<T>::prolong_add(int dim, const LevelDev<T>& Lc, const LevelDev<T>& Lf, const T* xc, T* xf,
                             const int* active, int nsys, hipStream_t st, unsigned long long* ctr) {
-  const dim3 g = stencil_grid(dim, Lf.n, nsys), blk(kTileX, kTileY);
+  const dim3 g = point_grid(dim, Lf.n, nsys), blk(kTileX, kTileY);
   if (dim == 2) hipLaunchKernelGGL((k_prolong<T, 2>), g, blk, 0, st, Lc, Lf, xc, xf, active, ctr);
   else hipLaunchKernelGGL((k_prolong<T, 3>), g, blk, 0, st, Lc, Lf, xc, xf, active, ctr);
 }
@@ -1413,15 +1580,6 @@ void Launch<T>::coarse_solve(int dim, bool var, const LdsHierarchy<T>& H, const 
 #define K_CO(D, V, dummy) hipLaunchKernelGGL((k_coarse<T, D, V>), g, blk, lds_bytes, st, H, b, x, shift, active, ctr)
   BURA_DISPATCH_DV(dim, var, K_CO, 0);
 #undef K_CO
-}
-
-template <typename T>
-void Launch<T>::spmv_dot(int dim, bool var, const LevelDev<T>& L, const T* p, T* q, const T* shift,
-                         const int* active, double* partial, int nsys, hipStream_t st, unsigned long long* ctr) {
-  const dim3 g = stencil_grid(dim, L.n, nsys), blk(kTileX, kTileY);
-#define K_SP(D, V, dummy) hipLaunchKernelGGL((k_spmv_dot<T, D, V>), g, blk, 0, st, L, p, q, shift, active, partial, ctr)
-  BURA_DISPATCH_DV(dim, var, K_SP, 0);
-#undef K_SP
 }
 
 template <typename T>
@@ -1469,18 +1627,16 @@ void Launch<T>::spmv_p(int dim, bool var, const LevelDev<T>& L, const T* z, cons
     });
     return;
   }
-  const dim3 g = stencil_grid(dim, L.n, nsys), blk(kTileX, kTileY);
-#define K_SPP(D, V, dummy)                                                                                          \
-  do {                                                                                                              \
-    if (xup)                                                                                                        \
-      hipLaunchKernelGGL((k_spmv_p<T, D, V, true>), g, blk, 0, st, L, z, pold, pnew, q, beta, shift, active,      \
-                         partial, ctr, fin, x, alpha);                                                              \
-    else                                                                                                            \
-      hipLaunchKernelGGL((k_spmv_p<T, D, V, false>), g, blk, 0, st, L, z, pold, pnew, q, beta, shift, active,     \
-                         partial, ctr, fin, x, alpha);                                                              \
-  } while (0)
-  BURA_DISPATCH_DV(dim, var, K_SPP, 0);
-#undef K_SPP
+  const dim3 g = march_grid(L.n, nsys), blk(kTileX, kTileY);
+#define K_SP3(V, X_)                                                                                              \
+  hipLaunchKernelGGL((k_spmv_p3<T, V, X_>), g, blk, 0, st, L, z, pold, pnew, q, beta, shift, active, partial, ctr, \
+                     fin, x, alpha)
+  if (var) {
+    if (xup) K_SP3(true, true); else K_SP3(true, false);
+  } else {
+    if (xup) K_SP3(false, true); else K_SP3(false, false);
+  }
+#undef K_SP3
 }
 
 template <typename T>
@@ -1571,10 +1727,18 @@ void launch_residual64(int dim, bool var, const LevelDev<double>& L, const doubl
     return;
   }
   const dim3 g = stencil_grid(dim, L.n, nsys), blk(kTileX, kTileY);
-#define K_R64(D, V, dummy) \
-  hipLaunchKernelGGL((k_residual64<D, V>), g, blk, 0, st, L, f, x64, e, r32, shift, active64, nrhs, partial, ctr)
-  BURA_DISPATCH_DV(dim, var, K_R64, 0);
-#undef K_R64
+  if (dim == 3) {
+    if (var)
+      hipLaunchKernelGGL((k_residual64_3<true>), g, blk, 0, st, L, f, x64, e, r32, shift, active64, nrhs, partial, ctr);
+    else
+      hipLaunchKernelGGL((k_residual64_3<false>), g, blk, 0, st, L, f, x64, e, r32, shift, active64, nrhs, partial,
+                         ctr);
+  } else if (var) {
+    hipLaunchKernelGGL((k_residual64<2, true>), g, blk, 0, st, L, f, x64, e, r32, shift, active64, nrhs, partial, ctr);
+  } else {
+    hipLaunchKernelGGL((k_residual64<2, false>), g, blk, 0, st, L, f, x64, e, r32, shift, active64, nrhs, partial,
+                       ctr);
+  }
 }
 
 void launch_x_from_e(const LevelDev<double>& L, int dim, const float* e, double* x64, const int* active64, int nsys,
@@ -1592,7 +1756,7 @@ void launch_combine(long long N, const double* x, const double* w, int nterms, i
 
 void launch_apply64(int dim, bool var, const LevelDev<double>& L, const double* x, double* y, double shift, int nvec,
                     hipStream_t st) {
-  const dim3 g = stencil_grid(dim, L.n, nvec), blk(kTileX, kTileY);
+  const dim3 g = point_grid(dim, L.n, nvec), blk(kTileX, kTileY);
 #define K_AP(D, V, dummy) hipLaunchKernelGGL((k_apply64<D, V>), g, blk, 0, st, L, x, y, shift)
   BURA_DISPATCH_DV(dim, var, K_AP, 0);
 #undef K_AP
