@@ -106,6 +106,7 @@ def make_rhs(w):
 
 
 PLAN_OPTS = {}   # plan options from --omega / --nu / --inner-tol / --autotune (empty: the library defaults)
+FORCED_TILES = None   # --tiles: tile-shape variants set on each plan of the main workload
 
 
 def run_gpu(w, steps, warmup, profile=True):
@@ -135,6 +136,9 @@ def run_gpu(w, steps, warmup, profile=True):
             kw["beta"] = 2
         plans.append(B.Plan(w["dim"], w["n"], a, w["k"], **kw))
     t_plan = time.perf_counter() - t_plan
+    if FORCED_TILES is not None:
+        for p, tv in zip(plans, FORCED_TILES):
+            p.tiles = tv
     tiles = [p.tiles for p in plans]
     outs = [torch.empty((p.nout,) + tuple(F.shape), dtype=F.dtype, device=dev) if p.nout > 1 else torch.empty_like(F)
             for p in plans]
@@ -217,9 +221,9 @@ def roofline(kstats):
     return roof, table
 
 
-def counter_traffic(workload, kclass):
+def counter_traffic(workload, kclass, tiles):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it was
-    taken on the current kernel source (else None)."""
+    taken on the current kernel source with the same tile shapes (else None)."""
     import glob
     import hashlib
     src = os.path.join(ROOT, "paper_1612_04846_amd", "csrc", "bura_kernels.hip")
@@ -231,7 +235,7 @@ def counter_traffic(workload, kclass):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
         if kv.get("workload") == workload and kv.get("kernel_class") == kclass and \
-                kv.get("kernel_source_sha256_prefix") == sha:
+                kv.get("kernel_source_sha256_prefix") == sha and kv.get("tiles") == json.dumps(tiles):
             return int(kv["traffic_bytes_per_launch"])
     return None
 
@@ -418,6 +422,9 @@ def main():
     ap.add_argument("--autotune", type=int, default=1, choices=(0, 1),
                     help="1: plans time the tile-shape variants at creation and keep the fastest; "
                          "0: default shapes")
+    ap.add_argument("--tiles", type=json.loads, default=None,
+                    help="JSON list (one list per plan) of tile-shape variants to set on the main workload's "
+                         "plans after creation, e.g. the 'tiles' of an earlier bench line")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of this many GiB (counter calibration)")
     ap.add_argument("--also", default="2d1023-k9-fp64-per-pole,2d1023-k9-fp64-batched,2d1023-k9-mixed-multi,"
@@ -431,7 +438,7 @@ def main():
         PLAN_OPTS["nu_pre"] = PLAN_OPTS["nu_post"] = args.nu
     if args.inner_tol > 0:
         PLAN_OPTS["inner_tol"] = args.inner_tol
-    PLAN_OPTS["autotune"] = args.autotune
+    PLAN_OPTS["autotune"] = args.autotune if args.tiles is None else 0
     if args.copy_probe > 0:
         import torch
         nbytes = int(args.copy_probe * (1 << 30))
@@ -499,13 +506,15 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
     w = WORKLOADS[args.workload]
+    global FORCED_TILES
+    FORCED_TILES = args.tiles
     print(f"[bench] workload {args.workload}: {describe(w)}", file=sys.stderr, flush=True)
     res = run_gpu(w, args.steps, args.warmup, profile=not args.no_profile)
     import numpy as np
     lat_ms = np.array(res["lat"]) * 1e3
     roof, ktable = roofline(res["kstats"])
     if roof is not None:
-        roof["traffic"] = counter_traffic(args.workload, roof["kernel"])
+        roof["traffic"] = counter_traffic(args.workload, roof["kernel"], res["tiles"])
     out = {
         "metric": METRIC,
         "value": None,
@@ -535,6 +544,7 @@ def main():
     }
     raw_rate = res["per_step"] * args.steps / res["elapsed"]
     paths = {}
+    FORCED_TILES = None
     for extra in [x for x in args.also.split(",") if x and x != args.workload]:
         we = WORKLOADS[extra]
         print(f"[bench] extra path {extra}", file=sys.stderr, flush=True)

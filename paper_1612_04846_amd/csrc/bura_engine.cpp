@@ -1200,7 +1200,10 @@ std::mutex g_tile_mu;
 std::map<std::string, TileChoice> g_tile_cache;
 
 constexpr int kTuneMinN = 127;
-constexpr int kTuneReps = 3;
+constexpr int kTuneReps = 3;          // iterations per timing
+constexpr int kTuneRounds = 3;        // interleaved timings per variant (the minimum counts)
+constexpr int kTuneWarmup = 5;        // iterations before the first timing (clocks, caches)
+constexpr float kTuneMargin = 0.005f; // a variant replaces the default only if this much faster
 
 template <typename T>
 int tune_tiles(bura_plan_t P, Work<T>& W) {
@@ -1256,7 +1259,6 @@ int tune_tiles(bura_plan_t P, Work<T>& W) {
   };
   bool ok = true;
   auto timed = [&]() {
-    iteration();   // warm-up
     float ms = 0.0f;
     ok = ok && hipEventRecord(e0, st) == hipSuccess;
     for (int r = 0; r < kTuneReps && ok; ++r) iteration();
@@ -1264,23 +1266,40 @@ int tune_tiles(bura_plan_t P, Work<T>& W) {
          hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
     return ms;
   };
-  // coordinate descent: each knob takes its fastest variant with the others fixed
+  // BURA_TUNE_LOG=1 prints the timings of each knob's variants to stderr
+  const char* tl_env = std::getenv("BURA_TUNE_LOG");
+  const bool log = tl_env && tl_env[0] == '1';
+  int knob_id = 0;
+  // coordinate descent: each knob takes its fastest variant with the others
+  // fixed.  The variants are timed in turn, kTuneRounds times over (so that a
+  // drift of clocks or caches does not favour one of them), each by its
+  // fastest round; a variant must beat the default by kTuneMargin to be
+  // taken, so that timing noise does not decide between equals.
   auto tune = [&](int* knob) {
-    int best = *knob;
-    float best_ms = 0.0f;
-    for (int v = 0; v < kTileVariants && ok; ++v) {
-      *knob = v;
-      const float ms = timed();
-      if (ok && (v == 0 || ms < best_ms)) {
-        best = v;
-        best_ms = ms;
+    float best_of[kTileVariants];
+    for (int v = 0; v < kTileVariants; ++v) best_of[v] = 0.0f;
+    // round -1 of the first knob is not counted: the first timings of a plan
+    // run slower (measured: by about 1 %) even after the warm-up iterations
+    for (int r = knob_id == 0 ? -1 : 0; r < kTuneRounds && ok; ++r) {
+      for (int v = 0; v < kTileVariants && ok; ++v) {
+        *knob = v;
+        const float ms = timed();
+        if (r == 0 || (r > 0 && ms < best_of[v])) best_of[v] = ms;
       }
     }
+    int best = 0;
+    for (int v = 1; v < kTileVariants; ++v)
+      if (best_of[v] < best_of[best] * (best == 0 ? 1.0f - kTuneMargin : 1.0f)) best = v;
     *knob = best;
+    if (log)
+      std::fprintf(stderr, "[bura tune] knob %d: %.4f %.4f %.4f ms -> %d\n", knob_id, best_of[0], best_of[1],
+                   best_of[2], best);
+    ++knob_id;
   };
   P->tile_spmv = 0;
   std::fill(P->tile_down.begin(), P->tile_down.end(), 0);
   std::fill(P->tile_up.begin(), P->tile_up.end(), 0);
+  for (int w = 0; w < kTuneWarmup; ++w) iteration();
   tune(&P->tile_spmv);
   for (int l = 0; l < lc && fused_ok(P) && ok; ++l) {
     if (P->lev[l].n < kTuneMinN) continue;

@@ -62,7 +62,7 @@ __device__ __forceinline__ void tile_ijk(const Tile& tl, int n, int& i, int& j, 
 // its column's values at planes k-1, k, k+1 in registers from one plane to the
 // next, so the points above and below are not loaded again (a
 // one-point-per-thread launch reads them from the last-level caches).
-constexpr int kMarchZ = 16;
+constexpr int kMarchZ = 8;
 
 struct Column {
   int i, j, k0, k1;   // the thread's column and its planes [k0, k1)
