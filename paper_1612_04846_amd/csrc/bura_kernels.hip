@@ -490,6 +490,143 @@ __global__ __launch_bounds__(kBlock) void k_prolong(LevelDev<T> Lc, LevelDev<T> 
 }
 
 // --------------------------------------------------------------------------
+// 3D transfer operators marching along z (grids of 2^L - 1 points: n_f = 2 n_c + 1)
+// --------------------------------------------------------------------------
+// The two coarse parents of fine index f on one axis and their weights: odd f
+// lies on coarse point (f - 1) / 2 (weight 1, second weight 0); even f halfway
+// between f/2 - 1 and f/2 (weight 1/2 each, 0 for a parent outside the grid,
+// whose index is clamped).
+template <typename T>
+__device__ __forceinline__ void axis_pair(int f, int nc, int& a, int& b, T& wa, T& wb) {
+  if (f & 1) {
+    a = b = f >> 1;
+    wa = T(1);
+    wb = T(0);
+  } else {
+    a = (f >> 1) - 1;
+    b = f >> 1;
+    wa = a >= 0 ? T(0.5) : T(0);
+    wb = b < nc ? T(0.5) : T(0);
+    a = max(a, 0);
+    b = min(b, nc - 1);
+  }
+}
+
+// x_f += P x_c: one thread per fine column (i, j) over kMarchZ fine planes.  The
+// in-plane interpolant of each coarse plane is formed once and kept for the
+// two or three fine planes that use it.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong3(LevelDev<T> Lc, LevelDev<T> Lf, const T* __restrict__ xc,
+                                                     T* __restrict__ xf, const int* __restrict__ active,
+                                                     unsigned long long* __restrict__ ctr) {
+  const Tile tl = block_tile();
+  const int sys = tl.z;
+  if (!active[sys]) return;
+  count_bytes_tile(tl, ctr, (unsigned long long)Lf.N * sizeof(T) * 2 + (unsigned long long)Lc.N * sizeof(T));
+  const int nf = Lf.n, nc = Lc.n;
+  const Column c = march_column(tl, nf);
+  if (c.i >= nf || c.j >= nf) return;
+  int ia, ib, ja, jb;
+  T wia, wib, wja, wjb;
+  axis_pair<T>(c.i, nc, ia, ib, wia, wib);
+  axis_pair<T>(c.j, nc, ja, jb, wja, wjb);
+  const T* xcs = xc + (long long)sys * Lc.N;
+  const long long ncc = (long long)nc * nc;
+  const long long oaa = (long long)ja * nc + ia, oab = (long long)ja * nc + ib;
+  const long long oba = (long long)jb * nc + ia, obb = (long long)jb * nc + ib;
+  // the in-plane interpolant on coarse plane K (0 off the grid)
+  auto plane = [&](int K) -> T {
+    const long long base = (long long)min(max(K, 0), nc - 1) * ncc;
+    const T v00 = xcs[base + oaa], v01 = xcs[base + oab], v10 = xcs[base + oba], v11 = xcs[base + obb];
+    const T v = wja * (wia * v00 + wib * v01) + wjb * (wia * v10 + wib * v11);
+    return (K >= 0 && K < nc) ? v : T(0);
+  };
+  // fine plane k: odd k lies on coarse plane (k - 1) / 2, even k halfway between
+  // k/2 - 1 and k/2; (vlo, vhi) hold coarse planes Kc and Kc + 1
+  int Kc = (c.k0 >> 1) - 1;
+  T vlo = plane(Kc), vhi = plane(Kc + 1);
+  T* xfs = xf + (long long)sys * Lf.N;
+  const long long nnf = (long long)nf * nf, col = (long long)c.j * nf + c.i;
+  for (int k = c.k0; k < c.k1; ++k) {
+    const int klo = (k >> 1) - 1 + (k & 1);
+    if (Kc < klo) {
+      vlo = vhi;
+      ++Kc;
+      vhi = plane(Kc + 1);
+    }
+    const T v = (k & 1) ? vlo : T(0.5) * (vlo + vhi);
+    const long long p = k * nnf + col;
+    xfs[p] += v;
+  }
+}
+
+// b_c = R (b - (A+s) x): one thread per coarse column (I, J) over kMarchZ coarse
+// planes.  The fine residual is formed on the 3 x 3 fine columns under the
+// coarse column, plane by plane (each fine column keeps x at the planes below
+// and at the current one in registers); each fine plane's in-plane weighted
+// sum is formed once and shared by the two coarse planes that weight it.
+template <typename T, bool VAR>
+__global__ __launch_bounds__(kBlock) void k_restrict3(LevelDev<T> Lf, LevelDev<T> Lc, const T* __restrict__ b,
+                                                      const T* __restrict__ x, T* __restrict__ bc,
+                                                      const T* __restrict__ shift, const int* __restrict__ active,
+                                                      unsigned long long* __restrict__ ctr) {
+  const Tile tl = block_tile();
+  const int sys = tl.z;
+  if (!active[sys]) return;
+  count_bytes_tile(tl, ctr, (unsigned long long)Lc.N * sizeof(T) * (2 * 8 + 1 + (VAR && sys == 0 ? 3 * 8 : 0)));
+  const int nf = Lf.n, nc = Lc.n;
+  const Column c = march_column(tl, nc);
+  if (c.i >= nc || c.j >= nc) return;
+  const T s = shift[sys];
+  const T* bs = b + (long long)sys * Lf.N;
+  const T* xs = x + (long long)sys * Lf.N;
+  const long long nnf = (long long)nf * nf;
+  const int fi0 = 2 * c.i, fj0 = 2 * c.j;   // the 3 x 3 fine columns: fi0 .. fi0 + 2, fj0 .. fj0 + 2
+  T xm[9], xc0[9];                          // x at the fine plane below and at the current fine plane
+  int fk = 2 * c.k0;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const long long col = (long long)(fj0 + q / 3) * nf + (fi0 + q % 3);
+    const long long p = fk * nnf + col;
+    const T xb = xs[fk > 0 ? p - nnf : p];
+    xm[q] = fk > 0 ? xb : T(0);
+    xc0[q] = xs[p];
+  }
+  // the weighted in-plane sum of the residual on fine plane fk; advances the registers
+  auto rplane = [&]() -> T {
+    const T wt[3] = {T(0.25), T(0.5), T(0.25)};
+    T acc = T(0);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const int di = q % 3, dj = q / 3;
+      const int fi = fi0 + di, fj = fj0 + dj;
+      const long long p = fk * nnf + (long long)fj * nf + fi;
+      const PlaneNb o = plane_nb(fi, fj, nf);
+      const T xa = xs[fk + 1 < nf ? p + nnf : p];
+      const T xl = xs[p + o.l], xr = xs[p + o.r], xd = xs[p + o.d], xu = xs[p + o.u];
+      const T bv = bs[p];
+      const T above = fk + 1 < nf ? xa : T(0);
+      const T r = bv - apply_col3<T, VAR>(Lf, fi, fj, fk, p, xc0[q], o.l ? xl : T(0), o.r ? xr : T(0),
+                                           o.d ? xd : T(0), o.u ? xu : T(0), xm[q], above, s, nullptr);
+      acc += wt[dj] * wt[di] * r;
+      xm[q] = xc0[q];
+      xc0[q] = above;
+    }
+    ++fk;
+    return acc;
+  };
+  T* bcs = bc + (long long)sys * Lc.N;
+  const long long col_c = (long long)c.j * nc + c.i, ncc = (long long)nc * nc;
+  T rlo = rplane();   // fine plane 2 K0
+  for (int K = c.k0; K < c.k1; ++K) {
+    const T rmid = rplane();   // 2K + 1
+    const T rhi = rplane();    // 2K + 2
+    bcs[K * ncc + col_c] = T(0.25) * rlo + T(0.5) * rmid + T(0.25) * rhi;
+    rlo = rhi;
+  }
+}
+
+// --------------------------------------------------------------------------
 // coarse solve: `cycles` V-cycles on the levels in H, one workgroup per system,
 // all vectors in LDS.  Symmetric (nu Jacobi sweeps before and after), so the
 // composite is an SPD preconditioner component.
@@ -1558,6 +1695,12 @@ template <typename T>
 void Launch<T>::restrict_residual(int dim, bool var, const LevelDev<T>& Lf, const LevelDev<T>& Lc, const T* b,
                                   const T* x, T* bc, const T* shift, const int* active, int nsys, hipStream_t st,
                                   unsigned long long* ctr) {
+  if (dim == 3) {
+    const dim3 g3 = march_grid(Lc.n, nsys), blk3(kTileX, kTileY);
+    if (var) hipLaunchKernelGGL((k_restrict3<T, true>), g3, blk3, 0, st, Lf, Lc, b, x, bc, shift, active, ctr);
+    else hipLaunchKernelGGL((k_restrict3<T, false>), g3, blk3, 0, st, Lf, Lc, b, x, bc, shift, active, ctr);
+    return;
+  }
   const dim3 g = point_grid(dim, Lc.n, nsys), blk(kTileX, kTileY);
 #define K_RES(D, V, dummy) hipLaunchKernelGGL((k_restrict<T, D, V>), g, blk, 0, st, Lf, Lc, b, x, bc, shift, active, ctr)
   BURA_DISPATCH_DV(dim, var, K_RES, 0);
@@ -1567,9 +1710,12 @@ void Launch<T>::restrict_residual(int dim, bool var, const LevelDev<T>& Lf, cons
 template <typename T>
 void Launch<T>::prolong_add(int dim, const LevelDev<T>& Lc, const LevelDev<T>& Lf, const T* xc, T* xf,
                             const int* active, int nsys, hipStream_t st, unsigned long long* ctr) {
-  const dim3 g = point_grid(dim, Lf.n, nsys), blk(kTileX, kTileY);
-  if (dim == 2) hipLaunchKernelGGL((k_prolong<T, 2>), g, blk, 0, st, Lc, Lf, xc, xf, active, ctr);
-  else hipLaunchKernelGGL((k_prolong<T, 3>), g, blk, 0, st, Lc, Lf, xc, xf, active, ctr);
+  if (dim == 2)
+    hipLaunchKernelGGL((k_prolong<T, 2>), point_grid(2, Lf.n, nsys), dim3(kTileX, kTileY), 0, st, Lc, Lf, xc, xf,
+                       active, ctr);
+  else
+    hipLaunchKernelGGL((k_prolong3<T>), march_grid(Lf.n, nsys), dim3(kTileX, kTileY), 0, st, Lc, Lf, xc, xf, active,
+                       ctr);
 }
 
 template <typename T>
