@@ -783,6 +783,41 @@ __device__ __forceinline__ T lds_apply2(const T* __restrict__ X, int q, int RX, 
   return wl * (xc - xl) + wr * (xc - xr) + wd * (xc - xd) + wu * (xc - xu) + s * xc;
 }
 
+// Face weights of the LDS region points a thread owns in the fused 2D kernels
+// (points tid + 256 u, u < PER), held in registers.  Constant coefficients:
+// empty.  Points off the grid hold the weights of the nearest grid point
+// (clamped; never used in a sweep).
+template <typename T, bool VAR, int PER>
+struct RegionFaces {
+  T wl[VAR ? PER : 1], wr[VAR ? PER : 1], wd[VAR ? PER : 1], wu[VAR ? PER : 1];
+  __device__ __forceinline__ void load(const LevelDev<T>& L, int tid, int RX, int RN, int gx0, int gy0) {
+    if (!VAR) return;
+    const int n = L.n;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int q = min(tid + 256 * u, RN - 1);
+      const int ry = q / RX, rx = q - ry * RX;
+      const int ci = min(max(gx0 + rx, 0), n - 1), cj = min(max(gy0 + ry, 0), n - 1);
+      const long long fx = (long long)cj * (n + 1) + ci;
+      const long long fy = (long long)cj * n + ci;
+      wl[u] = L.wf0[fx];
+      wr[u] = L.wf0[fx + 1];
+      wd[u] = L.wf1[fy];
+      wu[u] = L.wf1[fy + n];
+    }
+  }
+  // D = sum of the faces + s (same order as diag_pt)
+  __device__ __forceinline__ T diag(int u, T s) const { return wl[u] + wr[u] + wd[u] + wu[u] + s; }
+  // (A + s) x at region point q from LDS values X (row length RX); same
+  // arithmetic and order as lds_apply2; *dg = D when dg != nullptr
+  __device__ __forceinline__ T apply(int u, const T* X, int q, int RX, T s, T* dg) const {
+    const T xc = X[q];
+    const T xl = X[q - 1], xr = X[q + 1], xd = X[q - RX], xu = X[q + RX];
+    if (dg) *dg = wl[u] + wr[u] + wd[u] + wu[u] + s;
+    return wl[u] * (xc - xl) + wr[u] * (xc - xr) + wd[u] * (xc - xd) + wu[u] * (xc - xu) + s * xc;
+  }
+};
+
 // Tile shapes of the 2D kernels, one row per launch-shape variant (variant 0
 // is the default; a plan may time the others at creation and keep the
 // fastest): coarse points per block of the down kernel, fine points per block
@@ -825,6 +860,11 @@ __global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, c
   // results selected afterwards), so a wave keeps PER loads in flight.
   constexpr int PER = (RN + 255) / 256;
   T bl[PER], ql[PER];
+  // variable coefficients: the four face weights of each of this thread's
+  // region points (thread tid always owns points tid + 256 u), loaded once for
+  // every sweep and the residual instead of once per use
+  RegionFaces<T, VAR, PER> fw;
+  fw.load(Lf, tid, RX, RN, gx0, gy0);
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int q = tid + 256 * u;
@@ -844,10 +884,7 @@ __global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, c
       const bool in = gi >= 0 && gi < nf && gj >= 0 && gj < nf;
       const T bv = in ? (RUP ? bl[u] - am * ql[u] : bl[u]) : T(0);
       T xv = sweep_w(om, 0) * bv / dcon;
-      if (VAR) {
-        const int ci = min(max(gi, 0), nf - 1), cj = min(max(gj, 0), nf - 1);
-        xv = sweep_w(om, 0) * bv / diag_pt<T, 2, VAR>(Lf, ci, cj, 0, sh);
-      }
+      if (VAR) xv = sweep_w(om, 0) * bv / fw.diag(u, sh);
       sb[q] = bv;
       s0[q] = in ? xv : T(0);
       s1[q] = T(0);
@@ -858,18 +895,35 @@ __global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, c
   T* Y = s1;
 #pragma unroll
   for (int m = 1; m < NU; ++m) {   // sweep m+1 on the range shrunk by m
-    const int w = RX - 2 * m, hgt = RY - 2 * m;
     const T wm = sweep_w(om, m), wcon = wm / dcon;
-    for (int q2 = tid; q2 < w * hgt; q2 += 256) {
-      const int ry = m + q2 / w, rx = m + q2 % w;
-      const int q = ry * RX + rx;
-      const int gi = gx0 + rx, gj = gy0 + ry;
-      if (gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
-        T dg;
-        const T ax = lds_apply2<T, VAR>(X, q, RX, Lf, gi, gj, sh, VAR ? &dg : nullptr);
-        Y[q] = VAR ? X[q] + wm * (sb[q] - ax) / dg : X[q] + wcon * (sb[q] - ax);
-      } else {
-        Y[q] = T(0);
+    if (VAR) {
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int q = tid + 256 * u;
+        const int ry = q / RX, rx = q - ry * RX;
+        if (q < RN && rx >= m && rx < RX - m && ry >= m && ry < RY - m) {
+          const int gi = gx0 + rx, gj = gy0 + ry;
+          if (gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
+            T dg;
+            const T ax = fw.apply(u, X, q, RX, sh, &dg);
+            Y[q] = X[q] + wm * (sb[q] - ax) / dg;
+          } else {
+            Y[q] = T(0);
+          }
+        }
+      }
+    } else {
+      const int w = RX - 2 * m, hgt = RY - 2 * m;
+      for (int q2 = tid; q2 < w * hgt; q2 += 256) {
+        const int ry = m + q2 / w, rx = m + q2 % w;
+        const int q = ry * RX + rx;
+        const int gi = gx0 + rx, gj = gy0 + ry;
+        if (gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
+          const T ax = lds_apply2<T, false>(X, q, RX, Lf, gi, gj, sh, nullptr);
+          Y[q] = X[q] + wcon * (sb[q] - ax);
+        } else {
+          Y[q] = T(0);
+        }
       }
     }
     __syncthreads();
@@ -900,14 +954,26 @@ __global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, c
     }
   }
   // residual on the range shrunk by NU (fine points 2 I0 .. 2 I0 + 2 CX)
-  {
+  if (VAR) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int q = tid + 256 * u;
+      const int ry = q / RX, rx = q - ry * RX;
+      if (q < RN && rx >= NU && rx < RX - NU && ry >= NU && ry < RY - NU) {
+        const int gi = gx0 + rx, gj = gy0 + ry;
+        T r = T(0);
+        if (gi >= 0 && gi < nf && gj >= 0 && gj < nf) r = sb[q] - fw.apply(u, X, q, RX, sh, nullptr);
+        Y[q] = r;
+      }
+    }
+  } else {
     const int w = RX - 2 * NU, hgt = RY - 2 * NU;
     for (int q2 = tid; q2 < w * hgt; q2 += 256) {
       const int ry = NU + q2 / w, rx = NU + q2 % w;
       const int q = ry * RX + rx;
       const int gi = gx0 + rx, gj = gy0 + ry;
       T r = T(0);
-      if (gi >= 0 && gi < nf && gj >= 0 && gj < nf) r = sb[q] - lds_apply2<T, VAR>(X, q, RX, Lf, gi, gj, sh, nullptr);
+      if (gi >= 0 && gi < nf && gj >= 0 && gj < nf) r = sb[q] - lds_apply2<T, false>(X, q, RX, Lf, gi, gj, sh, nullptr);
       Y[q] = r;
     }
   }
@@ -1013,6 +1079,8 @@ __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, con
   T* Y = s1;
 #pragma unroll
   for (int m = 1; m <= NU; ++m) {   // post-smoothing: the pre-smoothing weights reversed
+    // (the face weights are read per sweep here: held in registers, as in the
+    // down kernel, they cost more occupancy than the two sweeps save)
     const int w = RX - 2 * m, hgt = RY - 2 * m;
     const T wm = sweep_w(om, NU - m), wcon = wm / dcon;
     for (int q2 = tid; q2 < w * hgt; q2 += 256) {
