@@ -1182,14 +1182,19 @@ using LateTerms = std::function<int(double lambda, Terms& t)>;
 // 2D stencil product and of each level's fused down and up kernels (levels
 // with n >= kTuneMinN; smaller ones are launch-bound and keep the default).
 // Each knob in turn (coordinate descent from the defaults, fine level first)
-// takes the variant for which kTuneReps whole PCG iterations -- stencil
-// product and V-cycle as a solve launches them, on the plan's own buffers,
-// every system active -- run fastest.  Timing whole iterations keeps the cache
-// state of the real sequence (one kernel timed alone on its own output would
-// see warmer caches).  The choice is cached per (precision, grid, coefficients
-// or not, sweeps, systems) for the life of the process.  The variants compute
-// the same value at every point; only the grouping of the per-block partial
-// sums of the dot products differs.
+// takes the variant for which a whole batched solve of the plan -- every
+// system, a fixed pseudo-random right-hand side, to the plan's tolerance --
+// runs fastest.  Timing real solves takes in what a proxy misses: systems
+// converging at different iterations (their blocks still launch and exit),
+// the alternating buffers, the scalar updates.  (Timed as a few PCG iterations
+// with every system active, the tuner picked a 2-row stencil product that is
+// 8 % slower in the 2048-system solves.)  The variants are timed in
+// interleaved rounds, each by its fastest round, and one must beat the default
+// by kTuneMargin.  The solves run without graph capture (captured graphs fix
+// the launch shapes).  The choice is cached per (precision, grid,
+// coefficients or not, sweeps, systems) for the life of the process.  The
+// variants compute the same value at every point; only the grouping of the
+// per-block partial sums of the dot products differs.
 // ---------------------------------------------------------------------------
 struct TileChoice {
   int spmv = 0;
@@ -1199,17 +1204,15 @@ struct TileChoice {
 std::mutex g_tile_mu;
 std::map<std::string, TileChoice> g_tile_cache;
 
-constexpr int kTuneMinN = 127;
-constexpr int kTuneReps = 3;          // iterations per timing
-constexpr int kTuneRounds = 3;        // interleaved timings per variant (the minimum counts)
-constexpr int kTuneWarmup = 5;        // iterations before the first timing (clocks, caches)
+constexpr int kTuneMinN = 255;
+constexpr int kTuneRounds = 2;        // interleaved timings per variant (the minimum counts)
 constexpr float kTuneMargin = 0.005f; // a variant replaces the default only if this much faster
 
-template <typename T>
-int tune_tiles(bura_plan_t P, Work<T>& W) {
+int tune_tiles(bura_plan_t P) {
   if (P->dim != 2) return BURA_OK;   // the 3D kernels have one shape
+  const bool mixed = P->opts.precision == BURA_MIXED;
   char key[160];
-  std::snprintf(key, sizeof(key), "%zu/%d/%d/%d/%d/%d/%d/%d", sizeof(T), P->dim, P->n, (int)P->var,
+  std::snprintf(key, sizeof(key), "%d/%d/%d/%d/%d/%d/%d/%d", mixed ? 4 : 8, P->dim, P->n, (int)P->var,
                 P->opts.nu_pre, P->opts.nu_post, P->S, (int)P->foldxr);
   {
     std::lock_guard<std::mutex> lk(g_tile_mu);
@@ -1222,47 +1225,36 @@ int tune_tiles(bura_plan_t P, Work<T>& W) {
     }
   }
   hipStream_t st = P->stream;
-  const int nsys = P->S;
-  const int lc = P->lc;
-  const SysState S = P->st;
-  // defined contents (zeros) everywhere the kernels read; every system
-  // active; alpha and beta nonzero so that the kernels move the bytes of a
-  // mid-solve iteration (p_old read, x and r updated)
-  for (int l = 1; l <= lc; ++l) {
-    const size_t b = (size_t)nsys * (size_t)P->lev[l].N * sizeof(T);
-    launch_zero(W.xl[l], b, st);
-    launch_zero(W.bl[l], b, st);
-    if (l < lc) launch_zero(W.tl[l], b, st);
+  // one right-hand side for every system (nrhs = 1 below): uniform in [-1, 1)
+  // from a fixed 64-bit linear congruential sequence
+  std::vector<double> hf((size_t)P->N);
+  uint64_t state = 0x9E3779B97F4A7C15ULL;
+  for (auto& v : hf) {
+    state = state * 6364136223846793005ULL + 1442695040888963407ULL;
+    v = (double)(state >> 11) * (2.0 / 9007199254740992.0) - 1.0;
   }
-  if (W.r2) launch_zero(W.r2, (size_t)nsys * (size_t)P->N * sizeof(T), st);
-  launch_fill_int(S.active, nsys, 1, st);
-  std::vector<double> half((size_t)nsys, 0.5);
-  HIPCHK(hipMemcpyAsync(S.alpha, half.data(), half.size() * 8, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(S.beta, half.data(), half.size() * 8, hipMemcpyHostToDevice, st));
+  double* df = nullptr;
+  if (hipMalloc((void**)&df, hf.size() * 8) != hipSuccess) return BURA_ENOMEM;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+  if (hipMemcpyAsync(df, hf.data(), hf.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) hipEventDestroy(e0);
+    hipFree(df);
     return BURA_EDEVICE;
   }
-  const bool fx = P->foldxr;
-  const LevelDev<T> L0 = level_view<T>(P, 0);
-  // one PCG iteration's stencil product and preconditioner, as run_pcg issues them
-  auto iteration = [&]() {
-    Launch<T>::spmv_p(2, P->var, L0, W.z, W.p, W.p2, W.q, S.beta, W.shift, S.active, P->partial, nsys, st, nullptr,
-                      Fin(), fx ? W.x : nullptr, S.alpha, P->tile_spmv);
-    if (fx) {
-      ResidUpdate<T> ru{W.r, W.r2, W.q, S.alpha, Fin(), nullptr};
-      precondition<T>(P, W, 0, nsys, S.active, P->partial, Fin(), &ru);
-    } else {
-      precondition<T>(P, W, 0, nsys, S.active, P->partial, Fin());
-    }
-  };
+  const bool graphs = P->use_graphs;
+  P->use_graphs = false;
   bool ok = true;
   auto timed = [&]() {
     float ms = 0.0f;
+    // the per-solve counters a solve starts from (as in do_solve)
+    set_flags(P, P->st.flags, 0, P->S, 0);
+    set_flags(P, P->st.total_iters, 0, P->S, 0);
+    set_flags(P, P->st.outer, 0, P->S, 0);
     ok = ok && hipEventRecord(e0, st) == hipSuccess;
-    for (int r = 0; r < kTuneReps && ok; ++r) iteration();
-    ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+    const int rc = ok ? (mixed ? solve_batch_mixed(P, df, 1, 0, P->S, false) : solve_batch_fp64(P, df, 1, 0, P->S, false))
+                      : BURA_EDEVICE;
+    ok = ok && rc == BURA_OK && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
          hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
     return ms;
   };
@@ -1270,21 +1262,14 @@ int tune_tiles(bura_plan_t P, Work<T>& W) {
   const char* tl_env = std::getenv("BURA_TUNE_LOG");
   const bool log = tl_env && tl_env[0] == '1';
   int knob_id = 0;
-  // coordinate descent: each knob takes its fastest variant with the others
-  // fixed.  The variants are timed in turn, kTuneRounds times over (so that a
-  // drift of clocks or caches does not favour one of them), each by its
-  // fastest round; a variant must beat the default by kTuneMargin to be
-  // taken, so that timing noise does not decide between equals.
   auto tune = [&](int* knob) {
     float best_of[kTileVariants];
     for (int v = 0; v < kTileVariants; ++v) best_of[v] = 0.0f;
-    // round -1 of the first knob is not counted: the first timings of a plan
-    // run slower (measured: by about 1 %) even after the warm-up iterations
-    for (int r = knob_id == 0 ? -1 : 0; r < kTuneRounds && ok; ++r) {
+    for (int r = 0; r < kTuneRounds && ok; ++r) {
       for (int v = 0; v < kTileVariants && ok; ++v) {
         *knob = v;
         const float ms = timed();
-        if (r == 0 || (r > 0 && ms < best_of[v])) best_of[v] = ms;
+        if (r == 0 || ms < best_of[v]) best_of[v] = ms;
       }
     }
     int best = 0;
@@ -1299,20 +1284,19 @@ int tune_tiles(bura_plan_t P, Work<T>& W) {
   P->tile_spmv = 0;
   std::fill(P->tile_down.begin(), P->tile_down.end(), 0);
   std::fill(P->tile_up.begin(), P->tile_up.end(), 0);
-  for (int w = 0; w < kTuneWarmup; ++w) iteration();
+  timed();   // warm-up (clocks, caches, first-touch)
   tune(&P->tile_spmv);
-  for (int l = 0; l < lc && fused_ok(P) && ok; ++l) {
+  for (int l = 0; l < P->lc && fused_ok(P) && ok; ++l) {
     if (P->lev[l].n < kTuneMinN) continue;
     tune(&P->tile_down[l]);
     tune(&P->tile_up[l]);
   }
+  P->use_graphs = graphs;
   hipEventDestroy(e0);
   hipEventDestroy(e1);
-  // the solves set flags and scalars themselves; leave no pending update behind
-  launch_zero(S.alpha, (size_t)nsys * 8, st);
-  launch_zero(S.beta, (size_t)nsys * 8, st);
-  launch_fill_int(S.active, nsys, 0, st);
-  if (!ok || hipStreamSynchronize(st) != hipSuccess) return BURA_EDEVICE;
+  const bool synced = hipStreamSynchronize(st) == hipSuccess;
+  hipFree(df);
+  if (!ok || !synced) return BURA_EDEVICE;
   TileChoice c;
   c.spmv = P->tile_spmv;
   c.down = P->tile_down;
@@ -1451,7 +1435,7 @@ int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_p
     return fail(BURA_ENOMEM);
   if (o.autotune) {
     if (hipStreamSynchronize(P->stream) != hipSuccess) return fail(BURA_EDEVICE);
-    if ((rc = mixed ? tune_tiles<float>(P, P->w32) : tune_tiles<double>(P, P->w64))) return fail(rc);
+    if ((rc = tune_tiles(P))) return fail(rc);
   }
   // only this plan's stream: a device-wide synchronisation would break graph
   // capture running on other plans' streams in other threads

@@ -63,21 +63,60 @@ __device__ __forceinline__ void tile_ijk(const Tile& tl, int n, int& i, int& j, 
 // next, so the points above and below are not loaded again (a
 // one-point-per-thread launch reads them from the last-level caches).
 constexpr int kMarchZ = 8;
+// rows per thread of the marching kernels that write per-block partials (the
+// rows above and below a thread's interior rows come from its own registers;
+// a workgroup covers kTileX x (kTileY kMarchRows) columns)
+constexpr int kMarchRows = 2;
 
 struct Column {
-  int i, j, k0, k1;   // the thread's column and its planes [k0, k1)
+  int i, j, k0, k1;   // the thread's first column (i, j) (rows j .. j + rows - 1) and its planes [k0, k1)
 };
 
-__device__ __forceinline__ Column march_column(const Tile& tl, int n) {
+__device__ __forceinline__ Column march_column(const Tile& tl, int n, int rows) {
   Column c;
-  const int yt = (n + kTileY - 1) / kTileY;
+  const int yt = (n + kTileY * rows - 1) / (kTileY * rows);
   const int kc = tl.y / yt;
   c.i = tl.x * kTileX + threadIdx.x;
-  c.j = (tl.y - kc * yt) * kTileY + threadIdx.y;
+  c.j = ((tl.y - kc * yt) * kTileY + threadIdx.y) * rows;
   c.k0 = kc * kMarchZ;
   c.k1 = min(c.k0 + kMarchZ, n);
   return c;
 }
+
+// A thread's R rows in a marching kernel: row r is j0 + r; rows at or beyond n
+// are not computed (their loads read row n - 1).  Offsets of the rows and of
+// the halo rows j0 - 1 and j0 + R within a plane.
+template <int R>
+struct Rows {
+  long long col[R];   // in-plane offset of row r (clamped)
+  bool valid[R];
+  bool has_d, has_u;  // rows j0 - 1 and j0 + R inside the grid
+  long long col_d, col_u;
+  int il, ir;         // x-neighbour offsets (0 at the boundary)
+  __device__ __forceinline__ Rows(int i, int j0, int n) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      valid[r] = j0 + r < n;
+      col[r] = (long long)min(j0 + r, n - 1) * n + i;
+    }
+    has_d = j0 > 0;
+    has_u = j0 + R < n;
+    col_d = (long long)(has_d ? j0 - 1 : j0) * n + i;
+    col_u = (long long)(has_u ? j0 + R : n - 1) * n + i;
+    il = i > 0 ? -1 : 0;
+    ir = i < n - 1 ? 1 : 0;
+  }
+  // the row-below / row-above neighbours of row r from the rows' centre values
+  // and the halo values (0 outside the grid)
+  template <typename T>
+  __device__ __forceinline__ T down(int r, const T* centre, T halo_d) const {
+    return r == 0 ? (has_d ? halo_d : T(0)) : centre[r - 1];
+  }
+  template <typename T>
+  __device__ __forceinline__ T up(int r, const T* centre, T halo_u) const {
+    return r == R - 1 ? (has_u ? halo_u : T(0)) : (valid[r + 1] ? centre[r + 1] : T(0));
+  }
+};
 
 // FP64 block sum; the result is valid in thread 0 only.  Fixed order.
 __device__ __forceinline__ double block_sum(double v) {
@@ -295,55 +334,84 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(LevelDev<T> L, const T* __res
   }
 }
 
-// k_jacobi in 3D, marching along z (one workgroup per kMarchZ planes).
+// k_jacobi in 3D, marching along z (one workgroup per kMarchZ planes,
+// kMarchRows rows per thread).
 template <typename T, bool VAR, bool ZERO, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_jacobi3(LevelDev<T> L, const T* __restrict__ b,
                                                     const T* __restrict__ xin, T* __restrict__ xout,
                                                     const T* __restrict__ shift, const int* __restrict__ active,
                                                     T omega, double* __restrict__ partial,
                                                     unsigned long long* __restrict__ ctr, Fin fin) {
+  constexpr int R = kMarchRows;
   const Tile tl = block_tile();
   const int sys = tl.z;
   if (!active[sys]) return;
   count_bytes_tile(tl, ctr, (unsigned long long)L.N * sizeof(T) * ((ZERO ? 2 : 3) + (VAR && sys == 0 ? 3 : 0)));
   const int n = L.n;
-  const Column c = march_column(tl, n);
+  const Column c = march_column(tl, n, R);
   double dot = 0.0;
   if (c.i < n && c.j < n) {
     const long long off = (long long)sys * L.N, nn = (long long)n * n;
-    const long long col = (long long)c.j * n + c.i;
+    const Rows<R> w(c.i, c.j, n);
     const T s = shift[sys];
     const T* bs = b + off;
     T* xo = xout + off;
     if (ZERO) {
       for (int k = c.k0; k < c.k1; ++k) {
-        const long long p = k * nn + col;
-        const T bv = bs[p];
-        const T xn = omega * bv / diag_pt<T, 3, VAR>(L, c.i, c.j, k, s);
-        xo[p] = xn;
-        if (DOT) dot += (double)bv * (double)xn;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (!w.valid[r]) continue;
+          const long long p = k * nn + w.col[r];
+          const T bv = bs[p];
+          const T xn = omega * bv / diag_pt<T, 3, VAR>(L, c.i, c.j + r, k, s);
+          xo[p] = xn;
+          if (DOT) dot += (double)bv * (double)xn;
+        }
       }
     } else {
       const T* xs = xin + off;
-      const PlaneNb o = plane_nb(c.i, c.j, n);
-      const long long p0 = c.k0 * nn + col;
-      const T xb0 = xs[c.k0 > 0 ? p0 - nn : p0];
-      T below = c.k0 > 0 ? xb0 : T(0);
-      T centre = xs[p0];
+      T below[R], centre[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const long long p0 = c.k0 * nn + w.col[r];
+        const T xb0 = xs[c.k0 > 0 ? p0 - nn : p0];
+        below[r] = c.k0 > 0 ? xb0 : T(0);
+        centre[r] = xs[p0];
+      }
       for (int k = c.k0; k < c.k1; ++k) {
-        const long long p = k * nn + col;
-        const T xa = xs[k + 1 < n ? p + nn : p];
-        const T xl = xs[p + o.l], xr = xs[p + o.r], xd = xs[p + o.d], xu = xs[p + o.u];
-        const T bv = bs[p];
-        const T above = k + 1 < n ? xa : T(0);
-        T dg;
-        const T ax = apply_col3<T, VAR>(L, c.i, c.j, k, p, centre, o.l ? xl : T(0), o.r ? xr : T(0),
-                                        o.d ? xd : T(0), o.u ? xu : T(0), below, above, s, &dg);
-        const T xn = centre + omega * (bv - ax) / dg;
-        xo[p] = xn;
-        if (DOT) dot += (double)bv * (double)xn;
-        below = centre;
-        centre = above;
+        const long long pk = k * nn;
+        // every load of the plane first, then the arithmetic (loading the next
+        // plane one step ahead measured slower)
+        T xa[R], xl[R], xr[R], bv[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const long long p = pk + w.col[r];
+          xa[r] = xs[k + 1 < n ? p + nn : p];
+          xl[r] = xs[p + w.il];
+          xr[r] = xs[p + w.ir];
+          bv[r] = bs[p];
+        }
+        const T hd = xs[pk + w.col_d], hu = xs[pk + w.col_u];
+        T above[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) above[r] = k + 1 < n ? xa[r] : T(0);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (!w.valid[r]) continue;
+          const long long p = pk + w.col[r];
+          T dg;
+          const T ax = apply_col3<T, VAR>(L, c.i, c.j + r, k, p, centre[r], w.il ? xl[r] : T(0),
+                                          w.ir ? xr[r] : T(0), w.down(r, centre, hd), w.up(r, centre, hu),
+                                          below[r], above[r], s, &dg);
+          const T xn = centre[r] + omega * (bv[r] - ax) / dg;
+          xo[p] = xn;
+          if (DOT) dot += (double)bv[r] * (double)xn;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          below[r] = centre[r];
+          centre[r] = above[r];
+        }
       }
     }
   }
@@ -368,9 +436,11 @@ __global__ __launch_bounds__(kBlock) void k_jacobi0_rup(LevelDev<T> L, const T* 
   const int sys = tl.z;
   if (!active[sys]) return;
   const int n = L.n;
-  int i, j, k0, k1;   // 2D: one point; 3D: a column over kMarchZ planes
+  // 2D: one point; 3D: kMarchRows rows over kMarchZ planes
+  constexpr int R = DIM == 3 ? kMarchRows : 1;
+  int i, j, k0, k1;
   if (DIM == 3) {
-    const Column c = march_column(tl, n);
+    const Column c = march_column(tl, n, R);
     i = c.i;
     j = c.j;
     k0 = c.k0;
@@ -385,13 +455,17 @@ __global__ __launch_bounds__(kBlock) void k_jacobi0_rup(LevelDev<T> L, const T* 
   // b_old and q read, b and x_out written; faces once per launch
   count_bytes_tile(tl, ctr, (unsigned long long)L.N * sizeof(T) * (4 + (VAR && sys == 0 ? DIM : 0)));
   double rr = 0.0;
-  if (i < n && j < n) {
+  if (i < n) {
     for (int k = k0; k < k1; ++k) {
-      const long long p = ((long long)k * n + j) * n + i;
-      const T bv = bold[off + p] - a * q[off + p];
-      bout[off + p] = bv;
-      xout[off + p] = omega * bv / diag_pt<T, DIM, VAR>(L, i, j, k, s);
-      rr += (double)bv * (double)bv;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (j + r >= n) continue;
+        const long long p = ((long long)k * n + j + r) * n + i;
+        const T bv = bold[off + p] - a * q[off + p];
+        bout[off + p] = bv;
+        xout[off + p] = omega * bv / diag_pt<T, DIM, VAR>(L, i, j + r, k, s);
+        rr += (double)bv * (double)bv;
+      }
     }
   }
   write_partial_tile(tl, partial, sys, rr);
@@ -524,7 +598,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong3(LevelDev<T> Lc, LevelDev<T>
   if (!active[sys]) return;
   count_bytes_tile(tl, ctr, (unsigned long long)Lf.N * sizeof(T) * 2 + (unsigned long long)Lc.N * sizeof(T));
   const int nf = Lf.n, nc = Lc.n;
-  const Column c = march_column(tl, nf);
+  const Column c = march_column(tl, nf, 1);
   if (c.i >= nf || c.j >= nf) return;
   int ia, ib, ja, jb;
   T wia, wib, wja, wjb;
@@ -560,68 +634,101 @@ __global__ __launch_bounds__(kBlock) void k_prolong3(LevelDev<T> Lc, LevelDev<T>
   }
 }
 
-// b_c = R (b - (A+s) x): one thread per coarse column (I, J) over kMarchZ coarse
-// planes.  The fine residual is formed on the 3 x 3 fine columns under the
-// coarse column, plane by plane (each fine column keeps x at the planes below
-// and at the current one in registers); each fine plane's in-plane weighted
-// sum is formed once and shared by the two coarse planes that weight it.
+// b_c = R (b - (A+s) x) in 3D.  A workgroup owns kRcx x kRcy coarse columns over
+// kMarchZ coarse planes, i.e. the (2 kRcx + 1) x (2 kRcy + 1) fine columns under
+// them.  Plane by plane, each fine point's residual is formed once (every
+// thread keeps x of its fine points at the plane below and at the current one
+// in registers) and put in LDS; each coarse column then takes the weighted
+// 3 x 3 sum of its plane, and the weighted sums of fine planes 2K, 2K+1, 2K+2
+// give coarse plane K (plane 2K+2 is shared with coarse plane K+1).
+constexpr int kRcx = 32, kRcy = 8;
+constexpr int kRfx = 2 * kRcx + 1, kRfy = 2 * kRcy + 1, kRfn = kRfx * kRfy;
+
+static_assert(kRcx * kRcy == 256, "one coarse column per thread");
+
 template <typename T, bool VAR>
-__global__ __launch_bounds__(kBlock) void k_restrict3(LevelDev<T> Lf, LevelDev<T> Lc, const T* __restrict__ b,
-                                                      const T* __restrict__ x, T* __restrict__ bc,
-                                                      const T* __restrict__ shift, const int* __restrict__ active,
-                                                      unsigned long long* __restrict__ ctr) {
+__global__ __launch_bounds__(256) void k_restrict3(LevelDev<T> Lf, LevelDev<T> Lc, const T* __restrict__ b,
+                                                   const T* __restrict__ x, T* __restrict__ bc,
+                                                   const T* __restrict__ shift, const int* __restrict__ active,
+                                                   unsigned long long* __restrict__ ctr) {
+  constexpr int PER = (kRfn + 255) / 256;
+  __shared__ T rb[kRfn];
   const Tile tl = block_tile();
   const int sys = tl.z;
   if (!active[sys]) return;
   count_bytes_tile(tl, ctr, (unsigned long long)Lc.N * sizeof(T) * (2 * 8 + 1 + (VAR && sys == 0 ? 3 * 8 : 0)));
   const int nf = Lf.n, nc = Lc.n;
-  const Column c = march_column(tl, nc);
-  if (c.i >= nc || c.j >= nc) return;
+  const int yt = (nc + kRcy - 1) / kRcy;
+  const int kc = tl.y / yt;
+  const int I0 = tl.x * kRcx, J0 = (tl.y - kc * yt) * kRcy;
+  const int K0 = kc * kMarchZ, K1 = min(K0 + kMarchZ, nc);
+  const int tid = threadIdx.x;
   const T s = shift[sys];
   const T* bs = b + (long long)sys * Lf.N;
   const T* xs = x + (long long)sys * Lf.N;
   const long long nnf = (long long)nf * nf;
-  const int fi0 = 2 * c.i, fj0 = 2 * c.j;   // the 3 x 3 fine columns: fi0 .. fi0 + 2, fj0 .. fj0 + 2
-  T xm[9], xc0[9];                          // x at the fine plane below and at the current fine plane
-  int fk = 2 * c.k0;
+  int fk = 2 * K0;
+  T xm[PER], xc0[PER];   // x at the fine plane below and at the current one, per owned fine point
 #pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    const long long col = (long long)(fj0 + q / 3) * nf + (fi0 + q % 3);
-    const long long p = fk * nnf + col;
-    const T xb = xs[fk > 0 ? p - nnf : p];
-    xm[q] = fk > 0 ? xb : T(0);
-    xc0[q] = xs[p];
+  for (int u = 0; u < PER; ++u) {
+    const int q = tid + 256 * u;
+    const int fy = q / kRfx, fx = q - fy * kRfx;
+    const int fi = 2 * I0 + fx, fj = 2 * J0 + fy;
+    xm[u] = T(0);
+    xc0[u] = T(0);
+    if (q < kRfn && fi < nf && fj < nf) {
+      const long long p = fk * nnf + (long long)fj * nf + fi;
+      const T xb = xs[fk > 0 ? p - nnf : p];
+      xm[u] = fk > 0 ? xb : T(0);
+      xc0[u] = xs[p];
+    }
   }
-  // the weighted in-plane sum of the residual on fine plane fk; advances the registers
+  const int ci = tid % kRcx, cj = tid / kRcx;
+  // the residual on fine plane fk (into LDS), then this coarse column's
+  // weighted in-plane sum of it; advances fk and the registers
   auto rplane = [&]() -> T {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int q = tid + 256 * u;
+      const int fy = q / kRfx, fx = q - fy * kRfx;
+      const int fi = 2 * I0 + fx, fj = 2 * J0 + fy;
+      if (q < kRfn) {
+        T r = T(0);
+        if (fi < nf && fj < nf) {
+          const long long p = fk * nnf + (long long)fj * nf + fi;
+          const PlaneNb o = plane_nb(fi, fj, nf);
+          const T xa = xs[fk + 1 < nf ? p + nnf : p];
+          const T xl = xs[p + o.l], xr = xs[p + o.r], xd = xs[p + o.d], xu = xs[p + o.u];
+          const T bv = bs[p];
+          const T above = fk + 1 < nf ? xa : T(0);
+          r = bv - apply_col3<T, VAR>(Lf, fi, fj, fk, p, xc0[u], o.l ? xl : T(0), o.r ? xr : T(0),
+                                      o.d ? xd : T(0), o.u ? xu : T(0), xm[u], above, s, nullptr);
+          xm[u] = xc0[u];
+          xc0[u] = above;
+        }
+        rb[q] = r;
+      }
+    }
+    __syncthreads();
     const T wt[3] = {T(0.25), T(0.5), T(0.25)};
     T acc = T(0);
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
       const int di = q % 3, dj = q / 3;
-      const int fi = fi0 + di, fj = fj0 + dj;
-      const long long p = fk * nnf + (long long)fj * nf + fi;
-      const PlaneNb o = plane_nb(fi, fj, nf);
-      const T xa = xs[fk + 1 < nf ? p + nnf : p];
-      const T xl = xs[p + o.l], xr = xs[p + o.r], xd = xs[p + o.d], xu = xs[p + o.u];
-      const T bv = bs[p];
-      const T above = fk + 1 < nf ? xa : T(0);
-      const T r = bv - apply_col3<T, VAR>(Lf, fi, fj, fk, p, xc0[q], o.l ? xl : T(0), o.r ? xr : T(0),
-                                           o.d ? xd : T(0), o.u ? xu : T(0), xm[q], above, s, nullptr);
-      acc += wt[dj] * wt[di] * r;
-      xm[q] = xc0[q];
-      xc0[q] = above;
+      acc += wt[dj] * wt[di] * rb[(2 * cj + dj) * kRfx + 2 * ci + di];
     }
+    __syncthreads();
     ++fk;
     return acc;
   };
-  T* bcs = bc + (long long)sys * Lc.N;
-  const long long col_c = (long long)c.j * nc + c.i, ncc = (long long)nc * nc;
+  const bool mine = I0 + ci < nc && J0 + cj < nc;
+  T* bcs = bc + (long long)sys * Lc.N + ((long long)(J0 + cj) * nc + (I0 + ci));
+  const long long ncc = (long long)nc * nc;
   T rlo = rplane();   // fine plane 2 K0
-  for (int K = c.k0; K < c.k1; ++K) {
+  for (int K = K0; K < K1; ++K) {
     const T rmid = rplane();   // 2K + 1
     const T rhi = rplane();    // 2K + 2
-    bcs[K * ncc + col_c] = T(0.25) * rlo + T(0.5) * rmid + T(0.25) * rhi;
+    if (mine) bcs[K * ncc] = T(0.25) * rlo + T(0.5) * rmid + T(0.25) * rhi;
     rlo = rhi;
   }
 }
@@ -1126,8 +1233,9 @@ __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, con
 // iteration, deferred to this pass which reads p_old anyway.  alpha == 0 marks
 // "nothing pending" (first iteration); p_old is then not used.
 //
-// 3D version, marching along z: p_new = z + beta p_old is formed once per
-// point; the column's values below and at the point stay in registers.
+// 3D version, marching along z with kMarchRows rows per thread: p_new =
+// z + beta p_old is formed once per point; the rows' values below and at the
+// point stay in registers.
 template <typename T, bool VAR, bool XUP>
 __global__ __launch_bounds__(kBlock) void k_spmv_p3(LevelDev<T> L, const T* __restrict__ z, const T* __restrict__ pold,
                                                     T* __restrict__ pnew, T* __restrict__ q,
@@ -1135,6 +1243,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p3(LevelDev<T> L, const T* __re
                                                     const int* __restrict__ active, double* __restrict__ partial,
                                                     unsigned long long* __restrict__ ctr, Fin fin,
                                                     T* __restrict__ x, const double* __restrict__ alpha) {
+  constexpr int R = kMarchRows;
   const Tile tl = block_tile();
   const int sys = tl.z;
   if (!active[sys]) return;
@@ -1143,42 +1252,64 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p3(LevelDev<T> L, const T* __re
   count_bytes_tile(tl, ctr, (unsigned long long)L.N * sizeof(T) *
                                 ((bt == T(0) ? 3 : 4) + (XUP && ap != T(0) ? 2 : 0) + (VAR && sys == 0 ? 3 : 0)));
   const int n = L.n;
-  const Column c = march_column(tl, n);
+  const Column c = march_column(tl, n, R);
   double dot = 0.0;
   if (c.i < n && c.j < n) {
     const long long off = (long long)sys * L.N, nn = (long long)n * n;
-    const long long col = (long long)c.j * n + c.i;
+    const Rows<R> w(c.i, c.j, n);
     const T* zs = z + off;
     // beta = 0 (first iteration): p_old may hold anything, so read z in its place
     const T* pe = bt == T(0) ? zs : pold + off;
     const T s = shift[sys];
-    const PlaneNb o = plane_nb(c.i, c.j, n);
-    const long long p0 = c.k0 * nn + col;
-    const long long pb = c.k0 > 0 ? p0 - nn : p0;
-    const T zb = zs[pb], eb = pe[pb], zc = zs[p0], ec = pe[p0];
-    T below = c.k0 > 0 ? zb + bt * eb : T(0);
-    T centre = zc + bt * ec;
-    T pold_c = ec;   // p_old at the point (used by the deferred update, alpha != 0 => beta != 0)
+    T below[R], centre[R], pold_c[R];   // pold_c: p_old at the point (alpha != 0 => beta != 0)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const long long p0 = c.k0 * nn + w.col[r];
+      const long long pb = c.k0 > 0 ? p0 - nn : p0;
+      const T zb = zs[pb], eb = pe[pb], zc = zs[p0], ec = pe[p0];
+      below[r] = c.k0 > 0 ? zb + bt * eb : T(0);
+      centre[r] = zc + bt * ec;
+      pold_c[r] = ec;
+    }
     for (int k = c.k0; k < c.k1; ++k) {
-      const long long p = k * nn + col;
-      const long long pa = k + 1 < n ? p + nn : p;
+      const long long pk = k * nn;
       // every load of the plane first, then the arithmetic
-      const T za = zs[pa], ea = pe[pa];
-      const T zl = zs[p + o.l], el = pe[p + o.l], zr = zs[p + o.r], er = pe[p + o.r];
-      const T zd = zs[p + o.d], ed = pe[p + o.d], zu = zs[p + o.u], eu = pe[p + o.u];
-      T xv = T(0);
-      if (XUP) xv = x[off + p];
-      const T above = k + 1 < n ? za + bt * ea : T(0);
-      const T lv = o.l ? zl + bt * el : T(0), rv = o.r ? zr + bt * er : T(0);
-      const T dv = o.d ? zd + bt * ed : T(0), uv = o.u ? zu + bt * eu : T(0);
-      const T qv = apply_col3<T, VAR>(L, c.i, c.j, k, p, centre, lv, rv, dv, uv, below, above, s, nullptr);
-      pnew[off + p] = centre;
-      q[off + p] = qv;
-      if (XUP && ap != T(0)) x[off + p] = xv + ap * pold_c;
-      dot += (double)centre * (double)qv;
-      below = centre;
-      centre = above;
-      pold_c = ea;
+      T za[R], ea[R], zl[R], el[R], zr[R], er[R], xv[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const long long p = pk + w.col[r];
+        const long long pa = k + 1 < n ? p + nn : p;
+        za[r] = zs[pa];
+        ea[r] = pe[pa];
+        zl[r] = zs[p + w.il];
+        el[r] = pe[p + w.il];
+        zr[r] = zs[p + w.ir];
+        er[r] = pe[p + w.ir];
+        xv[r] = XUP ? x[off + p] : T(0);
+      }
+      const T zd = zs[pk + w.col_d], ed = pe[pk + w.col_d], zu = zs[pk + w.col_u], eu = pe[pk + w.col_u];
+      const T hd = zd + bt * ed, hu = zu + bt * eu;
+      T above[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) above[r] = k + 1 < n ? za[r] + bt * ea[r] : T(0);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (!w.valid[r]) continue;
+        const long long p = pk + w.col[r];
+        const T lv = w.il ? zl[r] + bt * el[r] : T(0), rv = w.ir ? zr[r] + bt * er[r] : T(0);
+        const T qv = apply_col3<T, VAR>(L, c.i, c.j + r, k, p, centre[r], lv, rv, w.down(r, centre, hd),
+                                        w.up(r, centre, hu), below[r], above[r], s, nullptr);
+        pnew[off + p] = centre[r];
+        q[off + p] = qv;
+        if (XUP && ap != T(0)) x[off + p] = xv[r] + ap * pold_c[r];
+        dot += (double)centre[r] * (double)qv;
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        below[r] = centre[r];
+        centre[r] = above[r];
+        pold_c[r] = ea[r];
+      }
     }
   }
   write_partial_tile(tl, partial, sys, dot);
@@ -1411,7 +1542,7 @@ __global__ __launch_bounds__(kBlock) void k_residual64(LevelDev<double> L, const
   write_partial_tile(tl, partial, sys, rr);
 }
 
-// k_residual64 in 3D, marching along z
+// k_residual64 in 3D, marching along z with kMarchRows rows per thread
 template <bool VAR>
 __global__ __launch_bounds__(kBlock) void k_residual64_3(LevelDev<double> L, const double* __restrict__ f,
                                                          const double* __restrict__ x64, float* __restrict__ e,
@@ -1419,38 +1550,60 @@ __global__ __launch_bounds__(kBlock) void k_residual64_3(LevelDev<double> L, con
                                                          const int* __restrict__ active64, int nrhs,
                                                          double* __restrict__ partial,
                                                          unsigned long long* __restrict__ ctr) {
+  constexpr int R = kMarchRows;
   const Tile tl = block_tile();
   const int sys = tl.z;
   if (!active64[sys]) return;
   count_bytes_tile(tl, ctr, (unsigned long long)L.N * (8 + 8 + 4 + 4 + (VAR && sys == 0 ? 8 * 3 : 0)));
   const int n = L.n;
-  const Column c = march_column(tl, n);
+  const Column c = march_column(tl, n, R);
   double rr = 0.0;
   if (c.i < n && c.j < n) {
     const long long off = (long long)sys * L.N, nn = (long long)n * n;
-    const long long col = (long long)c.j * n + c.i;
+    const Rows<R> w(c.i, c.j, n);
     const double* xs = x64 + off;
     const double* fs = f + (long long)(sys % nrhs) * L.N;
     const double s = shift[sys];
-    const PlaneNb o = plane_nb(c.i, c.j, n);
-    const long long p0 = c.k0 * nn + col;
-    const double xb0 = xs[c.k0 > 0 ? p0 - nn : p0];
-    double below = c.k0 > 0 ? xb0 : 0.0;
-    double centre = xs[p0];
+    double below[R], centre[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const long long p0 = c.k0 * nn + w.col[r];
+      const double xb0 = xs[c.k0 > 0 ? p0 - nn : p0];
+      below[r] = c.k0 > 0 ? xb0 : 0.0;
+      centre[r] = xs[p0];
+    }
     for (int k = c.k0; k < c.k1; ++k) {
-      const long long p = k * nn + col;
-      const double xa = xs[k + 1 < n ? p + nn : p];
-      const double xl = xs[p + o.l], xr = xs[p + o.r], xd = xs[p + o.d], xu = xs[p + o.u];
-      const double fv = fs[p];
-      const double above = k + 1 < n ? xa : 0.0;
-      const double ax = apply_col3<double, VAR>(L, c.i, c.j, k, p, centre, o.l ? xl : 0.0, o.r ? xr : 0.0,
-                                                o.d ? xd : 0.0, o.u ? xu : 0.0, below, above, s, nullptr);
-      const double rv = fv - ax;
-      r32[off + p] = (float)rv;
-      e[off + p] = 0.0f;
-      rr += rv * rv;
-      below = centre;
-      centre = above;
+      const long long pk = k * nn;
+      double xa[R], xl[R], xr[R], fv[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const long long p = pk + w.col[r];
+        xa[r] = xs[k + 1 < n ? p + nn : p];
+        xl[r] = xs[p + w.il];
+        xr[r] = xs[p + w.ir];
+        fv[r] = fs[p];
+      }
+      const double hd = xs[pk + w.col_d], hu = xs[pk + w.col_u];
+      double above[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) above[r] = k + 1 < n ? xa[r] : 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (!w.valid[r]) continue;
+        const long long p = pk + w.col[r];
+        const double ax = apply_col3<double, VAR>(L, c.i, c.j + r, k, p, centre[r], w.il ? xl[r] : 0.0,
+                                                  w.ir ? xr[r] : 0.0, w.down(r, centre, hd), w.up(r, centre, hu),
+                                                  below[r], above[r], s, nullptr);
+        const double rv = fv[r] - ax;
+        r32[off + p] = (float)rv;
+        e[off + p] = 0.0f;
+        rr += rv * rv;
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        below[r] = centre[r];
+        centre[r] = above[r];
+      }
     }
   }
   write_partial_tile(tl, partial, sys, rr);
@@ -1654,10 +1807,10 @@ static inline dim3 point_grid(int dim, int n, int nsys) {
   return dim3(xt, yt * (dim == 3 ? n : 1), nsys);
 }
 
-// 3D kernels marching along z: kMarchZ planes per workgroup
-static inline dim3 march_grid(int n, int nsys) {
+// 3D kernels marching along z: kMarchZ planes per workgroup, `rows` rows per thread
+static inline dim3 march_grid(int n, int nsys, int rows) {
   const int xt = (n + kTileX - 1) / kTileX;
-  const int yt = (n + kTileY - 1) / kTileY;
+  const int yt = (n + kTileY * rows - 1) / (kTileY * rows);
   const int zt = (n + kMarchZ - 1) / kMarchZ;
   return dim3(xt, yt * zt, nsys);
 }
@@ -1665,7 +1818,7 @@ static inline dim3 march_grid(int n, int nsys) {
 // the smoothing sweeps, the stencil product and the FP64 residual (the kernels
 // that write per-block partials outside the fused 2D path)
 static inline dim3 stencil_grid(int dim, int n, int nsys) {
-  return dim == 3 ? march_grid(n, nsys) : point_grid(dim, n, nsys);
+  return dim == 3 ? march_grid(n, nsys, kMarchRows) : point_grid(dim, n, nsys);
 }
 
 int stencil_blocks(int dim, int n) {
@@ -1764,9 +1917,10 @@ void Launch<T>::restrict_residual(int dim, bool var, const LevelDev<T>& Lf, cons
                                   const T* x, T* bc, const T* shift, const int* active, int nsys, hipStream_t st,
                                   unsigned long long* ctr) {
   if (dim == 3) {
-    const dim3 g3 = march_grid(Lc.n, nsys), blk3(kTileX, kTileY);
-    if (var) hipLaunchKernelGGL((k_restrict3<T, true>), g3, blk3, 0, st, Lf, Lc, b, x, bc, shift, active, ctr);
-    else hipLaunchKernelGGL((k_restrict3<T, false>), g3, blk3, 0, st, Lf, Lc, b, x, bc, shift, active, ctr);
+    const int nc = Lc.n;
+    const dim3 g3((nc + kRcx - 1) / kRcx, ((nc + kRcy - 1) / kRcy) * ((nc + kMarchZ - 1) / kMarchZ), nsys);
+    if (var) hipLaunchKernelGGL((k_restrict3<T, true>), g3, dim3(256), 0, st, Lf, Lc, b, x, bc, shift, active, ctr);
+    else hipLaunchKernelGGL((k_restrict3<T, false>), g3, dim3(256), 0, st, Lf, Lc, b, x, bc, shift, active, ctr);
     return;
   }
   const dim3 g = point_grid(dim, Lc.n, nsys), blk(kTileX, kTileY);
@@ -1782,8 +1936,8 @@ void Launch<T>::prolong_add(int dim, const LevelDev<T>& Lc, const LevelDev<T>& L
     hipLaunchKernelGGL((k_prolong<T, 2>), point_grid(2, Lf.n, nsys), dim3(kTileX, kTileY), 0, st, Lc, Lf, xc, xf,
                        active, ctr);
   else
-    hipLaunchKernelGGL((k_prolong3<T>), march_grid(Lf.n, nsys), dim3(kTileX, kTileY), 0, st, Lc, Lf, xc, xf, active,
-                       ctr);
+    hipLaunchKernelGGL((k_prolong3<T>), march_grid(Lf.n, nsys, 1), dim3(kTileX, kTileY), 0, st, Lc, Lf, xc, xf,
+                       active, ctr);
 }
 
 template <typename T>
@@ -1841,7 +1995,7 @@ void Launch<T>::spmv_p(int dim, bool var, const LevelDev<T>& L, const T* z, cons
     });
     return;
   }
-  const dim3 g = march_grid(L.n, nsys), blk(kTileX, kTileY);
+  const dim3 g = march_grid(L.n, nsys, kMarchRows), blk(kTileX, kTileY);
 #define K_SP3(V, X_)                                                                                              \
   hipLaunchKernelGGL((k_spmv_p3<T, V, X_>), g, blk, 0, st, L, z, pold, pnew, q, beta, shift, active, partial, ctr, \
                      fin, x, alpha)

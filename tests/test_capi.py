@@ -81,3 +81,18 @@ def test_tile_variant_count_matches_header():
     src = open(os.path.join(ROOT, "include", "bura.h")).read()
     m = re.search(r"#define BURA_TILE_VARIANTS (\d+)", src)
     assert m and int(m.group(1)) == B.BURA_TILE_VARIANTS
+
+
+def test_slot_argument_marshalling():
+    """Per-rhs terms are laid out row by row, max_terms apart (no GPU needed)."""
+    import paper_1612_04846_amd as B
+    nt, w, s, t = B._slot_arrays(4, [([1.0, 2.0], [0.0, 0.5]), ([3.0], [1.5])], [1e-10, 1e-12])
+    assert list(nt) == [2, 1]
+    assert list(w) == [1.0, 2.0, 0.0, 0.0, 3.0, 0.0, 0.0, 0.0]
+    assert list(s) == [0.0, 0.5, 0.0, 0.0, 1.5, 0.0, 0.0, 0.0]
+    assert list(t) == [1e-10, 1e-12]
+    assert B._slot_arrays(2, [([1.0], [0.0])], None)[3] is None
+    with pytest.raises(ValueError):
+        B._slot_arrays(2, [([1.0, 2.0, 3.0], [0.0, 0.0, 0.0])], None)
+    with pytest.raises(ValueError):
+        B._slot_arrays(2, [([1.0, 2.0], [0.0])], None)
