@@ -8,8 +8,11 @@
 * Variable coefficients (reading): flux form
       (A~ x)_i = h^-2 sum_faces a_f (x_i - x_nb),  x_nb = 0 on the boundary,
   with a_f = 2 a_i a_nb / (a_i + a_nb) the harmonic mean of the nodal values
-  on the (n+2)^d lattice.  Lambda is Gershgorin's bound max_i sum_j |A~_ij|;
-  for constant coefficients it equals 4d/h^2, the paper's own scaling.
+  on the (n+2)^d lattice.  Lambda is Gershgorin's bound max_i sum_j |A~_ij|.
+* Constant coefficients: Lambda = 4d/h^2, the paper's own scaling, for every
+  n.  (Gershgorin's bound equals it for n >= 3; for n <= 2 no node has all its
+  neighbours inside and Gershgorin is smaller.  The closed-form eigenbasis of
+  `spectral` uses 4d/h^2.)
 """
 
 from __future__ import annotations
@@ -69,5 +72,5 @@ def gershgorin_bound(A: sp.spmatrix) -> float:
 def scaled_operator(n: int, dim: int, a_nodes: np.ndarray | None = None):
     """(A, Lambda) with A = A~/Lambda as in eq. (10)."""
     At = unscaled_operator(n, dim, a_nodes)
-    lam = gershgorin_bound(At)
+    lam = 4.0 * dim * (n + 1) ** 2 if a_nodes is None else gershgorin_bound(At)
     return (At / lam).tocsr(), lam

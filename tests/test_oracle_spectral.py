@@ -11,7 +11,7 @@ from conftest import golden_path, oracle_bura
 from oracle import metrics, operators, shifted, spectral
 
 
-@pytest.mark.parametrize("n,dim", [(7, 2), (5, 3), (8, 2)])
+@pytest.mark.parametrize("n,dim", [(7, 2), (5, 3), (8, 2), (1, 2), (2, 2), (1, 3), (2, 3)])
 def test_scaled_laplacian_matches_paper_scaling(n, dim):
     """Section 5.3: A = h^2 A~ / 8 (2D); 3D: h^2/12.  Diagonal 1/2, off-diagonals -1/(4d)."""
     A, lam = operators.scaled_operator(n, dim)
@@ -25,7 +25,16 @@ def test_scaled_laplacian_matches_paper_scaling(n, dim):
     assert np.allclose(Ad, Ad.T)
 
 
-@pytest.mark.parametrize("n,dim", [(7, 2), (5, 3)])
+@pytest.mark.parametrize("n,dim", [(3, 2), (4, 3), (9, 2)])
+def test_paper_scaling_is_gershgorin_from_n_3(n, dim):
+    """For n >= 3 an interior node with all neighbours inside attains Gershgorin's
+    bound, which then equals the paper's 4d/h^2; below that it is smaller."""
+    At = operators.unscaled_operator(n, dim)
+    assert operators.gershgorin_bound(At) == pytest.approx(4 * dim * (n + 1) ** 2, rel=1e-14)
+    assert operators.gershgorin_bound(operators.unscaled_operator(2, dim)) < 4 * dim * 3 ** 2
+
+
+@pytest.mark.parametrize("n,dim", [(7, 2), (5, 3), (1, 2), (2, 2), (1, 3), (2, 3)])
 def test_eigenvalues_against_dense_eigh(n, dim):
     A, _ = operators.scaled_operator(n, dim)
     w = np.linalg.eigvalsh(A.toarray())
