@@ -391,6 +391,9 @@ int build_levels(bura_plan_t P, const bura_grid_t* g) {
           }
         }
     gb /= h * h;
+    // constant coefficients: the paper's scaling 4d/h^2 (h^2/8 in 2D) for every
+    // n; Gershgorin's bound equals it for n >= 3 and is smaller below that
+    if (!P->var) gb = 4.0 * dim / (h * h);
   }
   if (g->lambda_upper > 0.0) {
     P->lambda = g->lambda_upper;   // caller's bound (cannot be verified cheaply)
@@ -484,8 +487,11 @@ void choose_lds(bura_plan_t P, size_t elem) {
       return;
     }
   }
-  P->lc = L - 1;
-  P->lds_bytes = 3 * (size_t)P->lev[L - 1].N * elem;
+  // the coarsest level alone does not fit (coarsening stopped early at a
+  // large even n, e.g. 201 -> 100): no exact coarse solve is possible, so the
+  // plan falls back to Jacobi-preconditioned CG on the fine level
+  P->lc = -1;
+  P->lds_bytes = 0;
 }
 
 template <typename T>
