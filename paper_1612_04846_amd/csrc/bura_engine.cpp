@@ -1212,7 +1212,7 @@ std::map<std::string, TileChoice> g_tile_cache;
 
 constexpr int kTuneMinN = 255;
 constexpr int kTuneRounds = 2;        // interleaved timings per variant (the minimum counts)
-constexpr float kTuneMargin = 0.005f; // a variant replaces the default only if this much faster
+constexpr float kTuneMargin = 0.01f;  // a variant replaces the default only if this much faster
 
 int tune_tiles(bura_plan_t P) {
   if (P->dim != 2) return BURA_OK;   // the 3D kernels have one shape
