@@ -935,10 +935,15 @@ struct RegionFaces {
 // Tile shapes of the 2D kernels, one row per launch-shape variant (variant 0
 // is the default; a plan may time the others at creation and keep the
 // fastest): coarse points per block of the down kernel, fine points per block
-// of the up kernel, rows per thread of the stencil product.
+// of the up kernel, rows per thread and threads along x (of 256) of the
+// stencil product.  The stencil product's default is 128 columns wide: each
+// row of a tile then spans 8 cache lines of 128 bytes (FP64) plus one line of
+// halo on each side, against 4 plus 2 at 64 columns, which took 3.5 % off its
+// time at 1023^2.  The LDS-staged down and up kernels were slower at 128 fine
+// columns (more LDS per workgroup, fewer resident workgroups).
 constexpr int kDownTile[kTileVariants][2] = {{32, 8}, {32, 4}, {32, 12}};
 constexpr int kUpTile[kTileVariants][2] = {{64, 16}, {64, 8}, {64, 24}};
-constexpr int kSpmvRows[kTileVariants] = {4, 2, 8};
+constexpr int kSpmvTile[kTileVariants][2] = {{4, 128}, {2, 64}, {8, 128}};
 
 // RUP: the right-hand side is first advanced by the PCG step, b = b_old - alpha q
 // (read from b, written to bout on the owned points, |b|^2 into partial), so the
@@ -1324,10 +1329,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p3(LevelDev<T> L, const T* __re
 }
 
 // 2D version: each thread owns R consecutive rows of one column (a workgroup
-// covers kTileX x kTileY*R points), so the column's p_new values are formed
+// of TX x (256 / TX) threads covers TX x (256 / TX) R points), so the column's p_new values are formed
 // once and reused by the rows above and below; only the left/right neighbours
 // are extra loads.
-template <typename T, bool VAR, bool XUP, int R>
+template <typename T, bool VAR, bool XUP, int R, int TX>
 __global__ __launch_bounds__(kBlock) void k_spmv_p2(LevelDev<T> L, const T* __restrict__ z, const T* __restrict__ pold,
                                                     T* __restrict__ pnew, T* __restrict__ q,
                                                     const double* __restrict__ beta, const T* __restrict__ shift,
@@ -1342,8 +1347,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p2(LevelDev<T> L, const T* __re
   count_bytes_tile(tl, ctr, (unsigned long long)L.N * sizeof(T) *
                                 ((bt == T(0) ? 3 : 4) + (XUP && ap != T(0) ? 2 : 0) + (VAR && sys == 0 ? 2 : 0)));
   const int n = L.n;
-  const int i = tl.x * kTileX + threadIdx.x;
-  const int j0 = (tl.y * kTileY + threadIdx.y) * R;
+  const int i = tl.x * TX + threadIdx.x;
+  const int j0 = (tl.y * (kBlock / TX) + threadIdx.y) * R;
   const long long off = (long long)sys * L.N;
   double dot = 0.0;
   if (i < n && j0 < n) {
@@ -1833,10 +1838,11 @@ int stencil_blocks(int dim, int n) {
   return (int)(g.x * g.y);
 }
 
-// the 2D stencil product: kTileX x (kTileY * R) points per workgroup
+// the 2D stencil product: TX x ((256 / TX) R) points per workgroup
 static inline dim3 spmv2_grid(int n, int nsys, int tv) {
-  const int rows = kTileY * kSpmvRows[tile_variant(tv)];
-  return dim3((n + kTileX - 1) / kTileX, (n + rows - 1) / rows, nsys);
+  const int tx = kSpmvTile[tile_variant(tv)][1];
+  const int rows = (kBlock / tx) * kSpmvTile[tile_variant(tv)][0];
+  return dim3((n + tx - 1) / tx, (n + rows - 1) / rows, nsys);
 }
 
 int spmv_blocks(int dim, int n, int tv) {
@@ -1987,12 +1993,13 @@ void Launch<T>::spmv_p(int dim, bool var, const LevelDev<T>& L, const T* z, cons
                        hipStream_t st, unsigned long long* ctr, Fin fin, T* x, const double* alpha, int tv) {
   const bool xup = x != nullptr;
   if (dim == 2) {
-    const dim3 g2 = spmv2_grid(L.n, nsys, tv), blk2(kTileX, kTileY);
+    const dim3 g2 = spmv2_grid(L.n, nsys, tv);
     with_tile(tv, [&](auto v) {
-      constexpr int R = kSpmvRows[decltype(v)::value];
+      constexpr int R = kSpmvTile[decltype(v)::value][0], TX = kSpmvTile[decltype(v)::value][1];
+      const dim3 blk2(TX, kBlock / TX);
 #define K_SP2(V, X_) \
-  hipLaunchKernelGGL((k_spmv_p2<T, V, X_, R>), g2, blk2, 0, st, L, z, pold, pnew, q, beta, shift, active, partial, \
-                     ctr, fin, x, alpha)
+  hipLaunchKernelGGL((k_spmv_p2<T, V, X_, R, TX>), g2, blk2, 0, st, L, z, pold, pnew, q, beta, shift, active, \
+                     partial, ctr, fin, x, alpha)
       if (var) {
         if (xup) K_SP2(true, true); else K_SP2(true, false);
       } else {
