@@ -221,21 +221,35 @@ def roofline(kstats):
     return roof, table
 
 
+# position of each fine-level 2D kernel class's launch shape in a plan's tiles
+# (bura_plan_tiles: stencil product, then down and up per level, finest first)
+TILE_INDEX = {"spmv": 0, "down_fine": 1, "up_fine": 2}
+
+
 def counter_traffic(workload, kclass, tiles):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it was
-    taken on the current kernel source with the same tile shapes (else None)."""
+    taken on the current kernel source with the same launch shape of that kernel
+    (every plan of the bench line using the summary's shape; classes without
+    shape variants need the same tiles throughout), else None."""
     import glob
     import hashlib
     src = os.path.join(ROOT, "paper_1612_04846_amd", "csrc", "bura_kernels.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    idx = TILE_INDEX.get(kclass)
     for path in glob.glob(os.path.join(ROOT, "profiles", "*_hbm_counters.md")):
         kv = {}
         for line in open(path):
             if ":" in line and not line.startswith(("#", "-", "`", " ")):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-        if kv.get("workload") == workload and kv.get("kernel_class") == kclass and \
-                kv.get("kernel_source_sha256_prefix") == sha and kv.get("tiles") == json.dumps(tiles):
+        if kv.get("workload") != workload or kv.get("kernel_class") != kclass or \
+                kv.get("kernel_source_sha256_prefix") != sha:
+            continue
+        if idx is not None and tiles and all(len(t) > idx for t in tiles):
+            same = all(str(t[idx]) == kv.get("kernel_tile") for t in tiles)
+        else:
+            same = kv.get("tiles") == json.dumps(tiles)
+        if same:
             return int(kv["traffic_bytes_per_launch"])
     return None
 

@@ -103,8 +103,9 @@ typedef struct {
                           device footprint would exceed this many bytes                 */
   int autotune;        /* 2D multigrid plans: 0 = default tile shapes; 1 = plan creation
                           times every tile-shape variant of the stencil product and of
-                          each level's fused kernels on the plan's buffers and keeps the
-                          fastest (cached per shape in the process; see bura_plan_tiles) */
+                          each level's fused kernels on the plan's buffers (whole solves
+                          in the plan's schedule) and keeps the fastest (cached per shape
+                          in the process; see bura_plan_tiles)                           */
 } bura_opts_t;
 
 /* Per-solve report (host struct filled by solve/poll). */
@@ -285,7 +286,11 @@ int bura_plan_apply(bura_plan_t plan, double shift, const double* x_dev, double*
  * and out[2 + 2l] for the fused down and up kernels of level l, for each of
  * the plan's levels with fused kernels; *len = 1 + 2 * (those levels) (0 for
  * a 3D plan, whose kernels have one shape).  With out == NULL only *len is
- * written.  BURA_EINVAL if max_len < *len. */
+ * written.  BURA_EINVAL if max_len < *len.  Untuned, every entry is 0 except
+ * the down kernel of a level whose default tile (64 x 6 coarse points) would
+ * give one launch fewer than 1024 workgroups over the systems that share it
+ * (all of them; one pole's right-hand sides in the per-pole schedule; the
+ * largest stage of a sequential form): that level takes variant 1 (32 x 8). */
 int bura_plan_tiles(bura_plan_t plan, int* out, int max_len, int* len);
 
 /* Set the variants (layout as bura_plan_tiles, len must equal its *len, each

@@ -1188,17 +1188,17 @@ using LateTerms = std::function<int(double lambda, Terms& t)>;
 // 2D stencil product and of each level's fused down and up kernels (levels
 // with n >= kTuneMinN; smaller ones are launch-bound and keep the default).
 // Each knob in turn (coordinate descent from the defaults, fine level first)
-// takes the variant for which a whole batched solve of the plan -- every
-// system, a fixed pseudo-random right-hand side, to the plan's tolerance --
-// runs fastest.  Timing real solves takes in what a proxy misses: systems
+// takes the variant for which a whole solve of the plan -- every system, in
+// the plan's schedule, a fixed pseudo-random right-hand side, to the plan's
+// tolerance -- runs fastest.  Timing real solves takes in what a proxy misses: systems
 // converging at different iterations (their blocks still launch and exit),
 // the alternating buffers, the scalar updates.  (Timed as a few PCG iterations
 // with every system active, the tuner picked a 2-row stencil product that is
 // 8 % slower in the 2048-system solves.)  The variants are timed in
 // interleaved rounds, each by its fastest round, and one must beat the default
-// by kTuneMargin.  The solves run without graph capture (captured graphs fix
+// (set_default_tiles) by kTuneMargin.  The solves run without graph capture (captured graphs fix
 // the launch shapes).  The choice is cached per (precision, grid,
-// coefficients or not, sweeps, systems) for the life of the process.  The
+// coefficients or not, sweeps, systems, schedule) for the life of the process.  The
 // variants compute the same value at every point; only the grouping of the
 // per-block partial sums of the dot products differs.
 // ---------------------------------------------------------------------------
@@ -1214,12 +1214,34 @@ constexpr int kTuneMinN = 255;
 constexpr int kTuneRounds = 2;        // interleaved timings per variant (the minimum counts)
 constexpr float kTuneMargin = 0.01f;  // a variant replaces the default only if this much faster
 
+// Systems that share one launch: all of them, one pole's right-hand sides
+// (per-pole schedule), or the largest stage (sequential forms).
+long long launch_systems(const bura_plan_t P) {
+  const long long R = P->opts.nrhs_max;
+  if (!P->stages.empty()) {
+    long long m = 1;
+    for (const Stage& g : P->stages) m = std::max(m, (long long)(g.te - g.tb) * R);
+    return m;
+  }
+  return P->opts.schedule == BURA_PER_POLE ? R : (long long)P->S;
+}
+
+// The default launch shapes: variant 0, except the down kernel on levels
+// whose launches would make too few workgroups with it (default_down_tile).
+void set_default_tiles(bura_plan_t P) {
+  const long long ns = launch_systems(P);
+  P->tile_spmv = 0;
+  for (size_t l = 0; l < P->tile_down.size(); ++l) P->tile_down[l] = default_down_tile(P->dim, P->lev[l].n, ns);
+  std::fill(P->tile_up.begin(), P->tile_up.end(), 0);
+}
+
 int tune_tiles(bura_plan_t P) {
   if (P->dim != 2) return BURA_OK;   // the 3D kernels have one shape
   const bool mixed = P->opts.precision == BURA_MIXED;
-  char key[160];
-  std::snprintf(key, sizeof(key), "%d/%d/%d/%d/%d/%d/%d/%d", mixed ? 4 : 8, P->dim, P->n, (int)P->var,
-                P->opts.nu_pre, P->opts.nu_post, P->S, (int)P->foldxr);
+  char key[192];
+  std::snprintf(key, sizeof(key), "%d/%d/%d/%d/%d/%d/%d/%d/%d/%d", mixed ? 4 : 8, P->dim, P->n, (int)P->var,
+                P->opts.nu_pre, P->opts.nu_post, P->S, (int)P->foldxr, (int)P->opts.schedule,
+                (int)P->stages.size());
   {
     std::lock_guard<std::mutex> lk(g_tile_mu);
     auto it = g_tile_cache.find(key);
@@ -1251,6 +1273,25 @@ int tune_tiles(bura_plan_t P) {
   const bool graphs = P->use_graphs;
   P->use_graphs = false;
   bool ok = true;
+  // a timed solve follows the plan's schedule (as in do_solve): stage by
+  // stage, pole by pole, or every system in one batch -- a one-system launch
+  // fills the chip differently from a batched one
+  const int R = P->opts.nrhs_max;
+  auto solve_once = [&]() {
+    auto batch = [&](size_t sys0, int nsys) {
+      return mixed ? solve_batch_mixed(P, df, 1, sys0, nsys, false) : solve_batch_fp64(P, df, 1, sys0, nsys, false);
+    };
+    int rc = BURA_OK;
+    if (!P->stages.empty()) {
+      for (size_t si = 0; si < P->stages.size() && rc == BURA_OK; ++si)
+        rc = batch((size_t)P->stages[si].tb * R, (P->stages[si].te - P->stages[si].tb) * R);
+    } else if (P->opts.schedule == BURA_PER_POLE) {
+      for (int j = 0; j < P->nterms && rc == BURA_OK; ++j) rc = batch((size_t)j * R, R);
+    } else {
+      rc = batch(0, P->S);
+    }
+    return rc;
+  };
   auto timed = [&]() {
     float ms = 0.0f;
     // the per-solve counters a solve starts from (as in do_solve)
@@ -1258,8 +1299,7 @@ int tune_tiles(bura_plan_t P) {
     set_flags(P, P->st.total_iters, 0, P->S, 0);
     set_flags(P, P->st.outer, 0, P->S, 0);
     ok = ok && hipEventRecord(e0, st) == hipSuccess;
-    const int rc = ok ? (mixed ? solve_batch_mixed(P, df, 1, 0, P->S, false) : solve_batch_fp64(P, df, 1, 0, P->S, false))
-                      : BURA_EDEVICE;
+    const int rc = ok ? solve_once() : BURA_EDEVICE;
     ok = ok && rc == BURA_OK && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
          hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
     return ms;
@@ -1269,6 +1309,7 @@ int tune_tiles(bura_plan_t P) {
   const bool log = tl_env && tl_env[0] == '1';
   int knob_id = 0;
   auto tune = [&](int* knob) {
+    const int def = *knob;
     float best_of[kTileVariants];
     for (int v = 0; v < kTileVariants; ++v) best_of[v] = 0.0f;
     for (int r = 0; r < kTuneRounds && ok; ++r) {
@@ -1278,18 +1319,16 @@ int tune_tiles(bura_plan_t P) {
         if (r == 0 || ms < best_of[v]) best_of[v] = ms;
       }
     }
-    int best = 0;
-    for (int v = 1; v < kTileVariants; ++v)
-      if (best_of[v] < best_of[best] * (best == 0 ? 1.0f - kTuneMargin : 1.0f)) best = v;
+    int best = def;
+    for (int v = 0; v < kTileVariants; ++v)
+      if (v != best && best_of[v] < best_of[best] * (best == def ? 1.0f - kTuneMargin : 1.0f)) best = v;
     *knob = best;
     if (log)
       std::fprintf(stderr, "[bura tune] knob %d: %.4f %.4f %.4f ms -> %d\n", knob_id, best_of[0], best_of[1],
                    best_of[2], best);
     ++knob_id;
   };
-  P->tile_spmv = 0;
-  std::fill(P->tile_down.begin(), P->tile_down.end(), 0);
-  std::fill(P->tile_up.begin(), P->tile_up.end(), 0);
+  set_default_tiles(P);
   timed();   // warm-up (clocks, caches, first-touch)
   tune(&P->tile_spmv);
   for (int l = 0; l < P->lc && fused_ok(P) && ok; ++l) {
@@ -1371,6 +1410,7 @@ int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_p
   P->E = terms.E;
   P->stages = terms.stages;
   P->S = nterms * o.nrhs_max;
+  set_default_tiles(P);
   const bool mixed = o.precision == BURA_MIXED;
   choose_lds(P, mixed ? 4 : 8);
   {

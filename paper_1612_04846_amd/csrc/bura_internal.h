@@ -164,6 +164,9 @@ int flat_blocks(long long N);        // blocks per system of an element-wise lau
 // level n) and of the stencil product with the p update, in shape variant tv
 int up_blocks(int dim, int n, int tv);
 int down_blocks(int dim, int n, int tv);
+// workgroups a launch needs to keep every CU of the chip busy (4 per CU)
+constexpr long long kFillBlocks = 4 * 256;
+int default_down_tile(int dim, int n, long long nsys);
 int spmv_blocks(int dim, int n, int tv);
 int max_partial_blocks(int dim, int n, long long N);   // over every launch shape
 

@@ -939,9 +939,11 @@ struct RegionFaces {
 // stencil product.  The stencil product's default is 128 columns wide: each
 // row of a tile then spans 8 cache lines of 128 bytes (FP64) plus one line of
 // halo on each side, against 4 plus 2 at 64 columns, which took 3.5 % off its
-// time at 1023^2.  The LDS-staged down and up kernels were slower at 128 fine
-// columns (more LDS per workgroup, fewer resident workgroups).
-constexpr int kDownTile[kTileVariants][2] = {{32, 8}, {32, 4}, {32, 12}};
+// time at 1023^2 (256 columns, two rows per thread, was slower: less reuse
+// along y).  The down kernel's default region is 133 fine columns wide for
+// the same reason (7 % faster than 69 columns); the up kernel stays at 64
+// fine columns, where it is faster than at 128.
+constexpr int kDownTile[kTileVariants][2] = {{64, 6}, {32, 8}, {64, 8}};
 constexpr int kUpTile[kTileVariants][2] = {{64, 16}, {64, 8}, {64, 24}};
 constexpr int kSpmvTile[kTileVariants][2] = {{4, 128}, {2, 64}, {8, 128}};
 
@@ -957,9 +959,13 @@ __global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, c
                                                const T* __restrict__ qv, const double* __restrict__ alpha,
                                                T* __restrict__ bout, double* __restrict__ partial, Fin fin) {
   constexpr int RX = 2 * CX + 2 * NU + 1, RY = 2 * CY + 2 * NU + 1, RN = RX * RY;
-  __shared__ T sb[RN];
-  __shared__ T s0[RN];
-  __shared__ T s1[RN];
+  // One LDS array: the iterate, then the residual.  Thread tid owns region
+  // points tid + 256 u (u < PER) throughout and keeps their b and x in
+  // registers; a sweep reads its neighbours from LDS, and its results are
+  // written back after a barrier (a second barrier before the next reads).
+  // Against separate b, x and x_new arrays this needs a third of the LDS, so
+  // twice the workgroups are resident per CU.
+  __shared__ T sx[RN];
   const Tile tl = block_tile();
   const int sys = tl.z;
   if (!active[sys]) return;
@@ -980,8 +986,8 @@ __global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, c
   constexpr int PER = (RN + 255) / 256;
   T bl[PER], ql[PER];
   // variable coefficients: the four face weights of each of this thread's
-  // region points (thread tid always owns points tid + 256 u), loaded once for
-  // every sweep and the residual instead of once per use
+  // region points, loaded once for every sweep and the residual instead of
+  // once per use
   RegionFaces<T, VAR, PER> fw;
   fw.load(Lf, tid, RX, RN, gx0, gy0);
 #pragma unroll
@@ -994,77 +1000,66 @@ __global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, c
     bl[u] = b[g];
     if (RUP) ql[u] = qv[g];
   }
+  T bv[PER], xv[PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int q = tid + 256 * u;
-    if (q < RN) {
-      const int ry = q / RX, rx = q - ry * RX;
-      const int gi = gx0 + rx, gj = gy0 + ry;
-      const bool in = gi >= 0 && gi < nf && gj >= 0 && gj < nf;
-      const T bv = in ? (RUP ? bl[u] - am * ql[u] : bl[u]) : T(0);
-      T xv = sweep_w(om, 0) * bv / dcon;
-      if (VAR) xv = sweep_w(om, 0) * bv / fw.diag(u, sh);
-      sb[q] = bv;
-      s0[q] = in ? xv : T(0);
-      s1[q] = T(0);
-    }
+    const int ry = q / RX, rx = q - ry * RX;
+    const int gi = gx0 + rx, gj = gy0 + ry;
+    const bool in = q < RN && gi >= 0 && gi < nf && gj >= 0 && gj < nf;
+    bv[u] = in ? (RUP ? bl[u] - am * ql[u] : bl[u]) : T(0);
+    T x1 = sweep_w(om, 0) * bv[u] / dcon;
+    if (VAR) x1 = sweep_w(om, 0) * bv[u] / fw.diag(u, sh);
+    xv[u] = in ? x1 : T(0);
+    if (q < RN) sx[q] = xv[u];
   }
   __syncthreads();
-  T* X = s0;
-  T* Y = s1;
 #pragma unroll
   for (int m = 1; m < NU; ++m) {   // sweep m+1 on the range shrunk by m
     const T wm = sweep_w(om, m), wcon = wm / dcon;
-    if (VAR) {
+    // xv is updated in place: the sweep reads every value, the point's own
+    // included, from sx
 #pragma unroll
-      for (int u = 0; u < PER; ++u) {
-        const int q = tid + 256 * u;
-        const int ry = q / RX, rx = q - ry * RX;
-        if (q < RN && rx >= m && rx < RX - m && ry >= m && ry < RY - m) {
-          const int gi = gx0 + rx, gj = gy0 + ry;
-          if (gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
-            T dg;
-            const T ax = fw.apply(u, X, q, RX, sh, &dg);
-            Y[q] = X[q] + wm * (sb[q] - ax) / dg;
-          } else {
-            Y[q] = T(0);
-          }
-        }
-      }
-    } else {
-      const int w = RX - 2 * m, hgt = RY - 2 * m;
-      for (int q2 = tid; q2 < w * hgt; q2 += 256) {
-        const int ry = m + q2 / w, rx = m + q2 % w;
-        const int q = ry * RX + rx;
-        const int gi = gx0 + rx, gj = gy0 + ry;
-        if (gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
-          const T ax = lds_apply2<T, false>(X, q, RX, Lf, gi, gj, sh, nullptr);
-          Y[q] = X[q] + wcon * (sb[q] - ax);
+    for (int u = 0; u < PER; ++u) {
+      const int q = tid + 256 * u;
+      const int ry = q / RX, rx = q - ry * RX;
+      const int gi = gx0 + rx, gj = gy0 + ry;
+      if (q < RN && rx >= m && rx < RX - m && ry >= m && ry < RY - m && gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
+        if (VAR) {
+          T dg;
+          const T ax = fw.apply(u, sx, q, RX, sh, &dg);
+          xv[u] = xv[u] + wm * (bv[u] - ax) / dg;
         } else {
-          Y[q] = T(0);
+          const T ax = lds_apply2<T, false>(sx, q, RX, Lf, gi, gj, sh, nullptr);
+          xv[u] = xv[u] + wcon * (bv[u] - ax);
         }
       }
     }
     __syncthreads();
-    T* t = X;
-    X = Y;
-    Y = t;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int q = tid + 256 * u;
+      if (q < RN) sx[q] = xv[u];
+    }
+    __syncthreads();
   }
   // owned fine points: [2 I0, 2 I0 + 2 CX) per axis, extended to the grid end on the last tile
   {
     const int hx = (I0 + CX >= nc) ? nf : 2 * (I0 + CX);
     const int hy = (J0 + CY >= nc) ? nf : 2 * (J0 + CY);
-    const int ow = hx - 2 * I0, oh = hy - 2 * J0;
     double rr = 0.0;
-    for (int q2 = tid; q2 < ow * oh; q2 += 256) {
-      const int oy = q2 / ow, ox = q2 - oy * ow;
-      const int gi = 2 * I0 + ox, gj = 2 * J0 + oy;
-      const int q = (gj - gy0) * RX + (gi - gx0);
-      __builtin_nontemporal_store(X[q], &xout[off + (long long)gj * nf + gi]);
-      if (RUP) {
-        const T bv = sb[q];
-        __builtin_nontemporal_store(bv, &bout[off + (long long)gj * nf + gi]);
-        rr += (double)bv * (double)bv;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int q = tid + 256 * u;
+      const int ry = q / RX, rx = q - ry * RX;
+      const int gi = gx0 + rx, gj = gy0 + ry;
+      if (q < RN && gi >= 2 * I0 && gi < hx && gj >= 2 * J0 && gj < hy) {
+        const long long g = off + (long long)gj * nf + gi;
+        __builtin_nontemporal_store(xv[u], &xout[g]);
+        if (RUP) {
+          __builtin_nontemporal_store(bv[u], &bout[g]);
+          rr += (double)bv[u] * (double)bv[u];
+        }
       }
     }
     if (RUP) {
@@ -1072,29 +1067,31 @@ __global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, c
       finish(fin, partial, sys, gridDim.x * gridDim.y);
     }
   }
-  // residual on the range shrunk by NU (fine points 2 I0 .. 2 I0 + 2 CX)
-  if (VAR) {
+  // residual on the range shrunk by NU (fine points 2 I0 .. 2 I0 + 2 CX),
+  // formed from the final iterate in sx (into xv, no longer needed) and then
+  // written over it
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int q = tid + 256 * u;
-      const int ry = q / RX, rx = q - ry * RX;
-      if (q < RN && rx >= NU && rx < RX - NU && ry >= NU && ry < RY - NU) {
-        const int gi = gx0 + rx, gj = gy0 + ry;
-        T r = T(0);
-        if (gi >= 0 && gi < nf && gj >= 0 && gj < nf) r = sb[q] - fw.apply(u, X, q, RX, sh, nullptr);
-        Y[q] = r;
+  for (int u = 0; u < PER; ++u) {
+    const int q = tid + 256 * u;
+    const int ry = q / RX, rx = q - ry * RX;
+    const int gi = gx0 + rx, gj = gy0 + ry;
+    T r = T(0);
+    if (q < RN && rx >= NU && rx < RX - NU && ry >= NU && ry < RY - NU && gi >= 0 && gi < nf && gj >= 0 &&
+        gj < nf) {
+      if (VAR) {
+        r = bv[u] - fw.apply(u, sx, q, RX, sh, nullptr);
+      } else {
+        r = bv[u] - lds_apply2<T, false>(sx, q, RX, Lf, gi, gj, sh, nullptr);
       }
     }
-  } else {
-    const int w = RX - 2 * NU, hgt = RY - 2 * NU;
-    for (int q2 = tid; q2 < w * hgt; q2 += 256) {
-      const int ry = NU + q2 / w, rx = NU + q2 % w;
-      const int q = ry * RX + rx;
-      const int gi = gx0 + rx, gj = gy0 + ry;
-      T r = T(0);
-      if (gi >= 0 && gi < nf && gj >= 0 && gj < nf) r = sb[q] - lds_apply2<T, false>(X, q, RX, Lf, gi, gj, sh, nullptr);
-      Y[q] = r;
-    }
+    xv[u] = r;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int q = tid + 256 * u;
+    const int ry = q / RX, rx = q - ry * RX;
+    if (q < RN && rx >= NU && rx < RX - NU && ry >= NU && ry < RY - NU) sx[q] = xv[u];
   }
   __syncthreads();
   // full weighting: coarse (I, J) <- fine 2I+1 +- 1
@@ -1102,7 +1099,7 @@ __global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, c
     const int I = I0 + (q2 % CX), J = J0 + (q2 / CX);
     if (I < nc && J < nc) {
       const int cx = 2 * I + 1 - gx0, cy = 2 * J + 1 - gy0;
-      const T* R = Y + cy * RX + cx;
+      const T* R = sx + cy * RX + cx;
       const T v = T(0.25) * R[0] + T(0.125) * (R[-1] + R[1] + R[-RX] + R[RX]) +
                   T(0.0625) * (R[-RX - 1] + R[-RX + 1] + R[RX - 1] + R[RX + 1]);
       bc[(long long)sys * Lc.N + (long long)J * nc + I] = v;
@@ -1119,9 +1116,9 @@ __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, con
   constexpr int RX = OX + 2 * NU, RY = OY + 2 * NU, RN = RX * RY;
   // coarse values under the region, zero-padded: coarse index c at cx0 + (c - c0)
   constexpr int CRX = RX / 2 + 3, CRY = RY / 2 + 3, CRN = CRX * CRY;
-  __shared__ T sb[RN];
-  __shared__ T s0[RN];
-  __shared__ T s1[RN];
+  // the iterate in one LDS array, b and x of a thread's points (tid + 256 u)
+  // in registers, as in k_down2
+  __shared__ T sx[RN];
   __shared__ T sc[CRN];
   const Tile tl = block_tile();
   const int sys = tl.z;
@@ -1171,9 +1168,12 @@ __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, con
     }
   }
   __syncthreads();
+  T bv[PER], xv[PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int q = tid + 256 * u;
+    bv[u] = T(0);
+    xv[u] = T(0);
     if (q < RN) {
       const int ry = q / RX, rx = q - ry * RX;
       const int gi = gx0 + rx, gj = gy0 + ry;
@@ -1188,46 +1188,50 @@ __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, con
       } else {
         v = (gj & 1) ? T(0.5) * (C[0] + C[1]) : T(0.25) * (C[0] + C[1] + C[CRX] + C[CRX + 1]);
       }
-      sb[q] = in ? bl[u] : T(0);
-      s0[q] = in ? xl[u] + v : T(0);
-      s1[q] = T(0);
+      if (in) {
+        bv[u] = bl[u];
+        xv[u] = xl[u] + v;
+      }
+      sx[q] = xv[u];
     }
   }
   __syncthreads();
-  T* X = s0;
-  T* Y = s1;
 #pragma unroll
   for (int m = 1; m <= NU; ++m) {   // post-smoothing: the pre-smoothing weights reversed
     // (the face weights are read per sweep here: held in registers, as in the
     // down kernel, they cost more occupancy than the two sweeps save)
-    const int w = RX - 2 * m, hgt = RY - 2 * m;
     const T wm = sweep_w(om, NU - m), wcon = wm / dcon;
-    for (int q2 = tid; q2 < w * hgt; q2 += 256) {
-      const int ry = m + q2 / w, rx = m + q2 % w;
-      const int q = ry * RX + rx;
+    // xv updated in place (the sweep reads every value from sx)
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int q = tid + 256 * u;
+      const int ry = q / RX, rx = q - ry * RX;
       const int gi = gx0 + rx, gj = gy0 + ry;
-      if (gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
+      if (q < RN && rx >= m && rx < RX - m && ry >= m && ry < RY - m && gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
         T dg;
-        const T ax = lds_apply2<T, VAR>(X, q, RX, Lf, gi, gj, sh, VAR ? &dg : nullptr);
-        Y[q] = VAR ? X[q] + wm * (sb[q] - ax) / dg : X[q] + wcon * (sb[q] - ax);
-      } else {
-        Y[q] = T(0);
+        const T ax = lds_apply2<T, VAR>(sx, q, RX, Lf, gi, gj, sh, VAR ? &dg : nullptr);
+        xv[u] = VAR ? xv[u] + wm * (bv[u] - ax) / dg : xv[u] + wcon * (bv[u] - ax);
       }
     }
-    __syncthreads();
-    T* t = X;
-    X = Y;
-    Y = t;
+    if (m < NU) {   // the last sweep's values are written out from registers
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int q = tid + 256 * u;
+        if (q < RN) sx[q] = xv[u];
+      }
+      __syncthreads();
+    }
   }
   double dot = 0.0;
-  for (int q2 = tid; q2 < OX * OY; q2 += 256) {
-    const int oy = q2 / OX, ox = q2 - oy * OX;
-    const int gi = ox0 + ox, gj = oy0 + oy;
-    if (gi < nf && gj < nf) {
-      const int q = (oy + NU) * RX + (ox + NU);
-      const T v = X[q];
-      __builtin_nontemporal_store(v, &xout[off + (long long)gj * nf + gi]);
-      if (DOT) dot += (double)sb[q] * (double)v;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int q = tid + 256 * u;
+    const int ry = q / RX, rx = q - ry * RX;
+    const int gi = gx0 + rx, gj = gy0 + ry;
+    if (q < RN && rx >= NU && rx < NU + OX && ry >= NU && ry < NU + OY && gi < nf && gj < nf) {
+      __builtin_nontemporal_store(xv[u], &xout[off + (long long)gj * nf + gi]);
+      if (DOT) dot += (double)bv[u] * (double)xv[u];
     }
   }
   if (DOT) {
@@ -2057,6 +2061,16 @@ int down_blocks(int dim, int n, int tv) {
   const int nc = (n - 1) / 2;
   const int cx = kDownTile[tile_variant(tv)][0], cy = kDownTile[tile_variant(tv)][1];
   return ((nc + cx - 1) / cx) * ((nc + cy - 1) / cy);
+}
+
+// The down kernel's default shape on a level of n points per axis when nsys
+// systems share each launch.  The 64-column tile (variant 0) fetches fewer
+// halo lines but makes fewer workgroups: below about four per CU (one-system
+// solves, coarse levels) the 32 x 8 tile (variant 1) keeps more of the chip
+// busy and is faster.
+int default_down_tile(int dim, int n, long long nsys) {
+  if (dim != 2) return 0;
+  return nsys * down_blocks(dim, n, 0) >= kFillBlocks ? 0 : 1;
 }
 
 template <typename T>

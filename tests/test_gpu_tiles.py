@@ -6,9 +6,9 @@ same value at every grid point, and only the grouping of the per-block
 partial sums of the PCG dot products differs.  So every variant, and the
 tuner's choice, must match the oracle at the same tolerance as the default
 shape.  The grids are chosen so that every variant has ragged edge tiles
-(255 -> 127 -> 63 ...: 127 is not a multiple of 4, 8 or 12 coarse rows, 255
-not a multiple of 8, 16 or 24 fine rows; 191 -> 95 -> 47 ... stops at an even
-level).
+(255 -> 127 -> 63 ...: 127 is not a multiple of 6 or 8 coarse rows or of 32
+or 64 coarse columns, 255 not a multiple of 8, 16 or 24 fine rows or of 64 or
+128 columns; 191 -> 95 -> 47 ... stops at an even level).
 """
 
 import numpy as np
@@ -50,6 +50,35 @@ def _reference(n, var, alpha, k, F, tag):
     return coeff, shifted.bura_by_solves(A, b.c_f64, b.d_f64, F)
 
 
+def _default_tiles(n, nsys, levels):
+    """The documented default: variant 0 everywhere except the down kernel on
+    levels whose 64 x 6 launch (coarse points per workgroup) would make fewer
+    than 1024 workgroups over all systems, which take the 32 x 8 tile (1)."""
+    out = [0]
+    for _ in range(levels):
+        nc = (n - 1) // 2
+        blocks = -(-nc // 64) * -(-nc // 6)
+        out += [0 if nsys * blocks >= 1024 else 1, 0]
+        n = nc
+    return out
+
+
+def test_default_down_tile_follows_launch_width():
+    B = _B()
+    b = oracle_bura(0.5, 9)
+    one = B.Plan(2, 1023, weights=[1.0], shifts=[0.25])
+    wide = B.Plan(2, 1023, weights=b.c_f64, shifts=[-x for x in b.d_f64], nrhs_max=3)
+    try:
+        t1, t30 = one.tiles, wide.tiles
+        print("1 system:", t1, " 30 systems:", t30)
+        assert t1 == _default_tiles(1023, 1, len(t1) // 2)
+        assert t30 == _default_tiles(1023, 30, len(t30) // 2)
+        assert t1[1] == 1 and t30[1] == 0   # the fine level: 688 workgroups per system
+    finally:
+        one.close()
+        wide.close()
+
+
 CASES = [
     # n, variable coefficients, precision, alpha, k
     (255, False, "FP64", 0.5, 5),
@@ -67,7 +96,8 @@ def test_every_tile_variant_matches_oracle(n, var, prec, alpha, k):
     plan = B.Plan(2, n, weights=b.c_f64, shifts=[-x for x in b.d_f64], coeff=coeff, nrhs_max=2,
                   precision=getattr(B, "BURA_" + prec), tol=1e-12)
     default = plan.tiles
-    assert default == [0] * len(default) and len(default) % 2 == 1 and len(default) >= 3
+    assert len(default) % 2 == 1 and len(default) >= 3
+    assert default == _default_tiles(n, 2 * (k + 1), len(default) // 2)
     settings = [[v] * len(default) for v in range(B.BURA_TILE_VARIANTS)]
     settings.append([(i % B.BURA_TILE_VARIANTS) for i in range(len(default))])   # mixed per level
     u0 = None
