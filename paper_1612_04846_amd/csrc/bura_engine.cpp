@@ -595,12 +595,15 @@ bool fused_ok(const bura_plan_t P) {
 // The PCG residual update folded into the fine down kernel: r_new = r_old -
 // alpha q is formed while staging, written to rnew (a different buffer) with
 // its squared norm; `after` runs once that kernel is queued (the convergence
-// test on |r_new|).
+// test on |r_new|).  The fused 2D down kernel takes the search direction p
+// and forms q = (A + s) p itself (the stencil product then stores no q); the
+// unfused first sweep reads q.
 template <typename T>
 struct ResidUpdate {
   const T* rold;
   T* rnew;
-  const T* q;
+  const T* q;   // (A + s) p, for the unfused first sweep
+  const T* p;   // p, for the fused down kernel
   const double* alpha;
   Fin fin;
   std::function<void()> after;
@@ -637,7 +640,7 @@ void precondition(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, const int* a
         ProfScope ps(P, l == 0 ? BURA_K_DOWN_FINE : BURA_K_SMOOTH_COARSE);
         if (l == 0 && ru)
           Launch<T>::fused_down(dim, var, nu1, level_view<T>(P, 0), level_view<T>(P, 1), ru->rold, A(0), bl(1),
-                                shift, active, wpre, nsys, st, ps.ctr, ru->q, ru->alpha, ru->rnew, partial,
+                                shift, active, wpre, nsys, st, ps.ctr, ru->p, ru->alpha, ru->rnew, partial,
                                 ru->fin, P->tile_down[0]);
         else
           Launch<T>::fused_down(dim, var, nu1, level_view<T>(P, l), level_view<T>(P, l + 1), bl(l), A(l),
@@ -779,15 +782,17 @@ int run_pcg(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, double tol, int ma
   const bool fx = P->foldxr;
   // blocks of the kernel that writes the |r_new|^2 partials
   const int nb_down = !fx ? 0 : fused_ok(P) ? down_blocks(dim, P->n, P->tile_down[0]) : stencil_blocks(dim, P->n);
+  // the fused down kernel forms q from p: the stencil product stores no q
+  const bool qfree = fx && fused_ok(P);
   auto body = [&](T* po, T* pn, T* ro, T* rn) {
     {
       ProfScope ps(P, BURA_K_SPMV);
-      Launch<T>::spmv_p(dim, P->var, L0, W.z + o, po, pn, W.q + o, S.beta, W.shift + sys0, S.active, part, nsys, st,
-                        ps.ctr, fin(OP_ALPHA), fx ? W.x + o : nullptr, S.alpha, P->tile_spmv);
+      Launch<T>::spmv_p(dim, P->var, L0, W.z + o, po, pn, qfree ? nullptr : W.q + o, S.beta, W.shift + sys0, S.active,
+                        part, nsys, st, ps.ctr, fin(OP_ALPHA), fx ? W.x + o : nullptr, S.alpha, P->tile_spmv);
     }
     if (!P->fold) scal(OP_ALPHA, spmv_blocks(dim, P->n, P->tile_spmv));
     if (fx) {
-      ResidUpdate<T> ru{ro, rn, W.q + o, S.alpha, fin(OP_RESID), [&]() {
+      ResidUpdate<T> ru{ro, rn, qfree ? nullptr : W.q + o, pn, S.alpha, fin(OP_RESID), [&]() {
                           if (!P->fold) scal(OP_RESID, nb_down);
                         }};
       precondition<T>(P, W, sys0, nsys, S.active, part, fin(OP_BETA), &ru);

@@ -116,7 +116,9 @@ struct Launch {
   static void update_p(const LevelDev<T>& L, int dim, T* p, const T* z, const double* beta,
                        const int* active, int nsys, hipStream_t st, unsigned long long* ctr);
   // p_new = z + beta p_old, q = (A+s) p_new, p_new.q; with x != nullptr also the
-  // deferred x += alpha p_old of the previous iteration
+  // deferred x += alpha p_old of the previous iteration.  2D with x != nullptr:
+  // q may be nullptr (only p_new.q is formed; the fused down kernel forms the
+  // product again from p_new)
   static void spmv_p(int dim, bool var, const LevelDev<T>& L, const T* z, const T* pold, T* pnew, T* q,
                      const double* beta, const T* shift, const int* active, double* partial, int nsys,
                      hipStream_t st, unsigned long long* ctr, Fin fin = Fin(), T* x = nullptr,
@@ -129,7 +131,7 @@ struct Launch {
   // squared norm to partial.
   static bool fused_down(int dim, bool var, int nu, const LevelDev<T>& Lf, const LevelDev<T>& Lc, const T* b,
                          T* xout, T* bc, const T* shift, const int* active, Sweeps<T> om, int nsys, hipStream_t st,
-                         unsigned long long* ctr, const T* q = nullptr, const double* alpha = nullptr,
+                         unsigned long long* ctr, const T* p = nullptr, const double* alpha = nullptr,
                          T* bout = nullptr, double* partial = nullptr, Fin fin = Fin(), int tv = 0);
   static bool fused_up(int dim, bool var, int nu, const LevelDev<T>& Lc, const LevelDev<T>& Lf, const T* xc,
                        const T* xin, const T* b, T* xout, const T* shift, const int* active, Sweeps<T> om,

@@ -947,25 +947,36 @@ constexpr int kDownTile[kTileVariants][2] = {{64, 6}, {32, 8}, {64, 8}};
 constexpr int kUpTile[kTileVariants][2] = {{64, 16}, {64, 8}, {64, 24}};
 constexpr int kSpmvTile[kTileVariants][2] = {{4, 128}, {2, 64}, {8, 128}};
 
-// RUP: the right-hand side is first advanced by the PCG step, b = b_old - alpha q
-// (read from b, written to bout on the owned points, |b|^2 into partial), so the
-// vector update of the PCG iteration costs no pass of its own.  bout must not
-// be b: neighbouring blocks still read b_old in their halos.
+// RUP: the right-hand side is first advanced by the PCG step, b = b_old -
+// alpha (A + s) p (read from b, written to bout on the owned points, |b|^2 into
+// partial), so the vector update of the PCG iteration costs no pass of its
+// own.  The product (A + s) p is formed here from p (pv), staged on the region
+// widened by one point, with the stencil product's arithmetic: that kernel
+// then only dots it with p and stores no q, one vector pass less per
+// iteration.  bout must not be b: neighbouring blocks still read b_old in
+// their halos.
+// (RUP with constant coefficients: the compiler is asked for 5 waves per
+// SIMD; left alone it spends up to 97 VGPRs on the FP64 64 x 6 tile, 4 waves,
+// and the kernel ran 4 % slower)
 template <typename T, bool VAR, int NU, bool RUP, int CX, int CY>
-__global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, const T* __restrict__ b,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RUP && !VAR ? 5 : 1))) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, const T* __restrict__ b,
                                                T* __restrict__ xout, T* __restrict__ bc,
                                                const T* __restrict__ shift, const int* __restrict__ active,
                                                Sweeps<T> om, unsigned long long* __restrict__ ctr,
-                                               const T* __restrict__ qv, const double* __restrict__ alpha,
+                                               const T* __restrict__ pv, const double* __restrict__ alpha,
                                                T* __restrict__ bout, double* __restrict__ partial, Fin fin) {
   constexpr int RX = 2 * CX + 2 * NU + 1, RY = 2 * CY + 2 * NU + 1, RN = RX * RY;
+  // RUP: p on the region widened by one point per side (row length PX),
+  // staged in the same LDS array before it takes the iterate
+  constexpr int PX = RX + 2, PY = RY + 2, PN = PX * PY;
+  constexpr int LN = RUP && PN > RN ? PN : RN;
   // One LDS array: the iterate, then the residual.  Thread tid owns region
   // points tid + 256 u (u < PER) throughout and keeps their b and x in
   // registers; a sweep reads its neighbours from LDS, and its results are
   // written back after a barrier (a second barrier before the next reads).
   // Against separate b, x and x_new arrays this needs a third of the LDS, so
   // twice the workgroups are resident per CU.
-  __shared__ T sx[RN];
+  __shared__ T sx[LN];
   const Tile tl = block_tile();
   const int sys = tl.z;
   if (!active[sys]) return;
@@ -983,22 +994,40 @@ __global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, c
   // stage b (0 outside the grid) and the first sweep from x = 0: x1 = omega b / D.
   // All loads of a thread are issued before any is used (clamped addresses,
   // results selected afterwards), so a wave keeps PER loads in flight.
-  constexpr int PER = (RN + 255) / 256;
-  T bl[PER], ql[PER];
+  constexpr int PER = (RN + 255) / 256, PPER = RUP ? (PN + 255) / 256 : 1;
+  T bl[PER], pl[PPER];
   // variable coefficients: the four face weights of each of this thread's
   // region points, loaded once for every sweep and the residual instead of
   // once per use
   RegionFaces<T, VAR, PER> fw;
   fw.load(Lf, tid, RX, RN, gx0, gy0);
+  if (RUP) {
+    // p first, into LDS; b is loaded after the barrier, so the two sets of
+    // loads do not hold registers at the same time
+#pragma unroll
+    for (int u = 0; u < PPER; ++u) {
+      const int q = tid + 256 * u;
+      const int py = q / PX, px = q - py * PX;
+      const int gi = gx0 - 1 + px, gj = gy0 - 1 + py;
+      const bool in = q < PN && gi >= 0 && gi < nf && gj >= 0 && gj < nf;
+      pl[u] = pv[off + (in ? (long long)gj * nf + gi : 0LL)];
+    }
+#pragma unroll
+    for (int u = 0; u < PPER; ++u) {
+      const int q = tid + 256 * u;
+      const int py = q / PX, px = q - py * PX;
+      const int gi = gx0 - 1 + px, gj = gy0 - 1 + py;
+      if (q < PN) sx[q] = (gi >= 0 && gi < nf && gj >= 0 && gj < nf) ? pl[u] : T(0);   // 0 off the grid
+    }
+    __syncthreads();
+  }
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int q = tid + 256 * u;
     const int ry = q / RX, rx = q - ry * RX;
     const int gi = gx0 + rx, gj = gy0 + ry;
     const bool in = q < RN && gi >= 0 && gi < nf && gj >= 0 && gj < nf;
-    const long long g = off + (in ? (long long)gj * nf + gi : 0LL);
-    bl[u] = b[g];
-    if (RUP) ql[u] = qv[g];
+    bl[u] = b[off + (in ? (long long)gj * nf + gi : 0LL)];
   }
   T bv[PER], xv[PER];
 #pragma unroll
@@ -1007,10 +1036,21 @@ __global__ __launch_bounds__(256) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, c
     const int ry = q / RX, rx = q - ry * RX;
     const int gi = gx0 + rx, gj = gy0 + ry;
     const bool in = q < RN && gi >= 0 && gi < nf && gj >= 0 && gj < nf;
-    bv[u] = in ? (RUP ? bl[u] - am * ql[u] : bl[u]) : T(0);
+    T bn = bl[u];
+    if (RUP && in) {
+      const int pq = (ry + 1) * PX + (rx + 1);
+      const T ap = VAR ? fw.apply(u, sx, pq, PX, sh, nullptr) : lds_apply2<T, false>(sx, pq, PX, Lf, gi, gj, sh, nullptr);
+      bn = bl[u] - am * ap;
+    }
+    bv[u] = in ? bn : T(0);
     T x1 = sweep_w(om, 0) * bv[u] / dcon;
     if (VAR) x1 = sweep_w(om, 0) * bv[u] / fw.diag(u, sh);
     xv[u] = in ? x1 : T(0);
+  }
+  if (RUP) __syncthreads();   // every read of p done before sx takes the iterate
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int q = tid + 256 * u;
     if (q < RN) sx[q] = xv[u];
   }
   __syncthreads();
@@ -1336,7 +1376,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p3(LevelDev<T> L, const T* __re
 // of TX x (256 / TX) threads covers TX x (256 / TX) R points), so the column's p_new values are formed
 // once and reused by the rows above and below; only the left/right neighbours
 // are extra loads.
-template <typename T, bool VAR, bool XUP, int R, int TX>
+template <typename T, bool VAR, bool XUP, bool WQ, int R, int TX>
 __global__ __launch_bounds__(kBlock) void k_spmv_p2(LevelDev<T> L, const T* __restrict__ z, const T* __restrict__ pold,
                                                     T* __restrict__ pnew, T* __restrict__ q,
                                                     const double* __restrict__ beta, const T* __restrict__ shift,
@@ -1349,7 +1389,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p2(LevelDev<T> L, const T* __re
   const T bt = (T)beta[sys];
   const T ap = XUP ? (T)alpha[sys] : T(0);
   count_bytes_tile(tl, ctr, (unsigned long long)L.N * sizeof(T) *
-                                ((bt == T(0) ? 3 : 4) + (XUP && ap != T(0) ? 2 : 0) + (VAR && sys == 0 ? 2 : 0)));
+                                ((bt == T(0) ? 3 : 4) - (WQ ? 0 : 1) + (XUP && ap != T(0) ? 2 : 0) +
+                                 (VAR && sys == 0 ? 2 : 0)));
   const int n = L.n;
   const int i = tl.x * TX + threadIdx.x;
   const int j0 = (tl.y * (kBlock / TX) + threadIdx.y) * R;
@@ -1403,7 +1444,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p2(LevelDev<T> L, const T* __re
         }
         const long long g = off + (long long)j * n + i;
         __builtin_nontemporal_store(c, &pnew[g]);
-        __builtin_nontemporal_store(qv, &q[g]);
+        if (WQ) __builtin_nontemporal_store(qv, &q[g]);
         // the deferred update uses p_old = pc (pe is p_old whenever alpha != 0)
         if (XUP && ap != T(0)) __builtin_nontemporal_store(xv[r] + ap * pc[r + 1], &x[g]);
         dot += (double)c * (double)qv;
@@ -2001,13 +2042,15 @@ void Launch<T>::spmv_p(int dim, bool var, const LevelDev<T>& L, const T* z, cons
     with_tile(tv, [&](auto v) {
       constexpr int R = kSpmvTile[decltype(v)::value][0], TX = kSpmvTile[decltype(v)::value][1];
       const dim3 blk2(TX, kBlock / TX);
-#define K_SP2(V, X_) \
-  hipLaunchKernelGGL((k_spmv_p2<T, V, X_, R, TX>), g2, blk2, 0, st, L, z, pold, pnew, q, beta, shift, active, \
+#define K_SP2(V, X_, Q_) \
+  hipLaunchKernelGGL((k_spmv_p2<T, V, X_, Q_, R, TX>), g2, blk2, 0, st, L, z, pold, pnew, q, beta, shift, active, \
                      partial, ctr, fin, x, alpha)
+      // q == nullptr: the product is only dotted with p (the fused down
+      // kernel forms it again from p); that needs the deferred x update
       if (var) {
-        if (xup) K_SP2(true, true); else K_SP2(true, false);
+        if (!q) K_SP2(true, true, false); else if (xup) K_SP2(true, true, true); else K_SP2(true, false, true);
       } else {
-        if (xup) K_SP2(false, true); else K_SP2(false, false);
+        if (!q) K_SP2(false, true, false); else if (xup) K_SP2(false, true, true); else K_SP2(false, false, true);
       }
 #undef K_SP2
     });
@@ -2034,7 +2077,7 @@ void Launch<T>::finish_x(long long N, T* x, const T* pa, const T* pb, const doub
 template <typename T>
 bool Launch<T>::fused_down(int dim, bool var, int nu, const LevelDev<T>& Lf, const LevelDev<T>& Lc, const T* b,
                            T* xout, T* bc, const T* shift, const int* active, Sweeps<T> om, int nsys, hipStream_t st,
-                           unsigned long long* ctr, const T* q, const double* alpha, T* bout, double* partial,
+                           unsigned long long* ctr, const T* p, const double* alpha, T* bout, double* partial,
                            Fin fin, int tv) {
   if (dim != 2 || nu < 1 || nu > 3) return false;
   const bool rup = bout != nullptr;
@@ -2043,7 +2086,7 @@ bool Launch<T>::fused_down(int dim, bool var, int nu, const LevelDev<T>& Lf, con
     const dim3 g((Lc.n + CX - 1) / CX, (Lc.n + CY - 1) / CY, nsys), blk(256);
 #define K_DN0(V, NU_, R_)                                                                                          \
   hipLaunchKernelGGL((k_down2<T, V, NU_, R_, CX, CY>), g, blk, 0, st, Lf, Lc, b, xout, bc, shift, active, om, ctr, \
-                     q, alpha, bout, partial, fin)
+                     p, alpha, bout, partial, fin)
 #define K_DN(V, NU_) do { if (rup) K_DN0(V, NU_, true); else K_DN0(V, NU_, false); } while (0)
     if (var) {
       if (nu == 1) K_DN(true, 1); else if (nu == 2) K_DN(true, 2); else K_DN(true, 3);
