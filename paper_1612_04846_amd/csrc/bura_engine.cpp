@@ -513,6 +513,12 @@ LdsHierarchy<T> lds_view(const bura_plan_t P) {
   return H;
 }
 
+bool fused_ok(const bura_plan_t P);
+
+// q = (A + s) p needs a buffer unless the fused 2D down kernel forms it from p
+// (the PCG updates folded into the level kernels)
+bool q_stored(const bura_plan_t P) { return !(P->foldxr && fused_ok(P)); }
+
 template <typename T>
 int alloc_work(bura_plan_t P, Work<T>& W) {
   const size_t S = (size_t)P->S;
@@ -524,7 +530,7 @@ int alloc_work(bura_plan_t P, Work<T>& W) {
   if ((rc = dev_alloc(P, (void**)&W.zt, vb))) return rc;
   if ((rc = dev_alloc(P, (void**)&W.p, vb))) return rc;
   if ((rc = dev_alloc(P, (void**)&W.p2, vb))) return rc;
-  if ((rc = dev_alloc(P, (void**)&W.q, vb))) return rc;
+  if (q_stored(P) && (rc = dev_alloc(P, (void**)&W.q, vb))) return rc;
   if (P->foldxr) {
     if ((rc = dev_alloc(P, (void**)&W.r2, vb))) return rc;
     HIPCHK(hipMemsetAsync(W.r2, 0, vb, P->stream));
@@ -548,13 +554,13 @@ int alloc_work(bura_plan_t P, Work<T>& W) {
   HIPCHK(hipMemcpyAsync(W.shift, sh.data(), S * sizeof(T), hipMemcpyHostToDevice, P->stream));
   HIPCHK(hipStreamSynchronize(P->stream));
   for (void* ptr : {(void*)W.x, (void*)W.r, (void*)W.z, (void*)W.zt, (void*)W.p, (void*)W.p2, (void*)W.q})
-    HIPCHK(hipMemsetAsync(ptr, 0, vb, P->stream));
+    if (ptr) HIPCHK(hipMemsetAsync(ptr, 0, vb, P->stream));
   return BURA_OK;
 }
 
 size_t footprint(const bura_plan_t P, size_t elem, bool mixed) {
   const size_t S = (size_t)P->S;
-  size_t t = (P->foldxr ? 8 : 7) * S * (size_t)P->N * elem;
+  size_t t = (6 + (P->foldxr ? 1 : 0) + (q_stored(P) ? 1 : 0)) * S * (size_t)P->N * elem;
   if (P->lc > 0)
     for (int l = 1; l <= P->lc; ++l) t += 3 * S * (size_t)P->lev[l].N * elem;
   if (mixed) t += S * (size_t)P->N * 8;
@@ -783,7 +789,7 @@ int run_pcg(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, double tol, int ma
   // blocks of the kernel that writes the |r_new|^2 partials
   const int nb_down = !fx ? 0 : fused_ok(P) ? down_blocks(dim, P->n, P->tile_down[0]) : stencil_blocks(dim, P->n);
   // the fused down kernel forms q from p: the stencil product stores no q
-  const bool qfree = fx && fused_ok(P);
+  const bool qfree = !q_stored(P);
   auto body = [&](T* po, T* pn, T* ro, T* rn) {
     {
       ProfScope ps(P, BURA_K_SPMV);
