@@ -515,9 +515,10 @@ LdsHierarchy<T> lds_view(const bura_plan_t P) {
 
 bool fused_ok(const bura_plan_t P);
 
-// q = (A + s) p needs a buffer unless the fused 2D down kernel forms it from p
+// q = (A + s) p needs a buffer unless the kernel that takes the PCG residual
+// update forms it from p: the fused 2D down kernel, the 3D first fine sweep
 // (the PCG updates folded into the level kernels)
-bool q_stored(const bura_plan_t P) { return !(P->foldxr && fused_ok(P)); }
+bool q_stored(const bura_plan_t P) { return !(P->foldxr && (fused_ok(P) || P->dim == 3)); }
 
 template <typename T>
 int alloc_work(bura_plan_t P, Work<T>& W) {
@@ -601,15 +602,15 @@ bool fused_ok(const bura_plan_t P) {
 // The PCG residual update folded into the fine down kernel: r_new = r_old -
 // alpha q is formed while staging, written to rnew (a different buffer) with
 // its squared norm; `after` runs once that kernel is queued (the convergence
-// test on |r_new|).  The fused 2D down kernel takes the search direction p
-// and forms q = (A + s) p itself (the stencil product then stores no q); the
-// unfused first sweep reads q.
+// test on |r_new|).  The fused 2D down kernel and the 3D first fine sweep
+// take the search direction p and form q = (A + s) p themselves (the stencil
+// product then stores no q); the 2D unfused first sweep reads q.
 template <typename T>
 struct ResidUpdate {
   const T* rold;
   T* rnew;
-  const T* q;   // (A + s) p, for the unfused first sweep
-  const T* p;   // p, for the fused down kernel
+  const T* q;   // (A + s) p, for the 2D unfused first sweep (nullptr: form it from p)
+  const T* p;   // p, for the fused down kernel and the 3D first sweep
   const double* alpha;
   Fin fin;
   std::function<void()> after;
@@ -687,7 +688,7 @@ void precondition(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, const int* a
       {
         ProfScope ps(P, scls);
         Launch<T>::jacobi_rup(dim, var, L, ru->rold, ru->q, ru->alpha, ru->rnew, out, shift, active, w_at(wpre, 0),
-                              partial, nsys, st, ps.ctr, ru->fin);
+                              partial, nsys, st, ps.ctr, ru->fin, ru->p);
       }
       if (ru->after) ru->after();
     } else {

@@ -99,9 +99,10 @@ struct Launch {
                      int nsys, hipStream_t st, unsigned long long* ctr, Fin fin = Fin());
   // zero-guess sweep with the PCG residual update: bout = bold - alpha q,
   // xout = omega D^-1 bout, partial = |bout|^2 (see k_jacobi0_rup)
+  // 3D with q == nullptr: q = (A + s) p is formed from p
   static void jacobi_rup(int dim, bool var, const LevelDev<T>& L, const T* bold, const T* q, const double* alpha,
                          T* bout, T* xout, const T* shift, const int* active, T omega, double* partial, int nsys,
-                         hipStream_t st, unsigned long long* ctr, Fin fin = Fin());
+                         hipStream_t st, unsigned long long* ctr, Fin fin = Fin(), const T* p = nullptr);
   static void restrict_residual(int dim, bool var, const LevelDev<T>& Lf, const LevelDev<T>& Lc,
                                 const T* b, const T* x, T* bc, const T* shift, const int* active,
                                 int nsys, hipStream_t st, unsigned long long* ctr);
@@ -116,9 +117,9 @@ struct Launch {
   static void update_p(const LevelDev<T>& L, int dim, T* p, const T* z, const double* beta,
                        const int* active, int nsys, hipStream_t st, unsigned long long* ctr);
   // p_new = z + beta p_old, q = (A+s) p_new, p_new.q; with x != nullptr also the
-  // deferred x += alpha p_old of the previous iteration.  2D with x != nullptr:
-  // q may be nullptr (only p_new.q is formed; the fused down kernel forms the
-  // product again from p_new)
+  // deferred x += alpha p_old of the previous iteration.  With x != nullptr q
+  // may be nullptr (only p_new.q is formed; the fused down kernel in 2D, the
+  // first fine sweep in 3D, forms the product again from p_new)
   static void spmv_p(int dim, bool var, const LevelDev<T>& L, const T* z, const T* pold, T* pnew, T* q,
                      const double* beta, const T* shift, const int* active, double* partial, int nsys,
                      hipStream_t st, unsigned long long* ctr, Fin fin = Fin(), T* x = nullptr,

@@ -472,6 +472,79 @@ __global__ __launch_bounds__(kBlock) void k_jacobi0_rup(LevelDev<T> L, const T* 
   finish(fin, partial, sys, gridDim.x * gridDim.y);
 }
 
+// 3D first fine sweep with the PCG residual update, forming q = (A + s) p
+// itself from p while marching along z (as k_jacobi3 forms (A + s) x):
+// b = b_old - alpha q to bout with |b|^2 into partial, x_out = omega D^-1 b.
+// The stencil product then stores no q (one vector pass less per iteration).
+template <typename T, bool VAR>
+__global__ __launch_bounds__(kBlock) void k_jacobi0_rup3p(LevelDev<T> L, const T* __restrict__ bold,
+                                                          const T* __restrict__ pv, const double* __restrict__ alpha,
+                                                          T* __restrict__ bout, T* __restrict__ xout,
+                                                          const T* __restrict__ shift, const int* __restrict__ active,
+                                                          T omega, double* __restrict__ partial,
+                                                          unsigned long long* __restrict__ ctr, Fin fin) {
+  constexpr int R = kMarchRows;
+  const Tile tl = block_tile();
+  const int sys = tl.z;
+  if (!active[sys]) return;
+  // b_old and p read, b and x_out written; faces once per launch
+  count_bytes_tile(tl, ctr, (unsigned long long)L.N * sizeof(T) * (4 + (VAR && sys == 0 ? 3 : 0)));
+  const int n = L.n;
+  const Column c = march_column(tl, n, R);
+  double rr = 0.0;
+  if (c.i < n && c.j < n) {
+    const long long off = (long long)sys * L.N, nn = (long long)n * n;
+    const Rows<R> w(c.i, c.j, n);
+    const T s = shift[sys];
+    const T a = (T)alpha[sys];
+    const T* ps = pv + off;
+    const T* bs = bold + off;
+    T below[R], centre[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const long long p0 = c.k0 * nn + w.col[r];
+      const T pb0 = ps[c.k0 > 0 ? p0 - nn : p0];
+      below[r] = c.k0 > 0 ? pb0 : T(0);
+      centre[r] = ps[p0];
+    }
+    for (int k = c.k0; k < c.k1; ++k) {
+      const long long pk = k * nn;
+      T pa[R], pl[R], pr[R], bv[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const long long p = pk + w.col[r];
+        pa[r] = ps[k + 1 < n ? p + nn : p];
+        pl[r] = ps[p + w.il];
+        pr[r] = ps[p + w.ir];
+        bv[r] = bs[p];
+      }
+      const T hd = ps[pk + w.col_d], hu = ps[pk + w.col_u];
+      T above[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) above[r] = k + 1 < n ? pa[r] : T(0);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (!w.valid[r]) continue;
+        const long long p = pk + w.col[r];
+        T dg;
+        const T ap = apply_col3<T, VAR>(L, c.i, c.j + r, k, p, centre[r], w.il ? pl[r] : T(0), w.ir ? pr[r] : T(0),
+                                        w.down(r, centre, hd), w.up(r, centre, hu), below[r], above[r], s, &dg);
+        const T bn = bv[r] - a * ap;
+        bout[off + p] = bn;
+        xout[off + p] = omega * bn / dg;
+        rr += (double)bn * (double)bn;
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        below[r] = centre[r];
+        centre[r] = above[r];
+      }
+    }
+  }
+  write_partial_tile(tl, partial, sys, rr);
+  finish(fin, partial, sys, gridDim.x * gridDim.y);
+}
+
 // --------------------------------------------------------------------------
 // b_c = R (b - (A+s) x): full weighting of the fine residual (weights
 // (1/4, 1/2, 1/4) per axis), fine node 2I+1 under coarse node I (0-based).
@@ -1292,7 +1365,7 @@ __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, con
 // 3D version, marching along z with kMarchRows rows per thread: p_new =
 // z + beta p_old is formed once per point; the rows' values below and at the
 // point stay in registers.
-template <typename T, bool VAR, bool XUP>
+template <typename T, bool VAR, bool XUP, bool WQ>
 __global__ __launch_bounds__(kBlock) void k_spmv_p3(LevelDev<T> L, const T* __restrict__ z, const T* __restrict__ pold,
                                                     T* __restrict__ pnew, T* __restrict__ q,
                                                     const double* __restrict__ beta, const T* __restrict__ shift,
@@ -1306,7 +1379,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p3(LevelDev<T> L, const T* __re
   const T bt = (T)beta[sys];
   const T ap = XUP ? (T)alpha[sys] : T(0);
   count_bytes_tile(tl, ctr, (unsigned long long)L.N * sizeof(T) *
-                                ((bt == T(0) ? 3 : 4) + (XUP && ap != T(0) ? 2 : 0) + (VAR && sys == 0 ? 3 : 0)));
+                                ((bt == T(0) ? 3 : 4) - (WQ ? 0 : 1) + (XUP && ap != T(0) ? 2 : 0) +
+                                 (VAR && sys == 0 ? 3 : 0)));
   const int n = L.n;
   const Column c = march_column(tl, n, R);
   double dot = 0.0;
@@ -1356,7 +1430,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p3(LevelDev<T> L, const T* __re
         const T qv = apply_col3<T, VAR>(L, c.i, c.j + r, k, p, centre[r], lv, rv, w.down(r, centre, hd),
                                         w.up(r, centre, hu), below[r], above[r], s, nullptr);
         pnew[off + p] = centre[r];
-        q[off + p] = qv;
+        if (WQ) q[off + p] = qv;
         if (XUP && ap != T(0)) x[off + p] = xv[r] + ap * pold_c[r];
         dot += (double)centre[r] * (double)qv;
       }
@@ -1961,8 +2035,17 @@ void Launch<T>::jacobi(int dim, bool var, const LevelDev<T>& L, const T* b, cons
 template <typename T>
 void Launch<T>::jacobi_rup(int dim, bool var, const LevelDev<T>& L, const T* bold, const T* q, const double* alpha,
                            T* bout, T* xout, const T* shift, const int* active, T omega, double* partial, int nsys,
-                           hipStream_t st, unsigned long long* ctr, Fin fin) {
+                           hipStream_t st, unsigned long long* ctr, Fin fin, const T* p) {
   const dim3 g = stencil_grid(dim, L.n, nsys), blk(kTileX, kTileY);
+  if (dim == 3 && !q) {   // q formed from p
+    if (var)
+      hipLaunchKernelGGL((k_jacobi0_rup3p<T, true>), g, blk, 0, st, L, bold, p, alpha, bout, xout, shift, active,
+                         omega, partial, ctr, fin);
+    else
+      hipLaunchKernelGGL((k_jacobi0_rup3p<T, false>), g, blk, 0, st, L, bold, p, alpha, bout, xout, shift, active,
+                         omega, partial, ctr, fin);
+    return;
+  }
 #define K_JR(D, V, dummy)                                                                                         \
   hipLaunchKernelGGL((k_jacobi0_rup<T, D, V>), g, blk, 0, st, L, bold, q, alpha, bout, xout, shift, active, omega, \
                      partial, ctr, fin)
@@ -2057,13 +2140,14 @@ void Launch<T>::spmv_p(int dim, bool var, const LevelDev<T>& L, const T* z, cons
     return;
   }
   const dim3 g = march_grid(L.n, nsys, kMarchRows), blk(kTileX, kTileY);
-#define K_SP3(V, X_)                                                                                              \
-  hipLaunchKernelGGL((k_spmv_p3<T, V, X_>), g, blk, 0, st, L, z, pold, pnew, q, beta, shift, active, partial, ctr, \
-                     fin, x, alpha)
+#define K_SP3(V, X_, Q_)                                                                                          \
+  hipLaunchKernelGGL((k_spmv_p3<T, V, X_, Q_>), g, blk, 0, st, L, z, pold, pnew, q, beta, shift, active, partial, \
+                     ctr, fin, x, alpha)
+  // q == nullptr: only p_new.q (the first fine sweep forms q from p_new)
   if (var) {
-    if (xup) K_SP3(true, true); else K_SP3(true, false);
+    if (!q) K_SP3(true, true, false); else if (xup) K_SP3(true, true, true); else K_SP3(true, false, true);
   } else {
-    if (xup) K_SP3(false, true); else K_SP3(false, false);
+    if (!q) K_SP3(false, true, false); else if (xup) K_SP3(false, true, true); else K_SP3(false, false, true);
   }
 #undef K_SP3
 }
