@@ -111,6 +111,46 @@ def test_variable_coefficient_matches_direct_solves(prec):
     plan.close()
 
 
+@pytest.mark.parametrize("prec", ["FP64", "MIXED"])
+def test_variable_coefficient_3d_matches_direct_solves(prec):
+    """3D, variable coefficients: the first fine sweep forms (A + s) p from p
+    with the face weights while marching along z (no q stored)."""
+    from oracle import operators, shifted
+    B = _B()
+    n, dim, alpha, k = 23, 3, 0.6, 5   # 23 -> 11 -> 5 -> 2: the fine level is outside LDS
+    b = oracle_bura(alpha, k)
+    coeff = synth.lognormal_coefficient(n, dim, tag=43)
+    A, _ = operators.scaled_operator(n, dim, coeff)
+    F = synth.normal_rhs(n, dim, nrhs=2, tag=44)
+    ref = shifted.bura_by_solves(A, b.c_f64, b.d_f64, F)
+    plan = B.Plan(dim, n, weights=b.c_f64, shifts=[-x for x in b.d_f64], coeff=coeff, nrhs_max=2,
+                  precision=getattr(B, "BURA_" + prec), tol=1e-12)
+    _, nlev, _ = plan.info
+    assert nlev >= 2
+    res = plan.solve(_dev(F))
+    rel2, relinf = _errs(_host(res.u), ref)
+    print(f"var 3D {prec} levels={nlev} rel2={rel2:.2e} relinf={relinf:.2e} iters={list(res.report.iters)[:k+1]}")
+    assert rel2 <= 1e-9 and relinf <= 1e-9
+    plan.close()
+
+
+def test_q_buffer_only_where_a_kernel_reads_q(monkeypatch):
+    """Plans whose residual update forms q = (A + s) p from p (fused 2D down
+    kernel) hold one vector per system less than the 2D unfused plan, whose
+    first sweep reads q; nothing else differs between the two."""
+    B = _B()
+    n, k = 255, 5
+    fused = B.Plan(2, n, 0.5, k, nrhs_max=2, precision=B.BURA_FP64)
+    monkeypatch.setenv("BURA_UNFUSED", "1")
+    unfused = B.Plan(2, n, 0.5, k, nrhs_max=2, precision=B.BURA_FP64)
+    try:
+        bf, bu = fused.info[2], unfused.info[2]
+        assert bu - bf == (k + 1) * 2 * n * n * 8
+    finally:
+        fused.close()
+        unfused.close()
+
+
 def test_batched_equals_per_pole_and_alone_equals_mixed():
     """The same system gives bit-identical results whatever else is in the launch."""
     B = _B()
