@@ -709,15 +709,22 @@ __global__ __launch_bounds__(kBlock) void k_prolong3(LevelDev<T> Lc, LevelDev<T>
 
 // b_c = R (b - (A+s) x) in 3D.  A workgroup owns kRcx x kRcy coarse columns over
 // kMarchZ coarse planes, i.e. the (2 kRcx + 1) x (2 kRcy + 1) fine columns under
-// them.  Plane by plane, each fine point's residual is formed once (every
-// thread keeps x of its fine points at the plane below and at the current one
-// in registers) and put in LDS; each coarse column then takes the weighted
-// 3 x 3 sum of its plane, and the weighted sums of fine planes 2K, 2K+1, 2K+2
-// give coarse plane K (plane 2K+2 is shared with coarse plane K+1).
+// them.  Plane by plane, each fine point's residual is formed once and put in
+// LDS; each coarse column then takes the weighted 3 x 3 sum of its plane, and
+// the weighted sums of fine planes 2K, 2K+1, 2K+2 give coarse plane K (plane
+// 2K+2 is shared with coarse plane K+1).  Every thread keeps x of its fine
+// points at the plane below and at the current one in registers; the current
+// plane also goes to an LDS tile with a one-point ring (loaded by the first
+// threads), from which the in-plane neighbours are read, so a point costs two
+// loads per plane (x above, b) instead of six, and the kernel holds far fewer
+// registers (FP32: 98 VGPRs instead of 146, 4 waves per SIMD instead of 3).
 constexpr int kRcx = 32, kRcy = 8;
 constexpr int kRfx = 2 * kRcx + 1, kRfy = 2 * kRcy + 1, kRfn = kRfx * kRfy;
+constexpr int kRhx = kRfx + 2, kRhy = kRfy + 2, kRhn = kRhx * kRhy;   // with the ring
+constexpr int kRring = 2 * kRhx + 2 * (kRhy - 2);
 
 static_assert(kRcx * kRcy == 256, "one coarse column per thread");
+static_assert(kRring <= 256, "one ring point per thread at most");
 
 template <typename T, bool VAR>
 __global__ __launch_bounds__(256) void k_restrict3(LevelDev<T> Lf, LevelDev<T> Lc, const T* __restrict__ b,
@@ -726,6 +733,7 @@ __global__ __launch_bounds__(256) void k_restrict3(LevelDev<T> Lf, LevelDev<T> L
                                                    unsigned long long* __restrict__ ctr) {
   constexpr int PER = (kRfn + 255) / 256;
   __shared__ T rb[kRfn];
+  __shared__ T xt[kRhn];
   const Tile tl = block_tile();
   const int sys = tl.z;
   if (!active[sys]) return;
@@ -756,10 +764,46 @@ __global__ __launch_bounds__(256) void k_restrict3(LevelDev<T> Lf, LevelDev<T> L
       xc0[u] = xs[p];
     }
   }
+  // this thread's ring point (tid < kRring): its place in the tile and its
+  // in-plane offset (-1 when outside the grid: it holds 0)
+  int ring_h = -1;
+  long long ring_off = -1;
+  if (tid < kRring) {
+    int hx, hy;
+    if (tid < kRhx) {
+      hx = tid;
+      hy = 0;
+    } else if (tid < 2 * kRhx) {
+      hx = tid - kRhx;
+      hy = kRhy - 1;
+    } else {
+      const int t2 = tid - 2 * kRhx;
+      hx = (t2 & 1) ? kRhx - 1 : 0;
+      hy = 1 + (t2 >> 1);
+    }
+    ring_h = hy * kRhx + hx;
+    const int fi = 2 * I0 - 1 + hx, fj = 2 * J0 - 1 + hy;
+    if (fi >= 0 && fi < nf && fj >= 0 && fj < nf) ring_off = (long long)fj * nf + fi;
+  }
   const int ci = tid % kRcx, cj = tid / kRcx;
   // the residual on fine plane fk (into LDS), then this coarse column's
   // weighted in-plane sum of it; advances fk and the registers
   auto rplane = [&]() -> T {
+    // x of plane fk into the tile (0 off the grid), x above and b loaded
+    T xa[PER], bv[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int q = tid + 256 * u;
+      const int fy = q / kRfx, fx = q - fy * kRfx;
+      const int fi = 2 * I0 + fx, fj = 2 * J0 + fy;
+      const bool in = q < kRfn && fi < nf && fj < nf;
+      const long long p = fk * nnf + (in ? (long long)fj * nf + fi : 0LL);
+      xa[u] = xs[fk + 1 < nf ? p + nnf : p];
+      bv[u] = bs[p];
+      if (q < kRfn) xt[(fy + 1) * kRhx + fx + 1] = xc0[u];
+    }
+    if (ring_h >= 0) xt[ring_h] = ring_off >= 0 ? xs[fk * nnf + ring_off] : T(0);
+    __syncthreads();
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int q = tid + 256 * u;
@@ -769,13 +813,10 @@ __global__ __launch_bounds__(256) void k_restrict3(LevelDev<T> Lf, LevelDev<T> L
         T r = T(0);
         if (fi < nf && fj < nf) {
           const long long p = fk * nnf + (long long)fj * nf + fi;
-          const PlaneNb o = plane_nb(fi, fj, nf);
-          const T xa = xs[fk + 1 < nf ? p + nnf : p];
-          const T xl = xs[p + o.l], xr = xs[p + o.r], xd = xs[p + o.d], xu = xs[p + o.u];
-          const T bv = bs[p];
-          const T above = fk + 1 < nf ? xa : T(0);
-          r = bv - apply_col3<T, VAR>(Lf, fi, fj, fk, p, xc0[u], o.l ? xl : T(0), o.r ? xr : T(0),
-                                      o.d ? xd : T(0), o.u ? xu : T(0), xm[u], above, s, nullptr);
+          const int h = (fy + 1) * kRhx + fx + 1;
+          const T above = fk + 1 < nf ? xa[u] : T(0);
+          r = bv[u] - apply_col3<T, VAR>(Lf, fi, fj, fk, p, xc0[u], xt[h - 1], xt[h + 1], xt[h - kRhx], xt[h + kRhx],
+                                         xm[u], above, s, nullptr);
           xm[u] = xc0[u];
           xc0[u] = above;
         }
@@ -790,7 +831,8 @@ __global__ __launch_bounds__(256) void k_restrict3(LevelDev<T> Lf, LevelDev<T> L
       const int di = q % 3, dj = q / 3;
       acc += wt[dj] * wt[di] * rb[(2 * cj + dj) * kRfx + 2 * ci + di];
     }
-    __syncthreads();
+    // (the next plane writes rb only after its first barrier, which every
+    // thread reaches after this sum)
     ++fk;
     return acc;
   };
