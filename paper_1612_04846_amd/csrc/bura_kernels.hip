@@ -57,7 +57,8 @@ __device__ __forceinline__ void tile_ijk(const Tile& tl, int n, int& i, int& j, 
 }
 
 // 3D launches that march along z (the stencil product, the smoothing sweeps
-// and the FP64 residual): a workgroup of kTileX x kTileY threads owns that
+// and the FP64 residual): a workgroup of march_x(n) x (256 / march_x(n))
+// threads owns that
 // block of columns over kMarchZ consecutive planes, and each thread carries
 // its column's values at planes k-1, k, k+1 in registers from one plane to the
 // next, so the points above and below are not loaded again (a
@@ -65,7 +66,7 @@ __device__ __forceinline__ void tile_ijk(const Tile& tl, int n, int& i, int& j, 
 constexpr int kMarchZ = 8;
 // rows per thread of the marching kernels that write per-block partials (the
 // rows above and below a thread's interior rows come from its own registers;
-// a workgroup covers kTileX x (kTileY kMarchRows) columns)
+// a workgroup covers march_x(n) x ((256 / march_x(n)) kMarchRows) columns)
 constexpr int kMarchRows = 2;
 
 struct Column {
@@ -74,10 +75,12 @@ struct Column {
 
 __device__ __forceinline__ Column march_column(const Tile& tl, int n, int rows) {
   Column c;
-  const int yt = (n + kTileY * rows - 1) / (kTileY * rows);
+  // the workgroup's shape is chosen per grid (march_x on the host)
+  const int my = blockDim.y;
+  const int yt = (n + my * rows - 1) / (my * rows);
   const int kc = tl.y / yt;
-  c.i = tl.x * kTileX + threadIdx.x;
-  c.j = ((tl.y - kc * yt) * kTileY + threadIdx.y) * rows;
+  c.i = tl.x * blockDim.x + threadIdx.x;
+  c.j = ((tl.y - kc * yt) * my + threadIdx.y) * rows;
   c.k0 = kc * kMarchZ;
   c.k1 = min(c.k0 + kMarchZ, n);
   return c;
@@ -1981,9 +1984,18 @@ static inline dim3 point_grid(int dim, int n, int nsys) {
 }
 
 // 3D kernels marching along z: kMarchZ planes per workgroup, `rows` rows per thread
+// Threads along x of a marching workgroup on a grid of n points per axis (the
+// rest of the 256 along y).  Rows of n points are not aligned to 128-byte
+// lines, so a wide row segment wastes a smaller share of its lines (255^3
+// mixed: 64 -> 128 -> 256 columns took the solve from 39.9 to 37.4 to
+// 36.5 ms); a narrow grid would leave most of a wide workgroup idle.
+static inline int march_x(int n) { return n >= 192 ? 256 : (n >= 96 ? 128 : 64); }
+static inline dim3 march_block(int n) { return dim3(march_x(n), kBlock / march_x(n)); }
+
 static inline dim3 march_grid(int n, int nsys, int rows) {
-  const int xt = (n + kTileX - 1) / kTileX;
-  const int yt = (n + kTileY * rows - 1) / (kTileY * rows);
+  const int mx = march_x(n), my = kBlock / mx;
+  const int xt = (n + mx - 1) / mx;
+  const int yt = (n + my * rows - 1) / (my * rows);
   const int zt = (n + kMarchZ - 1) / kMarchZ;
   return dim3(xt, yt * zt, nsys);
 }
@@ -1993,6 +2005,7 @@ static inline dim3 march_grid(int n, int nsys, int rows) {
 static inline dim3 stencil_grid(int dim, int n, int nsys) {
   return dim == 3 ? march_grid(n, nsys, kMarchRows) : point_grid(dim, n, nsys);
 }
+static inline dim3 stencil_block(int dim, int n) { return dim == 3 ? march_block(n) : dim3(kTileX, kTileY); }
 
 int stencil_blocks(int dim, int n) {
   const dim3 g = stencil_grid(dim, n, 1);
@@ -2048,7 +2061,7 @@ template <typename T>
 void Launch<T>::jacobi(int dim, bool var, const LevelDev<T>& L, const T* b, const T* xin, T* xout, const T* shift,
                        const int* active, T omega, bool zero_guess, double* partial, int nsys, hipStream_t st,
                        unsigned long long* ctr, Fin fin) {
-  const dim3 g = stencil_grid(dim, L.n, nsys), blk(kTileX, kTileY);
+  const dim3 g = stencil_grid(dim, L.n, nsys), blk = stencil_block(dim, L.n);
   const bool dot = partial != nullptr;
 #define K_JAC(D, V, Z, DT)                                                                                      \
   do {                                                                                                          \
@@ -2078,7 +2091,7 @@ template <typename T>
 void Launch<T>::jacobi_rup(int dim, bool var, const LevelDev<T>& L, const T* bold, const T* q, const double* alpha,
                            T* bout, T* xout, const T* shift, const int* active, T omega, double* partial, int nsys,
                            hipStream_t st, unsigned long long* ctr, Fin fin, const T* p) {
-  const dim3 g = stencil_grid(dim, L.n, nsys), blk(kTileX, kTileY);
+  const dim3 g = stencil_grid(dim, L.n, nsys), blk = stencil_block(dim, L.n);
   if (dim == 3 && !q) {   // q formed from p
     if (var)
       hipLaunchKernelGGL((k_jacobi0_rup3p<T, true>), g, blk, 0, st, L, bold, p, alpha, bout, xout, shift, active,
@@ -2119,7 +2132,7 @@ void Launch<T>::prolong_add(int dim, const LevelDev<T>& Lc, const LevelDev<T>& L
     hipLaunchKernelGGL((k_prolong<T, 2>), point_grid(2, Lf.n, nsys), dim3(kTileX, kTileY), 0, st, Lc, Lf, xc, xf,
                        active, ctr);
   else
-    hipLaunchKernelGGL((k_prolong3<T>), march_grid(Lf.n, nsys, 1), dim3(kTileX, kTileY), 0, st, Lc, Lf, xc, xf,
+    hipLaunchKernelGGL((k_prolong3<T>), march_grid(Lf.n, nsys, 1), march_block(Lf.n), 0, st, Lc, Lf, xc, xf,
                        active, ctr);
 }
 
@@ -2181,7 +2194,7 @@ void Launch<T>::spmv_p(int dim, bool var, const LevelDev<T>& L, const T* z, cons
     });
     return;
   }
-  const dim3 g = march_grid(L.n, nsys, kMarchRows), blk(kTileX, kTileY);
+  const dim3 g = march_grid(L.n, nsys, kMarchRows), blk = march_block(L.n);
 #define K_SP3(V, X_, Q_)                                                                                          \
   hipLaunchKernelGGL((k_spmv_p3<T, V, X_, Q_>), g, blk, 0, st, L, z, pold, pnew, q, beta, shift, active, partial, \
                      ctr, fin, x, alpha)
@@ -2291,7 +2304,7 @@ void launch_residual64(int dim, bool var, const LevelDev<double>& L, const doubl
                        r32, nrhs, active64, partial);
     return;
   }
-  const dim3 g = stencil_grid(dim, L.n, nsys), blk(kTileX, kTileY);
+  const dim3 g = stencil_grid(dim, L.n, nsys), blk = stencil_block(dim, L.n);
   if (dim == 3) {
     if (var)
       hipLaunchKernelGGL((k_residual64_3<true>), g, blk, 0, st, L, f, x64, e, r32, shift, active64, nrhs, partial, ctr);
