@@ -134,6 +134,27 @@ def test_variable_coefficient_3d_matches_direct_solves(prec):
     plan.close()
 
 
+@pytest.mark.parametrize("n,prec", [(191, "FP64"), (95, "MIXED")])
+def test_3d_march_widths_with_ragged_tiles(n, prec):
+    """3D marching workgroups are 256, 128 or 64 columns wide by grid size:
+    191 -> 95 -> 47 -> 23 runs 128-column workgroups over a ragged second tile
+    (63 columns) and 64-column ones below, 95 starts at 64 columns."""
+    from oracle import spectral
+    B = _B()
+    alpha, k = 0.5, 5
+    b = oracle_bura(alpha, k)
+    F = synth.normal_rhs(n, 3, nrhs=1, tag=71)
+    plan = B.Plan(3, n, weights=b.c_f64, shifts=[-x for x in b.d_f64], precision=getattr(B, "BURA_" + prec),
+                  tol=1e-12)
+    res = plan.solve(_dev(F))
+    u = _host(res.u)
+    ref = spectral.bura_spectral(F, 3, b.c_f64, b.d_f64)
+    err = float(np.linalg.norm(u - ref) / np.linalg.norm(ref))
+    print(f"3D {n} {prec}: rel err {err:.2e}, iters {list(res.report.iters)[:k + 1]}")
+    assert err <= 1e-9
+    plan.close()
+
+
 def test_q_buffer_only_where_a_kernel_reads_q(monkeypatch):
     """Plans whose residual update forms q = (A + s) p from p (fused 2D down
     kernel) hold one vector per system less than the 2D unfused plan, whose
