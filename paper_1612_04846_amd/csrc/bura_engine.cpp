@@ -758,8 +758,10 @@ int count_active(bura_plan_t P, const int* dev_flags, size_t sys0, int nsys) {
 }
 
 // PCG on systems [sys0, sys0+nsys): r holds b, x holds 0, OP_INIT done.
+// defer_finish: leave each system's last deferred x update pending (the
+// caller's next kernel applies it: k_x_from_e in the refinement loop).
 template <typename T>
-int run_pcg(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, double tol, int max_iter) {
+int run_pcg(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, double tol, int max_iter, bool defer_finish = false) {
   hipStream_t st = P->stream;
   const int dim = P->dim;
   const LevelDev<T> L0 = level_view<T>(P, 0);
@@ -887,7 +889,7 @@ int run_pcg(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, double tol, int ma
     if (g) prof_graph(P, *g);
     if (a == 0) break;
   }
-  if (fx) {
+  if (fx && !defer_finish) {
     // the iterate update of each system's last iteration is still pending
     ProfScope ps(P, BURA_K_UPDATE_XR);
     Launch<T>::finish_x(P->N, W.x + o, W.p + o, W.p2 + o, S.alpha, S.iters, nsys, st, ps.ctr);
@@ -955,10 +957,14 @@ int solve_batch_mixed(bura_plan_t P, const double* f, int nrhs, size_t sys0, int
       return BURA_EDEVICE;
     }
     if (a == 0) break;
-    if ((rc = run_pcg<float>(P, W, sys0, nsys, P->opts.inner_tol, P->opts.max_iter))) return rc;
+    // with the folded updates, x64 += e also applies the inner solve's last
+    // deferred update (k_finish_x is not launched)
+    const bool fx = P->foldxr;
+    if ((rc = run_pcg<float>(P, W, sys0, nsys, P->opts.inner_tol, P->opts.max_iter, fx))) return rc;
     {
       ProfScope ps(P, BURA_K_OTHER);
-      launch_x_from_e(L0, P->dim, W.x + o, P->x64 + o, S.active64, nsys, st);
+      launch_x_from_e(L0, P->dim, W.x + o, P->x64 + o, S.active64, nsys, st, fx ? W.p + o : nullptr,
+                      fx ? W.p2 + o : nullptr, S.alpha, S.iters);
     }
     {
       ProfScope ps(P, BURA_K_RESIDUAL64);

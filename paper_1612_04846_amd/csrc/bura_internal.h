@@ -146,8 +146,11 @@ struct Launch {
 void launch_residual64(int dim, bool var, const LevelDev<double>& L, const double* f, const double* x64, float* e,
                        float* r32, const double* shift, const int* active64, double* partial, int nrhs, int nsys,
                        bool first, hipStream_t st, unsigned long long* ctr);
+// x64 += e; with pa != nullptr e first takes the inner solve's pending update
+// e + alpha p (p = pa or pb by the parity of the system's iteration count)
 void launch_x_from_e(const LevelDev<double>& L, int dim, const float* e, double* x64, const int* active64,
-                     int nsys, hipStream_t st);
+                     int nsys, hipStream_t st, const float* pa = nullptr, const float* pb = nullptr,
+                     const double* alpha = nullptr, const int* iters = nullptr);
 // u_r = base_w base_r + sum_j w_j x_{j stride + r}; with w_per_system the weight
 // of term j of rhs r is w[j stride + r] and zero weights skip their term
 void launch_combine(long long N, const double* x, const double* w, int nterms, int nrhs, int stride, double* u,

@@ -1815,24 +1815,35 @@ __global__ __launch_bounds__(256) void k_first_residual(long long N, const doubl
 }
 
 // x64 += e (final refinement update after the last inner solve)
+// With pa != nullptr the inner solve's last deferred iterate update is
+// applied here too (as k_finish_x would, in FP32 and the same expression):
+// e + alpha p_last is formed in registers and never stored, one pass less.
 __global__ __launch_bounds__(256) void k_x_from_e(long long N, const float* __restrict__ e, double* __restrict__ x64,
-                                                  const int* __restrict__ active64) {
+                                                  const int* __restrict__ active64, const float* __restrict__ pa,
+                                                  const float* __restrict__ pb, const double* __restrict__ alpha,
+                                                  const int* __restrict__ iters) {
   const int sys = blockIdx.y;
   if (!active64[sys]) return;
   const long long off = (long long)sys * N;
   const long long base = (long long)blockIdx.x * 256 * kFlatItems + threadIdx.x;
+  const int its = pa ? iters[sys] : 0;
+  const float a = pa ? (float)alpha[sys] : 0.0f;
+  const bool pend = its > 0 && a != 0.0f;
+  const float* pl = ((its - 1) & 1) ? pa : pb;
   double xl[kFlatItems];
-  float el[kFlatItems];
+  float el[kFlatItems], pv[kFlatItems];
 #pragma unroll
   for (int it = 0; it < kFlatItems; ++it) {
     const long long p = min(base + (long long)it * 256, N - 1);
     xl[it] = x64[off + p];
     el[it] = e[off + p];
+    pv[it] = pend ? pl[off + p] : 0.0f;
   }
 #pragma unroll
   for (int it = 0; it < kFlatItems; ++it) {
     const long long p = base + (long long)it * 256;
-    if (p < N) x64[off + p] = xl[it] + (double)el[it];
+    const float en = pend ? el[it] + a * pv[it] : el[it];
+    if (p < N) x64[off + p] = xl[it] + (double)en;
   }
 }
 
@@ -2320,9 +2331,10 @@ void launch_residual64(int dim, bool var, const LevelDev<double>& L, const doubl
 }
 
 void launch_x_from_e(const LevelDev<double>& L, int dim, const float* e, double* x64, const int* active64, int nsys,
-                     hipStream_t st) {
+                     hipStream_t st, const float* pa, const float* pb, const double* alpha, const int* iters) {
   (void)dim;
-  hipLaunchKernelGGL(k_x_from_e, flat_grid(L.N, nsys), dim3(256), 0, st, L.N, e, x64, active64);
+  hipLaunchKernelGGL(k_x_from_e, flat_grid(L.N, nsys), dim3(256), 0, st, L.N, e, x64, active64, pa, pb, alpha,
+                     iters);
 }
 
 void launch_combine(long long N, const double* x, const double* w, int nterms, int nrhs, int stride, double* u,
