@@ -903,6 +903,14 @@ int set_flags(bura_plan_t P, int* dev, size_t sys0, int nsys, int value) {
   return BURA_OK;
 }
 
+// FP64 plans without stages leave each system's last deferred iterate update
+// to the combine, which reads x anyway (k_finish_x would read and write it
+// once more); a later stage of a sequential form reads x itself, so staged
+// plans finish it.
+bool combine_finishes_x(const bura_plan_t P) {
+  return P->foldxr && P->opts.precision == BURA_FP64 && P->stages.empty();
+}
+
 int solve_batch_fp64(bura_plan_t P, const double* f, int nrhs, size_t sys0, int nsys, bool preset) {
   hipStream_t st = P->stream;
   Work<double>& W = P->w64;
@@ -922,7 +930,7 @@ int solve_batch_fp64(bura_plan_t P, const double* f, int nrhs, size_t sys0, int 
     ProfScope ps(P, BURA_K_OTHER);
     launch_scalars(OP_INIT, P->partial, flat_blocks(P->N), nsys, S, P->opts.tol, P->opts.max_iter, st);
   }
-  return run_pcg<double>(P, W, sys0, nsys, P->opts.tol, P->opts.max_iter);
+  return run_pcg<double>(P, W, sys0, nsys, P->opts.tol, P->opts.max_iter, combine_finishes_x(P));
 }
 
 int solve_batch_mixed(bura_plan_t P, const double* f, int nrhs, size_t sys0, int nsys, bool preset) {
@@ -1071,7 +1079,9 @@ int do_solve(bura_plan_t P, const double* f, double* u, int nrhs, bura_report_t*
     rc = batch(0, (int)S_used, true);
     if (rc) return rc;
     ProfScope ps(P, BURA_K_COMBINE);
-    launch_combine(P->N, xsol, P->d_wsys, P->nterms, nrhs, R, u, P->stream, ps.ctr, nullptr, 0.0, true);
+    const bool pend = combine_finishes_x(P);
+    launch_combine(P->N, xsol, P->d_wsys, P->nterms, nrhs, R, u, P->stream, ps.ctr, nullptr, 0.0, true,
+                   pend ? P->w64.p : nullptr, pend ? P->w64.p2 : nullptr, P->st.alpha, P->st.iters);
   } else if (!P->stages.empty()) {
     // sequential form: each stage solves its terms against its input, then
     // combines into the stage buffer (or u for the last stage)
@@ -1115,8 +1125,11 @@ int do_solve(bura_plan_t P, const double* f, double* u, int nrhs, bura_report_t*
   for (int i = 0; i < P->nout && P->stages.empty() && !slot; ++i) {
     ProfScope ps(P, BURA_K_COMBINE);
     const int b = P->out_begin[i], e = P->out_end[i];
-    launch_combine(P->N, xsol + (size_t)b * R * P->N, P->d_w + b, e - b, nrhs, R, u + (size_t)i * nrhs * P->N,
-                   P->stream, ps.ctr);
+    const size_t ob = (size_t)b * R;   // first system of output i
+    const bool pend = combine_finishes_x(P);
+    launch_combine(P->N, xsol + ob * P->N, P->d_w + b, e - b, nrhs, R, u + (size_t)i * nrhs * P->N, P->stream,
+                   ps.ctr, nullptr, 0.0, false, pend ? P->w64.p + ob * P->N : nullptr,
+                   pend ? P->w64.p2 + ob * P->N : nullptr, P->st.alpha + ob, P->st.iters + ob);
   }
   HIPCHK(hipGetLastError());
   // report: one copy of the per-system scalar state into pinned memory

@@ -152,10 +152,14 @@ void launch_x_from_e(const LevelDev<double>& L, int dim, const float* e, double*
                      int nsys, hipStream_t st, const float* pa = nullptr, const float* pb = nullptr,
                      const double* alpha = nullptr, const int* iters = nullptr);
 // u_r = base_w base_r + sum_j w_j x_{j stride + r}; with w_per_system the weight
-// of term j of rhs r is w[j stride + r] and zero weights skip their term
+// of term j of rhs r is w[j stride + r] and zero weights skip their term.
+// With pa != nullptr system s = j stride + r still has its last deferred
+// update pending (alpha[s], p = pa or pb by the parity of iters[s]; arrays
+// indexed from the same first system as x), applied to x_s as it is read.
 void launch_combine(long long N, const double* x, const double* w, int nterms, int nrhs, int stride, double* u,
                     hipStream_t st, unsigned long long* ctr, const double* base = nullptr, double base_w = 0.0,
-                    bool w_per_system = false);
+                    bool w_per_system = false, const double* pa = nullptr, const double* pb = nullptr,
+                    const double* alpha = nullptr, const int* iters = nullptr);
 void launch_apply64(int dim, bool var, const LevelDev<double>& L, const double* x, double* y, double shift,
                     int nvec, hipStream_t st);
 void launch_scalars(int op, const double* partial, int nblk, int nsys, SysState st_, double tol,

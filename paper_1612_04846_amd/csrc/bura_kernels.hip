@@ -1850,22 +1850,32 @@ __global__ __launch_bounds__(256) void k_x_from_e(long long N, const float* __re
 // u[r] = base_w base[r] + sum_j w_j x[j * stride + r], summed in the fixed order
 // base, j = 0..nterms-1 (eq. (16); the base term serves the sequential forms).
 // base may be u itself (each element is read before it is written).
+// With pa != nullptr each system's last deferred iterate update is still
+// pending and is applied here, as k_finish_x would (same expression), while x
+// is read: x_j + alpha_j p_j, never stored (p = pa or pb by the parity of the
+// system's iteration count).
 __global__ __launch_bounds__(256) void k_combine(long long N, const double* x, const double* __restrict__ w,
                                                  int nterms, int stride, double* u, const double* base,
-                                                 double base_w, unsigned long long* __restrict__ ctr, int wsys) {
+                                                 double base_w, unsigned long long* __restrict__ ctr, int wsys,
+                                                 const double* __restrict__ pa, const double* __restrict__ pb,
+                                                 const double* __restrict__ alpha, const int* __restrict__ iters) {
   const int r = blockIdx.y;
   const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
-  count_bytes<COUNT_FLAT>(ctr, (unsigned long long)N * 8ULL * (nterms + 1 + (base ? 1 : 0)));
+  count_bytes<COUNT_FLAT>(ctr, (unsigned long long)N * 8ULL * (nterms * (pa ? 2 : 1) + 1 + (base ? 1 : 0)));
   if (p >= N) return;
   double acc = base ? base_w * base[(long long)r * N + p] : 0.0;
   for (int j = 0; j < nterms; ++j) {
-    if (wsys) {
-      // per-system weights: a zero weight marks an unused slot, whose x is not read
-      const double wv = w[(long long)j * stride + r];
-      if (wv != 0.0) acc += wv * x[((long long)j * stride + r) * N + p];
-    } else {
-      acc += w[j] * x[((long long)j * stride + r) * N + p];
+    const long long sys = (long long)j * stride + r;
+    const double wv = wsys ? w[sys] : w[j];
+    // per-system weights: a zero weight marks an unused slot, whose x is not read
+    if (wsys && wv == 0.0) continue;
+    double xv = x[sys * N + p];
+    if (pa) {
+      const int it = iters[sys];
+      const double a = alpha[sys];
+      if (it > 0 && a != 0.0) xv = xv + a * (((it - 1) & 1) ? pa : pb)[sys * N + p];
     }
+    acc += wv * xv;
   }
   u[(long long)r * N + p] = acc;
 }
@@ -2338,10 +2348,11 @@ void launch_x_from_e(const LevelDev<double>& L, int dim, const float* e, double*
 }
 
 void launch_combine(long long N, const double* x, const double* w, int nterms, int nrhs, int stride, double* u,
-                    hipStream_t st, unsigned long long* ctr, const double* base, double base_w, bool w_per_system) {
+                    hipStream_t st, unsigned long long* ctr, const double* base, double base_w, bool w_per_system,
+                    const double* pa, const double* pb, const double* alpha, const int* iters) {
   const dim3 g((unsigned)((N + 255) / 256), nrhs);
   hipLaunchKernelGGL(k_combine, g, dim3(256), 0, st, N, x, w, nterms, stride, u, base, base_w, ctr,
-                     w_per_system ? 1 : 0);
+                     w_per_system ? 1 : 0, pa, pb, alpha, iters);
 }
 
 void launch_apply64(int dim, bool var, const LevelDev<double>& L, const double* x, double* y, double shift, int nvec,
