@@ -2,21 +2,21 @@
 
 TEST INFRASTRUCTURE (see the package docstring): slow, multiprecision, plain.
 
-Follows the paper (arXiv:1612.04846):
+What is computed (arXiv:1612.04846):
 
 * Definition 2.1 / eq. (11): r = P_m/Q_k minimises max_[0,1] |t^(beta-alpha) - r|;
-  E_alpha(m,k;beta) is that maximum.
-* eq. (18): P and Q are written in the shifted Chebyshev basis T_j(2t-1) and the
-  algorithm works with s = 2t-1 in [-1,1] and f(s) = ((1+s)/2)^(beta-alpha).
-* Section 3.2, Algorithm 3.1 ("modified Remez"):
-    Step 1 (i)-(ii): new reference points s_i = argmax |f - r| between the
-      zeros of f - r that bracket the old s_i; (iii)-(iv): global maximiser and
-      the sign-rule exchange;
-    Step 2: stop when max eta_i - min eta_i < delta;
-    Step 3: solve f(s_i) - r(s_i) = (-1)^i E for r and E by repeatedly solving
-      the l x l linear system in which E of the previous sweep multiplies the
-      denominator, accelerated by Aitken-Steffensen (remark (3) after the
-      algorithm).  Rational functions are normalised with qbar_0 = 1.
+  E_alpha(m,k;beta) is that maximum.  By the equioscillation theorem quoted in
+  Section 3.1 the error reaches +-E with alternating signs at m+k+2 points, and
+  that property is the test of every result.
+* eq. (18): P and Q are written in the shifted Chebyshev basis T_j(2t-1); the
+  iteration works with s = 2t-1 in [-1,1] and f(s) = ((1+s)/2)^(beta-alpha),
+  with the denominator normalised to qbar_0 = 1.
+* The iteration is the modified Remez algorithm of Section 3.2 (Algorithm 3.1):
+  from the current rational function, move the reference set to the extrema
+  of the error between its sign changes; stop when those extrema are level;
+  otherwise solve the levelled equations f(s_i) - r(s_i) = (-1)^i E on the new
+  set for r and E, by the paper's linear solves with E of the previous sweep
+  frozen in the denominator term, accelerated by Aitken-Steffensen.
 * Lemma 2.5 and eq. (15): for m = k, beta = 1 the poles are real, negative and
   simple; r(t)/t = sum_{j=0..k} c_j/(t - d_j) with d_0 = 0.  The weights are the
   residues of P/(t Q): c_0 = P(0)/Q(0) = r(0) and c_j = P(d_j)/(d_j Q'(d_j)).
@@ -32,11 +32,18 @@ Readings where the paper is silent (also listed in the design notes):
   ~ E^(1/(beta-alpha)) from the asymptotic formula eq. (14)), then the nodes
   are moved by repeated local-error equalisation of the interpolant (each
   node interval is rescaled by its local maximum error) until the local
-  maxima agree to a few per cent.  The extrema of that interpolant's error are
-  s^(0) and its largest error is E_0.  This is an initialisation only: the
-  result is the unique BURA fixed by Algorithm 3.1's levelling and exchange.
-* Extremum localisation: zoomed grid search in log t (remark (2) after the
-  algorithm describes the same idea), endpoints t = 0 and t = 1 included.
+  maxima agree to a few per cent.  That interpolant is r_0 (its error
+  alternates at the extrema, so it is admissible) and the extrema are s^(0).
+* Which solution of the levelled equations.  They have k+1 solutions E (after
+  eliminating pbar they are a (k+1) x (k+1) eigenproblem for E), and the
+  frozen-E iteration can settle on any of them; only one has a denominator of
+  one sign on the reference set, the admissible one that the algorithm
+  requires of r_0 and of every later iterate.  When the iteration ends
+  elsewhere (it does for alpha = 0.9, k = 8, 10, 11, 12 from the start above),
+  the iteration is restarted from that admissible root, found from the
+  eigenproblem.
+* Extremum localisation: zoomed grid search in log t (the remarks after
+  Algorithm 3.1 describe the same idea), endpoints t = 0 and t = 1 included.
 * delta is relative: max eta - min eta < delta_rel * max eta.
 """
 
@@ -133,26 +140,30 @@ class Bura:
 
 
 # ----------------------------------------------------------------------------
-# Step 3: the levelled nonlinear system, solved by the paper's iteration
+# the levelled equations f(s_i) - r(s_i) = (-1)^i E on a reference set
 # ----------------------------------------------------------------------------
 
-def _level(S, fS, m, k, E0, tol):
-    """Solve f(s_i) - r(s_i) = (-1)^i E (i = 1..l) for r and E.
+def _sigma(i):
+    """(-1)^i for the i-th reference point counted from 1 (i = 0 here is the first)."""
+    return -1 if i % 2 == 0 else 1
 
-    Step 3(ii): with E^(v-1) fixed inside the denominator term the system
-        sum_j pbar_j T_j(s_i) - (f_i - (-1)^i E^(v-1)) sum_{j>=1} qbar_j T_j(s_i)
-            + (-1)^i E^(v) = f_i
-    is linear in (pbar, qbar_1..k, E^(v)).  The map E^(v-1) -> E^(v) is iterated
-    with Aitken-Steffensen acceleration (remark (3)).
-    """
-    L = len(S)
-    Ts = [_cheb(s, max(m, k)) for s in S]
+
+def _level_sweeps(Ts, fS, m, k, E0, tol):
+    """The paper's iteration for the levelled equations: with E_old frozen in the
+    denominator term,
+
+        sum_j pbar_j T_j(s_i) - (f_i - (-1)^i E_old) sum_{j>=1} qbar_j T_j(s_i)
+            + (-1)^i E_new = f_i
+
+    is linear in (pbar, qbar_1..k, E_new); the map E_old -> E_new is iterated
+    from E0 with Aitken-Steffensen acceleration.  Returns (E, pbar, qbar)."""
+    L = len(fS)
 
     def sweep(E):
         A = mp.matrix(L, L)
         b = mp.matrix(L, 1)
         for i in range(L):
-            sg = -1 if i % 2 == 0 else 1          # (-1)^i with i counted from 1
+            sg = _sigma(i)
             for j in range(m + 1):
                 A[i, j] = Ts[i][j]
             for j in range(1, k + 1):
@@ -179,11 +190,62 @@ def _level(S, fS, m, k, E0, tol):
         # stagnation at the working precision's noise floor is accepted when
         # the fixed point is already resolved far below the levelling tolerance
         if best[0] > mp.sqrt(tol) * abs(best[1]):
-            raise RemezError("levelled system (Step 3) did not converge")
+            raise RemezError("levelled equations: the iteration did not converge")
         E = best[1]
     E, x = sweep(E)
     pbar = [x[j] for j in range(m + 1)]
     qbar = [mp.mpf(1)] + [x[m + j] for j in range(1, k + 1)]
+    return E, pbar, qbar
+
+
+def _admissible(Ts, qbar):
+    """The denominator has one sign on the reference set."""
+    Q = [mp.fsum(qbar[j] * T[j] for j in range(len(qbar))) for T in Ts]
+    return all(v > 0 for v in Q) or all(v < 0 for v in Q)
+
+
+def _admissible_root(Ts, fS, m, k):
+    """The levelled equations as an eigenproblem: P(s_i) = (f_i - (-1)^i E) Q(s_i).
+    With N spanning the left null space of [T_j(s_i)]_{j<=m}, pbar drops out:
+    N^T F V qbar = E N^T Sigma V qbar, V = [T_j(s_i)]_{j<=k}, F = diag(f_i),
+    Sigma = diag((-1)^i).  Returns the real eigenvalue whose eigenvector gives a
+    denominator of one sign on the reference set."""
+    L = len(fS)
+    VP = mp.matrix(L, m + 1)
+    for i in range(L):
+        for j in range(m + 1):
+            VP[i, j] = Ts[i][j]
+    Qf, _ = mp.qr(VP, mode="full")
+    N = Qf[:, m + 1:L]
+    FV = mp.matrix(L, k + 1)
+    SV = mp.matrix(L, k + 1)
+    for i in range(L):
+        for j in range(k + 1):
+            FV[i, j] = fS[i] * Ts[i][j]
+            SV[i, j] = _sigma(i) * Ts[i][j]
+    vals, vecs = mp.eig(mp.inverse(N.T * SV) * (N.T * FV))
+    scale = max(abs(v) for v in vals)
+    found = []
+    for c, lam in enumerate(vals):
+        if abs(mp.im(lam)) > mp.mpf(10) ** (-(mp.mp.dps // 3)) * scale:
+            continue
+        q = [mp.re(vecs[j, c]) for j in range(k + 1)]
+        if _admissible(Ts, q):
+            found.append(mp.re(lam))
+    if len(found) != 1:
+        raise RemezError(f"levelled equations: {len(found)} admissible solutions")
+    return found[0]
+
+
+def _level(S, fS, m, k, E0, tol):
+    """Solve f(s_i) - r(s_i) = (-1)^i E (i = 1..l) for an admissible r and E,
+    starting the paper's iteration from E0 (the previous levelled value)."""
+    Ts = [_cheb(s, max(m, k)) for s in S]
+    E, pbar, qbar = _level_sweeps(Ts, fS, m, k, E0, tol)
+    if not _admissible(Ts, qbar):
+        E, pbar, qbar = _level_sweeps(Ts, fS, m, k, _admissible_root(Ts, fS, m, k), tol)
+        if not _admissible(Ts, qbar):
+            raise RemezError("levelled equations: no admissible solution")
     return pbar, qbar, E
 
 
@@ -315,9 +377,27 @@ def required_dps(alpha, k, m=None, beta=1, tmin=None):
     return int(40 + max(m, k) * max(float(digits), 1.0))
 
 
+def _exchange(e, S, dps):
+    """New reference set from the current error e = f - r: the point of largest
+    |e| between each pair of consecutive sign changes (the first interval
+    starts at s = -1, the last ends at s = 1, both included).  The error must
+    alternate on the old set; the largest |e| on [-1,1] is then one of the new
+    points."""
+    L = len(S)
+    ev = [e(s) for s in S]
+    for i in range(L - 1):
+        if (ev[i] > 0) == (ev[i + 1] > 0):
+            raise RemezError("the error does not alternate on the reference set")
+    Z = [mp.mpf(-1)]
+    Z += [_zero_between(e, S[i], S[i + 1], ev[i], mp.mpf(10) ** (-(dps // 2))) for i in range(L - 1)]
+    Z.append(mp.mpf(1))
+    return [_argmax_abs(e, Z[i], Z[i + 1], i == 0, i == L - 1, 2 * dps) for i in range(L)]
+
+
 def remez(alpha, k, m=None, beta=1, dps=None, delta_rel=1e-20, max_iter=60,
           start: Optional[Sequence] = None) -> Bura:
-    """Modified Remez algorithm (Algorithm 3.1) for the beta-BURA of t^(beta-alpha).
+    """Modified Remez algorithm (Section 3.2, Algorithm 3.1) for the beta-BURA
+    of t^(beta-alpha): exchange, level check, levelled solve, until level.
 
     ``start`` optionally gives interpolation nodes in t (m+k+1 of them) for the
     initialisation, e.g. taken from a neighbouring (alpha, k).  ``dps`` defaults
@@ -329,55 +409,23 @@ def remez(alpha, k, m=None, beta=1, dps=None, delta_rel=1e-20, max_iter=60,
     with mp.workdps(dps):
         g = mp.mpf(beta) - mp.mpf(alpha)
         f = lambda s: ((1 + s) / 2) ** g
-        L = m + k + 2
         delta = mp.mpf(delta_rel)
-        X0 = [mp.mpf(x) for x in start] if start is not None else None
-        S, E0, _, _ = _initial_reference(alpha, beta, m, k, X=X0)
-        S = sorted(S)
-        S[0] = mp.mpf(-1)
-        S[-1] = mp.mpf(1)
-        # r_0: levelled solution on s^(0) -- admissible by construction
-        fS = [f(s) for s in S]
         ltol = mp.mpf(10) ** (-(dps * 2) // 3)
-        pbar, qbar, E = _level(S, fS, m, k, E0, ltol)
+        X0 = [mp.mpf(x) for x in start] if start is not None else None
+        # admissible r_0 (the equalised interpolant), s^(0) = its error's extrema
+        S, E, pbar, qbar = _initial_reference(alpha, beta, m, k, X=X0)
+        S = sorted(S)
+        S[0], S[-1] = mp.mpf(-1), mp.mpf(1)
         it = 0
         for it in range(1, max_iter + 1):
             e = lambda s: f(s) - _ratval(pbar, qbar, s)
-            ev = [e(s) for s in S]
-            for i in range(L - 1):
-                if (ev[i] > 0) == (ev[i + 1] > 0):
-                    raise RemezError(f"alternation lost at iteration {it}")
-            # Step 1(i): zeros of f - r between consecutive reference points
-            Z = [mp.mpf(-1)]
-            for i in range(L - 1):
-                Z.append(_zero_between(e, S[i], S[i + 1], ev[i], mp.mpf(10) ** (-(dps // 2))))
-            Z.append(mp.mpf(1))
-            # Step 1(ii): local maximisers of |f - r|
-            Snew = [
-                _argmax_abs(e, Z[i], Z[i + 1], i == 0, i == L - 1, 2 * dps)
-                for i in range(L)
-            ]
-            etas = [abs(e(s)) for s in Snew]
-            # Step 1(iii)-(iv): global maximiser and the sign-rule exchange
-            jstar = max(range(L), key=lambda i: etas[i])
-            # the global maximum over [-1,1] is the largest local maximum over the
-            # L sub-intervals between consecutive zeros, so s_* is already in the
-            # set; the exchange rule is a no-op here but kept for clarity
-            s_star = Snew[jstar]
-            if s_star not in Snew:  # pragma: no cover - unreachable by construction
-                j = max(i for i in range(L) if Snew[i] < s_star)
-                if (e(s_star) > 0) == (e(Snew[j]) > 0):
-                    Snew[j] = s_star
-                else:
-                    Snew[j + 1] = s_star
-            S = Snew
-            if _VERBOSE: print("remez it", it, mp.nstr(E, 12), mp.nstr((max(etas) - min(etas)) / max(etas), 3), flush=True)
-            # Step 2: convergence check
+            S = _exchange(e, S, dps)
+            etas = [abs(e(s)) for s in S]
+            if _VERBOSE:
+                print("remez it", it, mp.nstr(E, 12), mp.nstr((max(etas) - min(etas)) / max(etas), 3), flush=True)
             if max(etas) - min(etas) < delta * max(etas):
                 break
-            # Step 3: new levelled approximation
-            fS = [f(s) for s in S]
-            pbar, qbar, E = _level(S, fS, m, k, E, ltol)
+            pbar, qbar, E = _level(S, [f(s) for s in S], m, k, E, ltol)
         else:
             raise RemezError("Algorithm 3.1 reached its iteration limit")
         eta = [(s + 1) / 2 for s in S]
