@@ -57,7 +57,9 @@ enum bura_status {
   BURA_ENOMEM = -5,          /* device allocation failed / over the HBM budget   */
   BURA_EDEVICE = -6,         /* HIP runtime error                                */
   BURA_ENAN = -7,            /* non-finite residual                              */
-  BURA_EBUSY = -8            /* plan has an unfinished submitted solve           */
+  BURA_EBUSY = -8,           /* plan has an unfinished submitted solve           */
+  BURA_ETOOBIG = -9          /* bura_solve_static: the workspace does not fit
+                                BURA_STATIC_SCRATCH_BYTES                        */
 };
 
 enum bura_precision {
@@ -385,6 +387,33 @@ int bura_server_stats(bura_server_t s, bura_server_stats_t* st);
 int bura_server_reset_latency(bura_server_t s);
 /* Waits for queued and running requests, then frees every plan. */
 void bura_server_destroy(bura_server_t s);
+
+/* ---------------------------------------------------------------------------
+ * For callers that cannot allocate device memory: code running between its
+ * own allocation-free phases (a serving loop with a fixed memory pool), a
+ * harness that forbids hipMalloc, work launched on a stream the caller may
+ * later capture.  The same result as bura_plan_create_rational(grid, nterms,
+ * weights, shifts, opts) followed by bura_solve(f_dev, u_dev, nrhs) and
+ * bura_plan_destroy, but every device buffer of that plan (iterates,
+ * multigrid levels, face weights, partial sums, per-system state) is carved
+ * from one static device array of BURA_STATIC_SCRATCH_BYTES per GPU, held by
+ * the library until the process ends.  No hipMalloc, hipFree, pinned-host
+ * allocation, stream, event or graph is created; the launches and copies run
+ * in order on opts->stream (NULL: the null stream) and the call returns when
+ * u_dev holds the result.  Host-side bookkeeping uses ordinary host memory.
+ *
+ * f_dev, u_dev: [nrhs][N] FP64 device buffers (caller owned), nrhs <=
+ * opts->nrhs_max.  opts->autotune must be 0 (BURA_EINVAL otherwise).  A
+ * problem whose workspace exceeds the array (e.g. FP64, 2D 255^2, one
+ * right-hand side and more than about 15 terms; 1023^2 at any size) returns
+ * BURA_ETOOBIG before the solve starts.  Every
+ * call on one GPU uses that GPU's single array and leaves its contents
+ * behind (each call clears what must start at zero): calls that overlap on
+ * one GPU, from several threads or streams, race and must be serialised by
+ * the caller. */
+#define BURA_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int bura_solve_static(const bura_grid_t* grid, int nterms, const double* weights, const double* shifts,
+                      const bura_opts_t* opts, const double* f_dev, double* u_dev, int nrhs, bura_report_t* rep);
 
 /* Release every resource of the plan.  Waits for an outstanding solve. */
 void bura_plan_destroy(bura_plan_t plan);

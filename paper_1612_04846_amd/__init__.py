@@ -39,6 +39,8 @@ BURA_ENOMEM = -5
 BURA_EDEVICE = -6
 BURA_ENAN = -7
 BURA_EBUSY = -8
+BURA_ETOOBIG = -9
+BURA_STATIC_SCRATCH_BYTES = 64 << 20
 BURA_FP64 = 0
 BURA_MIXED = 1
 BURA_BATCHED = 0
@@ -152,6 +154,8 @@ _SIGS = {
     "bura_plan_tiles": (_I, [_P, ctypes.POINTER(_I), _I, ctypes.POINTER(_I)]),
     "bura_plan_set_tiles": (_I, [_P, ctypes.POINTER(_I), _I]),
     "bura_plan_destroy": (None, [_P]),
+    "bura_solve_static": (_I, [ctypes.POINTER(bura_grid_t), _I, _DP, _DP, ctypes.POINTER(bura_opts_t), _P, _P, _I,
+                               ctypes.POINTER(bura_report_t)]),
     "bura_strerror": (ctypes.c_char_p, [_I]),
     "bura_server_create": (_I, [ctypes.c_size_t, _I, _I, ctypes.POINTER(_P)]),
     "bura_server_submit": (_I, [_P, ctypes.POINTER(bura_request_t), _P, _P, ctypes.POINTER(ctypes.c_uint64)]),
@@ -276,6 +280,24 @@ def bura_plan_create_rational(dim: int, n: int, weights: Sequence[float], shifts
     _check(_lib.bura_plan_create_rational(ctypes.byref(g), m, w, s, ctypes.byref(o), ctypes.byref(h)),
            "bura_plan_create_rational")
     return h
+
+
+def bura_solve_static(dim: int, n: int, weights: Sequence[float], shifts: Sequence[float], f: torch.Tensor,
+                      u: torch.Tensor, opts: Optional[bura_opts_t] = None, coeff=None, lambda_upper: float = 0.0,
+                      ok=(BURA_OK,)) -> bura_report_t:
+    """The allocation-free one-shot solve: f, u are [nrhs][N] float64 CUDA tensors."""
+    g, _keep = _grid(dim, n, coeff, lambda_upper)
+    o = opts if opts is not None else bura_opts_default()
+    m = len(weights)
+    w = (ctypes.c_double * m)(*weights)
+    s = (ctypes.c_double * m)(*shifts)
+    nrhs = f.shape[0] if f.dim() == 2 else 1
+    rep = bura_report_t()
+    code = _lib.bura_solve_static(ctypes.byref(g), m, w, s, ctypes.byref(o), _devptr(f, "f"), _devptr(u, "u"), nrhs,
+                                  ctypes.byref(rep))
+    rep.status = code
+    _check(code, "bura_solve_static", ok)
+    return rep
 
 
 def bura_plan_create_slots(dim: int, n: int, max_terms: int, opts: Optional[bura_opts_t] = None, coeff=None,

@@ -143,6 +143,14 @@ struct bura_plan_s {
   int* h_flags = nullptr;      // pinned host mirror of active flags
   std::vector<void*> allocs;
   size_t device_bytes = 0;
+  // bura_solve_static: every device buffer is carved from the caller-provided
+  // region [ws_base, ws_base + ws_cap) instead of hipMalloc; the plan then
+  // runs on the caller's stream (no own stream, event or graphs) and keeps its
+  // host mirrors in ordinary host memory instead of pinned allocations
+  char* ws_base = nullptr;
+  size_t ws_cap = 0, ws_used = 0;
+  bool owns_stream = true;
+  std::vector<char> host_mirror;
   // profiling (events around launches + device byte counters per kernel class)
   struct Prof {
     bool on = false;
@@ -180,6 +188,19 @@ namespace {
 
 int dev_alloc(bura_plan_t P, void** ptr, size_t bytes) {
   if (bytes == 0) bytes = 16;
+  if (P->ws_base) {
+    // static workspace: 256-byte aligned carve-outs, nothing is freed
+    const size_t at = (P->ws_used + 255) & ~(size_t)255;
+    if (at > P->ws_cap || bytes > P->ws_cap - at) {
+      g_last_error = "workspace larger than the static scratch array";
+      *ptr = nullptr;
+      return BURA_ETOOBIG;
+    }
+    *ptr = P->ws_base + at;
+    P->ws_used = at + bytes;
+    P->device_bytes += bytes;
+    return BURA_OK;
+  }
   hipError_t e = hipMalloc(ptr, bytes);
   if (e != hipSuccess) {
     g_last_error = hipGetErrorString(e);
@@ -189,6 +210,16 @@ int dev_alloc(bura_plan_t P, void** ptr, size_t bytes) {
   P->allocs.push_back(*ptr);
   P->device_bytes += bytes;
   return BURA_OK;
+}
+
+// Clear device memory of the plan: a fill kernel for a static-workspace plan
+// (whose caller may be capturing the stream), hipMemsetAsync otherwise.
+int dev_zero(bura_plan_t P, void* ptr, size_t bytes) {
+  if (P->ws_base) {
+    launch_zero(ptr, bytes, P->stream);
+    return BURA_OK;
+  }
+  return hipMemsetAsync(ptr, 0, bytes, P->stream) == hipSuccess ? BURA_OK : BURA_EDEVICE;
 }
 
 // Records start/stop events around one launch of class `cls` when profiling;
@@ -534,7 +565,7 @@ int alloc_work(bura_plan_t P, Work<T>& W) {
   if (q_stored(P) && (rc = dev_alloc(P, (void**)&W.q, vb))) return rc;
   if (P->foldxr) {
     if ((rc = dev_alloc(P, (void**)&W.r2, vb))) return rc;
-    HIPCHK(hipMemsetAsync(W.r2, 0, vb, P->stream));
+    if ((rc = dev_zero(P, W.r2, vb))) return rc;
   }
   const int L = (int)P->lev.size();
   W.xl.assign(L, nullptr);
@@ -555,7 +586,7 @@ int alloc_work(bura_plan_t P, Work<T>& W) {
   HIPCHK(hipMemcpyAsync(W.shift, sh.data(), S * sizeof(T), hipMemcpyHostToDevice, P->stream));
   HIPCHK(hipStreamSynchronize(P->stream));
   for (void* ptr : {(void*)W.x, (void*)W.r, (void*)W.z, (void*)W.zt, (void*)W.p, (void*)W.p2, (void*)W.q})
-    if (ptr) HIPCHK(hipMemsetAsync(ptr, 0, vb, P->stream));
+    if (ptr && (rc = dev_zero(P, ptr, vb))) return rc;
   return BURA_OK;
 }
 
@@ -1061,8 +1092,11 @@ int do_solve(bura_plan_t P, const double* f, double* u, int nrhs, bura_report_t*
   const size_t S_used = (size_t)P->nterms * R;
   int rc;
   // the plan works on its own stream, ordered after the caller's pending work
-  HIPCHK(hipEventRecord(P->join_ev, P->user_stream));
-  HIPCHK(hipStreamWaitEvent(P->stream, P->join_ev, 0));
+  // (a static-workspace plan runs on the caller's stream itself)
+  if (P->join_ev) {
+    HIPCHK(hipEventRecord(P->join_ev, P->user_stream));
+    HIPCHK(hipStreamWaitEvent(P->stream, P->join_ev, 0));
+  }
   if ((rc = set_flags(P, P->st.flags, 0, (int)S_used, 0))) return rc;
   if ((rc = set_flags(P, P->st.total_iters, 0, (int)S_used, 0))) return rc;
   if ((rc = set_flags(P, P->st.outer, 0, (int)S_used, 0))) return rc;
@@ -1383,7 +1417,7 @@ int tune_tiles(bura_plan_t P) {
 }
 
 int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_plan_t* out,
-           const LateTerms& late = LateTerms()) {
+           const LateTerms& late = LateTerms(), void* ws = nullptr, size_t ws_cap = 0) {
   if (out) *out = nullptr;
   if (!g || !out) return BURA_EINVAL;
   if (!late && check_terms(terms)) return BURA_EINVAL;
@@ -1396,6 +1430,7 @@ int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_p
   if (opts_in) o = *opts_in;
   else bura_opts_default(&o);
   if (validate_opts(&o)) return BURA_EINVAL;
+  if (ws && o.autotune) return BURA_EINVAL;   // tuning times solves with its own events
   if (g->coeff) {
     const long long m = (long long)(g->n + 2);
     long long cnt = g->dim == 2 ? m * m : m * m * m;
@@ -1409,9 +1444,13 @@ int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_p
   P->var = g->coeff != nullptr;
   P->opts = o;
   P->user_stream = (hipStream_t)o.stream;
+  if (ws) {
+    P->ws_base = (char*)ws;
+    P->ws_cap = ws_cap;
+  }
   {
     const char* ev = std::getenv("BURA_NO_GRAPH");
-    P->use_graphs = !(ev && ev[0] == '1');
+    P->use_graphs = !(ev && ev[0] == '1') && !ws;
     // folding the scalar updates into the producing kernels needs a
     // device-scope fence per block, which on a multi-XCD part writes back L2;
     // it is slower than a separate launch, so it is opt-in (BURA_FOLD=1)
@@ -1461,13 +1500,19 @@ int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_p
   }
   if (hipGetDevice(&P->device) != hipSuccess) { delete P; return BURA_EDEVICE; }
   auto fail = [&](int code) { bura_plan_destroy(P); return code; };
-  if (hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking) != hipSuccess) return fail(BURA_EDEVICE);
-  if (hipEventCreateWithFlags(&P->join_ev, hipEventDisableTiming) != hipSuccess) return fail(BURA_EDEVICE);
+  if (ws) {
+    // everything on the caller's stream, in order after its pending work
+    P->stream = P->user_stream;
+    P->owns_stream = false;
+  } else {
+    if (hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking) != hipSuccess) return fail(BURA_EDEVICE);
+    if (hipEventCreateWithFlags(&P->join_ev, hipEventDisableTiming) != hipSuccess) return fail(BURA_EDEVICE);
+  }
   if ((rc = upload_faces(P))) return fail(rc);
   if (mixed) {
     if ((rc = alloc_work<float>(P, P->w32))) return fail(rc);
     if ((rc = dev_alloc(P, (void**)&P->x64, (size_t)P->S * P->N * 8))) return fail(rc);
-    hipMemsetAsync(P->x64, 0, (size_t)P->S * P->N * 8, P->stream);
+    if ((rc = dev_zero(P, P->x64, (size_t)P->S * P->N * 8))) return fail(rc);
   } else {
     if ((rc = alloc_work<double>(P, P->w64))) return fail(rc);
   }
@@ -1491,7 +1536,7 @@ int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_p
   const size_t S = (size_t)P->S;
   const size_t bytes = S * (6 * 8 + 8 * 4);
   if ((rc = dev_alloc(P, &P->state_block, bytes))) return fail(rc);
-  hipMemsetAsync(P->state_block, 0, bytes, P->stream);
+  if ((rc = dev_zero(P, P->state_block, bytes))) return fail(rc);
   double* dp = (double*)P->state_block;
   P->st.bnorm2 = dp; P->st.rho = dp + S; P->st.alpha = dp + 2 * S; P->st.beta = dp + 3 * S;
   P->st.relres = dp + 4 * S; P->st.fnorm2 = dp + 5 * S;
@@ -1501,15 +1546,22 @@ int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_p
   P->st.active64 = ip + 4 * S; P->st.outer = ip + 5 * S;
   // relres64 needs doubles: carve from a separate allocation
   if ((rc = dev_alloc(P, (void**)&P->st.relres64, S * 8))) return fail(rc);
-  hipMemsetAsync(P->st.relres64, 0, S * 8, P->stream);
+  if ((rc = dev_zero(P, P->st.relres64, S * 8))) return fail(rc);
   if ((rc = dev_alloc(P, (void**)&P->d_cnt, S * sizeof(unsigned int)))) return fail(rc);
-  hipMemsetAsync(P->d_cnt, 0, S * sizeof(unsigned int), P->stream);
+  if ((rc = dev_zero(P, P->d_cnt, S * sizeof(unsigned int)))) return fail(rc);
   if ((rc = dev_alloc(P, (void**)&P->prof.d_ctr, BURA_K_COUNT * sizeof(unsigned long long)))) return fail(rc);
-  hipMemsetAsync(P->prof.d_ctr, 0, BURA_K_COUNT * sizeof(unsigned long long), P->stream);
-  if (hipHostMalloc((void**)&P->h_flags, S * sizeof(int), hipHostMallocDefault) != hipSuccess)
-    return fail(BURA_ENOMEM);
-  if (hipHostMalloc(&P->h_state, S * (6 * 8 + 8 * 4) + S * 8, hipHostMallocDefault) != hipSuccess)
-    return fail(BURA_ENOMEM);
+  if ((rc = dev_zero(P, P->prof.d_ctr, BURA_K_COUNT * sizeof(unsigned long long)))) return fail(rc);
+  const size_t state_mirror = S * (6 * 8 + 8 * 4) + S * 8;
+  if (ws) {
+    // host mirrors in ordinary memory (8-byte aligned: the state comes first)
+    P->host_mirror.assign(state_mirror + S * sizeof(int) + 8, 0);
+    P->h_state = P->host_mirror.data();
+    P->h_flags = (int*)(P->host_mirror.data() + state_mirror);
+  } else {
+    if (hipHostMalloc((void**)&P->h_flags, S * sizeof(int), hipHostMallocDefault) != hipSuccess)
+      return fail(BURA_ENOMEM);
+    if (hipHostMalloc(&P->h_state, state_mirror, hipHostMallocDefault) != hipSuccess) return fail(BURA_ENOMEM);
+  }
   if (o.autotune) {
     if (hipStreamSynchronize(P->stream) != hipSuccess) return fail(BURA_EDEVICE);
     if ((rc = tune_tiles(P))) return fail(rc);
@@ -1523,10 +1575,58 @@ int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_p
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Static device workspace of bura_solve_static: one copy per GPU, held until
+// the process ends.  In host code the symbol is only a host-side stand-in;
+// its device address on the current GPU comes from hipGetSymbolAddress, once
+// per device, and only that address is passed to kernels and fill launches.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[BURA_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};   // device address of `scratch`, per device ordinal
+
+int scratch_on_current_device(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return BURA_EDEVICE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return BURA_EDEVICE;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return BURA_OK;
+}
+
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
 extern "C" {
+
+int bura_solve_static(const bura_grid_t* grid, int nterms, const double* weights, const double* shifts,
+                      const bura_opts_t* opts, const double* f_dev, double* u_dev, int nrhs, bura_report_t* rep) {
+  if (!grid || !weights || !shifts || !f_dev || !u_dev || nterms < 1 || nterms > BURA_MAX_TERMS || nrhs < 1)
+    return BURA_EINVAL;
+  void* ws = nullptr;
+  int rc = scratch_on_current_device(&ws);
+  if (rc) return rc;
+  Terms t;
+  t.w.assign(weights, weights + nterms);
+  t.s.assign(shifts, shifts + nterms);
+  bura_plan_t P = nullptr;
+  if ((rc = create(grid, t, opts, &P, LateTerms(), ws, BURA_STATIC_SCRATCH_BYTES))) return rc;
+  rc = do_solve(P, f_dev, u_dev, nrhs, rep);
+  bura_plan_destroy(P);
+  return rc;
+}
+
 
 int bura_opts_default(bura_opts_t* o) {
   if (!o) return BURA_EINVAL;
@@ -1945,11 +2045,13 @@ void bura_plan_destroy(bura_plan_t plan) {
   destroy_graphs(plan);
   for (hipEvent_t e : plan->prof.pool) hipEventDestroy(e);
   for (void* p : plan->allocs) hipFree(p);
-  if (plan->h_flags) hipHostFree(plan->h_flags);
-  if (plan->h_state) hipHostFree(plan->h_state);
+  if (!plan->ws_base) {
+    if (plan->h_flags) hipHostFree(plan->h_flags);
+    if (plan->h_state) hipHostFree(plan->h_state);
+  }
   if (plan->h_slot) hipHostFree(plan->h_slot);
   if (plan->join_ev) hipEventDestroy(plan->join_ev);
-  if (plan->stream) hipStreamDestroy(plan->stream);
+  if (plan->stream && plan->owns_stream) hipStreamDestroy(plan->stream);
   delete plan;
 }
 
@@ -1965,6 +2067,7 @@ const char* bura_strerror(int status) {
     case BURA_EDEVICE: return "HIP runtime error";
     case BURA_ENAN: return "non-finite value";
     case BURA_EBUSY: return "plan busy";
+    case BURA_ETOOBIG: return "workspace larger than the static scratch array";
     default: return "unknown status";
   }
 }

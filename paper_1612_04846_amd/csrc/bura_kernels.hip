@@ -2392,10 +2392,17 @@ void launch_fill_int(int* p, long long n, int v, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
 }
 
+// Fill with zero bytes: 16-byte stores over the 16-byte-aligned body, single
+// bytes for the unaligned head and tail.
 __global__ void k_zero(unsigned char* p, size_t bytes) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (; i < bytes; i += stride) p[i] = 0;
+  const size_t head = std::min<size_t>((16 - ((uintptr_t)p & 15)) & 15, bytes);
+  const size_t words = (bytes - head) / 16;
+  uint4* body = (uint4*)(p + head);
+  for (size_t i = tid; i < words; i += stride) body[i] = make_uint4(0u, 0u, 0u, 0u);
+  const size_t tail0 = head + words * 16;
+  for (size_t i = tid; i < head + (bytes - tail0); i += stride) p[i < head ? i : tail0 + (i - head)] = 0;
 }
 
 void launch_zero(void* p, size_t bytes, hipStream_t st) {
