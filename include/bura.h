@@ -24,15 +24,21 @@
  * (x_i - x_nb), x_nb = 0 outside the grid; a_f = 1 (Laplacian, Section 5.3) or
  * the harmonic mean 2 a_i a_nb/(a_i + a_nb) of a caller-supplied nodal
  * coefficient a > 0 on the (n+2)^dim lattice including the boundary nodes.
- * Lambda = max_i sum_j |A~_ij| (Gershgorin; equals 4 dim/h^2 for the
- * Laplacian, the paper's scaling) unless the caller gives an upper bound.
+ * Lambda, the upper bound of the spectrum of A~ that scales A = A~/Lambda
+ * (Section 1.4, eq. (10)): for the Laplacian 4 dim/h^2 at every n (the
+ * paper's scaling in Section 5.3, h^2/8 in 2D; it equals the Gershgorin bound
+ * for n >= 3 and exceeds it below); with coefficients the Gershgorin bound
+ * max_i sum_j |A~_ij| = max_i 2 A~_ii; or the caller's upper bound.
  *
  * Conventions: every function returns an int status (enum bura_status); none
  * throws or aborts.  Pointers named *_dev are device pointers in the current
  * HIP device's address space (e.g. from hipMalloc or a torch CUDA tensor on
  * ROCm); all other pointers are host pointers.  A plan owns every internal
- * buffer it allocates and frees them in bura_plan_destroy.  Plans are not
- * thread-safe: one host thread at a time may call solve/submit on a plan.
+ * buffer it allocates and frees them in bura_plan_destroy.  Solves on one
+ * plan are serialised inside the library (synchronous solves and the plan's
+ * queue of asynchronous ones), so several host threads may solve and submit
+ * on one plan; creating or destroying a plan must not race with other calls
+ * on it.
  */
 #ifndef BURA_H
 #define BURA_H
@@ -47,6 +53,11 @@ extern "C" {
 /* Opaque plan: operator hierarchy, coefficients, device workspace. */
 typedef struct bura_plan_s* bura_plan_t;
 
+/* Handle of one asynchronous solve (bura_submit / bura_submit_slots), unique
+ * in the process; released by the bura_poll or bura_wait that returns its
+ * result.  0 is never a valid ticket. */
+typedef uint64_t bura_ticket_t;
+
 enum bura_status {
   BURA_OK = 0,
   BURA_PENDING = 1,          /* bura_poll: the solve is still running            */
@@ -57,7 +68,7 @@ enum bura_status {
   BURA_ENOMEM = -5,          /* device allocation failed / over the HBM budget   */
   BURA_EDEVICE = -6,         /* HIP runtime error                                */
   BURA_ENAN = -7,            /* non-finite residual                              */
-  BURA_EBUSY = -8,           /* plan has an unfinished submitted solve           */
+  BURA_EBUSY = -8,           /* plan has queued or running asynchronous solves   */
   BURA_ETOOBIG = -9          /* bura_solve_static: the workspace does not fit
                                 BURA_STATIC_SCRATCH_BYTES                        */
 };
@@ -81,8 +92,17 @@ typedef struct {
                               full hierarchy); otherwise the preconditioner is Jacobi. */
   const double* coeff;     /* NULL: Laplacian.  Else host array, (n+2)^dim nodal values
                               a > 0 incl. boundary, x fastest; copied at plan time.     */
-  double lambda_upper;     /* 0: Gershgorin bound.  >0: caller's bound, must be
-                              >= the largest eigenvalue of A~.                          */
+  double lambda_upper;     /* 0: the library's bound (below).  >0: caller's bound, must
+                              be >= the largest eigenvalue of A~.                       */
+  int rhs_unscaled;        /* 0: f is the right-hand side of the scaled problem
+                              A^alpha u = f, A = A~/Lambda (Section 1.4, eq. (10)).
+                              1: f is f~ of the unscaled A~^alpha u = f~, and the
+                              result is u = A~^-alpha f~ = Lambda^-alpha A^-alpha f~
+                              (the factor is applied in the FP64 combine).  Needs a
+                              plan that knows its fractional power: the plans of
+                              _rational, _rational_multi and _slots return
+                              BURA_EINVAL, as does any other value.  (0 keeps a
+                              zero-initialised struct on the scaled problem.)       */
 } bura_grid_t;
 
 /* Solver options.  bura_opts_default fills sensible values. */
@@ -187,6 +207,11 @@ int bura_plan_create_rational_multi(const bura_grid_t* grid, int nout, const int
 int bura_sinc_coefficients(double alpha, double kprime, double scale, int max_terms, double* weights,
                            double* shifts, int* nterms);
 
+/* The step k' of the sinc quadrature for Section 5.3's parameter k_Q =
+ * pi^2/(4 alpha (1-alpha) k'^2) (the nominal number of its systems):
+ * *kprime = pi/(2 sqrt(alpha (1-alpha) k_Q)).  alpha in (0,1), k_Q > 0. */
+int bura_sinc_kprime(double alpha, double kq, double* kprime);
+
 /* A plan for the sinc quadrature, one output per (alphas[a], kprimes[a]).
  * As in Section 5.3's comparison the rule is applied to the unscaled operator
  * Lambda * A (scale = the plan's spectral bound Lambda, see bura_plan_info), and
@@ -245,10 +270,10 @@ int bura_plan_create_slots(const bura_grid_t* grid, int max_terms, const bura_op
 int bura_solve_slots(bura_plan_t plan, const double* f_dev, double* u_dev, int nrhs, const int* nterms,
                      const double* weights, const double* shifts, const double* tol, bura_report_t* rep);
 
-/* Asynchronous bura_solve_slots (the host arrays are copied before it
- * returns); completion and report through bura_poll. */
+/* Asynchronous bura_solve_slots: queued like bura_submit (the host arrays are
+ * copied before it returns); *ticket identifies it for bura_poll/bura_wait. */
 int bura_submit_slots(bura_plan_t plan, const double* f_dev, double* u_dev, int nrhs, const int* nterms,
-                      const double* weights, const double* shifts, const double* tol);
+                      const double* weights, const double* shifts, const double* tol, bura_ticket_t* ticket);
 
 /* Number of outputs and their term ranges: output i uses terms
  * [term_begin[i], term_begin[i+1]); term_begin has nout + 1 entries. */
@@ -259,14 +284,26 @@ int bura_plan_outputs(bura_plan_t plan, int* nout, int* term_begin);
  * BURA_ENOCONV leaves the last iterate combined in u_dev. */
 int bura_solve(bura_plan_t plan, const double* f_dev, double* u_dev, int nrhs, bura_report_t* rep);
 
-/* Asynchronous variant: enqueue the solve on the plan's stream and return at
- * once.  f_dev/u_dev must stay valid and untouched until bura_poll returns a
- * value other than BURA_PENDING.  One outstanding solve per plan (BURA_EBUSY). */
-int bura_submit(bura_plan_t plan, const double* f_dev, double* u_dev, int nrhs);
+/* Asynchronous variant of bura_solve: queue the solve and return at once with
+ * *ticket set.  tol > 0 replaces opts.tol (the per-system FP64 relative
+ * residual) for this solve only; 0 keeps opts.tol.  Any number of solves may
+ * be queued on one plan: a worker thread of the plan runs them one after
+ * another in submission order (they share the plan's buffers), and a
+ * synchronous bura_solve on the same plan waits for the running one.
+ * f_dev/u_dev of each solve must stay valid and untouched until its ticket
+ * completes; solves whose u_dev overlap complete in submission order.
+ * BURA_EINVAL for a slot plan, nrhs outside [1, nrhs_max], tol < 0 or a null
+ * pointer (then *ticket = 0). */
+int bura_submit(bura_plan_t plan, const double* f_dev, double* u_dev, int nrhs, double tol, bura_ticket_t* ticket);
 
-/* BURA_PENDING while the submitted solve runs; then its final status, with
- * the report copied to *rep (may be NULL). */
-int bura_poll(bura_plan_t plan, bura_report_t* rep);
+/* BURA_PENDING while the ticket's solve is queued or running; then its final
+ * status, with the report copied to *rep (may be NULL), and the ticket is
+ * released (a second poll returns BURA_EINVAL, as does an unknown ticket).
+ * Thread-safe. */
+int bura_poll(bura_ticket_t ticket, bura_report_t* rep);
+
+/* Blocking bura_poll: returns once the ticket's solve has finished. */
+int bura_wait(bura_ticket_t ticket, bura_report_t* rep);
 
 /* Introspection: the plan's c_j, d_j (arrays of nterms) and E (may be NULL). */
 int bura_plan_coeffs(bura_plan_t plan, int* nterms, double* c, double* d, double* E);
@@ -297,7 +334,8 @@ int bura_plan_tiles(bura_plan_t plan, int* out, int max_len, int* len);
 
 /* Set the variants (layout as bura_plan_tiles, len must equal its *len, each
  * value in [0, BURA_TILE_VARIANTS)).  Synchronises the plan's stream and
- * drops its captured graphs; BURA_EBUSY while an asynchronous solve runs. */
+ * drops its captured graphs; BURA_EBUSY while asynchronous solves are queued
+ * or running. */
 int bura_plan_set_tiles(bura_plan_t plan, const int* v, int len);
 
 /* Kernel classes for profiling. */
@@ -415,7 +453,8 @@ void bura_server_destroy(bura_server_t s);
 int bura_solve_static(const bura_grid_t* grid, int nterms, const double* weights, const double* shifts,
                       const bura_opts_t* opts, const double* f_dev, double* u_dev, int nrhs, bura_report_t* rep);
 
-/* Release every resource of the plan.  Waits for an outstanding solve. */
+/* Release every resource of the plan.  Runs every queued asynchronous solve to
+ * completion first (their tickets stay pollable). */
 void bura_plan_destroy(bura_plan_t plan);
 
 /* Static string for a status code. */

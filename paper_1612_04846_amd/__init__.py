@@ -55,6 +55,7 @@ class bura_grid_t(ctypes.Structure):
         ("n", ctypes.c_int),
         ("coeff", ctypes.POINTER(ctypes.c_double)),
         ("lambda_upper", ctypes.c_double),
+        ("rhs_unscaled", ctypes.c_int),
     ]
 
 
@@ -132,6 +133,7 @@ _SIGS = {
     "bura_plan_create_rational_multi": (_I, [ctypes.POINTER(bura_grid_t), _I, ctypes.POINTER(_I), _DP, _DP,
                                              ctypes.POINTER(bura_opts_t), ctypes.POINTER(_P)]),
     "bura_sinc_coefficients": (_I, [_D, _D, _D, _I, _DP, _DP, ctypes.POINTER(_I)]),
+    "bura_sinc_kprime": (_I, [_D, _D, _DP]),
     "bura_zeros": (_I, [_D, _I, _I, _DP, _DP]),
     "bura_plan_create_multistep": (_I, [ctypes.POINTER(bura_grid_t), _I, _DP, ctypes.POINTER(_I),
                                         ctypes.POINTER(bura_opts_t), ctypes.POINTER(_P)]),
@@ -141,11 +143,12 @@ _SIGS = {
                                    ctypes.POINTER(_P)]),
     "bura_plan_create_slots": (_I, [ctypes.POINTER(bura_grid_t), _I, ctypes.POINTER(bura_opts_t), ctypes.POINTER(_P)]),
     "bura_solve_slots": (_I, [_P, _P, _P, _I, ctypes.POINTER(_I), _DP, _DP, _DP, ctypes.POINTER(bura_report_t)]),
-    "bura_submit_slots": (_I, [_P, _P, _P, _I, ctypes.POINTER(_I), _DP, _DP, _DP]),
+    "bura_submit_slots": (_I, [_P, _P, _P, _I, ctypes.POINTER(_I), _DP, _DP, _DP, ctypes.POINTER(ctypes.c_uint64)]),
     "bura_plan_outputs": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "bura_solve": (_I, [_P, _P, _P, _I, ctypes.POINTER(bura_report_t)]),
-    "bura_submit": (_I, [_P, _P, _P, _I]),
-    "bura_poll": (_I, [_P, ctypes.POINTER(bura_report_t)]),
+    "bura_submit": (_I, [_P, _P, _P, _I, _D, ctypes.POINTER(ctypes.c_uint64)]),
+    "bura_poll": (_I, [ctypes.c_uint64, ctypes.POINTER(bura_report_t)]),
+    "bura_wait": (_I, [ctypes.c_uint64, ctypes.POINTER(bura_report_t)]),
     "bura_plan_coeffs": (_I, [_P, ctypes.POINTER(_I), _DP, _DP, _DP]),
     "bura_plan_info": (_I, [_P, _DP, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_size_t)]),
     "bura_plan_apply": (_I, [_P, _D, _P, _P, _I]),
@@ -216,10 +219,11 @@ def bura_coefficients(alpha: float, k: int, beta: int = 1):
     return list(c)[: k + 1 + (beta == 2)], list(d), E.value
 
 
-def _grid(dim, n, coeff=None, lambda_upper=0.0):
+def _grid(dim, n, coeff=None, lambda_upper=0.0, rhs_unscaled=0):
     g = bura_grid_t()
     g.dim = dim
     g.n = n
+    g.rhs_unscaled = rhs_unscaled
     keep = None
     if coeff is not None:
         import numpy as np
@@ -240,8 +244,8 @@ def _stream_ptr(stream):
 
 
 def bura_plan_create(dim: int, n: int, alpha: float, k: int, opts: Optional[bura_opts_t] = None,
-                     coeff=None, lambda_upper: float = 0.0, beta: int = 1):
-    g, _keep = _grid(dim, n, coeff, lambda_upper)
+                     coeff=None, lambda_upper: float = 0.0, beta: int = 1, rhs_unscaled: int = 0):
+    g, _keep = _grid(dim, n, coeff, lambda_upper, rhs_unscaled)
     o = opts if opts is not None else bura_opts_default()
     h = _P()
     _check(_lib.bura_plan_create(ctypes.byref(g), alpha, beta, k, ctypes.byref(o), ctypes.byref(h)),
@@ -250,8 +254,8 @@ def bura_plan_create(dim: int, n: int, alpha: float, k: int, opts: Optional[bura
 
 
 def bura_plan_create_multi(dim: int, n: int, alphas: Sequence[float], ks: Sequence[int],
-                           opts: Optional[bura_opts_t] = None, coeff=None, lambda_upper: float = 0.0, beta: int = 1):
-    g, _keep = _grid(dim, n, coeff, lambda_upper)
+                           opts: Optional[bura_opts_t] = None, coeff=None, lambda_upper: float = 0.0, beta: int = 1, rhs_unscaled: int = 0):
+    g, _keep = _grid(dim, n, coeff, lambda_upper, rhs_unscaled)
     o = opts if opts is not None else bura_opts_default()
     m = len(alphas)
     a = (ctypes.c_double * m)(*alphas)
@@ -338,9 +342,12 @@ def bura_solve_slots(plan, max_terms: int, f: torch.Tensor, u: torch.Tensor, ter
 
 
 def bura_submit_slots(plan, max_terms: int, f: torch.Tensor, u: torch.Tensor, terms, tols=None) -> int:
+    """Queue a slot solve; returns its ticket (see bura_poll / bura_wait)."""
     nt, w, s, t = _slot_arrays(max_terms, terms, tols)
-    return _check(_lib.bura_submit_slots(plan, _devptr(f, "f"), _devptr(u, "u"), len(terms), nt, w, s, t),
-                  "bura_submit_slots")
+    tk = ctypes.c_uint64()
+    _check(_lib.bura_submit_slots(plan, _devptr(f, "f"), _devptr(u, "u"), len(terms), nt, w, s, t,
+                                  ctypes.byref(tk)), "bura_submit_slots")
+    return tk.value
 
 
 def bura_plan_create_rational_multi(dim: int, n: int, nterms: Sequence[int], weights: Sequence[float],
@@ -360,7 +367,9 @@ def bura_plan_create_rational_multi(dim: int, n: int, nterms: Sequence[int], wei
 
 def sinc_kprime(alpha: float, kq: float) -> float:
     """The quadrature step k' for a nominal number of systems k_Q = pi^2/(4 alpha (1-alpha) k'^2)."""
-    return math.pi / (2.0 * math.sqrt(alpha * (1.0 - alpha) * kq))
+    kp = ctypes.c_double()
+    _check(_lib.bura_sinc_kprime(alpha, kq, ctypes.byref(kp)), "bura_sinc_kprime")
+    return kp.value
 
 
 def bura_sinc_coefficients(alpha: float, kprime: float, scale: float = 1.0):
@@ -386,8 +395,8 @@ def bura_zeros(alpha: float, k: int, beta: int = 1):
 
 
 def bura_plan_create_multistep(dim: int, n: int, alphas: Sequence[float], ks: Sequence[int],
-                               opts: Optional[bura_opts_t] = None, coeff=None, lambda_upper: float = 0.0):
-    g, _keep = _grid(dim, n, coeff, lambda_upper)
+                               opts: Optional[bura_opts_t] = None, coeff=None, lambda_upper: float = 0.0, rhs_unscaled: int = 0):
+    g, _keep = _grid(dim, n, coeff, lambda_upper, rhs_unscaled)
     o = opts if opts is not None else bura_opts_default()
     m = len(alphas)
     a = (ctypes.c_double * m)(*alphas)
@@ -399,8 +408,8 @@ def bura_plan_create_multistep(dim: int, n: int, alphas: Sequence[float], ks: Se
 
 
 def bura_plan_create_product(dim: int, n: int, alpha: float, k: int, opts: Optional[bura_opts_t] = None,
-                             coeff=None, lambda_upper: float = 0.0, beta: int = 1):
-    g, _keep = _grid(dim, n, coeff, lambda_upper)
+                             coeff=None, lambda_upper: float = 0.0, beta: int = 1, rhs_unscaled: int = 0):
+    g, _keep = _grid(dim, n, coeff, lambda_upper, rhs_unscaled)
     o = opts if opts is not None else bura_opts_default()
     h = _P()
     _check(_lib.bura_plan_create_product(ctypes.byref(g), alpha, beta, k, ctypes.byref(o), ctypes.byref(h)),
@@ -409,8 +418,8 @@ def bura_plan_create_product(dim: int, n: int, alpha: float, k: int, opts: Optio
 
 
 def bura_plan_create_sinc(dim: int, n: int, alphas: Sequence[float], kprimes: Sequence[float],
-                          opts: Optional[bura_opts_t] = None, coeff=None, lambda_upper: float = 0.0):
-    g, _keep = _grid(dim, n, coeff, lambda_upper)
+                          opts: Optional[bura_opts_t] = None, coeff=None, lambda_upper: float = 0.0, rhs_unscaled: int = 0):
+    g, _keep = _grid(dim, n, coeff, lambda_upper, rhs_unscaled)
     o = opts if opts is not None else bura_opts_default()
     m = len(alphas)
     a = (ctypes.c_double * m)(*alphas)
@@ -435,13 +444,23 @@ def bura_solve(plan, f: torch.Tensor, u: torch.Tensor, nrhs: int, ok=(BURA_OK,))
     return rep
 
 
-def bura_submit(plan, f: torch.Tensor, u: torch.Tensor, nrhs: int) -> int:
-    return _check(_lib.bura_submit(plan, _devptr(f, "f"), _devptr(u, "u"), nrhs), "bura_submit")
+def bura_submit(plan, f: torch.Tensor, u: torch.Tensor, nrhs: int, tol: float = 0.0) -> int:
+    """Queue a solve (tol > 0 overrides the plan's tolerance for it); returns its ticket."""
+    tk = ctypes.c_uint64()
+    _check(_lib.bura_submit(plan, _devptr(f, "f"), _devptr(u, "u"), nrhs, tol, ctypes.byref(tk)), "bura_submit")
+    return tk.value
 
 
-def bura_poll(plan):
+def bura_poll(ticket: int):
+    """(status, report) of a ticket; BURA_PENDING while it runs, then the ticket is released."""
     rep = bura_report_t()
-    code = _lib.bura_poll(plan, ctypes.byref(rep))
+    code = _lib.bura_poll(ticket, ctypes.byref(rep))
+    return code, rep
+
+
+def bura_wait(ticket: int):
+    rep = bura_report_t()
+    code = _lib.bura_wait(ticket, ctypes.byref(rep))
     return code, rep
 
 
@@ -522,7 +541,7 @@ class Plan:
 
     def __init__(self, dim, n, alpha=None, k=None, *, weights=None, shifts=None, nterms=None, kprime=None,
                  form="fractions", beta=1, coeff=None, precision=BURA_MIXED, schedule=BURA_BATCHED, tol=1e-12,
-                 nrhs_max=1, stream=None, **opt):
+                 nrhs_max=1, stream=None, rhs_unscaled=0, **opt):
         """alpha (one value or a list) with k poles: the BURA; alpha with kprime
         (one value or lists): the sinc quadrature of step k'; weights/shifts
         (with nterms per output for several outputs): a caller-given form.
@@ -538,9 +557,9 @@ class Plan:
         if form == "multistep":
             al = list(alpha)
             ks = list(k) if isinstance(k, (list, tuple)) else [k] * len(al)
-            self.handle = bura_plan_create_multistep(dim, n, al, ks, o, coeff=coeff)
+            self.handle = bura_plan_create_multistep(dim, n, al, ks, o, coeff=coeff, rhs_unscaled=rhs_unscaled)
         elif form == "product":
-            self.handle = bura_plan_create_product(dim, n, alpha, k, o, coeff=coeff)
+            self.handle = bura_plan_create_product(dim, n, alpha, k, o, coeff=coeff, rhs_unscaled=rhs_unscaled)
         elif form != "fractions":
             raise ValueError("form must be 'fractions', 'multistep' or 'product'")
         elif weights is not None and nterms is not None:
@@ -551,14 +570,15 @@ class Plan:
         elif kprime is not None:
             al = list(alpha) if isinstance(alpha, (list, tuple)) else [alpha]
             kp = list(kprime) if isinstance(kprime, (list, tuple)) else [kprime] * len(al)
-            self.handle = bura_plan_create_sinc(dim, n, al, kp, o, coeff=coeff)
+            self.handle = bura_plan_create_sinc(dim, n, al, kp, o, coeff=coeff, rhs_unscaled=rhs_unscaled)
             self.nout = len(al) if isinstance(alpha, (list, tuple)) else 1
         elif isinstance(alpha, (list, tuple)):
             ks = list(k) if isinstance(k, (list, tuple)) else [k] * len(alpha)
-            self.handle = bura_plan_create_multi(dim, n, list(alpha), ks, o, coeff=coeff)
+            self.handle = bura_plan_create_multi(dim, n, list(alpha), ks, o, coeff=coeff, rhs_unscaled=rhs_unscaled)
             self.nout = len(alpha)
         else:
-            self.handle = bura_plan_create(dim, n, alpha, k, o, coeff=coeff, beta=beta)
+            self.handle = bura_plan_create(dim, n, alpha, k, o, coeff=coeff, beta=beta,
+                                           rhs_unscaled=rhs_unscaled)
 
     @property
     def coeffs(self):

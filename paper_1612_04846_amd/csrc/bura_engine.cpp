@@ -7,6 +7,8 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <deque>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -16,6 +18,7 @@
 #include <string>
 #include <tuple>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "bura_internal.h"
@@ -127,8 +130,6 @@ struct bura_plan_s {
   double* d_wsys = nullptr;
   double* d_tol = nullptr;
   void* h_slot = nullptr;
-  std::vector<int> slot_nterms;            // terms per rhs of the pending asynchronous solve
-  std::vector<double> slot_w, slot_s, slot_tol;
   // device buffers
   Work<double> w64;
   Work<float> w32;
@@ -177,11 +178,26 @@ struct bura_plan_s {
   hipStream_t user_stream = nullptr;   // caller's stream (opts.stream)
   hipEvent_t join_ev = nullptr;
   void* h_state = nullptr;             // pinned mirror of the scalar state for reports
-  // async
+  double run_tol = 0.0;                // stopping tolerance of the solve in progress
+  // asynchronous solves: a FIFO of submitted solves run in order by one
+  // worker thread; exec_mu serialises them with synchronous solves
+  struct Job {
+    const double* f = nullptr;
+    double* u = nullptr;
+    int nrhs = 0;
+    double tol = 0.0;
+    uint64_t ticket = 0;
+    bool slots = false;
+    std::vector<int> nterms;
+    std::vector<double> w, s, tolv;
+  };
+  std::mutex exec_mu;
+  std::mutex q_mu;
+  std::condition_variable q_cv;
+  std::deque<Job> queue;
+  int running = 0;
+  bool stop = false;
   std::thread worker;
-  std::atomic<int> busy{0};
-  int async_status = BURA_OK;
-  bura_report_t async_report{};
 };
 
 namespace {
@@ -959,9 +975,9 @@ int solve_batch_fp64(bura_plan_t P, const double* f, int nrhs, size_t sys0, int 
   }
   {
     ProfScope ps(P, BURA_K_OTHER);
-    launch_scalars(OP_INIT, P->partial, flat_blocks(P->N), nsys, S, P->opts.tol, P->opts.max_iter, st);
+    launch_scalars(OP_INIT, P->partial, flat_blocks(P->N), nsys, S, P->run_tol, P->opts.max_iter, st);
   }
-  return run_pcg<double>(P, W, sys0, nsys, P->opts.tol, P->opts.max_iter, combine_finishes_x(P));
+  return run_pcg<double>(P, W, sys0, nsys, P->run_tol, P->opts.max_iter, combine_finishes_x(P));
 }
 
 int solve_batch_mixed(bura_plan_t P, const double* f, int nrhs, size_t sys0, int nsys, bool preset) {
@@ -987,7 +1003,7 @@ int solve_batch_mixed(bura_plan_t P, const double* f, int nrhs, size_t sys0, int
   }
   {
     ProfScope ps(P, BURA_K_OTHER);
-    launch_scalars(OP_OUTER, P->partial, flat_blocks(P->N), nsys, S, P->opts.tol, P->opts.max_outer, st);
+    launch_scalars(OP_OUTER, P->partial, flat_blocks(P->N), nsys, S, P->run_tol, P->opts.max_outer, st);
   }
   for (int outer = 0; outer < P->opts.max_outer + 1; ++outer) {
     const int a = count_active(P, P->st.active64, sys0, nsys);
@@ -1012,7 +1028,7 @@ int solve_batch_mixed(bura_plan_t P, const double* f, int nrhs, size_t sys0, int
     }
     {
       ProfScope ps(P, BURA_K_OTHER);
-      launch_scalars(OP_OUTER, P->partial, stencil_blocks(P->dim, P->n), nsys, S, P->opts.tol, P->opts.max_outer,
+      launch_scalars(OP_OUTER, P->partial, stencil_blocks(P->dim, P->n), nsys, S, P->run_tol, P->opts.max_outer,
                      st);
     }
   }
@@ -1060,7 +1076,7 @@ int upload_slots(bura_plan_t P, int nrhs, const SlotTerms& t) {
       const bool used = r < nrhs && j < t.nterms[r];
       hw[i] = used ? t.w[(size_t)r * K + j] : 0.0;
       hs[i] = used ? t.s[(size_t)r * K + j] : 0.0;
-      ht[i] = used && t.tol ? t.tol[r] : P->opts.tol;
+      ht[i] = used && t.tol ? t.tol[r] : P->run_tol;
       hs32[i] = (float)hs[i];
       hf[i] = used ? 1 : 0;
     }
@@ -1080,9 +1096,11 @@ int upload_slots(bura_plan_t P, int nrhs, const SlotTerms& t) {
 }
 
 int do_solve(bura_plan_t P, const double* f, double* u, int nrhs, bura_report_t* rep,
-             const SlotTerms* slot = nullptr) {
+             const SlotTerms* slot = nullptr, double tol = 0.0) {
   const auto t0 = std::chrono::steady_clock::now();
   if (!P || !f || !u || nrhs < 1 || nrhs > P->opts.nrhs_max) return BURA_EINVAL;
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return BURA_EINVAL;
+  P->run_tol = tol > 0.0 ? tol : P->opts.tol;
   if (P->slots != (slot != nullptr)) return BURA_EINVAL;
   if (slot && check_slot_terms(P, nrhs, *slot)) return BURA_EINVAL;
   HIPCHK(hipSetDevice(P->device));
@@ -1187,7 +1205,7 @@ int do_solve(bura_plan_t P, const double* f, double* u, int nrhs, bura_report_t*
   for (int j = 0; j < P->nterms && j < BURA_MAX_TERMS; ++j) {
     for (int r = 0; r < nrhs; ++r) {
       if (slot && j >= slot->nterms[r]) continue;
-      const double tol = slot && slot->tol ? slot->tol[r] : P->opts.tol;
+      const double tol = slot && slot->tol ? slot->tol[r] : P->run_tol;
       const size_t s = (size_t)j * R + r;
       R_.iters[j] = std::max(R_.iters[j], it[s]);
       R_.outer[j] = std::max(R_.outer[j], outer[s]);
@@ -1208,6 +1226,10 @@ int validate_opts(const bura_opts_t* o) {
     return BURA_EINVAL;
   if (o->precision != BURA_FP64 && o->precision != BURA_MIXED) return BURA_EINVAL;
   if (o->schedule != BURA_BATCHED && o->schedule != BURA_PER_POLE) return BURA_EINVAL;
+  // the V-cycle must be symmetric for PCG (post-smoothing = pre-smoothing
+  // reversed), and the per-sweep weight sets hold up to three sweeps
+  if (o->nu_pre != o->nu_post || o->nu_pre < 1 || o->nu_pre > 3) return BURA_EINVAL;
+  if (o->check_every < 1) return BURA_EINVAL;
   return BURA_OK;
 }
 
@@ -1217,6 +1239,9 @@ struct Terms {
   std::vector<int> begin{0};   // first term of each output
   double E = 0.0;
   std::vector<Stage> stages;   // sequential form (one output), see Stage
+  // fractional power approximated by each output (empty for caller-given
+  // terms): with unscaled input the output is multiplied by Lambda^-alpha
+  std::vector<double> out_alpha;
 };
 
 int check_terms(const Terms& t) {
@@ -1423,6 +1448,7 @@ int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_p
   if (!late && check_terms(terms)) return BURA_EINVAL;
   if (g->dim != 2 && g->dim != 3) return BURA_EINVAL;
   if (g->n < 1) return BURA_EINVAL;
+  if (g->rhs_unscaled != 0 && g->rhs_unscaled != 1) return BURA_EINVAL;
   long long N = 1;
   for (int a = 0; a < g->dim; ++a) N *= g->n;
   if (N > 2147483647LL) return BURA_EINVAL;
@@ -1469,6 +1495,26 @@ int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_p
     if ((rc = late(P->lambda, terms)) || (rc = check_terms(terms))) { delete P; return rc ? rc : BURA_EINVAL; }
   }
   const int nterms = (int)terms.w.size();
+  // unscaled input f~ of A~^alpha u = f~ (Section 1.4, eq. (10)): u = A~^-alpha f~ =
+  // Lambda^-alpha A^-alpha f~, the factor folded into the combine weights of each
+  // output (for a sequential form: its last stage, whose output is u)
+  std::vector<double> wdev = terms.w;
+  if (g->rhs_unscaled) {
+    const int nout = (int)terms.begin.size();
+    if ((int)terms.out_alpha.size() != nout) { delete P; return BURA_EINVAL; }
+    if (!terms.stages.empty()) {
+      Stage& last = terms.stages.back();
+      const double f = std::pow(P->lambda, -terms.out_alpha[0]);
+      for (int j = last.tb; j < last.te; ++j) wdev[j] *= f;
+      last.base_w *= f;
+    } else {
+      for (int a = 0; a < nout; ++a) {
+        const double f = std::pow(P->lambda, -terms.out_alpha[a]);
+        const int e = a + 1 < nout ? terms.begin[a + 1] : nterms;
+        for (int j = terms.begin[a]; j < e; ++j) wdev[j] *= f;
+      }
+    }
+  }
   P->nterms = nterms;
   P->w = terms.w;
   P->s = terms.s;
@@ -1529,7 +1575,7 @@ int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_p
   if ((rc = dev_alloc(P, (void**)&P->partial, P->partial_len * 8))) return fail(rc);
   if ((rc = dev_alloc(P, (void**)&P->d_w, nterms * 8))) return fail(rc);
   if (!P->stages.empty() && (rc = dev_alloc(P, (void**)&P->d_buf, (size_t)o.nrhs_max * P->N * 8))) return fail(rc);
-  if (hipMemcpyAsync(P->d_w, P->w.data(), nterms * 8, hipMemcpyHostToDevice, P->stream) != hipSuccess ||
+  if (hipMemcpyAsync(P->d_w, wdev.data(), nterms * 8, hipMemcpyHostToDevice, P->stream) != hipSuccess ||
       hipStreamSynchronize(P->stream) != hipSuccess)
     return fail(BURA_EDEVICE);
   // state arrays: 6 double + 7 int arrays of length S
@@ -1603,6 +1649,71 @@ int scratch_on_current_device(void** out) {
   return BURA_OK;
 }
 
+// Tickets of asynchronous solves, valid across plans until polled.
+struct TicketRec {
+  int status = BURA_PENDING;
+  bura_report_t rep{};
+};
+std::mutex g_tk_mu;
+std::condition_variable g_tk_cv;
+std::unordered_map<uint64_t, TicketRec> g_tickets;
+uint64_t g_next_ticket = 1;
+
+void worker_loop(bura_plan_t P) {
+  for (;;) {
+    bura_plan_s::Job j;
+    {
+      std::unique_lock<std::mutex> lk(P->q_mu);
+      P->q_cv.wait(lk, [&]() { return P->stop || !P->queue.empty(); });
+      if (P->queue.empty()) return;   // stop requested and nothing left
+      j = std::move(P->queue.front());
+      P->queue.pop_front();
+      ++P->running;
+    }
+    bura_report_t rep{};
+    int rc;
+    {
+      std::lock_guard<std::mutex> ex(P->exec_mu);
+      if (j.slots) {
+        const SlotTerms t{j.nterms.data(), j.w.data(), j.s.data(), j.tolv.empty() ? nullptr : j.tolv.data()};
+        rc = do_solve(P, j.f, j.u, j.nrhs, &rep, &t);
+      } else {
+        rc = do_solve(P, j.f, j.u, j.nrhs, &rep, nullptr, j.tol);
+      }
+    }
+    rep.status = rc;
+    {
+      std::lock_guard<std::mutex> lk(g_tk_mu);
+      TicketRec& r = g_tickets[j.ticket];
+      r.status = rc;
+      r.rep = rep;
+    }
+    g_tk_cv.notify_all();
+    {
+      std::lock_guard<std::mutex> lk(P->q_mu);
+      --P->running;
+    }
+    P->q_cv.notify_all();
+  }
+}
+
+uint64_t enqueue(bura_plan_t P, bura_plan_s::Job&& j) {
+  uint64_t t;
+  {
+    std::lock_guard<std::mutex> lk(g_tk_mu);
+    t = g_next_ticket++;
+    g_tickets[t] = TicketRec{};
+  }
+  j.ticket = t;
+  {
+    std::lock_guard<std::mutex> lk(P->q_mu);
+    P->queue.push_back(std::move(j));
+    if (!P->worker.joinable()) P->worker = std::thread(worker_loop, P);
+  }
+  P->q_cv.notify_all();
+  return t;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1626,7 +1737,6 @@ int bura_solve_static(const bura_grid_t* grid, int nterms, const double* weights
   bura_plan_destroy(P);
   return rc;
 }
-
 
 int bura_opts_default(bura_opts_t* o) {
   if (!o) return BURA_EINVAL;
@@ -1724,6 +1834,7 @@ int bura_plan_create_sinc(const bura_grid_t* grid, int nalpha, const double* alp
       t.begin.push_back((int)t.w.size());
       t.w.insert(t.w.end(), w, w + cnt);
       t.s.insert(t.s.end(), s, s + cnt);
+      t.out_alpha.push_back(al[a]);
     }
     return BURA_OK;
   };
@@ -1756,6 +1867,7 @@ int bura_plan_create_multistep(const bura_grid_t* grid, int nsteps, const double
     t.E = std::max(t.E, E);
   }
   if (!(asum > 0.0) || (int)t.w.size() > BURA_MAX_TERMS) return BURA_EINVAL;
+  t.out_alpha = {asum};
   return create(grid, t, opts, out);
 }
 
@@ -1791,6 +1903,7 @@ int bura_plan_create_product(const bura_grid_t* grid, double alpha, int beta, in
     t.stages.push_back(g);
   }
   t.E = E;
+  t.out_alpha = {alpha};
   return create(grid, t, opts, out);
 }
 
@@ -1822,6 +1935,7 @@ int bura_plan_create_multi(const bura_grid_t* grid, int nalpha, const double* al
   t.s = s;
   t.begin = begin;
   t.E = E;
+  t.out_alpha.assign(alphas, alphas + nalpha);
   return create(grid, t, opts, out);
 }
 
@@ -1858,76 +1972,80 @@ int bura_plan_create(const bura_grid_t* grid, double alpha, int beta, int k, con
     g1.base_w = 1.0;
     t.stages = {g0, g1};
   }
+  t.out_alpha = {alpha};
   return create(grid, t, opts, out);
 }
 
 int bura_solve(bura_plan_t plan, const double* f_dev, double* u_dev, int nrhs, bura_report_t* rep) {
   if (!plan) return BURA_EINVAL;
-  if (plan->busy.load()) return BURA_EBUSY;
+  std::lock_guard<std::mutex> lk(plan->exec_mu);
   return do_solve(plan, f_dev, u_dev, nrhs, rep);
 }
 
 int bura_solve_slots(bura_plan_t plan, const double* f_dev, double* u_dev, int nrhs, const int* nterms,
                      const double* weights, const double* shifts, const double* tol, bura_report_t* rep) {
   if (!plan) return BURA_EINVAL;
-  if (plan->busy.load()) return BURA_EBUSY;
   const SlotTerms t{nterms, weights, shifts, tol};
+  std::lock_guard<std::mutex> lk(plan->exec_mu);
   return do_solve(plan, f_dev, u_dev, nrhs, rep, &t);
 }
 
 int bura_submit_slots(bura_plan_t plan, const double* f_dev, double* u_dev, int nrhs, const int* nterms,
-                      const double* weights, const double* shifts, const double* tol) {
-  if (!plan || !plan->slots || !f_dev || !u_dev || nrhs < 1 || nrhs > plan->opts.nrhs_max) return BURA_EINVAL;
+                      const double* weights, const double* shifts, const double* tol, bura_ticket_t* ticket) {
+  if (ticket) *ticket = 0;
+  if (!plan || !ticket || !plan->slots || !f_dev || !u_dev || nrhs < 1 || nrhs > plan->opts.nrhs_max)
+    return BURA_EINVAL;
   const SlotTerms t{nterms, weights, shifts, tol};
   if (check_slot_terms(plan, nrhs, t)) return BURA_EINVAL;
-  int expected = 0;
-  if (!plan->busy.compare_exchange_strong(expected, 1)) return BURA_EBUSY;
-  if (plan->worker.joinable()) plan->worker.join();
-  // the worker reads the plan's own copies (the caller's arrays may go away)
+  // the job keeps its own copies (the caller's arrays may go away)
+  bura_plan_s::Job j;
   const size_t K = (size_t)plan->nterms;
-  plan->slot_nterms.assign(nterms, nterms + nrhs);
-  plan->slot_w.assign(weights, weights + nrhs * K);
-  plan->slot_s.assign(shifts, shifts + nrhs * K);
-  if (tol) plan->slot_tol.assign(tol, tol + nrhs);
-  else plan->slot_tol.clear();
-  plan->worker = std::thread([plan, f_dev, u_dev, nrhs]() {
-    bura_report_t rep{};
-    const SlotTerms st{plan->slot_nterms.data(), plan->slot_w.data(), plan->slot_s.data(),
-                       plan->slot_tol.empty() ? nullptr : plan->slot_tol.data()};
-    const int rc = do_solve(plan, f_dev, u_dev, nrhs, &rep, &st);
-    plan->async_status = rc;
-    rep.status = rc;
-    plan->async_report = rep;
-    plan->busy.store(2);
-  });
+  j.f = f_dev;
+  j.u = u_dev;
+  j.nrhs = nrhs;
+  j.slots = true;
+  j.nterms.assign(nterms, nterms + nrhs);
+  j.w.assign(weights, weights + nrhs * K);
+  j.s.assign(shifts, shifts + nrhs * K);
+  if (tol) j.tolv.assign(tol, tol + nrhs);
+  *ticket = enqueue(plan, std::move(j));
   return BURA_OK;
 }
 
-int bura_submit(bura_plan_t plan, const double* f_dev, double* u_dev, int nrhs) {
-  if (!plan || plan->slots || !f_dev || !u_dev || nrhs < 1 || nrhs > plan->opts.nrhs_max) return BURA_EINVAL;
-  int expected = 0;
-  if (!plan->busy.compare_exchange_strong(expected, 1)) return BURA_EBUSY;
-  if (plan->worker.joinable()) plan->worker.join();
-  plan->worker = std::thread([plan, f_dev, u_dev, nrhs]() {
-    bura_report_t rep{};
-    const int rc = do_solve(plan, f_dev, u_dev, nrhs, &rep);
-    plan->async_status = rc;
-    rep.status = rc;
-    plan->async_report = rep;
-    plan->busy.store(2);
-  });
+int bura_submit(bura_plan_t plan, const double* f_dev, double* u_dev, int nrhs, double tol, bura_ticket_t* ticket) {
+  if (ticket) *ticket = 0;
+  if (!plan || !ticket || plan->slots || !f_dev || !u_dev || nrhs < 1 || nrhs > plan->opts.nrhs_max)
+    return BURA_EINVAL;
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return BURA_EINVAL;
+  bura_plan_s::Job j;
+  j.f = f_dev;
+  j.u = u_dev;
+  j.nrhs = nrhs;
+  j.tol = tol;
+  *ticket = enqueue(plan, std::move(j));
   return BURA_OK;
 }
 
-int bura_poll(bura_plan_t plan, bura_report_t* rep) {
-  if (!plan) return BURA_EINVAL;
-  const int b = plan->busy.load();
-  if (b == 1) return BURA_PENDING;
-  if (b == 0) return BURA_EINVAL;   // nothing submitted
-  if (plan->worker.joinable()) plan->worker.join();
-  if (rep) *rep = plan->async_report;
-  plan->busy.store(0);
-  return plan->async_status;
+int bura_poll(bura_ticket_t ticket, bura_report_t* rep) {
+  std::lock_guard<std::mutex> lk(g_tk_mu);
+  auto it = g_tickets.find(ticket);
+  if (it == g_tickets.end()) return BURA_EINVAL;
+  if (it->second.status == BURA_PENDING) return BURA_PENDING;
+  const int rc = it->second.status;
+  if (rep) *rep = it->second.rep;
+  g_tickets.erase(it);
+  return rc;
+}
+
+int bura_wait(bura_ticket_t ticket, bura_report_t* rep) {
+  std::unique_lock<std::mutex> lk(g_tk_mu);
+  auto it = g_tickets.find(ticket);
+  if (it == g_tickets.end()) return BURA_EINVAL;
+  g_tk_cv.wait(lk, [&]() { return it->second.status != BURA_PENDING; });
+  const int rc = it->second.status;
+  if (rep) *rep = it->second.rep;
+  g_tickets.erase(it);
+  return rc;
 }
 
 int bura_plan_coeffs(bura_plan_t plan, int* nterms, double* c, double* d, double* E) {
@@ -2025,7 +2143,11 @@ int bura_plan_set_tiles(bura_plan_t plan, const int* v, int len) {
   if (len == 0) return BURA_OK;
   for (int i = 0; i < len; ++i)
     if (v[i] < 0 || v[i] >= BURA_TILE_VARIANTS) return BURA_EINVAL;
-  if (plan->busy.load()) return BURA_EBUSY;
+  {
+    std::lock_guard<std::mutex> q(plan->q_mu);
+    if (!plan->queue.empty() || plan->running) return BURA_EBUSY;
+  }
+  std::lock_guard<std::mutex> lk(plan->exec_mu);
   HIPCHK(hipSetDevice(plan->device));
   HIPCHK(hipStreamSynchronize(plan->stream));
   destroy_graphs(plan);   // captured launches carry their grid shapes
@@ -2039,6 +2161,12 @@ int bura_plan_set_tiles(bura_plan_t plan, const int* v, int len) {
 
 void bura_plan_destroy(bura_plan_t plan) {
   if (!plan) return;
+  {
+    // the worker finishes every queued solve, then exits
+    std::lock_guard<std::mutex> q(plan->q_mu);
+    plan->stop = true;
+  }
+  plan->q_cv.notify_all();
   if (plan->worker.joinable()) plan->worker.join();
   hipSetDevice(plan->device);
   if (plan->stream) hipStreamSynchronize(plan->stream);

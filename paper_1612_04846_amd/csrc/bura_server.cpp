@@ -53,6 +53,7 @@ struct Entry {
   bura_request_t q{};
   bura_plan_t plan = nullptr;
   bool busy = false;
+  bura_ticket_t ticket = 0;   // the running solve
   std::vector<std::shared_ptr<Req>> group;
   double* f_stage = nullptr;
   double* u_stage = nullptr;
@@ -228,7 +229,7 @@ struct bura_server_s {
         Entry* e = kv.second.get();
         if (!e->busy) continue;
         bura_report_t rep{};
-        const int rc = bura_poll(e->plan, &rep);
+        const int rc = bura_poll(e->ticket, &rep);
         if (rc == BURA_PENDING) {
           ++active;
           continue;
@@ -300,7 +301,7 @@ struct bura_server_s {
           f = e->f_stage;
           u = e->u_stage;
         }
-        const int rc = bura_submit_slots(e->plan, f, u, g, nterms, w, sh, tol);
+        const int rc = bura_submit_slots(e->plan, f, u, g, nterms, w, sh, tol, &e->ticket);
         if (rc != BURA_OK) {
           for (auto& q : e->group) fail(q, rc);
           e->group.clear();

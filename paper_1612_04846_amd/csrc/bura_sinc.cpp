@@ -48,3 +48,12 @@ extern "C" int bura_sinc_coefficients(double alpha, double kprime, double scale,
   }
   return BURA_OK;
 }
+
+// Section 5.3 parametrises the rule by k_Q = pi^2/(4 alpha (1-alpha) k'^2), the
+// nominal count m + M of its systems; this inverts that relation.
+extern "C" int bura_sinc_kprime(double alpha, double kq, double* kprime) {
+  if (!(alpha > 0.0 && alpha < 1.0) || !(kq > 0.0) || !std::isfinite(kq) || !kprime) return BURA_EINVAL;
+  const long double pi = 3.141592653589793238462643383279502884L;
+  *kprime = (double)(pi / (2.0L * std::sqrt((long double)alpha * (1.0L - alpha) * kq)));
+  return BURA_OK;
+}

@@ -96,3 +96,56 @@ def test_slot_argument_marshalling():
         B._slot_arrays(2, [([1.0, 2.0, 3.0], [0.0, 0.0, 0.0])], None)
     with pytest.raises(ValueError):
         B._slot_arrays(2, [([1.0, 2.0], [0.0])], None)
+
+
+@pytest.mark.parametrize("field,value", [("nu_post", 3), ("nu_pre", 4), ("check_every", 0)])
+def test_plan_rejects_asymmetric_or_unsupported_smoothing(field, value):
+    """A V-cycle with nu_pre != nu_post is not symmetric (PCG needs an SPD
+    preconditioner) and the sweep weights cover 1..3 sweeps: BURA_EINVAL, on
+    the host, before any device work."""
+    import paper_1612_04846_amd as B
+    o = B.bura_opts_default(precision=B.BURA_FP64)
+    setattr(o, field, value)
+    if field == "nu_pre":
+        o.nu_post = value
+    with pytest.raises(B.BuraError) as ei:
+        B.bura_plan_create(2, 31, 0.5, 5, o)
+    assert ei.value.code == B.BURA_EINVAL
+
+
+def test_unscaled_rhs_needs_a_fractional_power():
+    """rhs_unscaled applies Lambda^-alpha: caller-given terms carry no alpha, so
+    the rational plans refuse it, as does a value other than 0 or 1."""
+    import paper_1612_04846_amd as B
+    o = B.bura_opts_default(precision=B.BURA_FP64)
+    g, _ = B._grid(2, 31, None, 0.0, 1)
+    w = (B.ctypes.c_double * 1)(1.0)
+    sh = (B.ctypes.c_double * 1)(0.0)
+    h = B._P()
+    assert B._lib.bura_plan_create_rational(B.ctypes.byref(g), 1, w, sh, B.ctypes.byref(o), B.ctypes.byref(h)) \
+        == B.BURA_EINVAL
+    g2, _ = B._grid(2, 31, None, 0.0, 2)
+    assert B._lib.bura_plan_create(B.ctypes.byref(g2), 0.5, 1, 5, B.ctypes.byref(o), B.ctypes.byref(h)) \
+        == B.BURA_EINVAL
+
+
+def test_unknown_tickets_and_null_arguments():
+    import paper_1612_04846_amd as B
+    assert B.bura_poll(987654321)[0] == B.BURA_EINVAL
+    assert B.bura_wait(987654321)[0] == B.BURA_EINVAL
+    t = B.ctypes.c_uint64(5)
+    assert B._lib.bura_submit(None, None, None, 1, 0.0, B.ctypes.byref(t)) == B.BURA_EINVAL
+    assert t.value == 0
+
+
+def test_sinc_kprime_inverts_the_system_count():
+    """Section 5.3: k_Q = pi^2/(4 alpha (1-alpha) k'^2)."""
+    import math
+    import paper_1612_04846_amd as B
+    for alpha, kq in ((0.25, 9), (0.5, 7), (0.75, 6), (0.5, 19)):
+        kp = B.sinc_kprime(alpha, kq)
+        assert abs(math.pi ** 2 / (4 * alpha * (1 - alpha) * kp * kp) - kq) <= 1e-12 * kq
+    with pytest.raises(B.BuraError):
+        B.sinc_kprime(1.0, 9)
+    with pytest.raises(B.BuraError):
+        B.sinc_kprime(0.5, 0.0)

@@ -58,8 +58,6 @@ def test_server_alone_equals_mix_and_matches_oracle():
     for a, m in zip(alone, mix):
         assert np.array_equal(a, m)
     for (d, n, al, k, t, tol), f, u in zip(REQS, fs, mix):
-        if al == 0.9:
-            continue   # no oracle coefficients at alpha = 0.9, k = 12 (Chebyshev-basis Remez fails there)
         b = oracle_coeffs(al, k)
         ref = spectral.bura_spectral(f.cpu().numpy()[None], d, b.c_f64, b.d_f64)[0]
         assert np.linalg.norm(u - ref) / np.linalg.norm(ref) <= 1e-9

@@ -114,11 +114,13 @@ def test_slots_async_submit_and_poll():
     plan = B.bura_plan_create_slots(2, n, K, B.bura_opts_default(nrhs_max=2))
     Fd = _dev(F)
     U = torch.empty_like(Fd)
-    B.bura_submit_slots(plan, K, Fd, U, terms, tols=[1e-12, 1e-12])
+    ticket = B.bura_submit_slots(plan, K, Fd, U, terms, tols=[1e-12, 1e-12])
+    t0 = time.time()
     while True:
-        code, rep = B.bura_poll(plan)
+        code, rep = B.bura_poll(ticket)
         if code != B.BURA_PENDING:
             break
+        assert time.time() - t0 < 60
         time.sleep(0.001)
     assert code == B.BURA_OK
     u = _host(U)

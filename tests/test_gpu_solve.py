@@ -263,26 +263,72 @@ def test_full_path_matches_oracle(dim, n, alpha, k, prec):
     plan.close()
 
 
-def test_submit_poll_matches_solve():
+def test_tickets_several_in_flight_on_one_plan():
+    """Three solves queued on one plan before the first completes (two
+    right-hand-side batches, one with its own tolerance): each ticket's result
+    is bit-identical to the synchronous solve of the same inputs, tickets are
+    distinct and released by the poll that returns them."""
     B = _B()
     n = 63
-    F = _dev(synth.normal_rhs(n, 2, nrhs=2, tag=81))
-    plan = B.Plan(2, n, 0.5, 5, nrhs_max=2)
-    u_sync = _host(plan.solve(F).u)
-    u = torch.empty_like(F)
+    F1 = _dev(synth.normal_rhs(n, 2, nrhs=2, tag=81))
+    F2 = _dev(synth.normal_rhs(n, 2, nrhs=2, tag=82))
+    plan = B.Plan(2, n, 0.5, 5, nrhs_max=2, precision=B.BURA_FP64, tol=1e-12)
+    loose = B.Plan(2, n, 0.5, 5, nrhs_max=2, precision=B.BURA_FP64, tol=1e-8)
+    u1 = _host(plan.solve(F1).u)
+    u2 = _host(plan.solve(F2).u)
+    u3 = _host(loose.solve(F1).u)
+    U = [torch.empty_like(F1) for _ in range(3)]
     torch.cuda.synchronize()
-    B.bura_submit(plan.handle, F, u, 2)
-    import time
-    t0 = time.time()
-    while True:
-        code, rep = B.bura_poll(plan.handle)
-        if code != B.BURA_PENDING:
-            break
-        assert time.time() - t0 < 60
-        time.sleep(0.001)
-    assert code == B.BURA_OK
-    assert np.array_equal(_host(u), u_sync)
+    t1 = B.bura_submit(plan.handle, F1, U[0], 2)
+    t2 = B.bura_submit(plan.handle, F2, U[1], 2)
+    t3 = B.bura_submit(plan.handle, F1, U[2], 2, tol=1e-8)
+    assert len({t1, t2, t3}) == 3 and 0 not in (t1, t2, t3)
+    code3, rep3 = B.bura_wait(t3)        # the last one: the others ran before it
+    assert code3 == B.BURA_OK and max(rep3.relres[:6]) <= 1e-8
+    code1, rep1 = B.bura_poll(t1)
+    code2, rep2 = B.bura_wait(t2)
+    assert code1 == B.BURA_OK and code2 == B.BURA_OK
+    assert max(rep1.relres[:6]) <= 1e-12
+    assert B.bura_poll(t1)[0] == B.BURA_EINVAL   # released
+    assert np.array_equal(_host(U[0]), u1)
+    assert np.array_equal(_host(U[1]), u2)
+    assert np.array_equal(_host(U[2]), u3)
     plan.close()
+    loose.close()
+
+
+def test_unscaled_rhs_returns_lambda_scaled_result():
+    """rhs_unscaled = 1: f is f~ of the unscaled A~^alpha u = f~, and the plan
+    returns Lambda^-alpha A^-alpha f~ (Section 1.4, eq. (10)), Lambda = 4 dim/h^2
+    for the Laplacian (Section 5.3's scaling); for the BURA, the multi-step and
+    the product forms, in FP64 and mixed precision."""
+    from conftest import oracle_coeffs
+    from oracle import spectral
+    B = _B()
+    n, dim = 127, 2
+    lam = 4.0 * dim * (n + 1) ** 2
+    F = synth.normal_rhs(n, dim, nrhs=1, tag=83)
+    cases = [
+        ("bura", dict(alpha=0.5, k=7), 0.5, [(0.5, 7)]),
+        ("product", dict(alpha=0.25, k=6, form="product"), 0.25, [(0.25, 6)]),
+        ("multistep", dict(alpha=[0.5, 0.25], k=[7, 6], form="multistep"), 0.75, [(0.5, 7), (0.25, 6)]),
+    ]
+    for name, kw, alpha, steps in cases:
+        for prec in (B.BURA_FP64, B.BURA_MIXED):
+            alpha_arg = kw.pop("alpha")
+            k_arg = kw.pop("k")
+            plan = B.Plan(dim, n, alpha_arg, k_arg, precision=prec, tol=1e-12, rhs_unscaled=1, **kw)
+            kw.update(alpha=alpha_arg, k=k_arg)
+            u = _host(plan.solve(_dev(F)).u)
+            ref = F
+            for a, k in steps:
+                b = oracle_coeffs(a, k)
+                ref = spectral.bura_spectral(ref, dim, b.c_f64, b.d_f64)
+            ref = lam ** (-alpha) * ref
+            err = float(np.linalg.norm(u - ref) / np.linalg.norm(ref))
+            print(f"unscaled {name} prec={prec}: rel err {err:.2e}")
+            assert err <= 1e-9
+            plan.close()
 
 
 def test_multi_alpha_plan_equals_single_plans():

@@ -53,9 +53,18 @@ def test_library_matches_oracle(alpha, k):
     assert d[0] == 0.0
 
 
-@pytest.mark.parametrize("alpha,k", [(0.5, 5), (0.25, 9), (0.75, 9), (0.1, 12), (0.9, 12), (0.9, 5), (0.6, 7)])
+EQUI_PAIRS = [(0.5, 5), (0.25, 9), (0.75, 9), (0.1, 12), (0.6, 7)] + [(0.9, k) for k in range(5, 13)]
+
+
+@pytest.mark.parametrize("alpha,k", EQUI_PAIRS)
 def test_library_equioscillation(alpha, k):
-    """Definition 2.1 / Lemma 2.5 on the library's own double-precision output."""
+    """Definition 2.1 and the equioscillation property of Section 3.1 (Lemma 2.5:
+    real negative interlaced poles, c_j > 0) on the library's own
+    double-precision output: the error t^(1-alpha) - r(t) of
+    r(t) = t sum_j c_j/(t - d_j) changes sign exactly 2k+1 times on [0,1], and
+    between consecutive sign changes (with t = 0 and t = 1 in the end pieces)
+    its local maximum |e| equals E -- levelled alternation at 2k+2 points,
+    which characterises the best approximation -- and nowhere exceeds E."""
     c, d, E = _lib().bura_coefficients(alpha, k)
     assert c[0] == pytest.approx(E, rel=1e-14)                       # eq. (23)
     assert all(x > 0 for x in c) and all(d[j] > d[j + 1] for j in range(k))
@@ -68,17 +77,32 @@ def test_library_equioscillation(alpha, k):
             r = cm[0] + mp.fsum(cm[j] * t / (t - dm[j]) for j in range(1, k + 1))
             return t ** g - r
 
-        # dense grid in log t and in t: nowhere larger than E (up to coefficient rounding)
-        grid = [mp.mpf(10) ** (-x / mp.mpf(25)) for x in range(0, 25 * 40)] + [mp.mpf(i) / 400 for i in range(401)]
+        # dense grid: 25 points per decade down to 1e-40, and uniform in t
+        grid = sorted(set([mp.mpf(0)] + [mp.mpf(10) ** (-x / mp.mpf(25)) for x in range(0, 25 * 40)]
+                          + [mp.mpf(i) / 400 for i in range(1, 401)]))
         vals = [err(t) for t in grid]
-        worst = max(abs(v) for v in vals)
-        assert worst <= E * (1 + 1e-6)
-        # and the error reaches -E at t = 0 and +-E at t = 1 with 2k+1 sign changes in between
-        assert err(mp.mpf(0)) == pytest.approx(-E, rel=1e-12)
-        assert abs(err(mp.mpf(1))) == pytest.approx(E, rel=1e-6)
-        signs = [v > 0 for v in sorted(zip(grid, vals))[::1] for v in [v[1]]]
-        changes = sum(1 for a, b in zip(signs, signs[1:]) if a != b)
-        assert changes >= 2 * k + 1
+        assert max(abs(v) for v in vals) <= E * (1 + 1e-6)
+        cut = [i for i in range(len(grid) - 1) if (vals[i] > 0) != (vals[i + 1] > 0)]
+        assert len(cut) == 2 * k + 1
+        # pieces between sign changes; the extremum of each by a zoomed search in log t
+        edges = [0] + [i + 1 for i in cut] + [len(grid)]
+        extrema = []
+        for p_ in range(2 * k + 2):
+            lo, hi = grid[max(edges[p_] - 1, 0)], grid[min(edges[p_ + 1], len(grid) - 1)]
+            cand = [grid[i] for i in range(edges[p_], edges[p_ + 1])]
+            best = max(cand, key=lambda t: abs(err(t)))
+            if 0 < best < 1:
+                a_, b_ = mp.log(max(lo, best / 10)), mp.log(min(hi, best * 10))
+                for _ in range(8):
+                    pts = [mp.exp(a_ + (b_ - a_) * j / 24) for j in range(25)]
+                    jb = max(range(25), key=lambda j: abs(err(pts[j])))
+                    a_, b_ = mp.log(pts[max(jb - 1, 0)]), mp.log(pts[min(jb + 1, 24)])
+                    best = max(best, pts[jb], key=lambda t: abs(err(t)))
+            extrema.append((best, err(best)))
+        assert extrema[0][0] == 0 and extrema[-1][0] == 1
+        for i, (t, e) in enumerate(extrema):
+            assert abs(e) == pytest.approx(E, rel=1e-6), (i, float(t), float(e), E)
+            assert (e > 0) == (i % 2 == 1), (i, float(t))    # -E at t = 0, then alternating
 
 
 @pytest.mark.parametrize("alpha,col", [(0.25, 1), (0.5, 1), (0.25, 3), (0.5, 3), (0.75, 3)])

@@ -165,3 +165,49 @@ def test_table11_eigenvector_columns(alpha):
         mean_ref, max_ref = cols[alpha]
         assert abs(err.mean() - mean_ref) <= tol * mean_ref, (N, err.mean(), mean_ref)
         assert abs(err.max() - max_ref) <= tol * max_ref, (N, err.max(), max_ref)
+
+
+def _stored_pairs():
+    d = _load_stored()
+    return sorted((float(k.split(",")[0]), int(k.split(",")[1])) for k in d if not k.startswith("_"))
+
+
+def _load_stored():
+    import json
+    from conftest import golden_path
+    return json.load(open(golden_path("oracle_bura_coefficients.json")))
+
+
+@pytest.mark.parametrize("alpha,k", _stored_pairs())
+def test_stored_oracle_coefficients_equioscillate(alpha, k):
+    """Every stored oracle result (the whole serving domain alpha = 0.1..0.9,
+    k = 5..12, and the workload pairs) is a best approximation: with its
+    30-digit c_j, d_j, r(t) = t sum_j c_j/(t - d_j) has error t^(1-alpha) - r
+    equal to -E, +E, -E, ... at its 2k+2 stored alternation points (t = 0 and
+    t = 1 among them; Section 3.1's equioscillation) and no larger value on a
+    dense log grid; poles interlace below zero and the weights are positive
+    (Lemma 2.5), c_0 = E (eq. (23))."""
+    rec = _load_stored()[f"{alpha:.2f},{k}"]
+    assert "error" not in rec
+    with mp.workdps(40):
+        c = [mp.mpf(x) for x in rec["c"]]
+        d = [mp.mpf(x) for x in rec["d"]]
+        E = mp.mpf(rec["E"])
+        eta = [mp.mpf(x) for x in rec["eta"]]
+        g = 1 - mp.mpf(alpha)
+        assert len(c) == k + 1 and len(eta) == 2 * k + 2
+        assert all(x > 0 for x in c) and d[0] == 0 and all(d[j] > d[j + 1] for j in range(k))
+        assert abs(c[0] / E - 1) < mp.mpf(10) ** -25
+
+        def err(t):
+            return t ** g - (c[0] + mp.fsum(c[j] * t / (t - d[j]) for j in range(1, k + 1)))
+
+        # the first point is t = 0 up to the zoomed search's resolution
+        assert eta[0] < mp.mpf(10) ** -30 and eta[-1] == 1 and all(eta[i] < eta[i + 1] for i in range(2 * k + 1))
+        assert abs(err(mp.mpf(0)) / E + 1) < mp.mpf(10) ** -12
+        for i, t in enumerate(eta):
+            e = err(t)
+            assert abs(abs(e) / E - 1) < mp.mpf(10) ** -12, (i, t)
+            assert (e > 0) == (i % 2 == 1)
+        grid = [mp.mpf(10) ** (-x / mp.mpf(20)) for x in range(0, 20 * 40)]
+        assert max(abs(err(t)) for t in grid) <= E * (1 + mp.mpf(10) ** -12)
