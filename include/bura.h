@@ -351,9 +351,13 @@ enum bura_kernel_class {
   BURA_K_RESIDUAL64 = 8,     /* FP64 refinement residual                                           */
   BURA_K_COMBINE = 9,        /* u = sum_j c_j x_j                                                  */
   BURA_K_OTHER = 10,         /* per-system scalar updates, copies                                  */
-  BURA_K_DOWN_FINE = 11,     /* finest level, fused: sweeps from zero + residual + restriction    */
+  BURA_K_DOWN_FINE = 11,     /* finest level, fused, with the PCG residual update r -= alpha q:
+                                sweeps from zero + residual + restriction                          */
   BURA_K_UP_FINE = 12,       /* finest level, fused: prolongation + sweeps + r.z                  */
-  BURA_K_COUNT = 13
+  BURA_K_DOWN_FINE_PLAIN = 13, /* finest level, fused, without the residual update (the first
+                                preconditioner application of each PCG solve)                    */
+  BURA_K_SMOOTH_FINE_RUP = 14, /* first fine-level sweep with the PCG residual update (3D)         */
+  BURA_K_COUNT = 15
 };
 
 /* Profiling of the plan's launches (for measurement, not for production use).
@@ -369,6 +373,13 @@ int bura_plan_profile(bura_plan_t plan, int enable);
  * class since profiling was enabled.  Synchronises the plan's stream. */
 int bura_plan_kernel_stats(bura_plan_t plan, int kclass, long long* launches, double* total_ms,
                            double* alg_bytes);
+
+/* Measurement utility (not part of the method): copy `bytes` bytes from
+ * src_dev to dst_dev on `stream` (NULL: the null stream) with the library's
+ * plain streaming kernel (16-byte loads and stores, one pass), so that HBM
+ * counters can be calibrated on a kernel of known traffic.  Both pointers
+ * must be 16-byte aligned and the buffers must not overlap.  Asynchronous. */
+int bura_device_copy(void* dst_dev, const void* src_dev, size_t bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Request server (continuous batching on one GPU).

@@ -13,11 +13,16 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 
+def shifted_factor(A: sp.spmatrix, shift: float):
+    """SuperLU factorisation of A + shift I (its .solve applies the inverse)."""
+    N = A.shape[0]
+    return spla.splu((A + shift * sp.identity(N, format="csr")).tocsc())
+
+
 def shifted_solve_direct(A: sp.spmatrix, shift: float, F: np.ndarray) -> np.ndarray:
     """(A + shift I)^-1 F for a batch F of shape (nrhs, N) by SuperLU."""
     N = A.shape[0]
-    M = (A + shift * sp.identity(N, format="csr")).tocsc()
-    lu = spla.splu(M)
+    lu = shifted_factor(A, shift)
     return lu.solve(np.ascontiguousarray(F.reshape(F.shape[0], N).T)).T
 
 

@@ -160,6 +160,7 @@ _SIGS = {
     "bura_solve_static": (_I, [ctypes.POINTER(bura_grid_t), _I, _DP, _DP, ctypes.POINTER(bura_opts_t), _P, _P, _I,
                                ctypes.POINTER(bura_report_t)]),
     "bura_strerror": (ctypes.c_char_p, [_I]),
+    "bura_device_copy": (_I, [_P, _P, ctypes.c_size_t, _P]),
     "bura_server_create": (_I, [ctypes.c_size_t, _I, _I, ctypes.POINTER(_P)]),
     "bura_server_submit": (_I, [_P, ctypes.POINTER(bura_request_t), _P, _P, ctypes.POINTER(ctypes.c_uint64)]),
     "bura_server_poll": (_I, [_P, ctypes.c_uint64, ctypes.POINTER(bura_report_t)]),
@@ -486,7 +487,8 @@ def bura_plan_apply(plan, shift: float, x: torch.Tensor, y: torch.Tensor, nvec: 
 
 
 KERNEL_CLASSES = ["smooth_fine", "smooth_coarse", "restrict", "prolong", "coarse_lds", "spmv", "update_xr",
-                  "update_p", "residual64", "combine", "other", "down_fine", "up_fine"]
+                  "update_p", "residual64", "combine", "other", "down_fine", "up_fine", "down_fine_plain",
+                  "smooth_fine_rup"]
 
 
 def bura_plan_profile(plan, enable):
@@ -519,6 +521,17 @@ def bura_plan_set_tiles(plan, variants):
     v = list(variants)
     buf = (ctypes.c_int * len(v))(*v)
     _check(_lib.bura_plan_set_tiles(plan, buf, len(v)), "bura_plan_set_tiles")
+
+
+def bura_device_copy(dst: torch.Tensor, src: torch.Tensor, stream=None):
+    """dst = src with the library's streaming copy kernel (counter calibration)."""
+    if not (dst.is_cuda and src.is_cuda and dst.is_contiguous() and src.is_contiguous()):
+        raise ValueError("contiguous CUDA tensors expected")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("dst is smaller than src")
+    _check(_lib.bura_device_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
+                                 _stream_ptr(stream)), "bura_device_copy")
 
 
 def bura_plan_destroy(plan):

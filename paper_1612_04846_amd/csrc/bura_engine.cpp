@@ -691,7 +691,7 @@ void precondition(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, const int* a
     auto bl = [&](int l) { return l == 0 ? (ru ? ru->rnew : off(W.r, 0)) : off(W.bl[l], l); };
     for (int l = 0; l < lc; ++l) {
       {
-        ProfScope ps(P, l == 0 ? BURA_K_DOWN_FINE : BURA_K_SMOOTH_COARSE);
+        ProfScope ps(P, l > 0 ? BURA_K_SMOOTH_COARSE : ru ? BURA_K_DOWN_FINE : BURA_K_DOWN_FINE_PLAIN);
         if (l == 0 && ru)
           Launch<T>::fused_down(dim, var, nu1, level_view<T>(P, 0), level_view<T>(P, 1), ru->rold, A(0), bl(1),
                                 shift, active, wpre, nsys, st, ps.ctr, ru->p, ru->alpha, ru->rnew, partial,
@@ -733,7 +733,7 @@ void precondition(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, const int* a
     const int scls = l == 0 ? BURA_K_SMOOTH_FINE : BURA_K_SMOOTH_COARSE;
     if (l == 0 && ru) {
       {
-        ProfScope ps(P, scls);
+        ProfScope ps(P, BURA_K_SMOOTH_FINE_RUP);
         Launch<T>::jacobi_rup(dim, var, L, ru->rold, ru->q, ru->alpha, ru->rnew, out, shift, active, w_at(wpre, 0),
                               partial, nsys, st, ps.ctr, ru->fin, ru->p);
       }
@@ -1736,6 +1736,16 @@ int bura_solve_static(const bura_grid_t* grid, int nterms, const double* weights
   rc = do_solve(P, f_dev, u_dev, nrhs, rep);
   bura_plan_destroy(P);
   return rc;
+}
+
+int bura_device_copy(void* dst_dev, const void* src_dev, size_t bytes, void* stream) {
+  if (!dst_dev || !src_dev || ((uintptr_t)dst_dev & 15) || ((uintptr_t)src_dev & 15)) return BURA_EINVAL;
+  const char* d = (const char*)dst_dev;
+  const char* s = (const char*)src_dev;
+  if (d < s + bytes && s < d + bytes) return BURA_EINVAL;
+  launch_stream_copy(dst_dev, src_dev, bytes, (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return BURA_OK;
 }
 
 int bura_opts_default(bura_opts_t* o) {

@@ -165,6 +165,8 @@ void launch_apply64(int dim, bool var, const LevelDev<double>& L, const double* 
 void launch_scalars(int op, const double* partial, int nblk, int nsys, SysState st_, double tol,
                     int max_iter, hipStream_t st);
 void launch_zero(void* p, size_t bytes, hipStream_t st);
+// dst = src, 16-byte aligned, non-overlapping (counter calibration)
+void launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
 void launch_fill_int(int* p, long long n, int v, hipStream_t st);
 void launch_slot_flags(int* p, int nterms, int R, int nrhs, hipStream_t st);
 

@@ -2405,6 +2405,26 @@ __global__ void k_zero(unsigned char* p, size_t bytes) {
   for (size_t i = tid; i < head + (bytes - tail0); i += stride) p[i < head ? i : tail0 + (i - head)] = 0;
 }
 
+// One read and one write of every byte: 16-byte vector accesses over the body,
+// grid-stride over 2048 workgroups x 256 threads (8 per CU), bytes for the tail.
+__global__ __launch_bounds__(256) void k_stream_copy(uint4* __restrict__ dst, const uint4* __restrict__ src,
+                                                     size_t words, unsigned char* __restrict__ dtail,
+                                                     const unsigned char* __restrict__ stail, int tail) {
+  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = tid; i < words; i += stride) dst[i] = src[i];
+  if (tid < (size_t)tail) dtail[tid] = stail[tid];
+}
+
+void launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return;
+  const size_t words = bytes / 16;
+  const int tail = (int)(bytes - words * 16);
+  const size_t blocks = std::max<size_t>(1, std::min<size_t>((words + 255) / 256, 2048));
+  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, st, (uint4*)dst, (const uint4*)src, words,
+                     (unsigned char*)dst + words * 16, (const unsigned char*)src + words * 16, tail);
+}
+
 void launch_zero(void* p, size_t bytes, hipStream_t st) {
   if (bytes == 0) return;
   const size_t blocks = std::min<size_t>((bytes + 255) / 256, 4096);
