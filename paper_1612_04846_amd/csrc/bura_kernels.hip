@@ -1068,6 +1068,26 @@ constexpr int kDownTile[kTileVariants][2] = {{64, 6}, {32, 8}, {64, 8}};
 constexpr int kUpTile[kTileVariants][2] = {{64, 16}, {64, 8}, {64, 24}};
 constexpr int kSpmvTile[kTileVariants][2] = {{4, 128}, {2, 64}, {8, 128}};
 
+// Reciprocal of a Jacobi diagonal, formed once per point and kernel: the sweeps
+// multiply by it.  FP32: the hardware reciprocal (within 1 ulp); FP64: IEEE
+// division.  A damped Jacobi sweep with D^-1 off by an ulp is the same
+// symmetric smoother up to rounding, and the value is the same for a point in
+// every launch shape.
+__device__ __forceinline__ float jacobi_recip(float d) { return __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double jacobi_recip(double d) { return 1.0 / d; }
+
+// The fused 2D level kernels are bound by instruction issue (FP32 moves half
+// the bytes of FP64 per point with the same instructions), so their sweeps are
+// branch-free: every thread updates all of its region points, points off the
+// grid carry a zero inverse diagonal and stay exactly 0 (b = 0 there), and the
+// LDS array is padded so that the neighbours of every lane's point, the
+// unused lanes of the last row of threads included, are inside it (the pads
+// hold zeros, everything else finite values).  A sweep's values are exact on
+// the range it is valid on (shrinking by one point per sweep) and finite
+// garbage outside it, which no valid point reads.  Per-point branches had
+// kept one exec mask per point and phase alive, which spilled the scalar
+// registers into vector lanes (about 600 lane moves per wave).
+
 // RUP: the right-hand side is first advanced by the PCG step, b = b_old -
 // alpha (A + s) p (read from b, written to bout on the owned points, |b|^2 into
 // partial), so the vector update of the PCG iteration costs no pass of its
@@ -1076,11 +1096,15 @@ constexpr int kSpmvTile[kTileVariants][2] = {{4, 128}, {2, 64}, {8, 128}};
 // then only dots it with p and stores no q, one vector pass less per
 // iteration.  bout must not be b: neighbouring blocks still read b_old in
 // their halos.
-// (RUP with constant coefficients: the compiler is asked for 5 waves per
-// SIMD; left alone it spends up to 97 VGPRs on the FP64 64 x 6 tile, 4 waves,
-// and the kernel ran 4 % slower)
+// (occupancy: for FP32 constant coefficients the compiler is asked for 5
+// waves per SIMD; left alone it takes a few registers more and one wave
+// less.  Variable coefficients (4 face weights per region point in
+// registers) and FP64 spill registers under such a request -- the 64 x 8
+// variable-coefficient tile at 4 waves ran at half the speed it has at 3 --
+// and are left to the compiler.)
 template <typename T, bool VAR, int NU, bool RUP, int CX, int CY>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RUP && !VAR ? 5 : 1))) void k_down2(LevelDev<T> Lf, LevelDev<T> Lc, const T* __restrict__ b,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && !VAR ? 5 : 1))) void k_down2(
+    LevelDev<T> Lf, LevelDev<T> Lc, const T* __restrict__ b,
                                                T* __restrict__ xout, T* __restrict__ bc,
                                                const T* __restrict__ shift, const int* __restrict__ active,
                                                Sweeps<T> om, unsigned long long* __restrict__ ctr,
@@ -1090,13 +1114,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RUP && !VAR
   // RUP: p on the region widened by one point per side (row length PX),
   // staged in the same LDS array before it takes the iterate
   constexpr int PX = RX + 2, PY = RY + 2, PN = PX * PY;
-  constexpr int LN = RUP && PN > RN ? PN : RN;
-  // One LDS array: the iterate, then the residual.  Thread tid owns region
-  // points tid + 256 u (u < PER) throughout and keeps their b and x in
-  // registers; a sweep reads its neighbours from LDS, and its results are
-  // written back after a barrier (a second barrier before the next reads).
-  // Against separate b, x and x_new arrays this needs a third of the LDS, so
-  // twice the workgroups are resident per CU.
+  constexpr int PER = (RN + 255) / 256, PPER = RUP ? (PN + 255) / 256 : 1;
+  // LDS: a zero pad of PAD values before the data, the data at PAD + q, and
+  // room after it for the farthest neighbour any lane reads (lanes q >= RN of
+  // the last row of threads included); the p layout (row length PX) reaches
+  // further than the iterate layout
+  constexpr int PAD = (RUP ? PX : RX) + 1;
+  constexpr int QMAX = PER * 256 - 1;
+  constexpr int PQMAX = RUP ? ((QMAX / RX) + 1) * PX + RX : 0;
+  constexpr int HI = (QMAX + RX) > (PQMAX + PX) ? (QMAX + RX) : (PQMAX + PX);
+  constexpr int DATA = PER * 256 > (RUP ? PPER * 256 : 0) ? PER * 256 : PPER * 256;
+  constexpr int LN = PAD + (HI + 1 > DATA ? HI + 1 : DATA);
+  // One LDS array: p (RUP), then the iterate, then the residual.  Thread tid
+  // owns region points tid + 256 u (u < PER) throughout and keeps their b,
+  // x and 1/D in registers; a sweep reads its neighbours from LDS, and its
+  // results are written back after a barrier (a second barrier before the
+  // next reads).
   __shared__ T sx[LN];
   const Tile tl = block_tile();
   const int sys = tl.z;
@@ -1110,160 +1143,145 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RUP && !VAR
   const int gx0 = 2 * I0 - NU, gy0 = 2 * J0 - NU;
   const T sh = shift[sys];
   const T dcon = Lf.wc * T(4) + sh;   // the diagonal for constant coefficients
+  const T rcon = jacobi_recip(dcon);
   const long long off = (long long)sys * Lf.N;
+  const T* __restrict__ bs = b + off;
   const int tid = threadIdx.x;
-  // stage b (0 outside the grid) and the first sweep from x = 0: x1 = omega b / D.
-  // All loads of a thread are issued before any is used (clamped addresses,
-  // results selected afterwards), so a wave keeps PER loads in flight.
-  constexpr int PER = (RN + 255) / 256, PPER = RUP ? (PN + 255) / 256 : 1;
-  T bl[PER], pl[PPER];
+  // the pads: zeros (the data range is written below before it is read)
+  for (int i = tid; i < PAD; i += 256) sx[i] = T(0);
+  for (int i = PAD + DATA + tid; i < LN; i += 256) sx[i] = T(0);
+  // per point: whether it is on the grid (bit u of `in`); its grid index,
+  // clamped into the grid for the loads, is recomputed where needed (held in
+  // registers it cost occupancy)
+  unsigned in = 0u;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int q = tid + 256 * u;
+    const int ry = q / RX, rx = q - ry * RX;
+    const int gi = gx0 + rx, gj = gy0 + ry;
+    const bool on = q < RN && gi >= 0 && gi < nf && gj >= 0 && gj < nf;
+    in |= (on ? 1u : 0u) << u;
+  }
+  auto gidx = [&](int u) {
+    const int q = tid + 256 * u;
+    const int ry = q / RX, rx = q - ry * RX;
+    return min(max(gy0 + ry, 0), nf - 1) * nf + min(max(gx0 + rx, 0), nf - 1);
+  };
   // variable coefficients: the four face weights of each of this thread's
-  // region points, loaded once for every sweep and the residual instead of
-  // once per use
+  // region points, loaded once for every sweep and the residual
   RegionFaces<T, VAR, PER> fw;
   fw.load(Lf, tid, RX, RN, gx0, gy0);
+  // stage b and the first sweep from x = 0: x1 = omega b / D.  All loads of a
+  // thread are issued before any is used, so a wave keeps them all in flight.
+  T bl[PER];
   if (RUP) {
-    // p first, into LDS; b is loaded after the barrier, so the two sets of
-    // loads do not hold registers at the same time
+    // p first, into LDS (0 off the grid); b is loaded after the barrier, so
+    // the two sets of loads do not hold registers at the same time
+    const T* __restrict__ ps = pv + off;
+    T pl[PPER];
 #pragma unroll
     for (int u = 0; u < PPER; ++u) {
       const int q = tid + 256 * u;
       const int py = q / PX, px = q - py * PX;
       const int gi = gx0 - 1 + px, gj = gy0 - 1 + py;
-      const bool in = q < PN && gi >= 0 && gi < nf && gj >= 0 && gj < nf;
-      pl[u] = pv[off + (in ? (long long)gj * nf + gi : 0LL)];
+      pl[u] = ps[min(max(gj, 0), nf - 1) * nf + min(max(gi, 0), nf - 1)];
     }
 #pragma unroll
     for (int u = 0; u < PPER; ++u) {
       const int q = tid + 256 * u;
       const int py = q / PX, px = q - py * PX;
       const int gi = gx0 - 1 + px, gj = gy0 - 1 + py;
-      if (q < PN) sx[q] = (gi >= 0 && gi < nf && gj >= 0 && gj < nf) ? pl[u] : T(0);   // 0 off the grid
+      const bool on = q < PN && gi >= 0 && gi < nf && gj >= 0 && gj < nf;
+      sx[PAD + q] = on ? pl[u] : T(0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int q = tid + 256 * u;
-    const int ry = q / RX, rx = q - ry * RX;
-    const int gi = gx0 + rx, gj = gy0 + ry;
-    const bool in = q < RN && gi >= 0 && gi < nf && gj >= 0 && gj < nf;
-    bl[u] = b[off + (in ? (long long)gj * nf + gi : 0LL)];
-  }
-  T bv[PER], xv[PER];
+  for (int u = 0; u < PER; ++u) bl[u] = bs[gidx(u)];
+  // 1/D per point (0 off the grid): held for variable coefficients, a select
+  // of the one constant value otherwise
+  T bv[PER], xv[PER], rdv[VAR ? PER : 1];
+  auto rd = [&](int u) { return VAR ? rdv[VAR ? u : 0] : (((in >> u) & 1u) ? rcon : T(0)); };
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int q = tid + 256 * u;
-    const int ry = q / RX, rx = q - ry * RX;
-    const int gi = gx0 + rx, gj = gy0 + ry;
-    const bool in = q < RN && gi >= 0 && gi < nf && gj >= 0 && gj < nf;
+    const bool on = (in >> u) & 1u;
     T bn = bl[u];
-    if (RUP && in) {
-      const int pq = (ry + 1) * PX + (rx + 1);
-      const T ap = VAR ? fw.apply(u, sx, pq, PX, sh, nullptr) : lds_apply2<T, false>(sx, pq, PX, Lf, gi, gj, sh, nullptr);
+    if (RUP) {
+      const int ry = q / RX, rx = q - ry * RX;
+      const int pq = PAD + (ry + 1) * PX + (rx + 1);
+      const T ap = VAR ? fw.apply(u, sx, pq, PX, sh, nullptr) : lds_apply2<T, false>(sx, pq, PX, Lf, 0, 0, sh, nullptr);
       bn = bl[u] - am * ap;
     }
-    bv[u] = in ? bn : T(0);
-    T x1 = sweep_w(om, 0) * bv[u] / dcon;
-    if (VAR) x1 = sweep_w(om, 0) * bv[u] / fw.diag(u, sh);
-    xv[u] = in ? x1 : T(0);
+    bv[u] = on ? bn : T(0);
+    if (VAR) rdv[VAR ? u : 0] = on ? jacobi_recip(fw.diag(u, sh)) : T(0);
+    xv[u] = sweep_w(om, 0) * bv[u] * rd(u);
   }
   if (RUP) __syncthreads();   // every read of p done before sx takes the iterate
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int q = tid + 256 * u;
-    if (q < RN) sx[q] = xv[u];
-  }
+  for (int u = 0; u < PER; ++u) sx[PAD + tid + 256 * u] = xv[u];
   __syncthreads();
 #pragma unroll
-  for (int m = 1; m < NU; ++m) {   // sweep m+1 on the range shrunk by m
-    const T wm = sweep_w(om, m), wcon = wm / dcon;
-    // xv is updated in place: the sweep reads every value, the point's own
-    // included, from sx
+  for (int m = 1; m < NU; ++m) {   // sweep m+1, exact on the range shrunk by m
+    const T wm = sweep_w(om, m);
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      const int q = tid + 256 * u;
-      const int ry = q / RX, rx = q - ry * RX;
-      const int gi = gx0 + rx, gj = gy0 + ry;
-      if (q < RN && rx >= m && rx < RX - m && ry >= m && ry < RY - m && gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
-        if (VAR) {
-          T dg;
-          const T ax = fw.apply(u, sx, q, RX, sh, &dg);
-          xv[u] = xv[u] + wm * (bv[u] - ax) / dg;
-        } else {
-          const T ax = lds_apply2<T, false>(sx, q, RX, Lf, gi, gj, sh, nullptr);
-          xv[u] = xv[u] + wcon * (bv[u] - ax);
-        }
-      }
+      const int q = PAD + tid + 256 * u;
+      const T ax = VAR ? fw.apply(u, sx, q, RX, sh, nullptr) : lds_apply2<T, false>(sx, q, RX, Lf, 0, 0, sh, nullptr);
+      xv[u] = xv[u] + wm * (bv[u] - ax) * rd(u);
     }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int q = tid + 256 * u;
-      if (q < RN) sx[q] = xv[u];
-    }
+    for (int u = 0; u < PER; ++u) sx[PAD + tid + 256 * u] = xv[u];
     __syncthreads();
   }
   // owned fine points: [2 I0, 2 I0 + 2 CX) per axis, extended to the grid end on the last tile
   {
     const int hx = (I0 + CX >= nc) ? nf : 2 * (I0 + CX);
     const int hy = (J0 + CY >= nc) ? nf : 2 * (J0 + CY);
+    T* __restrict__ xs = xout + off;
+    T* __restrict__ bo = RUP ? bout + off : nullptr;
     double rr = 0.0;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int q = tid + 256 * u;
       const int ry = q / RX, rx = q - ry * RX;
       const int gi = gx0 + rx, gj = gy0 + ry;
-      if (q < RN && gi >= 2 * I0 && gi < hx && gj >= 2 * J0 && gj < hy) {
-        const long long g = off + (long long)gj * nf + gi;
-        __builtin_nontemporal_store(xv[u], &xout[g]);
-        if (RUP) {
-          __builtin_nontemporal_store(bv[u], &bout[g]);
-          rr += (double)bv[u] * (double)bv[u];
-        }
+      const bool own = ((in >> u) & 1u) && gi >= 2 * I0 && gi < hx && gj >= 2 * J0 && gj < hy;
+      if (own) {
+        const int g = gj * nf + gi;
+        __builtin_nontemporal_store(xv[u], &xs[g]);
+        if (RUP) __builtin_nontemporal_store(bv[u], &bo[g]);
       }
+      if (RUP) rr += own ? (double)bv[u] * (double)bv[u] : 0.0;
     }
     if (RUP) {
       write_partial_tile(tl, partial, sys, rr);
       finish(fin, partial, sys, gridDim.x * gridDim.y);
     }
   }
-  // residual on the range shrunk by NU (fine points 2 I0 .. 2 I0 + 2 CX),
-  // formed from the final iterate in sx (into xv, no longer needed) and then
-  // written over it
+  // residual b - (A + s) x, exact on the range shrunk by NU (fine points
+  // 2 I0 .. 2 I0 + 2 CX, all on the grid: the weighting below reads no other),
+  // formed from the final iterate in sx and then written over it
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
-    const int q = tid + 256 * u;
-    const int ry = q / RX, rx = q - ry * RX;
-    const int gi = gx0 + rx, gj = gy0 + ry;
-    T r = T(0);
-    if (q < RN && rx >= NU && rx < RX - NU && ry >= NU && ry < RY - NU && gi >= 0 && gi < nf && gj >= 0 &&
-        gj < nf) {
-      if (VAR) {
-        r = bv[u] - fw.apply(u, sx, q, RX, sh, nullptr);
-      } else {
-        r = bv[u] - lds_apply2<T, false>(sx, q, RX, Lf, gi, gj, sh, nullptr);
-      }
-    }
-    xv[u] = r;
+    const int q = PAD + tid + 256 * u;
+    xv[u] = bv[u] - (VAR ? fw.apply(u, sx, q, RX, sh, nullptr) : lds_apply2<T, false>(sx, q, RX, Lf, 0, 0, sh, nullptr));
   }
   __syncthreads();
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int q = tid + 256 * u;
-    const int ry = q / RX, rx = q - ry * RX;
-    if (q < RN && rx >= NU && rx < RX - NU && ry >= NU && ry < RY - NU) sx[q] = xv[u];
-  }
+  for (int u = 0; u < PER; ++u) sx[PAD + tid + 256 * u] = xv[u];
   __syncthreads();
   // full weighting: coarse (I, J) <- fine 2I+1 +- 1
+  T* __restrict__ bcs = bc + (long long)sys * Lc.N;
   for (int q2 = tid; q2 < CX * CY; q2 += 256) {
     const int I = I0 + (q2 % CX), J = J0 + (q2 / CX);
     if (I < nc && J < nc) {
       const int cx = 2 * I + 1 - gx0, cy = 2 * J + 1 - gy0;
-      const T* R = sx + cy * RX + cx;
+      const T* R = sx + PAD + cy * RX + cx;
       const T v = T(0.25) * R[0] + T(0.125) * (R[-1] + R[1] + R[-RX] + R[RX]) +
                   T(0.0625) * (R[-RX - 1] + R[-RX + 1] + R[RX - 1] + R[RX + 1]);
-      bc[(long long)sys * Lc.N + (long long)J * nc + I] = v;
+      bcs[J * nc + I] = v;
     }
   }
 }
@@ -1277,9 +1295,11 @@ __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, con
   constexpr int RX = OX + 2 * NU, RY = OY + 2 * NU, RN = RX * RY;
   // coarse values under the region, zero-padded: coarse index c at cx0 + (c - c0)
   constexpr int CRX = RX / 2 + 3, CRY = RY / 2 + 3, CRN = CRX * CRY;
-  // the iterate in one LDS array, b and x of a thread's points (tid + 256 u)
-  // in registers, as in k_down2
-  __shared__ T sx[RN];
+  constexpr int PER = (RN + 255) / 256, CPER = (CRN + 255) / 256;
+  // the iterate at PAD + q, zero pads around it (branch-free sweeps, as in k_down2)
+  constexpr int PAD = RX + 1;
+  constexpr int LN = PAD + PER * 256 + RX + 1;
+  __shared__ T sx[LN];
   __shared__ T sc[CRN];
   const Tile tl = block_tile();
   const int sys = tl.z;
@@ -1293,31 +1313,44 @@ __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, con
   const int cx0 = ((gx0 >= 0) ? gx0 / 2 : -((-gx0 + 1) / 2)) - 1;
   const int cy0 = ((gy0 >= 0) ? gy0 / 2 : -((-gy0 + 1) / 2)) - 1;
   const T sh = shift[sys];
-  const T dcon = Lf.wc * T(4) + sh;
+  const T rcon = jacobi_recip(Lf.wc * T(4) + sh);
   const long long off = (long long)sys * Lf.N;
-  const T* xcs = xc + (long long)sys * Lc.N;
+  const T* __restrict__ xcs = xc + (long long)sys * Lc.N;
+  const T* __restrict__ bs = b + off;
+  const T* __restrict__ xis = xin + off;
   const int tid = threadIdx.x;
-  // every global load of the staging phase is issued up front (clamped
-  // addresses, selected afterwards): the coarse tile, then b and x_in
-  constexpr int CPER = (CRN + 255) / 256, PER = (RN + 255) / 256;
-  T cl[CPER], bl[PER], xl[PER];
-#pragma unroll
-  for (int u = 0; u < CPER; ++u) {
-    const int q = tid + 256 * u;
-    const int cy = q / CRX, cx = q - cy * CRX;
-    const int I = cx0 + cx, J = cy0 + cy;
-    const bool in = q < CRN && I >= 0 && I < nc && J >= 0 && J < nc;
-    cl[u] = xcs[in ? (long long)J * nc + I : 0LL];
-  }
+  for (int i = tid; i < PAD; i += 256) sx[i] = T(0);
+  for (int i = PAD + PER * 256 + tid; i < LN; i += 256) sx[i] = T(0);
+  unsigned in = 0u;
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int q = tid + 256 * u;
     const int ry = q / RX, rx = q - ry * RX;
     const int gi = gx0 + rx, gj = gy0 + ry;
-    const bool in = q < RN && gi >= 0 && gi < nf && gj >= 0 && gj < nf;
-    const long long g = off + (in ? (long long)gj * nf + gi : 0LL);
-    bl[u] = b[g];
-    xl[u] = xin[g];
+    const bool on = q < RN && gi >= 0 && gi < nf && gj >= 0 && gj < nf;
+    in |= (on ? 1u : 0u) << u;
+  }
+  auto gidx = [&](int u) {
+    const int q = tid + 256 * u;
+    const int ry = q / RX, rx = q - ry * RX;
+    return min(max(gy0 + ry, 0), nf - 1) * nf + min(max(gx0 + rx, 0), nf - 1);
+  };
+  RegionFaces<T, VAR, PER> fw;
+  fw.load(Lf, tid, RX, RN, gx0, gy0);
+  // every global load of the staging phase is issued up front (clamped
+  // addresses, selected afterwards): the coarse tile, then b and x_in
+  T cl[CPER], bl[PER], xl[PER];
+#pragma unroll
+  for (int u = 0; u < CPER; ++u) {
+    const int q = tid + 256 * u;
+    const int cy = q / CRX, cx = q - cy * CRX;
+    cl[u] = xcs[min(max(cy0 + cy, 0), nc - 1) * nc + min(max(cx0 + cx, 0), nc - 1)];
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int g = gidx(u);
+    bl[u] = bs[g];
+    xl[u] = xis[g];
   }
 #pragma unroll
   for (int u = 0; u < CPER; ++u) {
@@ -1329,71 +1362,56 @@ __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, con
     }
   }
   __syncthreads();
-  T bv[PER], xv[PER];
+  T bv[PER], xv[PER], rdv[VAR ? PER : 1];
+  auto rd = [&](int u) { return VAR ? rdv[VAR ? u : 0] : (((in >> u) & 1u) ? rcon : T(0)); };
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
-    const int q = tid + 256 * u;
-    bv[u] = T(0);
-    xv[u] = T(0);
-    if (q < RN) {
-      const int ry = q / RX, rx = q - ry * RX;
-      const int gi = gx0 + rx, gj = gy0 + ry;
-      const bool in = gi >= 0 && gi < nf && gj >= 0 && gj < nf;
-      // multilinear interpolation from the zero-padded coarse tile
-      const int ia = (gi & 1) ? (gi - 1) / 2 : gi / 2 - 1;
-      const int ja = (gj & 1) ? (gj - 1) / 2 : gj / 2 - 1;
-      const T* C = sc + (ja - cy0) * CRX + (ia - cx0);
-      T v;
-      if (gi & 1) {
-        v = (gj & 1) ? C[0] : T(0.5) * (C[0] + C[CRX]);
-      } else {
-        v = (gj & 1) ? T(0.5) * (C[0] + C[1]) : T(0.25) * (C[0] + C[1] + C[CRX] + C[CRX + 1]);
-      }
-      if (in) {
-        bv[u] = bl[u];
-        xv[u] = xl[u] + v;
-      }
-      sx[q] = xv[u];
+    // lanes past the region interpolate at its last point (in range of sc)
+    const int q = min(tid + 256 * u, RN - 1);
+    const int ry = q / RX, rx = q - ry * RX;
+    const int gi = gx0 + rx, gj = gy0 + ry;
+    const bool on = (in >> u) & 1u;
+    // multilinear interpolation from the zero-padded coarse tile
+    const int ia = (gi & 1) ? (gi - 1) / 2 : gi / 2 - 1;
+    const int ja = (gj & 1) ? (gj - 1) / 2 : gj / 2 - 1;
+    const T* C = sc + (ja - cy0) * CRX + (ia - cx0);
+    T v;
+    if (gi & 1) {
+      v = (gj & 1) ? C[0] : T(0.5) * (C[0] + C[CRX]);
+    } else {
+      v = (gj & 1) ? T(0.5) * (C[0] + C[1]) : T(0.25) * (C[0] + C[1] + C[CRX] + C[CRX + 1]);
     }
+    bv[u] = on ? bl[u] : T(0);
+    xv[u] = on ? xl[u] + v : T(0);
+    if (VAR) rdv[VAR ? u : 0] = on ? jacobi_recip(fw.diag(u, sh)) : T(0);
+    sx[PAD + tid + 256 * u] = xv[u];
   }
   __syncthreads();
 #pragma unroll
   for (int m = 1; m <= NU; ++m) {   // post-smoothing: the pre-smoothing weights reversed
-    // (the face weights are read per sweep here: held in registers, as in the
-    // down kernel, they cost more occupancy than the two sweeps save)
-    const T wm = sweep_w(om, NU - m), wcon = wm / dcon;
-    // xv updated in place (the sweep reads every value from sx)
+    const T wm = sweep_w(om, NU - m);
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      const int q = tid + 256 * u;
-      const int ry = q / RX, rx = q - ry * RX;
-      const int gi = gx0 + rx, gj = gy0 + ry;
-      if (q < RN && rx >= m && rx < RX - m && ry >= m && ry < RY - m && gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
-        T dg;
-        const T ax = lds_apply2<T, VAR>(sx, q, RX, Lf, gi, gj, sh, VAR ? &dg : nullptr);
-        xv[u] = VAR ? xv[u] + wm * (bv[u] - ax) / dg : xv[u] + wcon * (bv[u] - ax);
-      }
+      const int q = PAD + tid + 256 * u;
+      const T ax = VAR ? fw.apply(u, sx, q, RX, sh, nullptr) : lds_apply2<T, false>(sx, q, RX, Lf, 0, 0, sh, nullptr);
+      xv[u] = xv[u] + wm * (bv[u] - ax) * rd(u);
     }
     if (m < NU) {   // the last sweep's values are written out from registers
       __syncthreads();
 #pragma unroll
-      for (int u = 0; u < PER; ++u) {
-        const int q = tid + 256 * u;
-        if (q < RN) sx[q] = xv[u];
-      }
+      for (int u = 0; u < PER; ++u) sx[PAD + tid + 256 * u] = xv[u];
       __syncthreads();
     }
   }
   double dot = 0.0;
+  T* __restrict__ xs = xout + off;
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int q = tid + 256 * u;
     const int ry = q / RX, rx = q - ry * RX;
-    const int gi = gx0 + rx, gj = gy0 + ry;
-    if (q < RN && rx >= NU && rx < NU + OX && ry >= NU && ry < NU + OY && gi < nf && gj < nf) {
-      __builtin_nontemporal_store(xv[u], &xout[off + (long long)gj * nf + gi]);
-      if (DOT) dot += (double)bv[u] * (double)xv[u];
-    }
+    const bool own = ((in >> u) & 1u) && rx >= NU && rx < NU + OX && ry >= NU && ry < NU + OY;
+    if (own) __builtin_nontemporal_store(xv[u], &xs[(gy0 + ry) * nf + gx0 + rx]);
+    if (DOT) dot += own ? (double)bv[u] * (double)xv[u] : 0.0;
   }
   if (DOT) {
     write_partial_tile(tl, partial, sys, dot);
