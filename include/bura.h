@@ -128,6 +128,11 @@ typedef struct {
                           each level's fused kernels on the plan's buffers (whole solves
                           in the plan's schedule) and keeps the fastest (cached per shape
                           in the process; see bura_plan_tiles)                           */
+  double err_tol;      /* 0: stop on the residual test (tol) alone.  > 0 (BURA_MIXED, plans
+                          without stages; else BURA_EUNSUPPORTED): also require the certified
+                          bound of the report (err_bound) to be <= err_tol; the refinement
+                          continues on the systems of every output over it (at most four
+                          more rounds, else BURA_ENOCONV)                                */
 } bura_opts_t;
 
 /* Per-solve report (host struct filled by solve/poll). */
@@ -140,11 +145,22 @@ typedef struct {
   int outer[BURA_MAX_TERMS];        /* refinement steps (MIXED), max over rhs, per pole  */
   double relres[BURA_MAX_TERMS];    /* final FP64 relative residual, max over rhs       */
   double seconds;                   /* wall time of the solve on the host clock          */
+  double err_bound;                 /* certified bound, max over outputs and rhs, of
+                                       |u - u_r| / |u|: u as computed, u_r the exact
+                                       sum_j c_j (A - d_j I)^-1 f of the same terms.  Each
+                                       system's error is (A - d_j I)^-1 r_j, so |u - u_r| <=
+                                       sum_j |c_j| |r_j| / (lam_lb - d_j), lam_lb a guaranteed
+                                       lower bound of the spectrum of A (the Laplacian's
+                                       smallest eigenvalue, times the smallest face
+                                       coefficient for variable coefficients); FP64 plans use
+                                       the PCG's recursively updated residual, BURA_MIXED the
+                                       FP64 residual of the refinement.  -1 for plans with
+                                       stages (sequential forms), where it is not formed.   */
 } bura_report_t;
 
 /* Fill *o with defaults: tol 1e-12, inner_tol 1e-5, BURA_MIXED, BURA_BATCHED,
  * max_iter 0 (automatic), max_outer 12, nrhs_max 1, check_every 4, V(2,2),
- * stream NULL. */
+ * stream NULL, err_tol 0. */
 int bura_opts_default(bura_opts_t* o);
 
 /* Step 1-2 of Section 2.2 on the host: the (k,k) best uniform rational

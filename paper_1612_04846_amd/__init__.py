@@ -75,6 +75,7 @@ class bura_opts_t(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("hbm_budget", ctypes.c_size_t),
         ("autotune", ctypes.c_int),
+        ("err_tol", ctypes.c_double),
     ]
 
 
@@ -87,6 +88,7 @@ class bura_report_t(ctypes.Structure):
         ("outer", ctypes.c_int * BURA_MAX_TERMS),
         ("relres", ctypes.c_double * BURA_MAX_TERMS),
         ("seconds", ctypes.c_double),
+        ("err_bound", ctypes.c_double),
     ]
 
 

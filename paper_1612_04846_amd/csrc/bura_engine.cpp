@@ -179,6 +179,14 @@ struct bura_plan_s {
   hipEvent_t join_ev = nullptr;
   void* h_state = nullptr;             // pinned mirror of the scalar state for reports
   double run_tol = 0.0;                // stopping tolerance of the solve in progress
+  // a posteriori error bound (see do_solve): a guaranteed lower bound of the
+  // spectrum of the scaled operator, the combine weights as applied, the
+  // squared norms of the outputs (device, and their host copy after the state)
+  double lam_lb = 0.0;
+  std::vector<double> w_applied;
+  double* d_upart = nullptr;   // rows x ceil(N/256) partial sums
+  double* d_unorm = nullptr;   // rows = nout x nrhs_max
+  double* d_tol_err = nullptr; // MIXED: per-system refinement tolerances set by opts.err_tol
   // asynchronous solves: a FIFO of submitted solves run in order by one
   // worker thread; exec_mu serialises them with synchronous solves
   struct Job {
@@ -446,6 +454,17 @@ int build_levels(bura_plan_t P, const bura_grid_t* g) {
     P->lambda = g->lambda_upper;   // caller's bound (cannot be verified cheaply)
   } else {
     P->lambda = gb;
+  }
+  // lower bound of the spectrum of A = A~/Lambda: the Laplacian's smallest
+  // eigenvalue 4 dim sin^2(pi h/2)/h^2; with coefficients x^T A~ x =
+  // h^-2 sum_faces a_f (x_i - x_nb)^2 >= a_min x^T A~_Laplacian x
+  {
+    double amin = P->var ? HUGE_VAL : 1.0;
+    if (P->var)
+      for (int a = 0; a < dim; ++a)
+        for (double v : L0.wf[a]) amin = std::min(amin, v);
+    const double sn = std::sin(3.14159265358979323846 * h / 2.0);
+    P->lam_lb = amin * 4.0 * dim * sn * sn / (h * h) / P->lambda * (1.0 - 1e-12);
   }
   const double scale0 = 1.0 / (P->lambda * h * h);
   L0.wc = scale0;
@@ -980,31 +999,16 @@ int solve_batch_fp64(bura_plan_t P, const double* f, int nrhs, size_t sys0, int 
   return run_pcg<double>(P, W, sys0, nsys, P->run_tol, P->opts.max_iter, combine_finishes_x(P));
 }
 
-int solve_batch_mixed(bura_plan_t P, const double* f, int nrhs, size_t sys0, int nsys, bool preset) {
+// The refinement loop of a mixed batch (the FP64 residual of every active
+// system already formed and tested): FP32 inner solves on the active systems,
+// x64 += e, the FP64 residual and the outer test, until no system is active.
+int mixed_outer_loop(bura_plan_t P, const double* f, int nrhs, size_t sys0, int nsys) {
   hipStream_t st = P->stream;
   Work<float>& W = P->w32;
   const LevelDev<double> L0 = level_view<double>(P, 0);
   const size_t o = sys0 * (size_t)P->N;
   const SysState S = state_at(P, sys0);
   int rc;
-  if (!preset) {
-    if ((rc = set_flags(P, P->st.active64, sys0, nsys, 1))) return rc;
-    if ((rc = set_flags(P, P->st.active, sys0, nsys, 1))) return rc;
-  } else {
-    // inner flags follow the outer ones (OP_OUTER re-arms them per system)
-    HIPCHK(hipMemcpyAsync(P->st.active + sys0, P->st.active64 + sys0, nsys * sizeof(int), hipMemcpyDeviceToDevice,
-                          P->stream));
-  }
-  launch_zero(S.alpha, (size_t)nsys * sizeof(double), st);   // see solve_batch_fp64
-  {
-    ProfScope ps(P, BURA_K_RESIDUAL64);
-    launch_residual64(P->dim, P->var, L0, f, P->x64 + o, W.x + o, W.r + o, P->d_shift64 + sys0, S.active64,
-                      P->partial, nrhs, nsys, true, st, ps.ctr);
-  }
-  {
-    ProfScope ps(P, BURA_K_OTHER);
-    launch_scalars(OP_OUTER, P->partial, flat_blocks(P->N), nsys, S, P->run_tol, P->opts.max_outer, st);
-  }
   for (int outer = 0; outer < P->opts.max_outer + 1; ++outer) {
     const int a = count_active(P, P->st.active64, sys0, nsys);
     if (a < 0) {
@@ -1034,6 +1038,60 @@ int solve_batch_mixed(bura_plan_t P, const double* f, int nrhs, size_t sys0, int
   }
   HIPCHK(hipGetLastError());
   return BURA_OK;
+}
+
+int solve_batch_mixed(bura_plan_t P, const double* f, int nrhs, size_t sys0, int nsys, bool preset) {
+  hipStream_t st = P->stream;
+  Work<float>& W = P->w32;
+  const LevelDev<double> L0 = level_view<double>(P, 0);
+  const size_t o = sys0 * (size_t)P->N;
+  const SysState S = state_at(P, sys0);
+  int rc;
+  if (!preset) {
+    if ((rc = set_flags(P, P->st.active64, sys0, nsys, 1))) return rc;
+    if ((rc = set_flags(P, P->st.active, sys0, nsys, 1))) return rc;
+  } else {
+    // inner flags follow the outer ones (OP_OUTER re-arms them per system)
+    HIPCHK(hipMemcpyAsync(P->st.active + sys0, P->st.active64 + sys0, nsys * sizeof(int), hipMemcpyDeviceToDevice,
+                          P->stream));
+  }
+  launch_zero(S.alpha, (size_t)nsys * sizeof(double), st);   // see solve_batch_fp64
+  {
+    ProfScope ps(P, BURA_K_RESIDUAL64);
+    launch_residual64(P->dim, P->var, L0, f, P->x64 + o, W.x + o, W.r + o, P->d_shift64 + sys0, S.active64,
+                      P->partial, nrhs, nsys, true, st, ps.ctr);
+  }
+  {
+    ProfScope ps(P, BURA_K_OTHER);
+    launch_scalars(OP_OUTER, P->partial, flat_blocks(P->N), nsys, S, P->run_tol, P->opts.max_outer, st);
+  }
+  return mixed_outer_loop(P, f, nrhs, sys0, nsys);
+}
+
+// Continue the refinement of the systems of [sys0, sys0 + nsys) flagged in
+// the host array act (1 = continue) from their current x64: their FP64
+// residual is formed again and tested against the current tolerances (the
+// per-system ones if st.tol_outer is set).
+int resume_batch_mixed(bura_plan_t P, const double* f, int nrhs, size_t sys0, int nsys, const int* act) {
+  hipStream_t st = P->stream;
+  Work<float>& W = P->w32;
+  const LevelDev<double> L0 = level_view<double>(P, 0);
+  const size_t o = sys0 * (size_t)P->N;
+  const SysState S = state_at(P, sys0);
+  HIPCHK(hipMemcpyAsync(P->st.active64 + sys0, act, nsys * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(P->st.active + sys0, act, nsys * sizeof(int), hipMemcpyHostToDevice, st));
+  launch_zero(S.alpha, (size_t)nsys * sizeof(double), st);
+  {
+    ProfScope ps(P, BURA_K_RESIDUAL64);
+    launch_residual64(P->dim, P->var, L0, f, P->x64 + o, W.x + o, W.r + o, P->d_shift64 + sys0, S.active64,
+                      P->partial, nrhs, nsys, false, st, ps.ctr);
+  }
+  {
+    ProfScope ps(P, BURA_K_OTHER);
+    launch_scalars(OP_OUTER, P->partial, stencil_blocks(P->dim, P->n), nsys, S, P->run_tol, P->opts.max_outer,
+                   st);
+  }
+  return mixed_outer_loop(P, f, nrhs, sys0, nsys);
 }
 
 // Per-solve terms of a slot plan: rhs r has nterms[r] terms with weights
@@ -1129,11 +1187,6 @@ int do_solve(bura_plan_t P, const double* f, double* u, int nrhs, bura_report_t*
     // every rhs with its own terms, all in one batch; unused slots inactive
     if ((rc = upload_slots(P, nrhs, *slot))) return rc;
     rc = batch(0, (int)S_used, true);
-    if (rc) return rc;
-    ProfScope ps(P, BURA_K_COMBINE);
-    const bool pend = combine_finishes_x(P);
-    launch_combine(P->N, xsol, P->d_wsys, P->nterms, nrhs, R, u, P->stream, ps.ctr, nullptr, 0.0, true,
-                   pend ? P->w64.p : nullptr, pend ? P->w64.p2 : nullptr, P->st.alpha, P->st.iters);
   } else if (!P->stages.empty()) {
     // sequential form: each stage solves its terms against its input, then
     // combines into the stage buffer (or u for the last stage)
@@ -1173,30 +1226,131 @@ int do_solve(bura_plan_t P, const double* f, double* u, int nrhs, bura_report_t*
     rc = batch(0, (int)S_used, true);
   }
   if (rc) return rc;
-  // combine u_i = sum_{j in output i} w_j x_j (fixed order, FP64)
-  for (int i = 0; i < P->nout && P->stages.empty() && !slot; ++i) {
-    ProfScope ps(P, BURA_K_COMBINE);
-    const int b = P->out_begin[i], e = P->out_end[i];
-    const size_t ob = (size_t)b * R;   // first system of output i
-    const bool pend = combine_finishes_x(P);
-    launch_combine(P->N, xsol + ob * P->N, P->d_w + b, e - b, nrhs, R, u + (size_t)i * nrhs * P->N, P->stream,
-                   ps.ctr, nullptr, 0.0, false, pend ? P->w64.p + ob * P->N : nullptr,
-                   pend ? P->w64.p2 + ob * P->N : nullptr, P->st.alpha + ob, P->st.iters + ob);
-  }
-  HIPCHK(hipGetLastError());
-  // report: one copy of the per-system scalar state into pinned memory
   const size_t S = (size_t)P->S;
   const size_t sb = S * (6 * 8 + 8 * 4);
-  HIPCHK(hipMemcpyAsync(P->h_state, P->state_block, sb, hipMemcpyDeviceToHost, P->stream));
-  HIPCHK(hipMemcpyAsync((char*)P->h_state + sb, P->st.relres64, S * 8, hipMemcpyDeviceToHost, P->stream));
-  HIPCHK(hipStreamSynchronize(P->stream));
-  prof_flush(P);
+  // outputs with an error bound (rows of u): every output of a plan without
+  // stages, one per rhs of a slot plan
+  const int rows = slot ? nrhs : (P->stages.empty() ? P->nout * nrhs : 0);
+  // combine u_i = sum_{j in output i} w_j x_j (fixed order, FP64), then the
+  // squared norm of every output row
+  auto combine = [&]() -> int {
+    const bool pend = combine_finishes_x(P);
+    if (slot) {
+      ProfScope ps(P, BURA_K_COMBINE);
+      launch_combine(P->N, xsol, P->d_wsys, P->nterms, nrhs, R, u, P->stream, ps.ctr, nullptr, 0.0, true,
+                     pend ? P->w64.p : nullptr, pend ? P->w64.p2 : nullptr, P->st.alpha, P->st.iters);
+    }
+    for (int i = 0; i < P->nout && P->stages.empty() && !slot; ++i) {
+      ProfScope ps(P, BURA_K_COMBINE);
+      const int b = P->out_begin[i], e = P->out_end[i];
+      const size_t ob = (size_t)b * R;   // first system of output i
+      launch_combine(P->N, xsol + ob * P->N, P->d_w + b, e - b, nrhs, R, u + (size_t)i * nrhs * P->N, P->stream,
+                     ps.ctr, nullptr, 0.0, false, pend ? P->w64.p + ob * P->N : nullptr,
+                     pend ? P->w64.p2 + ob * P->N : nullptr, P->st.alpha + ob, P->st.iters + ob);
+    }
+    if (rows > 0) launch_row_norms(u, P->N, rows, P->d_upart, P->d_unorm, P->stream);
+    HIPCHK(hipGetLastError());
+    return BURA_OK;
+  };
+  // report: one copy of the per-system scalar state (and the output norms)
+  auto fetch = [&]() -> int {
+    HIPCHK(hipMemcpyAsync(P->h_state, P->state_block, sb, hipMemcpyDeviceToHost, P->stream));
+    HIPCHK(hipMemcpyAsync((char*)P->h_state + sb, P->st.relres64, S * 8, hipMemcpyDeviceToHost, P->stream));
+    if (rows > 0)
+      HIPCHK(hipMemcpyAsync((char*)P->h_state + sb + S * 8, P->d_unorm, (size_t)rows * 8, hipMemcpyDeviceToHost,
+                            P->stream));
+    HIPCHK(hipStreamSynchronize(P->stream));
+    prof_flush(P);
+    return BURA_OK;
+  };
   const double* hd = (const double*)P->h_state;
+  const double* rr = mixed ? (const double*)((const char*)P->h_state + sb) : hd + 4 * S;
+  const double* fn2 = mixed ? hd + 5 * S : hd;   // ||f_r||^2 of each system's rhs
+  const double* un2 = (const double*)((const char*)P->h_state + sb + S * 8);
+  // Certified a posteriori bound (Section 2.2, eq. (16); Lemma 2.5 for
+  // c_j > 0): system j stopped with residual r_j, so its error is
+  // (A - d_j)^-1 r_j, of norm at most |r_j| / (lambda_min + s_j) <=
+  // |r_j| / (lam_lb + s_j), and the output's distance to the exact
+  // sum_j c_j (A - d_j)^-1 f is at most sum_j |c_j| |r_j| / (lam_lb + s_j).
+  // Relative to |u|, the largest over the rows (and per row in *per).
+  auto term = [&](int row, int t, size_t* sys, double* w, double* sh) {
+    if (slot) {
+      const int K = P->nterms;
+      *sys = (size_t)t * R + row;
+      *w = slot->w[(size_t)row * K + t];
+      *sh = slot->s[(size_t)row * K + t];
+    } else {
+      const int a = row / nrhs, r = row % nrhs;
+      const int j = P->out_begin[a] + t;
+      *sys = (size_t)j * R + r;
+      *w = P->w_applied[j];
+      *sh = P->s[j];
+    }
+  };
+  auto nterms_of = [&](int row) {
+    return slot ? slot->nterms[row] : P->out_end[row / nrhs] - P->out_begin[row / nrhs];
+  };
+  auto bound = [&](std::vector<double>* per) {
+    double mx = 0.0;
+    if (per) per->assign(rows, 0.0);
+    for (int row = 0; row < rows; ++row) {
+      double acc = 0.0;
+      for (int t = 0; t < nterms_of(row); ++t) {
+        size_t sy;
+        double w, sh;
+        term(row, t, &sy, &w, &sh);
+        acc += std::fabs(w) * std::sqrt(fn2[sy]) * rr[sy] / (P->lam_lb + sh);
+      }
+      const double un = std::sqrt(un2[row]);
+      const double v = acc == 0.0 ? 0.0 : (un > 0.0 ? acc / un : HUGE_VAL);
+      if (per) (*per)[row] = v;
+      mx = std::max(mx, v);
+    }
+    return mx;
+  };
+  if ((rc = combine()) || (rc = fetch())) return rc;
+  double eb = rows > 0 ? bound(nullptr) : -1.0;
+  const double etol = P->opts.err_tol;
+  if (mixed && etol > 0.0 && rows > 0) {
+    // opts.err_tol: refine the terms of every row over the bound further.
+    // Their target residuals share the allowed error equally among the
+    // terms: |r_j| <= err_tol |u| (lam_lb + s_j) / (terms |c_j|), halved
+    // against the change of |u|.
+    std::vector<double> per, tolv(S);
+    for (int round = 0; round < 4 && eb > etol; ++round) {
+      bound(&per);
+      for (size_t i = 0; i < S; ++i) {
+        const int r = (int)(i % R);
+        tolv[i] = slot && slot->tol && r < nrhs ? slot->tol[r] : P->run_tol;
+        P->h_flags[i] = 0;
+      }
+      for (int row = 0; row < rows; ++row) {
+        if (!(per[row] > etol)) continue;
+        const int nt = nterms_of(row);
+        for (int t = 0; t < nt; ++t) {
+          size_t sy;
+          double w, sh;
+          term(row, t, &sy, &w, &sh);
+          const double fnr = std::sqrt(fn2[sy]);
+          if (w == 0.0 || !(fnr > 0.0)) continue;
+          const double target = 0.5 * etol * std::sqrt(un2[row]) * (P->lam_lb + sh) / (nt * std::fabs(w) * fnr);
+          tolv[sy] = std::min(tolv[sy], target);
+          if (rr[sy] > tolv[sy]) P->h_flags[sy] = 1;
+        }
+      }
+      HIPCHK(hipMemcpyAsync(P->d_tol_err, tolv.data(), S * 8, hipMemcpyHostToDevice, P->stream));
+      HIPCHK(hipStreamSynchronize(P->stream));
+      P->st.tol_outer = P->d_tol_err;
+      rc = resume_batch_mixed(P, f, R, 0, (int)S_used, P->h_flags);
+      P->st.tol_outer = P->slots ? P->d_tol : nullptr;
+      if (rc || (rc = combine()) || (rc = fetch())) return rc;
+      eb = bound(nullptr);
+    }
+  }
   const int* hi = (const int*)(hd + 6 * S);
   const int* it = hi + 2 * S;
   const int* flags = hi + 3 * S;
   const int* outer = hi + 5 * S;
-  const double* rr = mixed ? (const double*)((const char*)P->h_state + sb) : hd + 4 * S;
   int status = BURA_OK;
   bura_report_t R_{};
   R_.nterms = P->nterms;
@@ -1214,7 +1368,9 @@ int do_solve(bura_plan_t P, const double* f, double* u, int nrhs, bura_report_t*
       if (status == BURA_OK && !(rr[s] <= tol)) status = BURA_ENOCONV;
     }
   }
+  if (status == BURA_OK && mixed && etol > 0.0 && rows > 0 && !(eb <= etol)) status = BURA_ENOCONV;
   R_.status = status;
+  R_.err_bound = eb;
   R_.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (rep) *rep = R_;
   return status;
@@ -1230,6 +1386,8 @@ int validate_opts(const bura_opts_t* o) {
   // reversed), and the per-sweep weight sets hold up to three sweeps
   if (o->nu_pre != o->nu_post || o->nu_pre < 1 || o->nu_pre > 3) return BURA_EINVAL;
   if (o->check_every < 1) return BURA_EINVAL;
+  if (!(o->err_tol >= 0.0) || !std::isfinite(o->err_tol)) return BURA_EINVAL;
+  if (o->err_tol > 0.0 && o->precision != BURA_MIXED) return BURA_EUNSUPPORTED;
   return BURA_OK;
 }
 
@@ -1455,7 +1613,8 @@ int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_p
   bura_opts_t o;
   if (opts_in) o = *opts_in;
   else bura_opts_default(&o);
-  if (validate_opts(&o)) return BURA_EINVAL;
+  if (const int vr = validate_opts(&o)) return vr;
+  if (o.err_tol > 0.0 && !terms.stages.empty()) return BURA_EUNSUPPORTED;   // no bound for sequential forms
   if (ws && o.autotune) return BURA_EINVAL;   // tuning times solves with its own events
   if (g->coeff) {
     const long long m = (long long)(g->n + 2);
@@ -1517,6 +1676,7 @@ int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_p
   }
   P->nterms = nterms;
   P->w = terms.w;
+  P->w_applied = wdev;
   P->s = terms.s;
   P->nout = (int)terms.begin.size();
   for (int i = 0; i < P->nout; ++i) {
@@ -1597,7 +1757,15 @@ int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_p
   if ((rc = dev_zero(P, P->d_cnt, S * sizeof(unsigned int)))) return fail(rc);
   if ((rc = dev_alloc(P, (void**)&P->prof.d_ctr, BURA_K_COUNT * sizeof(unsigned long long)))) return fail(rc);
   if ((rc = dev_zero(P, P->prof.d_ctr, BURA_K_COUNT * sizeof(unsigned long long)))) return fail(rc);
-  const size_t state_mirror = S * (6 * 8 + 8 * 4) + S * 8;
+  // output norms for the error bound (rows = outputs x rhs)
+  {
+    const size_t rows = (size_t)P->nout * o.nrhs_max;
+    const size_t nb = (size_t)((P->N + 255) / 256);
+    if ((rc = dev_alloc(P, (void**)&P->d_upart, rows * nb * 8))) return fail(rc);
+    if ((rc = dev_alloc(P, (void**)&P->d_unorm, rows * 8))) return fail(rc);
+    if (mixed && (rc = dev_alloc(P, (void**)&P->d_tol_err, S * 8))) return fail(rc);
+  }
+  const size_t state_mirror = S * (6 * 8 + 8 * 4) + S * 8 + (size_t)P->nout * o.nrhs_max * 8;
   if (ws) {
     // host mirrors in ordinary memory (8-byte aligned: the state comes first)
     P->host_mirror.assign(state_mirror + S * sizeof(int) + 8, 0);
@@ -1765,6 +1933,7 @@ int bura_opts_default(bura_opts_t* o) {
   o->stream = nullptr;
   o->hbm_budget = 0;
   o->autotune = 0;
+  o->err_tol = 0.0;
   return BURA_OK;
 }
 

@@ -160,6 +160,9 @@ void launch_combine(long long N, const double* x, const double* w, int nterms, i
                     hipStream_t st, unsigned long long* ctr, const double* base = nullptr, double base_w = 0.0,
                     bool w_per_system = false, const double* pa = nullptr, const double* pb = nullptr,
                     const double* alpha = nullptr, const int* iters = nullptr);
+// out[r] = ||u_r||_2^2 for rows r < rows of [rows][N] (partial: rows x
+// ceil(N/256) doubles of scratch); fixed summation order per row
+void launch_row_norms(const double* u, long long N, int rows, double* partial, double* out, hipStream_t st);
 void launch_apply64(int dim, bool var, const LevelDev<double>& L, const double* x, double* y, double shift,
                     int nvec, hipStream_t st);
 void launch_scalars(int op, const double* partial, int nblk, int nsys, SysState st_, double tol,

@@ -1901,6 +1901,26 @@ __global__ __launch_bounds__(256) void k_combine(long long N, const double* x, c
   u[(long long)r * N + p] = acc;
 }
 
+// Squared l2 norm of each row of u ([rows][N], FP64): per-block partials, then
+// one block per row sums them in a fixed order (the result does not depend on
+// which other rows share the launch).
+__global__ __launch_bounds__(256) void k_row_norm2(const double* __restrict__ u, long long N,
+                                                   double* __restrict__ partial) {
+  const int r = blockIdx.y;
+  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  const double v = p < N ? u[(long long)r * N + p] : 0.0;
+  write_partial(partial, r, v * v, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_row_sum(const double* __restrict__ partial, int nblk,
+                                                 double* __restrict__ out) {
+  const int r = blockIdx.x;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) v += partial[(size_t)r * nblk + b];
+  const double tot = block_sum(v);
+  if (threadIdx.x == 0) out[r] = tot;
+}
+
 template <int DIM, bool VAR>
 __global__ __launch_bounds__(kBlock) void k_apply64(LevelDev<double> L, const double* __restrict__ x,
                                                     double* __restrict__ y, double s) {
@@ -2374,6 +2394,12 @@ void launch_combine(long long N, const double* x, const double* w, int nterms, i
   const dim3 g((unsigned)((N + 255) / 256), nrhs);
   hipLaunchKernelGGL(k_combine, g, dim3(256), 0, st, N, x, w, nterms, stride, u, base, base_w, ctr,
                      w_per_system ? 1 : 0, pa, pb, alpha, iters);
+}
+
+void launch_row_norms(const double* u, long long N, int rows, double* partial, double* out, hipStream_t st) {
+  const int nb = (int)((N + 255) / 256);
+  hipLaunchKernelGGL(k_row_norm2, dim3(nb, rows), dim3(256), 0, st, u, N, partial);
+  hipLaunchKernelGGL(k_row_sum, dim3(rows), dim3(256), 0, st, partial, nb, out);
 }
 
 void launch_apply64(int dim, bool var, const LevelDev<double>& L, const double* x, double* y, double shift, int nvec,

@@ -149,3 +149,18 @@ def test_sinc_kprime_inverts_the_system_count():
         B.sinc_kprime(1.0, 9)
     with pytest.raises(B.BuraError):
         B.sinc_kprime(0.5, 0.0)
+
+
+def test_err_tol_needs_mixed_precision_and_no_stages():
+    """The certified-bound enforcement refines FP64 iterates of the mixed
+    refinement loop, and sequential forms have no per-output bound."""
+    import paper_1612_04846_amd as B
+    with pytest.raises(B.BuraError) as ei:
+        B.bura_plan_create(2, 31, 0.5, 5, B.bura_opts_default(precision=B.BURA_FP64, err_tol=1e-8))
+    assert ei.value.code == B.BURA_EUNSUPPORTED
+    with pytest.raises(B.BuraError) as ei:
+        B.bura_plan_create_multistep(2, 31, [0.5, 0.25], [5, 5], B.bura_opts_default(err_tol=1e-8))
+    assert ei.value.code == B.BURA_EUNSUPPORTED
+    with pytest.raises(B.BuraError) as ei:
+        B.bura_plan_create(2, 31, 0.5, 5, B.bura_opts_default(err_tol=-1.0))
+    assert ei.value.code == B.BURA_EINVAL
