@@ -458,6 +458,13 @@ def run_serving(args):
         torch.cuda.synchronize()
         return time.perf_counter() - t0, codes
 
+    def per_step(b0, b1):
+        """Mean number of requests sharing a solve step between two stats
+        snapshots (an outer refinement step of a running solve in mixed
+        precision)."""
+        nb = b1["batches"] - b0["batches"]
+        return (b1["mean_batch"] * b1["batches"] - b0["mean_batch"] * b0["batches"]) / nb if nb else None
+
     print("[bench] serving warm-up (plans and coefficients)", file=sys.stderr, flush=True)
     cold, _ = stream(False)
     cold_st = B.bura_server_stats(server)
@@ -485,18 +492,18 @@ def run_serving(args):
         w_s, codes_s = stream(True, scale)
         b1 = B.bura_server_stats(server)
         codes_cap += codes_s
-        nb = b1["batches"] - b0["batches"]
         sweep.append({"load_factor": factor, "offered_solves_per_s": upole_cap / (span * scale) if scale else None,
                       "achieved_solves_per_s": (b1["unknown_pole_solves"] - b0["unknown_pole_solves"]) / w_s,
                       "p50_ms": 1e3 * b1["p50_latency_s"], "p99_ms": 1e3 * b1["p99_latency_s"],
-                      "requests_per_batch": (b1["completed"] - b0["completed"]) / nb if nb else None})
+                      "requests_per_step": per_step(b0, b1),
+                      "joined_running": b1["joined_running"] - b0["joined_running"]})
     B.bura_server_destroy(server)
     ok = [c == B.BURA_OK for c in codes + codes_cap]
     upole = st["unknown_pole_solves"] - base["unknown_pole_solves"]
     return dict(wall=wall, ok=ok, stats=st, base=base, upole=upole, reqs=reqs, F=F, U=U, failures=failures,
                 wall_cap=wall_cap, upole_cap=upole_cap, cold=cold, cold_p50=cold_st["p50_latency_s"],
                 cold_p99=cold_st["p99_latency_s"], sweep=sweep,
-                cap_batch=(st_cap["completed"] - base_cap["completed"]) / max(1, st_cap["batches"] - base_cap["batches"]))
+                cap_batch=per_step(base_cap, st_cap))
 
 
 def main():
@@ -581,7 +588,7 @@ def main():
                                    "per": "first pass, including plan creation (Remez, hierarchy, graphs)"},
                "offered_load_solves_per_s": res["upole"] / res["wall"],
                "capacity": {"seconds": res["wall_cap"], "unknown_pole_solves_per_s": res["upole_cap"] / res["wall_cap"],
-                            "requests_per_batch": res["cap_batch"], "per": "all requests queued at once"},
+                            "requests_per_step": res["cap_batch"], "per": "all requests queued at once"},
                "load_sweep": res["sweep"],
                "server": {k: v for k, v in st.items()}}
         accepted = all(res["ok"])

@@ -402,21 +402,24 @@ int bura_device_copy(void* dst_dev, const void* src_dev, size_t bytes, void* str
  *
  * Requests for the constant-coefficient grids are queued by bura_server_submit
  * (which computes the request's BURA terms, cached per (alpha, k), and fails
- * with that status if they cannot be computed) and served by a dispatcher
- * thread: one slot plan (bura_plan_create_slots, 17 terms per right-hand side)
- * is kept resident per (dim, n, precision); an idle plan takes the queued
- * requests for its grid, whatever their alpha, k and tol (up to max_group of
- * them, first come first served, batched as right-hand sides of one solve,
- * each with its own terms and tolerance); up to max_concurrent plans solve at
- * once on their own streams, so
- * requests that arrive while others run are admitted as soon as a plan and
- * memory are free.  New plans are admitted against hbm_budget bytes (0 =
- * unlimited), evicting idle plans least recently used first; a request whose
- * plan can never fit fails with BURA_ENOMEM.  A request's result does not
- * depend on which other requests share its batch.  f_dev / u_dev are FP64
- * device vectors of n^dim values; f_dev must be fully written (its stream
- * synchronised) before submit, and both must stay valid until the ticket
- * completes.  All server functions are thread-safe.
+ * with that status if they cannot be computed).  A dispatcher thread assigns
+ * each request to the resident slot plan (bura_plan_create_slots) of its key:
+ * grid, precision and a class of term counts (13 or 17 term slots per
+ * right-hand side, the smaller holding k+1), creating the plan if needed.
+ * Each plan has max_group right-hand-side slots and a worker thread.  With
+ * BURA_MIXED the worker admits queued requests into free slots of the solve
+ * that is running, at every outer refinement-step boundary, advances all
+ * admitted requests one outer step at a time, and returns each result as
+ * soon as that request's own systems have finished -- requests join and
+ * leave a running solve.  With BURA_FP64 each solve takes up to max_group
+ * queued requests of its key.  Up to max_concurrent plans have work at once,
+ * each on its own stream.  New plans are admitted against hbm_budget bytes
+ * (0 = unlimited), evicting idle plans least recently used first; a request
+ * whose plan can never fit fails with BURA_ENOMEM.  A request's result does
+ * not depend on which other requests share its plan or when they arrive.
+ * f_dev / u_dev are FP64 device vectors of n^dim values; f_dev must be fully
+ * written (its stream synchronised) before submit, and both must stay valid
+ * until the ticket completes.  All server functions are thread-safe.
  * ------------------------------------------------------------------------- */
 typedef struct bura_server_s* bura_server_t;
 
@@ -432,8 +435,10 @@ typedef struct {
   long long submitted, completed, failed, batches, plans_created, plans_evicted;
   double unknown_pole_solves;   /* sum over successful requests of n^dim (k+1)   */
   double p50_latency_s, p99_latency_s;   /* submit -> result, completed requests */
-  double mean_batch;            /* requests per solve                            */
+  double mean_batch;            /* requests per solve step (mixed precision: per outer
+                                   refinement step of a running solve; FP64: per solve) */
   size_t resident_bytes;        /* device bytes of resident plans                */
+  long long joined_running;     /* requests admitted into a solve already running     */
 } bura_server_stats_t;
 
 int bura_server_create(size_t hbm_budget, int max_concurrent, int max_group, bura_server_t* out);

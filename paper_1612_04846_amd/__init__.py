@@ -116,6 +116,7 @@ class bura_server_stats_t(ctypes.Structure):
         ("p99_latency_s", ctypes.c_double),
         ("mean_batch", ctypes.c_double),
         ("resident_bytes", ctypes.c_size_t),
+        ("joined_running", ctypes.c_longlong),
     ]
 
 

@@ -187,6 +187,12 @@ struct bura_plan_s {
   double* d_upart = nullptr;   // rows x ceil(N/256) partial sums
   double* d_unorm = nullptr;   // rows = nout x nrhs_max
   double* d_tol_err = nullptr; // MIXED: per-system refinement tolerances set by opts.err_tol
+  // continuous batching (bura::serve_*): the slots' right-hand sides, the
+  // systems being initialised, and the host copy of each slot's terms
+  double* d_fserve = nullptr;  // [nrhs_max][N]
+  int* d_init = nullptr;       // [S]
+  std::vector<int> serve_nterms;
+  std::vector<double> serve_w, serve_s, serve_tol;
   // asynchronous solves: a FIFO of submitted solves run in order by one
   // worker thread; exec_mu serialises them with synchronous solves
   struct Job {
@@ -1788,6 +1794,159 @@ int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_p
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// Continuous batching on a slot plan (see bura_internal.h)
+// ---------------------------------------------------------------------------
+namespace bura {
+
+int serve_reset(bura_plan_t P) {
+  if (!P || !P->slots || P->opts.precision != BURA_MIXED) return BURA_EUNSUPPORTED;
+  const int R = P->opts.nrhs_max, K = P->nterms;
+  const size_t S = (size_t)P->S;
+  int rc;
+  HIPCHK(hipSetDevice(P->device));
+  if (!P->d_fserve && (rc = dev_alloc(P, (void**)&P->d_fserve, (size_t)R * P->N * 8))) return rc;
+  if (!P->d_init && (rc = dev_alloc(P, (void**)&P->d_init, S * sizeof(int)))) return rc;
+  hipStream_t st = P->stream;
+  launch_zero(P->d_init, S * sizeof(int), st);
+  launch_zero(P->d_wsys, S * 8, st);
+  for (int* f : {P->st.active, P->st.active64, P->st.flags, P->st.total_iters, P->st.outer})
+    launch_fill_int(f, (long long)S, 0, st);
+  P->run_tol = P->opts.tol;
+  P->st.tol_outer = P->d_tol;
+  P->serve_nterms.assign(R, 0);
+  P->serve_w.assign((size_t)R * K, 0.0);
+  P->serve_s.assign((size_t)R * K, 0.0);
+  P->serve_tol.assign(R, P->opts.tol);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  return BURA_OK;
+}
+
+int serve_admit(bura_plan_t P, int slot, const double* f_dev, int nterms, const double* w, const double* s,
+                double tol) {
+  if (!P || !P->d_fserve || !f_dev || !w || !s) return BURA_EINVAL;
+  const int R = P->opts.nrhs_max, K = P->nterms;
+  if (slot < 0 || slot >= R || nterms < 1 || nterms > K || !(tol > 0.0) || P->serve_nterms[slot] != 0)
+    return BURA_EINVAL;
+  for (int j = 0; j < nterms; ++j)
+    if (!std::isfinite(w[j]) || !(s[j] >= 0.0) || !std::isfinite(s[j])) return BURA_EINVAL;
+  HIPCHK(hipSetDevice(P->device));
+  hipStream_t st = P->stream;
+  const size_t S = (size_t)P->S;
+  HIPCHK(hipMemcpyAsync(P->d_fserve + (size_t)slot * P->N, f_dev, (size_t)P->N * 8, hipMemcpyDeviceToDevice, st));
+  SlotTermsDev v{};
+  v.slot = slot;
+  v.R = R;
+  v.K = K;
+  v.nterms = nterms;
+  v.tol = tol;
+  for (int j = 0; j < nterms; ++j) {
+    v.w[j] = w[j];
+    v.s[j] = s[j];
+  }
+  launch_slot_terms(v, P->d_wsys, P->d_shift64, P->w32.shift, P->d_tol, P->d_init, P->st.total_iters, P->st.outer,
+                    P->st.flags, P->st.active, P->st.active64, st);
+  // first FP64 residual (x = 0) and outer test of the new systems only: they
+  // are flagged in d_init, which stands in for active64 until merged
+  SysState Si = P->st;
+  Si.active64 = P->d_init;
+  const LevelDev<double> L0 = level_view<double>(P, 0);
+  launch_residual64(P->dim, P->var, L0, P->d_fserve, P->x64, P->w32.x, P->w32.r, P->d_shift64, P->d_init,
+                    P->partial, R, (int)S, true, st, nullptr);
+  launch_scalars(OP_OUTER, P->partial, flat_blocks(P->N), (int)S, Si, P->run_tol, P->opts.max_outer, st);
+  launch_merge_init(P->d_init, P->st.active64, (int)S, st);
+  HIPCHK(hipGetLastError());
+  P->serve_nterms[slot] = nterms;
+  for (int j = 0; j < K; ++j) {
+    P->serve_w[(size_t)slot * K + j] = j < nterms ? w[j] : 0.0;
+    P->serve_s[(size_t)slot * K + j] = j < nterms ? s[j] : 0.0;
+  }
+  P->serve_tol[slot] = tol;
+  return BURA_OK;
+}
+
+int serve_step(bura_plan_t P) {
+  if (!P || !P->d_fserve) return BURA_EINVAL;
+  HIPCHK(hipSetDevice(P->device));
+  const int S = P->S;
+  int a = count_active(P, P->st.active64, 0, S);
+  if (a < 0) return BURA_EDEVICE;
+  if (a == 0) return 0;
+  hipStream_t st = P->stream;
+  const bool fx = P->foldxr;
+  const SysState Ss = state_at(P, 0);
+  const LevelDev<double> L0 = level_view<double>(P, 0);
+  Work<float>& W = P->w32;
+  int rc;
+  if ((rc = run_pcg<float>(P, W, 0, S, P->opts.inner_tol, P->opts.max_iter, fx))) return rc;
+  {
+    ProfScope ps(P, BURA_K_OTHER);
+    launch_x_from_e(L0, P->dim, W.x, P->x64, Ss.active64, S, st, fx ? W.p : nullptr, fx ? W.p2 : nullptr, Ss.alpha,
+                    Ss.iters);
+  }
+  {
+    ProfScope ps(P, BURA_K_RESIDUAL64);
+    launch_residual64(P->dim, P->var, L0, P->d_fserve, P->x64, W.x, W.r, P->d_shift64, Ss.active64, P->partial,
+                      P->opts.nrhs_max, S, false, st, ps.ctr);
+  }
+  {
+    ProfScope ps(P, BURA_K_OTHER);
+    launch_scalars(OP_OUTER, P->partial, stencil_blocks(P->dim, P->n), S, Ss, P->run_tol, P->opts.max_outer, st);
+  }
+  a = count_active(P, P->st.active64, 0, S);
+  return a < 0 ? BURA_EDEVICE : a;
+}
+
+int serve_slot_done(bura_plan_t P, int slot, double* u_dev, bura_report_t* rep) {
+  if (!P || !P->d_fserve || !u_dev) return BURA_EINVAL;
+  const int R = P->opts.nrhs_max, K = P->nterms;
+  if (slot < 0 || slot >= R) return BURA_EINVAL;
+  const int nt = P->serve_nterms[slot];
+  if (nt == 0) return BURA_EINVAL;
+  for (int j = 0; j < nt; ++j)
+    if (P->h_flags[(size_t)j * R + slot]) return 0;
+  HIPCHK(hipSetDevice(P->device));
+  hipStream_t st = P->stream;
+  const size_t S = (size_t)P->S;
+  {
+    ProfScope ps(P, BURA_K_COMBINE);
+    launch_combine(P->N, P->x64 + (size_t)slot * P->N, P->d_wsys + slot, K, 1, R, u_dev, st, ps.ctr, nullptr, 0.0,
+                   true);
+  }
+  launch_row_norms(u_dev, P->N, 1, P->d_upart, P->d_unorm, st);
+  const size_t sb = S * (6 * 8 + 8 * 4);
+  HIPCHK(hipMemcpyAsync(P->h_state, P->state_block, sb, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync((char*)P->h_state + sb, P->st.relres64, S * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync((char*)P->h_state + sb + S * 8, P->d_unorm, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const double* hd = (const double*)P->h_state;
+  const int* hi = (const int*)(hd + 6 * S);
+  const double* rr = (const double*)((const char*)P->h_state + sb);
+  const double un = std::sqrt(*(const double*)((const char*)P->h_state + sb + S * 8));
+  bura_report_t R_{};
+  R_.nterms = nt;
+  int status = BURA_OK;
+  double acc = 0.0;
+  for (int j = 0; j < nt; ++j) {
+    const size_t sy = (size_t)j * R + slot;
+    R_.iters[j] = hi[2 * S + sy];
+    R_.outer[j] = hi[5 * S + sy];
+    R_.relres[j] = rr[sy];
+    if (hi[3 * S + sy] & 1) status = BURA_ENAN;
+    if (status == BURA_OK && !(rr[sy] <= P->serve_tol[slot])) status = BURA_ENOCONV;
+    acc += std::fabs(P->serve_w[(size_t)slot * K + j]) * std::sqrt(hd[5 * S + sy]) * rr[sy] /
+           (P->lam_lb + P->serve_s[(size_t)slot * K + j]);
+  }
+  R_.status = status;
+  R_.err_bound = acc == 0.0 ? 0.0 : (un > 0.0 ? acc / un : HUGE_VAL);
+  P->serve_nterms[slot] = 0;
+  if (rep) *rep = R_;
+  return 1;
+}
+
+}  // namespace bura
 
 // ---------------------------------------------------------------------------
 // Static device workspace of bura_solve_static: one copy per GPU, held until

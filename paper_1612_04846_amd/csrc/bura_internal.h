@@ -168,6 +168,15 @@ void launch_apply64(int dim, bool var, const LevelDev<double>& L, const double* 
 void launch_scalars(int op, const double* partial, int nblk, int nsys, SysState st_, double tol,
                     int max_iter, hipStream_t st);
 void launch_zero(void* p, size_t bytes, hipStream_t st);
+// the terms of one rhs slot of a slot plan, passed by value to a kernel
+struct SlotTermsDev {
+  int slot, R, K, nterms;
+  double tol;
+  double w[BURA_MAX_TERMS], s[BURA_MAX_TERMS];
+};
+void launch_slot_terms(const SlotTermsDev& v, double* w, double* s64, float* s32, double* tol, int* init,
+                       int* total_iters, int* outer, int* flags, int* active, int* active64, hipStream_t st);
+void launch_merge_init(int* init, int* active64, int n, hipStream_t st);
 // dst = src, 16-byte aligned, non-overlapping (counter calibration)
 void launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
 void launch_fill_int(int* p, long long n, int v, hipStream_t st);
@@ -184,5 +193,24 @@ constexpr long long kFillBlocks = 4 * 256;
 int default_down_tile(int dim, int n, long long nsys);
 int spmv_blocks(int dim, int n, int tv);
 int max_partial_blocks(int dim, int n, long long N);   // over every launch shape
+
+// Continuous batching on a slot plan (BURA_MIXED): right-hand sides join and
+// leave a running solve at outer refinement-step boundaries, where every
+// system of the plan is at the start of an inner solve, so each one goes
+// through the same operations as in a solve of its own.  One host thread
+// drives a plan at a time.
+//   serve_reset: no slot in use.
+//   serve_admit: stage f into the plan's rhs slot, set its terms and
+//     tolerance, form its first FP64 residual (x = 0) and outer test.
+//   serve_step: one outer step of every active system (FP32 inner solve,
+//     x += e, FP64 residual, outer test); returns the systems still active
+//     (or a negative status).
+//   serve_slot_done: whether the slot's systems are all finished; if so its
+//     combine is written to u_dev, its report filled and 1 returned.
+int serve_reset(bura_plan_t P);
+int serve_admit(bura_plan_t P, int slot, const double* f_dev, int nterms, const double* w, const double* s,
+                double tol);
+int serve_step(bura_plan_t P);
+int serve_slot_done(bura_plan_t P, int slot, double* u_dev, bura_report_t* rep);
 
 }  // namespace bura

@@ -2415,6 +2415,49 @@ void launch_scalars(int op, const double* partial, int nblk, int nsys, SysState 
   hipLaunchKernelGGL(k_scalars, dim3(nsys), dim3(256), 0, st, op, partial, nblk, S, tol, max_iter);
 }
 
+// Terms of one right-hand-side slot of a slot plan (systems j R + slot,
+// j < K): weights, shifts (FP64 and FP32), tolerances; resets the systems'
+// counters and marks the used ones (j < nterms) in init.
+__global__ void k_slot_terms(SlotTermsDev v, double* __restrict__ w, double* __restrict__ s64,
+                             float* __restrict__ s32, double* __restrict__ tol, int* __restrict__ init,
+                             int* __restrict__ total_iters, int* __restrict__ outer, int* __restrict__ flags,
+                             int* __restrict__ active, int* __restrict__ active64) {
+  const int j = threadIdx.x;
+  if (j >= v.K) return;
+  const long long sys = (long long)j * v.R + v.slot;
+  const bool used = j < v.nterms;
+  w[sys] = used ? v.w[j] : 0.0;
+  s64[sys] = used ? v.s[j] : 0.0;
+  if (s32) s32[sys] = used ? (float)v.s[j] : 0.0f;
+  tol[sys] = v.tol;
+  init[sys] = used ? 1 : 0;
+  total_iters[sys] = 0;
+  outer[sys] = 0;
+  flags[sys] = 0;
+  active[sys] = 0;
+  active64[sys] = 0;
+}
+
+// active64 of the systems just initialised (their outer test ran on init)
+__global__ void k_merge_init(int* __restrict__ init, int* __restrict__ active64, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (init[i]) {
+    active64[i] = init[i];
+    init[i] = 0;
+  }
+}
+
+void launch_slot_terms(const SlotTermsDev& v, double* w, double* s64, float* s32, double* tol, int* init,
+                       int* total_iters, int* outer, int* flags, int* active, int* active64, hipStream_t st) {
+  hipLaunchKernelGGL(k_slot_terms, dim3(1), dim3(64), 0, st, v, w, s64, s32, tol, init, total_iters, outer, flags,
+                     active, active64);
+}
+
+void launch_merge_init(int* init, int* active64, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_merge_init, dim3((n + 255) / 256), dim3(256), 0, st, init, active64, n);
+}
+
 __global__ void k_fill_int(int* __restrict__ p, long long n, int v) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;

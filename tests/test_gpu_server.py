@@ -53,8 +53,8 @@ def test_server_alone_equals_mix_and_matches_oracle():
     st = B.bura_server_stats(s_mix)
     B.bura_server_destroy(s_mix)
     assert st["completed"] == len(REQS) and st["failed"] == 0
-    assert st["batches"] < len(REQS)          # same-grid requests were batched
-    assert st["plans_created"] == 4           # one plan per (dim, n, precision)
+    assert st["mean_batch"] > 1.0             # same-key requests shared solve steps
+    assert st["plans_created"] == 4           # one plan per (dim, n, precision, term class)
     for a, m in zip(alone, mix):
         assert np.array_equal(a, m)
     for (d, n, al, k, t, tol), f, u in zip(REQS, fs, mix):
@@ -65,12 +65,12 @@ def test_server_alone_equals_mix_and_matches_oracle():
 
 def test_server_budget_evicts_idle_plans():
     B = _B()
-    # room for the 127^2 plan (17 term slots x 2 rhs, plus 2 x 2 staging vectors)
-    # and 1 MiB more: the 63^2 plan (several MiB) cannot be resident beside it
-    h = B.bura_plan_create_slots(2, 127, 17, B.bura_opts_default(precision=B.BURA_MIXED, nrhs_max=2))
+    # room for the 127^2 plan (13 term slots x 2 rhs) and 1 MiB more: the 63^2
+    # plan (several MiB) cannot be resident beside it
+    h = B.bura_plan_create_slots(2, 127, 13, B.bura_opts_default(precision=B.BURA_MIXED, nrhs_max=2))
     plan_bytes = B.bura_plan_info(h)[2]
     B.bura_plan_destroy(h)
-    budget = plan_bytes + 2 * 2 * 127 * 127 * 8 + (1 << 20)
+    budget = plan_bytes + (1 << 20)
     server = B.bura_server_create(budget, 2, 2)
     reqs = [(2, 127, 0.5, 5, 111, 1e-10), (2, 63, 0.25, 5, 112, 1e-10), (2, 127, 0.5, 5, 113, 1e-10)]
     _solve_all(B, server, reqs, sequential=True)
@@ -94,3 +94,49 @@ def test_server_rejects_request_that_cannot_fit():
     code, _ = B.bura_server_wait(server, tk)
     B.bura_server_destroy(server)
     assert code == B.BURA_ENOMEM
+
+
+def test_request_joins_a_running_solve_bitwise():
+    """Continuous batching: B arrives while A's solve is running on the same
+    plan (1023^2, 13 term slots) and is admitted into it at an outer-step
+    boundary; B's result is bit-identical to B solved alone, and A's to A alone."""
+    import time
+    from oracle import spectral
+    B = _B()
+    n = 1023
+    fa = torch.from_numpy(synth.normal_rhs(n, 2, nrhs=1, tag=121)[0]).cuda()
+    fb = torch.from_numpy(synth.normal_rhs(n, 2, nrhs=1, tag=122)[0]).cuda()
+    torch.cuda.synchronize()
+
+    def alone(f, alpha, k, tol):
+        srv = B.bura_server_create(0, 1, 4)
+        u = torch.empty_like(f)
+        code, _ = B.bura_server_wait(srv, B.bura_server_submit(srv, 2, n, alpha, k, f, u, tol=tol))
+        B.bura_server_destroy(srv)
+        assert code == B.BURA_OK
+        torch.cuda.synchronize()
+        return u.cpu().numpy()
+
+    ua_alone = alone(fa, 0.5, 12, 1e-13)
+    ub_alone = alone(fb, 0.3, 9, 1e-11)
+    srv = B.bura_server_create(0, 2, 4)
+    ua, ub = torch.empty_like(fa), torch.empty_like(fb)
+    ta = B.bura_server_submit(srv, 2, n, 0.5, 12, fa, ua, tol=1e-13)
+    t0 = time.time()
+    while B.bura_server_stats(srv)["batches"] < 1:   # A's first outer step has started
+        assert time.time() - t0 < 60
+        time.sleep(0.0005)
+    tb = B.bura_server_submit(srv, 2, n, 0.3, 9, fb, ub, tol=1e-11)
+    ca, _ = B.bura_server_wait(srv, ta)
+    cb, _ = B.bura_server_wait(srv, tb)
+    st = B.bura_server_stats(srv)
+    B.bura_server_destroy(srv)
+    torch.cuda.synchronize()
+    print(f"joined {st['joined_running']}, requests per step {st['mean_batch']:.2f}, plans {st['plans_created']}")
+    assert ca == B.BURA_OK and cb == B.BURA_OK
+    assert st["joined_running"] >= 1 and st["plans_created"] == 1
+    assert np.array_equal(ua.cpu().numpy(), ua_alone)
+    assert np.array_equal(ub.cpu().numpy(), ub_alone)
+    b = oracle_coeffs(0.3, 9)
+    ref = spectral.bura_spectral(fb.cpu().numpy()[None], 2, b.c_f64, b.d_f64)[0]
+    assert np.linalg.norm(ub_alone - ref) / np.linalg.norm(ref) <= 1e-9
