@@ -192,6 +192,7 @@ int down_blocks(int dim, int n, int tv);
 constexpr long long kFillBlocks = 4 * 256;
 int default_down_tile(int dim, int n, long long nsys);
 int spmv_blocks(int dim, int n, int tv);
+int residual_blocks(int dim, int n);   // blocks per system of the FP64 residual (refinement step)
 int max_partial_blocks(int dim, int n, long long N);   // over every launch shape
 
 // Continuous batching on a slot plan (BURA_MIXED): right-hand sides join and

@@ -1026,8 +1026,8 @@ struct RegionFaces {
       const int q = min(tid + 256 * u, RN - 1);
       const int ry = q / RX, rx = q - ry * RX;
       const int ci = min(max(gx0 + rx, 0), n - 1), cj = min(max(gy0 + ry, 0), n - 1);
-      const long long fx = (long long)cj * (n + 1) + ci;
-      const long long fy = (long long)cj * n + ci;
+      const int fx = cj * (n + 1) + ci;   // 2D faces: fewer than 2^31
+      const int fy = cj * n + ci;
       wl[u] = L.wf0[fx];
       wr[u] = L.wf0[fx + 1];
       wd[u] = L.wf1[fy];
@@ -1711,30 +1711,73 @@ __global__ __launch_bounds__(256) void k_copy_rhs(long long N, const double* __r
 // --------------------------------------------------------------------------
 // FP64 refinement residual: r32 = f - (A + s) x64, e = 0, partial = ||r||^2
 // --------------------------------------------------------------------------
-template <int DIM, bool VAR>
-__global__ __launch_bounds__(kBlock) void k_residual64(LevelDev<double> L, const double* __restrict__ f,
-                                                       const double* __restrict__ x64, float* __restrict__ e,
-                                                       float* __restrict__ r32, const double* __restrict__ shift,
-                                                       const int* __restrict__ active64, int nrhs,
-                                                       double* __restrict__ partial, unsigned long long* __restrict__ ctr) {
+// k_residual64 in 2D with the stencil product's layout: R rows per thread over
+// TX columns, the column's values of the rows above and below from the
+// thread's own registers, every load issued before the arithmetic (a
+// one-point-per-thread launch reads each x value from the caches five times)
+constexpr int kRes2Rows = 4, kRes2Cols = 128;
+template <bool VAR>
+__global__ __launch_bounds__(kBlock) void k_residual64_2(LevelDev<double> L, const double* __restrict__ f,
+                                                         const double* __restrict__ x64, float* __restrict__ e,
+                                                         float* __restrict__ r32, const double* __restrict__ shift,
+                                                         const int* __restrict__ active64, int nrhs,
+                                                         double* __restrict__ partial,
+                                                         unsigned long long* __restrict__ ctr) {
+  constexpr int R = kRes2Rows, TX = kRes2Cols;
   const Tile tl = block_tile();
   const int sys = tl.z;
   if (!active64[sys]) return;
-  // x64, f read (FP64); r32, e written (FP32)
-  count_bytes_tile(tl, ctr, (unsigned long long)L.N * (8 + 8 + 4 + 4 + (VAR && sys == 0 ? 8 * DIM : 0)));
-  int i, j, k;
-  tile_ijk<DIM>(tl, L.n, i, j, k);
-  const bool ok = i < L.n && j < L.n;
-  const long long off = (long long)sys * L.N;
-  const long long p = ((long long)k * L.n + j) * L.n + i;
-  const int rhs = sys % nrhs;
+  count_bytes_tile(tl, ctr, (unsigned long long)L.N * (8 + 8 + 4 + 4 + (VAR && sys == 0 ? 16 : 0)));
+  const int n = L.n;
+  const int i = tl.x * TX + threadIdx.x;
+  const int j0 = (tl.y * (kBlock / TX) + threadIdx.y) * R;
   double rr = 0.0;
-  if (ok) {
-    const double ax = apply_pt<double, DIM, VAR>(L, x64 + off, i, j, k, p, shift[sys], nullptr);
-    const double rv = f[(long long)rhs * L.N + p] - ax;
-    r32[off + p] = (float)rv;
-    e[off + p] = 0.0f;
-    rr = rv * rv;
+  if (i < n && j0 < n) {
+    const long long off = (long long)sys * L.N;
+    const double* __restrict__ xs = x64 + off;
+    const double* __restrict__ fs = f + (long long)(sys % nrhs) * L.N;
+    const double s = shift[sys];
+    const int il = i > 0 ? i - 1 : i, ir = i < n - 1 ? i + 1 : i;
+    double xc[R + 2], xl[R], xr[R], fv[R];
+    double wl[VAR ? R : 1], wr[VAR ? R : 1], wd[VAR ? R : 1], wu[VAR ? R : 1];
+#pragma unroll
+    for (int r = 0; r < R + 2; ++r) xc[r] = xs[min(max(j0 - 1 + r, 0), n - 1) * n + i];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int row = min(j0 + r, n - 1) * n;
+      xl[r] = xs[row + il];
+      xr[r] = xs[row + ir];
+      fv[r] = fs[row + i];
+      if (VAR) {
+        const int jr = min(j0 + r, n - 1);
+        const int fx = jr * (n + 1) + i, fy = jr * n + i;
+        wl[VAR ? r : 0] = L.wf0[fx];
+        wr[VAR ? r : 0] = L.wf0[fx + 1];
+        wd[VAR ? r : 0] = L.wf1[fy];
+        wu[VAR ? r : 0] = L.wf1[fy + n];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int j = j0 + r;
+      if (j < n) {
+        const double c = xc[r + 1];
+        const double dn = j > 0 ? xc[r] : 0.0, up = j < n - 1 ? xc[r + 2] : 0.0;
+        const double lv = i > 0 ? xl[r] : 0.0, rv = i < n - 1 ? xr[r] : 0.0;
+        double ax;
+        if (!VAR) {
+          ax = L.wc * ((c - lv) + (c - rv) + (c - dn) + (c - up)) + s * c;
+        } else {
+          ax = wl[VAR ? r : 0] * (c - lv) + wr[VAR ? r : 0] * (c - rv) + wd[VAR ? r : 0] * (c - dn) +
+               wu[VAR ? r : 0] * (c - up) + s * c;
+        }
+        const double rv64 = fv[r] - ax;
+        const long long g = off + (long long)j * n + i;
+        r32[g] = (float)rv64;
+        e[g] = 0.0f;
+        rr += rv64 * rv64;
+      }
+    }
   }
   write_partial_tile(tl, partial, sys, rr);
 }
@@ -2349,7 +2392,7 @@ int up_blocks(int dim, int n, int tv) {
 
 // the most blocks per system any reduction-writing launch shape can have
 int max_partial_blocks(int dim, int n, long long N) {
-  int m = std::max(stencil_blocks(dim, n), flat_blocks(N));
+  int m = std::max({stencil_blocks(dim, n), flat_blocks(N), residual_blocks(dim, n)});
   for (int v = 0; v < kTileVariants; ++v)
     m = std::max({m, up_blocks(dim, n, v), down_blocks(dim, n, v), spmv_blocks(dim, n, v)});
   return m;
@@ -2366,19 +2409,29 @@ void launch_residual64(int dim, bool var, const LevelDev<double>& L, const doubl
                        r32, nrhs, active64, partial);
     return;
   }
-  const dim3 g = stencil_grid(dim, L.n, nsys), blk = stencil_block(dim, L.n);
   if (dim == 3) {
+    const dim3 g = stencil_grid(dim, L.n, nsys), blk = stencil_block(dim, L.n);
     if (var)
       hipLaunchKernelGGL((k_residual64_3<true>), g, blk, 0, st, L, f, x64, e, r32, shift, active64, nrhs, partial, ctr);
     else
       hipLaunchKernelGGL((k_residual64_3<false>), g, blk, 0, st, L, f, x64, e, r32, shift, active64, nrhs, partial,
                          ctr);
-  } else if (var) {
-    hipLaunchKernelGGL((k_residual64<2, true>), g, blk, 0, st, L, f, x64, e, r32, shift, active64, nrhs, partial, ctr);
   } else {
-    hipLaunchKernelGGL((k_residual64<2, false>), g, blk, 0, st, L, f, x64, e, r32, shift, active64, nrhs, partial,
-                       ctr);
+    constexpr int rows_per_block = (kBlock / kRes2Cols) * kRes2Rows;
+    const dim3 g2((L.n + kRes2Cols - 1) / kRes2Cols, (L.n + rows_per_block - 1) / rows_per_block, nsys);
+    const dim3 b2(kRes2Cols, kBlock / kRes2Cols);
+    if (var)
+      hipLaunchKernelGGL((k_residual64_2<true>), g2, b2, 0, st, L, f, x64, e, r32, shift, active64, nrhs, partial, ctr);
+    else
+      hipLaunchKernelGGL((k_residual64_2<false>), g2, b2, 0, st, L, f, x64, e, r32, shift, active64, nrhs, partial,
+                         ctr);
   }
+}
+
+int residual_blocks(int dim, int n) {
+  if (dim == 3) return stencil_blocks(dim, n);
+  constexpr int rows_per_block = (kBlock / kRes2Cols) * kRes2Rows;
+  return ((n + kRes2Cols - 1) / kRes2Cols) * ((n + rows_per_block - 1) / rows_per_block);
 }
 
 void launch_x_from_e(const LevelDev<double>& L, int dim, const float* e, double* x64, const int* active64, int nsys,
