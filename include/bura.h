@@ -133,7 +133,27 @@ typedef struct {
                           bound of the report (err_bound) to be <= err_tol; the refinement
                           continues on the systems of every output over it (at most four
                           more rounds, else BURA_ENOCONV)                                */
+  int variant;         /* 0: the default code path.  Else a bitwise OR of enum bura_variant:
+                          alternative implementations of the same steps, which give the same
+                          result to rounding (bitwise for the scalar and graph variants) and
+                          are kept to cross-check the default path and to measure it against
+                          them; any other bit: BURA_EINVAL                               */
 } bura_opts_t;
+
+/* Alternative code paths (bura_opts_t.variant). */
+enum bura_variant {
+  BURA_VARIANT_UNFUSED = 1,      /* 2D multigrid: one kernel per V-cycle step (sweep, residual
+                                    and restriction, prolongation) instead of the two fused
+                                    LDS-tiled level kernels                                 */
+  BURA_VARIANT_NO_FOLDXR = 2,    /* PCG vector updates x += alpha p, r -= alpha q in a pass of
+                                    their own instead of inside the stencil product and the
+                                    first fine pre-smoothing kernel                          */
+  BURA_VARIANT_FOLD_SCALARS = 4, /* the per-system scalar updates by the last block of the
+                                    producing kernel (device-scope fence) instead of a small
+                                    kernel of their own                                      */
+  BURA_VARIANT_NO_GRAPH = 8      /* launch every PCG iteration eagerly instead of replaying a
+                                    captured graph per chunk of iterations                   */
+};
 
 /* Per-solve report (host struct filled by solve/poll). */
 #define BURA_MAX_TERMS 64
@@ -160,7 +180,7 @@ typedef struct {
 
 /* Fill *o with defaults: tol 1e-12, inner_tol 1e-5, BURA_MIXED, BURA_BATCHED,
  * max_iter 0 (automatic), max_outer 12, nrhs_max 1, check_every 4, V(2,2),
- * stream NULL, err_tol 0. */
+ * stream NULL, err_tol 0, variant 0. */
 int bura_opts_default(bura_opts_t* o);
 
 /* Step 1-2 of Section 2.2 on the host: the (k,k) best uniform rational

@@ -47,6 +47,11 @@ BURA_BATCHED = 0
 BURA_PER_POLE = 1
 BURA_MAX_TERMS = 64
 BURA_TILE_VARIANTS = 3
+# bura_opts_t.variant bits: alternative code paths of the same steps
+BURA_VARIANT_UNFUSED = 1
+BURA_VARIANT_NO_FOLDXR = 2
+BURA_VARIANT_FOLD_SCALARS = 4
+BURA_VARIANT_NO_GRAPH = 8
 
 
 class bura_grid_t(ctypes.Structure):
@@ -76,6 +81,7 @@ class bura_opts_t(ctypes.Structure):
         ("hbm_budget", ctypes.c_size_t),
         ("autotune", ctypes.c_int),
         ("err_tol", ctypes.c_double),
+        ("variant", ctypes.c_int),
     ]
 
 

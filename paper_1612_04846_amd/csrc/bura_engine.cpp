@@ -111,11 +111,11 @@ struct bura_plan_s {
   // hierarchy
   std::vector<HostLevel> lev;
   int lc = -1;                 // first level solved in LDS; -1: no multigrid (Jacobi PCG)
-  bool unfused = false;        // force the one-kernel-per-step V-cycle (BURA_UNFUSED=1)
+  bool unfused = false;        // the one-kernel-per-step V-cycle (BURA_VARIANT_UNFUSED)
   // PCG vector updates folded into other passes: x += alpha p deferred to the
   // next stencil-product pass, r -= alpha q done by the first fine-level
   // pre-smoothing kernel (the fused down kernel in 2D, k_jacobi0_rup
-  // otherwise) into a second residual buffer (off with BURA_NO_FOLDXR=1)
+  // otherwise) into a second residual buffer (off with BURA_VARIANT_NO_FOLDXR)
   bool foldxr = false;
   size_t lds_bytes = 0;
   // launch-shape variant of the 2D stencil product and, per global level, of
@@ -1394,6 +1394,8 @@ int validate_opts(const bura_opts_t* o) {
   if (o->check_every < 1) return BURA_EINVAL;
   if (!(o->err_tol >= 0.0) || !std::isfinite(o->err_tol)) return BURA_EINVAL;
   if (o->err_tol > 0.0 && o->precision != BURA_MIXED) return BURA_EUNSUPPORTED;
+  const int known = BURA_VARIANT_UNFUSED | BURA_VARIANT_NO_FOLDXR | BURA_VARIANT_FOLD_SCALARS | BURA_VARIANT_NO_GRAPH;
+  if (o->variant & ~known) return BURA_EINVAL;
   return BURA_OK;
 }
 
@@ -1639,19 +1641,12 @@ int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_p
     P->ws_base = (char*)ws;
     P->ws_cap = ws_cap;
   }
-  {
-    const char* ev = std::getenv("BURA_NO_GRAPH");
-    P->use_graphs = !(ev && ev[0] == '1') && !ws;
-    // folding the scalar updates into the producing kernels needs a
-    // device-scope fence per block, which on a multi-XCD part writes back L2;
-    // it is slower than a separate launch, so it is opt-in (BURA_FOLD=1)
-    const char* ef = std::getenv("BURA_FOLD");
-    P->fold = ef && ef[0] == '1';
-  }
-  {
-    const char* ev = std::getenv("BURA_UNFUSED");
-    P->unfused = ev && ev[0] == '1';
-  }
+  P->use_graphs = !(o.variant & BURA_VARIANT_NO_GRAPH) && !ws;
+  // folding the scalar updates into the producing kernels needs a device-scope
+  // fence per block, which on a multi-XCD part writes back L2; it is slower
+  // than a separate launch, so it is a variant, not the default
+  P->fold = (o.variant & BURA_VARIANT_FOLD_SCALARS) != 0;
+  P->unfused = (o.variant & BURA_VARIANT_UNFUSED) != 0;
   int rc = build_levels(P, g);
   if (rc) { delete P; return rc; }
   P->tile_down.assign(P->lev.size(), 0);
@@ -1695,12 +1690,9 @@ int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_p
   set_default_tiles(P);
   const bool mixed = o.precision == BURA_MIXED;
   choose_lds(P, mixed ? 4 : 8);
-  {
-    const char* ev = std::getenv("BURA_NO_FOLDXR");
-    // needs a multigrid level with a pre-smoothing sweep (the fused down
-    // kernel in 2D, the first Jacobi sweep otherwise)
-    P->foldxr = P->lc > 0 && !(ev && ev[0] == '1');
-  }
+  // the folded vector updates need a multigrid level with a pre-smoothing
+  // sweep (the fused down kernel in 2D, the first Jacobi sweep otherwise)
+  P->foldxr = P->lc > 0 && !(o.variant & BURA_VARIANT_NO_FOLDXR);
   if (P->opts.max_iter == 0) {
     // automatic cap: multigrid-PCG needs O(1) iterations per digit; Jacobi-PCG
     // (no hierarchy) needs O(sqrt(kappa)) = O(n) per digit
@@ -2093,6 +2085,7 @@ int bura_opts_default(bura_opts_t* o) {
   o->hbm_budget = 0;
   o->autotune = 0;
   o->err_tol = 0.0;
+  o->variant = 0;
   return BURA_OK;
 }
 

@@ -164,3 +164,15 @@ def test_err_tol_needs_mixed_precision_and_no_stages():
     with pytest.raises(B.BuraError) as ei:
         B.bura_plan_create(2, 31, 0.5, 5, B.bura_opts_default(err_tol=-1.0))
     assert ei.value.code == B.BURA_EINVAL
+
+
+def test_unknown_variant_bits_are_rejected():
+    """opts.variant takes only the documented alternative code paths."""
+    import paper_1612_04846_amd as B
+    allbits = (B.BURA_VARIANT_UNFUSED | B.BURA_VARIANT_NO_FOLDXR | B.BURA_VARIANT_FOLD_SCALARS
+               | B.BURA_VARIANT_NO_GRAPH)
+    assert B.bura_opts_default().variant == 0
+    for v in (16, allbits | 32, -1):
+        with pytest.raises(B.BuraError) as ei:
+            B.bura_plan_create(2, 31, 0.5, 5, B.bura_opts_default(variant=v))
+        assert ei.value.code == B.BURA_EINVAL

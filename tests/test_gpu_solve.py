@@ -155,15 +155,14 @@ def test_3d_march_widths_with_ragged_tiles(n, prec):
     plan.close()
 
 
-def test_q_buffer_only_where_a_kernel_reads_q(monkeypatch):
+def test_q_buffer_only_where_a_kernel_reads_q():
     """Plans whose residual update forms q = (A + s) p from p (fused 2D down
     kernel) hold one vector per system less than the 2D unfused plan, whose
     first sweep reads q; nothing else differs between the two."""
     B = _B()
     n, k = 255, 5
     fused = B.Plan(2, n, 0.5, k, nrhs_max=2, precision=B.BURA_FP64)
-    monkeypatch.setenv("BURA_UNFUSED", "1")
-    unfused = B.Plan(2, n, 0.5, k, nrhs_max=2, precision=B.BURA_FP64)
+    unfused = B.Plan(2, n, 0.5, k, nrhs_max=2, precision=B.BURA_FP64, variant=B.BURA_VARIANT_UNFUSED)
     try:
         bf, bu = fused.info[2], unfused.info[2]
         assert bu - bf == (k + 1) * 2 * n * n * 8
@@ -353,29 +352,28 @@ def test_multi_alpha_plan_equals_single_plans():
     pm.close()
 
 
-def test_folded_scalars_match_separate_launches(monkeypatch):
+def test_folded_scalars_match_separate_launches():
     """Scalar updates folded into the producing kernels (opt-in) give the same bits as separate launches,
     with and without graph replay."""
     B = _B()
     n = 63
     F = _dev(synth.normal_rhs(n, 2, nrhs=1, tag=92))
     u_sep = _host(B.Plan(2, n, 0.5, 5, precision=B.BURA_MIXED).solve(F).u)
-    monkeypatch.setenv("BURA_FOLD", "1")
-    u_fold = _host(B.Plan(2, n, 0.5, 5, precision=B.BURA_MIXED).solve(F).u)
-    monkeypatch.setenv("BURA_NO_GRAPH", "1")
-    u_eager = _host(B.Plan(2, n, 0.5, 5, precision=B.BURA_MIXED).solve(F).u)
+    u_fold = _host(B.Plan(2, n, 0.5, 5, precision=B.BURA_MIXED, variant=B.BURA_VARIANT_FOLD_SCALARS).solve(F).u)
+    u_eager = _host(B.Plan(2, n, 0.5, 5, precision=B.BURA_MIXED,
+                           variant=B.BURA_VARIANT_FOLD_SCALARS | B.BURA_VARIANT_NO_GRAPH).solve(F).u)
     assert np.array_equal(u_fold, u_sep)
     assert np.array_equal(u_eager, u_sep)
 
 
-FOLD_CASES = [  # dim, n, precision, one kernel per V-cycle step (BURA_UNFUSED=1)
+FOLD_CASES = [  # dim, n, precision, one kernel per V-cycle step (BURA_VARIANT_UNFUSED)
     (2, 255, "FP64", False), (2, 255, "MIXED", False),
     (3, 63, "FP64", False), (3, 63, "MIXED", False), (2, 127, "MIXED", True),
 ]
 
 
 @pytest.mark.parametrize("dim,n,prec,unfused", FOLD_CASES)
-def test_folded_vector_updates_match_separate_pass(monkeypatch, dim, n, prec, unfused):
+def test_folded_vector_updates_match_separate_pass(dim, n, prec, unfused):
     """x += alpha p deferred into the stencil-product pass and r -= alpha q done by the
     first fine pre-smoothing kernel (fused down kernel in 2D, the zero-guess Jacobi
     sweep in 3D or unfused) give the same result as the separate update pass; both
@@ -384,13 +382,12 @@ def test_folded_vector_updates_match_separate_pass(monkeypatch, dim, n, prec, un
     from oracle import spectral
     B = _B()
     alpha, k = 0.75, 9
-    if unfused:
-        monkeypatch.setenv("BURA_UNFUSED", "1")
+    v = B.BURA_VARIANT_UNFUSED if unfused else 0
     F = synth.normal_rhs(n, dim, nrhs=2, tag=93)
     pr = getattr(B, "BURA_" + prec)
-    u_fold = _host(B.Plan(dim, n, alpha, k, precision=pr, nrhs_max=2, tol=1e-11).solve(_dev(F)).u)
-    monkeypatch.setenv("BURA_NO_FOLDXR", "1")
-    u_sep = _host(B.Plan(dim, n, alpha, k, precision=pr, nrhs_max=2, tol=1e-11).solve(_dev(F)).u)
+    u_fold = _host(B.Plan(dim, n, alpha, k, precision=pr, nrhs_max=2, tol=1e-11, variant=v).solve(_dev(F)).u)
+    u_sep = _host(B.Plan(dim, n, alpha, k, precision=pr, nrhs_max=2, tol=1e-11,
+                         variant=v | B.BURA_VARIANT_NO_FOLDXR).solve(_dev(F)).u)
     b = oracle_bura(alpha, k)
     ref = spectral.bura_spectral(F, dim, b.c_f64, b.d_f64)
     d = np.linalg.norm((u_fold - u_sep).reshape(2, -1), axis=1) / np.linalg.norm(ref.reshape(2, -1), axis=1)
