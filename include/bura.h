@@ -108,7 +108,10 @@ typedef struct {
 /* Solver options.  bura_opts_default fills sensible values. */
 typedef struct {
   double tol;          /* per-system stop: ||f - (A - d_j I) x_j||_2 <= tol ||f||_2 (FP64) */
-  double inner_tol;    /* MIXED: relative reduction of each FP32 inner solve             */
+  double inner_tol;    /* MIXED: the largest relative reduction asked of one FP32 inner
+                          solve.  A refinement step that can finish a system asks only for
+                          what its tol still needs (half of tol / its current FP64 relative
+                          residual, when that is larger than inner_tol)                   */
   int precision;       /* enum bura_precision                                            */
   int schedule;        /* enum bura_schedule                                             */
   int max_iter;        /* PCG iteration cap (per inner solve in MIXED mode); 0 = automatic
@@ -178,7 +181,7 @@ typedef struct {
                                        stages (sequential forms), where it is not formed.   */
 } bura_report_t;
 
-/* Fill *o with defaults: tol 1e-12, inner_tol 1e-5, BURA_MIXED, BURA_BATCHED,
+/* Fill *o with defaults: tol 1e-12, inner_tol 5e-6, BURA_MIXED, BURA_BATCHED,
  * max_iter 0 (automatic), max_outer 12, nrhs_max 1, check_every 4, V(2,2),
  * stream NULL, err_tol 0, variant 0. */
 int bura_opts_default(bura_opts_t* o);

@@ -815,6 +815,7 @@ SysState state_at(const bura_plan_t P, size_t sys0) {
   s.fnorm2 += sys0; s.relres64 += sys0; s.active64 += sys0; s.outer += sys0;
   if (s.tol_pcg) s.tol_pcg += sys0;
   if (s.tol_outer) s.tol_outer += sys0;
+  if (s.tol_inner) s.tol_inner += sys0;
   return s;
 }
 
@@ -1763,6 +1764,12 @@ int create(const bura_grid_t* g, Terms terms, const bura_opts_t* opts_in, bura_p
     if ((rc = dev_alloc(P, (void**)&P->d_unorm, rows * 8))) return fail(rc);
     if (mixed && (rc = dev_alloc(P, (void**)&P->d_tol_err, S * 8))) return fail(rc);
   }
+  if (mixed) {
+    // each inner solve's tolerance, set per system by the refinement test
+    // before the solve starts (every path runs OP_OUTER first)
+    if ((rc = dev_alloc(P, (void**)&P->st.tol_inner, S * 8))) return fail(rc);
+    P->st.inner_floor = o.inner_tol;
+  }
   const size_t state_mirror = S * (6 * 8 + 8 * 4) + S * 8 + (size_t)P->nout * o.nrhs_max * 8;
   if (ws) {
     // host mirrors in ordinary memory (8-byte aligned: the state comes first)
@@ -2071,7 +2078,7 @@ int bura_opts_default(bura_opts_t* o) {
   if (!o) return BURA_EINVAL;
   std::memset(o, 0, sizeof(*o));
   o->tol = 1e-12;
-  o->inner_tol = 1e-5;
+  o->inner_tol = 5e-6;
   o->precision = BURA_MIXED;
   o->schedule = BURA_BATCHED;
   o->max_iter = 0;

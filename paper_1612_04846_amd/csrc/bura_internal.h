@@ -76,6 +76,11 @@ struct SysState {
   // operation): of the PCG (FP64 mode) and of the refinement (MIXED mode)
   const double* tol_pcg = nullptr;
   const double* tol_outer = nullptr;
+  // MIXED: the stopping tolerance of each system's next inner solve, set by
+  // the refinement test: the reduction its outer tolerance still needs
+  // (halved for margin), but no smaller than inner_floor (opts.inner_tol)
+  double* tol_inner = nullptr;
+  double inner_floor = 0.0;
 };
 
 enum ScalarOp { OP_INIT = 0, OP_ALPHA = 1, OP_RESID = 2, OP_BETA = 3, OP_OUTER = 4 };

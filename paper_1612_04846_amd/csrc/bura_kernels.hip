@@ -2030,7 +2030,7 @@ __device__ void apply_op(int op, double tot, const SysState& S, int sys, double 
       if (!isfinite(rel)) {
         S.flags[sys] |= 1;
         S.active[sys] = 0;
-      } else if (rel <= (S.tol_pcg ? S.tol_pcg[sys] : tol) || it >= max_iter) {
+      } else if (rel <= (S.tol_inner ? S.tol_inner[sys] : S.tol_pcg ? S.tol_pcg[sys] : tol) || it >= max_iter) {
         S.active[sys] = 0;
       }
       break;
@@ -2050,7 +2050,8 @@ __device__ void apply_op(int op, double tot, const SysState& S, int sys, double 
       const double rel = fn > 0.0 ? sqrt(tot / fn) : 0.0;
       S.relres64[sys] = rel;
       S.outer[sys] = o + 1;
-      if (rel <= (S.tol_outer ? S.tol_outer[sys] : tol) || o >= max_iter) {
+      const double to = S.tol_outer ? S.tol_outer[sys] : tol;
+      if (rel <= to || o >= max_iter) {
         S.active64[sys] = 0;
         S.active[sys] = 0;
       } else {
@@ -2059,6 +2060,11 @@ __device__ void apply_op(int op, double tot, const SysState& S, int sys, double 
         S.iters[sys] = 0;
         S.relres[sys] = 1.0;
         S.beta[sys] = 0.0;
+        if (S.tol_inner) {
+          // a step that can finish the system asks only for what is left
+          const double want = 0.5 * to / rel;
+          S.tol_inner[sys] = want > S.inner_floor ? want : S.inner_floor;
+        }
       }
       break;
     }
