@@ -667,8 +667,11 @@ int upload_faces(bura_plan_t P) {
 // ---------------------------------------------------------------------------
 // the fused level kernels exist for 2D hierarchies with 1..3 sweeps
 bool fused_ok(const bura_plan_t P) {
-  return P->dim == 2 && P->lc > 0 && P->opts.nu_pre >= 1 && P->opts.nu_pre <= 3 && P->opts.nu_post >= 1 &&
-         P->opts.nu_post <= 3 && !P->unfused;
+  if (P->lc <= 0 || P->unfused || P->opts.nu_pre < 1 || P->opts.nu_post < 1) return false;
+  if (P->dim == 2) return P->opts.nu_pre <= 3 && P->opts.nu_post <= 3;
+  // 3D: constant coefficients, up to two sweeps (the z-marching kernels hold
+  // every sweep's planes in LDS)
+  return !P->var && P->opts.nu_pre <= 2 && P->opts.nu_post <= 2;
 }
 
 // The PCG residual update folded into the fine down kernel: r_new = r_old -

@@ -126,7 +126,7 @@ struct Rows {
 
 // FP64 block sum; the result is valid in thread 0 only.  Fixed order.
 __device__ __forceinline__ double block_sum(double v) {
-  __shared__ double sh[kBlock / 64];
+  __shared__ double sh[16];   // one value per wave, up to 1024 threads
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   const int tid = threadIdx.x + threadIdx.y * blockDim.x;
@@ -1420,6 +1420,489 @@ __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, con
 }
 
 // --------------------------------------------------------------------------
+// Fused 3D level kernels (constant coefficients), marching along z.  The 2D
+// fused kernels stage a tile with a halo and run every sweep on it in LDS; in
+// 3D a halo in z would cost about as much as the tile, so a workgroup owns an
+// xy tile (with its halo) and walks up the planes with the stages lagging one
+// plane behind each other.  At step t plane t enters; the first sweep (from
+// x = 0 in the down kernel, the interpolated correction in the up kernel) is
+// formed on it pointwise, and sweep m on plane t - m + 1 (down) or t - m (up).
+// The newest plane of every stage goes into LDS for its in-plane neighbours;
+// the planes above and below stay in registers.  A workgroup starts NU planes
+// below its own (warm-up), so every plane it writes is exact; two barriers per
+// plane.  Points off the grid (also planes below 0 and above n - 1) carry a
+// zero right-hand side and a zero inverse diagonal, so they stay exactly 0,
+// and the sweeps are branch-free as in the 2D kernels.
+//
+// k_down3: b (or, RUP, b_old - alpha (A + s) p formed on the fly, as in
+// k_down2), NU sweeps from zero, the residual b - (A + s) x and its full
+// weighting (the weights and order of k_restrict3); writes the pre-smoothed
+// iterate on the owned fine planes and kD3Kz coarse planes of the coarse
+// right-hand side.  One coarse column per thread.
+// k_up3: x = x_in + P x_c (trilinear, as k_prolong3 along z), NU sweeps (the
+// pre-smoothing weights reversed); writes the result on kU3Fz owned fine
+// planes (and b.x when it is the finest level).
+// --------------------------------------------------------------------------
+constexpr int kD3Cx = 32, kD3Cy = 8, kD3Kz = 16;   // coarse columns and planes per workgroup (down)
+constexpr int kU3Ox = 64, kU3Oy = 16, kU3Fz = 32;  // fine columns and planes per workgroup (up)
+// 512 threads per workgroup: half the region points per thread of a
+// 256-thread workgroup, so every sweep's planes fit in about 100 registers
+// (FP32; 4 waves per SIMD instead of 2)
+constexpr int kF3Threads = 512;
+static_assert(kD3Cx * kD3Cy <= kF3Threads, "one coarse column per thread");
+
+// (A + s) x at region point PAD + q from the in-plane values in LDS (row
+// length RX) and the values below (xb) and above (xf): constant
+// coefficients, the arithmetic and order of apply_col3
+template <typename T>
+__device__ __forceinline__ T lds_apply3(const T* X, int q, int RX, T xb, T xf, T w, T s) {
+  const T xc = X[q];
+  T sum = (xc - X[q - 1]) + (xc - X[q + 1]) + (xc - X[q - RX]) + (xc - X[q + RX]);
+  sum += (xc - xb) + (xc - xf);
+  return w * sum + s * xc;
+}
+
+template <typename T, int NU, bool RUP>
+__global__ __launch_bounds__(kF3Threads) void k_down3(LevelDev<T> Lf, LevelDev<T> Lc, const T* __restrict__ b,
+                                               T* __restrict__ xout, T* __restrict__ bc,
+                                               const T* __restrict__ shift, const int* __restrict__ active,
+                                               Sweeps<T> om, unsigned long long* __restrict__ ctr,
+                                               const T* __restrict__ pv, const double* __restrict__ alpha,
+                                               T* __restrict__ bout, double* __restrict__ partial, Fin fin) {
+  constexpr int CX = kD3Cx, CY = kD3Cy;
+  // the region: the owned fine columns with a halo of NU + 1; p (RUP) on
+  // the region widened by one point, in a layout of its own
+  constexpr int RX = 2 * CX + 2 * NU + 1, RY = 2 * CY + 2 * NU + 1, RN = RX * RY;
+  constexpr int PX = RX + 2, PY = RY + 2, PN = PX * PY;
+  constexpr int PER = (RN + kF3Threads - 1) / kF3Threads, PPER = RUP ? (PN + kF3Threads - 1) / kF3Threads : 1;
+  constexpr int PAD = RX + 1, LX = PAD + PER * kF3Threads + RX + 1;
+  constexpr int PADP = PX + 1, LP = RUP ? PADP + PPER * kF3Threads + PX + 1 : 1;
+  __shared__ T sx[NU][LX];         // newest plane of each sweep's output
+  __shared__ T sr[LX];             // residual plane
+  __shared__ T sp[RUP ? 3 : 1][LP];   // p of planes z in slot z mod 3 (RUP): below, centre, above
+  const Tile tl = block_tile();
+  const int sys = tl.z;
+  if (!active[sys]) return;
+  count_bytes_tile(tl, ctr, (unsigned long long)Lf.N * sizeof(T) * (RUP ? 4 : 2) +
+                                   (unsigned long long)Lc.N * sizeof(T));
+  const int nf = Lf.n, nc = Lc.n;
+  const int yt = (nc + CY - 1) / CY;
+  const int kseg = tl.y / yt;
+  const int I0 = tl.x * CX, J0 = (tl.y - kseg * yt) * CY;
+  const int K0 = kseg * kD3Kz, K1 = min(K0 + kD3Kz, nc);
+  const int fz1 = K1 == nc ? nf : 2 * K1;   // owned fine planes [2 K0, fz1) (the last segment: the top one too)
+  const int gx0 = 2 * I0 - NU, gy0 = 2 * J0 - NU;
+  const long long nn = (long long)nf * nf, off = (long long)sys * Lf.N;
+  const T sh = shift[sys], w = Lf.wc;
+  const T rcon = jacobi_recip(w * T(6) + sh);
+  const T am = RUP ? (T)alpha[sys] : T(0);
+  const int tid = threadIdx.x;
+  // zero planes: the pads stay 0, the rest is written before a valid point reads it
+  for (int i = tid; i < LX; i += kF3Threads) {
+#pragma unroll
+    for (int m = 0; m < NU; ++m) sx[m][i] = T(0);
+    sr[i] = T(0);
+  }
+  if (RUP)
+    for (int i = tid; i < LP; i += kF3Threads) sp[0][i] = sp[1][i] = sp[2][i] = T(0);
+  __syncthreads();
+  // region point u of this thread: on the grid in-plane (bit u of `in`),
+  // owned (bit u of `own`), its in-plane offset clamped into the grid
+  const int hx = (I0 + CX >= nc) ? nf : 2 * (I0 + CX);
+  const int hy = (J0 + CY >= nc) ? nf : 2 * (J0 + CY);
+  unsigned in = 0u, own = 0u;
+  int col[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int q = tid + kF3Threads * u;
+    const int ry = q / RX, rx = q - ry * RX;
+    const int gi = gx0 + rx, gj = gy0 + ry;
+    const bool on = q < RN && gi >= 0 && gi < nf && gj >= 0 && gj < nf;
+    in |= (on ? 1u : 0u) << u;
+    own |= ((on && gi >= 2 * I0 && gi < hx && gj >= 2 * J0 && gj < hy) ? 1u : 0u) << u;
+    col[u] = min(max(gj, 0), nf - 1) * nf + min(max(gi, 0), nf - 1);
+  }
+  const T* __restrict__ bs = b + off;
+  const T* __restrict__ ps = RUP ? pv + off : nullptr;
+  // p-layout point u of this thread: on the grid (bit u of `pin`), its clamped in-plane offset
+  unsigned pin = 0u;
+  int pcol[PPER];
+#pragma unroll
+  for (int u = 0; u < PPER; ++u) {
+    const int q = tid + kF3Threads * u;
+    const int py = q / PX, px = q - py * PX;
+    const int gi = gx0 - 1 + px, gj = gy0 - 1 + py;
+    pin |= ((RUP && q < PN && gi >= 0 && gi < nf && gj >= 0 && gj < nf) ? 1u : 0u) << u;
+    pcol[u] = min(max(gj, 0), nf - 1) * nf + min(max(gi, 0), nf - 1);
+  }
+  // a plane z of p at this thread's p-layout points (0 off the grid)
+  auto load_p = [&](int z, T* dst) {
+    const bool zin = z >= 0 && z < nf;
+    const long long base = (long long)min(max(z, 0), nf - 1) * nn;
+#pragma unroll
+    for (int u = 0; u < PPER; ++u) {
+      const T v = ps[base + pcol[u]];
+      dst[u] = (zin && ((pin >> u) & 1u)) ? v : T(0);
+    }
+  };
+  auto slot = [](int z) { return ((z % 3) + 3) % 3; };
+  // planes t0 .. t1 enter: the first written residual (fine plane 2 K0)
+  // depends on the first sweep down to plane 2 K0 - NU; the last is the
+  // residual of fine plane 2 K1
+  const int t0 = 2 * K0 - NU, t1 = 2 * K1 + NU;
+  // registers: bh[d] = b of plane t - d; xh[m][0], xh[m][1] = sweep m+1's
+  // output at its newest plane of the previous step and the one below
+  T bh[NU + 1][PER], xh[NU][2][PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+#pragma unroll
+    for (int d = 0; d <= NU; ++d) bh[d][u] = T(0);
+#pragma unroll
+    for (int m = 0; m < NU; ++m) xh[m][0][u] = xh[m][1][u] = T(0);
+  }
+  if (RUP) {
+    for (int z = t0 - 1; z <= t0 + 1; ++z) {
+      T pl[PPER];
+      load_p(z, pl);
+#pragma unroll
+      for (int u = 0; u < PPER; ++u) sp[slot(z)][PADP + tid + kF3Threads * u] = pl[u];
+    }
+  }
+  // the coarse column of this thread: its centre fine point in the region and
+  // the weighted in-plane sums of the residual on fine planes 2K and 2K + 1
+  const bool restricts = tid < CX * CY;   // whole waves
+  const int ci = tid % CX, cj = restricts ? tid / CX : 0;
+  const bool mine = restricts && I0 + ci < nc && J0 + cj < nc;
+  const int rcq = PAD + (2 * cj + NU) * RX + (2 * ci + NU);   // fine (2I, 2J) of its 3 x 3 block
+  T s_lo = T(0), s_mid = T(0);
+  const long long ncc = (long long)nc * nc;
+  T* __restrict__ bcs = bc + (long long)sys * Lc.N + ((long long)(J0 + cj) * nc + (I0 + ci));
+  T* __restrict__ xs = xout + off;
+  T* __restrict__ bo = RUP ? bout + off : nullptr;
+  double rr = 0.0;
+  // b of the next plane is loaded a step ahead, so its latency overlaps a step
+  T bnx[PER];
+  {
+    const long long b0 = (long long)min(max(t0, 0), nf - 1) * nn;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) bnx[u] = bs[b0 + col[u]];
+  }
+  __syncthreads();
+  for (int t = t0; t <= t1; ++t) {
+    const long long base = (long long)min(max(t, 0), nf - 1) * nn;
+    // the loads of the step: b(t + 1) for the next step, and p(t + 2) (RUP)
+    T bl[PER], pn[RUP ? PPER : 1];
+    {
+      const long long bb = (long long)min(max(t + 1, 0), nf - 1) * nn;
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        bl[u] = bnx[u];
+        bnx[u] = bs[bb + col[u]];
+      }
+    }
+    if (RUP) load_p(t + 2, pn);
+    // in-grid mask of plane g for point u (0 off the grid, above and below it)
+    auto on_at = [&](int g, int u) { return g >= 0 && g < nf && ((in >> u) & 1u); };
+#pragma unroll
+    for (int d = NU; d > 0; --d)
+#pragma unroll
+      for (int u = 0; u < PER; ++u) bh[d][u] = bh[d - 1][u];
+    const bool wr_t = RUP && t >= 2 * K0 && t < fz1;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      T bn = bl[u];
+      if (RUP) {
+        const int q = tid + kF3Threads * u;
+        const int ry = q / RX, rx = q - ry * RX;
+        const int pq = PADP + (ry + 1) * PX + (rx + 1);
+        bn = bl[u] - am * lds_apply3<T>(sp[slot(t)], pq, PX, sp[slot(t - 1)][pq], sp[slot(t + 1)][pq], w, sh);
+      }
+      bh[0][u] = on_at(t, u) ? bn : T(0);
+      if (wr_t && ((own >> u) & 1u)) {
+        __builtin_nontemporal_store(bh[0][u], &bo[base + col[u]]);
+        rr += (double)bh[0][u] * (double)bh[0][u];
+      }
+    }
+    // sweep 1 on plane t from x = 0; sweep m + 1 on plane t - m from sweep
+    // m's output (centre plane in sx[m - 1], below in xh, above just formed)
+    T xn[NU][PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) xn[0][u] = sweep_w(om, 0) * bh[0][u] * (on_at(t, u) ? rcon : T(0));
+#pragma unroll
+    for (int m = 1; m < NU; ++m) {
+      const T wm = sweep_w(om, m);
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int q = PAD + tid + kF3Threads * u;
+        const T ax = lds_apply3<T>(sx[m - 1], q, RX, xh[m - 1][1][u], xn[m - 1][u], w, sh);
+        xn[m][u] = xh[m - 1][0][u] + wm * (bh[m][u] - ax) * (on_at(t - m, u) ? rcon : T(0));
+      }
+    }
+    // the residual on plane t - NU
+    T res[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int q = PAD + tid + kF3Threads * u;
+      res[u] = bh[NU][u] - lds_apply3<T>(sx[NU - 1], q, RX, xh[NU - 1][1][u], xn[NU - 1][u], w, sh);
+    }
+    // the pre-smoothed iterate: sweep NU's newest plane t - NU + 1
+    const int gx = t - NU + 1;
+    if (gx >= 2 * K0 && gx < fz1) {
+      const long long bx = (long long)gx * nn;
+#pragma unroll
+      for (int u = 0; u < PER; ++u)
+        if ((own >> u) & 1u) __builtin_nontemporal_store(xn[NU - 1][u], &xs[bx + col[u]]);
+    }
+    __syncthreads();   // every read of this step's LDS planes is done
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int q = PAD + tid + kF3Threads * u;
+#pragma unroll
+      for (int m = 0; m < NU; ++m) sx[m][q] = xn[m][u];
+      sr[q] = res[u];
+    }
+    if (RUP) {   // p(t + 2) takes the slot of p(t - 1)
+#pragma unroll
+      for (int u = 0; u < PPER; ++u) sp[slot(t + 2)][PADP + tid + kF3Threads * u] = pn[u];
+    }
+    __syncthreads();
+    // full weighting: this coarse column's in-plane sum of fine plane f = t - NU,
+    // and coarse plane K = f/2 - 1 once f = 2K + 2 (weights 1/4, 1/2, 1/4 along z)
+    const int f = t - NU;
+    if (restricts && f >= 2 * K0) {
+      const T wt[3] = {T(0.25), T(0.5), T(0.25)};
+      T acc = T(0);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        const int di = q % 3, dj = q / 3;
+        acc += wt[dj] * wt[di] * sr[rcq + dj * RX + di];
+      }
+      if (f == 2 * K0) {
+        s_lo = acc;
+      } else if (f & 1) {
+        s_mid = acc;
+      } else {
+        const int K = f / 2 - 1;
+        if (mine) bcs[K * ncc] = T(0.25) * s_lo + T(0.5) * s_mid + T(0.25) * acc;
+        s_lo = acc;
+      }
+    }
+    // shift the registers one plane up
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+#pragma unroll
+      for (int m = 0; m < NU; ++m) {
+        xh[m][1][u] = xh[m][0][u];
+        xh[m][0][u] = xn[m][u];
+      }
+    }
+  }
+  if (RUP) {
+    write_partial_tile(tl, partial, sys, rr);
+    finish(fin, partial, sys, gridDim.x * gridDim.y);
+  }
+}
+
+template <typename T, int NU, bool DOT>
+__global__ __launch_bounds__(kF3Threads) void k_up3(LevelDev<T> Lc, LevelDev<T> Lf, const T* __restrict__ xc,
+                                             const T* __restrict__ xin, const T* __restrict__ b, T* __restrict__ xout,
+                                             const T* __restrict__ shift, const int* __restrict__ active, Sweeps<T> om,
+                                             double* __restrict__ partial, unsigned long long* __restrict__ ctr,
+                                             Fin fin) {
+  constexpr int OX = kU3Ox, OY = kU3Oy;
+  constexpr int RX = OX + 2 * NU, RY = OY + 2 * NU, RN = RX * RY;
+  constexpr int PER = (RN + kF3Threads - 1) / kF3Threads;
+  constexpr int PAD = RX + 1, LX = PAD + PER * kF3Threads + RX + 1;
+  // the coarse columns under the region, zero-padded: coarse index c at cx0 + (c - c0)
+  constexpr int CRX = RX / 2 + 3, CRY = RY / 2 + 3, CRN = CRX * CRY;
+  constexpr int CPER = (CRN + kF3Threads - 1) / kF3Threads;
+  __shared__ T sx[NU][LX];   // newest plane of the correction and of sweeps 1 .. NU-1
+  __shared__ T sc[CRN];      // one coarse plane under the region
+  const Tile tl = block_tile();
+  const int sys = tl.z;
+  if (!active[sys]) return;
+  count_bytes_tile(tl, ctr, (unsigned long long)Lf.N * sizeof(T) * 3 + (unsigned long long)Lc.N * sizeof(T));
+  const int nf = Lf.n, nc = Lc.n;
+  const int yt = (nf + OY - 1) / OY;
+  const int zseg = tl.y / yt;
+  const int ox0 = tl.x * OX, oy0 = (tl.y - zseg * yt) * OY;
+  const int z0 = zseg * kU3Fz, z1 = min(z0 + kU3Fz, nf);
+  const int gx0 = ox0 - NU, gy0 = oy0 - NU;
+  const int cx0 = ((gx0 >= 0) ? gx0 / 2 : -((-gx0 + 1) / 2)) - 1;
+  const int cy0 = ((gy0 >= 0) ? gy0 / 2 : -((-gy0 + 1) / 2)) - 1;
+  const long long nn = (long long)nf * nf, off = (long long)sys * Lf.N, ncc = (long long)nc * nc;
+  const T sh = shift[sys], w = Lf.wc;
+  const T rcon = jacobi_recip(w * T(6) + sh);
+  const int tid = threadIdx.x;
+  // zero planes: the pads stay 0, the rest is written before a valid point reads it
+  for (int i = tid; i < LX; i += kF3Threads) {
+#pragma unroll
+    for (int m = 0; m < NU; ++m) sx[m][i] = T(0);
+  }
+  unsigned in = 0u, own = 0u;
+  int col[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int q = tid + kF3Threads * u;
+    const int ry = q / RX, rx = q - ry * RX;
+    const int gi = gx0 + rx, gj = gy0 + ry;
+    const bool on = q < RN && gi >= 0 && gi < nf && gj >= 0 && gj < nf;
+    in |= (on ? 1u : 0u) << u;
+    own |= ((on && rx >= NU && rx < NU + OX && ry >= NU && ry < NU + OY) ? 1u : 0u) << u;
+    col[u] = min(max(gj, 0), nf - 1) * nf + min(max(gi, 0), nf - 1);
+  }
+  const T* __restrict__ xcs = xc + (long long)sys * Lc.N;
+  const T* __restrict__ bs = b + off;
+  const T* __restrict__ xis = xin + off;
+  // coarse plane K under the region into sc (0 off the grid)
+  auto stage = [&](int K) {
+    const long long cb = (long long)min(max(K, 0), nc - 1) * ncc;
+    T cl[CPER];
+#pragma unroll
+    for (int u = 0; u < CPER; ++u) {
+      const int q = tid + kF3Threads * u;
+      const int cy = q / CRX, cx = q - cy * CRX;
+      cl[u] = xcs[cb + (long long)min(max(cy0 + cy, 0), nc - 1) * nc + min(max(cx0 + cx, 0), nc - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < CPER; ++u) {
+      const int q = tid + kF3Threads * u;
+      if (q < CRN) {
+        const int cy = q / CRX, cx = q - cy * CRX;
+        const int I = cx0 + cx, J = cy0 + cy;
+        sc[q] = (K >= 0 && K < nc && I >= 0 && I < nc && J >= 0 && J < nc) ? cl[u] : T(0);
+      }
+    }
+  };
+  // the in-plane interpolant of the staged coarse plane at region point u
+  // (lanes past the region interpolate at its last point, in range of sc)
+  auto interp = [&](int u) -> T {
+    const int q = min(tid + kF3Threads * u, RN - 1);
+    const int ry = q / RX, rx = q - ry * RX;
+    const int gi = gx0 + rx, gj = gy0 + ry;
+    const int ia = (gi & 1) ? (gi - 1) / 2 : gi / 2 - 1;
+    const int ja = (gj & 1) ? (gj - 1) / 2 : gj / 2 - 1;
+    const T* C = sc + (ja - cy0) * CRX + (ia - cx0);
+    if (gi & 1) return (gj & 1) ? C[0] : T(0.5) * (C[0] + C[CRX]);
+    return (gj & 1) ? T(0.5) * (C[0] + C[1]) : T(0.25) * (C[0] + C[1] + C[CRX] + C[CRX + 1]);
+  };
+  // lowest coarse plane of fine plane t (odd t lies on it, even t halfway to the next)
+  auto klo = [](int t) { return (t >> 1) - 1 + (t & 1); };
+  // planes t0 .. t1 enter: the owned plane z0 needs the correction down to z0 - NU
+  const int t0 = z0 - NU, t1 = z1 + NU - 1;
+  // vlo, vhi: the in-plane interpolants of coarse planes Kc and Kc + 1
+  int Kc = klo(t0);
+  T vlo[PER], vhi[PER];
+  stage(Kc);
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) vlo[u] = interp(u);
+  __syncthreads();
+  stage(Kc + 1);
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) vhi[u] = interp(u);
+  // registers: bh[d] = b of plane t - d; xh[m][0], xh[m][1] = stage m's
+  // output (m = 0: the corrected x) at its newest plane of the previous step and
+  // the one below
+  T bh[NU + 1][PER], xh[NU][2][PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+#pragma unroll
+    for (int d = 0; d <= NU; ++d) bh[d][u] = T(0);
+#pragma unroll
+    for (int m = 0; m < NU; ++m) xh[m][0][u] = xh[m][1][u] = T(0);
+  }
+  T* __restrict__ xs = xout + off;
+  double dot = 0.0;
+  // x_in and b of the next plane are loaded a step ahead
+  T xnx[PER], bnx[PER];
+  {
+    const long long b0 = (long long)min(max(t0, 0), nf - 1) * nn;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      xnx[u] = xis[b0 + col[u]];
+      bnx[u] = bs[b0 + col[u]];
+    }
+  }
+  for (int t = t0; t <= t1; ++t) {
+    T xl[PER], bl[PER];
+    {
+      const long long bb = (long long)min(max(t + 1, 0), nf - 1) * nn;
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        xl[u] = xnx[u];
+        bl[u] = bnx[u];
+        xnx[u] = xis[bb + col[u]];
+        bnx[u] = bs[bb + col[u]];
+      }
+    }
+    auto on_at = [&](int g, int u) { return g >= 0 && g < nf && ((in >> u) & 1u); };
+    if (klo(t) > Kc) {   // sc holds coarse plane Kc + 2 (staged in the previous step)
+      ++Kc;
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        vlo[u] = vhi[u];
+        vhi[u] = interp(u);
+      }
+    }
+#pragma unroll
+    for (int d = NU; d > 0; --d)
+#pragma unroll
+      for (int u = 0; u < PER; ++u) bh[d][u] = bh[d - 1][u];
+    // stage 0 on plane t: x_in + P x_c; stage m on plane t - m
+    T xn[NU + 1][PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const bool on = on_at(t, u);
+      bh[0][u] = on ? bl[u] : T(0);
+      const T v = (t & 1) ? vlo[u] : T(0.5) * (vlo[u] + vhi[u]);
+      xn[0][u] = on ? xl[u] + v : T(0);
+    }
+#pragma unroll
+    for (int m = 1; m <= NU; ++m) {
+      const T wm = sweep_w(om, NU - m);
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int q = PAD + tid + kF3Threads * u;
+        const T ax = lds_apply3<T>(sx[m - 1], q, RX, xh[m - 1][1][u], xn[m - 1][u], w, sh);
+        xn[m][u] = xh[m - 1][0][u] + wm * (bh[m][u] - ax) * (on_at(t - m, u) ? rcon : T(0));
+      }
+    }
+    const int g = t - NU;
+    if (g >= z0 && g < z1) {
+      const long long bx = (long long)g * nn;
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const bool o = (own >> u) & 1u;
+        if (o) __builtin_nontemporal_store(xn[NU][u], &xs[bx + col[u]]);
+        if (DOT) dot += o ? (double)bh[NU][u] * (double)xn[NU][u] : 0.0;
+      }
+    }
+    __syncthreads();   // every read of this step's LDS planes is done
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int q = PAD + tid + kF3Threads * u;
+#pragma unroll
+      for (int m = 0; m < NU; ++m) sx[m][q] = xn[m][u];
+    }
+    if (klo(t + 1) > Kc) stage(Kc + 2);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u)
+#pragma unroll
+      for (int m = 0; m < NU; ++m) {
+        xh[m][1][u] = xh[m][0][u];
+        xh[m][0][u] = xn[m][u];
+      }
+  }
+  if (DOT) {
+    write_partial_tile(tl, partial, sys, dot);
+    finish(fin, partial, sys, gridDim.x * gridDim.y);
+  }
+}
+
+// --------------------------------------------------------------------------
 // PCG pieces
 // --------------------------------------------------------------------------
 // p_new = z + beta p_old and q = (A+s) p_new in one pass (p_new formed at the
@@ -2329,8 +2812,22 @@ bool Launch<T>::fused_down(int dim, bool var, int nu, const LevelDev<T>& Lf, con
                            T* xout, T* bc, const T* shift, const int* active, Sweeps<T> om, int nsys, hipStream_t st,
                            unsigned long long* ctr, const T* p, const double* alpha, T* bout, double* partial,
                            Fin fin, int tv) {
-  if (dim != 2 || nu < 1 || nu > 3) return false;
   const bool rup = bout != nullptr;
+  if (dim == 3) {
+    if (var || nu < 1 || nu > 2) return false;
+    const dim3 g((Lc.n + kD3Cx - 1) / kD3Cx, ((Lc.n + kD3Cy - 1) / kD3Cy) * ((Lc.n + kD3Kz - 1) / kD3Kz), nsys);
+#define K_D3(NU_, R_)                                                                                        \
+  hipLaunchKernelGGL((k_down3<T, NU_, R_>), g, dim3(kF3Threads), 0, st, Lf, Lc, b, xout, bc, shift, active, om, ctr, \
+                     p, alpha, bout, partial, fin)
+    if (rup) {
+      if (nu == 1) K_D3(1, true); else K_D3(2, true);
+    } else {
+      if (nu == 1) K_D3(1, false); else K_D3(2, false);
+    }
+#undef K_D3
+    return true;
+  }
+  if (dim != 2 || nu < 1 || nu > 3) return false;
   with_tile(tv, [&](auto v) {
     constexpr int CX = kDownTile[decltype(v)::value][0], CY = kDownTile[decltype(v)::value][1];
     const dim3 g((Lc.n + CX - 1) / CX, (Lc.n + CY - 1) / CY, nsys), blk(256);
@@ -2350,8 +2847,9 @@ bool Launch<T>::fused_down(int dim, bool var, int nu, const LevelDev<T>& Lf, con
 }
 
 int down_blocks(int dim, int n, int tv) {
-  if (dim != 2) return stencil_blocks(dim, n);
   const int nc = (n - 1) / 2;
+  if (dim == 3)
+    return ((nc + kD3Cx - 1) / kD3Cx) * ((nc + kD3Cy - 1) / kD3Cy) * ((nc + kD3Kz - 1) / kD3Kz);
   const int cx = kDownTile[tile_variant(tv)][0], cy = kDownTile[tile_variant(tv)][1];
   return ((nc + cx - 1) / cx) * ((nc + cy - 1) / cy);
 }
@@ -2370,8 +2868,22 @@ template <typename T>
 bool Launch<T>::fused_up(int dim, bool var, int nu, const LevelDev<T>& Lc, const LevelDev<T>& Lf, const T* xc,
                          const T* xin, const T* b, T* xout, const T* shift, const int* active, Sweeps<T> om,
                          double* partial, int nsys, hipStream_t st, unsigned long long* ctr, Fin fin, int tv) {
-  if (dim != 2 || nu < 1 || nu > 3) return false;
   const bool dot = partial != nullptr;
+  if (dim == 3) {
+    if (var || nu < 1 || nu > 2) return false;
+    const dim3 g((Lf.n + kU3Ox - 1) / kU3Ox, ((Lf.n + kU3Oy - 1) / kU3Oy) * ((Lf.n + kU3Fz - 1) / kU3Fz), nsys);
+#define K_U3(NU_, D_)                                                                                          \
+  hipLaunchKernelGGL((k_up3<T, NU_, D_>), g, dim3(kF3Threads), 0, st, Lc, Lf, xc, xin, b, xout, shift, active, om, partial, \
+                     ctr, fin)
+    if (dot) {
+      if (nu == 1) K_U3(1, true); else K_U3(2, true);
+    } else {
+      if (nu == 1) K_U3(1, false); else K_U3(2, false);
+    }
+#undef K_U3
+    return true;
+  }
+  if (dim != 2 || nu < 1 || nu > 3) return false;
   with_tile(tv, [&](auto v) {
     constexpr int OX = kUpTile[decltype(v)::value][0], OY = kUpTile[decltype(v)::value][1];
     const dim3 g((Lf.n + OX - 1) / OX, (Lf.n + OY - 1) / OY, nsys), blk(256);
@@ -2391,7 +2903,7 @@ bool Launch<T>::fused_up(int dim, bool var, int nu, const LevelDev<T>& Lc, const
 }
 
 int up_blocks(int dim, int n, int tv) {
-  if (dim != 2) return stencil_blocks(dim, n);
+  if (dim == 3) return ((n + kU3Ox - 1) / kU3Ox) * ((n + kU3Oy - 1) / kU3Oy) * ((n + kU3Fz - 1) / kU3Fz);
   const int ox = kUpTile[tile_variant(tv)][0], oy = kUpTile[tile_variant(tv)][1];
   return ((n + ox - 1) / ox) * ((n + oy - 1) / oy);
 }

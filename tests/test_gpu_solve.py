@@ -155,6 +155,44 @@ def test_3d_march_widths_with_ragged_tiles(n, prec):
     plan.close()
 
 
+FUSED3D_CASES = [
+    # n, precision, sweeps: 63 -> 31 -> 15 (whole tiles at the top level are
+    # ragged: 31 coarse columns of 32, 31 coarse rows of 8, one z segment),
+    # 127 (four coarse rows of tiles, one segment of 16 coarse planes and a
+    # short one), 47 (an even coarsest level), one sweep
+    (63, "FP64", 2), (63, "MIXED", 2), (127, "MIXED", 2), (47, "MIXED", 2), (63, "MIXED", 1), (31, "FP64", 1),
+]
+
+
+@pytest.mark.parametrize("n,prec,nu", FUSED3D_CASES)
+def test_fused_3d_levels_match_unfused_and_oracle(n, prec, nu):
+    """The z-marching fused 3D level kernels (constant coefficients) against
+    the one-kernel-per-step V-cycle (BURA_VARIANT_UNFUSED) and the oracle: the
+    same preconditioner up to rounding, so both solutions agree to the solver
+    tolerance and match the DST evaluation of eq. (16); with and without the
+    PCG updates folded into the level kernels."""
+    from oracle import spectral
+    B = _B()
+    alpha, k = 0.75, 7
+    b = oracle_bura(alpha, k)
+    F = synth.normal_rhs(n, 3, nrhs=2, tag=97)
+    ref = spectral.bura_spectral(F, 3, b.c_f64, b.d_f64)
+    kw = dict(weights=b.c_f64, shifts=[-x for x in b.d_f64], precision=getattr(B, "BURA_" + prec), nrhs_max=2,
+              tol=1e-12, nu_pre=nu, nu_post=nu)
+    out = {}
+    for name, v in (("fused", 0), ("fused-sep", B.BURA_VARIANT_NO_FOLDXR), ("unfused", B.BURA_VARIANT_UNFUSED)):
+        plan = B.Plan(3, n, variant=v, **kw)
+        res = plan.solve(_dev(F))
+        out[name] = (_host(res.u), list(res.report.iters)[:k + 1])
+        plan.close()
+    for name, (u, it) in out.items():
+        err = float(np.max(np.linalg.norm((u - ref).reshape(2, -1), axis=1) / np.linalg.norm(ref.reshape(2, -1), axis=1)))
+        print(f"3D {n} {prec} nu={nu} {name}: rel err {err:.2e}, iters {it}")
+        assert err <= 1e-9
+    # same preconditioner: the iteration counts agree within one per pole
+    assert all(abs(a - c) <= 1 for a, c in zip(out["fused"][1], out["unfused"][1]))
+
+
 def test_q_buffer_only_where_a_kernel_reads_q():
     """Plans whose residual update forms q = (A + s) p from p (fused 2D down
     kernel) hold one vector per system less than the 2D unfused plan, whose
