@@ -1471,8 +1471,13 @@ std::mutex g_tile_mu;
 std::map<std::string, TileChoice> g_tile_cache;
 
 constexpr int kTuneMinN = 255;
-constexpr int kTuneRounds = 2;        // interleaved timings per variant (the minimum counts)
-constexpr float kTuneMargin = 0.01f;  // a variant replaces the default only if this much faster
+// interleaved timings per variant (the minimum counts), and how much faster
+// than the default a variant must be to replace it: whole solves of a
+// batched plan repeat to about 0.3 %, and the shapes that win on the largest
+// batches win by 1-2 % per knob (two rounds and a 1 % margin kept the default
+// on the 511^2 variable-coefficient workload at 2048 systems, 2 % slower)
+constexpr int kTuneRounds = 3;
+constexpr float kTuneMargin = 0.005f;
 
 // Systems that share one launch: all of them, one pole's right-hand sides
 // (per-pole schedule), or the largest stage (sequential forms).
