@@ -121,8 +121,9 @@ typedef struct {
   int check_every;     /* PCG iterations between host convergence checks (>= 1)          */
   int nu_pre, nu_post; /* Jacobi sweeps before / after coarse-grid correction             */
   double omega;        /* Jacobi damping of every sweep; 0 = library default: 4/5 (2D)
-                          or 6/7 (3D), and for the FP32 inner solves of BURA_MIXED in
-                          2D per-sweep Chebyshev weights on [0.4, 2] (nu = 2)         */
+                          or 6/7 (3D), and for the FP32 inner solves of BURA_MIXED
+                          per-sweep Chebyshev weights on [0.4, 2] (2D) or [0.5, 2]
+                          (3D) for nu <= 2, on [0.3, 2] for nu = 3                     */
   void* stream;        /* hipStream_t used for every launch and copy; NULL = null stream */
   size_t hbm_budget;   /* 0 = unlimited; else plan creation fails with BURA_ENOMEM if its
                           device footprint would exceed this many bytes                 */

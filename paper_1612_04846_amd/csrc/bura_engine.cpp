@@ -359,22 +359,24 @@ double default_omega(int dim) { return dim == 2 ? 0.8 : 6.0 / 7.0; }
 
 // Damping of the nu sweeps of a half-cycle.  opts.omega > 0: that weight for
 // every sweep.  Otherwise FP64 solves use the uniform default_omega, and the
-// FP32 inner solves of BURA_MIXED in 2D use the reciprocals of the roots of the
+// FP32 inner solves of BURA_MIXED use the reciprocals of the roots of the
 // degree-nu Chebyshev polynomial on [lo, 2] (D^-1 A has its spectrum in
-// (0, 2], its high-frequency part above ~0.5 for full coarsening), which damp
-// that range by 1/T_nu((2 + lo)/(2 - lo)) instead of max|1 - omega t|^nu (for
-// nu = 2, 0.21 against 0.36).  The Chebyshev weights shorten the 1e-5 inner
-// solves (7 % less time on the 1023^2 three-alpha workload) but lengthen the
-// 1e-10 FP64 solves (+5 % iterations: they damp the poles with large shifts,
-// whose spectrum sits near 1, less than omega = 0.8 does), hence the split.
-// The weights are polynomials in the same operator, so the smoother stays
-// symmetric in any order.  3D keeps the uniform 6/7.
+// (0, 2], its high-frequency part above ~0.5 in 2D and ~1/3 in 3D for full
+// coarsening), which damp that range by 1/T_nu((2 + lo)/(2 - lo)) instead of
+// max|1 - omega t|^nu (2D, nu = 2: 0.21 against 0.36).  The Chebyshev weights
+// shorten the 1e-5 inner solves (7 % less time on the 1023^2 three-alpha
+// workload, 4-7 % on 255^3) but lengthen the 1e-10 FP64 solves (+5 %
+// iterations: they damp the poles with large shifts, whose spectrum sits near
+// 1, less than omega = 0.8 does), hence the split.  lo was chosen by timing:
+// 0.4 in 2D, 0.5 in 3D (0.4 and 0.6 were slower there).  The weights are
+// polynomials in the same operator, so the smoother stays symmetric in any
+// order.
 template <typename T>
 Sweeps<T> sweep_weights(const bura_plan_t P, int nu) {
   Sweeps<T> s{};
   const double om = P->opts.omega;
-  const double lo = nu >= 3 ? 0.3 : 0.4;
-  const bool cheb = !(om > 0) && P->dim == 2 && sizeof(T) == 4;
+  const double lo = nu >= 3 ? 0.3 : (P->dim == 3 ? 0.5 : 0.4);
+  const bool cheb = !(om > 0) && sizeof(T) == 4;
   for (int i = 0; i < 3; ++i) {
     double w = om > 0 ? om : default_omega(P->dim);
     if (cheb && i < nu) {
