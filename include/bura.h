@@ -356,10 +356,14 @@ int bura_plan_apply(bura_plan_t plan, double shift, const double* x_dev, double*
 
 /* Tile-shape variants of the 2D stencil product and fused multigrid level
  * kernels (an implementation choice, not part of the method).  Every variant
- * computes the same value at every grid point; only the grouping of the
- * per-block partial sums of the PCG dot products differs, so results of two
- * variants agree to rounding, not bit for bit. */
-#define BURA_TILE_VARIANTS 3
+ * computes the same value at every grid point up to rounding (the grouping of
+ * the per-block partial sums of the PCG dot products differs, and variant 3
+ * of the down kernel sums the full weighting in another order), so results
+ * of two variants agree to rounding, not bit for bit.  Variant 3 of the down
+ * and up kernels walks whole grid rows (levels of up to 1023 points per
+ * axis; a larger level runs variant 0); of the stencil product it is the
+ * same shape as variant 0. */
+#define BURA_TILE_VARIANTS 4
 
 /* The variants a 2D plan launches: out[0] for the stencil product, out[1 + 2l]
  * and out[2 + 2l] for the fused down and up kernels of level l, for each of

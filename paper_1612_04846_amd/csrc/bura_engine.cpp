@@ -1575,12 +1575,19 @@ int tune_tiles(bura_plan_t P) {
   const char* tl_env = std::getenv("BURA_TUNE_LOG");
   const bool log = tl_env && tl_env[0] == '1';
   int knob_id = 0;
-  auto tune = [&](int* knob) {
+  // kind: 0 stencil product, 1 down, 2 up (variants that repeat another's
+  // shape on this level are not timed)
+  auto tune = [&](int* knob, int kind, int n) {
     const int def = *knob;
     float best_of[kTileVariants];
-    for (int v = 0; v < kTileVariants; ++v) best_of[v] = 0.0f;
+    bool timed_v[kTileVariants];
+    for (int v = 0; v < kTileVariants; ++v) {
+      best_of[v] = 0.0f;
+      timed_v[v] = v == def || tile_variant_distinct(kind, P->dim, n, v);
+    }
     for (int r = 0; r < kTuneRounds && ok; ++r) {
       for (int v = 0; v < kTileVariants && ok; ++v) {
+        if (!timed_v[v]) continue;
         *knob = v;
         const float ms = timed();
         if (r == 0 || ms < best_of[v]) best_of[v] = ms;
@@ -1588,20 +1595,23 @@ int tune_tiles(bura_plan_t P) {
     }
     int best = def;
     for (int v = 0; v < kTileVariants; ++v)
-      if (v != best && best_of[v] < best_of[best] * (best == def ? 1.0f - kTuneMargin : 1.0f)) best = v;
+      if (timed_v[v] && v != best && best_of[v] < best_of[best] * (best == def ? 1.0f - kTuneMargin : 1.0f))
+        best = v;
     *knob = best;
-    if (log)
-      std::fprintf(stderr, "[bura tune] knob %d: %.4f %.4f %.4f ms -> %d\n", knob_id, best_of[0], best_of[1],
-                   best_of[2], best);
+    if (log) {
+      std::fprintf(stderr, "[bura tune] knob %d:", knob_id);
+      for (int v = 0; v < kTileVariants; ++v) std::fprintf(stderr, " %.4f", timed_v[v] ? best_of[v] : 0.0f);
+      std::fprintf(stderr, " ms -> %d\n", best);
+    }
     ++knob_id;
   };
   set_default_tiles(P);
   timed();   // warm-up (clocks, caches, first-touch)
-  tune(&P->tile_spmv);
+  tune(&P->tile_spmv, 0, P->n);
   for (int l = 0; l < P->lc && fused_ok(P) && ok; ++l) {
     if (P->lev[l].n < kTuneMinN) continue;
-    tune(&P->tile_down[l]);
-    tune(&P->tile_up[l]);
+    tune(&P->tile_down[l], 1, P->lev[l].n);
+    tune(&P->tile_up[l], 2, P->lev[l].n);
   }
   P->use_graphs = graphs;
   hipEventDestroy(e0);

@@ -1064,9 +1064,14 @@ struct RegionFaces {
 // along y).  The down kernel's default region is 133 fine columns wide for
 // the same reason (7 % faster than 69 columns); the up kernel stays at 64
 // fine columns, where it is faster than at 128.
-constexpr int kDownTile[kTileVariants][2] = {{64, 6}, {32, 8}, {64, 8}};
-constexpr int kUpTile[kTileVariants][2] = {{64, 16}, {64, 8}, {64, 24}};
-constexpr int kSpmvTile[kTileVariants][2] = {{4, 128}, {2, 64}, {8, 128}};
+// Variant 3 of the down and up kernels is k_down2r / k_up2r (whole rows,
+// levels of up to 1023 points per axis; a larger level runs variant 0 in its
+// place); of the stencil product it is variant 0 again (the tuner skips it).
+constexpr int kDownTile[kTileVariants][2] = {{64, 6}, {32, 8}, {64, 8}, {64, 6}};
+constexpr int kUpTile[kTileVariants][2] = {{64, 16}, {64, 8}, {64, 24}, {64, 16}};
+constexpr int kSpmvTile[kTileVariants][2] = {{4, 128}, {2, 64}, {8, 128}, {4, 128}};
+constexpr int kRowsVariant = 3;
+constexpr int kRowsMaxN = 1023;
 
 // Reciprocal of a Jacobi diagonal, formed once per point and kernel: the sweeps
 // multiply by it.  FP32: the hardware reciprocal (within 1 ulp); FP64: IEEE
@@ -1425,6 +1430,367 @@ __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, con
     const bool own = ((in >> u) & 1u) && rx >= NU && rx < NU + OX && ry >= NU && ry < NU + OY;
     if (own) __builtin_nontemporal_store(xv[u], &xs[(gy0 + ry) * nf + gx0 + rx]);
     if (DOT) dot += own ? (double)bv[u] * (double)xv[u] : 0.0;
+  }
+  if (DOT) {
+    write_partial_tile(tl, partial, sys, dot);
+    finish(fin, partial, sys, gridDim.x * gridDim.y);
+  }
+}
+
+// --------------------------------------------------------------------------
+// k_down2r: the down kernel of k_down2 (same inputs and outputs, the same
+// arithmetic per point except the order of the full weighting's sum)
+// marching along y over whole grid rows.  A workgroup has one
+// thread per grid column (blockDim.x >= n + 1, a multiple of 64) and owns the
+// fine rows of kDown2rKy coarse rows; it walks up its rows with the stages
+// lagging one row behind each other, as the 3D kernels walk up their planes:
+// at step t row t of b (RUP: b_old - alpha (A + s) p, p of rows t - 1 .. t + 1)
+// enters, the first sweep is formed on it pointwise, sweep m + 1 on row t - m,
+// the residual on row t - NU, and the full weighting of coarse row K once the
+// residual of fine row 2K + 2 is there.  The newest row of every stage goes
+// into LDS for the left/right neighbours; the rows below and above stay in
+// registers.  A workgroup starts NU rows below its first owned row (warm-up),
+// so every row it writes is exact.  There is no halo across columns and none
+// along y beyond the warm-up rows, where the tiles of k_down2 fetch 1.4 - 1.8
+// times their points (halo rows and columns, partial cache lines) and sweep
+// that many.  Columns past the grid and rows outside it carry a zero
+// right-hand side and a zero inverse diagonal, so they stay exactly 0; the
+// LDS rows have a zero pad on each side.  Two barriers per row.
+// --------------------------------------------------------------------------
+constexpr int kDown2rKy = 64;   // coarse rows per workgroup
+
+template <typename T, bool VAR, int NU, bool RUP>
+__global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc, const T* __restrict__ b,
+                                                 T* __restrict__ xout, T* __restrict__ bc,
+                                                 const T* __restrict__ shift, const int* __restrict__ active,
+                                                 Sweeps<T> om, unsigned long long* __restrict__ ctr,
+                                                 const T* __restrict__ pv, const double* __restrict__ alpha,
+                                                 T* __restrict__ bout, double* __restrict__ partial, Fin fin) {
+  constexpr int LW = 1024 + 2;   // an LDS row: pad, up to 1024 columns, pad
+  __shared__ T sx[NU][LW];       // newest row of each sweep's output
+  __shared__ T sr[LW];           // residual row
+  __shared__ T sp[RUP ? LW : 1]; // p of the row being updated (RUP)
+  const Tile tl = block_tile();
+  const int sys = tl.z;
+  if (!active[sys]) return;
+  count_bytes_tile(tl, ctr, (unsigned long long)Lf.N * sizeof(T) * (RUP ? 4 : 2) +
+                                   (unsigned long long)Lc.N * sizeof(T) +
+                                   (VAR && sys == 0 ? (unsigned long long)Lf.N * sizeof(T) * 2 : 0ULL));
+  const int nf = Lf.n, nc = Lc.n;
+  const int K0 = tl.y * kDown2rKy, K1 = min(K0 + kDown2rKy, nc);
+  const int f1 = K1 == nc ? nf : 2 * K1;   // owned fine rows [2 K0, f1) (the last segment: the top one too)
+  const int i = threadIdx.x;               // this thread's column
+  const int NT = blockDim.x;
+  const bool col_on = i < nf;
+  const int ic = min(i, nf - 1);           // clamped column for the loads
+  const T sh = shift[sys];
+  const T rcon = jacobi_recip(Lf.wc * T(4) + sh);
+  const T am = RUP ? (T)alpha[sys] : T(0);
+  const long long off = (long long)sys * Lf.N;
+  const T* __restrict__ bs = b + off;
+  const T* __restrict__ ps = RUP ? pv + off : nullptr;
+  T* __restrict__ xs = xout + off;
+  T* __restrict__ bo = RUP ? bout + off : nullptr;
+  const int q = 1 + i;   // this column in an LDS row
+  // the pads (columns -1 and NT) stay 0; every other entry is written before it is read
+  if (i < 2) {
+    const int pq = i == 0 ? 0 : NT + 1;
+#pragma unroll
+    for (int m = 0; m < NU; ++m) sx[m][pq] = T(0);
+    sr[pq] = T(0);
+    if (RUP) sp[pq] = T(0);
+  }
+  auto row_on = [&](int r) { return col_on && r >= 0 && r < nf; };
+  auto crow = [&](int r) { return min(max(r, 0), nf - 1); };
+  // face weights of row r at this column (clamped row: finite off the grid,
+  // where no sweep uses them) and the inverse diagonal of row r
+  struct Faces { T l, r, d, u; };
+  auto load_faces = [&](int r) {
+    Faces f{T(0), T(0), T(0), T(0)};
+    if (VAR) {
+      const int rr = crow(r);
+      const int fx = rr * (nf + 1) + ic, fy = rr * nf + ic;
+      f.l = Lf.wf0[fx];
+      f.r = Lf.wf0[fx + 1];
+      f.d = Lf.wf1[fy];
+      f.u = Lf.wf1[fy + nf];
+    }
+    return f;
+  };
+  auto rdiag = [&](const Faces& f, int r) {
+    if (!VAR) return row_on(r) ? rcon : T(0);
+    return row_on(r) ? jacobi_recip(f.l + f.r + f.d + f.u + sh) : T(0);
+  };
+  // (A + s) x at this column of a row with faces f, centre xc, left/right from
+  // the LDS row X, below xd and above xu (the arithmetic and order of k_down2)
+  auto apply = [&](const Faces& f, const T* X, T xc, T xd, T xu) {
+    const T xl = X[q - 1], xr = X[q + 1];
+    if (!VAR) return Lf.wc * ((xc - xl) + (xc - xr) + (xc - xd) + (xc - xu)) + sh * xc;
+    return f.l * (xc - xl) + f.r * (xc - xr) + f.d * (xc - xd) + f.u * (xc - xu) + sh * xc;
+  };
+  const int t0 = 2 * K0 - NU, t1 = 2 * K1 + NU;
+  // registers: bh[d] = b of row t - d; xh[m][0], xh[m][1] = sweep m+1's output
+  // at its newest row of the previous step and the one below; fw[d], rd[d] =
+  // faces and inverse diagonal of row t - d
+  T bh[NU + 1], xh[NU][2], rd[NU + 1];
+  Faces fw[NU + 1];
+#pragma unroll
+  for (int d = 0; d <= NU; ++d) {
+    bh[d] = T(0);
+    rd[d] = T(0);
+    fw[d] = load_faces(t0 - 1 - d);
+  }
+#pragma unroll
+  for (int m = 0; m < NU; ++m) xh[m][0] = xh[m][1] = T(0);
+  // p of rows t - 1, t, t + 1 (RUP; 0 outside the grid), p(t) also in sp
+  auto load_p = [&](int r) {
+    const T v = ps[(long long)crow(r) * nf + ic];
+    return row_on(r) ? v : T(0);
+  };
+  T pm = T(0), pc = T(0), pa = T(0);
+  if (RUP) {
+    pm = load_p(t0 - 1);
+    pc = load_p(t0);
+    pa = load_p(t0 + 1);
+    sp[q] = pc;
+  }
+  // b and the faces of the next row are loaded a step ahead
+  T bnx = bs[(long long)crow(t0) * nf + ic];
+  Faces fnx = load_faces(t0);
+  // the coarse column of this thread (threads I < nc) and its weighted
+  // in-row sums of the residual on fine rows 2K and 2K + 1
+  const bool restricts = i < nc;
+  T s_lo = T(0), s_mid = T(0);
+  T* __restrict__ bcs = bc + (long long)sys * Lc.N + min(i, nc - 1);
+  double rr = 0.0;
+  __syncthreads();
+  for (int t = t0; t <= t1; ++t) {
+    // the loads of the step: b and faces of row t + 1, p of row t + 2
+    const T bl = bnx;
+    bnx = bs[(long long)crow(t + 1) * nf + ic];
+    const T pn = RUP ? load_p(t + 2) : T(0);
+#pragma unroll
+    for (int d = NU; d > 0; --d) {
+      bh[d] = bh[d - 1];
+      fw[d] = fw[d - 1];
+      rd[d] = rd[d - 1];
+    }
+    fw[0] = fnx;
+    fnx = load_faces(t + 1);
+    rd[0] = rdiag(fw[0], t);
+    T bn = bl;
+    if (RUP) bn = bl - am * apply(fw[0], sp, pc, pm, pa);
+    bh[0] = row_on(t) ? bn : T(0);
+    if (RUP && t >= 2 * K0 && t < f1 && col_on) {
+      __builtin_nontemporal_store(bh[0], &bo[(long long)t * nf + i]);
+      rr += (double)bh[0] * (double)bh[0];
+    }
+    // sweep 1 on row t from x = 0; sweep m + 1 on row t - m from sweep m's
+    // output (centre row in sx[m - 1], below in xh, above just formed)
+    T xn[NU];
+    xn[0] = sweep_w(om, 0) * bh[0] * rd[0];
+#pragma unroll
+    for (int m = 1; m < NU; ++m) {
+      const T ax = apply(fw[m], sx[m - 1], xh[m - 1][0], xh[m - 1][1], xn[m - 1]);
+      xn[m] = xh[m - 1][0] + sweep_w(om, m) * (bh[m] - ax) * rd[m];
+    }
+    // the residual on row t - NU
+    const T res = bh[NU] - apply(fw[NU], sx[NU - 1], xh[NU - 1][0], xh[NU - 1][1], xn[NU - 1]);
+    // the pre-smoothed iterate: sweep NU's newest row t - NU + 1
+    const int gx = t - NU + 1;
+    if (gx >= 2 * K0 && gx < f1 && col_on) __builtin_nontemporal_store(xn[NU - 1], &xs[(long long)gx * nf + i]);
+    __syncthreads();   // every read of this step's LDS rows is done
+#pragma unroll
+    for (int m = 0; m < NU; ++m) sx[m][q] = xn[m];
+    sr[q] = res;
+    if (RUP) sp[q] = pa;   // p(t + 1), the centre row of the next step
+    __syncthreads();
+    // full weighting: this coarse column's in-row sum of fine row f = t - NU,
+    // and coarse row K = f/2 - 1 once f = 2K + 2 (weights 1/4, 1/2, 1/4 along y)
+    const int f = t - NU;
+    if (restricts && f >= 2 * K0) {
+      const T* R = sr + 1 + 2 * i;   // fine columns 2I .. 2I + 2
+      const T acc = T(0.25) * R[0] + T(0.5) * R[1] + T(0.25) * R[2];
+      if (f == 2 * K0) {
+        s_lo = acc;
+      } else if (f & 1) {
+        s_mid = acc;
+      } else {
+        const int K = f / 2 - 1;
+        bcs[(long long)K * nc] = T(0.25) * s_lo + T(0.5) * s_mid + T(0.25) * acc;
+        s_lo = acc;
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+      xh[m][1] = xh[m][0];
+      xh[m][0] = xn[m];
+    }
+    if (RUP) {
+      pm = pc;
+      pc = pa;
+      pa = pn;
+    }
+  }
+  if (RUP) {
+    write_partial_tile(tl, partial, sys, rr);
+    finish(fin, partial, sys, gridDim.x * gridDim.y);
+  }
+}
+
+// k_up2r: the up kernel of k_up2 (same inputs, outputs and arithmetic per
+// point) marching along y over whole grid rows, as k_down2r: at step t the
+// corrected iterate x_in + P x_c of row t enters and sweep m runs on row t - m
+// (the pre-smoothing weights reversed); sweep NU's row t - NU is written on
+// the owned rows [kUp2rRows s, kUp2rRows (s + 1)) of segment s, with b.x
+// when this is the finest level.  Each thread reads the coarse values under
+// its column (the coarse columns left and right of it) from the two coarse
+// rows that bracket fine row t, a coarse row ahead of their use.
+constexpr int kUp2rRows = 128;   // fine rows per workgroup
+
+template <typename T, bool VAR, int NU, bool DOT>
+__global__ __launch_bounds__(1024) void k_up2r(LevelDev<T> Lc, LevelDev<T> Lf, const T* __restrict__ xc,
+                                               const T* __restrict__ xin, const T* __restrict__ b,
+                                               T* __restrict__ xout, const T* __restrict__ shift,
+                                               const int* __restrict__ active, Sweeps<T> om,
+                                               double* __restrict__ partial, unsigned long long* __restrict__ ctr,
+                                               Fin fin) {
+  constexpr int LW = 1024 + 2;
+  __shared__ T sx[NU][LW];   // newest row of the correction and of sweeps 1 .. NU-1
+  const Tile tl = block_tile();
+  const int sys = tl.z;
+  if (!active[sys]) return;
+  count_bytes_tile(tl, ctr, (unsigned long long)Lf.N * sizeof(T) * 3 + (unsigned long long)Lc.N * sizeof(T) +
+                                   (VAR && sys == 0 ? (unsigned long long)Lf.N * sizeof(T) * 2 : 0ULL));
+  const int nf = Lf.n, nc = Lc.n;
+  const int y0 = tl.y * kUp2rRows, y1 = min(y0 + kUp2rRows, nf);   // owned fine rows
+  const int i = threadIdx.x;
+  const int NT = blockDim.x;
+  const bool col_on = i < nf;
+  const int ic = min(i, nf - 1);
+  const T sh = shift[sys];
+  const T rcon = jacobi_recip(Lf.wc * T(4) + sh);
+  const long long off = (long long)sys * Lf.N;
+  const T* __restrict__ xcs = xc + (long long)sys * Lc.N;
+  const T* __restrict__ bs = b + off;
+  const T* __restrict__ xis = xin + off;
+  T* __restrict__ xs = xout + off;
+  const int q = 1 + i;
+  if (i < 2) {
+    const int pq = i == 0 ? 0 : NT + 1;
+#pragma unroll
+    for (int m = 0; m < NU; ++m) sx[m][pq] = T(0);
+  }
+  auto row_on = [&](int r) { return col_on && r >= 0 && r < nf; };
+  auto crow = [&](int r) { return min(max(r, 0), nf - 1); };
+  struct Faces { T l, r, d, u; };
+  auto load_faces = [&](int r) {
+    Faces f{T(0), T(0), T(0), T(0)};
+    if (VAR) {
+      const int rr = crow(r);
+      const int fx = rr * (nf + 1) + ic, fy = rr * nf + ic;
+      f.l = Lf.wf0[fx];
+      f.r = Lf.wf0[fx + 1];
+      f.d = Lf.wf1[fy];
+      f.u = Lf.wf1[fy + nf];
+    }
+    return f;
+  };
+  auto rdiag = [&](const Faces& f, int r) {
+    if (!VAR) return row_on(r) ? rcon : T(0);
+    return row_on(r) ? jacobi_recip(f.l + f.r + f.d + f.u + sh) : T(0);
+  };
+  auto apply = [&](const Faces& f, const T* X, T xc_, T xd, T xu) {
+    const T xl = X[q - 1], xr = X[q + 1];
+    if (!VAR) return Lf.wc * ((xc_ - xl) + (xc_ - xr) + (xc_ - xd) + (xc_ - xu)) + sh * xc_;
+    return f.l * (xc_ - xl) + f.r * (xc_ - xr) + f.d * (xc_ - xd) + f.u * (xc_ - xu) + sh * xc_;
+  };
+  // the coarse columns of this fine column: ia (and ia + 1 for an even column)
+  const int ia = (i & 1) ? (i - 1) / 2 : i / 2 - 1;
+  // coarse row K at columns ia, ia + 1 (0 outside the coarse grid)
+  auto load_c = [&](int K, T& c0, T& c1) {
+    const int Kc_ = min(max(K, 0), nc - 1);
+    const T a0 = xcs[(long long)Kc_ * nc + min(max(ia, 0), nc - 1)];
+    const T a1 = xcs[(long long)Kc_ * nc + min(max(ia + 1, 0), nc - 1)];
+    const bool kin = K >= 0 && K < nc;
+    c0 = kin && ia >= 0 && ia < nc ? a0 : T(0);
+    c1 = kin && ia + 1 >= 0 && ia + 1 < nc ? a1 : T(0);
+  };
+  // lowest coarse row of fine row t (odd t lies on it, even t halfway to the next)
+  auto klo = [](int t) { return (t >> 1) - 1 + (t & 1); };
+  const int t0 = y0 - NU, t1 = y1 + NU - 1;
+  int Kc = klo(t0);
+  T lo0, lo1, hi0, hi1, nx0, nx1;   // coarse rows Kc, Kc + 1 and (loaded ahead) Kc + 2
+  load_c(Kc, lo0, lo1);
+  load_c(Kc + 1, hi0, hi1);
+  load_c(Kc + 2, nx0, nx1);
+  T bh[NU + 1], xh[NU][2], rd[NU + 1];
+  Faces fw[NU + 1];
+#pragma unroll
+  for (int d = 0; d <= NU; ++d) {
+    bh[d] = T(0);
+    rd[d] = T(0);
+    fw[d] = load_faces(t0 - 1 - d);
+  }
+#pragma unroll
+  for (int m = 0; m < NU; ++m) xh[m][0] = xh[m][1] = T(0);
+  T xnx = xis[(long long)crow(t0) * nf + ic], bnx = bs[(long long)crow(t0) * nf + ic];
+  Faces fnx = load_faces(t0);
+  double dot = 0.0;
+  __syncthreads();
+  for (int t = t0; t <= t1; ++t) {
+    const T xl = xnx, bl = bnx;
+    xnx = xis[(long long)crow(t + 1) * nf + ic];
+    bnx = bs[(long long)crow(t + 1) * nf + ic];
+    if (klo(t) > Kc) {   // the next coarse row pair: (Kc + 1, Kc + 2)
+      ++Kc;
+      lo0 = hi0;
+      lo1 = hi1;
+      hi0 = nx0;
+      hi1 = nx1;
+      load_c(Kc + 2, nx0, nx1);
+    }
+#pragma unroll
+    for (int d = NU; d > 0; --d) {
+      bh[d] = bh[d - 1];
+      fw[d] = fw[d - 1];
+      rd[d] = rd[d - 1];
+    }
+    fw[0] = fnx;
+    fnx = load_faces(t + 1);
+    rd[0] = rdiag(fw[0], t);
+    // stage 0 on row t: x_in + P x_c (multilinear, the expressions of k_up2)
+    const bool on = row_on(t);
+    T v;
+    if (i & 1) {
+      v = (t & 1) ? lo0 : T(0.5) * (lo0 + hi0);
+    } else {
+      v = (t & 1) ? T(0.5) * (lo0 + lo1) : T(0.25) * (lo0 + lo1 + hi0 + hi1);
+    }
+    bh[0] = on ? bl : T(0);
+    T xn[NU + 1];
+    xn[0] = on ? xl + v : T(0);
+    // sweep m on row t - m from stage m - 1's output (centre row in
+    // sx[m - 1], below in xh, above just formed)
+#pragma unroll
+    for (int m = 1; m <= NU; ++m) {
+      const T ax = apply(fw[m], sx[m - 1], xh[m - 1][0], xh[m - 1][1], xn[m - 1]);
+      xn[m] = xh[m - 1][0] + sweep_w(om, NU - m) * (bh[m] - ax) * rd[m];
+    }
+    const int g = t - NU;
+    if (g >= y0 && g < y1 && col_on) {
+      __builtin_nontemporal_store(xn[NU], &xs[(long long)g * nf + i]);
+      if (DOT) dot += (double)bh[NU] * (double)xn[NU];
+    }
+    __syncthreads();   // every read of this step's LDS rows is done
+#pragma unroll
+    for (int m = 0; m < NU; ++m) sx[m][q] = xn[m];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+      xh[m][1] = xh[m][0];
+      xh[m][0] = xn[m];
+    }
   }
   if (DOT) {
     write_partial_tile(tl, partial, sys, dot);
@@ -2645,12 +3011,26 @@ static inline dim3 flat_grid(long long N, int nsys) {
 // Calls f(std::integral_constant<int, v>) for the runtime variant tv.
 template <typename F>
 static inline void with_tile(int tv, F&& f) {
-  static_assert(kTileVariants == 3, "one case per variant");
+  static_assert(kTileVariants == 4, "one case per variant");
   switch (tile_variant(tv)) {
     case 1: f(std::integral_constant<int, 1>{}); break;
     case 2: f(std::integral_constant<int, 2>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
     default: f(std::integral_constant<int, 0>{}); break;
   }
+}
+
+// whether the down / up kernel of a level of n points per axis runs k_down2r /
+// k_up2r in variant tv
+static inline bool down_rows(int dim, int n, int tv) {
+  return dim == 2 && tile_variant(tv) == kRowsVariant && n <= kRowsMaxN;
+}
+static inline bool up_rows(int dim, int n, int tv) { return down_rows(dim, n, tv); }
+static inline int rows_threads(int n) { return ((n + 1 + 63) / 64) * 64; }
+
+bool tile_variant_distinct(int kind, int dim, int n, int tv) {
+  if (tile_variant(tv) != kRowsVariant) return true;
+  return kind != 0 && down_rows(dim, n, tv);
 }
 
 #define BURA_DISPATCH_DV(dim, var, KERNEL, ...)        \
@@ -2841,6 +3221,21 @@ bool Launch<T>::fused_down(int dim, bool var, int nu, const LevelDev<T>& Lf, con
     return true;
   }
   if (dim != 2 || nu < 1 || nu > 3) return false;
+  if (down_rows(dim, Lf.n, tv)) {
+    const dim3 g(1, (Lc.n + kDown2rKy - 1) / kDown2rKy, nsys), blk(rows_threads(Lf.n));
+#define K_DR0(V, NU_, R_)                                                                                     \
+  hipLaunchKernelGGL((k_down2r<T, V, NU_, R_>), g, blk, 0, st, Lf, Lc, b, xout, bc, shift, active, om, ctr, p, \
+                     alpha, bout, partial, fin)
+#define K_DR(V, NU_) do { if (rup) K_DR0(V, NU_, true); else K_DR0(V, NU_, false); } while (0)
+    if (var) {
+      if (nu == 1) K_DR(true, 1); else if (nu == 2) K_DR(true, 2); else K_DR(true, 3);
+    } else {
+      if (nu == 1) K_DR(false, 1); else if (nu == 2) K_DR(false, 2); else K_DR(false, 3);
+    }
+#undef K_DR
+#undef K_DR0
+    return true;
+  }
   with_tile(tv, [&](auto v) {
     constexpr int CX = kDownTile[decltype(v)::value][0], CY = kDownTile[decltype(v)::value][1];
     const dim3 g((Lc.n + CX - 1) / CX, (Lc.n + CY - 1) / CY, nsys), blk(256);
@@ -2863,6 +3258,7 @@ int down_blocks(int dim, int n, int tv) {
   const int nc = (n - 1) / 2;
   if (dim == 3)
     return ((nc + kD3Cx - 1) / kD3Cx) * ((nc + kD3Cy - 1) / kD3Cy) * ((nc + kD3Kz - 1) / kD3Kz);
+  if (down_rows(dim, n, tv)) return (nc + kDown2rKy - 1) / kDown2rKy;
   const int cx = kDownTile[tile_variant(tv)][0], cy = kDownTile[tile_variant(tv)][1];
   return ((nc + cx - 1) / cx) * ((nc + cy - 1) / cy);
 }
@@ -2897,6 +3293,21 @@ bool Launch<T>::fused_up(int dim, bool var, int nu, const LevelDev<T>& Lc, const
     return true;
   }
   if (dim != 2 || nu < 1 || nu > 3) return false;
+  if (up_rows(dim, Lf.n, tv)) {
+    const dim3 g(1, (Lf.n + kUp2rRows - 1) / kUp2rRows, nsys), blk(rows_threads(Lf.n));
+#define K_UR0(V, NU_, D_)                                                                                        \
+  hipLaunchKernelGGL((k_up2r<T, V, NU_, D_>), g, blk, 0, st, Lc, Lf, xc, xin, b, xout, shift, active, om, partial, \
+                     ctr, fin)
+#define K_UR(V, NU_) do { if (dot) K_UR0(V, NU_, true); else K_UR0(V, NU_, false); } while (0)
+    if (var) {
+      if (nu == 1) K_UR(true, 1); else if (nu == 2) K_UR(true, 2); else K_UR(true, 3);
+    } else {
+      if (nu == 1) K_UR(false, 1); else if (nu == 2) K_UR(false, 2); else K_UR(false, 3);
+    }
+#undef K_UR
+#undef K_UR0
+    return true;
+  }
   with_tile(tv, [&](auto v) {
     constexpr int OX = kUpTile[decltype(v)::value][0], OY = kUpTile[decltype(v)::value][1];
     const dim3 g((Lf.n + OX - 1) / OX, (Lf.n + OY - 1) / OY, nsys), blk(256);
@@ -2917,6 +3328,7 @@ bool Launch<T>::fused_up(int dim, bool var, int nu, const LevelDev<T>& Lc, const
 
 int up_blocks(int dim, int n, int tv) {
   if (dim == 3) return ((n + kU3Ox - 1) / kU3Ox) * ((n + kU3Oy - 1) / kU3Oy) * ((n + kU3Fz - 1) / kU3Fz);
+  if (up_rows(dim, n, tv)) return (n + kUp2rRows - 1) / kUp2rRows;
   const int ox = kUpTile[tile_variant(tv)][0], oy = kUpTile[tile_variant(tv)][1];
   return ((n + ox - 1) / ox) * ((n + oy - 1) / oy);
 }
