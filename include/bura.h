@@ -359,21 +359,24 @@ int bura_plan_apply(bura_plan_t plan, double shift, const double* x_dev, double*
  * computes the same value at every grid point up to rounding (the grouping of
  * the per-block partial sums of the PCG dot products differs, and variant 3
  * of the down kernel sums the full weighting in another order), so results
- * of two variants agree to rounding, not bit for bit.  Variant 3 of the down
- * and up kernels walks whole grid rows (levels of up to 1023 points per
- * axis; a larger level runs variant 0); of the stencil product it is the
- * same shape as variant 0. */
+ * of two variants agree to rounding, not bit for bit.  Variant 3 walks
+ * whole grid rows (levels of up to 1023 points per axis; a larger level runs
+ * variant 0). */
 #define BURA_TILE_VARIANTS 4
 
 /* The variants a 2D plan launches: out[0] for the stencil product, out[1 + 2l]
  * and out[2 + 2l] for the fused down and up kernels of level l, for each of
  * the plan's levels with fused kernels; *len = 1 + 2 * (those levels) (0 for
  * a 3D plan, whose kernels have one shape).  With out == NULL only *len is
- * written.  BURA_EINVAL if max_len < *len.  Untuned, every entry is 0 except
- * the down kernel of a level whose default tile (64 x 6 coarse points) would
- * give one launch fewer than 1024 workgroups over the systems that share it
- * (all of them; one pole's right-hand sides in the per-pole schedule; the
- * largest stage of a sequential form): that level takes variant 1 (32 x 8). */
+ * written.  BURA_EINVAL if max_len < *len.  Untuned, with nsys the systems
+ * that share a launch (all of them; one pole's right-hand sides in the
+ * per-pole schedule; the largest stage of a sequential form): a kernel of a
+ * level of 255 to 1023 points per axis takes variant 3 (whole rows) when
+ * nsys times its row segments per system is at least 1024 (segments of 128
+ * fine rows for the stencil product and the up kernel, of 64 coarse rows for
+ * the down kernel); otherwise every entry is 0 except the down kernel of a
+ * level whose default tile (64 x 6 coarse points) would give one launch fewer
+ * than 1024 workgroups: that level takes variant 1 (32 x 8). */
 int bura_plan_tiles(bura_plan_t plan, int* out, int max_len, int* len);
 
 /* Set the variants (layout as bura_plan_tiles, len must equal its *len, each

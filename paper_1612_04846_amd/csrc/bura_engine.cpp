@@ -1493,13 +1493,16 @@ long long launch_systems(const bura_plan_t P) {
   return P->opts.schedule == BURA_PER_POLE ? R : (long long)P->S;
 }
 
-// The default launch shapes: variant 0, except the down kernel on levels
-// whose launches would make too few workgroups with it (default_down_tile).
+// The default launch shapes (default_spmv_tile, default_down_tile,
+// default_up_tile): the row-marching kernels on large levels whose launches
+// make enough workgroups with them, else the tiles.
 void set_default_tiles(bura_plan_t P) {
   const long long ns = launch_systems(P);
-  P->tile_spmv = 0;
-  for (size_t l = 0; l < P->tile_down.size(); ++l) P->tile_down[l] = default_down_tile(P->dim, P->lev[l].n, ns);
-  std::fill(P->tile_up.begin(), P->tile_up.end(), 0);
+  P->tile_spmv = default_spmv_tile(P->dim, P->n, ns);
+  for (size_t l = 0; l < P->tile_down.size(); ++l) {
+    P->tile_down[l] = default_down_tile(P->dim, P->lev[l].n, ns);
+    P->tile_up[l] = default_up_tile(P->dim, P->lev[l].n, ns);
+  }
 }
 
 int tune_tiles(bura_plan_t P) {

@@ -195,7 +195,10 @@ int up_blocks(int dim, int n, int tv);
 int down_blocks(int dim, int n, int tv);
 // workgroups a launch needs to keep every CU of the chip busy (4 per CU)
 constexpr long long kFillBlocks = 4 * 256;
+// default launch-shape variants of a level of n points per axis, nsys systems per launch
 int default_down_tile(int dim, int n, long long nsys);
+int default_up_tile(int dim, int n, long long nsys);
+int default_spmv_tile(int dim, int n, long long nsys);
 int spmv_blocks(int dim, int n, int tv);
 // false where launch-shape variant tv of a kernel kind (0 stencil product, 1 down,
 // 2 up) on a level of n points per axis runs the same shape as another variant

@@ -1064,14 +1064,23 @@ struct RegionFaces {
 // along y).  The down kernel's default region is 133 fine columns wide for
 // the same reason (7 % faster than 69 columns); the up kernel stays at 64
 // fine columns, where it is faster than at 128.
-// Variant 3 of the down and up kernels is k_down2r / k_up2r (whole rows,
-// levels of up to 1023 points per axis; a larger level runs variant 0 in its
-// place); of the stencil product it is variant 0 again (the tuner skips it).
+// Variant 3 of the stencil product and of the down and up kernels is
+// k_spmv_r2 / k_down2r / k_up2r (whole rows, levels of up to 1023 points per
+// axis; a larger level runs variant 0 in its place, and the tuner skips it).
 constexpr int kDownTile[kTileVariants][2] = {{64, 6}, {32, 8}, {64, 8}, {64, 6}};
 constexpr int kUpTile[kTileVariants][2] = {{64, 16}, {64, 8}, {64, 24}, {64, 16}};
 constexpr int kSpmvTile[kTileVariants][2] = {{4, 128}, {2, 64}, {8, 128}, {4, 128}};
 constexpr int kRowsVariant = 3;
 constexpr int kRowsMaxN = 1023;
+// whether the stencil product / down / up kernel of a level of n points per
+// axis runs k_spmv_r2 / k_down2r / k_up2r in variant tv, and their threads
+// per workgroup (one per column and at least one past the grid, in waves)
+static inline bool down_rows(int dim, int n, int tv) {
+  return dim == 2 && tile_variant(tv) == kRowsVariant && n <= kRowsMaxN;
+}
+static inline bool up_rows(int dim, int n, int tv) { return down_rows(dim, n, tv); }
+static inline bool spmv_rows(int dim, int n, int tv) { return down_rows(dim, n, tv); }
+static inline int rows_threads(int n) { return ((n + 1 + 63) / 64) * 64; }
 
 // Reciprocal of a Jacobi diagonal, formed once per point and kernel: the sweeps
 // multiply by it.  FP32: the hardware reciprocal (within 1 ulp); FP64: IEEE
@@ -2457,6 +2466,107 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p2(LevelDev<T> L, const T* __re
   finish(fin, partial, sys, gridDim.x * gridDim.y);
 }
 
+// Row-marching version of k_spmv_p2 (launch-shape variant 3): one thread per
+// grid column, a workgroup walks kSpmvRows rows; p_new of the rows below, at
+// and above the current one stays in registers and the current row's p_new
+// is in LDS for the left/right neighbours, so z and p_old are read once per
+// point (plus one row above and below a segment).  Same values per point as
+// k_spmv_p2; two barriers per row.
+constexpr int kSpmvRows = 128;
+
+template <typename T, bool VAR, bool XUP, bool WQ>
+__global__ __launch_bounds__(1024) void k_spmv_r2(LevelDev<T> L, const T* __restrict__ z, const T* __restrict__ pold,
+                                                  T* __restrict__ pnew, T* __restrict__ q,
+                                                  const double* __restrict__ beta, const T* __restrict__ shift,
+                                                  const int* __restrict__ active, double* __restrict__ partial,
+                                                  unsigned long long* __restrict__ ctr, Fin fin,
+                                                  T* __restrict__ x, const double* __restrict__ alpha) {
+  constexpr int LW = 1024 + 2;
+  __shared__ T sp[LW];   // p_new of the current row, zero pads at columns -1 and blockDim.x
+  const Tile tl = block_tile();
+  const int sys = tl.z;
+  if (!active[sys]) return;
+  const T bt = (T)beta[sys];
+  const T ap = XUP ? (T)alpha[sys] : T(0);
+  count_bytes_tile(tl, ctr, (unsigned long long)L.N * sizeof(T) *
+                                ((bt == T(0) ? 3 : 4) - (WQ ? 0 : 1) + (XUP && ap != T(0) ? 2 : 0) +
+                                 (VAR && sys == 0 ? 2 : 0)));
+  const int n = L.n;
+  const int i = threadIdx.x, NT = blockDim.x;
+  const int j0 = tl.y * kSpmvRows, j1 = min(j0 + kSpmvRows, n);
+  const bool col_on = i < n;
+  const int ic = min(i, n - 1);
+  const int qi = 1 + i;
+  const long long off = (long long)sys * L.N;
+  const T* __restrict__ zs = z + off;
+  // beta = 0 (first iteration): p_old may hold anything, so read z in its place
+  const T* __restrict__ pe = bt == T(0) ? zs : pold + off;
+  const T s = shift[sys];
+  if (i < 2) sp[i == 0 ? 0 : NT + 1] = T(0);
+  auto crow = [&](int r) { return min(max(r, 0), n - 1); };
+  // 1 on the grid, 0 off it: a factor rather than a select (a select lets the
+  // compiler move a load into a branch and wait there for every load in flight)
+  auto on_f = [&](int r) { return (col_on && r >= 0 && r < n) ? T(1) : T(0); };
+  // p_new below and at row j0, p_old at row j0, and z, p_old of row j0 + 1 (a row ahead)
+  T dn, c, pc, za_n, ea_n;
+  {
+    const int rb = crow(j0 - 1) * n + ic, rc = j0 * n + ic, ra = crow(j0 + 1) * n + ic;
+    const T zb = zs[rb], eb = pe[rb], zc = zs[rc], ec = pe[rc];
+    za_n = zs[ra];
+    ea_n = pe[ra];
+    dn = (zb + bt * eb) * on_f(j0 - 1);
+    c = (zc + bt * ec) * on_f(j0);
+    pc = ec;
+  }
+  sp[qi] = c;
+  double dot = 0.0;
+  __syncthreads();
+  auto walk = [&](auto upd_c) {
+    constexpr bool UPD = XUP && decltype(upd_c)::value;
+    for (int j = j0; j < j1; ++j) {
+      const int row = j * n;   // 2D grids: fewer than 2^31 points
+      const T za = za_n, ea = ea_n;
+      {
+        const int r2 = crow(j + 2) * n + ic;
+        za_n = zs[r2];
+        ea_n = pe[r2];
+      }
+      const T xv = UPD ? x[off + row + ic] : T(0);
+      T fl = T(0), fr = T(0), fd = T(0), fu = T(0);
+      if (VAR) {
+        const int fx = j * (n + 1) + ic, fy = row + ic;
+        fl = L.wf0[fx];
+        fr = L.wf0[fx + 1];
+        fd = L.wf1[fy];
+        fu = L.wf1[fy + n];
+      }
+      const T up = (za + bt * ea) * on_f(j + 1);
+      const T lv = sp[qi - 1], rv = sp[qi + 1];
+      T qv;
+      if (!VAR) qv = L.wc * ((c - lv) + (c - rv) + (c - dn) + (c - up)) + s * c;
+      else qv = fl * (c - lv) + fr * (c - rv) + fd * (c - dn) + fu * (c - up) + s * c;
+      if (col_on) {
+        const long long g = off + row + i;
+        __builtin_nontemporal_store(c, &pnew[g]);
+        if (WQ) __builtin_nontemporal_store(qv, &q[g]);
+        // the deferred update uses p_old = pc (pe is p_old whenever alpha != 0)
+        if (UPD) __builtin_nontemporal_store(xv + ap * pc, &x[g]);
+        dot += (double)c * (double)qv;
+      }
+      __syncthreads();   // every read of this row's p_new is done
+      sp[qi] = up;
+      __syncthreads();
+      dn = c;
+      c = up;
+      pc = ea;
+    }
+  };
+  if (XUP && ap != T(0)) walk(std::true_type{});
+  else walk(std::false_type{});
+  write_partial_tile(tl, partial, sys, dot);
+  finish(fin, partial, sys, gridDim.x * gridDim.y);
+}
+
 // --------------------------------------------------------------------------
 constexpr int kFlatItems = 4;
 
@@ -2994,6 +3104,7 @@ static inline dim3 spmv2_grid(int n, int nsys, int tv) {
 
 int spmv_blocks(int dim, int n, int tv) {
   if (dim != 2) return stencil_blocks(dim, n);
+  if (spmv_rows(dim, n, tv)) return (n + kSpmvRows - 1) / kSpmvRows;
   const dim3 g = spmv2_grid(n, 1, tv);
   return (int)(g.x * g.y);
 }
@@ -3020,17 +3131,11 @@ static inline void with_tile(int tv, F&& f) {
   }
 }
 
-// whether the down / up kernel of a level of n points per axis runs k_down2r /
-// k_up2r in variant tv
-static inline bool down_rows(int dim, int n, int tv) {
-  return dim == 2 && tile_variant(tv) == kRowsVariant && n <= kRowsMaxN;
-}
-static inline bool up_rows(int dim, int n, int tv) { return down_rows(dim, n, tv); }
-static inline int rows_threads(int n) { return ((n + 1 + 63) / 64) * 64; }
 
 bool tile_variant_distinct(int kind, int dim, int n, int tv) {
+  (void)kind;
   if (tile_variant(tv) != kRowsVariant) return true;
-  return kind != 0 && down_rows(dim, n, tv);
+  return down_rows(dim, n, tv);
 }
 
 #define BURA_DISPATCH_DV(dim, var, KERNEL, ...)        \
@@ -3162,6 +3267,19 @@ void Launch<T>::spmv_p(int dim, bool var, const LevelDev<T>& L, const T* z, cons
                        const double* beta, const T* shift, const int* active, double* partial, int nsys,
                        hipStream_t st, unsigned long long* ctr, Fin fin, T* x, const double* alpha, int tv) {
   const bool xup = x != nullptr;
+  if (dim == 2 && spmv_rows(dim, L.n, tv)) {
+    const dim3 g(1, (L.n + kSpmvRows - 1) / kSpmvRows, nsys), blk(rows_threads(L.n));
+#define K_SR(V, X_, Q_) \
+  hipLaunchKernelGGL((k_spmv_r2<T, V, X_, Q_>), g, blk, 0, st, L, z, pold, pnew, q, beta, shift, active, partial, \
+                     ctr, fin, x, alpha)
+    if (var) {
+      if (!q) K_SR(true, true, false); else if (xup) K_SR(true, true, true); else K_SR(true, false, true);
+    } else {
+      if (!q) K_SR(false, true, false); else if (xup) K_SR(false, true, true); else K_SR(false, false, true);
+    }
+#undef K_SR
+    return;
+  }
   if (dim == 2) {
     const dim3 g2 = spmv2_grid(L.n, nsys, tv);
     with_tile(tv, [&](auto v) {
@@ -3263,14 +3381,35 @@ int down_blocks(int dim, int n, int tv) {
   return ((nc + cx - 1) / cx) * ((nc + cy - 1) / cy);
 }
 
-// The down kernel's default shape on a level of n points per axis when nsys
-// systems share each launch.  The 64-column tile (variant 0) fetches fewer
-// halo lines but makes fewer workgroups: below about four per CU (one-system
-// solves, coarse levels) the 32 x 8 tile (variant 1) keeps more of the chip
-// busy and is faster.
+// The default shapes on a level of n points per axis when nsys systems share
+// each launch.  The row-marching kernels (variant 3) fetch each point about
+// once where the tiles fetch 1.3 - 1.8 times, but make one workgroup per
+// system and segment of rows: on levels of at least kRowsMinN points per axis
+// whose launches still make kFillBlocks of them they are the default (511^2,
+// 2048 systems: stencil product 1286 -> 1105 us, down 1684 -> 1265, up 1351
+// -> 811, the solve 107 -> 85 ms); with fewer systems (1023^2, 30 systems:
+// 240 workgroups) or on small levels they are slower.  Otherwise the
+// 64-column down tile (variant 0) fetches fewer halo lines but makes fewer
+// workgroups than the 32 x 8 tile (variant 1): below about four per CU
+// (one-system solves, coarse levels) variant 1 keeps more of the chip busy.
+constexpr int kRowsMinN = 255;
+
+static inline bool rows_default(int dim, int n, long long nsys, int blocks) {
+  return dim == 2 && n >= kRowsMinN && n <= kRowsMaxN && nsys * blocks >= kFillBlocks;
+}
+
 int default_down_tile(int dim, int n, long long nsys) {
   if (dim != 2) return 0;
+  if (rows_default(dim, n, nsys, down_blocks(dim, n, kRowsVariant))) return kRowsVariant;
   return nsys * down_blocks(dim, n, 0) >= kFillBlocks ? 0 : 1;
+}
+
+int default_up_tile(int dim, int n, long long nsys) {
+  return rows_default(dim, n, nsys, up_blocks(dim, n, kRowsVariant)) ? kRowsVariant : 0;
+}
+
+int default_spmv_tile(int dim, int n, long long nsys) {
+  return rows_default(dim, n, nsys, spmv_blocks(dim, n, kRowsVariant)) ? kRowsVariant : 0;
 }
 
 template <typename T>

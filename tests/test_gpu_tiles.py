@@ -50,15 +50,24 @@ def _reference(n, var, alpha, k, F, tag):
     return coeff, shifted.bura_by_solves(A, b.c_f64, b.d_f64, F)
 
 
+def _rows(n, nsys, segments):
+    return 255 <= n <= 1023 and nsys * segments >= 1024
+
+
 def _default_tiles(n, nsys, levels):
-    """The documented default: variant 0 everywhere except the down kernel on
-    levels whose 64 x 6 launch (coarse points per workgroup) would make fewer
-    than 1024 workgroups over all systems, which take the 32 x 8 tile (1)."""
-    out = [0]
+    """The documented default: the row-marching variant 3 for a kernel of a
+    level of 255..1023 points per axis whose launch makes at least 1024 row
+    segments over all systems (128 fine rows for the stencil product and the
+    up kernel, 64 coarse rows for the down kernel); otherwise variant 0,
+    except the down kernel on levels whose 64 x 6 launch (coarse points per
+    workgroup) would make fewer than 1024 workgroups, which take the 32 x 8
+    tile (1)."""
+    out = [3 if _rows(n, nsys, -(-n // 128)) else 0]
     for _ in range(levels):
         nc = (n - 1) // 2
         blocks = -(-nc // 64) * -(-nc // 6)
-        out += [0 if nsys * blocks >= 1024 else 1, 0]
+        down = 3 if _rows(n, nsys, -(-nc // 64)) else (0 if nsys * blocks >= 1024 else 1)
+        out += [down, 3 if _rows(n, nsys, -(-n // 128)) else 0]
         n = nc
     return out
 
