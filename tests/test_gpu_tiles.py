@@ -125,6 +125,36 @@ def test_every_tile_variant_matches_oracle(n, var, prec, alpha, k):
     plan.close()
 
 
+def test_wide_launch_defaults_to_rows_and_matches_oracle():
+    """512 systems of a 255^2 grid (8 poles x 64 right-hand sides): the stencil
+    product and the fine down and up kernels default to the row-marching
+    variant 3 (2 row segments per system, 1024 per launch), the coarser levels
+    to the tiles.  The solve matches the spectral oracle for every right-hand
+    side, and the all-tiles shape to rounding."""
+    from oracle import spectral
+    B = _B()
+    n, alpha, k, R = 255, 0.5, 7, 64
+    b = oracle_bura(alpha, k)
+    F = synth.normal_rhs(n, 2, nrhs=R, tag=431)
+    ref = spectral.bura_spectral(F, 2, b.c_f64, b.d_f64)
+    plan = B.Plan(2, n, weights=b.c_f64, shifts=[-x for x in b.d_f64], nrhs_max=R, precision=B.BURA_MIXED,
+                  tol=1e-12)
+    try:
+        t = plan.tiles
+        print("default tiles at 512 systems:", t)
+        assert t == _default_tiles(n, R * (k + 1), len(t) // 2)
+        assert t[:3] == [3, 3, 3] and all(v != 3 for v in t[3:])
+        u_rows = _host(plan.solve(_dev(F)).u)
+        err = _rel2(u_rows, ref)
+        plan.tiles = [0] * len(t)
+        u_tiles = _host(plan.solve(_dev(F)).u)
+        print(f"rows rel2 vs oracle {err:.2e}; rows vs tiles {_rel2(u_rows, u_tiles):.2e}")
+        assert err <= 1e-9
+        assert _rel2(u_rows, u_tiles) <= 1e-9
+    finally:
+        plan.close()
+
+
 def test_tuner_choice_is_valid_cached_and_correct():
     B = _B()
     n, alpha, k = 255, 0.6, 7
