@@ -1044,7 +1044,7 @@ int mixed_outer_loop(bura_plan_t P, const double* f, int nrhs, size_t sys0, int 
     }
     {
       ProfScope ps(P, BURA_K_OTHER);
-      launch_scalars(OP_OUTER, P->partial, residual_blocks(P->dim, P->n), nsys, S, P->run_tol, P->opts.max_outer,
+      launch_scalars(OP_OUTER, P->partial, residual_blocks(P->dim, P->n, nsys), nsys, S, P->run_tol, P->opts.max_outer,
                      st);
     }
   }
@@ -1100,7 +1100,7 @@ int resume_batch_mixed(bura_plan_t P, const double* f, int nrhs, size_t sys0, in
   }
   {
     ProfScope ps(P, BURA_K_OTHER);
-    launch_scalars(OP_OUTER, P->partial, residual_blocks(P->dim, P->n), nsys, S, P->run_tol, P->opts.max_outer,
+    launch_scalars(OP_OUTER, P->partial, residual_blocks(P->dim, P->n, nsys), nsys, S, P->run_tol, P->opts.max_outer,
                    st);
   }
   return mixed_outer_loop(P, f, nrhs, sys0, nsys);
@@ -1915,7 +1915,7 @@ int serve_step(bura_plan_t P) {
   }
   {
     ProfScope ps(P, BURA_K_OTHER);
-    launch_scalars(OP_OUTER, P->partial, residual_blocks(P->dim, P->n), S, Ss, P->run_tol, P->opts.max_outer, st);
+    launch_scalars(OP_OUTER, P->partial, residual_blocks(P->dim, P->n, S), S, Ss, P->run_tol, P->opts.max_outer, st);
   }
   a = count_active(P, P->st.active64, 0, S);
   return a < 0 ? BURA_EDEVICE : a;

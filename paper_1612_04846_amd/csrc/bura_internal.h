@@ -203,7 +203,8 @@ int spmv_blocks(int dim, int n, int tv);
 // false where launch-shape variant tv of a kernel kind (0 stencil product, 1 down,
 // 2 up) on a level of n points per axis runs the same shape as another variant
 bool tile_variant_distinct(int kind, int dim, int n, int tv);
-int residual_blocks(int dim, int n);   // blocks per system of the FP64 residual (refinement step)
+// blocks per system of the FP64 residual (refinement step) of a batch of nsys systems
+int residual_blocks(int dim, int n, long long nsys);
 int max_partial_blocks(int dim, int n, long long N);   // over every launch shape
 
 // Continuous batching on a slot plan (BURA_MIXED): right-hand sides join and

@@ -201,6 +201,7 @@ __device__ __forceinline__ void count_bytes_tile(const Tile& tl, unsigned long l
   if (tl.x == 0 && tl.y == 0) atomicAdd(ctr, b);
 }
 
+
 // (A_l + s I) x at interior point (i,j,k), flux form sum_f w_f (x_c - x_nb) + s x_c.
 // Also returns the diagonal through *dg when dg != nullptr.
 template <typename T, int DIM, bool VAR>
@@ -1072,6 +1073,28 @@ constexpr int kUpTile[kTileVariants][2] = {{64, 16}, {64, 8}, {64, 24}, {64, 16}
 constexpr int kSpmvTile[kTileVariants][2] = {{4, 128}, {2, 64}, {8, 128}, {4, 128}};
 constexpr int kRowsVariant = 3;
 constexpr int kRowsMaxN = 1023;
+constexpr int kRowsMinN = 255;   // smallest level the row kernels are the default on
+// A row kernel's workgroup: its system and row segment, from a launch grid of
+// (1, segments, systems): the segments of a system run next to each other.
+// Systems first, (systems, segments), so that workgroups running at the same
+// time share a segment's face weights in the L2, made the FP64 residual 1 %
+// faster but the FP32 row kernels 1 - 2 % slower (511^2, 2048 systems).
+struct RowTile {
+  int sys, seg, nseg;
+};
+__device__ __forceinline__ RowTile row_tile() {
+  RowTile r;
+  r.sys = blockIdx.z;
+  r.seg = blockIdx.y;
+  r.nseg = gridDim.y;
+  return r;
+}
+static inline dim3 rows_grid(int nseg, int nsys) { return dim3(1, nseg, nsys); }
+// profiling: the workgroup of segment 0 of each system counts its bytes
+__device__ __forceinline__ void count_bytes_row(const RowTile& rt, unsigned long long* ctr, unsigned long long b) {
+  if (ctr == nullptr || threadIdx.x != 0 || rt.seg != 0) return;
+  atomicAdd(ctr, b);
+}
 // whether the stencil product / down / up kernel of a level of n points per
 // axis runs k_spmv_r2 / k_down2r / k_up2r in variant tv, and their threads
 // per workgroup (one per column and at least one past the grid, in waves)
@@ -1479,14 +1502,14 @@ __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc,
   __shared__ T sx[NU][LW];       // newest row of each sweep's output
   __shared__ T sr[LW];           // residual row
   __shared__ T sp[RUP ? LW : 1]; // p of the row being updated (RUP)
-  const Tile tl = block_tile();
-  const int sys = tl.z;
+  const RowTile rt = row_tile();
+  const int sys = rt.sys;
   if (!active[sys]) return;
-  count_bytes_tile(tl, ctr, (unsigned long long)Lf.N * sizeof(T) * (RUP ? 4 : 2) +
+  count_bytes_row(rt, ctr, (unsigned long long)Lf.N * sizeof(T) * (RUP ? 4 : 2) +
                                    (unsigned long long)Lc.N * sizeof(T) +
                                    (VAR && sys == 0 ? (unsigned long long)Lf.N * sizeof(T) * 2 : 0ULL));
   const int nf = Lf.n, nc = Lc.n;
-  const int K0 = tl.y * kDown2rKy, K1 = min(K0 + kDown2rKy, nc);
+  const int K0 = rt.seg * kDown2rKy, K1 = min(K0 + kDown2rKy, nc);
   const int f1 = K1 == nc ? nf : 2 * K1;   // owned fine rows [2 K0, f1) (the last segment: the top one too)
   const int i = threadIdx.x;               // this thread's column
   const int NT = blockDim.x;
@@ -1642,8 +1665,8 @@ __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc,
     }
   }
   if (RUP) {
-    write_partial_tile(tl, partial, sys, rr);
-    finish(fin, partial, sys, gridDim.x * gridDim.y);
+    write_partial(partial, sys, rr, rt.seg, rt.nseg);
+    finish(fin, partial, sys, rt.nseg);
   }
 }
 
@@ -1666,13 +1689,13 @@ __global__ __launch_bounds__(1024) void k_up2r(LevelDev<T> Lc, LevelDev<T> Lf, c
                                                Fin fin) {
   constexpr int LW = 1024 + 2;
   __shared__ T sx[NU][LW];   // newest row of the correction and of sweeps 1 .. NU-1
-  const Tile tl = block_tile();
-  const int sys = tl.z;
+  const RowTile rt = row_tile();
+  const int sys = rt.sys;
   if (!active[sys]) return;
-  count_bytes_tile(tl, ctr, (unsigned long long)Lf.N * sizeof(T) * 3 + (unsigned long long)Lc.N * sizeof(T) +
+  count_bytes_row(rt, ctr, (unsigned long long)Lf.N * sizeof(T) * 3 + (unsigned long long)Lc.N * sizeof(T) +
                                    (VAR && sys == 0 ? (unsigned long long)Lf.N * sizeof(T) * 2 : 0ULL));
   const int nf = Lf.n, nc = Lc.n;
-  const int y0 = tl.y * kUp2rRows, y1 = min(y0 + kUp2rRows, nf);   // owned fine rows
+  const int y0 = rt.seg * kUp2rRows, y1 = min(y0 + kUp2rRows, nf);   // owned fine rows
   const int i = threadIdx.x;
   const int NT = blockDim.x;
   const bool col_on = i < nf;
@@ -1802,8 +1825,8 @@ __global__ __launch_bounds__(1024) void k_up2r(LevelDev<T> Lc, LevelDev<T> Lf, c
     }
   }
   if (DOT) {
-    write_partial_tile(tl, partial, sys, dot);
-    finish(fin, partial, sys, gridDim.x * gridDim.y);
+    write_partial(partial, sys, dot, rt.seg, rt.nseg);
+    finish(fin, partial, sys, rt.nseg);
   }
 }
 
@@ -2483,17 +2506,17 @@ __global__ __launch_bounds__(1024) void k_spmv_r2(LevelDev<T> L, const T* __rest
                                                   T* __restrict__ x, const double* __restrict__ alpha) {
   constexpr int LW = 1024 + 2;
   __shared__ T sp[LW];   // p_new of the current row, zero pads at columns -1 and blockDim.x
-  const Tile tl = block_tile();
-  const int sys = tl.z;
+  const RowTile rt = row_tile();
+  const int sys = rt.sys;
   if (!active[sys]) return;
   const T bt = (T)beta[sys];
   const T ap = XUP ? (T)alpha[sys] : T(0);
-  count_bytes_tile(tl, ctr, (unsigned long long)L.N * sizeof(T) *
+  count_bytes_row(rt, ctr, (unsigned long long)L.N * sizeof(T) *
                                 ((bt == T(0) ? 3 : 4) - (WQ ? 0 : 1) + (XUP && ap != T(0) ? 2 : 0) +
                                  (VAR && sys == 0 ? 2 : 0)));
   const int n = L.n;
   const int i = threadIdx.x, NT = blockDim.x;
-  const int j0 = tl.y * kSpmvRows, j1 = min(j0 + kSpmvRows, n);
+  const int j0 = rt.seg * kSpmvRows, j1 = min(j0 + kSpmvRows, n);
   const bool col_on = i < n;
   const int ic = min(i, n - 1);
   const int qi = 1 + i;
@@ -2563,8 +2586,8 @@ __global__ __launch_bounds__(1024) void k_spmv_r2(LevelDev<T> L, const T* __rest
   };
   if (XUP && ap != T(0)) walk(std::true_type{});
   else walk(std::false_type{});
-  write_partial_tile(tl, partial, sys, dot);
-  finish(fin, partial, sys, gridDim.x * gridDim.y);
+  write_partial(partial, sys, dot, rt.seg, rt.nseg);
+  finish(fin, partial, sys, rt.nseg);
 }
 
 // --------------------------------------------------------------------------
@@ -2752,6 +2775,88 @@ __global__ __launch_bounds__(kBlock) void k_residual64_2(LevelDev<double> L, con
     }
   }
   write_partial_tile(tl, partial, sys, rr);
+}
+
+// Row-marching version of k_residual64_2 for wide launches: one thread per
+// grid column, a workgroup walks kRes2rRows rows of one system with x64 of
+// the rows below, at and above in registers and the current row in LDS, so
+// x64 is read once per point (the 128 x 8 tiles read 1.25 - 1.5 times; 511^2,
+// 2048 systems: 3290 -> 2890 us per launch).  Same values per point as
+// k_residual64_2.
+constexpr int kRes2rRows = 128;
+
+template <bool VAR>
+__global__ __launch_bounds__(1024) void k_residual64_2r(LevelDev<double> L, const double* __restrict__ f,
+                                                        const double* __restrict__ x64, float* __restrict__ e,
+                                                        float* __restrict__ r32, const double* __restrict__ shift,
+                                                        const int* __restrict__ active64, int nrhs,
+                                                        double* __restrict__ partial,
+                                                        unsigned long long* __restrict__ ctr) {
+  constexpr int LW = 1024 + 2;
+  __shared__ double sx[LW];   // x64 of the current row, zero pads at columns -1 and blockDim.x
+  const RowTile rt = row_tile();
+  const int sys = rt.sys, seg = rt.seg;
+  if (!active64[sys]) return;
+  count_bytes_row(rt, ctr, (unsigned long long)L.N * (8 + 8 + 4 + 4 + (VAR && sys == 0 ? 16 : 0)));
+  const int n = L.n;
+  const int i = threadIdx.x, NT = blockDim.x;
+  const int j0 = seg * kRes2rRows, j1 = min(j0 + kRes2rRows, n);
+  const bool col_on = i < n;
+  const int ic = min(i, n - 1), q = 1 + i;
+  const long long off = (long long)sys * L.N;
+  const double* __restrict__ xs = x64 + off;
+  const double* __restrict__ fs = f + (long long)(sys % nrhs) * L.N;
+  const double s = shift[sys];
+  if (i < 2) sx[i == 0 ? 0 : NT + 1] = 0.0;
+  auto crow = [&](int r) { return min(max(r, 0), n - 1); };
+  // 1 on the grid, 0 off it (a factor, not a select: see k_spmv_r2)
+  auto on_f = [&](int r) { return (col_on && r >= 0 && r < n) ? 1.0 : 0.0; };
+  auto ldx = [&](int r) { return xs[crow(r) * n + ic] * on_f(r); };
+  double dn = ldx(j0 - 1), c = ldx(j0), up = ldx(j0 + 1), nx = ldx(j0 + 2);
+  double fv = fs[j0 * n + ic];
+  sx[q] = c;
+  double rr = 0.0;
+  __syncthreads();
+  for (int j = j0; j < j1; ++j) {
+    const int row = j * n;   // 2D grids: fewer than 2^31 points
+    // loads for the next rows: x64 of row j + 3, f of row j + 1
+    const double x3 = ldx(j + 3);
+    const double fn = fs[crow(j + 1) * n + ic];
+    double wl = 0.0, wr = 0.0, wd = 0.0, wu = 0.0;
+    if (VAR) {
+      const int fx = j * (n + 1) + ic, fy = row + ic;
+      wl = L.wf0[fx];
+      wr = L.wf0[fx + 1];
+      wd = L.wf1[fy];
+      wu = L.wf1[fy + n];
+    }
+    const double lv = sx[q - 1], rv = sx[q + 1];
+    double ax;
+    if (!VAR) ax = L.wc * ((c - lv) + (c - rv) + (c - dn) + (c - up)) + s * c;
+    else ax = wl * (c - lv) + wr * (c - rv) + wd * (c - dn) + wu * (c - up) + s * c;
+    const double rv64 = fv - ax;
+    if (col_on) {
+      const long long g = off + row + i;
+      r32[g] = (float)rv64;
+      e[g] = 0.0f;
+      rr += rv64 * rv64;
+    }
+    __syncthreads();   // every read of row j's x64 is done
+    sx[q] = up;
+    __syncthreads();
+    dn = c;
+    c = up;
+    up = nx;
+    nx = x3;
+    fv = fn;
+  }
+  write_partial(partial, sys, rr, seg, rt.nseg);
+}
+
+// the FP64 residual of a 2D batch of nsys systems walks whole rows when the
+// other kernels do (levels of 255 - 1023 points, enough row segments)
+static inline bool residual_rows(int dim, int n, long long nsys) {
+  return dim == 2 && n >= kRowsMinN && n <= kRowsMaxN && nsys * ((n + kRes2rRows - 1) / kRes2rRows) >= kFillBlocks;
 }
 
 // k_residual64 in 3D, marching along z with kMarchRows rows per thread
@@ -3268,7 +3373,7 @@ void Launch<T>::spmv_p(int dim, bool var, const LevelDev<T>& L, const T* z, cons
                        hipStream_t st, unsigned long long* ctr, Fin fin, T* x, const double* alpha, int tv) {
   const bool xup = x != nullptr;
   if (dim == 2 && spmv_rows(dim, L.n, tv)) {
-    const dim3 g(1, (L.n + kSpmvRows - 1) / kSpmvRows, nsys), blk(rows_threads(L.n));
+    const dim3 g = rows_grid((L.n + kSpmvRows - 1) / kSpmvRows, nsys), blk(rows_threads(L.n));
 #define K_SR(V, X_, Q_) \
   hipLaunchKernelGGL((k_spmv_r2<T, V, X_, Q_>), g, blk, 0, st, L, z, pold, pnew, q, beta, shift, active, partial, \
                      ctr, fin, x, alpha)
@@ -3340,7 +3445,7 @@ bool Launch<T>::fused_down(int dim, bool var, int nu, const LevelDev<T>& Lf, con
   }
   if (dim != 2 || nu < 1 || nu > 3) return false;
   if (down_rows(dim, Lf.n, tv)) {
-    const dim3 g(1, (Lc.n + kDown2rKy - 1) / kDown2rKy, nsys), blk(rows_threads(Lf.n));
+    const dim3 g = rows_grid((Lc.n + kDown2rKy - 1) / kDown2rKy, nsys), blk(rows_threads(Lf.n));
 #define K_DR0(V, NU_, R_)                                                                                     \
   hipLaunchKernelGGL((k_down2r<T, V, NU_, R_>), g, blk, 0, st, Lf, Lc, b, xout, bc, shift, active, om, ctr, p, \
                      alpha, bout, partial, fin)
@@ -3392,7 +3497,6 @@ int down_blocks(int dim, int n, int tv) {
 // 64-column down tile (variant 0) fetches fewer halo lines but makes fewer
 // workgroups than the 32 x 8 tile (variant 1): below about four per CU
 // (one-system solves, coarse levels) variant 1 keeps more of the chip busy.
-constexpr int kRowsMinN = 255;
 
 static inline bool rows_default(int dim, int n, long long nsys, int blocks) {
   return dim == 2 && n >= kRowsMinN && n <= kRowsMaxN && nsys * blocks >= kFillBlocks;
@@ -3433,7 +3537,7 @@ bool Launch<T>::fused_up(int dim, bool var, int nu, const LevelDev<T>& Lc, const
   }
   if (dim != 2 || nu < 1 || nu > 3) return false;
   if (up_rows(dim, Lf.n, tv)) {
-    const dim3 g(1, (Lf.n + kUp2rRows - 1) / kUp2rRows, nsys), blk(rows_threads(Lf.n));
+    const dim3 g = rows_grid((Lf.n + kUp2rRows - 1) / kUp2rRows, nsys), blk(rows_threads(Lf.n));
 #define K_UR0(V, NU_, D_)                                                                                        \
   hipLaunchKernelGGL((k_up2r<T, V, NU_, D_>), g, blk, 0, st, Lc, Lf, xc, xin, b, xout, shift, active, om, partial, \
                      ctr, fin)
@@ -3474,7 +3578,7 @@ int up_blocks(int dim, int n, int tv) {
 
 // the most blocks per system any reduction-writing launch shape can have
 int max_partial_blocks(int dim, int n, long long N) {
-  int m = std::max({stencil_blocks(dim, n), flat_blocks(N), residual_blocks(dim, n)});
+  int m = std::max({stencil_blocks(dim, n), flat_blocks(N), residual_blocks(dim, n, 1)});
   for (int v = 0; v < kTileVariants; ++v)
     m = std::max({m, up_blocks(dim, n, v), down_blocks(dim, n, v), spmv_blocks(dim, n, v)});
   return m;
@@ -3498,6 +3602,13 @@ void launch_residual64(int dim, bool var, const LevelDev<double>& L, const doubl
     else
       hipLaunchKernelGGL((k_residual64_3<false>), g, blk, 0, st, L, f, x64, e, r32, shift, active64, nrhs, partial,
                          ctr);
+  } else if (residual_rows(dim, L.n, nsys)) {
+    const dim3 g = rows_grid((L.n + kRes2rRows - 1) / kRes2rRows, nsys), blk(rows_threads(L.n));
+    if (var)
+      hipLaunchKernelGGL((k_residual64_2r<true>), g, blk, 0, st, L, f, x64, e, r32, shift, active64, nrhs, partial, ctr);
+    else
+      hipLaunchKernelGGL((k_residual64_2r<false>), g, blk, 0, st, L, f, x64, e, r32, shift, active64, nrhs, partial,
+                         ctr);
   } else {
     constexpr int rows_per_block = (kBlock / kRes2Cols) * kRes2Rows;
     const dim3 g2((L.n + kRes2Cols - 1) / kRes2Cols, (L.n + rows_per_block - 1) / rows_per_block, nsys);
@@ -3510,7 +3621,8 @@ void launch_residual64(int dim, bool var, const LevelDev<double>& L, const doubl
   }
 }
 
-int residual_blocks(int dim, int n) {
+int residual_blocks(int dim, int n, long long nsys) {
+  if (residual_rows(dim, n, nsys)) return (n + kRes2rRows - 1) / kRes2rRows;
   if (dim == 3) return stencil_blocks(dim, n);
   constexpr int rows_per_block = (kBlock / kRes2Cols) * kRes2Rows;
   return ((n + kRes2Cols - 1) / kRes2Cols) * ((n + rows_per_block - 1) / rows_per_block);
