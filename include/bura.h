@@ -359,10 +359,11 @@ int bura_plan_apply(bura_plan_t plan, double shift, const double* x_dev, double*
  * computes the same value at every grid point up to rounding (the grouping of
  * the per-block partial sums of the PCG dot products differs, and variant 3
  * of the down kernel sums the full weighting in another order), so results
- * of two variants agree to rounding, not bit for bit.  Variant 3 walks
- * whole grid rows (levels of up to 1023 points per axis; a larger level runs
+ * of two variants agree to rounding, not bit for bit.  Variants 3 and 4
+ * walk whole grid rows, in segments of 128 and of 32 fine rows per
+ * workgroup (levels of up to 1023 points per axis; a larger level runs
  * variant 0). */
-#define BURA_TILE_VARIANTS 4
+#define BURA_TILE_VARIANTS 5
 
 /* The variants a 2D plan launches: out[0] for the stencil product, out[1 + 2l]
  * and out[2 + 2l] for the fused down and up kernels of level l, for each of

@@ -46,7 +46,7 @@ BURA_MIXED = 1
 BURA_BATCHED = 0
 BURA_PER_POLE = 1
 BURA_MAX_TERMS = 64
-BURA_TILE_VARIANTS = 4
+BURA_TILE_VARIANTS = 5
 # bura_opts_t.variant bits: alternative code paths of the same steps
 BURA_VARIANT_UNFUSED = 1
 BURA_VARIANT_NO_FOLDXR = 2

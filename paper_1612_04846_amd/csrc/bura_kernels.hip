@@ -1065,13 +1065,18 @@ struct RegionFaces {
 // along y).  The down kernel's default region is 133 fine columns wide for
 // the same reason (7 % faster than 69 columns); the up kernel stays at 64
 // fine columns, where it is faster than at 128.
-// Variant 3 of the stencil product and of the down and up kernels is
+// Variants 3 and 4 of the stencil product and of the down and up kernels are
 // k_spmv_r2 / k_down2r / k_up2r (whole rows, levels of up to 1023 points per
-// axis; a larger level runs variant 0 in its place, and the tuner skips it).
-constexpr int kDownTile[kTileVariants][2] = {{64, 6}, {32, 8}, {64, 8}, {64, 6}};
-constexpr int kUpTile[kTileVariants][2] = {{64, 16}, {64, 8}, {64, 24}, {64, 16}};
-constexpr int kSpmvTile[kTileVariants][2] = {{4, 128}, {2, 64}, {8, 128}, {4, 128}};
-constexpr int kRowsVariant = 3;
+// axis; a larger level runs variant 0 in their place, and the tuner skips
+// them there): segments of 128 fine rows (variant 3) or 32 (variant 4, more
+// workgroups for launches of few systems; 1023^2 with 30 systems: stencil
+// product 121 -> 109 us in FP32 and 229 -> 214 us in FP64, the FP32 up
+// kernel 108 -> 92 us, where 128-row segments were slower than the tiles).
+constexpr int kDownTile[kTileVariants][2] = {{64, 6}, {32, 8}, {64, 8}, {64, 6}, {64, 6}};
+constexpr int kUpTile[kTileVariants][2] = {{64, 16}, {64, 8}, {64, 24}, {64, 16}, {64, 16}};
+constexpr int kSpmvTile[kTileVariants][2] = {{4, 128}, {2, 64}, {8, 128}, {4, 128}, {4, 128}};
+constexpr int kRowsVariant = 3, kShortRowsVariant = 4;
+constexpr int kRowsSeg = 128, kShortRowsSeg = 32;   // fine rows per workgroup
 constexpr int kRowsMaxN = 1023;
 constexpr int kRowsMinN = 255;   // smallest level the row kernels are the default on
 // A row kernel's workgroup: its system and row segment, from a launch grid of
@@ -1099,11 +1104,14 @@ __device__ __forceinline__ void count_bytes_row(const RowTile& rt, unsigned long
 // axis runs k_spmv_r2 / k_down2r / k_up2r in variant tv, and their threads
 // per workgroup (one per column and at least one past the grid, in waves)
 static inline bool down_rows(int dim, int n, int tv) {
-  return dim == 2 && tile_variant(tv) == kRowsVariant && n <= kRowsMaxN;
+  const int v = tile_variant(tv);
+  return dim == 2 && (v == kRowsVariant || v == kShortRowsVariant) && n <= kRowsMaxN;
 }
 static inline bool up_rows(int dim, int n, int tv) { return down_rows(dim, n, tv); }
 static inline bool spmv_rows(int dim, int n, int tv) { return down_rows(dim, n, tv); }
 static inline int rows_threads(int n) { return ((n + 1 + 63) / 64) * 64; }
+// fine rows per workgroup of a row variant (the down kernel: half as many coarse rows)
+static inline int rows_seg(int tv) { return tile_variant(tv) == kShortRowsVariant ? kShortRowsSeg : kRowsSeg; }
 
 // Reciprocal of a Jacobi diagonal, formed once per point and kernel: the sweeps
 // multiply by it.  FP32: the hardware reciprocal (within 1 ulp); FP64: IEEE
@@ -1474,7 +1482,7 @@ __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, con
 // arithmetic per point except the order of the full weighting's sum)
 // marching along y over whole grid rows.  A workgroup has one
 // thread per grid column (blockDim.x >= n + 1, a multiple of 64) and owns the
-// fine rows of kDown2rKy coarse rows; it walks up its rows with the stages
+// fine rows of ky coarse rows (a launch parameter); it walks up its rows with the stages
 // lagging one row behind each other, as the 3D kernels walk up their planes:
 // at step t row t of b (RUP: b_old - alpha (A + s) p, p of rows t - 1 .. t + 1)
 // enters, the first sweep is formed on it pointwise, sweep m + 1 on row t - m,
@@ -1489,15 +1497,14 @@ __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, con
 // right-hand side and a zero inverse diagonal, so they stay exactly 0; the
 // LDS rows have a zero pad on each side.  Two barriers per row.
 // --------------------------------------------------------------------------
-constexpr int kDown2rKy = 64;   // coarse rows per workgroup
-
 template <typename T, bool VAR, int NU, bool RUP>
 __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc, const T* __restrict__ b,
                                                  T* __restrict__ xout, T* __restrict__ bc,
                                                  const T* __restrict__ shift, const int* __restrict__ active,
                                                  Sweeps<T> om, unsigned long long* __restrict__ ctr,
                                                  const T* __restrict__ pv, const double* __restrict__ alpha,
-                                                 T* __restrict__ bout, double* __restrict__ partial, Fin fin) {
+                                                 T* __restrict__ bout, double* __restrict__ partial, Fin fin,
+                                                 int ky) {
   constexpr int LW = 1024 + 2;   // an LDS row: pad, up to 1024 columns, pad
   __shared__ T sx[NU][LW];       // newest row of each sweep's output
   __shared__ T sr[LW];           // residual row
@@ -1509,7 +1516,7 @@ __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc,
                                    (unsigned long long)Lc.N * sizeof(T) +
                                    (VAR && sys == 0 ? (unsigned long long)Lf.N * sizeof(T) * 2 : 0ULL));
   const int nf = Lf.n, nc = Lc.n;
-  const int K0 = rt.seg * kDown2rKy, K1 = min(K0 + kDown2rKy, nc);
+  const int K0 = rt.seg * ky, K1 = min(K0 + ky, nc);
   const int f1 = K1 == nc ? nf : 2 * K1;   // owned fine rows [2 K0, f1) (the last segment: the top one too)
   const int i = threadIdx.x;               // this thread's column
   const int NT = blockDim.x;
@@ -1674,19 +1681,17 @@ __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc,
 // point) marching along y over whole grid rows, as k_down2r: at step t the
 // corrected iterate x_in + P x_c of row t enters and sweep m runs on row t - m
 // (the pre-smoothing weights reversed); sweep NU's row t - NU is written on
-// the owned rows [kUp2rRows s, kUp2rRows (s + 1)) of segment s, with b.x
+// the owned rows [rows s, rows (s + 1)) of segment s (rows: a launch parameter), with b.x
 // when this is the finest level.  Each thread reads the coarse values under
 // its column (the coarse columns left and right of it) from the two coarse
 // rows that bracket fine row t, a coarse row ahead of their use.
-constexpr int kUp2rRows = 128;   // fine rows per workgroup
-
 template <typename T, bool VAR, int NU, bool DOT>
 __global__ __launch_bounds__(1024) void k_up2r(LevelDev<T> Lc, LevelDev<T> Lf, const T* __restrict__ xc,
                                                const T* __restrict__ xin, const T* __restrict__ b,
                                                T* __restrict__ xout, const T* __restrict__ shift,
                                                const int* __restrict__ active, Sweeps<T> om,
                                                double* __restrict__ partial, unsigned long long* __restrict__ ctr,
-                                               Fin fin) {
+                                               Fin fin, int rows) {
   constexpr int LW = 1024 + 2;
   __shared__ T sx[NU][LW];   // newest row of the correction and of sweeps 1 .. NU-1
   const RowTile rt = row_tile();
@@ -1695,7 +1700,7 @@ __global__ __launch_bounds__(1024) void k_up2r(LevelDev<T> Lc, LevelDev<T> Lf, c
   count_bytes_row(rt, ctr, (unsigned long long)Lf.N * sizeof(T) * 3 + (unsigned long long)Lc.N * sizeof(T) +
                                    (VAR && sys == 0 ? (unsigned long long)Lf.N * sizeof(T) * 2 : 0ULL));
   const int nf = Lf.n, nc = Lc.n;
-  const int y0 = rt.seg * kUp2rRows, y1 = min(y0 + kUp2rRows, nf);   // owned fine rows
+  const int y0 = rt.seg * rows, y1 = min(y0 + rows, nf);   // owned fine rows
   const int i = threadIdx.x;
   const int NT = blockDim.x;
   const bool col_on = i < nf;
@@ -2490,12 +2495,11 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p2(LevelDev<T> L, const T* __re
 }
 
 // Row-marching version of k_spmv_p2 (launch-shape variant 3): one thread per
-// grid column, a workgroup walks kSpmvRows rows; p_new of the rows below, at
+// grid column, a workgroup walks `rows` rows (a launch parameter); p_new of the rows below, at
 // and above the current one stays in registers and the current row's p_new
 // is in LDS for the left/right neighbours, so z and p_old are read once per
 // point (plus one row above and below a segment).  Same values per point as
 // k_spmv_p2; two barriers per row.
-constexpr int kSpmvRows = 128;
 
 template <typename T, bool VAR, bool XUP, bool WQ>
 __global__ __launch_bounds__(1024) void k_spmv_r2(LevelDev<T> L, const T* __restrict__ z, const T* __restrict__ pold,
@@ -2503,7 +2507,7 @@ __global__ __launch_bounds__(1024) void k_spmv_r2(LevelDev<T> L, const T* __rest
                                                   const double* __restrict__ beta, const T* __restrict__ shift,
                                                   const int* __restrict__ active, double* __restrict__ partial,
                                                   unsigned long long* __restrict__ ctr, Fin fin,
-                                                  T* __restrict__ x, const double* __restrict__ alpha) {
+                                                  T* __restrict__ x, const double* __restrict__ alpha, int rows) {
   constexpr int LW = 1024 + 2;
   __shared__ T sp[LW];   // p_new of the current row, zero pads at columns -1 and blockDim.x
   const RowTile rt = row_tile();
@@ -2516,7 +2520,7 @@ __global__ __launch_bounds__(1024) void k_spmv_r2(LevelDev<T> L, const T* __rest
                                  (VAR && sys == 0 ? 2 : 0)));
   const int n = L.n;
   const int i = threadIdx.x, NT = blockDim.x;
-  const int j0 = rt.seg * kSpmvRows, j1 = min(j0 + kSpmvRows, n);
+  const int j0 = rt.seg * rows, j1 = min(j0 + rows, n);
   const bool col_on = i < n;
   const int ic = min(i, n - 1);
   const int qi = 1 + i;
@@ -3209,7 +3213,7 @@ static inline dim3 spmv2_grid(int n, int nsys, int tv) {
 
 int spmv_blocks(int dim, int n, int tv) {
   if (dim != 2) return stencil_blocks(dim, n);
-  if (spmv_rows(dim, n, tv)) return (n + kSpmvRows - 1) / kSpmvRows;
+  if (spmv_rows(dim, n, tv)) return (n + rows_seg(tv) - 1) / rows_seg(tv);
   const dim3 g = spmv2_grid(n, 1, tv);
   return (int)(g.x * g.y);
 }
@@ -3227,11 +3231,12 @@ static inline dim3 flat_grid(long long N, int nsys) {
 // Calls f(std::integral_constant<int, v>) for the runtime variant tv.
 template <typename F>
 static inline void with_tile(int tv, F&& f) {
-  static_assert(kTileVariants == 4, "one case per variant");
+  static_assert(kTileVariants == 5, "one case per variant");
   switch (tile_variant(tv)) {
     case 1: f(std::integral_constant<int, 1>{}); break;
     case 2: f(std::integral_constant<int, 2>{}); break;
     case 3: f(std::integral_constant<int, 3>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
     default: f(std::integral_constant<int, 0>{}); break;
   }
 }
@@ -3239,7 +3244,8 @@ static inline void with_tile(int tv, F&& f) {
 
 bool tile_variant_distinct(int kind, int dim, int n, int tv) {
   (void)kind;
-  if (tile_variant(tv) != kRowsVariant) return true;
+  const int v = tile_variant(tv);
+  if (v != kRowsVariant && v != kShortRowsVariant) return true;
   return down_rows(dim, n, tv);
 }
 
@@ -3373,10 +3379,11 @@ void Launch<T>::spmv_p(int dim, bool var, const LevelDev<T>& L, const T* z, cons
                        hipStream_t st, unsigned long long* ctr, Fin fin, T* x, const double* alpha, int tv) {
   const bool xup = x != nullptr;
   if (dim == 2 && spmv_rows(dim, L.n, tv)) {
-    const dim3 g = rows_grid((L.n + kSpmvRows - 1) / kSpmvRows, nsys), blk(rows_threads(L.n));
+    const int rows = rows_seg(tv);
+    const dim3 g = rows_grid((L.n + rows - 1) / rows, nsys), blk(rows_threads(L.n));
 #define K_SR(V, X_, Q_) \
   hipLaunchKernelGGL((k_spmv_r2<T, V, X_, Q_>), g, blk, 0, st, L, z, pold, pnew, q, beta, shift, active, partial, \
-                     ctr, fin, x, alpha)
+                     ctr, fin, x, alpha, rows)
     if (var) {
       if (!q) K_SR(true, true, false); else if (xup) K_SR(true, true, true); else K_SR(true, false, true);
     } else {
@@ -3445,10 +3452,11 @@ bool Launch<T>::fused_down(int dim, bool var, int nu, const LevelDev<T>& Lf, con
   }
   if (dim != 2 || nu < 1 || nu > 3) return false;
   if (down_rows(dim, Lf.n, tv)) {
-    const dim3 g = rows_grid((Lc.n + kDown2rKy - 1) / kDown2rKy, nsys), blk(rows_threads(Lf.n));
+    const int ky = rows_seg(tv) / 2;
+    const dim3 g = rows_grid((Lc.n + ky - 1) / ky, nsys), blk(rows_threads(Lf.n));
 #define K_DR0(V, NU_, R_)                                                                                     \
   hipLaunchKernelGGL((k_down2r<T, V, NU_, R_>), g, blk, 0, st, Lf, Lc, b, xout, bc, shift, active, om, ctr, p, \
-                     alpha, bout, partial, fin)
+                     alpha, bout, partial, fin, ky)
 #define K_DR(V, NU_) do { if (rup) K_DR0(V, NU_, true); else K_DR0(V, NU_, false); } while (0)
     if (var) {
       if (nu == 1) K_DR(true, 1); else if (nu == 2) K_DR(true, 2); else K_DR(true, 3);
@@ -3481,7 +3489,7 @@ int down_blocks(int dim, int n, int tv) {
   const int nc = (n - 1) / 2;
   if (dim == 3)
     return ((nc + kD3Cx - 1) / kD3Cx) * ((nc + kD3Cy - 1) / kD3Cy) * ((nc + kD3Kz - 1) / kD3Kz);
-  if (down_rows(dim, n, tv)) return (nc + kDown2rKy - 1) / kDown2rKy;
+  if (down_rows(dim, n, tv)) return (nc + rows_seg(tv) / 2 - 1) / (rows_seg(tv) / 2);
   const int cx = kDownTile[tile_variant(tv)][0], cy = kDownTile[tile_variant(tv)][1];
   return ((nc + cx - 1) / cx) * ((nc + cy - 1) / cy);
 }
@@ -3537,10 +3545,11 @@ bool Launch<T>::fused_up(int dim, bool var, int nu, const LevelDev<T>& Lc, const
   }
   if (dim != 2 || nu < 1 || nu > 3) return false;
   if (up_rows(dim, Lf.n, tv)) {
-    const dim3 g = rows_grid((Lf.n + kUp2rRows - 1) / kUp2rRows, nsys), blk(rows_threads(Lf.n));
+    const int rows = rows_seg(tv);
+    const dim3 g = rows_grid((Lf.n + rows - 1) / rows, nsys), blk(rows_threads(Lf.n));
 #define K_UR0(V, NU_, D_)                                                                                        \
   hipLaunchKernelGGL((k_up2r<T, V, NU_, D_>), g, blk, 0, st, Lc, Lf, xc, xin, b, xout, shift, active, om, partial, \
-                     ctr, fin)
+                     ctr, fin, rows)
 #define K_UR(V, NU_) do { if (dot) K_UR0(V, NU_, true); else K_UR0(V, NU_, false); } while (0)
     if (var) {
       if (nu == 1) K_UR(true, 1); else if (nu == 2) K_UR(true, 2); else K_UR(true, 3);
@@ -3571,7 +3580,7 @@ bool Launch<T>::fused_up(int dim, bool var, int nu, const LevelDev<T>& Lc, const
 
 int up_blocks(int dim, int n, int tv) {
   if (dim == 3) return ((n + kU3Ox - 1) / kU3Ox) * ((n + kU3Oy - 1) / kU3Oy) * ((n + kU3Fz - 1) / kU3Fz);
-  if (up_rows(dim, n, tv)) return (n + kUp2rRows - 1) / kUp2rRows;
+  if (up_rows(dim, n, tv)) return (n + rows_seg(tv) - 1) / rows_seg(tv);
   const int ox = kUpTile[tile_variant(tv)][0], oy = kUpTile[tile_variant(tv)][1];
   return ((n + ox - 1) / ox) * ((n + oy - 1) / oy);
 }
