@@ -125,6 +125,45 @@ def test_every_tile_variant_matches_oracle(n, var, prec, alpha, k):
     plan.close()
 
 
+ROW_CASES = [
+    # n, variable coefficients, precision, smoothing sweeps
+    (95, False, "FP64", 1),
+    (127, True, "MIXED", 3),
+    (191, False, "MIXED", 3),
+    (255, True, "FP64", 1),
+]
+
+
+@pytest.mark.parametrize("n,var,prec,nu", ROW_CASES)
+def test_row_variants_with_one_and_three_sweeps(n, var, prec, nu):
+    """The row-marching variants (3: segments of 128 fine rows, 4: of 32) on
+    every level with one and with three smoothing sweeps, FP64 and mixed,
+    constant and variable coefficients; no grid's rows are a multiple of a
+    segment (95 -> 47 -> 23 -> 11 -> 5 ..., 191 -> 95 ...).  Each matches the
+    oracle at the tiles' tolerance, and the tiles' result to rounding."""
+    B = _B()
+    alpha, k = 0.5, 6
+    b = oracle_bura(alpha, k)
+    F = synth.normal_rhs(n, 2, nrhs=2, tag=441)
+    coeff, ref = _reference(n, var, alpha, k, F, tag=442)
+    plan = B.Plan(2, n, weights=b.c_f64, shifts=[-x for x in b.d_f64], coeff=coeff, nrhs_max=2,
+                  precision=getattr(B, "BURA_" + prec), tol=1e-12, nu_pre=nu, nu_post=nu)
+    try:
+        nt = len(plan.tiles)
+        outs = {}
+        for v in (0, 3, 4):
+            plan.tiles = [v] * nt
+            res = plan.solve(_dev(F))
+            outs[v] = _host(res.u)
+            err = _rel2(outs[v], ref)
+            print(f"n={n} var={var} {prec} nu={nu} variant {v}: rel2 vs oracle {err:.2e}, "
+                  f"iters {list(res.report.iters)[:k + 1]}")
+            assert err <= 1e-9
+        assert _rel2(outs[3], outs[0]) <= 1e-9 and _rel2(outs[4], outs[0]) <= 1e-9
+    finally:
+        plan.close()
+
+
 def test_wide_launch_defaults_to_rows_and_matches_oracle():
     """512 systems of a 255^2 grid (8 poles x 64 right-hand sides): the stencil
     product and the fine down and up kernels default to the row-marching
