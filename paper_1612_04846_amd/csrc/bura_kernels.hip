@@ -1077,6 +1077,53 @@ constexpr int kUpTile[kTileVariants][2] = {{64, 16}, {64, 8}, {64, 24}, {64, 16}
 constexpr int kSpmvTile[kTileVariants][2] = {{4, 128}, {2, 64}, {8, 128}, {4, 128}, {4, 128}};
 constexpr int kRowsVariant = 3, kShortRowsVariant = 4;
 constexpr int kRowsSeg = 128, kShortRowsSeg = 32;   // fine rows per workgroup
+// The marching kernels keep the global loads of the next kRowLead rows in
+// flight in a ring of registers: slot s serves steps s, s + kRowLead, ...,
+// is used at the start of its step and is refilled after the step's
+// barriers with the row kRowLead steps ahead (the barriers keep the compiler
+// from issuing the new load before the old value is used, so the slot stays
+// one register and no register copy has to wait on a load).  The loop over
+// steps is unrolled by kRowLead so that every slot index is a constant.  A
+// load used in the step that issued it (or copied at its end) makes the wave
+// wait there for every load in flight: one memory round trip per row.
+constexpr int kRowLead = 3;
+// A copy of a value the register allocator cannot merge with its source:
+// the ring slot the source came from is free after it, so the refill load
+// can go into the same register and no copy at the loop's end waits on it.
+// Runs step(t, slot) for t = t0 .. t1 with slot = (t - t0) mod kRowLead as a
+// compile-time constant: whole groups of kRowLead steps in a loop without
+// exits (an exit inside the group makes the compiler peel the loop, and the
+// waits of the loop then serve the peeled path too), then the remainder.
+template <int LEAD, typename Step, int... S>
+__device__ __forceinline__ void ring_march_impl(int t0, int t1, Step& step, std::integer_sequence<int, S...>) {
+  int tb = t0;
+  for (; tb + LEAD - 1 <= t1; tb += LEAD) (step(tb + S, std::integral_constant<int, S>{}), ...);
+  const int rem = t1 - tb + 1;
+  ((S < rem ? (step(tb + S, std::integral_constant<int, S>{}), 0) : 0), ...);
+}
+template <int LEAD = kRowLead, typename Step>
+__device__ __forceinline__ void ring_march(int t0, int t1, Step step) {
+  ring_march_impl<LEAD>(t0, t1, step, std::make_integer_sequence<int, LEAD>{});
+}
+// the lead of the fused row kernels: in FP64 with variable coefficients
+// three rows of loads do not fit the registers a 1024-thread workgroup
+// leaves (they spilled to scratch memory), so those keep two, and one with
+// three sweeps
+template <typename T, bool VAR, int NU>
+constexpr int row_lead() { return sizeof(T) == 8 && VAR ? (NU >= 3 ? 1 : 2) : kRowLead; }
+// Before a marching loop starts its ring: every load of the set-up has
+// arrived.  The waits inside the loop must suit both the first step and the
+// steady state; with set-up loads still in flight they are computed for the
+// shorter history before the first step and wait for far more than the
+// steady state needs, on every step.
+__device__ __forceinline__ void ring_prologue_wait() { __builtin_amdgcn_s_waitcnt(0); }
+template <typename T>
+__device__ __forceinline__ T ring_take(T v) {
+  T o;
+  if constexpr (sizeof(T) == 4) asm("v_mov_b32 %0, %1" : "=v"(o) : "v"(v));
+  else asm("v_mov_b64 %0, %1" : "=v"(o) : "v"(v));
+  return o;
+}
 constexpr int kRowsMaxN = 1023;
 constexpr int kRowsMinN = 255;   // smallest level the row kernels are the default on
 // A row kernel's workgroup: its system and row segment, from a launch grid of
@@ -1511,6 +1558,7 @@ __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc,
   __shared__ T sp[RUP ? LW : 1]; // p of the row being updated (RUP)
   const RowTile rt = row_tile();
   const int sys = rt.sys;
+  constexpr int LEAD = row_lead<T, VAR, NU>();
   if (!active[sys]) return;
   count_bytes_row(rt, ctr, (unsigned long long)Lf.N * sizeof(T) * (RUP ? 4 : 2) +
                                    (unsigned long long)Lc.N * sizeof(T) +
@@ -1541,6 +1589,8 @@ __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc,
   }
   auto row_on = [&](int r) { return col_on && r >= 0 && r < nf; };
   auto crow = [&](int r) { return min(max(r, 0), nf - 1); };
+  // 1 on the grid, 0 off it, applied to a row's loads when they are used
+  auto on_f = [&](int r) { return row_on(r) ? T(1) : T(0); };
   // face weights of row r at this column (clamped row: finite off the grid,
   // where no sweep uses them) and the inverse diagonal of row r
   struct Faces { T l, r, d, u; };
@@ -1581,44 +1631,49 @@ __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc,
   }
 #pragma unroll
   for (int m = 0; m < NU; ++m) xh[m][0] = xh[m][1] = T(0);
-  // p of rows t - 1, t, t + 1 (RUP; 0 outside the grid), p(t) also in sp
-  auto load_p = [&](int r) {
-    const T v = ps[(long long)crow(r) * nf + ic];
-    return row_on(r) ? v : T(0);
-  };
+  // p of rows t - 1, t, t + 1 (RUP; 0 outside the grid) during step t, p(t)
+  // also in sp; before the first step they hold rows t0 - 1 and t0
   T pm = T(0), pc = T(0), pa = T(0);
   if (RUP) {
-    pm = load_p(t0 - 1);
-    pc = load_p(t0);
-    pa = load_p(t0 + 1);
-    sp[q] = pc;
+    pc = ps[(long long)crow(t0 - 1) * nf + ic] * on_f(t0 - 1);
+    pa = ps[(long long)crow(t0) * nf + ic] * on_f(t0);
+    sp[q] = pa;
   }
-  // b and the faces of the next row are loaded a step ahead
-  T bnx = bs[(long long)crow(t0) * nf + ic];
-  Faces fnx = load_faces(t0);
   // the coarse column of this thread (threads I < nc) and its weighted
   // in-row sums of the residual on fine rows 2K and 2K + 1
   const bool restricts = i < nc;
   T s_lo = T(0), s_mid = T(0);
   T* __restrict__ bcs = bc + (long long)sys * Lc.N + min(i, nc - 1);
   double rr = 0.0;
+  ring_prologue_wait();
   __syncthreads();
-  for (int t = t0; t <= t1; ++t) {
-    // the loads of the step: b and faces of row t + 1, p of row t + 2
-    const T bl = bnx;
-    bnx = bs[(long long)crow(t + 1) * nf + ic];
-    const T pn = RUP ? load_p(t + 2) : T(0);
+  // the ring of row loads (see kRowLead): slot s of step t holds b and the
+  // faces of row t and p of row t + 1, as loaded (clamped rows, unmasked)
+  T rb[LEAD], rp[LEAD];
+  Faces rf[LEAD];
+#pragma unroll
+  for (int s = 0; s < LEAD; ++s) {
+    rb[s] = bs[(long long)crow(t0 + s) * nf + ic];
+    rf[s] = load_faces(t0 + s);
+    rp[s] = RUP ? ps[(long long)crow(t0 + 1 + s) * nf + ic] : T(0);
+  }
+  ring_march<LEAD>(t0, t1, [&](int t, auto slot) {
+    constexpr int s = decltype(slot)::value;
 #pragma unroll
     for (int d = NU; d > 0; --d) {
       bh[d] = bh[d - 1];
       fw[d] = fw[d - 1];
       rd[d] = rd[d - 1];
     }
-    fw[0] = fnx;
-    fnx = load_faces(t + 1);
+    if (VAR) fw[0] = Faces{ring_take(rf[s].l), ring_take(rf[s].r), ring_take(rf[s].d), ring_take(rf[s].u)};
     rd[0] = rdiag(fw[0], t);
-    T bn = bl;
-    if (RUP) bn = bl - am * apply(fw[0], sp, pc, pm, pa);
+    if (RUP) {
+      pm = pc;
+      pc = pa;
+      pa = rp[s] * on_f(t + 1);
+    }
+    T bn = rb[s];
+    if (RUP) bn = bn - am * apply(fw[0], sp, pc, pm, pa);
     bh[0] = row_on(t) ? bn : T(0);
     if (RUP && t >= 2 * K0 && t < f1 && col_on) {
       __builtin_nontemporal_store(bh[0], &bo[(long long)t * nf + i]);
@@ -1644,33 +1699,32 @@ __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc,
     sr[q] = res;
     if (RUP) sp[q] = pa;   // p(t + 1), the centre row of the next step
     __syncthreads();
+    // refill the slot with the rows LEAD steps ahead
+    rb[s] = bs[(long long)crow(t + LEAD) * nf + ic];
+    rf[s] = load_faces(t + LEAD);
+    if (RUP) rp[s] = ps[(long long)crow(t + 1 + LEAD) * nf + ic];
     // full weighting: this coarse column's in-row sum of fine row f = t - NU,
     // and coarse row K = f/2 - 1 once f = 2K + 2 (weights 1/4, 1/2, 1/4 along y)
     const int f = t - NU;
     if (restricts && f >= 2 * K0) {
       const T* R = sr + 1 + 2 * i;   // fine columns 2I .. 2I + 2
       const T acc = T(0.25) * R[0] + T(0.5) * R[1] + T(0.25) * R[2];
-      if (f == 2 * K0) {
-        s_lo = acc;
-      } else if (f & 1) {
-        s_mid = acc;
-      } else {
+      const bool odd = f & 1;
+      if (!odd && f != 2 * K0) {
         const int K = f / 2 - 1;
         bcs[(long long)K * nc] = T(0.25) * s_lo + T(0.5) * s_mid + T(0.25) * acc;
-        s_lo = acc;
       }
+      // selects, not stores in two branches: the compiler would merge those
+      // into one store through a pointer and keep both sums in scratch memory
+      s_mid = odd ? acc : s_mid;
+      s_lo = odd ? s_lo : acc;
     }
 #pragma unroll
     for (int m = 0; m < NU; ++m) {
       xh[m][1] = xh[m][0];
       xh[m][0] = xn[m];
     }
-    if (RUP) {
-      pm = pc;
-      pc = pa;
-      pa = pn;
-    }
-  }
+  });
   if (RUP) {
     write_partial(partial, sys, rr, rt.seg, rt.nseg);
     finish(fin, partial, sys, rt.nseg);
@@ -1696,6 +1750,7 @@ __global__ __launch_bounds__(1024) void k_up2r(LevelDev<T> Lc, LevelDev<T> Lf, c
   __shared__ T sx[NU][LW];   // newest row of the correction and of sweeps 1 .. NU-1
   const RowTile rt = row_tile();
   const int sys = rt.sys;
+  constexpr int LEAD = row_lead<T, VAR, NU>();
   if (!active[sys]) return;
   count_bytes_row(rt, ctr, (unsigned long long)Lf.N * sizeof(T) * 3 + (unsigned long long)Lc.N * sizeof(T) +
                                    (VAR && sys == 0 ? (unsigned long long)Lf.N * sizeof(T) * 2 : 0ULL));
@@ -1744,23 +1799,22 @@ __global__ __launch_bounds__(1024) void k_up2r(LevelDev<T> Lc, LevelDev<T> Lf, c
   };
   // the coarse columns of this fine column: ia (and ia + 1 for an even column)
   const int ia = (i & 1) ? (i - 1) / 2 : i / 2 - 1;
-  // coarse row K at columns ia, ia + 1 (0 outside the coarse grid)
+  const bool ia0_on = ia >= 0 && ia < nc, ia1_on = ia + 1 >= 0 && ia + 1 < nc;
+  // coarse row K at columns ia, ia + 1 as loaded (clamped, unmasked) and the
+  // masks that make them 0 outside the coarse grid
   auto load_c = [&](int K, T& c0, T& c1) {
     const int Kc_ = min(max(K, 0), nc - 1);
-    const T a0 = xcs[(long long)Kc_ * nc + min(max(ia, 0), nc - 1)];
-    const T a1 = xcs[(long long)Kc_ * nc + min(max(ia + 1, 0), nc - 1)];
+    c0 = xcs[(long long)Kc_ * nc + min(max(ia, 0), nc - 1)];
+    c1 = xcs[(long long)Kc_ * nc + min(max(ia + 1, 0), nc - 1)];
+  };
+  auto mask_c = [&](int K, T& c0, T& c1) {
     const bool kin = K >= 0 && K < nc;
-    c0 = kin && ia >= 0 && ia < nc ? a0 : T(0);
-    c1 = kin && ia + 1 >= 0 && ia + 1 < nc ? a1 : T(0);
+    c0 = kin && ia0_on ? c0 : T(0);
+    c1 = kin && ia1_on ? c1 : T(0);
   };
   // lowest coarse row of fine row t (odd t lies on it, even t halfway to the next)
   auto klo = [](int t) { return (t >> 1) - 1 + (t & 1); };
   const int t0 = y0 - NU, t1 = y1 + NU - 1;
-  int Kc = klo(t0);
-  T lo0, lo1, hi0, hi1, nx0, nx1;   // coarse rows Kc, Kc + 1 and (loaded ahead) Kc + 2
-  load_c(Kc, lo0, lo1);
-  load_c(Kc + 1, hi0, hi1);
-  load_c(Kc + 2, nx0, nx1);
   T bh[NU + 1], xh[NU][2], rd[NU + 1];
   Faces fw[NU + 1];
 #pragma unroll
@@ -1771,30 +1825,36 @@ __global__ __launch_bounds__(1024) void k_up2r(LevelDev<T> Lc, LevelDev<T> Lf, c
   }
 #pragma unroll
   for (int m = 0; m < NU; ++m) xh[m][0] = xh[m][1] = T(0);
-  T xnx = xis[(long long)crow(t0) * nf + ic], bnx = bs[(long long)crow(t0) * nf + ic];
-  Faces fnx = load_faces(t0);
   double dot = 0.0;
+  ring_prologue_wait();
   __syncthreads();
-  for (int t = t0; t <= t1; ++t) {
-    const T xl = xnx, bl = bnx;
-    xnx = xis[(long long)crow(t + 1) * nf + ic];
-    bnx = bs[(long long)crow(t + 1) * nf + ic];
-    if (klo(t) > Kc) {   // the next coarse row pair: (Kc + 1, Kc + 2)
-      ++Kc;
-      lo0 = hi0;
-      lo1 = hi1;
-      hi0 = nx0;
-      hi1 = nx1;
-      load_c(Kc + 2, nx0, nx1);
-    }
+  // the ring of row loads (see kRowLead): slot s of step t holds x_in, b and
+  // the faces of row t and the coarse rows klo(t), klo(t) + 1 at columns ia,
+  // ia + 1, as loaded (clamped, unmasked); a coarse row serves four fine
+  // steps and is loaded for each (the repeats hit the cache)
+  T rx[LEAD], rb[LEAD], rl0[LEAD], rl1[LEAD], rh0[LEAD], rh1[LEAD];
+  Faces rf[LEAD];
+  auto fill = [&](int t, int s) {
+    rx[s] = xis[(long long)crow(t) * nf + ic];
+    rb[s] = bs[(long long)crow(t) * nf + ic];
+    rf[s] = load_faces(t);
+    load_c(klo(t), rl0[s], rl1[s]);
+    load_c(klo(t) + 1, rh0[s], rh1[s]);
+  };
+#pragma unroll
+  for (int s = 0; s < LEAD; ++s) fill(t0 + s, s);
+  ring_march<LEAD>(t0, t1, [&](int t, auto slot) {
+    constexpr int s = decltype(slot)::value;
+    T lo0 = rl0[s], lo1 = rl1[s], hi0 = rh0[s], hi1 = rh1[s];
+    mask_c(klo(t), lo0, lo1);
+    mask_c(klo(t) + 1, hi0, hi1);
 #pragma unroll
     for (int d = NU; d > 0; --d) {
       bh[d] = bh[d - 1];
       fw[d] = fw[d - 1];
       rd[d] = rd[d - 1];
     }
-    fw[0] = fnx;
-    fnx = load_faces(t + 1);
+    if (VAR) fw[0] = Faces{ring_take(rf[s].l), ring_take(rf[s].r), ring_take(rf[s].d), ring_take(rf[s].u)};
     rd[0] = rdiag(fw[0], t);
     // stage 0 on row t: x_in + P x_c (multilinear, the expressions of k_up2)
     const bool on = row_on(t);
@@ -1804,9 +1864,9 @@ __global__ __launch_bounds__(1024) void k_up2r(LevelDev<T> Lc, LevelDev<T> Lf, c
     } else {
       v = (t & 1) ? T(0.5) * (lo0 + lo1) : T(0.25) * (lo0 + lo1 + hi0 + hi1);
     }
-    bh[0] = on ? bl : T(0);
+    bh[0] = on ? rb[s] : T(0);
     T xn[NU + 1];
-    xn[0] = on ? xl + v : T(0);
+    xn[0] = on ? rx[s] + v : T(0);
     // sweep m on row t - m from stage m - 1's output (centre row in
     // sx[m - 1], below in xh, above just formed)
 #pragma unroll
@@ -1823,12 +1883,13 @@ __global__ __launch_bounds__(1024) void k_up2r(LevelDev<T> Lc, LevelDev<T> Lf, c
 #pragma unroll
     for (int m = 0; m < NU; ++m) sx[m][q] = xn[m];
     __syncthreads();
+    fill(t + LEAD, s);   // refill the slot with row t + LEAD
 #pragma unroll
     for (int m = 0; m < NU; ++m) {
       xh[m][1] = xh[m][0];
       xh[m][0] = xn[m];
     }
-  }
+  });
   if (DOT) {
     write_partial(partial, sys, dot, rt.seg, rt.nseg);
     finish(fin, partial, sys, rt.nseg);
@@ -2528,65 +2589,71 @@ __global__ __launch_bounds__(1024) void k_spmv_r2(LevelDev<T> L, const T* __rest
   const T* __restrict__ zs = z + off;
   // beta = 0 (first iteration): p_old may hold anything, so read z in its place
   const T* __restrict__ pe = bt == T(0) ? zs : pold + off;
-  const T s = shift[sys];
+  const T s_ = shift[sys];
   if (i < 2) sp[i == 0 ? 0 : NT + 1] = T(0);
   auto crow = [&](int r) { return min(max(r, 0), n - 1); };
   // 1 on the grid, 0 off it: a factor rather than a select (a select lets the
   // compiler move a load into a branch and wait there for every load in flight)
   auto on_f = [&](int r) { return (col_on && r >= 0 && r < n) ? T(1) : T(0); };
-  // p_new below and at row j0, p_old at row j0, and z, p_old of row j0 + 1 (a row ahead)
-  T dn, c, pc, za_n, ea_n;
+  // p_new below and at row j0 (dn, c) and p_old at row j0 (pc)
+  T dn, c, pc;
   {
-    const int rb = crow(j0 - 1) * n + ic, rc = j0 * n + ic, ra = crow(j0 + 1) * n + ic;
+    const int rb = crow(j0 - 1) * n + ic, rc = j0 * n + ic;
     const T zb = zs[rb], eb = pe[rb], zc = zs[rc], ec = pe[rc];
-    za_n = zs[ra];
-    ea_n = pe[ra];
     dn = (zb + bt * eb) * on_f(j0 - 1);
     c = (zc + bt * ec) * on_f(j0);
     pc = ec;
   }
   sp[qi] = c;
   double dot = 0.0;
+  ring_prologue_wait();
   __syncthreads();
   auto walk = [&](auto upd_c) {
     constexpr bool UPD = XUP && decltype(upd_c)::value;
-    for (int j = j0; j < j1; ++j) {
-      const int row = j * n;   // 2D grids: fewer than 2^31 points
-      const T za = za_n, ea = ea_n;
-      {
-        const int r2 = crow(j + 2) * n + ic;
-        za_n = zs[r2];
-        ea_n = pe[r2];
-      }
-      const T xv = UPD ? x[off + row + ic] : T(0);
-      T fl = T(0), fr = T(0), fd = T(0), fu = T(0);
+    // the ring of row loads (see kRowLead): slot s of step j holds z and
+    // p_old of row j + 1 and x and the faces of row j, as loaded (clamped
+    // rows, unmasked)
+    T rz[kRowLead], re[kRowLead], rx[kRowLead], rfl[kRowLead], rfr[kRowLead], rfd[kRowLead], rfu[kRowLead];
+    auto fill = [&](int j, int s) {
+      const int ra = crow(j + 1) * n + ic, rw = crow(j) * n + ic;
+      rz[s] = zs[ra];
+      re[s] = pe[ra];
+      rx[s] = UPD ? x[off + rw] : T(0);
       if (VAR) {
-        const int fx = j * (n + 1) + ic, fy = row + ic;
-        fl = L.wf0[fx];
-        fr = L.wf0[fx + 1];
-        fd = L.wf1[fy];
-        fu = L.wf1[fy + n];
+        const int fx = crow(j) * (n + 1) + ic;
+        rfl[s] = L.wf0[fx];
+        rfr[s] = L.wf0[fx + 1];
+        rfd[s] = L.wf1[rw];
+        rfu[s] = L.wf1[rw + n];
       }
-      const T up = (za + bt * ea) * on_f(j + 1);
+    };
+#pragma unroll
+    for (int s = 0; s < kRowLead; ++s) fill(j0 + s, s);
+    ring_march(j0, j1 - 1, [&](int j, auto slot) {
+      constexpr int s = decltype(slot)::value;
+      const int row = j * n;   // 2D grids: fewer than 2^31 points
+      const T up = (rz[s] + bt * re[s]) * on_f(j + 1);
       const T lv = sp[qi - 1], rv = sp[qi + 1];
       T qv;
-      if (!VAR) qv = L.wc * ((c - lv) + (c - rv) + (c - dn) + (c - up)) + s * c;
-      else qv = fl * (c - lv) + fr * (c - rv) + fd * (c - dn) + fu * (c - up) + s * c;
+      if (!VAR) qv = L.wc * ((c - lv) + (c - rv) + (c - dn) + (c - up)) + s_ * c;
+      else qv = rfl[s] * (c - lv) + rfr[s] * (c - rv) + rfd[s] * (c - dn) + rfu[s] * (c - up) + s_ * c;
       if (col_on) {
         const long long g = off + row + i;
         __builtin_nontemporal_store(c, &pnew[g]);
         if (WQ) __builtin_nontemporal_store(qv, &q[g]);
         // the deferred update uses p_old = pc (pe is p_old whenever alpha != 0)
-        if (UPD) __builtin_nontemporal_store(xv + ap * pc, &x[g]);
+        if (UPD) __builtin_nontemporal_store(rx[s] + ap * pc, &x[g]);
         dot += (double)c * (double)qv;
       }
+      const T pn = ring_take(re[s]);   // p_old of row j + 1, the next step's pc
       __syncthreads();   // every read of this row's p_new is done
       sp[qi] = up;
       __syncthreads();
+      fill(j + kRowLead, s);
       dn = c;
       c = up;
-      pc = ea;
-    }
+      pc = pn;
+    });
   };
   if (XUP && ap != T(0)) walk(std::true_type{});
   else walk(std::false_type{});
@@ -2810,35 +2877,46 @@ __global__ __launch_bounds__(1024) void k_residual64_2r(LevelDev<double> L, cons
   const long long off = (long long)sys * L.N;
   const double* __restrict__ xs = x64 + off;
   const double* __restrict__ fs = f + (long long)(sys % nrhs) * L.N;
-  const double s = shift[sys];
+  const double sh = shift[sys];
   if (i < 2) sx[i == 0 ? 0 : NT + 1] = 0.0;
   auto crow = [&](int r) { return min(max(r, 0), n - 1); };
   // 1 on the grid, 0 off it (a factor, not a select: see k_spmv_r2)
   auto on_f = [&](int r) { return (col_on && r >= 0 && r < n) ? 1.0 : 0.0; };
-  auto ldx = [&](int r) { return xs[crow(r) * n + ic] * on_f(r); };
-  double dn = ldx(j0 - 1), c = ldx(j0), up = ldx(j0 + 1), nx = ldx(j0 + 2);
-  double fv = fs[j0 * n + ic];
-  sx[q] = c;
+  // x64 of rows j - 1, j, j + 1 during step j (dn, c, up); before the first
+  // step c and up hold rows j0 - 1 and j0
+  double dn = 0.0, c = xs[crow(j0 - 1) * n + ic] * on_f(j0 - 1), up = xs[j0 * n + ic] * on_f(j0);
+  sx[q] = up;
   double rr = 0.0;
+  ring_prologue_wait();
   __syncthreads();
-  for (int j = j0; j < j1; ++j) {
-    const int row = j * n;   // 2D grids: fewer than 2^31 points
-    // loads for the next rows: x64 of row j + 3, f of row j + 1
-    const double x3 = ldx(j + 3);
-    const double fn = fs[crow(j + 1) * n + ic];
-    double wl = 0.0, wr = 0.0, wd = 0.0, wu = 0.0;
+  // the ring of row loads (see kRowLead): slot s of step j holds x64 of row
+  // j + 1 and f and the faces of row j, as loaded (clamped rows, unmasked)
+  double rx[kRowLead], rf[kRowLead], wl[kRowLead], wr[kRowLead], wd[kRowLead], wu[kRowLead];
+  auto fill = [&](int j, int s) {
+    const int rw = crow(j) * n + ic;
+    rx[s] = xs[crow(j + 1) * n + ic];
+    rf[s] = fs[rw];
     if (VAR) {
-      const int fx = j * (n + 1) + ic, fy = row + ic;
-      wl = L.wf0[fx];
-      wr = L.wf0[fx + 1];
-      wd = L.wf1[fy];
-      wu = L.wf1[fy + n];
+      const int fx = crow(j) * (n + 1) + ic;
+      wl[s] = L.wf0[fx];
+      wr[s] = L.wf0[fx + 1];
+      wd[s] = L.wf1[rw];
+      wu[s] = L.wf1[rw + n];
     }
+  };
+#pragma unroll
+  for (int s = 0; s < kRowLead; ++s) fill(j0 + s, s);
+  ring_march(j0, j1 - 1, [&](int j, auto slot) {
+    constexpr int s = decltype(slot)::value;
+    const int row = j * n;   // 2D grids: fewer than 2^31 points
+    dn = c;
+    c = up;
+    up = rx[s] * on_f(j + 1);
     const double lv = sx[q - 1], rv = sx[q + 1];
     double ax;
-    if (!VAR) ax = L.wc * ((c - lv) + (c - rv) + (c - dn) + (c - up)) + s * c;
-    else ax = wl * (c - lv) + wr * (c - rv) + wd * (c - dn) + wu * (c - up) + s * c;
-    const double rv64 = fv - ax;
+    if (!VAR) ax = L.wc * ((c - lv) + (c - rv) + (c - dn) + (c - up)) + sh * c;
+    else ax = wl[s] * (c - lv) + wr[s] * (c - rv) + wd[s] * (c - dn) + wu[s] * (c - up) + sh * c;
+    const double rv64 = rf[s] - ax;
     if (col_on) {
       const long long g = off + row + i;
       r32[g] = (float)rv64;
@@ -2848,12 +2926,8 @@ __global__ __launch_bounds__(1024) void k_residual64_2r(LevelDev<double> L, cons
     __syncthreads();   // every read of row j's x64 is done
     sx[q] = up;
     __syncthreads();
-    dn = c;
-    c = up;
-    up = nx;
-    nx = x3;
-    fv = fn;
-  }
+    fill(j + kRowLead, s);
+  });
   write_partial(partial, sys, rr, seg, rt.nseg);
 }
 
