@@ -1090,6 +1090,34 @@ constexpr int kRowLead = 3;
 // A copy of a value the register allocator cannot merge with its source:
 // the ring slot the source came from is free after it, so the refill load
 // can go into the same register and no copy at the loop's end waits on it.
+// A vector (one system's, or the face weights every system shares) as a
+// buffer resource: loads and stores at this lane's byte offset voff (a vector
+// register, fixed for the whole march) plus a byte offset soff that is the
+// same for the whole workgroup (a scalar register, the row).  Addressing a
+// row then costs no per-lane arithmetic, where a 64-bit pointer costs a
+// 64-bit add per access.  Every access is in range (rows are clamped), so
+// the bounds of the resource never apply.
+constexpr int kBufWord3 = 0x00020000;   // resource word 3: 32-bit data format
+template <typename T>
+struct RowBuf {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ RowBuf(const T* base, long long count)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), 0, (int)(count * (long long)sizeof(T)), kBufWord3)) {}
+  __device__ __forceinline__ T ld(unsigned voff, unsigned soff) const {
+    if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  }
+  // NT: the nontemporal hint (the value is read again only by a later kernel)
+  template <bool NT>
+  __device__ __forceinline__ void st(T v, unsigned voff, unsigned soff) const {
+    if constexpr (sizeof(T) == 4)
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, NT ? 2 : 0);
+    else
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(unsigned __attribute__((ext_vector_type(2))), v), r,
+                                            voff, soff, NT ? 2 : 0);
+  }
+};
+
 // Runs step(t, slot) for t = t0 .. t1 with slot = (t - t0) mod kRowLead as a
 // compile-time constant: whole groups of kRowLead steps in a loop without
 // exits (an exit inside the group makes the compiler peel the loop, and the
@@ -1570,6 +1598,8 @@ __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc,
   const int NT = blockDim.x;
   const bool col_on = i < nf;
   const int ic = min(i, nf - 1);           // clamped column for the loads
+  const unsigned cb = (unsigned)ic * (unsigned)sizeof(T), ib = (unsigned)i * (unsigned)sizeof(T);
+  const unsigned rowb = (unsigned)nf * (unsigned)sizeof(T);   // bytes per grid row
   const T sh = shift[sys];
   const T rcon = jacobi_recip(Lf.wc * T(4) + sh);
   const T am = RUP ? (T)alpha[sys] : T(0);
@@ -1578,6 +1608,8 @@ __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc,
   const T* __restrict__ ps = RUP ? pv + off : nullptr;
   T* __restrict__ xs = xout + off;
   T* __restrict__ bo = RUP ? bout + off : nullptr;
+  const RowBuf<T> bsb(bs, Lf.N), psb(RUP ? ps : bs, Lf.N), xsb(xs, Lf.N), bob(RUP ? bo : xs, Lf.N);
+  const RowBuf<T> w0b(VAR ? Lf.wf0 : bs, VAR ? (long long)(nf + 1) * nf : 1), w1b(VAR ? Lf.wf1 : bs, VAR ? (long long)(nf + 1) * nf : 1);
   const int q = 1 + i;   // this column in an LDS row
   // the pads (columns -1 and NT) stay 0; every other entry is written before it is read
   if (i < 2) {
@@ -1597,12 +1629,12 @@ __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc,
   auto load_faces = [&](int r) {
     Faces f{T(0), T(0), T(0), T(0)};
     if (VAR) {
-      const int rr = crow(r);
-      const int fx = rr * (nf + 1) + ic, fy = rr * nf + ic;
-      f.l = Lf.wf0[fx];
-      f.r = Lf.wf0[fx + 1];
-      f.d = Lf.wf1[fy];
-      f.u = Lf.wf1[fy + nf];
+      const unsigned rr = (unsigned)crow(r);
+      const unsigned o0 = rr * (unsigned)(nf + 1) * (unsigned)sizeof(T), o1 = rr * rowb;
+      f.l = w0b.ld(cb, o0);
+      f.r = w0b.ld(cb + (unsigned)sizeof(T), o0);
+      f.d = w1b.ld(cb, o1);
+      f.u = w1b.ld(cb, o1 + rowb);
     }
     return f;
   };
@@ -1643,7 +1675,8 @@ __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc,
   // in-row sums of the residual on fine rows 2K and 2K + 1
   const bool restricts = i < nc;
   T s_lo = T(0), s_mid = T(0);
-  T* __restrict__ bcs = bc + (long long)sys * Lc.N + min(i, nc - 1);
+  const RowBuf<T> bcb(bc + (long long)sys * Lc.N, Lc.N);
+  const unsigned cbc = (unsigned)min(i, nc - 1) * (unsigned)sizeof(T);   // this lane's coarse column
   double rr = 0.0;
   ring_prologue_wait();
   __syncthreads();
@@ -1653,9 +1686,9 @@ __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc,
   Faces rf[LEAD];
 #pragma unroll
   for (int s = 0; s < LEAD; ++s) {
-    rb[s] = bs[(long long)crow(t0 + s) * nf + ic];
+    rb[s] = bsb.ld(cb, (unsigned)crow(t0 + s) * rowb);
     rf[s] = load_faces(t0 + s);
-    rp[s] = RUP ? ps[(long long)crow(t0 + 1 + s) * nf + ic] : T(0);
+    rp[s] = RUP ? psb.ld(cb, (unsigned)crow(t0 + 1 + s) * rowb) : T(0);
   }
   ring_march<LEAD>(t0, t1, [&](int t, auto slot) {
     constexpr int s = decltype(slot)::value;
@@ -1676,7 +1709,7 @@ __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc,
     if (RUP) bn = bn - am * apply(fw[0], sp, pc, pm, pa);
     bh[0] = row_on(t) ? bn : T(0);
     if (RUP && t >= 2 * K0 && t < f1 && col_on) {
-      __builtin_nontemporal_store(bh[0], &bo[(long long)t * nf + i]);
+      bob.template st<true>(bh[0], ib, (unsigned)t * rowb);
       rr += (double)bh[0] * (double)bh[0];
     }
     // sweep 1 on row t from x = 0; sweep m + 1 on row t - m from sweep m's
@@ -1692,7 +1725,7 @@ __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc,
     const T res = bh[NU] - apply(fw[NU], sx[NU - 1], xh[NU - 1][0], xh[NU - 1][1], xn[NU - 1]);
     // the pre-smoothed iterate: sweep NU's newest row t - NU + 1
     const int gx = t - NU + 1;
-    if (gx >= 2 * K0 && gx < f1 && col_on) __builtin_nontemporal_store(xn[NU - 1], &xs[(long long)gx * nf + i]);
+    if (gx >= 2 * K0 && gx < f1 && col_on) xsb.template st<true>(xn[NU - 1], ib, (unsigned)gx * rowb);
     __syncthreads();   // every read of this step's LDS rows is done
 #pragma unroll
     for (int m = 0; m < NU; ++m) sx[m][q] = xn[m];
@@ -1700,9 +1733,9 @@ __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc,
     if (RUP) sp[q] = pa;   // p(t + 1), the centre row of the next step
     __syncthreads();
     // refill the slot with the rows LEAD steps ahead
-    rb[s] = bs[(long long)crow(t + LEAD) * nf + ic];
+    rb[s] = bsb.ld(cb, (unsigned)crow(t + LEAD) * rowb);
     rf[s] = load_faces(t + LEAD);
-    if (RUP) rp[s] = ps[(long long)crow(t + 1 + LEAD) * nf + ic];
+    if (RUP) rp[s] = psb.ld(cb, (unsigned)crow(t + 1 + LEAD) * rowb);
     // full weighting: this coarse column's in-row sum of fine row f = t - NU,
     // and coarse row K = f/2 - 1 once f = 2K + 2 (weights 1/4, 1/2, 1/4 along y)
     const int f = t - NU;
@@ -1712,7 +1745,7 @@ __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc,
       const bool odd = f & 1;
       if (!odd && f != 2 * K0) {
         const int K = f / 2 - 1;
-        bcs[(long long)K * nc] = T(0.25) * s_lo + T(0.5) * s_mid + T(0.25) * acc;
+        bcb.template st<false>(T(0.25) * s_lo + T(0.5) * s_mid + T(0.25) * acc, cbc, (unsigned)K * (unsigned)nc * (unsigned)sizeof(T));
       }
       // selects, not stores in two branches: the compiler would merge those
       // into one store through a pointer and keep both sums in scratch memory
@@ -1767,6 +1800,10 @@ __global__ __launch_bounds__(1024) void k_up2r(LevelDev<T> Lc, LevelDev<T> Lf, c
   const T* __restrict__ bs = b + off;
   const T* __restrict__ xis = xin + off;
   T* __restrict__ xs = xout + off;
+  const unsigned cb = (unsigned)ic * (unsigned)sizeof(T), ib = (unsigned)i * (unsigned)sizeof(T);
+  const unsigned rowb = (unsigned)nf * (unsigned)sizeof(T);   // bytes per grid row
+  const RowBuf<T> xcb(xcs, Lc.N), bsb(bs, Lf.N), xib(xis, Lf.N), xsb(xs, Lf.N);
+  const RowBuf<T> w0b(VAR ? Lf.wf0 : bs, VAR ? (long long)(nf + 1) * nf : 1), w1b(VAR ? Lf.wf1 : bs, VAR ? (long long)(nf + 1) * nf : 1);
   const int q = 1 + i;
   if (i < 2) {
     const int pq = i == 0 ? 0 : NT + 1;
@@ -1780,11 +1817,11 @@ __global__ __launch_bounds__(1024) void k_up2r(LevelDev<T> Lc, LevelDev<T> Lf, c
     Faces f{T(0), T(0), T(0), T(0)};
     if (VAR) {
       const int rr = crow(r);
-      const int fx = rr * (nf + 1) + ic, fy = rr * nf + ic;
-      f.l = Lf.wf0[fx];
-      f.r = Lf.wf0[fx + 1];
-      f.d = Lf.wf1[fy];
-      f.u = Lf.wf1[fy + nf];
+      const unsigned o0 = (unsigned)rr * (unsigned)(nf + 1) * (unsigned)sizeof(T), o1 = (unsigned)rr * rowb;
+      f.l = w0b.ld(cb, o0);
+      f.r = w0b.ld(cb + (unsigned)sizeof(T), o0);
+      f.d = w1b.ld(cb, o1);
+      f.u = w1b.ld(cb, o1 + rowb);
     }
     return f;
   };
@@ -1800,12 +1837,15 @@ __global__ __launch_bounds__(1024) void k_up2r(LevelDev<T> Lc, LevelDev<T> Lf, c
   // the coarse columns of this fine column: ia (and ia + 1 for an even column)
   const int ia = (i & 1) ? (i - 1) / 2 : i / 2 - 1;
   const bool ia0_on = ia >= 0 && ia < nc, ia1_on = ia + 1 >= 0 && ia + 1 < nc;
+  const unsigned ca0 = (unsigned)min(max(ia, 0), nc - 1) * (unsigned)sizeof(T),
+                 ca1 = (unsigned)min(max(ia + 1, 0), nc - 1) * (unsigned)sizeof(T);
   // coarse row K at columns ia, ia + 1 as loaded (clamped, unmasked) and the
   // masks that make them 0 outside the coarse grid
   auto load_c = [&](int K, T& c0, T& c1) {
     const int Kc_ = min(max(K, 0), nc - 1);
-    c0 = xcs[(long long)Kc_ * nc + min(max(ia, 0), nc - 1)];
-    c1 = xcs[(long long)Kc_ * nc + min(max(ia + 1, 0), nc - 1)];
+    const unsigned ko = (unsigned)Kc_ * (unsigned)nc * (unsigned)sizeof(T);
+    c0 = xcb.ld(ca0, ko);
+    c1 = xcb.ld(ca1, ko);
   };
   auto mask_c = [&](int K, T& c0, T& c1) {
     const bool kin = K >= 0 && K < nc;
@@ -1835,8 +1875,8 @@ __global__ __launch_bounds__(1024) void k_up2r(LevelDev<T> Lc, LevelDev<T> Lf, c
   T rx[LEAD], rb[LEAD], rl0[LEAD], rl1[LEAD], rh0[LEAD], rh1[LEAD];
   Faces rf[LEAD];
   auto fill = [&](int t, int s) {
-    rx[s] = xis[(long long)crow(t) * nf + ic];
-    rb[s] = bs[(long long)crow(t) * nf + ic];
+    rx[s] = xib.ld(cb, (unsigned)crow(t) * rowb);
+    rb[s] = bsb.ld(cb, (unsigned)crow(t) * rowb);
     rf[s] = load_faces(t);
     load_c(klo(t), rl0[s], rl1[s]);
     load_c(klo(t) + 1, rh0[s], rh1[s]);
@@ -1876,7 +1916,7 @@ __global__ __launch_bounds__(1024) void k_up2r(LevelDev<T> Lc, LevelDev<T> Lf, c
     }
     const int g = t - NU;
     if (g >= y0 && g < y1 && col_on) {
-      __builtin_nontemporal_store(xn[NU], &xs[(long long)g * nf + i]);
+      xsb.template st<true>(xn[NU], ib, (unsigned)g * rowb);
       if (DOT) dot += (double)bh[NU] * (double)xn[NU];
     }
     __syncthreads();   // every read of this step's LDS rows is done
@@ -2589,6 +2629,10 @@ __global__ __launch_bounds__(1024) void k_spmv_r2(LevelDev<T> L, const T* __rest
   const T* __restrict__ zs = z + off;
   // beta = 0 (first iteration): p_old may hold anything, so read z in its place
   const T* __restrict__ pe = bt == T(0) ? zs : pold + off;
+  const unsigned cb = (unsigned)ic * (unsigned)sizeof(T), ib = (unsigned)i * (unsigned)sizeof(T);
+  const unsigned rowb = (unsigned)n * (unsigned)sizeof(T);   // bytes per grid row
+  const RowBuf<T> zsb(zs, L.N), peb(pe, L.N), xb(XUP ? x + off : zs, L.N), pnb(pnew + off, L.N), qb(WQ ? q + off : pnew + off, L.N);
+  const RowBuf<T> w0b(VAR ? L.wf0 : zs, VAR ? (long long)(n + 1) * n : 1), w1b(VAR ? L.wf1 : zs, VAR ? (long long)(n + 1) * n : 1);
   const T s_ = shift[sys];
   if (i < 2) sp[i == 0 ? 0 : NT + 1] = T(0);
   auto crow = [&](int r) { return min(max(r, 0), n - 1); };
@@ -2615,16 +2659,16 @@ __global__ __launch_bounds__(1024) void k_spmv_r2(LevelDev<T> L, const T* __rest
     // rows, unmasked)
     T rz[kRowLead], re[kRowLead], rx[kRowLead], rfl[kRowLead], rfr[kRowLead], rfd[kRowLead], rfu[kRowLead];
     auto fill = [&](int j, int s) {
-      const int ra = crow(j + 1) * n + ic, rw = crow(j) * n + ic;
-      rz[s] = zs[ra];
-      re[s] = pe[ra];
-      rx[s] = UPD ? x[off + rw] : T(0);
+      const unsigned ra = (unsigned)crow(j + 1) * rowb, rw = (unsigned)crow(j) * rowb;
+      rz[s] = zsb.ld(cb, ra);
+      re[s] = peb.ld(cb, ra);
+      rx[s] = UPD ? xb.ld(cb, rw) : T(0);
       if (VAR) {
-        const int fx = crow(j) * (n + 1) + ic;
-        rfl[s] = L.wf0[fx];
-        rfr[s] = L.wf0[fx + 1];
-        rfd[s] = L.wf1[rw];
-        rfu[s] = L.wf1[rw + n];
+        const unsigned fx = (unsigned)crow(j) * (unsigned)(n + 1) * (unsigned)sizeof(T);
+        rfl[s] = w0b.ld(cb, fx);
+        rfr[s] = w0b.ld(cb + (unsigned)sizeof(T), fx);
+        rfd[s] = w1b.ld(cb, rw);
+        rfu[s] = w1b.ld(cb, rw + rowb);
       }
     };
 #pragma unroll
@@ -2638,11 +2682,11 @@ __global__ __launch_bounds__(1024) void k_spmv_r2(LevelDev<T> L, const T* __rest
       if (!VAR) qv = L.wc * ((c - lv) + (c - rv) + (c - dn) + (c - up)) + s_ * c;
       else qv = rfl[s] * (c - lv) + rfr[s] * (c - rv) + rfd[s] * (c - dn) + rfu[s] * (c - up) + s_ * c;
       if (col_on) {
-        const long long g = off + row + i;
-        __builtin_nontemporal_store(c, &pnew[g]);
-        if (WQ) __builtin_nontemporal_store(qv, &q[g]);
+        const unsigned g = (unsigned)row * (unsigned)sizeof(T);
+        pnb.template st<true>(c, ib, g);
+        if (WQ) qb.template st<true>(qv, ib, g);
         // the deferred update uses p_old = pc (pe is p_old whenever alpha != 0)
-        if (UPD) __builtin_nontemporal_store(rx[s] + ap * pc, &x[g]);
+        if (UPD) xb.template st<true>(rx[s] + ap * pc, ib, g);
         dot += (double)c * (double)qv;
       }
       const T pn = ring_take(re[s]);   // p_old of row j + 1, the next step's pc
@@ -2878,6 +2922,10 @@ __global__ __launch_bounds__(1024) void k_residual64_2r(LevelDev<double> L, cons
   const double* __restrict__ xs = x64 + off;
   const double* __restrict__ fs = f + (long long)(sys % nrhs) * L.N;
   const double sh = shift[sys];
+  const unsigned cb = (unsigned)ic * 8u, rowb = (unsigned)n * 8u;
+  const RowBuf<double> xsb(xs, L.N), fsb(fs, L.N);
+  const RowBuf<double> w0b(VAR ? L.wf0 : xs, VAR ? (long long)(n + 1) * n : 1), w1b(VAR ? L.wf1 : xs, VAR ? (long long)(n + 1) * n : 1);
+  const RowBuf<float> rb32(r32 + off, L.N), eb(e + off, L.N);
   if (i < 2) sx[i == 0 ? 0 : NT + 1] = 0.0;
   auto crow = [&](int r) { return min(max(r, 0), n - 1); };
   // 1 on the grid, 0 off it (a factor, not a select: see k_spmv_r2)
@@ -2893,15 +2941,15 @@ __global__ __launch_bounds__(1024) void k_residual64_2r(LevelDev<double> L, cons
   // j + 1 and f and the faces of row j, as loaded (clamped rows, unmasked)
   double rx[kRowLead], rf[kRowLead], wl[kRowLead], wr[kRowLead], wd[kRowLead], wu[kRowLead];
   auto fill = [&](int j, int s) {
-    const int rw = crow(j) * n + ic;
-    rx[s] = xs[crow(j + 1) * n + ic];
-    rf[s] = fs[rw];
+    const unsigned rw = (unsigned)crow(j) * rowb;
+    rx[s] = xsb.ld(cb, (unsigned)crow(j + 1) * rowb);
+    rf[s] = fsb.ld(cb, rw);
     if (VAR) {
-      const int fx = crow(j) * (n + 1) + ic;
-      wl[s] = L.wf0[fx];
-      wr[s] = L.wf0[fx + 1];
-      wd[s] = L.wf1[rw];
-      wu[s] = L.wf1[rw + n];
+      const unsigned fx = (unsigned)crow(j) * (unsigned)(n + 1) * 8u;
+      wl[s] = w0b.ld(cb, fx);
+      wr[s] = w0b.ld(cb + 8u, fx);
+      wd[s] = w1b.ld(cb, rw);
+      wu[s] = w1b.ld(cb, rw + rowb);
     }
   };
 #pragma unroll
@@ -2918,9 +2966,9 @@ __global__ __launch_bounds__(1024) void k_residual64_2r(LevelDev<double> L, cons
     else ax = wl[s] * (c - lv) + wr[s] * (c - rv) + wd[s] * (c - dn) + wu[s] * (c - up) + sh * c;
     const double rv64 = rf[s] - ax;
     if (col_on) {
-      const long long g = off + row + i;
-      r32[g] = (float)rv64;
-      e[g] = 0.0f;
+      const unsigned g = (unsigned)row * 4u, ib = (unsigned)i * 4u;
+      rb32.template st<false>((float)rv64, ib, g);
+      eb.template st<false>(0.0f, ib, g);
       rr += rv64 * rv64;
     }
     __syncthreads();   // every read of row j's x64 is done
