@@ -725,11 +725,11 @@ void precondition(bura_plan_t P, Work<T>& W, size_t sys0, int nsys, const int* a
         if (l == 0 && ru)
           Launch<T>::fused_down(dim, var, nu1, level_view<T>(P, 0), level_view<T>(P, 1), ru->rold, A(0), bl(1),
                                 shift, active, wpre, nsys, st, ps.ctr, ru->p, ru->alpha, ru->rnew, partial,
-                                ru->fin, P->tile_down[0]);
+                                ru->fin, P->tile_down[0], P->tile_up[0]);
         else
           Launch<T>::fused_down(dim, var, nu1, level_view<T>(P, l), level_view<T>(P, l + 1), bl(l), A(l),
                                 bl(l + 1), shift, active, wpre, nsys, st, ps.ctr, nullptr, nullptr, nullptr,
-                                nullptr, Fin(), P->tile_down[l]);
+                                nullptr, Fin(), P->tile_down[l], P->tile_up[l]);
       }
       if (l == 0 && ru && ru->after) ru->after();
     }

@@ -138,7 +138,8 @@ struct Launch {
   static bool fused_down(int dim, bool var, int nu, const LevelDev<T>& Lf, const LevelDev<T>& Lc, const T* b,
                          T* xout, T* bc, const T* shift, const int* active, Sweeps<T> om, int nsys, hipStream_t st,
                          unsigned long long* ctr, const T* p = nullptr, const double* alpha = nullptr,
-                         T* bout = nullptr, double* partial = nullptr, Fin fin = Fin(), int tv = 0);
+                         T* bout = nullptr, double* partial = nullptr, Fin fin = Fin(), int tv = 0,
+                         int tv_up = 0);
   static bool fused_up(int dim, bool var, int nu, const LevelDev<T>& Lc, const LevelDev<T>& Lf, const T* xc,
                        const T* xin, const T* b, T* xout, const T* shift, const int* active, Sweeps<T> om,
                        double* partial, int nsys, hipStream_t st, unsigned long long* ctr, Fin fin = Fin(),

@@ -1139,6 +1139,10 @@ __device__ __forceinline__ void ring_march(int t0, int t1, Step step) {
 // three sweeps
 template <typename T, bool VAR, int NU>
 constexpr int row_lead() { return sizeof(T) == 8 && VAR ? (NU >= 3 ? 1 : 2) : kRowLead; }
+// the up kernel holds twice the sweeps' rows (it forms the pre-smoothed
+// iterate again): FP64 with variable coefficients keeps one row of lead
+template <typename T, bool VAR, int NU>
+constexpr int up_row_lead() { return sizeof(T) == 8 && VAR ? 1 : kRowLead; }
 // Before a marching loop starts its ring: every load of the set-up has
 // arrived.  The waits inside the loop must suit both the first step and the
 // steady state; with set-up loads still in flight they are computed for the
@@ -1588,7 +1592,10 @@ __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc,
   const int sys = rt.sys;
   constexpr int LEAD = row_lead<T, VAR, NU>();
   if (!active[sys]) return;
-  count_bytes_row(rt, ctr, (unsigned long long)Lf.N * sizeof(T) * (RUP ? 4 : 2) +
+  // xout == nullptr: the pre-smoothed iterate is not stored (the level's up
+  // kernel is k_up2r, which forms it again)
+  const bool keepx = xout != nullptr;
+  count_bytes_row(rt, ctr, (unsigned long long)Lf.N * sizeof(T) * ((RUP ? 3 : 1) + (keepx ? 1 : 0)) +
                                    (unsigned long long)Lc.N * sizeof(T) +
                                    (VAR && sys == 0 ? (unsigned long long)Lf.N * sizeof(T) * 2 : 0ULL));
   const int nf = Lf.n, nc = Lc.n;
@@ -1606,7 +1613,7 @@ __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc,
   const long long off = (long long)sys * Lf.N;
   const T* __restrict__ bs = b + off;
   const T* __restrict__ ps = RUP ? pv + off : nullptr;
-  T* __restrict__ xs = xout + off;
+  T* __restrict__ xs = keepx ? xout + off : nullptr;
   T* __restrict__ bo = RUP ? bout + off : nullptr;
   const RowBuf<T> bsb(bs, Lf.N), psb(RUP ? ps : bs, Lf.N), xsb(xs, Lf.N), bob(RUP ? bo : xs, Lf.N);
   const RowBuf<T> w0b(VAR ? Lf.wf0 : bs, VAR ? (long long)(nf + 1) * nf : 1), w1b(VAR ? Lf.wf1 : bs, VAR ? (long long)(nf + 1) * nf : 1);
@@ -1725,7 +1732,7 @@ __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc,
     const T res = bh[NU] - apply(fw[NU], sx[NU - 1], xh[NU - 1][0], xh[NU - 1][1], xn[NU - 1]);
     // the pre-smoothed iterate: sweep NU's newest row t - NU + 1
     const int gx = t - NU + 1;
-    if (gx >= 2 * K0 && gx < f1 && col_on) xsb.template st<true>(xn[NU - 1], ib, (unsigned)gx * rowb);
+    if (keepx && gx >= 2 * K0 && gx < f1 && col_on) xsb.template st<true>(xn[NU - 1], ib, (unsigned)gx * rowb);
     __syncthreads();   // every read of this step's LDS rows is done
 #pragma unroll
     for (int m = 0; m < NU; ++m) sx[m][q] = xn[m];
@@ -1764,14 +1771,20 @@ __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc,
   }
 }
 
-// k_up2r: the up kernel of k_up2 (same inputs, outputs and arithmetic per
-// point) marching along y over whole grid rows, as k_down2r: at step t the
-// corrected iterate x_in + P x_c of row t enters and sweep m runs on row t - m
-// (the pre-smoothing weights reversed); sweep NU's row t - NU is written on
-// the owned rows [rows s, rows (s + 1)) of segment s (rows: a launch parameter), with b.x
-// when this is the finest level.  Each thread reads the coarse values under
-// its column (the coarse columns left and right of it) from the two coarse
-// rows that bracket fine row t, a coarse row ahead of their use.
+// k_up2r: the up kernel of k_up2 (same output, the same arithmetic per point)
+// marching along y over whole grid rows, as k_down2r, without reading the
+// pre-smoothed iterate: it forms it again from b, as the down kernel did
+// (NU sweeps from zero, the same weights and order), so the down kernel of
+// the level need not store it (8 bytes per point in FP32 less for the pair,
+// 30 -> 22).  2 NU stages lag one row behind each other: at step t row t of
+// b enters, pre-sweep k + 1 runs on row t - k (k < NU; the first one
+// pointwise), the last of them adds P x_c, and post-sweep m on row
+// t - NU + 1 - m (the pre-smoothing weights reversed); post-sweep NU's row
+// t - 2 NU + 1 is written on the owned rows [rows s, rows (s + 1)) of
+// segment s (rows: a launch parameter), with b.x when this is the finest
+// level.  Each thread reads the coarse values under its column (the coarse
+// columns left and right of it) from the two coarse rows that bracket the row
+// where P x_c is added.  xin is not read.
 template <typename T, bool VAR, int NU, bool DOT>
 __global__ __launch_bounds__(1024) void k_up2r(LevelDev<T> Lc, LevelDev<T> Lf, const T* __restrict__ xc,
                                                const T* __restrict__ xin, const T* __restrict__ b,
@@ -1779,13 +1792,15 @@ __global__ __launch_bounds__(1024) void k_up2r(LevelDev<T> Lc, LevelDev<T> Lf, c
                                                const int* __restrict__ active, Sweeps<T> om,
                                                double* __restrict__ partial, unsigned long long* __restrict__ ctr,
                                                Fin fin, int rows) {
+  (void)xin;
   constexpr int LW = 1024 + 2;
-  __shared__ T sx[NU][LW];   // newest row of the correction and of sweeps 1 .. NU-1
+  constexpr int NS = 2 * NU;   // stages: NU pre-sweeps (the last one adds P x_c), NU post-sweeps
+  __shared__ T sx[NS - 1][LW];   // newest row of stages 0 .. NS - 2 (the next stage's left/right neighbours)
   const RowTile rt = row_tile();
   const int sys = rt.sys;
-  constexpr int LEAD = row_lead<T, VAR, NU>();
+  constexpr int LEAD = up_row_lead<T, VAR, NU>();
   if (!active[sys]) return;
-  count_bytes_row(rt, ctr, (unsigned long long)Lf.N * sizeof(T) * 3 + (unsigned long long)Lc.N * sizeof(T) +
+  count_bytes_row(rt, ctr, (unsigned long long)Lf.N * sizeof(T) * 2 + (unsigned long long)Lc.N * sizeof(T) +
                                    (VAR && sys == 0 ? (unsigned long long)Lf.N * sizeof(T) * 2 : 0ULL));
   const int nf = Lf.n, nc = Lc.n;
   const int y0 = rt.seg * rows, y1 = min(y0 + rows, nf);   // owned fine rows
@@ -1798,17 +1813,16 @@ __global__ __launch_bounds__(1024) void k_up2r(LevelDev<T> Lc, LevelDev<T> Lf, c
   const long long off = (long long)sys * Lf.N;
   const T* __restrict__ xcs = xc + (long long)sys * Lc.N;
   const T* __restrict__ bs = b + off;
-  const T* __restrict__ xis = xin + off;
   T* __restrict__ xs = xout + off;
   const unsigned cb = (unsigned)ic * (unsigned)sizeof(T), ib = (unsigned)i * (unsigned)sizeof(T);
   const unsigned rowb = (unsigned)nf * (unsigned)sizeof(T);   // bytes per grid row
-  const RowBuf<T> xcb(xcs, Lc.N), bsb(bs, Lf.N), xib(xis, Lf.N), xsb(xs, Lf.N);
+  const RowBuf<T> xcb(xcs, Lc.N), bsb(bs, Lf.N), xsb(xs, Lf.N);
   const RowBuf<T> w0b(VAR ? Lf.wf0 : bs, VAR ? (long long)(nf + 1) * nf : 1), w1b(VAR ? Lf.wf1 : bs, VAR ? (long long)(nf + 1) * nf : 1);
   const int q = 1 + i;
   if (i < 2) {
     const int pq = i == 0 ? 0 : NT + 1;
 #pragma unroll
-    for (int m = 0; m < NU; ++m) sx[m][pq] = T(0);
+    for (int k = 0; k < NS - 1; ++k) sx[k][pq] = T(0);
   }
   auto row_on = [&](int r) { return col_on && r >= 0 && r < nf; };
   auto crow = [&](int r) { return min(max(r, 0), nf - 1); };
@@ -1854,80 +1868,89 @@ __global__ __launch_bounds__(1024) void k_up2r(LevelDev<T> Lc, LevelDev<T> Lf, c
   };
   // lowest coarse row of fine row t (odd t lies on it, even t halfway to the next)
   auto klo = [](int t) { return (t >> 1) - 1 + (t & 1); };
-  const int t0 = y0 - NU, t1 = y1 + NU - 1;
-  T bh[NU + 1], xh[NU][2], rd[NU + 1];
-  Faces fw[NU + 1];
+  const int t0 = y0 - (NS - 1), t1 = y1 + NS - 2;
+  // registers: bh[d], fw[d], rd[d] = b, faces and inverse diagonal of row
+  // t - d; xh[k][0], xh[k][1] = stage k's output at its newest row of the
+  // previous step and the one below
+  T bh[NS], xh[NS - 1][2], rd[NS];
+  Faces fw[NS];
 #pragma unroll
-  for (int d = 0; d <= NU; ++d) {
+  for (int d = 0; d < NS; ++d) {
     bh[d] = T(0);
     rd[d] = T(0);
     fw[d] = load_faces(t0 - 1 - d);
   }
 #pragma unroll
-  for (int m = 0; m < NU; ++m) xh[m][0] = xh[m][1] = T(0);
+  for (int k = 0; k < NS - 1; ++k) xh[k][0] = xh[k][1] = T(0);
   double dot = 0.0;
   ring_prologue_wait();
   __syncthreads();
-  // the ring of row loads (see kRowLead): slot s of step t holds x_in, b and
-  // the faces of row t and the coarse rows klo(t), klo(t) + 1 at columns ia,
-  // ia + 1, as loaded (clamped, unmasked); a coarse row serves four fine
-  // steps and is loaded for each (the repeats hit the cache)
-  T rx[LEAD], rb[LEAD], rl0[LEAD], rl1[LEAD], rh0[LEAD], rh1[LEAD];
+  // the ring of row loads (see kRowLead): slot s of step t holds b and the
+  // faces of row t and the coarse rows klo(r), klo(r) + 1 at columns ia,
+  // ia + 1 for the row r = t - NU + 1 where P x_c is added, as loaded
+  // (clamped, unmasked); a coarse row serves four fine steps and is loaded
+  // for each (the repeats hit the cache)
+  T rb[LEAD], rl0[LEAD], rl1[LEAD], rh0[LEAD], rh1[LEAD];
   Faces rf[LEAD];
   auto fill = [&](int t, int s) {
-    rx[s] = xib.ld(cb, (unsigned)crow(t) * rowb);
     rb[s] = bsb.ld(cb, (unsigned)crow(t) * rowb);
     rf[s] = load_faces(t);
-    load_c(klo(t), rl0[s], rl1[s]);
-    load_c(klo(t) + 1, rh0[s], rh1[s]);
+    const int r = t - (NU - 1);
+    load_c(klo(r), rl0[s], rl1[s]);
+    load_c(klo(r) + 1, rh0[s], rh1[s]);
   };
 #pragma unroll
   for (int s = 0; s < LEAD; ++s) fill(t0 + s, s);
   ring_march<LEAD>(t0, t1, [&](int t, auto slot) {
     constexpr int s = decltype(slot)::value;
-    T lo0 = rl0[s], lo1 = rl1[s], hi0 = rh0[s], hi1 = rh1[s];
-    mask_c(klo(t), lo0, lo1);
-    mask_c(klo(t) + 1, hi0, hi1);
 #pragma unroll
-    for (int d = NU; d > 0; --d) {
+    for (int d = NS - 1; d > 0; --d) {
       bh[d] = bh[d - 1];
       fw[d] = fw[d - 1];
       rd[d] = rd[d - 1];
     }
     if (VAR) fw[0] = Faces{ring_take(rf[s].l), ring_take(rf[s].r), ring_take(rf[s].d), ring_take(rf[s].u)};
     rd[0] = rdiag(fw[0], t);
-    // stage 0 on row t: x_in + P x_c (multilinear, the expressions of k_up2)
-    const bool on = row_on(t);
+    bh[0] = row_on(t) ? rb[s] : T(0);
+    // P x_c on row r = t - NU + 1 (multilinear, the expressions of k_up2)
+    const int r = t - (NU - 1);
+    T lo0 = rl0[s], lo1 = rl1[s], hi0 = rh0[s], hi1 = rh1[s];
+    mask_c(klo(r), lo0, lo1);
+    mask_c(klo(r) + 1, hi0, hi1);
     T v;
     if (i & 1) {
-      v = (t & 1) ? lo0 : T(0.5) * (lo0 + hi0);
+      v = (r & 1) ? lo0 : T(0.5) * (lo0 + hi0);
     } else {
-      v = (t & 1) ? T(0.5) * (lo0 + lo1) : T(0.25) * (lo0 + lo1 + hi0 + hi1);
+      v = (r & 1) ? T(0.5) * (lo0 + lo1) : T(0.25) * (lo0 + lo1 + hi0 + hi1);
     }
-    bh[0] = on ? rb[s] : T(0);
-    T xn[NU + 1];
-    xn[0] = on ? rx[s] + v : T(0);
-    // sweep m on row t - m from stage m - 1's output (centre row in
-    // sx[m - 1], below in xh, above just formed)
+    // stage k on row t - k from stage k - 1's output (centre row in
+    // sx[k - 1], below in xh, above just formed); the pre-sweeps are those
+    // of the down kernel (zero start, the first one pointwise)
+    T xn[NS];
+    xn[0] = sweep_w(om, 0) * bh[0] * rd[0];
 #pragma unroll
-    for (int m = 1; m <= NU; ++m) {
-      const T ax = apply(fw[m], sx[m - 1], xh[m - 1][0], xh[m - 1][1], xn[m - 1]);
-      xn[m] = xh[m - 1][0] + sweep_w(om, NU - m) * (bh[m] - ax) * rd[m];
+    for (int k = 0; k < NS; ++k) {
+      if (k > 0) {
+        const T ax = apply(fw[k], sx[k - 1], xh[k - 1][0], xh[k - 1][1], xn[k - 1]);
+        const T w = k < NU ? sweep_w(om, k) : sweep_w(om, NS - 1 - k);
+        xn[k] = xh[k - 1][0] + w * (bh[k] - ax) * rd[k];
+      }
+      if (k == NU - 1) xn[k] = row_on(r) ? xn[k] + v : T(0);   // x_pre + P x_c
     }
-    const int g = t - NU;
+    const int g = t - (NS - 1);
     if (g >= y0 && g < y1 && col_on) {
-      xsb.template st<true>(xn[NU], ib, (unsigned)g * rowb);
-      if (DOT) dot += (double)bh[NU] * (double)xn[NU];
+      xsb.template st<true>(xn[NS - 1], ib, (unsigned)g * rowb);
+      if (DOT) dot += (double)bh[NS - 1] * (double)xn[NS - 1];
     }
     __syncthreads();   // every read of this step's LDS rows is done
 #pragma unroll
-    for (int m = 0; m < NU; ++m) sx[m][q] = xn[m];
+    for (int k = 0; k < NS - 1; ++k) sx[k][q] = xn[k];
     __syncthreads();
     fill(t + LEAD, s);   // refill the slot with row t + LEAD
 #pragma unroll
-    for (int m = 0; m < NU; ++m) {
-      xh[m][1] = xh[m][0];
-      xh[m][0] = xn[m];
+    for (int k = 0; k < NS - 1; ++k) {
+      xh[k][1] = xh[k][0];
+      xh[k][0] = xn[k];
     }
   });
   if (DOT) {
@@ -3556,7 +3579,7 @@ template <typename T>
 bool Launch<T>::fused_down(int dim, bool var, int nu, const LevelDev<T>& Lf, const LevelDev<T>& Lc, const T* b,
                            T* xout, T* bc, const T* shift, const int* active, Sweeps<T> om, int nsys, hipStream_t st,
                            unsigned long long* ctr, const T* p, const double* alpha, T* bout, double* partial,
-                           Fin fin, int tv) {
+                           Fin fin, int tv, int tv_up) {
   const bool rup = bout != nullptr;
   if (dim == 3) {
     if (var || nu < 1 || nu > 2) return false;
@@ -3574,6 +3597,7 @@ bool Launch<T>::fused_down(int dim, bool var, int nu, const LevelDev<T>& Lf, con
   }
   if (dim != 2 || nu < 1 || nu > 3) return false;
   if (down_rows(dim, Lf.n, tv)) {
+    if (up_rows(dim, Lf.n, tv_up)) xout = nullptr;   // k_up2r forms the pre-smoothed iterate again
     const int ky = rows_seg(tv) / 2;
     const dim3 g = rows_grid((Lc.n + ky - 1) / ky, nsys), blk(rows_threads(Lf.n));
 #define K_DR0(V, NU_, R_)                                                                                     \

@@ -131,6 +131,8 @@ ROW_CASES = [
     (127, True, "MIXED", 3),
     (191, False, "MIXED", 3),
     (255, True, "FP64", 1),
+    (127, True, "FP64", 3),
+    (191, True, "FP64", 2),
 ]
 
 
