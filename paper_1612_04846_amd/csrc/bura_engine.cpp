@@ -1032,15 +1032,23 @@ int mixed_outer_loop(bura_plan_t P, const double* f, int nrhs, size_t sys0, int 
     // deferred update (k_finish_x is not launched)
     const bool fx = P->foldxr;
     if ((rc = run_pcg<float>(P, W, sys0, nsys, P->opts.inner_tol, P->opts.max_iter, fx))) return rc;
-    {
-      ProfScope ps(P, BURA_K_OTHER);
-      launch_x_from_e(L0, P->dim, W.x + o, P->x64 + o, S.active64, nsys, st, fx ? W.p + o : nullptr,
-                      fx ? W.p2 + o : nullptr, S.alpha, S.iters);
-    }
-    {
+    if (residual_marches_rows(P->dim, P->n, nsys)) {
+      // x64 += e and the FP64 residual in one pass where the residual marches rows
       ProfScope ps(P, BURA_K_RESIDUAL64);
-      launch_residual64(P->dim, P->var, L0, f, P->x64 + o, W.x + o, W.r + o, P->d_shift64 + sys0, S.active64,
-                        P->partial, nrhs, nsys, false, st, ps.ctr);
+      launch_update_residual64(P->dim, P->var, L0, f, P->x64 + o, W.x + o, W.r + o, P->d_shift64 + sys0, S.active64,
+                               P->partial, nrhs, nsys, st, ps.ctr, fx ? W.p + o : nullptr, fx ? W.p2 + o : nullptr,
+                               S.alpha, S.iters);
+    } else {
+      {
+        ProfScope ps(P, BURA_K_OTHER);
+        launch_x_from_e(L0, P->dim, W.x + o, P->x64 + o, S.active64, nsys, st, fx ? W.p + o : nullptr,
+                        fx ? W.p2 + o : nullptr, S.alpha, S.iters);
+      }
+      {
+        ProfScope ps(P, BURA_K_RESIDUAL64);
+        launch_residual64(P->dim, P->var, L0, f, P->x64 + o, W.x + o, W.r + o, P->d_shift64 + sys0, S.active64,
+                          P->partial, nrhs, nsys, false, st, ps.ctr);
+      }
     }
     {
       ProfScope ps(P, BURA_K_OTHER);

@@ -2923,49 +2923,86 @@ __global__ __launch_bounds__(kBlock) void k_residual64_2(LevelDev<double> L, con
 // k_residual64_2.
 constexpr int kRes2rRows = 128;
 
-template <bool VAR>
+// With UPD the kernel first applies the inner solve's correction, as
+// k_x_from_e does (x64 += e, e taking the pending update e + alpha p when
+// pa != nullptr), to every row it reads, and forms the residual of the
+// updated iterate: one pass instead of two.  It writes the updated x64 and
+// clears e on its own rows except the first and last one of its segment;
+// those are the rows a neighbouring workgroup reads (with their old x64
+// and e), and k_update_seg_rows updates and clears them after this kernel.
+struct XUpdate {
+  const float* pa;      // nullptr: e alone
+  const float* pb;
+  const double* alpha;
+  const int* iters;
+};
+template <bool VAR, bool UPD>
 __global__ __launch_bounds__(1024) void k_residual64_2r(LevelDev<double> L, const double* __restrict__ f,
-                                                        const double* __restrict__ x64, float* __restrict__ e,
+                                                        double* __restrict__ x64, float* __restrict__ e,
                                                         float* __restrict__ r32, const double* __restrict__ shift,
                                                         const int* __restrict__ active64, int nrhs,
                                                         double* __restrict__ partial,
-                                                        unsigned long long* __restrict__ ctr) {
+                                                        unsigned long long* __restrict__ ctr, XUpdate xu) {
   constexpr int LW = 1024 + 2;
   __shared__ double sx[LW];   // x64 of the current row, zero pads at columns -1 and blockDim.x
   const RowTile rt = row_tile();
   const int sys = rt.sys, seg = rt.seg;
   if (!active64[sys]) return;
-  count_bytes_row(rt, ctr, (unsigned long long)L.N * (8 + 8 + 4 + 4 + (VAR && sys == 0 ? 16 : 0)));
+  count_bytes_row(rt, ctr, (unsigned long long)L.N * (8 + 8 + 4 + 4 + (UPD ? 8 + 4 : 0) + (VAR && sys == 0 ? 16 : 0)));
   const int n = L.n;
   const int i = threadIdx.x, NT = blockDim.x;
   const int j0 = seg * kRes2rRows, j1 = min(j0 + kRes2rRows, n);
   const bool col_on = i < n;
   const int ic = min(i, n - 1), q = 1 + i;
   const long long off = (long long)sys * L.N;
-  const double* __restrict__ xs = x64 + off;
+  double* __restrict__ xs = x64 + off;
   const double* __restrict__ fs = f + (long long)(sys % nrhs) * L.N;
   const double sh = shift[sys];
   const unsigned cb = (unsigned)ic * 8u, rowb = (unsigned)n * 8u;
   const RowBuf<double> xsb(xs, L.N), fsb(fs, L.N);
   const RowBuf<double> w0b(VAR ? L.wf0 : xs, VAR ? (long long)(n + 1) * n : 1), w1b(VAR ? L.wf1 : xs, VAR ? (long long)(n + 1) * n : 1);
   const RowBuf<float> rb32(r32 + off, L.N), eb(e + off, L.N);
+  // the pending update of the inner solve (UPD)
+  const int its = UPD && xu.pa ? xu.iters[sys] : 0;
+  const float a = UPD && xu.pa ? (float)xu.alpha[sys] : 0.0f;
+  const bool pend = its > 0 && a != 0.0f;
+  const float* pl = pend ? (((its - 1) & 1) ? xu.pa : xu.pb) + off : e + off;
+  const RowBuf<float> plb(pl, L.N);
   if (i < 2) sx[i == 0 ? 0 : NT + 1] = 0.0;
   auto crow = [&](int r) { return min(max(r, 0), n - 1); };
   // 1 on the grid, 0 off it (a factor, not a select: see k_spmv_r2)
   auto on_f = [&](int r) { return (col_on && r >= 0 && r < n) ? 1.0 : 0.0; };
+  // the iterate of a row from its loads (UPD: x64 + e, the arithmetic of k_x_from_e)
+  auto xnew = [&](double xv, float ev, float pv) {
+    if (!UPD) return xv;
+    const float en = pend ? ev + a * pv : ev;
+    return xv + (double)en;
+  };
+  auto ldrow = [&](int r) {
+    const unsigned o = (unsigned)crow(r) * rowb, o4 = (unsigned)crow(r) * (unsigned)n * 4u;
+    const double xv = xsb.ld(cb, o);
+    const float ev = UPD ? eb.ld(cb / 2, o4) : 0.0f, pv = UPD && pend ? plb.ld(cb / 2, o4) : 0.0f;
+    return xnew(xv, ev, pv) * on_f(r);
+  };
   // x64 of rows j - 1, j, j + 1 during step j (dn, c, up); before the first
   // step c and up hold rows j0 - 1 and j0
-  double dn = 0.0, c = xs[crow(j0 - 1) * n + ic] * on_f(j0 - 1), up = xs[j0 * n + ic] * on_f(j0);
+  double dn = 0.0, c = ldrow(j0 - 1), up = ldrow(j0);
   sx[q] = up;
   double rr = 0.0;
   ring_prologue_wait();
   __syncthreads();
-  // the ring of row loads (see kRowLead): slot s of step j holds x64 of row
-  // j + 1 and f and the faces of row j, as loaded (clamped rows, unmasked)
+  // the ring of row loads (see kRowLead): slot s of step j holds x64 (UPD:
+  // and e, p) of row j + 1 and f and the faces of row j, as loaded (clamped
+  // rows, unmasked)
   double rx[kRowLead], rf[kRowLead], wl[kRowLead], wr[kRowLead], wd[kRowLead], wu[kRowLead];
+  float re[kRowLead], rp[kRowLead];
   auto fill = [&](int j, int s) {
-    const unsigned rw = (unsigned)crow(j) * rowb;
-    rx[s] = xsb.ld(cb, (unsigned)crow(j + 1) * rowb);
+    const unsigned rw = (unsigned)crow(j) * rowb, ra = (unsigned)crow(j + 1) * rowb;
+    rx[s] = xsb.ld(cb, ra);
+    if (UPD) {
+      re[s] = eb.ld(cb / 2, ra / 2);
+      rp[s] = pend ? plb.ld(cb / 2, ra / 2) : 0.0f;
+    }
     rf[s] = fsb.ld(cb, rw);
     if (VAR) {
       const unsigned fx = (unsigned)crow(j) * (unsigned)(n + 1) * 8u;
@@ -2982,7 +3019,7 @@ __global__ __launch_bounds__(1024) void k_residual64_2r(LevelDev<double> L, cons
     const int row = j * n;   // 2D grids: fewer than 2^31 points
     dn = c;
     c = up;
-    up = rx[s] * on_f(j + 1);
+    up = xnew(rx[s], UPD ? re[s] : 0.0f, UPD ? rp[s] : 0.0f) * on_f(j + 1);
     const double lv = sx[q - 1], rv = sx[q + 1];
     double ax;
     if (!VAR) ax = L.wc * ((c - lv) + (c - rv) + (c - dn) + (c - up)) + sh * c;
@@ -2991,7 +3028,11 @@ __global__ __launch_bounds__(1024) void k_residual64_2r(LevelDev<double> L, cons
     if (col_on) {
       const unsigned g = (unsigned)row * 4u, ib = (unsigned)i * 4u;
       rb32.template st<false>((float)rv64, ib, g);
-      eb.template st<false>(0.0f, ib, g);
+      // UPD: the segment's first and last rows are left to k_update_seg_rows
+      if (!UPD || (j != j0 && j != j1 - 1)) {
+        eb.template st<false>(0.0f, ib, g);
+        if (UPD) xsb.template st<false>(c, 2u * ib, 2u * g);
+      }
       rr += rv64 * rv64;
     }
     __syncthreads();   // every read of row j's x64 is done
@@ -3000,6 +3041,32 @@ __global__ __launch_bounds__(1024) void k_residual64_2r(LevelDev<double> L, cons
     fill(j + kRowLead, s);
   });
   write_partial(partial, sys, rr, seg, rt.nseg);
+}
+
+// After k_residual64_2r<.., true>: x64 += e (with the pending update, as
+// there) and e = 0 on the first and last row of every row segment.  One
+// workgroup per system and such row, one thread per column.
+__global__ __launch_bounds__(1024) void k_update_seg_rows(long long N, int n, double* __restrict__ x64,
+                                                          float* __restrict__ e, const int* __restrict__ active64,
+                                                          XUpdate xu) {
+  const int sys = blockIdx.z;
+  if (!active64[sys]) return;
+  const int k = blockIdx.y;   // row 2 s or 2 s + 1 of segment s: its first or last row
+  const int j0 = (k / 2) * kRes2rRows, j1 = min(j0 + kRes2rRows, n);
+  const int j = (k & 1) ? j1 - 1 : j0;
+  const int i = threadIdx.x;
+  if (i >= n || ((k & 1) && j == j0)) return;   // a one-row segment: its row once
+  const int its = xu.pa ? xu.iters[sys] : 0;
+  const float a = xu.pa ? (float)xu.alpha[sys] : 0.0f;
+  const bool pend = its > 0 && a != 0.0f;
+  const long long g = (long long)sys * N + (long long)j * n + i;
+  float en = e[g];
+  if (pend) {
+    const float* pl = ((its - 1) & 1) ? xu.pa : xu.pb;
+    en = en + a * pl[g];
+  }
+  x64[g] = x64[g] + (double)en;
+  e[g] = 0.0f;
 }
 
 // the FP64 residual of a 2D batch of nsys systems walks whole rows when the
@@ -3759,11 +3826,13 @@ void launch_residual64(int dim, bool var, const LevelDev<double>& L, const doubl
                          ctr);
   } else if (residual_rows(dim, L.n, nsys)) {
     const dim3 g = rows_grid((L.n + kRes2rRows - 1) / kRes2rRows, nsys), blk(rows_threads(L.n));
+    double* x = const_cast<double*>(x64);   // not written without the update
     if (var)
-      hipLaunchKernelGGL((k_residual64_2r<true>), g, blk, 0, st, L, f, x64, e, r32, shift, active64, nrhs, partial, ctr);
+      hipLaunchKernelGGL((k_residual64_2r<true, false>), g, blk, 0, st, L, f, x, e, r32, shift, active64, nrhs, partial,
+                         ctr, XUpdate{});
     else
-      hipLaunchKernelGGL((k_residual64_2r<false>), g, blk, 0, st, L, f, x64, e, r32, shift, active64, nrhs, partial,
-                         ctr);
+      hipLaunchKernelGGL((k_residual64_2r<false, false>), g, blk, 0, st, L, f, x, e, r32, shift, active64, nrhs,
+                         partial, ctr, XUpdate{});
   } else {
     constexpr int rows_per_block = (kBlock / kRes2Cols) * kRes2Rows;
     const dim3 g2((L.n + kRes2Cols - 1) / kRes2Cols, (L.n + rows_per_block - 1) / rows_per_block, nsys);
@@ -3774,6 +3843,26 @@ void launch_residual64(int dim, bool var, const LevelDev<double>& L, const doubl
       hipLaunchKernelGGL((k_residual64_2<false>), g2, b2, 0, st, L, f, x64, e, r32, shift, active64, nrhs, partial,
                          ctr);
   }
+}
+
+bool residual_marches_rows(int dim, int n, long long nsys) { return residual_rows(dim, n, nsys); }
+
+bool launch_update_residual64(int dim, bool var, const LevelDev<double>& L, const double* f, double* x64, float* e,
+                              float* r32, const double* shift, const int* active64, double* partial, int nrhs,
+                              int nsys, hipStream_t st, unsigned long long* ctr, const float* pa, const float* pb,
+                              const double* alpha, const int* iters) {
+  if (!residual_rows(dim, L.n, nsys)) return false;
+  const int nseg = (L.n + kRes2rRows - 1) / kRes2rRows;
+  const dim3 g = rows_grid(nseg, nsys), blk(rows_threads(L.n));
+  const XUpdate xu{pa, pb, alpha, iters};
+  if (var)
+    hipLaunchKernelGGL((k_residual64_2r<true, true>), g, blk, 0, st, L, f, x64, e, r32, shift, active64, nrhs, partial,
+                       ctr, xu);
+  else
+    hipLaunchKernelGGL((k_residual64_2r<false, true>), g, blk, 0, st, L, f, x64, e, r32, shift, active64, nrhs,
+                       partial, ctr, xu);
+  hipLaunchKernelGGL(k_update_seg_rows, dim3(1, 2 * nseg, nsys), blk, 0, st, L.N, L.n, x64, e, active64, xu);
+  return true;
 }
 
 int residual_blocks(int dim, int n, long long nsys) {
