@@ -1574,7 +1574,9 @@ __global__ __launch_bounds__(256) void k_up2(LevelDev<T> Lc, LevelDev<T> Lf, con
 // times their points (halo rows and columns, partial cache lines) and sweep
 // that many.  Columns past the grid and rows outside it carry a zero
 // right-hand side and a zero inverse diagonal, so they stay exactly 0; the
-// LDS rows have a zero pad on each side.  Two barriers per row.
+// LDS rows have a zero pad on each side.  Two barriers per row.  With xout
+// == nullptr the pre-smoothed iterate is not stored (the level's up kernel
+// is k_up2r, which forms it again).
 // --------------------------------------------------------------------------
 template <typename T, bool VAR, int NU, bool RUP>
 __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc, const T* __restrict__ b,
