@@ -1087,6 +1087,9 @@ constexpr int kRowsSeg = 128, kShortRowsSeg = 32;   // fine rows per workgroup
 // load used in the step that issued it (or copied at its end) makes the wave
 // wait there for every load in flight: one memory round trip per row.
 constexpr int kRowLead = 3;
+// the lead of the 3D marching kernels, in planes (a plane's loads are
+// several points per thread)
+constexpr int kPlaneLead = 2;
 // A copy of a value the register allocator cannot merge with its source:
 // the ring slot the source came from is free after it, so the refill load
 // can go into the same register and no copy at the loop's end waits on it.
@@ -2122,27 +2125,27 @@ __global__ __launch_bounds__(kF3Threads) void k_down3(LevelDev<T> Lf, LevelDev<T
   T* __restrict__ xs = xout + off;
   T* __restrict__ bo = RUP ? bout + off : nullptr;
   double rr = 0.0;
-  // b of the next plane is loaded a step ahead, so its latency overlaps a step
-  T bnx[PER];
-  {
-    const long long b0 = (long long)min(max(t0, 0), nf - 1) * nn;
-#pragma unroll
-    for (int u = 0; u < PER; ++u) bnx[u] = bs[b0 + col[u]];
-  }
+  ring_prologue_wait();
   __syncthreads();
-  for (int t = t0; t <= t1; ++t) {
-    const long long base = (long long)min(max(t, 0), nf - 1) * nn;
-    // the loads of the step: b(t + 1) for the next step, and p(t + 2) (RUP)
-    T bl[PER], pn[RUP ? PPER : 1];
-    {
-      const long long bb = (long long)min(max(t + 1, 0), nf - 1) * nn;
+  // the ring of plane loads (see kRowLead; kPlaneLead planes ahead): slot s
+  // of step t holds b of plane t and p of plane t + 2 (RUP), as loaded
+  // (clamped planes, unmasked)
+  T rbv[kPlaneLead][PER], rpv[kPlaneLead][RUP ? PPER : 1];
+  auto fill = [&](int t, int s) {
+    const long long bb = (long long)min(max(t, 0), nf - 1) * nn;
 #pragma unroll
-      for (int u = 0; u < PER; ++u) {
-        bl[u] = bnx[u];
-        bnx[u] = bs[bb + col[u]];
-      }
+    for (int u = 0; u < PER; ++u) rbv[s][u] = bs[bb + col[u]];
+    if (RUP) {
+      const long long pb = (long long)min(max(t + 2, 0), nf - 1) * nn;
+#pragma unroll
+      for (int u = 0; u < PPER; ++u) rpv[s][u] = ps[pb + pcol[u]];
     }
-    if (RUP) load_p(t + 2, pn);
+  };
+#pragma unroll
+  for (int s = 0; s < kPlaneLead; ++s) fill(t0 + s, s);
+  ring_march<kPlaneLead>(t0, t1, [&](int t, auto sl) {
+    constexpr int s = decltype(sl)::value;
+    const long long base = (long long)min(max(t, 0), nf - 1) * nn;
     // in-grid mask of plane g for point u (0 off the grid, above and below it)
     auto on_at = [&](int g, int u) { return g >= 0 && g < nf && ((in >> u) & 1u); };
 #pragma unroll
@@ -2152,12 +2155,12 @@ __global__ __launch_bounds__(kF3Threads) void k_down3(LevelDev<T> Lf, LevelDev<T
     const bool wr_t = RUP && t >= 2 * K0 && t < fz1;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      T bn = bl[u];
+      T bn = rbv[s][u];
       if (RUP) {
         const int q = tid + kF3Threads * u;
         const int ry = q / RX, rx = q - ry * RX;
         const int pq = PADP + (ry + 1) * PX + (rx + 1);
-        bn = bl[u] - am * lds_apply3<T>(sp[slot(t)], pq, PX, sp[slot(t - 1)][pq], sp[slot(t + 1)][pq], w, sh);
+        bn = bn - am * lds_apply3<T>(sp[slot(t)], pq, PX, sp[slot(t - 1)][pq], sp[slot(t + 1)][pq], w, sh);
       }
       bh[0][u] = on_at(t, u) ? bn : T(0);
       if (wr_t && ((own >> u) & 1u)) {
@@ -2203,11 +2206,14 @@ __global__ __launch_bounds__(kF3Threads) void k_down3(LevelDev<T> Lf, LevelDev<T
       for (int m = 0; m < NU; ++m) sx[m][q] = xn[m][u];
       sr[q] = res[u];
     }
-    if (RUP) {   // p(t + 2) takes the slot of p(t - 1)
+    if (RUP) {   // p(t + 2) takes the slot of p(t - 1) (0 off the grid)
+      const bool zin = t + 2 >= 0 && t + 2 < nf;
 #pragma unroll
-      for (int u = 0; u < PPER; ++u) sp[slot(t + 2)][PADP + tid + kF3Threads * u] = pn[u];
+      for (int u = 0; u < PPER; ++u)
+        sp[slot(t + 2)][PADP + tid + kF3Threads * u] = (zin && ((pin >> u) & 1u)) ? rpv[s][u] : T(0);
     }
     __syncthreads();
+    fill(t + kPlaneLead, s);   // refill the slot with the planes kPlaneLead steps ahead
     // full weighting: this coarse column's in-plane sum of fine plane f = t - NU,
     // and coarse plane K = f/2 - 1 once f = 2K + 2 (weights 1/4, 1/2, 1/4 along z)
     const int f = t - NU;
@@ -2219,15 +2225,14 @@ __global__ __launch_bounds__(kF3Threads) void k_down3(LevelDev<T> Lf, LevelDev<T
         const int di = q % 3, dj = q / 3;
         acc += wt[dj] * wt[di] * sr[rcq + dj * RX + di];
       }
-      if (f == 2 * K0) {
-        s_lo = acc;
-      } else if (f & 1) {
-        s_mid = acc;
-      } else {
+      const bool odd = f & 1;
+      if (!odd && f != 2 * K0) {
         const int K = f / 2 - 1;
         if (mine) bcs[K * ncc] = T(0.25) * s_lo + T(0.5) * s_mid + T(0.25) * acc;
-        s_lo = acc;
       }
+      // selects, not stores in two branches (see k_down2r)
+      s_mid = odd ? acc : s_mid;
+      s_lo = odd ? s_lo : acc;
     }
     // shift the registers one plane up
 #pragma unroll
@@ -2238,7 +2243,7 @@ __global__ __launch_bounds__(kF3Threads) void k_down3(LevelDev<T> Lf, LevelDev<T
         xh[m][0][u] = xn[m][u];
       }
     }
-  }
+  });
   if (RUP) {
     write_partial_tile(tl, partial, sys, rr);
     finish(fin, partial, sys, gridDim.x * gridDim.y);
@@ -2357,28 +2362,32 @@ __global__ __launch_bounds__(kF3Threads) void k_up3(LevelDev<T> Lc, LevelDev<T> 
   }
   T* __restrict__ xs = xout + off;
   double dot = 0.0;
-  // x_in and b of the next plane are loaded a step ahead
-  T xnx[PER], bnx[PER];
-  {
-    const long long b0 = (long long)min(max(t0, 0), nf - 1) * nn;
+  ring_prologue_wait();
+  __syncthreads();
+  // the ring of plane loads (see kRowLead; kPlaneLead planes ahead): slot s
+  // of step t holds x_in and b of plane t and the coarse plane klo(t + 1) + 1
+  // under the region (staged at step t when klo(t + 1) > klo(t)), as loaded
+  // (clamped, unmasked)
+  T rxv[kPlaneLead][PER], rbv[kPlaneLead][PER], rcv[kPlaneLead][CPER];
+  auto fill = [&](int t, int s) {
+    const long long bb = (long long)min(max(t, 0), nf - 1) * nn;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      xnx[u] = xis[b0 + col[u]];
-      bnx[u] = bs[b0 + col[u]];
+      rxv[s][u] = xis[bb + col[u]];
+      rbv[s][u] = bs[bb + col[u]];
     }
-  }
-  for (int t = t0; t <= t1; ++t) {
-    T xl[PER], bl[PER];
-    {
-      const long long bb = (long long)min(max(t + 1, 0), nf - 1) * nn;
+    const long long cb = (long long)min(max(klo(t + 1) + 1, 0), nc - 1) * ncc;
 #pragma unroll
-      for (int u = 0; u < PER; ++u) {
-        xl[u] = xnx[u];
-        bl[u] = bnx[u];
-        xnx[u] = xis[bb + col[u]];
-        bnx[u] = bs[bb + col[u]];
-      }
+    for (int u = 0; u < CPER; ++u) {
+      const int q = tid + kF3Threads * u;
+      const int cy = q / CRX, cx = q - cy * CRX;
+      rcv[s][u] = xcs[cb + (long long)min(max(cy0 + cy, 0), nc - 1) * nc + min(max(cx0 + cx, 0), nc - 1)];
     }
+  };
+#pragma unroll
+  for (int s = 0; s < kPlaneLead; ++s) fill(t0 + s, s);
+  ring_march<kPlaneLead>(t0, t1, [&](int t, auto sl) {
+    constexpr int s = decltype(sl)::value;
     auto on_at = [&](int g, int u) { return g >= 0 && g < nf && ((in >> u) & 1u); };
     if (klo(t) > Kc) {   // sc holds coarse plane Kc + 2 (staged in the previous step)
       ++Kc;
@@ -2397,9 +2406,9 @@ __global__ __launch_bounds__(kF3Threads) void k_up3(LevelDev<T> Lc, LevelDev<T> 
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const bool on = on_at(t, u);
-      bh[0][u] = on ? bl[u] : T(0);
+      bh[0][u] = on ? rbv[s][u] : T(0);
       const T v = (t & 1) ? vlo[u] : T(0.5) * (vlo[u] + vhi[u]);
-      xn[0][u] = on ? xl[u] + v : T(0);
+      xn[0][u] = on ? rxv[s][u] + v : T(0);
     }
 #pragma unroll
     for (int m = 1; m <= NU; ++m) {
@@ -2428,8 +2437,20 @@ __global__ __launch_bounds__(kF3Threads) void k_up3(LevelDev<T> Lc, LevelDev<T> 
 #pragma unroll
       for (int m = 0; m < NU; ++m) sx[m][q] = xn[m][u];
     }
-    if (klo(t + 1) > Kc) stage(Kc + 2);
+    if (klo(t + 1) > Kc) {   // coarse plane Kc + 2 into sc (0 off the grid)
+      const int K = Kc + 2;
+#pragma unroll
+      for (int u = 0; u < CPER; ++u) {
+        const int q = tid + kF3Threads * u;
+        if (q < CRN) {
+          const int cy = q / CRX, cx = q - cy * CRX;
+          const int I = cx0 + cx, J = cy0 + cy;
+          sc[q] = (K >= 0 && K < nc && I >= 0 && I < nc && J >= 0 && J < nc) ? rcv[s][u] : T(0);
+        }
+      }
+    }
     __syncthreads();
+    fill(t + kPlaneLead, s);   // refill the slot with the planes kPlaneLead steps ahead
 #pragma unroll
     for (int u = 0; u < PER; ++u)
 #pragma unroll
@@ -2437,7 +2458,7 @@ __global__ __launch_bounds__(kF3Threads) void k_up3(LevelDev<T> Lc, LevelDev<T> 
         xh[m][1][u] = xh[m][0][u];
         xh[m][0][u] = xn[m][u];
       }
-  }
+  });
   if (DOT) {
     write_partial_tile(tl, partial, sys, dot);
     finish(fin, partial, sys, gridDim.x * gridDim.y);
