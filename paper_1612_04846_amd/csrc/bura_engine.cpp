@@ -1480,7 +1480,10 @@ struct TileChoice {
 std::mutex g_tile_mu;
 std::map<std::string, TileChoice> g_tile_cache;
 
-constexpr int kTuneMinN = 255;
+// (127: the 511^2 workload's third level, 2048 systems, runs 0.5 - 1 % of
+// the solve faster with the row-marching kernels, which the default rule
+// keeps to levels of at least 255 points)
+constexpr int kTuneMinN = 127;
 // interleaved timings per variant (the minimum counts), and how much faster
 // than the default a variant must be to replace it: whole solves of a
 // batched plan repeat to about 0.3 %, and the shapes that win on the largest
