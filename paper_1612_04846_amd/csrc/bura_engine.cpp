@@ -1014,7 +1014,9 @@ int solve_batch_fp64(bura_plan_t P, const double* f, int nrhs, size_t sys0, int 
 // The refinement loop of a mixed batch (the FP64 residual of every active
 // system already formed and tested): FP32 inner solves on the active systems,
 // x64 += e, the FP64 residual and the outer test, until no system is active.
-int mixed_outer_loop(bura_plan_t P, const double* f, int nrhs, size_t sys0, int nsys) {
+// x_zero: x64 was not cleared (k_first_residual with zero_x false) and the
+// first update assigns it (the fused update and residual pass only)
+int mixed_outer_loop(bura_plan_t P, const double* f, int nrhs, size_t sys0, int nsys, bool x_zero = false) {
   hipStream_t st = P->stream;
   Work<float>& W = P->w32;
   const LevelDev<double> L0 = level_view<double>(P, 0);
@@ -1037,7 +1039,7 @@ int mixed_outer_loop(bura_plan_t P, const double* f, int nrhs, size_t sys0, int 
       ProfScope ps(P, BURA_K_RESIDUAL64);
       launch_update_residual64(P->dim, P->var, L0, f, P->x64 + o, W.x + o, W.r + o, P->d_shift64 + sys0, S.active64,
                                P->partial, nrhs, nsys, st, ps.ctr, fx ? W.p + o : nullptr, fx ? W.p2 + o : nullptr,
-                               S.alpha, S.iters);
+                               S.alpha, S.iters, x_zero && outer == 0);
     } else {
       {
         ProfScope ps(P, BURA_K_OTHER);
@@ -1076,16 +1078,19 @@ int solve_batch_mixed(bura_plan_t P, const double* f, int nrhs, size_t sys0, int
                           P->stream));
   }
   launch_zero(S.alpha, (size_t)nsys * sizeof(double), st);   // see solve_batch_fp64
+  // with the fused update and residual pass the first update assigns x64,
+  // so the first residual need not clear it
+  const bool x_zero = residual_marches_rows(P->dim, P->n, nsys);
   {
     ProfScope ps(P, BURA_K_RESIDUAL64);
     launch_residual64(P->dim, P->var, L0, f, P->x64 + o, W.x + o, W.r + o, P->d_shift64 + sys0, S.active64,
-                      P->partial, nrhs, nsys, true, st, ps.ctr);
+                      P->partial, nrhs, nsys, true, st, ps.ctr, !x_zero);
   }
   {
     ProfScope ps(P, BURA_K_OTHER);
     launch_scalars(OP_OUTER, P->partial, flat_blocks(P->N), nsys, S, P->run_tol, P->opts.max_outer, st);
   }
-  return mixed_outer_loop(P, f, nrhs, sys0, nsys);
+  return mixed_outer_loop(P, f, nrhs, sys0, nsys, x_zero);
 }
 
 // Continue the refinement of the systems of [sys0, sys0 + nsys) flagged in

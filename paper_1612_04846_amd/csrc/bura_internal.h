@@ -151,7 +151,7 @@ struct Launch {
 // FP64-only steps of the refinement loop and the combine.
 void launch_residual64(int dim, bool var, const LevelDev<double>& L, const double* f, const double* x64, float* e,
                        float* r32, const double* shift, const int* active64, double* partial, int nrhs, int nsys,
-                       bool first, hipStream_t st, unsigned long long* ctr);
+                       bool first, hipStream_t st, unsigned long long* ctr, bool zero_x = true);
 // whether the FP64 residual of nsys systems on a level of n points per axis
 // marches whole rows (then launch_update_residual64 applies)
 bool residual_marches_rows(int dim, int n, long long nsys);
@@ -161,7 +161,7 @@ bool residual_marches_rows(int dim, int n, long long nsys);
 bool launch_update_residual64(int dim, bool var, const LevelDev<double>& L, const double* f, double* x64, float* e,
                               float* r32, const double* shift, const int* active64, double* partial, int nrhs,
                               int nsys, hipStream_t st, unsigned long long* ctr, const float* pa, const float* pb,
-                              const double* alpha, const int* iters);
+                              const double* alpha, const int* iters, bool assign = false);
 // x64 += e; with pa != nullptr e first takes the inner solve's pending update
 // e + alpha p (p = pa or pb by the parity of the system's iteration count)
 void launch_x_from_e(const LevelDev<double>& L, int dim, const float* e, double* x64, const int* active64,

@@ -2958,6 +2958,7 @@ struct XUpdate {
   const float* pb;
   const double* alpha;
   const int* iters;
+  int assign;           // x64 = e instead of x64 += e (x64 not read: the first update of a solve)
 };
 template <bool VAR, bool UPD>
 __global__ __launch_bounds__(1024) void k_residual64_2r(LevelDev<double> L, const double* __restrict__ f,
@@ -3001,9 +3002,10 @@ __global__ __launch_bounds__(1024) void k_residual64_2r(LevelDev<double> L, cons
     const float en = pend ? ev + a * pv : ev;
     return xv + (double)en;
   };
+  const bool assign = UPD && xu.assign;
   auto ldrow = [&](int r) {
     const unsigned o = (unsigned)crow(r) * rowb, o4 = (unsigned)crow(r) * (unsigned)n * 4u;
-    const double xv = xsb.ld(cb, o);
+    const double xv = assign ? 0.0 : xsb.ld(cb, o);
     const float ev = UPD ? eb.ld(cb / 2, o4) : 0.0f, pv = UPD && pend ? plb.ld(cb / 2, o4) : 0.0f;
     return xnew(xv, ev, pv) * on_f(r);
   };
@@ -3021,7 +3023,7 @@ __global__ __launch_bounds__(1024) void k_residual64_2r(LevelDev<double> L, cons
   float re[kRowLead], rp[kRowLead];
   auto fill = [&](int j, int s) {
     const unsigned rw = (unsigned)crow(j) * rowb, ra = (unsigned)crow(j + 1) * rowb;
-    rx[s] = xsb.ld(cb, ra);
+    rx[s] = assign ? 0.0 : xsb.ld(cb, ra);
     if (UPD) {
       re[s] = eb.ld(cb / 2, ra / 2);
       rp[s] = pend ? plb.ld(cb / 2, ra / 2) : 0.0f;
@@ -3088,7 +3090,7 @@ __global__ __launch_bounds__(1024) void k_update_seg_rows(long long N, int n, do
     const float* pl = ((its - 1) & 1) ? xu.pa : xu.pb;
     en = en + a * pl[g];
   }
-  x64[g] = x64[g] + (double)en;
+  x64[g] = (xu.assign ? 0.0 : x64[g]) + (double)en;
   e[g] = 0.0f;
 }
 
@@ -3166,11 +3168,14 @@ __global__ __launch_bounds__(kBlock) void k_residual64_3(LevelDev<double> L, con
 }
 
 // first refinement step: x64 = 0 so r = f; partial = ||f||^2
+// zero_x false: x64 is cleared only where f is 0 (a right-hand side that is
+// 0 everywhere leaves its system inactive, and its x64 must read 0); the
+// first x64 update of the refinement then assigns x64 = e instead of adding
 __global__ __launch_bounds__(256) void k_first_residual(long long N, const double* __restrict__ f,
                                                         double* __restrict__ x64, float* __restrict__ e,
                                                         float* __restrict__ r32, int nrhs,
                                                         const int* __restrict__ active64,
-                                                        double* __restrict__ partial) {
+                                                        double* __restrict__ partial, bool zero_x) {
   const int sys = blockIdx.y;
   if (!active64[sys]) return;
   const int rhs = sys % nrhs;
@@ -3186,7 +3191,7 @@ __global__ __launch_bounds__(256) void k_first_residual(long long N, const doubl
     if (p < N) {
       const double fv = fl[it];
       r32[off + p] = (float)fv;
-      x64[off + p] = 0.0;
+      if (zero_x || fv == 0.0) x64[off + p] = 0.0;
       e[off + p] = 0.0f;
       ff += fv * fv;
     }
@@ -3834,10 +3839,10 @@ template struct Launch<double>;
 
 void launch_residual64(int dim, bool var, const LevelDev<double>& L, const double* f, const double* x64, float* e,
                        float* r32, const double* shift, const int* active64, double* partial, int nrhs, int nsys,
-                       bool first, hipStream_t st, unsigned long long* ctr) {
+                       bool first, hipStream_t st, unsigned long long* ctr, bool zero_x) {
   if (first) {
     hipLaunchKernelGGL(k_first_residual, flat_grid(L.N, nsys), dim3(256), 0, st, L.N, f, const_cast<double*>(x64), e,
-                       r32, nrhs, active64, partial);
+                       r32, nrhs, active64, partial, zero_x);
     return;
   }
   if (dim == 3) {
@@ -3873,11 +3878,11 @@ bool residual_marches_rows(int dim, int n, long long nsys) { return residual_row
 bool launch_update_residual64(int dim, bool var, const LevelDev<double>& L, const double* f, double* x64, float* e,
                               float* r32, const double* shift, const int* active64, double* partial, int nrhs,
                               int nsys, hipStream_t st, unsigned long long* ctr, const float* pa, const float* pb,
-                              const double* alpha, const int* iters) {
+                              const double* alpha, const int* iters, bool assign) {
   if (!residual_rows(dim, L.n, nsys)) return false;
   const int nseg = (L.n + kRes2rRows - 1) / kRes2rRows;
   const dim3 g = rows_grid(nseg, nsys), blk(rows_threads(L.n));
-  const XUpdate xu{pa, pb, alpha, iters};
+  const XUpdate xu{pa, pb, alpha, iters, assign ? 1 : 0};
   if (var)
     hipLaunchKernelGGL((k_residual64_2r<true, true>), g, blk, 0, st, L, f, x64, e, r32, shift, active64, nrhs, partial,
                        ctr, xu);

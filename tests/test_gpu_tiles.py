@@ -256,16 +256,19 @@ def test_tiles_of_jacobi_pcg_grid():
 def test_wide_mixed_refinement_fuses_the_x64_update(variant):
     """Mixed refinement on a wide launch (255^2, 8 poles x 64 right-hand
     sides: the FP64 residual marches rows, 2 segments per system) folds
-    x64 += e into the residual pass, with the inner solve's pending update
-    (default) and without it (separate vector updates).  Every right-hand
-    side matches the spectral oracle, and the first four match a narrow
-    launch of the same terms (4 right-hand sides: two separate passes)."""
+    x64 += e into the residual pass (the first update assigns x64 = e, the
+    first residual having left x64 uncleared), with the inner solve's
+    pending update (default) and without it (separate vector updates).
+    Every right-hand side matches the spectral oracle (a zero one gives
+    exactly 0), and the first four match a narrow launch of the same terms
+    (4 right-hand sides: two separate passes, x64 cleared first)."""
     from oracle import spectral
     B = _B()
     n, alpha, k, R = 255, 0.5, 7, 64
     b = oracle_bura(alpha, k)
     v = 0 if variant == 0 else getattr(B, "BURA_VARIANT_" + variant)
     F = synth.normal_rhs(n, 2, nrhs=R, tag=451)
+    F[5] = 0.0   # a zero right-hand side: its systems stay inactive, and their x64 must read 0
     ref = spectral.bura_spectral(F, 2, b.c_f64, b.d_f64)
     kw = dict(weights=b.c_f64, shifts=[-x for x in b.d_f64], precision=B.BURA_MIXED, tol=1e-12, variant=v)
     wide = B.Plan(2, n, nrhs_max=R, **kw)
@@ -274,7 +277,9 @@ def test_wide_mixed_refinement_fuses_the_x64_update(variant):
         res = wide.solve(_dev(F))
         u_wide = _host(res.u)
         u_narrow = _host(narrow.solve(_dev(F[:4])).u)
-        err = _rel2(u_wide, ref)
+        assert np.all(u_wide[5] == 0.0)
+        keep = [r for r in range(R) if r != 5]
+        err = _rel2(u_wide[keep], ref[keep])
         print(f"variant {variant}: wide rel2 vs oracle {err:.2e}, outer steps {list(res.report.outer)[:k + 1]}, "
               f"wide vs narrow {_rel2(u_wide[:4], u_narrow):.2e}")
         assert err <= 1e-9
