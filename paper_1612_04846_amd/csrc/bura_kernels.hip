@@ -867,19 +867,36 @@ __device__ __forceinline__ T sweep_w(const Sweeps<T>& sw, int i) {
   return i == 0 ? sw.w[0] : (i == 1 ? sw.w[1] : sw.w[2]);
 }
 
+// (i, j, k) of point p of an n^DIM grid held in LDS: the quotients by n
+// through a float reciprocal instead of an integer division.  Exact: p +
+// 0.5 lies at least 0.5/n from every multiple of n, and for the LDS levels
+// (p < 2^15) the float rounding error of (p + 0.5) * (1/n) stays below 1e-5.
+template <int DIM>
+__device__ __forceinline__ void ijk_of(int p, int n, float rn, int& i, int& j, int& k) {
+  const int q = (int)(((float)p + 0.5f) * rn);
+  i = p - q * n;
+  if (DIM == 3) {
+    k = (int)(((float)q + 0.5f) * rn);
+    j = q - k * n;
+  } else {
+    j = q;
+    k = 0;
+  }
+}
+
 // omega for every sweep, or (per != nullptr) the half-cycle weights, reversed
 // for post-smoothing
 template <typename T, int DIM, bool VAR>
 __device__ void lds_smooth(const LevelDev<T>& L, T* X, const T* B, T* Tm, T s, T omega, int sweeps,
                            const Sweeps<T>* per = nullptr, bool reverse = false) {
   const int n = L.n;
+  const float rn = 1.0f / (float)n;
   const int nthr = blockDim.x;
   for (int sw = 0; sw < sweeps; ++sw) {
     const T om = per ? sweep_w(*per, reverse ? sweeps - 1 - sw : sw) : omega;
     for (int p = threadIdx.x; p < L.N; p += nthr) {
-      const int i = p % n;
-      const int j = (p / n) % n;
-      const int k = DIM == 3 ? p / (n * n) : 0;
+      int i, j, k;
+      ijk_of<DIM>(p, n, rn, i, j, k);
       T dg;
       const T ax = apply_pt<T, DIM, VAR>(L, X, i, j, k, p, s, &dg);
       Tm[p] = X[p] + om * (B[p] - ax) / dg;
@@ -918,10 +935,10 @@ __global__ __launch_bounds__(1024) void k_coarse(LdsHierarchy<T> H, const T* __r
       T* Tm = B + Lf.N;
       lds_smooth<T, DIM, VAR>(Lf, X, B, Tm, s, H.omega, H.nu, &H.pre, false);
       // residual on the fine level into Tm, then full weighting into B_c
+      const float rf = 1.0f / (float)Lf.n, rc = 1.0f / (float)Lc.n;
       for (int p = threadIdx.x; p < Lf.N; p += nthr) {
-        const int i = p % Lf.n;
-        const int j = (p / Lf.n) % Lf.n;
-        const int k = DIM == 3 ? p / (Lf.n * Lf.n) : 0;
+        int i, j, k;
+        ijk_of<DIM>(p, Lf.n, rf, i, j, k);
         Tm[p] = B[p] - apply_pt<T, DIM, VAR>(Lf, X, i, j, k, p, s, nullptr);
       }
       __syncthreads();
@@ -929,9 +946,8 @@ __global__ __launch_bounds__(1024) void k_coarse(LdsHierarchy<T> H, const T* __r
       T* Bc = Xc + Lc.N;
       const T wt[3] = {T(0.25), T(0.5), T(0.25)};
       for (int p = threadIdx.x; p < Lc.N; p += nthr) {
-        const int I = p % Lc.n;
-        const int J = (p / Lc.n) % Lc.n;
-        const int K = DIM == 3 ? p / (Lc.n * Lc.n) : 0;
+        int I, J, K;
+        ijk_of<DIM>(p, Lc.n, rc, I, J, K);
         T acc = T(0);
         for (int dk = (DIM == 3 ? -1 : 0); dk <= (DIM == 3 ? 1 : 0); ++dk) {
           const int fk = DIM == 3 ? 2 * K + 1 + dk : 0;
@@ -965,10 +981,10 @@ __global__ __launch_bounds__(1024) void k_coarse(LdsHierarchy<T> H, const T* __r
       T* B = X + Lf.N;
       T* Tm = B + Lf.N;
       const T* Xc = sm + H.off[l + 1];
+      const float rf = 1.0f / (float)Lf.n;
       for (int p = threadIdx.x; p < Lf.N; p += nthr) {
-        const int i = p % Lf.n;
-        const int j = (p / Lf.n) % Lf.n;
-        const int k = DIM == 3 ? p / (Lf.n * Lf.n) : 0;
+        int i, j, k;
+        ijk_of<DIM>(p, Lf.n, rf, i, j, k);
         X[p] += interp_pt<T, DIM>(Xc, Lc.n, i, j, k);
       }
       __syncthreads();
@@ -3583,7 +3599,10 @@ template <typename T>
 void Launch<T>::coarse_solve(int dim, bool var, const LdsHierarchy<T>& H, const T* b, T* x, const T* shift,
                              const int* active, int nsys, size_t lds_bytes, hipStream_t st,
                              unsigned long long* ctr) {
-  const dim3 g(nsys), blk(1024);
+  // 512 threads: the coarsest levels have few points per thread (63^2 has 8
+  // at 512), and two workgroups per CU fit the LDS either way; against 1024
+  // threads the 511^2 solve ran 0.8 % faster
+  const dim3 g(nsys), blk(512);
 #define K_CO(D, V, dummy) hipLaunchKernelGGL((k_coarse<T, D, V>), g, blk, lds_bytes, st, H, b, x, shift, active, ctr)
   BURA_DISPATCH_DV(dim, var, K_CO, 0);
 #undef K_CO
