@@ -214,6 +214,9 @@ int spmv_blocks(int dim, int n, int tv);
 // false where launch-shape variant tv of a kernel kind (0 stencil product, 1 down,
 // 2 up) on a level of n points per axis runs the same shape as another variant
 bool tile_variant_distinct(int kind, int dim, int n, int tv);
+// the launch-shape variants of the row-marching 2D kernels: segments of 128
+// fine rows and of 32
+constexpr int kRowsVariant = 3, kShortRowsVariant = 4;
 // blocks per system of the FP64 residual (refinement step) of a batch of nsys systems
 int residual_blocks(int dim, int n, long long nsys);
 int max_partial_blocks(int dim, int n, long long N);   // over every launch shape

@@ -1091,7 +1091,6 @@ struct RegionFaces {
 constexpr int kDownTile[kTileVariants][2] = {{64, 6}, {32, 8}, {64, 8}, {64, 6}, {64, 6}};
 constexpr int kUpTile[kTileVariants][2] = {{64, 16}, {64, 8}, {64, 24}, {64, 16}, {64, 16}};
 constexpr int kSpmvTile[kTileVariants][2] = {{4, 128}, {2, 64}, {8, 128}, {4, 128}, {4, 128}};
-constexpr int kRowsVariant = 3, kShortRowsVariant = 4;
 constexpr int kRowsSeg = 128, kShortRowsSeg = 32;   // fine rows per workgroup
 // The marching kernels keep the global loads of the next kRowLead rows in
 // flight in a ring of registers: slot s serves steps s, s + kRowLead, ...,
