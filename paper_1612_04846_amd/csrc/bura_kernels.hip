@@ -1676,6 +1676,16 @@ __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc,
     if (!VAR) return Lf.wc * ((xc - xl) + (xc - xr) + (xc - xd) + (xc - xu)) + sh * xc;
     return f.l * (xc - xl) + f.r * (xc - xr) + f.d * (xc - xd) + f.u * (xc - xu) + sh * xc;
   };
+  // one damped Jacobi update x + w (b - (A + s) x) / diag written as
+  // x + w ((b + the neighbours' face-weighted sum) / diag - x): diag holds
+  // every face weight and the shift, so the two agree in exact arithmetic, and
+  // this form takes 6 instead of 12 vector operations per point (the residual
+  // keeps the difference form)
+  auto relax = [&](const Faces& f, const T* X, T xc, T xd, T xu, T bb, T w, T r) {
+    const T xl = X[q - 1], xr = X[q + 1];
+    const T nb = VAR ? bb + f.l * xl + f.r * xr + f.d * xd + f.u * xu : bb + Lf.wc * ((xl + xr) + (xd + xu));
+    return xc + w * (r * nb - xc);
+  };
   const int t0 = 2 * K0 - NU, t1 = 2 * K1 + NU;
   // registers: bh[d] = b of row t - d; xh[m][0], xh[m][1] = sweep m+1's output
   // at its newest row of the previous step and the one below; fw[d], rd[d] =
@@ -1745,8 +1755,7 @@ __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc,
     xn[0] = sweep_w(om, 0) * bh[0] * rd[0];
 #pragma unroll
     for (int m = 1; m < NU; ++m) {
-      const T ax = apply(fw[m], sx[m - 1], xh[m - 1][0], xh[m - 1][1], xn[m - 1]);
-      xn[m] = xh[m - 1][0] + sweep_w(om, m) * (bh[m] - ax) * rd[m];
+      xn[m] = relax(fw[m], sx[m - 1], xh[m - 1][0], xh[m - 1][1], xn[m - 1], bh[m], sweep_w(om, m), rd[m]);
     }
     // the residual on row t - NU
     const T res = bh[NU] - apply(fw[NU], sx[NU - 1], xh[NU - 1][0], xh[NU - 1][1], xn[NU - 1]);
@@ -1791,7 +1800,8 @@ __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc,
   }
 }
 
-// k_up2r: the up kernel of k_up2 (same output, the same arithmetic per point)
+// k_up2r: the up kernel of k_up2 (same output; its sweeps in the form of
+// k_down2r's relax, equal in exact arithmetic)
 // marching along y over whole grid rows, as k_down2r, without reading the
 // pre-smoothed iterate: it forms it again from b, as the down kernel did
 // (NU sweeps from zero, the same weights and order), so the down kernel of
@@ -1805,8 +1815,10 @@ __global__ __launch_bounds__(1024) void k_down2r(LevelDev<T> Lf, LevelDev<T> Lc,
 // level.  Each thread reads the coarse values under its column (the coarse
 // columns left and right of it) from the two coarse rows that bracket the row
 // where P x_c is added.  xin is not read.
+// (FP32, up to two sweeps: at most 80 VGPRs, six waves per SIMD, three
+// 512-thread workgroups per CU)
 template <typename T, bool VAR, int NU, bool DOT>
-__global__ __launch_bounds__(1024) void k_up2r(LevelDev<T> Lc, LevelDev<T> Lf, const T* __restrict__ xc,
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NU <= 2 ? 6 : 1))) void k_up2r(LevelDev<T> Lc, LevelDev<T> Lf, const T* __restrict__ xc,
                                                const T* __restrict__ xin, const T* __restrict__ b,
                                                T* __restrict__ xout, const T* __restrict__ shift,
                                                const int* __restrict__ active, Sweeps<T> om,
@@ -1863,10 +1875,11 @@ __global__ __launch_bounds__(1024) void k_up2r(LevelDev<T> Lc, LevelDev<T> Lf, c
     if (!VAR) return row_on(r) ? rcon : T(0);
     return row_on(r) ? jacobi_recip(f.l + f.r + f.d + f.u + sh) : T(0);
   };
-  auto apply = [&](const Faces& f, const T* X, T xc_, T xd, T xu) {
+  // the damped Jacobi update in the form of k_down2r's relax
+  auto relax = [&](const Faces& f, const T* X, T xc_, T xd, T xu, T bb, T w, T r) {
     const T xl = X[q - 1], xr = X[q + 1];
-    if (!VAR) return Lf.wc * ((xc_ - xl) + (xc_ - xr) + (xc_ - xd) + (xc_ - xu)) + sh * xc_;
-    return f.l * (xc_ - xl) + f.r * (xc_ - xr) + f.d * (xc_ - xd) + f.u * (xc_ - xu) + sh * xc_;
+    const T nb = VAR ? bb + f.l * xl + f.r * xr + f.d * xd + f.u * xu : bb + Lf.wc * ((xl + xr) + (xd + xu));
+    return xc_ + w * (r * nb - xc_);
   };
   // the coarse columns of this fine column: ia (and ia + 1 for an even column)
   const int ia = (i & 1) ? (i - 1) / 2 : i / 2 - 1;
@@ -1937,12 +1950,12 @@ __global__ __launch_bounds__(1024) void k_up2r(LevelDev<T> Lc, LevelDev<T> Lf, c
     T lo0 = rl0[s], lo1 = rl1[s], hi0 = rh0[s], hi1 = rh1[s];
     mask_c(klo(r), lo0, lo1);
     mask_c(klo(r) + 1, hi0, hi1);
-    T v;
-    if (i & 1) {
-      v = (r & 1) ? lo0 : T(0.5) * (lo0 + hi0);
-    } else {
-      v = (r & 1) ? T(0.5) * (lo0 + lo1) : T(0.25) * (lo0 + lo1 + hi0 + hi1);
-    }
+    // without a branch on the column's parity (odd and even columns share a
+    // wave): an odd column counts its one coarse column twice, which the
+    // weights 1/2 and 1/4 undo exactly
+    const bool odd_col = i & 1;
+    const T sl = lo0 + (odd_col ? lo0 : lo1), sh_ = hi0 + (odd_col ? hi0 : hi1);
+    const T v = (r & 1) ? T(0.5) * sl : T(0.25) * (sl + sh_);
     // stage k on row t - k from stage k - 1's output (centre row in
     // sx[k - 1], below in xh, above just formed); the pre-sweeps are those
     // of the down kernel (zero start, the first one pointwise)
@@ -1951,9 +1964,8 @@ __global__ __launch_bounds__(1024) void k_up2r(LevelDev<T> Lc, LevelDev<T> Lf, c
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       if (k > 0) {
-        const T ax = apply(fw[k], sx[k - 1], xh[k - 1][0], xh[k - 1][1], xn[k - 1]);
         const T w = k < NU ? sweep_w(om, k) : sweep_w(om, NS - 1 - k);
-        xn[k] = xh[k - 1][0] + w * (bh[k] - ax) * rd[k];
+        xn[k] = relax(fw[k], sx[k - 1], xh[k - 1][0], xh[k - 1][1], xn[k - 1], bh[k], w, rd[k]);
       }
       if (k == NU - 1) xn[k] = row_on(r) ? xn[k] + v : T(0);   // x_pre + P x_c
     }
