@@ -133,13 +133,18 @@ ROW_CASES = [
     (255, True, "FP64", 1),
     (127, True, "FP64", 3),
     (191, True, "FP64", 2),
+    # FP32 inner solves with one and two sweeps (the up kernel's register
+    # budget is fixed for these), 159 -> 79 -> 39 ...
+    (159, True, "MIXED", 2),
+    (79, True, "MIXED", 1),
+    (79, False, "MIXED", 2),
 ]
 
 
 @pytest.mark.parametrize("n,var,prec,nu", ROW_CASES)
 def test_row_variants_with_one_and_three_sweeps(n, var, prec, nu):
     """The row-marching variants (3: segments of 128 fine rows, 4: of 32) on
-    every level with one and with three smoothing sweeps, FP64 and mixed,
+    every level with one, two and three smoothing sweeps, FP64 and mixed,
     constant and variable coefficients; no grid's rows are a multiple of a
     segment (95 -> 47 -> 23 -> 11 -> 5 ..., 191 -> 95 ...).  Each matches the
     oracle at the tiles' tolerance, and the tiles' result to rounding."""
